@@ -1,0 +1,325 @@
+"""ctypes front end of the plain CPU oracle (liboracle.so).
+
+TEST INFRASTRUCTURE ONLY: imported by the test suite, the smoke check and the
+CPU-baseline leg of the benchmark, never by the stitching library.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "liboracle.so")
+SRC = os.path.join(HERE, "vso_oracle.c")
+
+MAX_CAMS = 16
+MAX_PAIRS = 16
+
+TAP = dict(strip=1, mask=2, hist=3, lut=4, mom=5, mpair=6, mk=7, flags=8, pyr=9, flow=10,
+           pano_pre=11, pano_hist=12, bal_lut=13, quant=14, mbar=15, cover=16)
+
+
+def build(verbose: bool = False) -> str:
+    """Compile liboracle.so with gcc (no FP contraction, OpenMP)."""
+    cmd = ["gcc", "-O2", "-ffp-contract=off", "-fopenmp", "-fPIC", "-shared", "-Wall",
+           "-o", LIB_PATH + ".tmp", SRC, "-lm"]
+    if verbose:
+        print(" ".join(cmd))
+    subprocess.run(cmd, check=True)
+    os.replace(LIB_PATH + ".tmp", LIB_PATH)
+    return LIB_PATH
+
+
+class Rig(C.Structure):
+    _fields_ = [("n_cams", C.c_int), ("cam_w", C.c_int * MAX_CAMS), ("cam_h", C.c_int * MAX_CAMS),
+                ("H_pair", (C.c_double * 9) * MAX_CAMS), ("H_ref", C.c_double * 9),
+                ("ring", C.c_int), ("ring_period", C.c_int), ("canvas_w", C.c_int),
+                ("canvas_h", C.c_int)]
+
+
+class Params(C.Structure):
+    _fields_ = [("color_window", C.c_int), ("ridge", C.c_double), ("min_pixels", C.c_int),
+                ("flow", C.c_int), ("lk_levels", C.c_int), ("lk_iters", C.c_int),
+                ("lk_radius", C.c_int), ("lk_lambda", C.c_float), ("balance", C.c_int),
+                ("lambda_pct", C.c_int)]
+
+
+class PlanInfo(C.Structure):
+    _fields_ = [("canvas_w", C.c_int), ("canvas_h", C.c_int), ("n_pairs", C.c_int),
+                ("n_cams", C.c_int), ("ring", C.c_int), ("ring_period", C.c_int),
+                ("pair_j", C.c_int * MAX_PAIRS), ("pair_i", C.c_int * MAX_PAIRS),
+                ("pair_si", C.c_int * MAX_PAIRS),
+                ("strip_x0", C.c_int * MAX_PAIRS), ("strip_y0", C.c_int * MAX_PAIRS),
+                ("strip_w", C.c_int * MAX_PAIRS), ("strip_h", C.c_int * MAX_PAIRS),
+                ("hinv", (C.c_float * 9) * MAX_CAMS), ("hk", (C.c_double * 9) * MAX_CAMS),
+                ("n_covered", C.c_longlong)]
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            build()
+        L = C.CDLL(LIB_PATH)
+        L.vso_create.restype = C.c_void_p
+        L.vso_create.argtypes = [C.POINTER(Rig), C.POINTER(Params), C.POINTER(C.c_int)]
+        L.vso_destroy.argtypes = [C.c_void_p]
+        L.vso_plan_info_get.argtypes = [C.c_void_p, C.POINTER(PlanInfo)]
+        L.vso_stitch.argtypes = [C.c_void_p, C.POINTER(C.c_void_p), C.POINTER(C.c_int), C.c_void_p]
+        L.vso_reset.argtypes = [C.c_void_p]
+        L.vso_frames_seen.argtypes = [C.c_void_p]
+        L.vso_get.argtypes = [C.c_void_p, C.c_int, C.c_int, C.c_int, C.c_void_p, C.c_size_t]
+        L.vso_default_params.argtypes = [C.POINTER(Params)]
+        L.vso_histspec_lut.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p]
+        L.vso_solve_color.argtypes = [C.c_void_p, C.c_void_p, C.c_double, C.c_void_p]
+        L.vso_quantiles.argtypes = [C.c_void_p, C.c_longlong, C.c_int, C.POINTER(C.c_int),
+                                    C.POINTER(C.c_int)]
+        L.vso_balance_lut.argtypes = [C.c_double, C.c_double, C.c_int, C.c_void_p]
+        L.vso_pyr_down.argtypes = [C.c_void_p, C.c_int, C.c_int, C.c_void_p]
+        L.vso_lk_level.argtypes = [C.c_void_p, C.c_void_p, C.c_int, C.c_int, C.c_void_p, C.c_int,
+                                   C.c_int, C.c_int, C.c_int, C.c_float, C.c_void_p]
+        L.vso_lk_level_f64.argtypes = [C.c_void_p, C.c_void_p, C.c_int, C.c_int, C.c_void_p,
+                                       C.c_int, C.c_int, C.c_int, C.c_int, C.c_double, C.c_void_p]
+        L.vso_hom_valid.argtypes = [C.c_void_p, C.c_float, C.c_float, C.c_int, C.c_int,
+                                    C.POINTER(C.c_float), C.POINTER(C.c_float)]
+        L.vso_bilinear.restype = C.c_float
+        L.vso_bilinear.argtypes = [C.c_void_p, C.c_int, C.c_int, C.c_int, C.c_int, C.c_float,
+                                   C.c_float]
+        L.vso_round8.argtypes = [C.c_float]
+        _lib = L
+    return _lib
+
+
+def _ptr(a: np.ndarray):
+    return a.ctypes.data_as(C.c_void_p)
+
+
+def make_rig(rig: dict) -> Rig:
+    r = Rig()
+    n = rig["n_cams"]
+    r.n_cams = n
+    W = rig["W"] if "W" in rig else None
+    for k in range(n):
+        r.cam_w[k] = rig["cam_w"][k] if "cam_w" in rig else W
+        r.cam_h[k] = rig["cam_h"][k] if "cam_h" in rig else rig["H"]
+    for k in range(1, n):
+        hp = np.asarray(rig["H_pair"][k], dtype=np.float64).ravel()
+        for i in range(9):
+            r.H_pair[k][i] = float(hp[i])
+    href = np.asarray(rig["H_ref"], dtype=np.float64).ravel()
+    for i in range(9):
+        r.H_ref[i] = float(href[i])
+    r.ring = int(rig.get("ring", 0))
+    r.ring_period = int(rig.get("ring_period", 0))
+    r.canvas_w = int(rig["canvas_w"])
+    r.canvas_h = int(rig["canvas_h"])
+    return r
+
+
+def default_params(**over) -> Params:
+    p = Params()
+    lib().vso_default_params(C.byref(p))
+    for k, v in over.items():
+        setattr(p, k, v)
+    return p
+
+
+class OracleError(RuntimeError):
+    pass
+
+
+class Oracle:
+    """One stitching context on the CPU oracle."""
+
+    def __init__(self, rig: dict, **params):
+        self.rig_struct = make_rig(rig)
+        self.params = default_params(**params)
+        st = C.c_int(0)
+        self.h = lib().vso_create(C.byref(self.rig_struct), C.byref(self.params), C.byref(st))
+        if not self.h:
+            raise OracleError(f"vso_create failed: status {st.value}")
+        self.status = st.value
+        pi = PlanInfo()
+        lib().vso_plan_info_get(self.h, C.byref(pi))
+        self.plan = pi
+        self.n_cams = rig["n_cams"]
+
+    def __del__(self):
+        h = getattr(self, "h", None)
+        if h:
+            lib().vso_destroy(h)
+            self.h = None
+
+    @property
+    def canvas(self):
+        return self.plan.canvas_h, self.plan.canvas_w
+
+    @property
+    def n_pairs(self):
+        return self.plan.n_pairs
+
+    def strip_box(self, p):
+        P = self.plan
+        return P.strip_x0[p], P.strip_y0[p], P.strip_w[p], P.strip_h[p]
+
+    def stitch(self, frames) -> np.ndarray:
+        frames = [np.ascontiguousarray(f, dtype=np.uint8) for f in frames]
+        arr = (C.c_void_p * self.n_cams)(*[f.ctypes.data for f in frames])
+        pitch = (C.c_int * self.n_cams)(*[f.shape[1] * 3 for f in frames])
+        H, W = self.canvas
+        pano = np.zeros((H, W, 3), dtype=np.uint8)
+        st = lib().vso_stitch(self.h, arr, pitch, _ptr(pano))
+        if st != 0:
+            raise OracleError(f"vso_stitch failed: {st}")
+        return pano
+
+    def reset(self):
+        lib().vso_reset(self.h)
+
+    def frames_seen(self) -> int:
+        return lib().vso_frames_seen(self.h)
+
+    def tap(self, name: str, pair: int = 0, sub: int = 0) -> np.ndarray:
+        P = self.plan
+        H, W = self.canvas
+        sw, sh = (P.strip_w[pair], P.strip_h[pair]) if 0 <= pair < P.n_pairs else (0, 0)
+        if name == "strip":
+            out = np.zeros((sh, sw, 3), np.uint8)
+        elif name == "mask":
+            out = np.zeros((sh, sw), np.uint8)
+        elif name == "hist":
+            out = np.zeros((2, 3, 256), np.uint32)
+        elif name == "lut":
+            out = np.zeros((3, 256), np.uint8)
+        elif name == "mom":
+            out = np.zeros(16, np.uint64)
+        elif name == "mpair":
+            out = np.zeros((P.n_pairs, 3, 3), np.float64)
+        elif name == "mk":
+            out = np.zeros((self.n_cams, 3, 3), np.float32)
+        elif name == "flags":
+            out = np.zeros(P.n_pairs, np.int32)
+        elif name == "pyr":
+            lvl = sub % 8
+            w, h = sw, sh
+            for _ in range(lvl):
+                w, h = (w + 1) // 2, (h + 1) // 2
+            out = np.zeros((h, w), np.float32)
+        elif name == "flow":
+            out = np.zeros((sh, sw, 2), np.float32)
+        elif name == "pano_pre":
+            out = np.zeros((H, W, 3), np.uint8)
+        elif name == "pano_hist":
+            out = np.zeros((3, 256), np.uint32)
+        elif name == "bal_lut":
+            out = np.zeros((3, 256), np.uint8)
+        elif name == "quant":
+            out = np.zeros((3, 2), np.int32)
+        elif name == "mbar":
+            out = np.zeros((3, 2), np.float64)
+        elif name == "cover":
+            out = np.zeros((H, W), np.uint8)
+        else:
+            raise KeyError(name)
+        st = lib().vso_get(self.h, TAP[name], pair, sub, _ptr(out), out.nbytes)
+        if st != 0:
+            raise OracleError(f"vso_get({name}) failed: {st}")
+        return out
+
+
+# ---- single steps --------------------------------------------------------
+
+def histspec_lut(Gi, Gj) -> np.ndarray:
+    Gi = np.ascontiguousarray(Gi, np.uint32)
+    Gj = np.ascontiguousarray(Gj, np.uint32)
+    out = np.zeros(256, np.uint8)
+    lib().vso_histspec_lut(_ptr(Gi), _ptr(Gj), _ptr(out))
+    return out
+
+
+def solve_color(A, B, ridge=1e-9):
+    A = np.ascontiguousarray(A, np.float64).reshape(9)
+    B = np.ascontiguousarray(B, np.float64).reshape(9)
+    M = np.zeros(9, np.float64)
+    flag = lib().vso_solve_color(_ptr(A), _ptr(B), ridge, _ptr(M))
+    return M.reshape(3, 3), flag
+
+
+def quantiles(hist, n, lambda_pct=5):
+    h = np.ascontiguousarray(hist, np.uint32)
+    q1, q2 = C.c_int(), C.c_int()
+    lib().vso_quantiles(_ptr(h), int(n), lambda_pct, C.byref(q1), C.byref(q2))
+    return q1.value, q2.value
+
+
+def balance_lut(m1, m2, lambda_pct=5) -> np.ndarray:
+    out = np.zeros(256, np.uint8)
+    lib().vso_balance_lut(float(m1), float(m2), lambda_pct, _ptr(out))
+    return out
+
+
+def pyr_down(img) -> np.ndarray:
+    img = np.ascontiguousarray(img, np.float32)
+    h, w = img.shape
+    out = np.zeros(((h + 1) // 2, (w + 1) // 2), np.float32)
+    lib().vso_pyr_down(_ptr(img), w, h, _ptr(out))
+    return out
+
+
+def lk_level(T, Mv, u_coarse=None, radius=4, iters=5, lam=1.0) -> np.ndarray:
+    T = np.ascontiguousarray(T, np.float32)
+    Mv = np.ascontiguousarray(Mv, np.float32)
+    h, w = T.shape
+    out = np.zeros((h, w, 2), np.float32)
+    if u_coarse is not None:
+        uc = np.ascontiguousarray(u_coarse, np.float32)
+        lib().vso_lk_level(_ptr(T), _ptr(Mv), w, h, _ptr(uc), uc.shape[1], uc.shape[0], radius,
+                           iters, lam, _ptr(out))
+    else:
+        lib().vso_lk_level(_ptr(T), _ptr(Mv), w, h, None, 0, 0, radius, iters, lam, _ptr(out))
+    return out
+
+
+def lk_level_f64(T, Mv, u_coarse=None, radius=4, iters=5, lam=1.0) -> np.ndarray:
+    T = np.ascontiguousarray(T, np.float64)
+    Mv = np.ascontiguousarray(Mv, np.float64)
+    h, w = T.shape
+    out = np.zeros((h, w, 2), np.float64)
+    if u_coarse is not None:
+        uc = np.ascontiguousarray(u_coarse, np.float64)
+        lib().vso_lk_level_f64(_ptr(T), _ptr(Mv), w, h, _ptr(uc), uc.shape[1], uc.shape[0],
+                               radius, iters, lam, _ptr(out))
+    else:
+        lib().vso_lk_level_f64(_ptr(T), _ptr(Mv), w, h, None, 0, 0, radius, iters, lam, _ptr(out))
+    return out
+
+
+def pyramid_flow(Tpyr, Mpyr, radius=4, iters=5, lam=1.0, f64=False):
+    """Coarse-to-fine flow over lists of pyramid levels (finest first)."""
+    u = None
+    for l in range(len(Tpyr) - 1, -1, -1):
+        f = lk_level_f64 if f64 else lk_level
+        u = f(Tpyr[l], Mpyr[l], u, radius, iters, lam)
+    return u
+
+
+def hom_valid(h, x, y, W, H):
+    h = np.ascontiguousarray(h, np.float32).reshape(9)
+    u, v = C.c_float(), C.c_float()
+    ok = lib().vso_hom_valid(_ptr(h), float(x), float(y), W, H, C.byref(u), C.byref(v))
+    return bool(ok), u.value, v.value
+
+
+def bilinear(F, ch, u, v) -> float:
+    F = np.ascontiguousarray(F, np.uint8)
+    return lib().vso_bilinear(_ptr(F), F.shape[1] * 3, F.shape[1], F.shape[0], ch, u, v)
+
+
+def round8(r) -> int:
+    return lib().vso_round8(float(r))

@@ -1,0 +1,1091 @@
+/*
+ * vso_oracle.c -- plain CPU oracle of the per-frame stitching path of
+ * arXiv 2308.09209.  TEST INFRASTRUCTURE ONLY (see vso_oracle.h).
+ *
+ * Written straight from the paper's sections and equations plus the readings
+ * listed where the paper is silent; direct per-pixel sums and loops, no
+ * histogram tricks, no tiling.  OpenMP is used only over independent output
+ * pixels; every accumulation that crosses pixels is a serial loop.
+ *
+ * Build: gcc -O2 -ffp-contract=off -fopenmp -fPIC -shared (no contraction:
+ * every fused multiply-add below is an explicit fmaf).
+ */
+#include "vso_oracle.h"
+
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define NCH 3
+
+/* ------------------------------------------------------------------------ */
+/* Global conventions                                                        */
+/* ------------------------------------------------------------------------ */
+
+/* round-half-up to a byte: clamp(floor(r + 0.5), 0, 255) */
+int vso_round8(float r)
+{
+    float f = floorf(r + 0.5f);
+    if (f < 0.0f) f = 0.0f;
+    if (f > 255.0f) f = 255.0f;
+    return (int)f;
+}
+
+static int clampi(int v, int lo, int hi) { return v < lo ? lo : (v > hi ? hi : v); }
+static float clampf(float v, float lo, float hi) { return v < lo ? lo : (v > hi ? hi : v); }
+
+/* Apply a canvas->camera homography (section 3.1) in FP32:
+ *   nu = h0 x + (h1 y + h2), nv = h3 x + (h4 y + h5), w = h6 x + (h7 y + h8),
+ * each as two fused multiply-adds, then u = nu / w, v = nv / w.
+ * Valid iff w > 0 and (u, v) lies in [0, W-1] x [0, H-1].  When w <= 0 the
+ * position is defined as (0, 0). */
+int vso_hom_valid(const float h[9], float x, float y, int W, int H, float* u, float* v)
+{
+    float nu = fmaf(h[0], x, fmaf(h[1], y, h[2]));
+    float nv = fmaf(h[3], x, fmaf(h[4], y, h[5]));
+    float w = fmaf(h[6], x, fmaf(h[7], y, h[8]));
+    if (!(w > 0.0f)) {
+        *u = 0.0f;
+        *v = 0.0f;
+        return 0;
+    }
+    *u = nu / w;
+    *v = nv / w;
+    return (*u >= 0.0f) && (*u <= (float)(W - 1)) && (*v >= 0.0f) && (*v <= (float)(H - 1));
+}
+
+/* Bilinear sample of channel ch of an HWC uint8 image at (u, v): the
+ * position is clamped into the image, x0 = floor(u), fx = u - x0,
+ * x1 = min(x0 + 1, W - 1) (same in y), and
+ *   a = fx (p10 - p00) + p00, b = fx (p11 - p01) + p01, r = fy (b - a) + a
+ * each as one fused multiply-add. */
+float vso_bilinear(const uint8_t* F, int pitch, int W, int H, int ch, float u, float v)
+{
+    float uc = clampf(u, 0.0f, (float)(W - 1));
+    float vc = clampf(v, 0.0f, (float)(H - 1));
+    float flx = floorf(uc), fly = floorf(vc);
+    int x0 = (int)flx, y0 = (int)fly;
+    float fx = uc - flx, fy = vc - fly;
+    int x1 = x0 + 1 < W ? x0 + 1 : W - 1;
+    int y1 = y0 + 1 < H ? y0 + 1 : H - 1;
+    float p00 = (float)F[(size_t)y0 * pitch + (size_t)x0 * NCH + ch];
+    float p10 = (float)F[(size_t)y0 * pitch + (size_t)x1 * NCH + ch];
+    float p01 = (float)F[(size_t)y1 * pitch + (size_t)x0 * NCH + ch];
+    float p11 = (float)F[(size_t)y1 * pitch + (size_t)x1 * NCH + ch];
+    float a = fmaf(fx, p10 - p00, p00);
+    float b = fmaf(fx, p11 - p01, p01);
+    return fmaf(fy, b - a, a);
+}
+
+/* Colour application, row-vector convention of eq. (4): t = s . M, i.e.
+ * t_c = s_R M[0][c] + s_G M[1][c] + s_B M[2][c], evaluated as
+ * fmaf(s_R, M0c, fmaf(s_G, M1c, s_B * M2c)) and clamped to [0, 255]. */
+static float color_apply(const float s[3], const float M[9], int c)
+{
+    float t = fmaf(s[0], M[0 * 3 + c], fmaf(s[1], M[1 * 3 + c], s[2] * M[2 * 3 + c]));
+    return clampf(t, 0.0f, 255.0f);
+}
+
+/* ------------------------------------------------------------------------ */
+/* Context                                                                   */
+/* ------------------------------------------------------------------------ */
+
+typedef struct {
+    uint64_t A[6], B[9], n;
+} moments;
+
+struct vso_ctx {
+    vso_rig rig;
+    vso_params prm;
+    vso_plan_info plan;
+    uint8_t* cover;                          /* coverage count per canvas pixel */
+    /* colour state: moments of frames T-1, T-2 per pair; quantiles of T-1, T-2 */
+    int T;
+    moments mom_prev[VSO_MAX_PAIRS][2];
+    int q_prev[2][3][2];
+    /* taps of the last frame */
+    uint8_t* strip[VSO_MAX_PAIRS][2];
+    uint8_t* mask[VSO_MAX_PAIRS];
+    uint32_t hist[VSO_MAX_PAIRS][2][3][256];
+    uint8_t lut[VSO_MAX_PAIRS][3][256];
+    moments mom[VSO_MAX_PAIRS];
+    double Mpair[VSO_MAX_PAIRS][9];
+    float Mk[VSO_MAX_CAMS][9];
+    int flags[VSO_MAX_PAIRS];
+    float* pyr[VSO_MAX_PAIRS][2][VSO_MAX_LEVELS];
+    int pw[VSO_MAX_PAIRS][VSO_MAX_LEVELS], ph[VSO_MAX_PAIRS][VSO_MAX_LEVELS];
+    float* flow[VSO_MAX_PAIRS][2];
+    uint8_t* pano_pre;
+    uint32_t pano_hist[3][256];
+    uint8_t bal_lut[3][256];
+    int quant[3][2];
+    double mbar[3][2];
+};
+
+void vso_default_params(vso_params* p)
+{
+    p->color_window = 3;
+    p->ridge = 1e-9;
+    p->min_pixels = 64;
+    p->flow = 1;
+    p->lk_levels = 4;
+    p->lk_iters = 5;
+    p->lk_radius = 4;
+    p->lk_lambda = 1.0f;
+    p->balance = 1;
+    p->lambda_pct = 5;
+}
+
+/* 3x3 product c = a b, each entry ((a_r0 b_0c + a_r1 b_1c) + a_r2 b_2c). */
+static void mat3_mul(const double a[9], const double b[9], double c[9])
+{
+    double t[9];
+    for (int r = 0; r < 3; ++r)
+        for (int k = 0; k < 3; ++k)
+            t[r * 3 + k] = (a[r * 3 + 0] * b[0 * 3 + k] + a[r * 3 + 1] * b[1 * 3 + k]) + a[r * 3 + 2] * b[2 * 3 + k];
+    memcpy(c, t, sizeof t);
+}
+
+/* Inverse of a homography, normalised so that its last entry is +1: the
+ * adjugate divided by the adjugate's last entry.  Fails if the determinant
+ * is not finite and non-zero or the last adjugate entry is zero. */
+static int hom_inverse(const double a[9], double inv[9])
+{
+    double adj[9];
+    adj[0] = a[4] * a[8] - a[5] * a[7];
+    adj[1] = a[2] * a[7] - a[1] * a[8];
+    adj[2] = a[1] * a[5] - a[2] * a[4];
+    adj[3] = a[5] * a[6] - a[3] * a[8];
+    adj[4] = a[0] * a[8] - a[2] * a[6];
+    adj[5] = a[2] * a[3] - a[0] * a[5];
+    adj[6] = a[3] * a[7] - a[4] * a[6];
+    adj[7] = a[1] * a[6] - a[0] * a[7];
+    adj[8] = a[0] * a[4] - a[1] * a[3];
+    double det = (a[0] * adj[0] + a[1] * adj[3]) + a[2] * adj[6];
+    if (!isfinite(det) || det == 0.0 || adj[8] == 0.0 || !isfinite(adj[8])) return -1;
+    for (int i = 0; i < 9; ++i) inv[i] = adj[i] / adj[8];
+    return 0;
+}
+
+/* Coverage of one canvas pixel: every (camera, period shift) whose image
+ * contains it.  Returns the count (up to 4 recorded). */
+typedef struct {
+    int cam, m;
+    float u, v;
+} hit;
+
+static int cover_pixel(const vso_ctx* c, int x, int y, hit h[4])
+{
+    const vso_plan_info* P = &c->plan;
+    int n = 0;
+    for (int k = 0; k < P->n_cams; ++k) {
+        for (int m = -1; m <= 1; ++m) {
+            if (!P->ring && m != 0) continue;
+            float u, v;
+            int X = x + m * P->ring_period;
+            if (vso_hom_valid(P->hinv[k], (float)X, (float)y, c->rig.cam_w[k], c->rig.cam_h[k], &u, &v)) {
+                if (n < 4) {
+                    h[n].cam = k;
+                    h[n].m = m;
+                    h[n].u = u;
+                    h[n].v = v;
+                }
+                ++n;
+            }
+        }
+    }
+    return n;
+}
+
+/* Which overlap pair a doubly covered pixel belongs to; -1 if none.
+ * Pair p joins cameras (j, i); camera i sits si periods to the right of its
+ * own canvas position in the pair's coordinates, so a canvas pixel covered by
+ * j at shift mj and by i at shift mi belongs to p iff mj == mi + si. */
+static int pair_for(const vso_plan_info* P, const hit* a, const hit* b, int* jidx)
+{
+    for (int p = 0; p < P->n_pairs; ++p) {
+        const hit *hj = NULL, *hi = NULL;
+        if (a->cam == P->pair_j[p] && b->cam == P->pair_i[p]) {
+            hj = a;
+            hi = b;
+        } else if (b->cam == P->pair_j[p] && a->cam == P->pair_i[p]) {
+            hj = b;
+            hi = a;
+        } else {
+            continue;
+        }
+        if (hj->m != hi->m + P->pair_si[p]) continue;
+        *jidx = (hj == a) ? 0 : 1;
+        return p;
+    }
+    return -1;
+}
+
+/* Plan (section 2.1 step 1, section 3.1): camera k -> canvas is
+ * H_k = H_ref H_{1,0} ... H_{k,k-1}; the overlap of neighbouring cameras is
+ * found by testing every canvas pixel against every camera. */
+static int build_plan(vso_ctx* c)
+{
+    const vso_rig* R = &c->rig;
+    vso_plan_info* P = &c->plan;
+    memset(P, 0, sizeof *P);
+    if (R->n_cams < 2 || R->n_cams > VSO_MAX_CAMS) return VSO_E_INVAL;
+    if (R->canvas_w <= 0 || R->canvas_h <= 0) return VSO_E_INVAL;
+    if (R->ring && (R->n_cams < 3 || R->ring_period != R->canvas_w)) return VSO_E_INVAL;
+    for (int k = 0; k < R->n_cams; ++k)
+        if (R->cam_w[k] < 2 || R->cam_h[k] < 2) return VSO_E_INVAL;
+    P->canvas_w = R->canvas_w;
+    P->canvas_h = R->canvas_h;
+    P->n_cams = R->n_cams;
+    P->ring = R->ring;
+    P->ring_period = R->ring ? R->ring_period : 0;
+
+    double Hk[9];
+    memcpy(Hk, R->H_ref, sizeof Hk);
+    for (int k = 0; k < R->n_cams; ++k) {
+        if (k > 0) mat3_mul(Hk, R->H_pair[k], Hk);
+        for (int i = 0; i < 9; ++i)
+            if (!isfinite(Hk[i])) return VSO_E_INVAL;
+        memcpy(P->hk[k], Hk, sizeof Hk);
+        double inv[9];
+        if (hom_inverse(Hk, inv) != 0) return VSO_E_INVAL;
+        for (int i = 0; i < 9; ++i) P->hinv[k][i] = (float)inv[i];
+    }
+    /* pairs: (k-1, k) along the chain, plus (N-1, 0) closing a ring */
+    P->n_pairs = R->n_cams - 1 + (R->ring ? 1 : 0);
+    for (int p = 0; p < R->n_cams - 1; ++p) {
+        P->pair_j[p] = p;
+        P->pair_i[p] = p + 1;
+        P->pair_si[p] = 0;
+    }
+    if (R->ring) {
+        P->pair_j[R->n_cams - 1] = R->n_cams - 1;
+        P->pair_i[R->n_cams - 1] = 0;
+        P->pair_si[R->n_cams - 1] = 1;
+    }
+    int bx0[VSO_MAX_PAIRS], bx1[VSO_MAX_PAIRS], by0[VSO_MAX_PAIRS], by1[VSO_MAX_PAIRS];
+    for (int p = 0; p < P->n_pairs; ++p) {
+        bx0[p] = by0[p] = 1 << 30;
+        bx1[p] = by1[p] = -(1 << 30);
+    }
+    c->cover = (uint8_t*)calloc((size_t)P->canvas_w * P->canvas_h, 1);
+    if (!c->cover) return VSO_E_NOMEM;
+    int err = 0;
+    long long ncov = 0;
+    for (int y = 0; y < P->canvas_h; ++y) {
+        for (int x = 0; x < P->canvas_w; ++x) {
+            hit h[4];
+            int n = cover_pixel(c, x, y, h);
+            c->cover[(size_t)y * P->canvas_w + x] = (uint8_t)(n > 255 ? 255 : n);
+            if (n > 0) ++ncov;
+            if (n > 2) err = 1;
+            if (n == 2) {
+                int jidx;
+                int p = pair_for(P, &h[0], &h[1], &jidx);
+                if (p < 0) {
+                    err = 1;
+                    continue;
+                }
+                int X = x + h[jidx].m * P->ring_period;
+                if (X < bx0[p]) bx0[p] = X;
+                if (X > bx1[p]) bx1[p] = X;
+                if (y < by0[p]) by0[p] = y;
+                if (y > by1[p]) by1[p] = y;
+            }
+        }
+    }
+    P->n_covered = ncov;
+    if (err || ncov == 0) return VSO_E_GEOMETRY;
+    for (int p = 0; p < P->n_pairs; ++p) {
+        if (bx1[p] < bx0[p]) return VSO_E_GEOMETRY;
+        P->strip_x0[p] = bx0[p];
+        P->strip_y0[p] = by0[p];
+        P->strip_w[p] = bx1[p] - bx0[p] + 1;
+        P->strip_h[p] = by1[p] - by0[p] + 1;
+    }
+    return VSO_OK;
+}
+
+static void free_ctx(vso_ctx* c)
+{
+    if (!c) return;
+    free(c->cover);
+    for (int p = 0; p < VSO_MAX_PAIRS; ++p) {
+        free(c->strip[p][0]);
+        free(c->strip[p][1]);
+        free(c->mask[p]);
+        free(c->flow[p][0]);
+        free(c->flow[p][1]);
+        for (int k = 0; k < 2; ++k)
+            for (int l = 0; l < VSO_MAX_LEVELS; ++l) free(c->pyr[p][k][l]);
+    }
+    free(c->pano_pre);
+    free(c);
+}
+
+vso_ctx* vso_create(const vso_rig* rig, const vso_params* prm, int* status)
+{
+    vso_ctx* c = (vso_ctx*)calloc(1, sizeof *c);
+    if (!c) {
+        *status = VSO_E_NOMEM;
+        return NULL;
+    }
+    c->rig = *rig;
+    if (prm) c->prm = *prm;
+    else vso_default_params(&c->prm);
+    if (c->prm.lk_levels < 1 || c->prm.lk_levels > VSO_MAX_LEVELS || c->prm.lk_iters < 0 ||
+        c->prm.lk_radius < 0 || c->prm.color_window < 0 || c->prm.color_window > 3 ||
+        c->prm.lambda_pct < 0 || c->prm.lambda_pct >= 50) {
+        *status = VSO_E_INVAL;
+        free_ctx(c);
+        return NULL;
+    }
+    int st = build_plan(c);
+    if (st != VSO_OK) {
+        *status = st;
+        free_ctx(c);
+        return NULL;
+    }
+    const vso_plan_info* P = &c->plan;
+    for (int p = 0; p < P->n_pairs; ++p) {
+        size_t n = (size_t)P->strip_w[p] * P->strip_h[p];
+        c->strip[p][0] = (uint8_t*)calloc(n * 3, 1);
+        c->strip[p][1] = (uint8_t*)calloc(n * 3, 1);
+        c->mask[p] = (uint8_t*)calloc(n, 1);
+        c->flow[p][0] = (float*)calloc(n * 2, sizeof(float));
+        c->flow[p][1] = (float*)calloc(n * 2, sizeof(float));
+        int w = P->strip_w[p], h = P->strip_h[p];
+        for (int l = 0; l < c->prm.lk_levels; ++l) {
+            c->pw[p][l] = w;
+            c->ph[p][l] = h;
+            for (int k = 0; k < 2; ++k) c->pyr[p][k][l] = (float*)calloc((size_t)w * h, sizeof(float));
+            w = (w + 1) / 2;
+            h = (h + 1) / 2;
+        }
+    }
+    c->pano_pre = (uint8_t*)calloc((size_t)P->canvas_w * P->canvas_h * 3, 1);
+    *status = VSO_OK;
+    return c;
+}
+
+void vso_destroy(vso_ctx* c) { free_ctx(c); }
+
+int vso_plan_info_get(const vso_ctx* c, vso_plan_info* out)
+{
+    *out = c->plan;
+    return VSO_OK;
+}
+
+void vso_reset(vso_ctx* c)
+{
+    c->T = 0;
+    memset(c->mom_prev, 0, sizeof c->mom_prev);
+    memset(c->q_prev, 0, sizeof c->q_prev);
+}
+
+int vso_frames_seen(const vso_ctx* c) { return c->T; }
+
+/* ------------------------------------------------------------------------ */
+/* Section 2.1: 3D-M colour transfer                                         */
+/* ------------------------------------------------------------------------ */
+
+/* Step 3, histogram specification of G_i onto G_j (image j is the reference):
+ * with cumulative counts C_i, C_j over the same overlap pixels,
+ *   LUT(v) = min { w : C_j(w) >= C_i(v) }. */
+void vso_histspec_lut(const uint32_t Gi[256], const uint32_t Gj[256], uint8_t lut[256])
+{
+    uint64_t Ci[256], Cj[256];
+    uint64_t si = 0, sj = 0;
+    for (int v = 0; v < 256; ++v) {
+        si += Gi[v];
+        sj += Gj[v];
+        Ci[v] = si;
+        Cj[v] = sj;
+    }
+    for (int v = 0; v < 256; ++v) {
+        int w = 0;
+        while (w < 255 && Cj[w] < Ci[v]) ++w;
+        lut[v] = (uint8_t)w;
+    }
+}
+
+/* Eq. (1)/(3): M = [I_i^T I_i]^-1 I_i^T I_j with the 3D stacking of eq. (2)
+ * entering as summed moments.  Solved as (A + eps I) M = B + eps I with
+ * eps = ridge * trace(A) (a small pull toward the identity that keeps A = B
+ * exactly at M = I), by Gaussian elimination with partial pivoting (first
+ * largest |pivot| on ties) and back substitution, all FP64.  Returns 1 and
+ * M = I if the smallest pivot is below 1e-12 of the largest |entry|. */
+int vso_solve_color(const double A[9], const double B[9], double ridge, double M[9])
+{
+    double a[3][3], b[3][3];
+    double eps = ridge * ((A[0] + A[4]) + A[8]);
+    double maxabs = 0.0;
+    for (int r = 0; r < 3; ++r)
+        for (int k = 0; k < 3; ++k) {
+            a[r][k] = A[r * 3 + k] + (r == k ? eps : 0.0);
+            b[r][k] = B[r * 3 + k] + (r == k ? eps : 0.0);
+            if (fabs(a[r][k]) > maxabs) maxabs = fabs(a[r][k]);
+        }
+    for (int col = 0; col < 3; ++col) {
+        int piv = col;
+        for (int r = col + 1; r < 3; ++r)
+            if (fabs(a[r][col]) > fabs(a[piv][col])) piv = r;
+        if (piv != col) {
+            for (int k = 0; k < 3; ++k) {
+                double t = a[col][k];
+                a[col][k] = a[piv][k];
+                a[piv][k] = t;
+                t = b[col][k];
+                b[col][k] = b[piv][k];
+                b[piv][k] = t;
+            }
+        }
+        if (!(fabs(a[col][col]) >= 1e-12 * maxabs) || a[col][col] == 0.0) {
+            for (int i = 0; i < 9; ++i) M[i] = (i % 4 == 0) ? 1.0 : 0.0;
+            return 1;
+        }
+        for (int r = col + 1; r < 3; ++r) {
+            double f = a[r][col] / a[col][col];
+            for (int k = col; k < 3; ++k) a[r][k] = a[r][k] - f * a[col][k];
+            for (int k = 0; k < 3; ++k) b[r][k] = b[r][k] - f * b[col][k];
+        }
+    }
+    double x[3][3];
+    for (int r = 2; r >= 0; --r) {
+        for (int k = 0; k < 3; ++k) {
+            double s = b[r][k];
+            for (int q = r + 1; q < 3; ++q) s = s - a[r][q] * x[q][k];
+            x[r][k] = s / a[r][r];
+        }
+    }
+    for (int r = 0; r < 3; ++r)
+        for (int k = 0; k < 3; ++k) M[r * 3 + k] = x[r][k];
+    return 0;
+}
+
+/* Steps 1-2: pre-warp both cameras of every pair onto its overlap strip
+ * (bilinear, rounded to bytes), the overlap mask (covered by both), and the
+ * per-channel histograms over the mask. */
+static void step_strips(vso_ctx* c, const uint8_t* const F[], const int pitch[])
+{
+    const vso_plan_info* P = &c->plan;
+    for (int p = 0; p < P->n_pairs; ++p) {
+        int sw = P->strip_w[p], sh = P->strip_h[p];
+        int cams[2] = {P->pair_j[p], P->pair_i[p]};
+        int shifts[2] = {0, P->pair_si[p]};
+#pragma omp parallel for schedule(static)
+        for (int ly = 0; ly < sh; ++ly) {
+            for (int lx = 0; lx < sw; ++lx) {
+                int X = P->strip_x0[p] + lx, Y = P->strip_y0[p] + ly;
+                int ok = 1;
+                for (int s = 0; s < 2; ++s) {
+                    int k = cams[s];
+                    float u, v;
+                    int xs = X - shifts[s] * P->ring_period;
+                    int val = vso_hom_valid(P->hinv[k], (float)xs, (float)Y, c->rig.cam_w[k], c->rig.cam_h[k], &u, &v);
+                    ok = ok && val;
+                    for (int ch = 0; ch < 3; ++ch) {
+                        float r = vso_bilinear(F[k], pitch[k], c->rig.cam_w[k], c->rig.cam_h[k], ch, u, v);
+                        c->strip[p][s][((size_t)ly * sw + lx) * 3 + ch] = (uint8_t)vso_round8(r);
+                    }
+                }
+                c->mask[p][(size_t)ly * sw + lx] = (uint8_t)ok;
+            }
+        }
+        memset(c->hist[p], 0, sizeof c->hist[p]);
+        for (size_t q = 0; q < (size_t)sw * sh; ++q) {
+            if (!c->mask[p][q]) continue;
+            for (int s = 0; s < 2; ++s)
+                for (int ch = 0; ch < 3; ++ch) c->hist[p][s][ch][c->strip[p][s][q * 3 + ch]]++;
+        }
+    }
+}
+
+/* Steps 3-4: histogram-specification LUT per channel and the exact integer
+ * moments A = I_i^T I_i and B = I_i^T I_j, where I_i holds the raw overlap
+ * pixels of camera i and I_j the same pixels revised by the LUT (eq. (1)). */
+static void step_moments(vso_ctx* c)
+{
+    const vso_plan_info* P = &c->plan;
+    for (int p = 0; p < P->n_pairs; ++p) {
+        for (int ch = 0; ch < 3; ++ch) vso_histspec_lut(c->hist[p][1][ch], c->hist[p][0][ch], c->lut[p][ch]);
+        moments m;
+        memset(&m, 0, sizeof m);
+        size_t N = (size_t)P->strip_w[p] * P->strip_h[p];
+        for (size_t q = 0; q < N; ++q) {
+            if (!c->mask[p][q]) continue;
+            uint64_t pv[3], qv[3];
+            for (int ch = 0; ch < 3; ++ch) {
+                pv[ch] = c->strip[p][1][q * 3 + ch];
+                qv[ch] = c->lut[p][ch][pv[ch]];
+            }
+            m.A[0] += pv[0] * pv[0];
+            m.A[1] += pv[0] * pv[1];
+            m.A[2] += pv[0] * pv[2];
+            m.A[3] += pv[1] * pv[1];
+            m.A[4] += pv[1] * pv[2];
+            m.A[5] += pv[2] * pv[2];
+            for (int r = 0; r < 3; ++r)
+                for (int k = 0; k < 3; ++k) m.B[r * 3 + k] += pv[r] * qv[k];
+            m.n += 1;
+        }
+        c->mom[p] = m;
+    }
+}
+
+/* Eqs. (2)-(3) (3D-M): the stacked rows of frames T, T-1, T-2 enter the
+ * normal equations as summed moments (frames before 0 do not exist), then
+ * eq. (4)'s matrix per pair; cameras are chained to camera 0 as
+ * M_0 = I, M_k = M_(k-1,k) M_(k-1) (row vectors: camera k -> k-1 -> ... -> 0). */
+static void step_solve(vso_ctx* c)
+{
+    const vso_plan_info* P = &c->plan;
+    int W = c->prm.color_window;
+    for (int p = 0; p < P->n_pairs; ++p) {
+        c->flags[p] = 0;
+        double M[9] = {1, 0, 0, 0, 1, 0, 0, 0, 1};
+        if (W > 0) {
+            uint64_t A3[6], B3[9], n3;
+            memcpy(A3, c->mom[p].A, sizeof A3);
+            memcpy(B3, c->mom[p].B, sizeof B3);
+            n3 = c->mom[p].n;
+            for (int d = 1; d < W && d <= c->T; ++d) {
+                const moments* o = &c->mom_prev[p][d - 1];
+                for (int i = 0; i < 6; ++i) A3[i] += o->A[i];
+                for (int i = 0; i < 9; ++i) B3[i] += o->B[i];
+                n3 += o->n;
+            }
+            if (n3 < (uint64_t)c->prm.min_pixels) {
+                c->flags[p] = 1;
+            } else {
+                double A[9] = {(double)A3[0], (double)A3[1], (double)A3[2],
+                               (double)A3[1], (double)A3[3], (double)A3[4],
+                               (double)A3[2], (double)A3[4], (double)A3[5]};
+                double B[9];
+                for (int i = 0; i < 9; ++i) B[i] = (double)B3[i];
+                if (vso_solve_color(A, B, c->prm.ridge, M)) c->flags[p] = 2;
+            }
+        }
+        memcpy(c->Mpair[p], M, sizeof M);
+    }
+    double Mk[9] = {1, 0, 0, 0, 1, 0, 0, 0, 1};
+    for (int i = 0; i < 9; ++i) c->Mk[0][i] = (float)Mk[i];
+    for (int k = 1; k < P->n_cams; ++k) {
+        mat3_mul(c->Mpair[k - 1], Mk, Mk);
+        for (int i = 0; i < 9; ++i) c->Mk[k][i] = (float)Mk[i];
+    }
+}
+
+/* ------------------------------------------------------------------------ */
+/* Section 3.2: dense flow on the overlap strips                             */
+/* ------------------------------------------------------------------------ */
+
+/* One 2x reduction of the Gaussian pyramid: separable [1 4 6 4 1]/16,
+ * horizontal pass first, clamped indices, kept at even positions.  Each pass
+ * sums ((((a0 + 4 a1) + 6 a2) + 4 a3) + a4) and scales by 1/16. */
+void vso_pyr_down(const float* src, int w, int h, float* dst)
+{
+    int wd = (w + 1) / 2, hd = (h + 1) / 2;
+#pragma omp parallel for schedule(static)
+    for (int y = 0; y < hd; ++y) {
+        for (int x = 0; x < wd; ++x) {
+            float rows[5];
+            for (int t = 0; t < 5; ++t) {
+                const float* s = src + (size_t)clampi(2 * y + t - 2, 0, h - 1) * w;
+                float a0 = s[clampi(2 * x - 2, 0, w - 1)];
+                float a1 = s[clampi(2 * x - 1, 0, w - 1)];
+                float a2 = s[clampi(2 * x, 0, w - 1)];
+                float a3 = s[clampi(2 * x + 1, 0, w - 1)];
+                float a4 = s[clampi(2 * x + 2, 0, w - 1)];
+                float acc = a0 + 4.0f * a1;
+                acc = acc + 6.0f * a2;
+                acc = acc + 4.0f * a3;
+                acc = acc + a4;
+                rows[t] = acc * 0.0625f;
+            }
+            float acc = rows[0] + 4.0f * rows[1];
+            acc = acc + 6.0f * rows[2];
+            acc = acc + 4.0f * rows[3];
+            acc = acc + rows[4];
+            dst[(size_t)y * wd + x] = acc * 0.0625f;
+        }
+    }
+}
+
+static float img_at(const float* I, int w, int h, int x, int y)
+{
+    return I[(size_t)clampi(y, 0, h - 1) * w + clampi(x, 0, w - 1)];
+}
+
+/* Dense pyramidal Lucas-Kanade at one level (the flow estimator reading):
+ * for every pixel x, with template T and moving image Mv, minimise
+ * sum_{x' in window} (Mv(x' + u) - T(x'))^2 over the (2r+1)^2 window clipped
+ * to the level, by `iters` Gauss-Newton steps with the template gradient
+ * (central differences, clamped) and a Tikhonov term lambda * |window|:
+ *   G = sum [Ix^2, Ix Iy; Ix Iy, Iy^2] + lambda |window| I,
+ *   b = sum [Ix e, Iy e], e = bilinear(Mv, x' + u) - T(x'),
+ *   du = (G01 bv - G11 bu) / det, dv = (G01 bu - G00 bv) / det.
+ * The warp position x' + u is split once per step into floor(u) and
+ * frac(u) so that every tap is the exact bilinear interpolation at x' + u
+ * (indices clamped).  Sums run over the window in row-major order.  The
+ * initial flow is 0 at the coarsest level, else twice the bilinear sample
+ * of the coarser flow at ((x + 1/2)/2 - 1/2, (y + 1/2)/2 - 1/2). */
+void vso_lk_level(const float* T, const float* Mv, int w, int h,
+                  const float* uc, int wc, int hc,
+                  int r, int iters, float lambda, float* u_out)
+{
+#pragma omp parallel for schedule(dynamic, 4)
+    for (int y = 0; y < h; ++y) {
+        for (int x = 0; x < w; ++x) {
+            float ux = 0.0f, uy = 0.0f;
+            if (uc) {
+                float cx = clampf(fmaf((float)x, 0.5f, -0.25f), 0.0f, (float)(wc - 1));
+                float cy = clampf(fmaf((float)y, 0.5f, -0.25f), 0.0f, (float)(hc - 1));
+                float flx = floorf(cx), fly = floorf(cy);
+                int x0 = (int)flx, y0 = (int)fly;
+                float fx = cx - flx, fy = cy - fly;
+                int x1 = x0 + 1 < wc ? x0 + 1 : wc - 1;
+                int y1 = y0 + 1 < hc ? y0 + 1 : hc - 1;
+                float comp[2];
+                for (int d = 0; d < 2; ++d) {
+                    float p00 = uc[((size_t)y0 * wc + x0) * 2 + d];
+                    float p10 = uc[((size_t)y0 * wc + x1) * 2 + d];
+                    float p01 = uc[((size_t)y1 * wc + x0) * 2 + d];
+                    float p11 = uc[((size_t)y1 * wc + x1) * 2 + d];
+                    float a = fmaf(fx, p10 - p00, p00);
+                    float b = fmaf(fx, p11 - p01, p01);
+                    comp[d] = fmaf(fy, b - a, a);
+                }
+                ux = 2.0f * comp[0];
+                uy = 2.0f * comp[1];
+            }
+            int wx0 = x - r < 0 ? 0 : x - r, wx1 = x + r > w - 1 ? w - 1 : x + r;
+            int wy0 = y - r < 0 ? 0 : y - r, wy1 = y + r > h - 1 ? h - 1 : y + r;
+            float g00 = 0.0f, g01 = 0.0f, g11 = 0.0f;
+            for (int yy = wy0; yy <= wy1; ++yy)
+                for (int xx = wx0; xx <= wx1; ++xx) {
+                    float ix = 0.5f * (img_at(T, w, h, xx + 1, yy) - img_at(T, w, h, xx - 1, yy));
+                    float iy = 0.5f * (img_at(T, w, h, xx, yy + 1) - img_at(T, w, h, xx, yy - 1));
+                    g00 = fmaf(ix, ix, g00);
+                    g01 = fmaf(ix, iy, g01);
+                    g11 = fmaf(iy, iy, g11);
+                }
+            float reg = lambda * (float)((wy1 - wy0 + 1) * (wx1 - wx0 + 1));
+            g00 = g00 + reg;
+            g11 = g11 + reg;
+            float det = g00 * g11 - g01 * g01;
+            for (int it = 0; it < iters; ++it) {
+                float flx = floorf(ux), fly = floorf(uy);
+                int ox = (int)flx, oy = (int)fly;
+                float fx = ux - flx, fy = uy - fly;
+                float bu = 0.0f, bv = 0.0f;
+                for (int yy = wy0; yy <= wy1; ++yy)
+                    for (int xx = wx0; xx <= wx1; ++xx) {
+                        float p00 = img_at(Mv, w, h, xx + ox, yy + oy);
+                        float p10 = img_at(Mv, w, h, xx + ox + 1, yy + oy);
+                        float p01 = img_at(Mv, w, h, xx + ox, yy + oy + 1);
+                        float p11 = img_at(Mv, w, h, xx + ox + 1, yy + oy + 1);
+                        float a = fmaf(fx, p10 - p00, p00);
+                        float b = fmaf(fx, p11 - p01, p01);
+                        float m = fmaf(fy, b - a, a);
+                        float e = m - T[(size_t)yy * w + xx];
+                        float ix = 0.5f * (img_at(T, w, h, xx + 1, yy) - img_at(T, w, h, xx - 1, yy));
+                        float iy = 0.5f * (img_at(T, w, h, xx, yy + 1) - img_at(T, w, h, xx, yy - 1));
+                        bu = fmaf(ix, e, bu);
+                        bv = fmaf(iy, e, bv);
+                    }
+                float du = (g01 * bv - g11 * bu) / det;
+                float dv = (g01 * bu - g00 * bv) / det;
+                ux = ux + du;
+                uy = uy + dv;
+            }
+            u_out[((size_t)y * w + x) * 2 + 0] = ux;
+            u_out[((size_t)y * w + x) * 2 + 1] = uy;
+        }
+    }
+}
+
+/* The same estimator in FP64 (no prescribed rounding), used only to bound how
+ * far FP32 rounding moves the flow. */
+static double img_at_d(const double* I, int w, int h, int x, int y)
+{
+    return I[(size_t)clampi(y, 0, h - 1) * w + clampi(x, 0, w - 1)];
+}
+
+void vso_lk_level_f64(const double* T, const double* Mv, int w, int h,
+                      const double* uc, int wc, int hc,
+                      int r, int iters, double lambda, double* u_out)
+{
+#pragma omp parallel for schedule(dynamic, 4)
+    for (int y = 0; y < h; ++y) {
+        for (int x = 0; x < w; ++x) {
+            double ux = 0.0, uy = 0.0;
+            if (uc) {
+                double cx = x * 0.5 - 0.25, cy = y * 0.5 - 0.25;
+                cx = cx < 0 ? 0 : (cx > wc - 1 ? wc - 1 : cx);
+                cy = cy < 0 ? 0 : (cy > hc - 1 ? hc - 1 : cy);
+                int x0 = (int)floor(cx), y0 = (int)floor(cy);
+                double fx = cx - x0, fy = cy - y0;
+                int x1 = x0 + 1 < wc ? x0 + 1 : wc - 1;
+                int y1 = y0 + 1 < hc ? y0 + 1 : hc - 1;
+                double comp[2];
+                for (int d = 0; d < 2; ++d) {
+                    double p00 = uc[((size_t)y0 * wc + x0) * 2 + d];
+                    double p10 = uc[((size_t)y0 * wc + x1) * 2 + d];
+                    double p01 = uc[((size_t)y1 * wc + x0) * 2 + d];
+                    double p11 = uc[((size_t)y1 * wc + x1) * 2 + d];
+                    double a = p00 + fx * (p10 - p00), b = p01 + fx * (p11 - p01);
+                    comp[d] = a + fy * (b - a);
+                }
+                ux = 2.0 * comp[0];
+                uy = 2.0 * comp[1];
+            }
+            int wx0 = x - r < 0 ? 0 : x - r, wx1 = x + r > w - 1 ? w - 1 : x + r;
+            int wy0 = y - r < 0 ? 0 : y - r, wy1 = y + r > h - 1 ? h - 1 : y + r;
+            double g00 = 0, g01 = 0, g11 = 0;
+            for (int yy = wy0; yy <= wy1; ++yy)
+                for (int xx = wx0; xx <= wx1; ++xx) {
+                    double ix = 0.5 * (img_at_d(T, w, h, xx + 1, yy) - img_at_d(T, w, h, xx - 1, yy));
+                    double iy = 0.5 * (img_at_d(T, w, h, xx, yy + 1) - img_at_d(T, w, h, xx, yy - 1));
+                    g00 += ix * ix;
+                    g01 += ix * iy;
+                    g11 += iy * iy;
+                }
+            double reg = lambda * (double)((wy1 - wy0 + 1) * (wx1 - wx0 + 1));
+            g00 += reg;
+            g11 += reg;
+            double det = g00 * g11 - g01 * g01;
+            for (int it = 0; it < iters; ++it) {
+                double flx = floor(ux), fly = floor(uy);
+                int ox = (int)flx, oy = (int)fly;
+                double fx = ux - flx, fy = uy - fly;
+                double bu = 0, bv = 0;
+                for (int yy = wy0; yy <= wy1; ++yy)
+                    for (int xx = wx0; xx <= wx1; ++xx) {
+                        double p00 = img_at_d(Mv, w, h, xx + ox, yy + oy);
+                        double p10 = img_at_d(Mv, w, h, xx + ox + 1, yy + oy);
+                        double p01 = img_at_d(Mv, w, h, xx + ox, yy + oy + 1);
+                        double p11 = img_at_d(Mv, w, h, xx + ox + 1, yy + oy + 1);
+                        double a = p00 + fx * (p10 - p00), b = p01 + fx * (p11 - p01);
+                        double e = a + fy * (b - a) - T[(size_t)yy * w + xx];
+                        double ix = 0.5 * (img_at_d(T, w, h, xx + 1, yy) - img_at_d(T, w, h, xx - 1, yy));
+                        double iy = 0.5 * (img_at_d(T, w, h, xx, yy + 1) - img_at_d(T, w, h, xx, yy - 1));
+                        bu += ix * e;
+                        bv += iy * e;
+                    }
+                ux += (g01 * bv - g11 * bu) / det;
+                uy += (g01 * bu - g00 * bv) / det;
+            }
+            u_out[((size_t)y * w + x) * 2 + 0] = ux;
+            u_out[((size_t)y * w + x) * 2 + 1] = uy;
+        }
+    }
+}
+
+/* Flow input: the colour-corrected strips (every strip pixel), reduced to
+ * integer luma Y = (77 R + 150 G + 29 B + 128) >> 8, then the pyramid. */
+static void step_pyramids(vso_ctx* c)
+{
+    const vso_plan_info* P = &c->plan;
+    for (int p = 0; p < P->n_pairs; ++p) {
+        int sw = P->strip_w[p], sh = P->strip_h[p];
+        int cams[2] = {P->pair_j[p], P->pair_i[p]};
+        for (int s = 0; s < 2; ++s) {
+            const float* M = c->Mk[cams[s]];
+            float* Y = c->pyr[p][s][0];
+#pragma omp parallel for schedule(static)
+            for (int q = 0; q < sw * sh; ++q) {
+                float px[3];
+                int cc[3];
+                for (int ch = 0; ch < 3; ++ch) px[ch] = (float)c->strip[p][s][(size_t)q * 3 + ch];
+                for (int ch = 0; ch < 3; ++ch) cc[ch] = vso_round8(color_apply(px, M, ch));
+                Y[q] = (float)((77 * cc[0] + 150 * cc[1] + 29 * cc[2] + 128) >> 8);
+            }
+            for (int l = 1; l < c->prm.lk_levels; ++l)
+                vso_pyr_down(c->pyr[p][s][l - 1], c->pw[p][l - 1], c->ph[p][l - 1], c->pyr[p][s][l]);
+        }
+    }
+}
+
+/* flow_ij satisfies P_i(x + flow_ij(x)) ~ P_j(x): template j, moving i;
+ * flow_ji the other way round.  Coarse to fine. */
+static void step_flow(vso_ctx* c)
+{
+    const vso_plan_info* P = &c->plan;
+    int L = c->prm.lk_levels;
+    for (int p = 0; p < P->n_pairs; ++p) {
+        size_t n0 = (size_t)P->strip_w[p] * P->strip_h[p];
+        for (int dir = 0; dir < 2; ++dir) {
+            if (!c->prm.flow) {
+                memset(c->flow[p][dir], 0, n0 * 2 * sizeof(float));
+                continue;
+            }
+            int tmpl = dir == 0 ? 0 : 1; /* 0 = camera j, 1 = camera i */
+            int mov = 1 - tmpl;
+            float* prev = NULL;
+            int pwc = 0, phc = 0;
+            for (int l = L - 1; l >= 0; --l) {
+                int w = c->pw[p][l], h = c->ph[p][l];
+                float* u = (l == 0) ? c->flow[p][dir] : (float*)malloc((size_t)w * h * 2 * sizeof(float));
+                vso_lk_level(c->pyr[p][tmpl][l], c->pyr[p][mov][l], w, h, prev, pwc, phc,
+                             c->prm.lk_radius, c->prm.lk_iters, c->prm.lk_lambda, u);
+                free(prev);
+                prev = (l == 0) ? NULL : u;
+                pwc = w;
+                phc = h;
+            }
+        }
+    }
+}
+
+/* ------------------------------------------------------------------------ */
+/* Eqs. (15)-(18): local warp and weighted fusion                            */
+/* ------------------------------------------------------------------------ */
+
+static void sample_color(const vso_ctx* c, const uint8_t* const F[], const int pitch[], int k,
+                         float X, float Y, float t[3])
+{
+    float u, v;
+    vso_hom_valid(c->plan.hinv[k], X, Y, c->rig.cam_w[k], c->rig.cam_h[k], &u, &v);
+    float s[3];
+    for (int ch = 0; ch < 3; ++ch) s[ch] = vso_bilinear(F[k], pitch[k], c->rig.cam_w[k], c->rig.cam_h[k], ch, u, v);
+    for (int ch = 0; ch < 3; ++ch) t[ch] = color_apply(s, c->Mk[k], ch);
+}
+
+/* Per canvas pixel: uncovered -> 0; one camera -> its colour-corrected
+ * resample; two cameras (j left, i right) -> eq. (16) weights from the
+ * distance to each camera's own vertical border (theta_i + theta_j = 1),
+ * eq. (17) displacements that meet in the middle (camera i moved by
+ * theta_j flow_ij, camera j by theta_i flow_ji), eq. (18) blend
+ * out = round8(theta_i (t_i - t_j) + t_j), t = colour-corrected resamples. */
+static void step_blend(vso_ctx* c, const uint8_t* const F[], const int pitch[])
+{
+    const vso_plan_info* P = &c->plan;
+    int W = P->canvas_w, H = P->canvas_h;
+#pragma omp parallel for schedule(dynamic, 4)
+    for (int y = 0; y < H; ++y) {
+        for (int x = 0; x < W; ++x) {
+            uint8_t* o = c->pano_pre + ((size_t)y * W + x) * 3;
+            hit h[4];
+            int n = cover_pixel(c, x, y, h);
+            if (n == 0) {
+                o[0] = o[1] = o[2] = 0;
+            } else if (n == 1) {
+                float t[3];
+                sample_color(c, F, pitch, h[0].cam, (float)(x + h[0].m * P->ring_period), (float)y, t);
+                for (int ch = 0; ch < 3; ++ch) o[ch] = (uint8_t)vso_round8(t[ch]);
+            } else {
+                int jidx;
+                int p = pair_for(P, &h[0], &h[1], &jidx);
+                const hit* hj = &h[jidx];
+                const hit* hi = &h[1 - jidx];
+                int j = hj->cam, i = hi->cam;
+                float dj = fminf(hj->u, (float)(c->rig.cam_w[j] - 1) - hj->u);
+                float di = fminf(hi->u, (float)(c->rig.cam_w[i] - 1) - hi->u);
+                if (dj < 0.0f) dj = 0.0f;
+                if (di < 0.0f) di = 0.0f;
+                float sum = di + dj;
+                float th_i = sum > 0.0f ? di / sum : 0.5f;
+                float th_j = 1.0f - th_i;
+                int X = x + hj->m * P->ring_period;
+                int lx = X - P->strip_x0[p], ly = y - P->strip_y0[p];
+                size_t q = ((size_t)ly * P->strip_w[p] + lx) * 2;
+                float fij_x = c->flow[p][0][q], fij_y = c->flow[p][0][q + 1];
+                float fji_x = c->flow[p][1][q], fji_y = c->flow[p][1][q + 1];
+                float Xi = fmaf(th_j, fij_x, (float)(x + hi->m * P->ring_period));
+                float Yi = fmaf(th_j, fij_y, (float)y);
+                float Xj = fmaf(th_i, fji_x, (float)(x + hj->m * P->ring_period));
+                float Yj = fmaf(th_i, fji_y, (float)y);
+                float ti[3], tj[3];
+                sample_color(c, F, pitch, i, Xi, Yi, ti);
+                sample_color(c, F, pitch, j, Xj, Yj, tj);
+                for (int ch = 0; ch < 3; ++ch) o[ch] = (uint8_t)vso_round8(fmaf(th_i, ti[ch] - tj[ch], tj[ch]));
+            }
+        }
+    }
+}
+
+/* ------------------------------------------------------------------------ */
+/* Section 2.2, eqs. (5)-(7): online colour balancing                        */
+/* ------------------------------------------------------------------------ */
+
+/* m1 = smallest level whose cumulative count reaches lambda of the n pixels,
+ * m2 the same for 1 - lambda (integer comparisons, lambda in percent). */
+void vso_quantiles(const uint32_t hist[256], long long n, int lambda_pct, int* q1, int* q2)
+{
+    long long C = 0;
+    *q1 = -1;
+    *q2 = -1;
+    for (int v = 0; v < 256; ++v) {
+        C += hist[v];
+        if (*q1 < 0 && 100LL * C >= (long long)lambda_pct * n) *q1 = v;
+        if (*q2 < 0 && 100LL * C >= (long long)(100 - lambda_pct) * n) *q2 = v;
+    }
+    if (*q1 < 0) *q1 = 0;
+    if (*q2 < 0) *q2 = 255;
+}
+
+/* Eq. (5) piecewise F per channel (reading of the missing figure): the
+ * thresholds go to where an equalised histogram puts its lambda and
+ * 1 - lambda quantiles, t1 = 255 lambda and t2 = 255 (1 - lambda); linear
+ * on [m1, m2], gamma curves a + T (x / T)^b on [0, m1] and [m2, 255] whose
+ * exponents make F continuously differentiable at m1 and m2 (clamped to
+ * [1/8, 8]).  Identity if m2 - m1 < 1.  FP64, rounded half up. */
+void vso_balance_lut(double m1, double m2, int lambda_pct, uint8_t lut[256])
+{
+    double lam = (double)lambda_pct / 100.0;
+    double t1 = 255.0 * lam, t2 = 255.0 * (1.0 - lam);
+    if (m2 - m1 < 1.0) {
+        for (int v = 0; v < 256; ++v) lut[v] = (uint8_t)v;
+        return;
+    }
+    double s = (t2 - t1) / (m2 - m1);
+    double g1 = s * m1 / t1, g2 = s * (255.0 - m2) / (255.0 - t2);
+    if (g1 < 0.125) g1 = 0.125;
+    if (g1 > 8.0) g1 = 8.0;
+    if (g2 < 0.125) g2 = 0.125;
+    if (g2 > 8.0) g2 = 8.0;
+    for (int v = 0; v < 256; ++v) {
+        double x = (double)v, F;
+        if (x < m1) F = t1 * pow(x / m1, g1);
+        else if (x <= m2) F = t1 + s * (x - m1);
+        else F = 255.0 - (255.0 - t2) * pow((255.0 - x) / (255.0 - m2), g2);
+        double f = floor(F + 0.5);
+        if (f < 0) f = 0;
+        if (f > 255) f = 255;
+        lut[v] = (uint8_t)f;
+    }
+}
+
+static void step_balance(vso_ctx* c, uint8_t* pano)
+{
+    const vso_plan_info* P = &c->plan;
+    size_t N = (size_t)P->canvas_w * P->canvas_h;
+    memset(c->pano_hist, 0, sizeof c->pano_hist);
+    long long n = 0;
+    for (size_t q = 0; q < N; ++q) {
+        if (!c->cover[q]) continue;
+        ++n;
+        for (int ch = 0; ch < 3; ++ch) c->pano_hist[ch][c->pano_pre[q * 3 + ch]]++;
+    }
+    for (int ch = 0; ch < 3; ++ch) {
+        int q1, q2;
+        vso_quantiles(c->pano_hist[ch], n, c->prm.lambda_pct, &q1, &q2);
+        c->quant[ch][0] = q1;
+        c->quant[ch][1] = q2;
+        /* eqs. (6)-(7): mean over the current frame and up to two earlier ones */
+        int s1 = q1, s2 = q2, cnt = 1;
+        for (int d = 1; d <= 2 && d <= c->T; ++d) {
+            s1 += c->q_prev[d - 1][ch][0];
+            s2 += c->q_prev[d - 1][ch][1];
+            ++cnt;
+        }
+        c->mbar[ch][0] = (double)s1 / (double)cnt;
+        c->mbar[ch][1] = (double)s2 / (double)cnt;
+        vso_balance_lut(c->mbar[ch][0], c->mbar[ch][1], c->prm.lambda_pct, c->bal_lut[ch]);
+    }
+    for (size_t q = 0; q < N; ++q) {
+        for (int ch = 0; ch < 3; ++ch) {
+            uint8_t v = c->pano_pre[q * 3 + ch];
+            pano[q * 3 + ch] = (c->prm.balance && c->cover[q]) ? c->bal_lut[ch][v] : v;
+        }
+    }
+}
+
+/* ------------------------------------------------------------------------ */
+/* One frame                                                                 */
+/* ------------------------------------------------------------------------ */
+
+int vso_stitch(vso_ctx* c, const uint8_t* const frames[], const int pitch[], uint8_t* pano)
+{
+    if (!c || !frames || !pitch || !pano) return VSO_E_INVAL;
+    for (int k = 0; k < c->plan.n_cams; ++k)
+        if (!frames[k] || pitch[k] < 3 * c->rig.cam_w[k]) return VSO_E_INVAL;
+    step_strips(c, frames, pitch);
+    step_moments(c);
+    step_solve(c);
+    step_pyramids(c);
+    step_flow(c);
+    step_blend(c, frames, pitch);
+    step_balance(c, pano);
+    /* state: shift the per-pair moments and the quantiles, T += 1 */
+    for (int p = 0; p < c->plan.n_pairs; ++p) {
+        c->mom_prev[p][1] = c->mom_prev[p][0];
+        c->mom_prev[p][0] = c->mom[p];
+    }
+    memcpy(c->q_prev[1], c->q_prev[0], sizeof c->q_prev[0]);
+    for (int ch = 0; ch < 3; ++ch) {
+        c->q_prev[0][ch][0] = c->quant[ch][0];
+        c->q_prev[0][ch][1] = c->quant[ch][1];
+    }
+    c->T += 1;
+    return VSO_OK;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Taps                                                                      */
+/* ------------------------------------------------------------------------ */
+
+static int copy_out(void* dst, size_t nbytes, const void* src, size_t have)
+{
+    if (nbytes != have) return VSO_E_INVAL;
+    memcpy(dst, src, have);
+    return VSO_OK;
+}
+
+int vso_get(const vso_ctx* c, int tap, int p, int sub, void* dst, size_t nbytes)
+{
+    const vso_plan_info* P = &c->plan;
+    int pair_ok = p >= 0 && p < P->n_pairs;
+    size_t n = pair_ok ? (size_t)P->strip_w[p] * P->strip_h[p] : 0;
+    switch (tap) {
+    case VSO_TAP_STRIP:
+        if (!pair_ok || sub < 0 || sub > 1) return VSO_E_INVAL;
+        return copy_out(dst, nbytes, c->strip[p][sub], n * 3);
+    case VSO_TAP_MASK:
+        if (!pair_ok) return VSO_E_INVAL;
+        return copy_out(dst, nbytes, c->mask[p], n);
+    case VSO_TAP_HIST:
+        if (!pair_ok) return VSO_E_INVAL;
+        return copy_out(dst, nbytes, c->hist[p], sizeof c->hist[p]);
+    case VSO_TAP_LUT:
+        if (!pair_ok) return VSO_E_INVAL;
+        return copy_out(dst, nbytes, c->lut[p], sizeof c->lut[p]);
+    case VSO_TAP_MOM: {
+        if (!pair_ok) return VSO_E_INVAL;
+        uint64_t m[16];
+        memcpy(m, c->mom[p].A, 6 * 8);
+        memcpy(m + 6, c->mom[p].B, 9 * 8);
+        m[15] = c->mom[p].n;
+        return copy_out(dst, nbytes, m, sizeof m);
+    }
+    case VSO_TAP_MPAIR:
+        return copy_out(dst, nbytes, c->Mpair, (size_t)P->n_pairs * 9 * sizeof(double));
+    case VSO_TAP_MK:
+        return copy_out(dst, nbytes, c->Mk, (size_t)P->n_cams * 9 * sizeof(float));
+    case VSO_TAP_FLAGS:
+        return copy_out(dst, nbytes, c->flags, (size_t)P->n_pairs * sizeof(int));
+    case VSO_TAP_PYR: {
+        int cam = sub / 8, l = sub % 8;
+        if (!pair_ok || cam < 0 || cam > 1 || l >= c->prm.lk_levels) return VSO_E_INVAL;
+        return copy_out(dst, nbytes, c->pyr[p][cam][l], (size_t)c->pw[p][l] * c->ph[p][l] * sizeof(float));
+    }
+    case VSO_TAP_FLOW:
+        if (!pair_ok || sub < 0 || sub > 1) return VSO_E_INVAL;
+        return copy_out(dst, nbytes, c->flow[p][sub], n * 2 * sizeof(float));
+    case VSO_TAP_PANO_PRE:
+        return copy_out(dst, nbytes, c->pano_pre, (size_t)P->canvas_w * P->canvas_h * 3);
+    case VSO_TAP_PANO_HIST:
+        return copy_out(dst, nbytes, c->pano_hist, sizeof c->pano_hist);
+    case VSO_TAP_BAL_LUT:
+        return copy_out(dst, nbytes, c->bal_lut, sizeof c->bal_lut);
+    case VSO_TAP_QUANT:
+        return copy_out(dst, nbytes, c->quant, sizeof c->quant);
+    case VSO_TAP_MBAR:
+        return copy_out(dst, nbytes, c->mbar, sizeof c->mbar);
+    case VSO_TAP_COVER:
+        return copy_out(dst, nbytes, c->cover, (size_t)P->canvas_w * P->canvas_h);
+    default:
+        return VSO_E_INVAL;
+    }
+}

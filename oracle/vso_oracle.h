@@ -1,0 +1,126 @@
+/*
+ * vso_oracle.h -- plain, slow CPU oracle of the per-frame video-stitching path
+ * of "GPU Accelerated Color Correction and Frame Warping for Real-time Video
+ * Stitching" (arXiv 2308.09209).
+ *
+ * TEST INFRASTRUCTURE ONLY.  Only the test suite, the smoke check and the CPU
+ * baseline leg of the benchmark may load this library.  It shares no code,
+ * header, table or helper with the HIP library; the two are independent
+ * implementations of the same definitions.
+ *
+ * Precision: per-pixel geometry, resampling, colour application, the luma
+ * pyramid and the flow are FP32 with every operation order spelled out
+ * (explicit fmaf, no contraction), because each of them decides a uint8 output
+ * and the workload fixes FP32 coordinates; the colour-matrix solve and the
+ * balancing curve are FP64; histograms, quantiles and moments are exact
+ * integers.
+ *
+ * Parity pins: see the "not gpu" tests.  The only step whose shape the paper
+ * does not pin is the balancing curve of section 2.2 (its figure is missing):
+ * "parity unpinned" against the paper; invariants pin it.
+ */
+#ifndef VSO_ORACLE_H
+#define VSO_ORACLE_H
+#include <stddef.h>
+#include <stdint.h>
+
+#define VSO_MAX_CAMS 16
+#define VSO_MAX_PAIRS 16
+#define VSO_MAX_LEVELS 6
+
+enum {
+    VSO_OK = 0,
+    VSO_E_INVAL = -1,
+    VSO_E_GEOMETRY = -2,
+    VSO_E_NOMEM = -3,
+};
+
+typedef struct {
+    int n_cams;
+    int cam_w[VSO_MAX_CAMS];
+    int cam_h[VSO_MAX_CAMS];
+    double H_pair[VSO_MAX_CAMS][9]; /* [k], k >= 1: camera k pixel -> camera k-1 pixel, row-major */
+    double H_ref[9];                /* camera 0 pixel -> canvas pixel */
+    int ring;                       /* 1: 360-degree ring, canvas periodic in x */
+    int ring_period;                /* canvas period in px (ring only) */
+    int canvas_w, canvas_h;
+} vso_rig;
+
+typedef struct {
+    int color_window;   /* 0: no colour transfer; 1: 2D-M (frame T only); 2..3: 3D-M window */
+    double ridge;       /* relative ridge of the colour solve (x trace) */
+    int min_pixels;     /* fewer overlap samples than this -> M = I */
+    int flow;           /* 0: zero flow; 1: pyramidal Lucas-Kanade */
+    int lk_levels, lk_iters, lk_radius;
+    float lk_lambda;
+    int balance;        /* 0: skip the balancing LUT apply; 1: apply */
+    int lambda_pct;     /* balancing quantile, percent (5 -> lambda = 0.05) */
+} vso_params;
+
+void vso_default_params(vso_params* p);
+
+typedef struct vso_ctx vso_ctx;
+
+/* Build the plan of section 2.1 step 1 / section 3.1 (camera-to-canvas
+ * homographies, coverage, overlap pairs and strips).  Returns NULL and sets
+ * *status on error. */
+vso_ctx* vso_create(const vso_rig* rig, const vso_params* p, int* status);
+void vso_destroy(vso_ctx* c);
+
+typedef struct {
+    int canvas_w, canvas_h, n_pairs, n_cams, ring, ring_period;
+    int pair_j[VSO_MAX_PAIRS], pair_i[VSO_MAX_PAIRS], pair_si[VSO_MAX_PAIRS];
+    int strip_x0[VSO_MAX_PAIRS], strip_y0[VSO_MAX_PAIRS];
+    int strip_w[VSO_MAX_PAIRS], strip_h[VSO_MAX_PAIRS];
+    float hinv[VSO_MAX_CAMS][9];   /* canvas -> camera k, FP32 */
+    double hk[VSO_MAX_CAMS][9];    /* camera k -> canvas, FP64 */
+    long long n_covered;
+} vso_plan_info;
+int vso_plan_info_get(const vso_ctx* c, vso_plan_info* out);
+
+/* One frame: frames[k] is camera k's HWC RGB uint8 image with row pitch
+ * pitch[k] bytes; pano receives canvas_h x canvas_w x 3 uint8 (tight).  Uses
+ * and advances the context's colour state. */
+int vso_stitch(vso_ctx* c, const uint8_t* const frames[], const int pitch[], uint8_t* pano);
+/* Forget the colour state (next frame is T = 0). */
+void vso_reset(vso_ctx* c);
+int vso_frames_seen(const vso_ctx* c);
+
+enum {
+    VSO_TAP_STRIP = 1,     /* pair, sub 0=j 1=i : sw*sh*3 u8 */
+    VSO_TAP_MASK = 2,      /* pair : sw*sh u8 */
+    VSO_TAP_HIST = 3,      /* pair : [2][3][256] u32, [0]=camera j, [1]=camera i */
+    VSO_TAP_LUT = 4,       /* pair : [3][256] u8 */
+    VSO_TAP_MOM = 5,       /* pair : 16 u64 = A[6] (00,01,02,11,12,22), B[9] row-major, n */
+    VSO_TAP_MPAIR = 6,     /* [n_pairs][9] f64 */
+    VSO_TAP_MK = 7,        /* [n_cams][9] f32 */
+    VSO_TAP_FLAGS = 8,     /* [n_pairs] i32 */
+    VSO_TAP_PYR = 9,       /* pair, sub = cam*8 + level : w_l*h_l f32 */
+    VSO_TAP_FLOW = 10,     /* pair, sub 0=ij 1=ji : sw*sh*2 f32 */
+    VSO_TAP_PANO_PRE = 11, /* canvas_h*canvas_w*3 u8 */
+    VSO_TAP_PANO_HIST = 12,/* [3][256] u32 */
+    VSO_TAP_BAL_LUT = 13,  /* [3][256] u8 */
+    VSO_TAP_QUANT = 14,    /* [3][2] i32 : q1, q2 of frame T */
+    VSO_TAP_MBAR = 15,     /* [3][2] f64 */
+    VSO_TAP_COVER = 16,    /* canvas_h*canvas_w u8 : number of covering cameras */
+};
+int vso_get(const vso_ctx* c, int tap, int pair, int sub, void* dst, size_t nbytes);
+
+/* ---- individual steps, exposed for the pins ---- */
+void vso_histspec_lut(const uint32_t Gi[256], const uint32_t Gj[256], uint8_t lut[256]);
+/* (A + eps I) M = B + eps I, eps = ridge * trace(A); returns 0 ok, 1 singular */
+int vso_solve_color(const double A[9], const double B[9], double ridge, double M[9]);
+void vso_quantiles(const uint32_t hist[256], long long n, int lambda_pct, int* q1, int* q2);
+void vso_balance_lut(double m1, double m2, int lambda_pct, uint8_t lut[256]);
+void vso_pyr_down(const float* src, int w, int h, float* dst);
+void vso_lk_level(const float* T, const float* Mv, int w, int h,
+                  const float* u_coarse, int wc, int hc,
+                  int radius, int iters, float lambda, float* u_out);
+void vso_lk_level_f64(const double* T, const double* Mv, int w, int h,
+                      const double* u_coarse, int wc, int hc,
+                      int radius, int iters, double lambda, double* u_out);
+int vso_hom_valid(const float h[9], float x, float y, int W, int H, float* u, float* v);
+float vso_bilinear(const uint8_t* F, int pitch, int W, int H, int ch, float u, float v);
+int vso_round8(float r);
+
+#endif

@@ -1,0 +1,249 @@
+"""Seeded synthetic multi-camera scenes: the inputs of the stitching path.
+
+This module only *produces inputs* (camera frames, the rig's homographies and
+the ground truth that generated them).  It holds none of the stitching
+arithmetic: it never resamples with the stitcher's conventions, never rounds
+the way the stitcher does, and is imported by both the GPU tests and the CPU
+oracle tests so that the two sides see identical bytes.
+
+Recipe (the paper's own video database is not available, so these scenes stand
+in for it, with the shapes of the workloads the stitcher is measured on):
+
+* Texture: 0.5 plus 16 sinusoids (orientation U[0, pi), wavelength
+  log-uniform in [8, 128] px, phase U[0, 2 pi), per-channel amplitude
+  U[0, 1/16]), min-max normalised per channel to [0, 1] over the texture
+  domain, then 40 flat-coloured rectangles (sides U[16, H_tex/4], colour
+  U[0,1]^3) painted in order.  In a 360-degree ring the texture is periodic in
+  x: every sinusoid's x-frequency is quantised to whole cycles per ring period
+  and rectangles wrap.
+* Cameras: nominal crop offset x0_k = k * W * (1 - overlap).  The true
+  camera-to-canvas homography is that offset composed with a perturbation about
+  the frame centre: rotation U[-3, 3] deg, scale U[0.98, 1.02], translation
+  U[-10, 10] px, perspective terms U[-1e-4, 1e-4].
+* Residual: a smooth displacement per camera (Gaussian-smoothed white noise,
+  sigma = 20 px, rescaled to a maximum magnitude of 3 px) added after the
+  homography: pixel (u, v) of camera k shows texture(H_k(u, v) + d_k(u, v)).
+  The stitcher is told only the homographies; the residual is what its flow
+  must absorb.
+* Colour: c = clip(g_k(t) * C_k @ rgb, 0, 1) ** gamma_k with C_k diagonal
+  U[0.8, 1.2], off-diagonal U[-0.05, 0.05], gamma_k U[0.9, 1.1]; the exposure
+  gain g_k starts at 1 and, for drifting scenes, takes a Gaussian random-walk
+  step of sigma 0.01 per frame.  Stored as uint8 = floor(255 c + 0.5).
+* Seeds: seed = 1000 * config + 10 * stream + camera (camera-level draws);
+  the texture uses seed = 1000 * config + 10 * stream + 9.
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass, field
+
+import numpy as np
+from scipy.ndimage import gaussian_filter
+
+# Workloads, by what they are.  "frames" is the sequence length the workload is
+# quoted on; the generator produces any number of frames.
+WORKLOADS = {
+    "2x640x360_chain": dict(config=1, n_cams=2, W=640, H=360, overlap=0.30, ring=False,
+                            tex_w=1200, tex_h=400, frames=8, drift=0.0, resid=3.0),
+    "4x1920x1080_ring": dict(config=2, n_cams=4, W=1920, H=1080, overlap=0.20, ring=True,
+                             tex_w=None, tex_h=1200, frames=60, drift=0.01, resid=3.0),
+}
+
+
+def _rot_scale_persp(theta, s, tx, ty, p1, p2):
+    c, si = math.cos(theta), math.sin(theta)
+    return np.array([[s * c, -s * si, tx],
+                     [s * si, s * c, ty],
+                     [p1, p2, 1.0]], dtype=np.float64)
+
+
+def _translate(tx, ty):
+    return np.array([[1.0, 0.0, tx], [0.0, 1.0, ty], [0.0, 0.0, 1.0]], dtype=np.float64)
+
+
+class Texture:
+    """Analytic texture: evaluable at any real canvas coordinate."""
+
+    def __init__(self, rng: np.random.Generator, x_lo: float, x_hi: float, y_lo: float,
+                 y_hi: float, period: float | None):
+        self.period = period
+        theta = rng.uniform(0.0, math.pi, 16)
+        lam = np.exp(rng.uniform(math.log(8.0), math.log(128.0), 16))
+        self.phase = rng.uniform(0.0, 2.0 * math.pi, 16)
+        self.amp = rng.uniform(0.0, 1.0 / 16.0, (16, 3))
+        kx = 2.0 * math.pi * np.cos(theta) / lam
+        ky = 2.0 * math.pi * np.sin(theta) / lam
+        if period is not None:
+            cycles = np.round(kx * period / (2.0 * math.pi))
+            kx = cycles * 2.0 * math.pi / period
+        self.kx, self.ky = kx, ky
+        # per-channel min-max over the texture domain (2 px grid)
+        gx = np.arange(x_lo, x_hi, 2.0)
+        gy = np.arange(y_lo, y_hi, 2.0)
+        lo = np.full(3, np.inf)
+        hi = np.full(3, -np.inf)
+        for y0 in range(0, len(gy), 64):
+            X, Y = np.meshgrid(gx, gy[y0:y0 + 64])
+            v = self._sines(X.ravel(), Y.ravel())
+            lo = np.minimum(lo, v.min(axis=0))
+            hi = np.maximum(hi, v.max(axis=0))
+        self.lo, self.hi = lo, hi
+        tex_h = y_hi - y_lo
+        self.rects = []
+        for _ in range(40):
+            w = rng.uniform(16.0, tex_h / 4.0)
+            h = rng.uniform(16.0, tex_h / 4.0)
+            x0 = rng.uniform(x_lo, x_hi)
+            y0 = rng.uniform(y_lo, y_hi)
+            col = rng.uniform(0.0, 1.0, 3)
+            self.rects.append((x0, y0, w, h, col))
+
+    def _sines(self, X, Y):
+        ph = np.outer(X, self.kx) + np.outer(Y, self.ky) + self.phase
+        return 0.5 + np.sin(ph) @ self.amp
+
+    def __call__(self, X: np.ndarray, Y: np.ndarray) -> np.ndarray:
+        shape = X.shape
+        X = X.ravel()
+        Y = Y.ravel()
+        out = np.clip((self._sines(X, Y) - self.lo) / (self.hi - self.lo), 0.0, 1.0)
+        for (x0, y0, w, h, col) in self.rects:
+            dx = X - x0
+            if self.period is not None:
+                dx = np.mod(dx, self.period)
+            inside = (dx >= 0.0) & (dx < w) & (Y >= y0) & (Y < y0 + h)
+            out[inside] = col
+        return out.reshape(shape + (3,))
+
+
+@dataclass
+class Camera:
+    H_true: np.ndarray          # camera pixel -> canvas, float64 3x3
+    resid: np.ndarray           # (H, W, 2) canvas-unit residual displacement
+    C: np.ndarray               # 3x3 colour matrix (column-vector convention)
+    gamma: float
+    gains: list = field(default_factory=list)   # exposure gain per frame index
+
+
+class Scene:
+    """One camera rig looking at one analytic texture.
+
+    ``rig()`` gives what the stitcher is told (pairwise homographies, camera 0
+    to canvas, canvas size, ring period); ``frames(t)`` gives the uint8 HWC
+    frames of time step t.
+    """
+
+    def __init__(self, n_cams: int, W: int, H: int, overlap: float, ring: bool,
+                 tex_h: int, tex_w: int | None = None, drift: float = 0.0,
+                 resid: float = 3.0, config: int = 0, stream: int = 0,
+                 perturb: bool = True, colour: bool = True):
+        self.n_cams, self.W, self.H, self.ring = n_cams, W, H, ring
+        self.step = int(round(W * (1.0 - overlap)))
+        if ring:
+            self.canvas_w = n_cams * self.step
+            self.period = self.canvas_w
+        else:
+            self.canvas_w = W + (n_cams - 1) * self.step
+            self.period = None
+        self.canvas_h = H
+        self.drift = drift
+        base = 1000 * config + 10 * stream
+        trng = np.random.default_rng(base + 9)
+        my = (tex_h - H) / 2.0
+        if ring:
+            x_lo, x_hi = 0.0, float(self.canvas_w)
+        else:
+            tw = tex_w if tex_w is not None else self.canvas_w
+            mx = (tw - self.canvas_w) / 2.0
+            x_lo, x_hi = -mx, self.canvas_w + mx
+        self.texture = Texture(trng, x_lo, x_hi, -my, H + my, self.period)
+        self.cams: list[Camera] = []
+        cx, cy = (W - 1) / 2.0, (H - 1) / 2.0
+        for k in range(n_cams):
+            rng = np.random.default_rng(base + k)
+            th = math.radians(rng.uniform(-3.0, 3.0))
+            s = rng.uniform(0.98, 1.02)
+            tx, ty = rng.uniform(-10.0, 10.0, 2)
+            p1, p2 = rng.uniform(-1e-4, 1e-4, 2)
+            if not perturb:
+                th, s, tx, ty, p1, p2 = 0.0, 1.0, 0.0, 0.0, 0.0, 0.0
+            P = _rot_scale_persp(th, s, tx, ty, p1, p2)
+            Hk = _translate(k * self.step, 0.0) @ _translate(cx, cy) @ P @ _translate(-cx, -cy)
+            Hk = Hk / Hk[2, 2]
+            noise = rng.standard_normal((2, H, W))
+            d = np.stack([gaussian_filter(noise[0], 20.0, mode="reflect"),
+                          gaussian_filter(noise[1], 20.0, mode="reflect")], axis=-1)
+            mag = np.sqrt((d ** 2).sum(-1)).max()
+            d = d * (resid / mag) if (resid > 0 and mag > 0) else np.zeros_like(d)
+            if colour:
+                C = np.diag(rng.uniform(0.8, 1.2, 3))
+                off = rng.uniform(-0.05, 0.05, (3, 3))
+                C = C + off * (1.0 - np.eye(3))
+                gamma = float(rng.uniform(0.9, 1.1))
+            else:
+                C, gamma = np.eye(3), 1.0
+            cam = Camera(H_true=Hk, resid=d, C=C, gamma=gamma, gains=[1.0])
+            cam._rng = rng  # drift draws continue this camera's stream
+            self.cams.append(cam)
+        self._base_rgb: list[np.ndarray | None] = [None] * n_cams
+
+    # --- what the stitcher is told ---------------------------------------
+    def rig(self) -> dict:
+        Hs = [c.H_true for c in self.cams]
+        H_pair = [np.eye(3)]  # entry 0 unused
+        for k in range(1, self.n_cams):
+            Hp = np.linalg.inv(Hs[k - 1]) @ Hs[k]
+            H_pair.append(Hp / Hp[2, 2])
+        return dict(n_cams=self.n_cams, W=self.W, H=self.H, ring=int(self.ring),
+                    ring_period=int(self.period or 0), canvas_w=self.canvas_w,
+                    canvas_h=self.canvas_h, H_pair=H_pair, H_ref=Hs[0].copy())
+
+    # --- frames -----------------------------------------------------------
+    def base_rgb(self, k: int) -> np.ndarray:
+        if self._base_rgb[k] is None:
+            cam = self.cams[k]
+            out = np.empty((self.H, self.W, 3), dtype=np.float64)
+            us = np.arange(self.W, dtype=np.float64)
+            h = cam.H_true
+            for v0 in range(0, self.H, 64):
+                vs = np.arange(v0, min(v0 + 64, self.H), dtype=np.float64)
+                U, V = np.meshgrid(us, vs)
+                w = h[2, 0] * U + h[2, 1] * V + h[2, 2]
+                X = (h[0, 0] * U + h[0, 1] * V + h[0, 2]) / w
+                Y = (h[1, 0] * U + h[1, 1] * V + h[1, 2]) / w
+                d = cam.resid[v0:v0 + len(vs)]
+                out[v0:v0 + len(vs)] = self.texture(X + d[..., 0], Y + d[..., 1])
+            self._base_rgb[k] = out
+        return self._base_rgb[k]
+
+    def gain(self, k: int, t: int) -> float:
+        cam = self.cams[k]
+        while len(cam.gains) <= t:
+            step = cam._rng.normal(0.0, self.drift) if self.drift > 0 else 0.0
+            cam.gains.append(cam.gains[-1] + step)
+        return cam.gains[t]
+
+    def frame(self, k: int, t: int) -> np.ndarray:
+        cam = self.cams[k]
+        rgb = self.base_rgb(k)
+        c = np.clip(self.gain(k, t) * (rgb @ cam.C.T), 0.0, 1.0) ** cam.gamma
+        return np.floor(255.0 * c + 0.5).astype(np.uint8)
+
+    def frames(self, t: int) -> list[np.ndarray]:
+        return [self.frame(k, t) for k in range(self.n_cams)]
+
+
+def scene_for(workload: str, stream: int = 0, **over) -> Scene:
+    p = dict(WORKLOADS[workload])
+    p.update(over)
+    p.pop("frames", None)
+    return Scene(n_cams=p["n_cams"], W=p["W"], H=p["H"], overlap=p["overlap"], ring=p["ring"],
+                 tex_h=p["tex_h"], tex_w=p["tex_w"], drift=p["drift"], resid=p["resid"],
+                 config=p["config"], stream=stream,
+                 perturb=p.get("perturb", True), colour=p.get("colour", True))
+
+
+def small_scene(n_cams=2, W=96, H=64, overlap=0.35, ring=False, seed_config=90, **kw) -> Scene:
+    """A tiny scene with the same recipe, for parity tests that span a few tiles."""
+    return Scene(n_cams=n_cams, W=W, H=H, overlap=overlap, ring=ring,
+                 tex_h=int(H * 1.2), tex_w=None, config=seed_config, **kw)
