@@ -1,0 +1,175 @@
+#!/usr/bin/env python3
+"""Benchmark of the per-frame stitching path on one MI355X.
+
+One step = one frame through the whole path (pre-warp strips + histograms,
+histogram specification + moments + 3D-M solve, luma pyramids, pyramidal
+flow, local warp + blend, balancing) on the 4 x 1920x1080 ring (20 % overlap,
+6144 x 1080 panorama, exposure drift).  Frames are generated with the seeded
+scene generator, uploaded once and resident in HBM before the timed region.
+
+Prints one JSON line: panorama Mpix/s (value), p50/p99 frame latency, per-step
+device times, the roofline of the dominant kernel (the flow kernel) and the
+CPU oracle timed on a bounded sample of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+FP32_VECTOR_PEAK_TFLOPS = 157.3   # MI355X published FP32 vector peak
+HBM_PEAK_GBS = 8000.0
+
+
+def window_sum(n, r):
+    """sum over positions of the clipped window length along one axis"""
+    return sum(min(x + r, n - 1) - max(x - r, 0) + 1 for x in range(n))
+
+
+def lk_flops_per_frame(info, r, iters):
+    """Algorithmic FP32 flops of the flow kernel per frame (FMA = 2 flops):
+    per window tap 3 FMAs for the normal matrix, then per Gauss-Newton step
+    2 subtractions + 3 FMAs (bilinear), 1 subtraction (residual) and 2 FMAs
+    (right-hand side) = 14 flops; both directions of every pair, every level."""
+    total = 0
+    for p in range(info.n_pairs):
+        w, h = info.strip_w[p], info.strip_h[p]
+        for _ in range(info.lk_levels):
+            taps = window_sum(w, r) * window_sum(h, r)
+            total += 2 * taps * (6 + 14 * iters)
+            w, h = (w + 1) // 2, (h + 1) // 2
+    return total
+
+
+def load_pmc(kernel, workload):
+    """HBM traffic of the kernel measured with rocprofv3 counters, if the record
+    was taken on the current kernel source (else None)."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", f"{kernel}_{workload}_pmc.json")
+    if not os.path.exists(path):
+        return None
+    rec = json.load(open(path))
+    src = open(os.path.join(ROOT, "paper_2308_09209_amd", "csrc", "vs_kernels.hip"), "rb").read()
+    if rec.get("kernels_sha256") != hashlib.sha256(src).hexdigest():
+        return None
+    return rec.get("bytes_per_launch")
+
+
+def cpu_baseline(scene, frames_list, n_frames):
+    from oracle import oracle as O
+    rig = scene.rig()
+    orc = O.Oracle(rig)
+    H, W = orc.canvas
+    t0 = time.perf_counter()
+    for t in range(n_frames):
+        orc.stitch(frames_list[t])
+    dt = time.perf_counter() - t0
+    threads = int(os.environ.get("OMP_NUM_THREADS", "0")) or len(os.sched_getaffinity(0))
+    threads = min(threads, len(os.sched_getaffinity(0)))
+    return dict(value=round(n_frames * H * W / dt / 1e6, 4), unit="Mpix/s", cores=threads,
+                kind="oracle", sample=f"{n_frames} consecutive frames of the same workload, every step "
+                                      f"({dt:.1f} s on {threads} OpenMP threads)")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=300)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--workload", default="4x1920x1080_ring")
+    ap.add_argument("--seq", type=int, default=60, help="distinct frames generated (cycled)")
+    ap.add_argument("--cpu-frames", type=int, default=3)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py: this build measures one GPU; the path's sharding across GPUs is a design "
+              "only (see DESIGN.md). Run with --gpus 1.", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    from paper_2308_09209_amd import vstitch as V
+    from paper_2308_09209_amd.scenes import WORKLOADS, scene_for
+
+    wl = WORKLOADS[args.workload]
+    t_gen = time.perf_counter()
+    scene = scene_for(args.workload)
+    rig = scene.rig()
+    seq = max(1, args.seq)
+    host_frames = []
+    for t in range(seq):
+        host_frames.append(scene.frames(t))
+    print(f"# generated {seq} frames in {time.perf_counter() - t_gen:.1f} s", file=sys.stderr, flush=True)
+    dev = torch.device("cuda:0")
+    frames = [[torch.from_numpy(f).to(dev) for f in fr] for fr in host_frames]
+
+    st = V.Stitcher(rig)
+    info = st.info
+    H, W = st.canvas
+    pano = st.new_pano(dev)
+    torch.cuda.synchronize()
+    for i in range(args.warmup):
+        st.stitch(frames[i % seq], pano=pano)
+    torch.cuda.synchronize()
+    print(f"# warmup done ({args.warmup} frames)", file=sys.stderr, flush=True)
+
+    K = args.steps
+    st.set_timing(True)
+    starts = [torch.cuda.Event(enable_timing=True) for _ in range(K)]
+    ends = [torch.cuda.Event(enable_timing=True) for _ in range(K)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(K):
+        starts[i].record()
+        st.stitch(frames[(args.warmup + i) % seq], pano=pano)
+        ends[i].record()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    wall = t1 - t0
+    lat = np.array([starts[i].elapsed_time(ends[i]) for i in range(K)])
+    step_ms, nfr = st.timing()
+    st.set_timing(False)
+    print(f"# timed {K} frames in {wall:.3f} s", file=sys.stderr, flush=True)
+
+    mpix = K * H * W / wall / 1e6
+    levels = info.lk_levels
+    p = st.params
+    flops = lk_flops_per_frame(info, p.lk_radius, p.lk_iters)
+    lk_launch_ms = step_ms[2] / nfr / levels
+    achieved = flops / levels / (lk_launch_ms * 1e-3) / 1e12
+    traffic = load_pmc("k_lk", args.workload)
+    roofline = dict(bound="alu", kernel="vs::k_lk (pyramidal flow, one launch per level)",
+                    achieved=round(achieved, 3), peak=FP32_VECTOR_PEAK_TFLOPS, unit="TFLOP/s",
+                    frac=round(achieved / FP32_VECTOR_PEAK_TFLOPS, 4),
+                    traffic=traffic, avg_launch_ms=round(lk_launch_ms, 5),
+                    flops_per_launch=int(flops / levels))
+    names = V.Stitcher.TIMING_STEPS
+    out = dict(metric="panorama Mpix/s (4x1080p ring)", value=round(mpix, 2), unit="Mpix/s", n_gpus=1,
+               steps=K, warmup=args.warmup, ms_per_step=round(wall / K * 1e3, 4),
+               higher_is_better=True, scaling="weak", vs_baseline=None, dtype="f32",
+               data="synthetic",
+               config=dict(workload=args.workload, cams=wl["n_cams"], frame=f"{wl['W']}x{wl['H']}",
+                           overlap=wl["overlap"], ring=wl["ring"], panorama=f"{W}x{H}",
+                           seq_frames=seq, flow="plain pyramidal LK (L=4, K=5, r=4)",
+                           parallelism="single GPU"),
+               p50_ms=round(float(np.percentile(lat, 50)), 4),
+               p99_ms=round(float(np.percentile(lat, 99)), 4),
+               step_ms={n: round(v / nfr, 5) for n, v in zip(names, step_ms)},
+               roofline=roofline)
+    if not args.no_cpu_baseline:
+        print(f"# timing the CPU oracle on {args.cpu_frames} frames", file=sys.stderr, flush=True)
+        out["cpu_baseline"] = cpu_baseline(scene, host_frames, min(args.cpu_frames, seq))
+    else:
+        out["cpu_baseline"] = None
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,215 @@
+/*
+ * vstitch.h -- C ABI of the MI355X (gfx950) per-frame video-stitching path of
+ * "GPU Accelerated Color Correction and Frame Warping for Real-time Video
+ * Stitching" (arXiv 2308.09209).
+ *
+ * Problem statement (section 1, section 4): N camera videos are stitched into
+ * one panorama per frame.  The geometric input is the pairwise homographies of
+ * neighbouring cameras (section 3.1, eqs. (12)/(14)); the colour correction
+ * needs the colour information of the previous two frames (eqs. (2)-(3) and
+ * (6)-(7)).  Per frame the library runs, all in hand-written HIP kernels:
+ *   pre-warp of every camera's overlap strip (section 3.1) and its
+ *   per-channel histograms (section 2.1 steps 1-2) -> histogram specification
+ *   (step 3) -> 3D-M colour matrix (eqs. (1)-(4)) -> dense pyramidal flow on
+ *   the corrected overlap strips (section 3.2) -> flow-displaced resampling and
+ *   weighted fusion (eqs. (15)-(18)) -> online piecewise colour balancing of
+ *   the panorama (section 2.2, eqs. (5)-(7)).
+ *
+ * Conventions
+ *  - Images are RGB, 8 bits per channel, HWC (interleaved), row pitch in
+ *    bytes.  Frames and the panorama are caller-owned DEVICE pointers; the
+ *    library never frees or retains them beyond a call.
+ *  - A context owns every workspace it needs (allocated in vs_create, freed in
+ *    vs_destroy).  A context is not thread-safe; distinct contexts are.
+ *  - Every call returns a vs_status; no exception crosses the ABI.  A device
+ *    error is sticky: the context must be destroyed.
+ *  - Numerical degeneracies are not errors: they are reported in
+ *    vs_frame_info (identity colour matrix fallback, identity balancing).
+ */
+#ifndef VSTITCH_H
+#define VSTITCH_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define VS_ABI_VERSION 1
+#define VS_STATE_VERSION 1
+#define VS_MAX_CAMS 16
+#define VS_MAX_PAIRS 16
+#define VS_MAX_LEVELS 6
+
+typedef enum {
+    VS_OK = 0,
+    VS_E_INVAL = -1,       /* NULL pointer, bad size, non-finite or singular homography */
+    VS_E_GEOMETRY = -2,    /* neighbours do not overlap, a pixel covered 3+ times, empty canvas */
+    VS_E_NOMEM = -3,       /* device allocation failed */
+    VS_E_DEVICE = -4,      /* HIP error (sticky) */
+    VS_E_STATE = -5,       /* colour state of another version / pair count */
+    VS_E_UNSUPPORTED = -6
+} vs_status;
+
+/* Camera rig (section 3.1).  Camera k >= 1 is related to camera k-1 by
+ * H_pair[k], which maps camera-k pixel coordinates to camera-(k-1) pixel
+ * coordinates (the paper's H_ij with i = k, j = k-1); H_ref maps camera 0
+ * pixels to canvas pixels.  All matrices row-major, column-vector
+ * convention, pixel centres at integer coordinates.  In a ring (ring = 1,
+ * n_cams >= 3) the canvas is periodic in x with period ring_period, which
+ * must equal canvas_w, and cameras N-1 and 0 form a closing pair. */
+typedef struct {
+    int32_t n_cams;                     /* 2..VS_MAX_CAMS */
+    int32_t cam_w[VS_MAX_CAMS];         /* >= 2 */
+    int32_t cam_h[VS_MAX_CAMS];         /* >= 2 */
+    int32_t cam_pitch[VS_MAX_CAMS];     /* bytes per row, >= 3 * cam_w */
+    double H_pair[VS_MAX_CAMS][9];      /* entry 0 unused */
+    double H_ref[9];
+    int32_t ring;
+    int32_t ring_period;
+    int32_t canvas_w, canvas_h;         /* > 0; the panorama size */
+} vs_rig;
+
+/* Method parameters.  vs_default_params gives the paper's constants:
+ * lambda = 0.05 (section 2.2), a 3-frame temporal window (eqs. (2)-(3),
+ * (6)-(7)); the flow-estimator parameters are this implementation's. */
+typedef struct {
+    int32_t color_window;   /* 0: no colour transfer (M = I); 1: 2D-M; 2-3: 3D-M window (3) */
+    double ridge;           /* relative ridge of the colour solve, x trace(A) (1e-9) */
+    int32_t min_pixels;     /* fewer overlap samples over the window -> M = I (64) */
+    int32_t flow;           /* 0: zero flow; 1: dense pyramidal Lucas-Kanade (1) */
+    int32_t lk_levels;      /* pyramid levels, 1..VS_MAX_LEVELS (4) */
+    int32_t lk_iters;       /* Gauss-Newton steps per level (5) */
+    int32_t lk_radius;      /* window half-size r, window (2r+1)^2, 0..4 (4) */
+    float lk_lambda;        /* Tikhonov weight per window pixel (1.0) */
+    int32_t balance;        /* 1: apply the balancing LUT to covered pixels (1) */
+    int32_t lambda_pct;     /* balancing quantile in percent, 1..49 (5) */
+    int32_t debug_taps;     /* 1: keep a copy of the pre-balance panorama for vs_debug_tap (0) */
+} vs_params;
+
+/* Temporal colour state: the only information carried between frames.
+ * mom[p][0] / mom[p][1] hold the overlap moments of pair p at frames T-1 and
+ * T-2 (A = I_i^T I_i as 00,01,02,11,12,22; B = I_i^T I_j row-major; n the
+ * overlap pixel count; eqs. (1)-(3)); q[0] / q[1] hold the balancing
+ * thresholds (m1, m2) per channel of frames T-1 and T-2 (eqs. (6)-(7)).
+ * A plain POD: save it, restore it, move it between contexts of the same
+ * rig. */
+typedef struct {
+    uint64_t A[6];
+    uint64_t B[9];
+    uint64_t n;
+} vs_moments;
+
+typedef struct {
+    uint32_t version;       /* VS_STATE_VERSION */
+    uint32_t size;          /* sizeof(vs_color_state) */
+    uint32_t n_pairs;
+    uint32_t frames_seen;   /* T of the next frame */
+    vs_moments mom[VS_MAX_PAIRS][2];
+    int32_t q[2][3][2];
+} vs_color_state;
+
+/* What vs_create planned. */
+typedef struct {
+    int32_t canvas_w, canvas_h;
+    int32_t pano_pitch;                 /* bytes per panorama row (= 3 * canvas_w) */
+    int32_t n_cams, n_pairs, ring, ring_period, lk_levels;
+    int32_t pair_j[VS_MAX_PAIRS];       /* left / reference camera of pair p */
+    int32_t pair_i[VS_MAX_PAIRS];       /* right / corrected camera of pair p */
+    int32_t pair_si[VS_MAX_PAIRS];      /* periods camera i is shifted by in the pair (ring closure: 1) */
+    int32_t strip_x0[VS_MAX_PAIRS], strip_y0[VS_MAX_PAIRS];  /* unwrapped canvas coordinates */
+    int32_t strip_w[VS_MAX_PAIRS], strip_h[VS_MAX_PAIRS];
+    int64_t n_covered;                  /* canvas pixels seen by at least one camera */
+    uint64_t workspace_bytes;           /* device bytes owned by the context */
+    uint32_t state_bytes;               /* sizeof(vs_color_state) */
+} vs_plan_info;
+
+/* Per-frame diagnostics (valid after the call returns when requested). */
+typedef struct {
+    float Mk[VS_MAX_CAMS][9];           /* camera -> camera-0 colour matrix, row-vector convention (eq. (4)) */
+    double Mpair[VS_MAX_PAIRS][9];      /* pair matrix, camera i -> camera j */
+    int32_t flags[VS_MAX_PAIRS];        /* 0 ok, 1 too few overlap pixels (M = I), 2 singular (M = I) */
+    int32_t quant[3][2];                /* m1, m2 per channel of this frame */
+    double mbar[3][2];                  /* their 3-frame means (eqs. (6)-(7)) */
+    uint32_t frames_seen;               /* T after this frame */
+} vs_frame_info;
+
+typedef struct vs_ctx vs_ctx;
+
+int vs_abi_version(void);
+const char* vs_status_str(vs_status s);
+
+/* Fill p with the defaults listed in vs_params. */
+vs_status vs_default_params(vs_params* p);
+
+/* Host-only helper (no device work): the camera-to-canvas homographies
+ * H_k = H_ref H_pair[1] ... H_pair[k] in FP64 and their canvas-to-camera
+ * inverses (adjugate scaled so its last entry is 1) rounded to FP32, exactly
+ * as vs_create computes them.  Hk and Hinv hold n_cams x 9 entries. */
+vs_status vs_compose_homographies(const vs_rig* rig, double* Hk, float* Hinv);
+
+/* Plan the rig (coverage of every canvas pixel by every camera on the
+ * device, overlap pairs, strip boxes, pyramid sizes), allocate every
+ * workspace and reset the colour state to T = 0.  p may be NULL (defaults).
+ * Synchronous; uses the null stream.  *out receives the context. */
+vs_status vs_create(const vs_rig* rig, const vs_params* p, vs_ctx** out);
+void vs_destroy(vs_ctx* c);
+vs_status vs_query(const vs_ctx* c, vs_plan_info* out);
+const char* vs_last_error(const vs_ctx* c);
+
+/* Stitch one frame.
+ *  frames[k]: device pointer to camera k's image (cam_h x cam_pitch bytes).
+ *  in: optional host colour state to start from (NULL: continue from the
+ *      context's own device-resident state).
+ *  pano: device pointer, canvas_h x pano_pitch bytes; written completely
+ *      (uncovered pixels are 0).
+ *  out, info: optional host outputs; when either is non-NULL the call waits
+ *      for the stream before returning.
+ *  stream: hipStream_t to run on (NULL: the null stream).
+ * Without out/info the call is asynchronous with respect to the host. */
+vs_status vs_stitch(vs_ctx* c, const uint8_t* const frames[], const vs_color_state* in,
+                    uint8_t* pano, vs_color_state* out, vs_frame_info* info, void* stream);
+
+/* Copy the device-resident colour state out / in (synchronous). */
+vs_status vs_state_get(vs_ctx* c, vs_color_state* out);
+vs_status vs_state_set(vs_ctx* c, const vs_color_state* in);
+
+/* Intermediates of the last frame, copied to host memory dst (nbytes must
+ * match exactly; synchronous).  Layouts:
+ *  VS_TAP_STRIP     pair, sub 0 = camera j, 1 = camera i: strip_h x strip_w x 3 u8
+ *  VS_TAP_MASK      pair: strip_h x strip_w u8 (1 = covered by both cameras)
+ *  VS_TAP_HIST      pair: [2][3][256] u32, [0] camera j, [1] camera i
+ *  VS_TAP_LUT       pair: [3][256] u8 histogram-specification LUT
+ *  VS_TAP_MOM       pair: 16 u64 = A[6], B[9], n of this frame
+ *  VS_TAP_MPAIR     [n_pairs][9] f64;  VS_TAP_MK [n_cams][9] f32;  VS_TAP_FLAGS [n_pairs] i32
+ *  VS_TAP_PYR       pair, sub = cam * 8 + level: level image f32
+ *  VS_TAP_FLOW      pair, sub 0 = flow_ij, 1 = flow_ji: strip_h x strip_w x 2 f32
+ *  VS_TAP_PANO_PRE  canvas_h x canvas_w x 3 u8 (needs debug_taps = 1)
+ *  VS_TAP_PANO_HIST [3][256] u32;  VS_TAP_BAL_LUT [3][256] u8
+ *  VS_TAP_QUANT     [3][2] i32;  VS_TAP_MBAR [3][2] f64
+ *  VS_TAP_COVER     canvas_h x canvas_w u8 (1 = covered) */
+enum {
+    VS_TAP_STRIP = 1, VS_TAP_MASK = 2, VS_TAP_HIST = 3, VS_TAP_LUT = 4, VS_TAP_MOM = 5,
+    VS_TAP_MPAIR = 6, VS_TAP_MK = 7, VS_TAP_FLAGS = 8, VS_TAP_PYR = 9, VS_TAP_FLOW = 10,
+    VS_TAP_PANO_PRE = 11, VS_TAP_PANO_HIST = 12, VS_TAP_BAL_LUT = 13, VS_TAP_QUANT = 14,
+    VS_TAP_MBAR = 15, VS_TAP_COVER = 16
+};
+vs_status vs_debug_tap(vs_ctx* c, int tap, int pair, int sub, void* dst, size_t nbytes);
+
+/* Per-step device time (HIP events on each call's stream), summed over every
+ * frame stitched since timing was last switched on, in milliseconds:
+ *  [0] strips + histograms + moments + colour solve (section 2.1)
+ *  [1] flow-input pyramids            [2] pyramidal flow (section 3.2)
+ *  [3] warp + blend (eqs. (15)-(18))  [4] balancing (section 2.2)
+ *  [5] whole frame
+ * vs_set_timing(c, 1) resets the sums and records events around every later
+ * frame; vs_set_timing(c, 0) stops.  vs_get_timing waits for the recorded
+ * frames to finish and returns the sums and the frame count. */
+vs_status vs_set_timing(vs_ctx* c, int on);
+vs_status vs_get_timing(vs_ctx* c, double ms[6], uint32_t* frames);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -152,8 +152,11 @@ class Oracle:
 
     def __del__(self):
         h = getattr(self, "h", None)
-        if h:
-            lib().vso_destroy(h)
+        if h and _lib is not None:
+            try:
+                _lib.vso_destroy(h)
+            except Exception:  # interpreter shutdown
+                pass
             self.h = None
 
     @property

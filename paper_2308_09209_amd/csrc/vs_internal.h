@@ -1,0 +1,97 @@
+// vs_internal.h -- device-side plan and workspace layout of libvstitch, shared
+// by the host runtime (vs_host.cpp) and the kernels (vs_kernels.hip).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/vstitch.h"
+
+namespace vs {
+
+constexpr int MAXC = VS_MAX_CAMS;
+constexpr int MAXP = VS_MAX_PAIRS;
+constexpr int MAXL = VS_MAX_LEVELS;
+
+// Tile shapes.
+constexpr int STRIP_TX = 64, STRIP_TY = 32;   // strip kernels: 256 threads, 8 rows each
+constexpr int PYR_TX = 64, PYR_TY = 16;       // pyramid kernels: 256 threads, 4 rows each
+constexpr int LK_T = 16;                      // flow kernel: 16 x 16 pixels, one per thread
+constexpr int LK_R_MAX = 4;                   // window half-size limit of the staged tiles
+constexpr int LK_D = 8;                       // displacement the staged moving tile covers
+constexpr int BL_TX = 256, BL_TY = 32;        // blend / balance: 256 threads x 4 px x 8 rows
+
+// Per-frame accumulators, zeroed at the start of every frame.
+struct Accum {
+    uint32_t hist[MAXP][2][3][256];   // [pair][0 = camera j, 1 = camera i][channel][level]
+    unsigned long long A[MAXP][6];
+    unsigned long long B[MAXP][9];
+    unsigned long long n[MAXP];
+    uint32_t pano_hist[3][256];
+};
+
+// Per-frame results (also the taps).
+struct Results {
+    uint8_t lut[MAXP][3][256];
+    double Mpair[MAXP][9];
+    float Mk[MAXC][9];
+    int32_t flags[MAXP];
+    unsigned long long mom[MAXP][16];
+    uint8_t bal_lut[3][256];
+    int32_t quant[3][2];
+    double mbar[3][2];
+};
+
+struct DevPlan {
+    int32_t n_cams, n_pairs, canvas_w, canvas_h, ring, Wp, levels, pano_pitch;
+    int32_t color_window, min_pixels, use_flow, balance, lambda_pct, lk_radius, lk_iters;
+    float lk_lambda;
+    double ridge;
+    int32_t cam_w[MAXC], cam_h[MAXC], cam_pitch[MAXC];
+    float hinv[MAXC][9];
+    int32_t pj[MAXP], pi[MAXP], psi[MAXP];
+    int32_t sx0[MAXP], sy0[MAXP], sw[MAXP], sh[MAXP];
+    int32_t pair_of[MAXC][MAXC];      // unordered camera pair -> pair index (-1: none)
+    int32_t lw[MAXP][MAXL], lh[MAXP][MAXL];
+    // tile tables (prefix sums over pairs / fields)
+    int32_t strip_off[MAXP + 1], strip_tx[MAXP];
+    int32_t pyr_off[MAXL][2 * MAXP + 1], pyr_tx[MAXL][2 * MAXP];   // field f = 2 p + cam
+    int32_t lk_off[MAXL][2 * MAXP + 1], lk_tx[MAXL][2 * MAXP];     // field f = 2 p + dir
+    int32_t blend_tx, blend_ty, cover_words;
+    // device buffers
+    uint32_t* strip[MAXP];             // [2][sh][sw] packed R | G << 8 | B << 16
+    uint8_t* mask[MAXP];               // [sh][sw]
+    float* pyr[MAXP][2][MAXL];         // [h_l][w_l]
+    float2* flow[MAXP][2][MAXL];       // [h_l][w_l], [0] = flow_ij, [1] = flow_ji
+    uint32_t* cover;                   // [canvas_h][cover_words] coverage bits
+    unsigned long long* cand;          // [blend_ty][blend_tx] (camera, shift) candidates
+    Accum* acc;
+    Results* res;
+    vs_color_state* state;
+};
+
+struct FrameSet {
+    const uint8_t* f[MAXC];
+};
+
+// plan-time output of the coverage kernel
+struct PlanScan {
+    int32_t bx0[MAXP], bx1[MAXP], by0[MAXP], by1[MAXP];
+    unsigned long long n_covered;
+    uint32_t err;
+};
+
+// launchers (vs_kernels.hip); all return hipGetLastError() of the launch
+hipError_t launch_plan_scan(const DevPlan* dp, const DevPlan& hp, PlanScan* scan, hipStream_t s);
+hipError_t launch_zero(const DevPlan* dp, Accum* acc, hipStream_t s);
+hipError_t launch_strips(const DevPlan* dp, const DevPlan& hp, FrameSet fs, hipStream_t s);
+hipError_t launch_lut(const DevPlan* dp, const DevPlan& hp, hipStream_t s);
+hipError_t launch_moments_b(const DevPlan* dp, const DevPlan& hp, hipStream_t s);
+hipError_t launch_solve(const DevPlan* dp, hipStream_t s);
+hipError_t launch_pyr0(const DevPlan* dp, const DevPlan& hp, hipStream_t s);
+hipError_t launch_pyr_down(const DevPlan* dp, const DevPlan& hp, int level, hipStream_t s);
+hipError_t launch_lk(const DevPlan* dp, const DevPlan& hp, int level, hipStream_t s);
+hipError_t launch_blend(const DevPlan* dp, const DevPlan& hp, FrameSet fs, uint8_t* pano, hipStream_t s);
+hipError_t launch_balance_lut(const DevPlan* dp, hipStream_t s);
+hipError_t launch_balance_apply(const DevPlan* dp, const DevPlan& hp, uint8_t* pano, hipStream_t s);
+
+}  // namespace vs

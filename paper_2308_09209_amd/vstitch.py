@@ -1,0 +1,303 @@
+"""Python binding of libvstitch (the C ABI in include/vstitch.h).
+
+Argument marshalling only: every step of the stitching path runs in the HIP
+kernels of libvstitch.so.  torch supplies device memory and streams.  There
+is no fallback: if the library is missing, importing the binding fails.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+try:  # load torch first so that libvstitch binds to the HIP runtime torch already holds
+    import torch
+except ImportError:  # pragma: no cover - symbol checks without torch
+    torch = None
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libvstitch.so")
+
+MAX_CAMS = 16
+MAX_PAIRS = 16
+MAX_LEVELS = 6
+STATE_VERSION = 1
+
+STATUS = {0: "VS_OK", -1: "VS_E_INVAL", -2: "VS_E_GEOMETRY", -3: "VS_E_NOMEM", -4: "VS_E_DEVICE",
+          -5: "VS_E_STATE", -6: "VS_E_UNSUPPORTED"}
+TAP = dict(strip=1, mask=2, hist=3, lut=4, mom=5, mpair=6, mk=7, flags=8, pyr=9, flow=10,
+           pano_pre=11, pano_hist=12, bal_lut=13, quant=14, mbar=15, cover=16)
+
+# every symbol include/vstitch.h declares
+EXPORTS = ["vs_abi_version", "vs_status_str", "vs_default_params", "vs_compose_homographies",
+           "vs_create", "vs_destroy", "vs_query", "vs_last_error", "vs_stitch", "vs_state_get",
+           "vs_state_set", "vs_debug_tap", "vs_set_timing", "vs_get_timing"]
+
+
+class Rig(C.Structure):
+    _fields_ = [("n_cams", C.c_int32), ("cam_w", C.c_int32 * MAX_CAMS),
+                ("cam_h", C.c_int32 * MAX_CAMS), ("cam_pitch", C.c_int32 * MAX_CAMS),
+                ("H_pair", (C.c_double * 9) * MAX_CAMS), ("H_ref", C.c_double * 9),
+                ("ring", C.c_int32), ("ring_period", C.c_int32), ("canvas_w", C.c_int32),
+                ("canvas_h", C.c_int32)]
+
+
+class Params(C.Structure):
+    _fields_ = [("color_window", C.c_int32), ("ridge", C.c_double), ("min_pixels", C.c_int32),
+                ("flow", C.c_int32), ("lk_levels", C.c_int32), ("lk_iters", C.c_int32),
+                ("lk_radius", C.c_int32), ("lk_lambda", C.c_float), ("balance", C.c_int32),
+                ("lambda_pct", C.c_int32), ("debug_taps", C.c_int32)]
+
+
+class Moments(C.Structure):
+    _fields_ = [("A", C.c_uint64 * 6), ("B", C.c_uint64 * 9), ("n", C.c_uint64)]
+
+
+class ColorState(C.Structure):
+    _fields_ = [("version", C.c_uint32), ("size", C.c_uint32), ("n_pairs", C.c_uint32),
+                ("frames_seen", C.c_uint32), ("mom", (Moments * 2) * MAX_PAIRS),
+                ("q", ((C.c_int32 * 2) * 3) * 2)]
+
+
+class PlanInfo(C.Structure):
+    _fields_ = [("canvas_w", C.c_int32), ("canvas_h", C.c_int32), ("pano_pitch", C.c_int32),
+                ("n_cams", C.c_int32), ("n_pairs", C.c_int32), ("ring", C.c_int32),
+                ("ring_period", C.c_int32), ("lk_levels", C.c_int32),
+                ("pair_j", C.c_int32 * MAX_PAIRS), ("pair_i", C.c_int32 * MAX_PAIRS),
+                ("pair_si", C.c_int32 * MAX_PAIRS),
+                ("strip_x0", C.c_int32 * MAX_PAIRS), ("strip_y0", C.c_int32 * MAX_PAIRS),
+                ("strip_w", C.c_int32 * MAX_PAIRS), ("strip_h", C.c_int32 * MAX_PAIRS),
+                ("n_covered", C.c_int64), ("workspace_bytes", C.c_uint64),
+                ("state_bytes", C.c_uint32)]
+
+
+class FrameInfo(C.Structure):
+    _fields_ = [("Mk", (C.c_float * 9) * MAX_CAMS), ("Mpair", (C.c_double * 9) * MAX_PAIRS),
+                ("flags", C.c_int32 * MAX_PAIRS), ("quant", (C.c_int32 * 2) * 3),
+                ("mbar", (C.c_double * 2) * 3), ("frames_seen", C.c_uint32)]
+
+
+_lib = None
+
+
+def lib():
+    """The loaded libvstitch.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with __graft_entry__.build()")
+        L = C.CDLL(LIB_PATH)
+        L.vs_abi_version.restype = C.c_int
+        L.vs_status_str.restype = C.c_char_p
+        L.vs_status_str.argtypes = [C.c_int]
+        L.vs_default_params.argtypes = [C.POINTER(Params)]
+        L.vs_compose_homographies.argtypes = [C.POINTER(Rig), C.c_void_p, C.c_void_p]
+        L.vs_create.argtypes = [C.POINTER(Rig), C.POINTER(Params), C.POINTER(C.c_void_p)]
+        L.vs_destroy.argtypes = [C.c_void_p]
+        L.vs_destroy.restype = None
+        L.vs_query.argtypes = [C.c_void_p, C.POINTER(PlanInfo)]
+        L.vs_last_error.restype = C.c_char_p
+        L.vs_last_error.argtypes = [C.c_void_p]
+        L.vs_stitch.argtypes = [C.c_void_p, C.c_void_p, C.POINTER(ColorState), C.c_void_p,
+                                C.POINTER(ColorState), C.POINTER(FrameInfo), C.c_void_p]
+        L.vs_state_get.argtypes = [C.c_void_p, C.POINTER(ColorState)]
+        L.vs_state_set.argtypes = [C.c_void_p, C.POINTER(ColorState)]
+        L.vs_debug_tap.argtypes = [C.c_void_p, C.c_int, C.c_int, C.c_int, C.c_void_p, C.c_size_t]
+        L.vs_set_timing.argtypes = [C.c_void_p, C.c_int]
+        L.vs_get_timing.argtypes = [C.c_void_p, C.c_void_p, C.POINTER(C.c_uint32)]
+        _lib = L
+    return _lib
+
+
+class VSError(RuntimeError):
+    def __init__(self, status, msg=""):
+        super().__init__(f"{STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+def make_rig(rig: dict) -> Rig:
+    r = Rig()
+    n = rig["n_cams"]
+    r.n_cams = n
+    for k in range(n):
+        w = rig["cam_w"][k] if "cam_w" in rig else rig["W"]
+        h = rig["cam_h"][k] if "cam_h" in rig else rig["H"]
+        r.cam_w[k] = w
+        r.cam_h[k] = h
+        r.cam_pitch[k] = rig["cam_pitch"][k] if "cam_pitch" in rig else 3 * w
+    for k in range(1, n):
+        hp = np.asarray(rig["H_pair"][k], dtype=np.float64).ravel()
+        for i in range(9):
+            r.H_pair[k][i] = float(hp[i])
+    href = np.asarray(rig["H_ref"], dtype=np.float64).ravel()
+    for i in range(9):
+        r.H_ref[i] = float(href[i])
+    r.ring = int(rig.get("ring", 0))
+    r.ring_period = int(rig.get("ring_period", 0))
+    r.canvas_w = int(rig["canvas_w"])
+    r.canvas_h = int(rig["canvas_h"])
+    return r
+
+
+def default_params(**over) -> Params:
+    p = Params()
+    lib().vs_default_params(C.byref(p))
+    for k, v in over.items():
+        setattr(p, k, v)
+    return p
+
+
+def compose_homographies(rig: dict):
+    r = make_rig(rig)
+    n = rig["n_cams"]
+    Hk = np.zeros((n, 9), np.float64)
+    Hinv = np.zeros((n, 9), np.float32)
+    st = lib().vs_compose_homographies(C.byref(r), Hk.ctypes.data_as(C.c_void_p),
+                                       Hinv.ctypes.data_as(C.c_void_p))
+    if st != 0:
+        raise VSError(st, "compose")
+    return Hk.reshape(n, 3, 3), Hinv.reshape(n, 3, 3)
+
+
+def _stream_handle(stream):
+    if stream is None:
+        return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+    return C.c_void_p(stream.cuda_stream)
+
+
+class Stitcher:
+    """One stitching context: one camera rig, its workspaces and colour state."""
+
+    def __init__(self, rig: dict, **params):
+        self.rig_struct = make_rig(rig)
+        self.params = default_params(**params)
+        h = C.c_void_p()
+        st = lib().vs_create(C.byref(self.rig_struct), C.byref(self.params), C.byref(h))
+        if st != 0:
+            raise VSError(st, "vs_create")
+        self.h = h
+        info = PlanInfo()
+        lib().vs_query(self.h, C.byref(info))
+        self.info = info
+        self.n_cams = rig["n_cams"]
+        self.cam_shape = [(self.rig_struct.cam_h[k], self.rig_struct.cam_w[k])
+                          for k in range(self.n_cams)]
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().vs_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        self.close()
+
+    @property
+    def canvas(self):
+        return self.info.canvas_h, self.info.canvas_w
+
+    @property
+    def n_pairs(self):
+        return self.info.n_pairs
+
+    def strip_box(self, p):
+        I = self.info
+        return I.strip_x0[p], I.strip_y0[p], I.strip_w[p], I.strip_h[p]
+
+    def _err(self, st, what):
+        raise VSError(st, f"{what}: {lib().vs_last_error(self.h).decode()}")
+
+    def new_pano(self, device="cuda"):
+        H, W = self.canvas
+        return torch.empty((H, W, 3), dtype=torch.uint8, device=device)
+
+    def stitch(self, frames, pano=None, state_in: ColorState | None = None, want_state=False,
+               want_info=False, stream=None):
+        """Stitch one frame of device tensors (H, W, 3) uint8; returns the panorama
+        (and the state / frame info when asked)."""
+        if len(frames) != self.n_cams:
+            raise ValueError("one frame per camera")
+        for k, f in enumerate(frames):
+            if (f.dtype != torch.uint8 or not f.is_cuda or tuple(f.shape) != self.cam_shape[k] + (3,)
+                    or not f.is_contiguous()):
+                raise ValueError(f"frame {k}: need a contiguous cuda uint8 tensor of shape "
+                                 f"{self.cam_shape[k] + (3,)}")
+        if pano is None:
+            pano = self.new_pano(frames[0].device)
+        H, W = self.canvas
+        if pano.dtype != torch.uint8 or tuple(pano.shape) != (H, W, 3) or not pano.is_contiguous():
+            raise ValueError("pano: contiguous uint8 (canvas_h, canvas_w, 3)")
+        ptrs = (C.c_void_p * self.n_cams)(*[f.data_ptr() for f in frames])
+        out = ColorState() if want_state else None
+        info = FrameInfo() if want_info else None
+        st = lib().vs_stitch(self.h, ptrs, C.byref(state_in) if state_in is not None else None,
+                             C.c_void_p(pano.data_ptr()), C.byref(out) if out is not None else None,
+                             C.byref(info) if info is not None else None, _stream_handle(stream))
+        if st != 0:
+            self._err(st, "vs_stitch")
+        if want_state or want_info:
+            return pano, out, info
+        return pano
+
+    def state_get(self) -> ColorState:
+        s = ColorState()
+        st = lib().vs_state_get(self.h, C.byref(s))
+        if st != 0:
+            self._err(st, "vs_state_get")
+        return s
+
+    def state_set(self, s: ColorState):
+        st = lib().vs_state_set(self.h, C.byref(s))
+        if st != 0:
+            self._err(st, "vs_state_set")
+
+    def set_timing(self, on=True):
+        st = lib().vs_set_timing(self.h, 1 if on else 0)
+        if st != 0:
+            self._err(st, "vs_set_timing")
+
+    TIMING_STEPS = ("colour", "pyramids", "flow", "blend", "balance", "frame")
+
+    def timing(self):
+        """(summed step times in ms over the timed frames, number of frames)"""
+        ms = np.zeros(6, np.float64)
+        n = C.c_uint32()
+        st = lib().vs_get_timing(self.h, ms.ctypes.data_as(C.c_void_p), C.byref(n))
+        if st != 0:
+            self._err(st, "vs_get_timing")
+        return ms, n.value
+
+    def tap(self, name: str, pair: int = 0, sub: int = 0) -> np.ndarray:
+        I = self.info
+        H, W = self.canvas
+        sw, sh = (I.strip_w[pair], I.strip_h[pair]) if 0 <= pair < I.n_pairs else (0, 0)
+        shapes = dict(strip=((sh, sw, 3), np.uint8), mask=((sh, sw), np.uint8),
+                      hist=((2, 3, 256), np.uint32), lut=((3, 256), np.uint8), mom=((16,), np.uint64),
+                      mpair=((I.n_pairs, 3, 3), np.float64), mk=((self.n_cams, 3, 3), np.float32),
+                      flags=((I.n_pairs,), np.int32), flow=((sh, sw, 2), np.float32),
+                      pano_pre=((H, W, 3), np.uint8), pano_hist=((3, 256), np.uint32),
+                      bal_lut=((3, 256), np.uint8), quant=((3, 2), np.int32),
+                      mbar=((3, 2), np.float64), cover=((H, W), np.uint8))
+        if name == "pyr":
+            w, h = sw, sh
+            for _ in range(sub % 8):
+                w, h = (w + 1) // 2, (h + 1) // 2
+            shape, dt = (h, w), np.float32
+        else:
+            shape, dt = shapes[name]
+        out = np.zeros(shape, dt)
+        st = lib().vs_debug_tap(self.h, TAP[name], pair, sub, out.ctypes.data_as(C.c_void_p),
+                                out.nbytes)
+        if st != 0:
+            self._err(st, f"vs_debug_tap({name})")
+        return out
+
+
+def state_bytes(s: ColorState) -> bytes:
+    return bytes(s)
+
+
+def state_from_bytes(b: bytes) -> ColorState:
+    s = ColorState()
+    C.memmove(C.addressof(s), b, C.sizeof(s))
+    return s

@@ -1,0 +1,96 @@
+"""Host-side checks of the C ABI (no GPU): the library loads, exports every
+function include/vstitch.h declares, its structs have the header's layout,
+and the host planner's homographies are the oracle's bit for bit."""
+import ctypes as C
+import os
+import re
+import subprocess
+
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_2308_09209_amd import vstitch as V
+from paper_2308_09209_amd.scenes import small_scene, scene_for
+from tests.rigs import crop_rig, smooth_image
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "vstitch.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(vs_[a-z_]+)\s*\(", text)))
+
+
+def test_library_exports_every_declared_function():
+    names = declared_functions()
+    assert len(names) >= 14
+    L = V.lib()
+    for n in names:
+        assert hasattr(L, n), n
+    assert sorted(V.EXPORTS) == names
+    assert L.vs_abi_version() == 1
+
+
+def test_struct_layouts_match_the_header(tmp_path):
+    src = tmp_path / "sz.c"
+    src.write_text('#include "vstitch.h"\n#include <stdio.h>\n#include <stddef.h>\n'
+                   'int main(void){printf("%zu %zu %zu %zu %zu %zu %zu\\n", sizeof(vs_color_state),'
+                   'sizeof(vs_rig), sizeof(vs_params), sizeof(vs_plan_info), sizeof(vs_frame_info),'
+                   'offsetof(vs_color_state, q), offsetof(vs_rig, ring));return 0;}\n')
+    exe = tmp_path / "sz"
+    subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), "-o", str(exe), str(src)], check=True)
+    got = [int(v) for v in subprocess.run([str(exe)], capture_output=True, text=True).stdout.split()]
+    want = [C.sizeof(V.ColorState), C.sizeof(V.Rig), C.sizeof(V.Params), C.sizeof(V.PlanInfo),
+            C.sizeof(V.FrameInfo), V.ColorState.q.offset, V.Rig.ring.offset]
+    assert got == want
+
+
+def test_default_params_are_the_papers():
+    p = V.default_params()
+    assert p.lambda_pct == 5 and p.color_window == 3
+    assert (p.lk_levels, p.lk_iters, p.lk_radius, p.lk_lambda) == (4, 5, 4, 1.0)
+    assert V.lib().vs_status_str(-2) == b"geometry"
+
+
+@pytest.mark.parametrize("rigf", [lambda: small_scene(n_cams=3, ring=True, W=120, H=64).rig(),
+                                  lambda: scene_for("2x640x360_chain").rig()])
+def test_host_planner_homographies_match_oracle_bitwise(rigf):
+    rig = rigf()
+    Hk, Hinv = V.compose_homographies(rig)
+    o = O.Oracle(rig)
+    n = rig["n_cams"]
+    assert np.array_equal(np.array(o.plan.hk)[:n].reshape(n, 3, 3), Hk)
+    assert np.array_equal(np.array(o.plan.hinv)[:n].reshape(n, 3, 3), Hinv)
+    assert np.all(Hinv[:, 2, 2] == 1.0)
+
+
+def test_invalid_rigs_rejected_before_any_device_work():
+    tex = smooth_image(20, 200, seed=1)
+    rig, _ = crop_rig(tex, 100, 20, [(0, 0), (60, 0)])
+    bad = []
+    r = dict(rig)
+    r["n_cams"] = 1
+    bad.append(r)
+    r = dict(rig)
+    r["ring"], r["ring_period"] = 1, 160   # a ring needs >= 3 cameras
+    bad.append(r)
+    r = dict(rig)
+    r["cam_pitch"] = [200, 300]            # pitch below 3 * width
+    bad.append(r)
+    r = dict(rig)
+    r["H_pair"] = [np.eye(3), np.full((3, 3), np.nan)]
+    bad.append(r)
+    r = dict(rig)
+    r["canvas_w"] = 0
+    bad.append(r)
+    for b in bad:
+        with pytest.raises(V.VSError) as e:
+            V.Stitcher(b)
+        assert e.value.status == -1
+    with pytest.raises(V.VSError):
+        V.Stitcher(rig, lk_radius=9)
+    with pytest.raises(V.VSError):
+        V.Stitcher(rig, lambda_pct=60)
