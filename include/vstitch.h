@@ -188,12 +188,18 @@ vs_status vs_state_set(vs_ctx* c, const vs_color_state* in);
  *  VS_TAP_PANO_PRE  canvas_h x canvas_w x 3 u8 (needs debug_taps = 1)
  *  VS_TAP_PANO_HIST [3][256] u32;  VS_TAP_BAL_LUT [3][256] u8
  *  VS_TAP_QUANT     [3][2] i32;  VS_TAP_MBAR [3][2] f64
- *  VS_TAP_COVER     canvas_h x canvas_w u8 (1 = covered) */
+ *  VS_TAP_COVER     canvas_h x canvas_w u8 (1 = covered)
+ *  VS_TAP_NEED      pair, sub = level: u8 per level pixel, 1 where the flow is
+ *                   estimated (the overlap at level 0, and at coarser levels the
+ *                   pixels the finer level's initialisation samples); 0 elsewhere
+ *                   and the flow there is 0
+ *  VS_TAP_DEFERRED  sub = level: u32, flow pixels of that level finished by the
+ *                   global-memory tail kernel (displacement beyond the staged tile) */
 enum {
     VS_TAP_STRIP = 1, VS_TAP_MASK = 2, VS_TAP_HIST = 3, VS_TAP_LUT = 4, VS_TAP_MOM = 5,
     VS_TAP_MPAIR = 6, VS_TAP_MK = 7, VS_TAP_FLAGS = 8, VS_TAP_PYR = 9, VS_TAP_FLOW = 10,
     VS_TAP_PANO_PRE = 11, VS_TAP_PANO_HIST = 12, VS_TAP_BAL_LUT = 13, VS_TAP_QUANT = 14,
-    VS_TAP_MBAR = 15, VS_TAP_COVER = 16
+    VS_TAP_MBAR = 15, VS_TAP_COVER = 16, VS_TAP_NEED = 17, VS_TAP_DEFERRED = 18
 };
 vs_status vs_debug_tap(vs_ctx* c, int tap, int pair, int sub, void* dst, size_t nbytes);
 

@@ -19,7 +19,7 @@ MAX_CAMS = 16
 MAX_PAIRS = 16
 
 TAP = dict(strip=1, mask=2, hist=3, lut=4, mom=5, mpair=6, mk=7, flags=8, pyr=9, flow=10,
-           pano_pre=11, pano_hist=12, bal_lut=13, quant=14, mbar=15, cover=16)
+           pano_pre=11, pano_hist=12, bal_lut=13, quant=14, mbar=15, cover=16, need=17)
 
 
 def build(verbose: bool = False) -> str:
@@ -83,7 +83,7 @@ def lib():
         L.vso_balance_lut.argtypes = [C.c_double, C.c_double, C.c_int, C.c_void_p]
         L.vso_pyr_down.argtypes = [C.c_void_p, C.c_int, C.c_int, C.c_void_p]
         L.vso_lk_level.argtypes = [C.c_void_p, C.c_void_p, C.c_int, C.c_int, C.c_void_p, C.c_int,
-                                   C.c_int, C.c_int, C.c_int, C.c_float, C.c_void_p]
+                                   C.c_int, C.c_int, C.c_int, C.c_float, C.c_void_p, C.c_void_p]
         L.vso_lk_level_f64.argtypes = [C.c_void_p, C.c_void_p, C.c_int, C.c_int, C.c_void_p,
                                        C.c_int, C.c_int, C.c_int, C.c_int, C.c_double, C.c_void_p]
         L.vso_hom_valid.argtypes = [C.c_void_p, C.c_float, C.c_float, C.c_int, C.c_int,
@@ -208,12 +208,12 @@ class Oracle:
             out = np.zeros((self.n_cams, 3, 3), np.float32)
         elif name == "flags":
             out = np.zeros(P.n_pairs, np.int32)
-        elif name == "pyr":
+        elif name in ("pyr", "need"):
             lvl = sub % 8
             w, h = sw, sh
             for _ in range(lvl):
                 w, h = (w + 1) // 2, (h + 1) // 2
-            out = np.zeros((h, w), np.float32)
+            out = np.zeros((h, w), np.float32 if name == "pyr" else np.uint8)
         elif name == "flow":
             out = np.zeros((sh, sw, 2), np.float32)
         elif name == "pano_pre":
@@ -275,17 +275,19 @@ def pyr_down(img) -> np.ndarray:
     return out
 
 
-def lk_level(T, Mv, u_coarse=None, radius=4, iters=5, lam=1.0) -> np.ndarray:
+def lk_level(T, Mv, u_coarse=None, radius=4, iters=5, lam=1.0, need=None) -> np.ndarray:
     T = np.ascontiguousarray(T, np.float32)
     Mv = np.ascontiguousarray(Mv, np.float32)
     h, w = T.shape
     out = np.zeros((h, w, 2), np.float32)
+    nd = None if need is None else np.ascontiguousarray(need, np.uint8)
+    ndp = None if nd is None else _ptr(nd)
     if u_coarse is not None:
         uc = np.ascontiguousarray(u_coarse, np.float32)
         lib().vso_lk_level(_ptr(T), _ptr(Mv), w, h, _ptr(uc), uc.shape[1], uc.shape[0], radius,
-                           iters, lam, _ptr(out))
+                           iters, lam, ndp, _ptr(out))
     else:
-        lib().vso_lk_level(_ptr(T), _ptr(Mv), w, h, None, 0, 0, radius, iters, lam, _ptr(out))
+        lib().vso_lk_level(_ptr(T), _ptr(Mv), w, h, None, 0, 0, radius, iters, lam, ndp, _ptr(out))
     return out
 
 

@@ -113,6 +113,7 @@ struct vso_ctx {
     float Mk[VSO_MAX_CAMS][9];
     int flags[VSO_MAX_PAIRS];
     float* pyr[VSO_MAX_PAIRS][2][VSO_MAX_LEVELS];
+    uint8_t* need[VSO_MAX_PAIRS][VSO_MAX_LEVELS];
     int pw[VSO_MAX_PAIRS][VSO_MAX_LEVELS], ph[VSO_MAX_PAIRS][VSO_MAX_LEVELS];
     float* flow[VSO_MAX_PAIRS][2];
     uint8_t* pano_pre;
@@ -318,6 +319,7 @@ static void free_ctx(vso_ctx* c)
         free(c->flow[p][1]);
         for (int k = 0; k < 2; ++k)
             for (int l = 0; l < VSO_MAX_LEVELS; ++l) free(c->pyr[p][k][l]);
+        for (int l = 0; l < VSO_MAX_LEVELS; ++l) free(c->need[p][l]);
     }
     free(c->pano_pre);
     free(c);
@@ -359,6 +361,7 @@ vso_ctx* vso_create(const vso_rig* rig, const vso_params* prm, int* status)
             c->pw[p][l] = w;
             c->ph[p][l] = h;
             for (int k = 0; k < 2; ++k) c->pyr[p][k][l] = (float*)calloc((size_t)w * h, sizeof(float));
+            c->need[p][l] = (uint8_t*)calloc((size_t)w * h, 1);
             w = (w + 1) / 2;
             h = (h + 1) / 2;
         }
@@ -617,7 +620,9 @@ static float img_at(const float* I, int w, int h, int x, int y)
     return I[(size_t)clampi(y, 0, h - 1) * w + clampi(x, 0, w - 1)];
 }
 
-/* Dense pyramidal Lucas-Kanade at one level (the flow estimator reading):
+/* Dense pyramidal Lucas-Kanade at one level (the flow estimator reading),
+ * evaluated at the pixels marked in `need` (all pixels when need is NULL;
+ * the others get flow 0):
  * for every pixel x, with template T and moving image Mv, minimise
  * sum_{x' in window} (Mv(x' + u) - T(x'))^2 over the (2r+1)^2 window clipped
  * to the level, by `iters` Gauss-Newton steps with the template gradient
@@ -632,11 +637,16 @@ static float img_at(const float* I, int w, int h, int x, int y)
  * of the coarser flow at ((x + 1/2)/2 - 1/2, (y + 1/2)/2 - 1/2). */
 void vso_lk_level(const float* T, const float* Mv, int w, int h,
                   const float* uc, int wc, int hc,
-                  int r, int iters, float lambda, float* u_out)
+                  int r, int iters, float lambda, const uint8_t* need, float* u_out)
 {
 #pragma omp parallel for schedule(dynamic, 4)
     for (int y = 0; y < h; ++y) {
         for (int x = 0; x < w; ++x) {
+            if (need && !need[(size_t)y * w + x]) {
+                u_out[((size_t)y * w + x) * 2 + 0] = 0.0f;
+                u_out[((size_t)y * w + x) * 2 + 1] = 0.0f;
+                continue;
+            }
             float ux = 0.0f, uy = 0.0f;
             if (uc) {
                 float cx = clampf(fmaf((float)x, 0.5f, -0.25f), 0.0f, (float)(wc - 1));
@@ -807,6 +817,34 @@ static void step_pyramids(vso_ctx* c)
     }
 }
 
+/* Where the flow is estimated (section 3.2 computes it between the overlap
+ * regions): at level 0 the overlap pixels of the strip (the mask); at a
+ * coarser level the pixels that the finer level's initialisation samples
+ * (the two-by-two bilinear footprint of every needed finer pixel). */
+static void build_need(vso_ctx* c, int p)
+{
+    size_t n0 = (size_t)c->pw[p][0] * c->ph[p][0];
+    memcpy(c->need[p][0], c->mask[p], n0);
+    for (int l = 0; l + 1 < c->prm.lk_levels; ++l) {
+        int w = c->pw[p][l], h = c->ph[p][l], wc = c->pw[p][l + 1], hc = c->ph[p][l + 1];
+        uint8_t* dst = c->need[p][l + 1];
+        memset(dst, 0, (size_t)wc * hc);
+        for (int y = 0; y < h; ++y)
+            for (int x = 0; x < w; ++x) {
+                if (!c->need[p][l][(size_t)y * w + x]) continue;
+                float cx = clampf(fmaf((float)x, 0.5f, -0.25f), 0.0f, (float)(wc - 1));
+                float cy = clampf(fmaf((float)y, 0.5f, -0.25f), 0.0f, (float)(hc - 1));
+                int x0 = (int)floorf(cx), y0 = (int)floorf(cy);
+                int x1 = x0 + 1 < wc ? x0 + 1 : wc - 1;
+                int y1 = y0 + 1 < hc ? y0 + 1 : hc - 1;
+                dst[(size_t)y0 * wc + x0] = 1;
+                dst[(size_t)y0 * wc + x1] = 1;
+                dst[(size_t)y1 * wc + x0] = 1;
+                dst[(size_t)y1 * wc + x1] = 1;
+            }
+    }
+}
+
 /* flow_ij satisfies P_i(x + flow_ij(x)) ~ P_j(x): template j, moving i;
  * flow_ji the other way round.  Coarse to fine. */
 static void step_flow(vso_ctx* c)
@@ -815,6 +853,7 @@ static void step_flow(vso_ctx* c)
     int L = c->prm.lk_levels;
     for (int p = 0; p < P->n_pairs; ++p) {
         size_t n0 = (size_t)P->strip_w[p] * P->strip_h[p];
+        build_need(c, p);
         for (int dir = 0; dir < 2; ++dir) {
             if (!c->prm.flow) {
                 memset(c->flow[p][dir], 0, n0 * 2 * sizeof(float));
@@ -828,7 +867,7 @@ static void step_flow(vso_ctx* c)
                 int w = c->pw[p][l], h = c->ph[p][l];
                 float* u = (l == 0) ? c->flow[p][dir] : (float*)malloc((size_t)w * h * 2 * sizeof(float));
                 vso_lk_level(c->pyr[p][tmpl][l], c->pyr[p][mov][l], w, h, prev, pwc, phc,
-                             c->prm.lk_radius, c->prm.lk_iters, c->prm.lk_lambda, u);
+                             c->prm.lk_radius, c->prm.lk_iters, c->prm.lk_lambda, c->need[p][l], u);
                 free(prev);
                 prev = (l == 0) ? NULL : u;
                 pwc = w;
@@ -1085,6 +1124,9 @@ int vso_get(const vso_ctx* c, int tap, int p, int sub, void* dst, size_t nbytes)
         return copy_out(dst, nbytes, c->mbar, sizeof c->mbar);
     case VSO_TAP_COVER:
         return copy_out(dst, nbytes, c->cover, (size_t)P->canvas_w * P->canvas_h);
+    case VSO_TAP_NEED:
+        if (!pair_ok || sub < 0 || sub >= c->prm.lk_levels) return VSO_E_INVAL;
+        return copy_out(dst, nbytes, c->need[p][sub], (size_t)c->pw[p][sub] * c->ph[p][sub]);
     default:
         return VSO_E_INVAL;
     }

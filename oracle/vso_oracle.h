@@ -103,6 +103,7 @@ enum {
     VSO_TAP_QUANT = 14,    /* [3][2] i32 : q1, q2 of frame T */
     VSO_TAP_MBAR = 15,     /* [3][2] f64 */
     VSO_TAP_COVER = 16,    /* canvas_h*canvas_w u8 : number of covering cameras */
+    VSO_TAP_NEED = 17,     /* pair, sub = level : w_l*h_l u8, 1 where the flow is estimated */
 };
 int vso_get(const vso_ctx* c, int tap, int pair, int sub, void* dst, size_t nbytes);
 
@@ -115,7 +116,7 @@ void vso_balance_lut(double m1, double m2, int lambda_pct, uint8_t lut[256]);
 void vso_pyr_down(const float* src, int w, int h, float* dst);
 void vso_lk_level(const float* T, const float* Mv, int w, int h,
                   const float* u_coarse, int wc, int hc,
-                  int radius, int iters, float lambda, float* u_out);
+                  int radius, int iters, float lambda, const uint8_t* need, float* u_out);
 void vso_lk_level_f64(const double* T, const double* Mv, int w, int h,
                       const double* u_coarse, int wc, int hc,
                       int radius, int iters, double lambda, double* u_out);

@@ -286,24 +286,49 @@ vs_status vs_create(const vs_rig* rig, const vs_params* prm, vs_ctx** out)
     }
     for (int l = 0; l < h.levels; ++l) {
         h.pyr_off[l][0] = 0;
-        h.lk_off[l][0] = 0;
         for (int f = 0; f < 2 * h.n_pairs; ++f) {
             const int p = f >> 1, w = h.lw[p][l], hh = h.lh[p][l];
             h.pyr_tx[l][f] = (w + PYR_TX - 1) / PYR_TX;
             h.pyr_off[l][f + 1] = h.pyr_off[l][f] + h.pyr_tx[l][f] * ((hh + PYR_TY - 1) / PYR_TY);
-            h.lk_tx[l][f] = (w + LK_T - 1) / LK_T;
-            h.lk_off[l][f + 1] = h.lk_off[l][f] + h.lk_tx[l][f] * ((hh + LK_T - 1) / LK_T);
+        }
+        // flow kernel: the 9x9-window kernel with 4 px per thread where that still
+        // gives >= 1024 blocks, else 1 px per thread; other radii use the generic kernel
+        auto tiles = [&](int tx, int ty) {
+            int n = 0;
+            for (int f = 0; f < 2 * h.n_pairs; ++f) {
+                const int p = f >> 1;
+                n += ((h.lw[p][l] + tx - 1) / tx) * ((h.lh[p][l] + ty - 1) / ty);
+            }
+            return n;
+        };
+        int tx = LK_T, ty = LK_T;
+        h.lk_P[l] = 0;
+        if (P.lk_radius == LK_R_MAX) {
+            h.lk_P[l] = tiles(LKW_TX, 16) >= 1024 ? 4 : 1;
+            tx = LKW_TX;
+            ty = 4 * h.lk_P[l];
+        }
+        h.lk_off[l][0] = 0;
+        for (int f = 0; f < 2 * h.n_pairs; ++f) {
+            const int p = f >> 1, w = h.lw[p][l], hh = h.lh[p][l];
+            h.lk_tx[l][f] = (w + tx - 1) / tx;
+            h.lk_off[l][f + 1] = h.lk_off[l][f] + h.lk_tx[l][f] * ((hh + ty - 1) / ty);
         }
     }
     // ---- workspace arena ----
     size_t off = 0;
-    size_t o_strip[MAXP], o_mask[MAXP], o_pyr[MAXP][2][MAXL], o_flow[MAXP][2][MAXL];
+    size_t o_strip[MAXP], o_mask[MAXP], o_pyr[MAXP][2][MAXL], o_flow[MAXP][2][MAXL], o_need[MAXP][MAXL];
+    size_t o_queue[MAXL];
     for (int p = 0; p < h.n_pairs; ++p) {
         const size_t n = (size_t)h.sw[p] * h.sh[p];
         o_strip[p] = off;
         off = align_up(off + 2 * n * 4, 256);
         o_mask[p] = off;
         off = align_up(off + n, 256);
+        for (int l = 0; l < h.levels; ++l) {
+            o_need[p][l] = off;
+            off = align_up(off + (size_t)h.lw[p][l] * h.lh[p][l], 256);
+        }
         for (int k = 0; k < 2; ++k)
             for (int l = 0; l < h.levels; ++l) {
                 o_pyr[p][k][l] = off;
@@ -311,6 +336,14 @@ vs_status vs_create(const vs_rig* rig, const vs_params* prm, vs_ctx** out)
                 o_flow[p][k][l] = off;
                 off = align_up(off + (size_t)h.lw[p][l] * h.lh[p][l] * 8, 256);
             }
+    }
+    for (int l = 0; l < h.levels; ++l) {
+        // every flow pixel of the level can be deferred at most once per frame
+        size_t cap = 0;
+        for (int p = 0; p < h.n_pairs; ++p) cap += 2 * (size_t)h.lw[p][l] * h.lh[p][l];
+        h.lk_qcap[l] = h.lk_P[l] > 0 ? (int32_t)cap : 0;
+        o_queue[l] = off;
+        off = align_up(off + (size_t)h.lk_qcap[l] * 16, 256);
     }
     const size_t o_acc = off;
     off = align_up(off + sizeof(Accum), 256);
@@ -324,9 +357,11 @@ vs_status vs_create(const vs_rig* rig, const vs_params* prm, vs_ctx** out)
         return VS_E_NOMEM;
     }
     uint8_t* base = (uint8_t*)c->arena;
+    for (int l = 0; l < h.levels; ++l) h.lk_queue[l] = (uint4*)(base + o_queue[l]);
     for (int p = 0; p < h.n_pairs; ++p) {
         h.strip[p] = (uint32_t*)(base + o_strip[p]);
         h.mask[p] = base + o_mask[p];
+        for (int l = 0; l < h.levels; ++l) h.need[p][l] = base + o_need[p][l];
         for (int k = 0; k < 2; ++k)
             for (int l = 0; l < h.levels; ++l) {
                 h.pyr[p][k][l] = (float*)(base + o_pyr[p][k][l]);
@@ -344,6 +379,8 @@ vs_status vs_create(const vs_rig* rig, const vs_params* prm, vs_ctx** out)
         }
     }
     if ((e = hipMemcpy(c->dp, &h, sizeof h, hipMemcpyHostToDevice)) != hipSuccess) return cleanup_dev(e, "hipMemcpy");
+    if ((e = launch_need(c->dp, h, nullptr)) != hipSuccess) return cleanup_dev(e, "flow domain launch");
+    if ((e = hipDeviceSynchronize()) != hipSuccess) return cleanup_dev(e, "flow domain");
     vs_color_state s0;
     std::memset(&s0, 0, sizeof s0);
     s0.version = VS_STATE_VERSION;
@@ -600,6 +637,12 @@ vs_status vs_debug_tap(vs_ctx* c, int tap, int p, int sub, void* dst, size_t nby
         return copy(&h.res->quant[0][0], 6 * 4);
     case VS_TAP_MBAR:
         return copy(&h.res->mbar[0][0], 6 * 8);
+    case VS_TAP_NEED:
+        if (!pair_ok || sub < 0 || sub >= h.levels) return VS_E_INVAL;
+        return copy(h.need[p][sub], (size_t)h.lw[p][sub] * h.lh[p][sub]);
+    case VS_TAP_DEFERRED:
+        if (sub < 0 || sub >= h.levels) return VS_E_INVAL;
+        return copy(&h.acc->lk_qn[sub], 4);
     case VS_TAP_COVER: {
         const size_t npx = (size_t)h.canvas_w * h.canvas_h;
         if (nbytes != npx) return fail(c, VS_E_INVAL, "tap size mismatch");

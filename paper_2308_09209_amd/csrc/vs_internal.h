@@ -15,10 +15,13 @@ constexpr int MAXL = VS_MAX_LEVELS;
 // Tile shapes.
 constexpr int STRIP_TX = 64, STRIP_TY = 32;   // strip kernels: 256 threads, 8 rows each
 constexpr int PYR_TX = 64, PYR_TY = 16;       // pyramid kernels: 256 threads, 4 rows each
-constexpr int LK_T = 16;                      // flow kernel: 16 x 16 pixels, one per thread
+constexpr int LK_T = 16;                      // generic flow kernel: 16 x 16 pixels, one per thread
 constexpr int LK_R_MAX = 4;                   // window half-size limit of the staged tiles
 constexpr int LK_D = 8;                       // displacement the staged moving tile covers
-constexpr int BL_TX = 256, BL_TY = 32;        // blend / balance: 256 threads x 4 px x 8 rows
+constexpr int LKW_TX = 64;                    // 9x9-window flow kernel: 64 px wide, 4 * P rows,
+                                              // P vertically adjacent pixels per thread
+constexpr int BL_TX = 256, BL_TY = 32;        // blend / balance tile: 256 x 32 px
+constexpr int BL_THREADS = 1024;              // 64 quads of 4 px x 16 rows, 2 rows per thread
 
 // Per-frame accumulators, zeroed at the start of every frame.
 struct Accum {
@@ -27,7 +30,9 @@ struct Accum {
     unsigned long long B[MAXP][9];
     unsigned long long n[MAXP];
     uint32_t pano_hist[3][256];
+    uint32_t lk_qn[8];                // flow pixels deferred to the tail kernel, per level
 };
+static_assert(MAXL <= 8, "one deferral counter per level");
 
 // Per-frame results (also the taps).
 struct Results {
@@ -56,12 +61,16 @@ struct DevPlan {
     int32_t strip_off[MAXP + 1], strip_tx[MAXP];
     int32_t pyr_off[MAXL][2 * MAXP + 1], pyr_tx[MAXL][2 * MAXP];   // field f = 2 p + cam
     int32_t lk_off[MAXL][2 * MAXP + 1], lk_tx[MAXL][2 * MAXP];     // field f = 2 p + dir
+    int32_t lk_P[MAXL];               // 0: generic kernel (16 x 16 tiles); 1, 2, 4: 9x9 kernel, P px per thread
     int32_t blend_tx, blend_ty, cover_words;
     // device buffers
     uint32_t* strip[MAXP];             // [2][sh][sw] packed R | G << 8 | B << 16
     uint8_t* mask[MAXP];               // [sh][sw]
     float* pyr[MAXP][2][MAXL];         // [h_l][w_l]
     float2* flow[MAXP][2][MAXL];       // [h_l][w_l], [0] = flow_ij, [1] = flow_ji
+    uint8_t* need[MAXP][MAXL];         // [h_l][w_l] 1 where the flow is estimated (static)
+    uint4* lk_queue[MAXL];             // deferred flow pixels: {field | iter << 8, x | y << 16, ux, uy}
+    int32_t lk_qcap[MAXL];
     uint32_t* cover;                   // [canvas_h][cover_words] coverage bits
     unsigned long long* cand;          // [blend_ty][blend_tx] (camera, shift) candidates
     Accum* acc;
@@ -90,6 +99,7 @@ hipError_t launch_solve(const DevPlan* dp, hipStream_t s);
 hipError_t launch_pyr0(const DevPlan* dp, const DevPlan& hp, hipStream_t s);
 hipError_t launch_pyr_down(const DevPlan* dp, const DevPlan& hp, int level, hipStream_t s);
 hipError_t launch_lk(const DevPlan* dp, const DevPlan& hp, int level, hipStream_t s);
+hipError_t launch_need(const DevPlan* dp, const DevPlan& hp, hipStream_t s);
 hipError_t launch_blend(const DevPlan* dp, const DevPlan& hp, FrameSet fs, uint8_t* pano, hipStream_t s);
 hipError_t launch_balance_lut(const DevPlan* dp, hipStream_t s);
 hipError_t launch_balance_apply(const DevPlan* dp, const DevPlan& hp, uint8_t* pano, hipStream_t s);

@@ -27,7 +27,8 @@ STATE_VERSION = 1
 STATUS = {0: "VS_OK", -1: "VS_E_INVAL", -2: "VS_E_GEOMETRY", -3: "VS_E_NOMEM", -4: "VS_E_DEVICE",
           -5: "VS_E_STATE", -6: "VS_E_UNSUPPORTED"}
 TAP = dict(strip=1, mask=2, hist=3, lut=4, mom=5, mpair=6, mk=7, flags=8, pyr=9, flow=10,
-           pano_pre=11, pano_hist=12, bal_lut=13, quant=14, mbar=15, cover=16)
+           pano_pre=11, pano_hist=12, bal_lut=13, quant=14, mbar=15, cover=16, need=17,
+           deferred=18)
 
 # every symbol include/vstitch.h declares
 EXPORTS = ["vs_abi_version", "vs_status_str", "vs_default_params", "vs_compose_homographies",
@@ -277,12 +278,13 @@ class Stitcher:
                       flags=((I.n_pairs,), np.int32), flow=((sh, sw, 2), np.float32),
                       pano_pre=((H, W, 3), np.uint8), pano_hist=((3, 256), np.uint32),
                       bal_lut=((3, 256), np.uint8), quant=((3, 2), np.int32),
-                      mbar=((3, 2), np.float64), cover=((H, W), np.uint8))
-        if name == "pyr":
+                      mbar=((3, 2), np.float64), cover=((H, W), np.uint8),
+                      deferred=((1,), np.uint32))
+        if name in ("pyr", "need"):
             w, h = sw, sh
             for _ in range(sub % 8):
                 w, h = (w + 1) // 2, (h + 1) // 2
-            shape, dt = (h, w), np.float32
+            shape, dt = (h, w), (np.float32 if name == "pyr" else np.uint8)
         else:
             shape, dt = shapes[name]
         out = np.zeros(shape, dt)

@@ -51,6 +51,9 @@ def check_steps(st, orc, label, full=True, flow=True):
             for cam in (0, 1):
                 a, b = st.tap("pyr", p, cam * 8), orc.tap("pyr", p, cam * 8)
                 np.testing.assert_array_equal(a, b, err_msg=f"{label} luma {p}/{cam}")
+            for lvl in range(st.info.lk_levels):
+                np.testing.assert_array_equal(st.tap("need", p, lvl), orc.tap("need", p, lvl),
+                                              err_msg=f"{label} flow domain {p}/{lvl}")
         for d in (0, 1):
             a, b = st.tap("flow", p, d), orc.tap("flow", p, d)
             epe = np.sqrt(((a.astype(np.float64) - b) ** 2).sum(-1))
@@ -218,5 +221,7 @@ def test_parity_4x1920x1080_ring_full_size():
         d = lsb(pano, want)
         say(f"  final max diff {d} LSB, identical px {np.mean(np.all(pano == want, -1)):.6f}")
         assert d <= 1
+        deferred = [int(st.tap("deferred", 0, lvl)[0]) for lvl in range(st.info.lk_levels)]
+        say(f"  flow pixels finished by the tail kernel per level: {deferred}")
         check_steps(st, orc, f"4x1080p t={t}", full=(t == 0))
     st.close()

@@ -129,3 +129,23 @@ def test_fp32_flow_agrees_with_fp64():
     u64 = O.pyramid_flow(Tp, Mp, f64=True)
     epe = np.sqrt(((u32 - u64) ** 2).sum(-1))
     assert epe.mean() < 1e-4 and epe.max() < 1e-2, (epe.mean(), epe.max())
+
+
+def test_flow_domain_restriction_keeps_the_overlap_flow():
+    """Estimating the flow only on the overlap (and the coarse pixels its
+    initialisation samples) leaves the overlap flow bit-identical to the
+    flow estimated everywhere; elsewhere it is 0."""
+    from paper_2308_09209_amd.scenes import small_scene
+    s = small_scene(n_cams=2, W=200, H=120, overlap=0.3)
+    o = O.Oracle(s.rig())
+    o.stitch(s.frames(0))
+    for p in range(o.n_pairs):
+        m = o.tap("mask", p) > 0
+        np.testing.assert_array_equal(o.tap("need", p, 0), m.astype(np.uint8))
+        for d in (0, 1):
+            T = [o.tap("pyr", p, (d * 8) + l) for l in range(4)]
+            M = [o.tap("pyr", p, ((1 - d) * 8) + l) for l in range(4)]
+            full = O.pyramid_flow(T, M)
+            got = o.tap("flow", p, d)
+            np.testing.assert_array_equal(got[m], full[m])
+            assert np.all(got[~m] == 0)
