@@ -87,6 +87,9 @@ def main():
     ap.add_argument("--seq", type=int, default=60, help="distinct frames generated (cycled)")
     ap.add_argument("--cpu-frames", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calibration-mb", type=int, default=0,
+                    help="also run one plain device-to-device copy of this many MiB (a "
+                         "counter reference for rocprofv3 byte counters)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py: this build measures one GPU; the path's sharding across GPUs is a design "
@@ -109,6 +112,17 @@ def main():
     print(f"# generated {seq} frames in {time.perf_counter() - t_gen:.1f} s", file=sys.stderr, flush=True)
     dev = torch.device("cuda:0")
     frames = [[torch.from_numpy(f).to(dev) for f in fr] for fr in host_frames]
+
+    if args.copy_calibration_mb > 0:
+        n = args.copy_calibration_mb << 20
+        src = torch.empty(n, dtype=torch.uint8, device=dev).fill_(1)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+        print(f"# copied {args.copy_calibration_mb} MiB device to device (counter reference)",
+              file=sys.stderr, flush=True)
 
     st = V.Stitcher(rig)
     info = st.info
@@ -145,7 +159,8 @@ def main():
     lk_launch_ms = step_ms[2] / nfr / levels
     achieved = flops / levels / (lk_launch_ms * 1e-3) / 1e12
     traffic = load_pmc("k_lk", args.workload)
-    roofline = dict(bound="alu", kernel="vs::k_lk (pyramidal flow, one launch per level)",
+    roofline = dict(bound="alu", kernel="vs::k_lk_w9 + vs::k_lk_tail (pyramidal flow, one launch "
+                                        "pair per level)",
                     achieved=round(achieved, 3), peak=FP32_VECTOR_PEAK_TFLOPS, unit="TFLOP/s",
                     frac=round(achieved / FP32_VECTOR_PEAK_TFLOPS, 4),
                     traffic=traffic, avg_launch_ms=round(lk_launch_ms, 5),

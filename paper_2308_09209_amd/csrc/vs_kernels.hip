@@ -217,15 +217,16 @@ __device__ __forceinline__ int find_field(const int32_t* off, int n, int b)
 
 __global__ __launch_bounds__(256) void k_strips(const DevPlan* __restrict__ P, FrameSet fs)
 {
-    __shared__ uint32_t s_hist[2 * 3 * 256];
+    __shared__ uint32_t s_hist[4][2 * 3 * 256];   // 4 copies (lane & 3) against same-value conflicts
     __shared__ uint32_t s_red[4][7];
     const int tid = threadIdx.x;
     const int p = find_field(P->strip_off, P->n_pairs, blockIdx.x);
     const int t = blockIdx.x - P->strip_off[p];
     const int sw = P->sw[p], sh = P->sh[p];
     const int tx0 = (t % P->strip_tx[p]) * STRIP_TX, ty0 = (t / P->strip_tx[p]) * STRIP_TY;
-    for (int i = tid; i < 2 * 3 * 256; i += 256) s_hist[i] = 0;
+    for (int i = tid; i < 4 * 2 * 3 * 256; i += 256) (&s_hist[0][0])[i] = 0;
     __syncthreads();
+    uint32_t* const my_hist = s_hist[tid & 3];
 
     const int kj = P->pj[p], ki = P->pi[p];
     const int shift_i = P->psi[p] * P->Wp;
@@ -250,12 +251,12 @@ __global__ __launch_bounds__(256) void k_strips(const DevPlan* __restrict__ P, F
         const bool ok = okj && oki;
         mask[q] = ok ? 1 : 0;
         if (ok) {
-            atomicAdd(&s_hist[0 * 256 + cj0], 1u);
-            atomicAdd(&s_hist[1 * 256 + cj1], 1u);
-            atomicAdd(&s_hist[2 * 256 + cj2], 1u);
-            atomicAdd(&s_hist[3 * 256 + ci0], 1u);
-            atomicAdd(&s_hist[4 * 256 + ci1], 1u);
-            atomicAdd(&s_hist[5 * 256 + ci2], 1u);
+            atomicAdd(&my_hist[0 * 256 + cj0], 1u);
+            atomicAdd(&my_hist[1 * 256 + cj1], 1u);
+            atomicAdd(&my_hist[2 * 256 + cj2], 1u);
+            atomicAdd(&my_hist[3 * 256 + ci0], 1u);
+            atomicAdd(&my_hist[4 * 256 + ci1], 1u);
+            atomicAdd(&my_hist[5 * 256 + ci2], 1u);
             a00 += ci0 * ci0;
             a01 += ci0 * ci1;
             a02 += ci0 * ci2;
@@ -283,7 +284,7 @@ __global__ __launch_bounds__(256) void k_strips(const DevPlan* __restrict__ P, F
     }
     uint32_t* gh = &acc->hist[p][0][0][0];
     for (int i = tid; i < 2 * 3 * 256; i += 256) {
-        uint32_t h = s_hist[i];
+        const uint32_t h = s_hist[0][i] + s_hist[1][i] + s_hist[2][i] + s_hist[3][i];
         if (h) atomicAdd(&gh[i], h);
     }
 }
@@ -1120,10 +1121,13 @@ hipError_t launch_lk(const DevPlan* dp, const DevPlan& hp, int level, hipStream_
 
 __global__ __launch_bounds__(BL_THREADS) void k_blend(const DevPlan* __restrict__ P, FrameSet fs, uint8_t* __restrict__ pano)
 {
-    __shared__ uint32_t s_hist[3 * 256];
+    // 8 copies of the histogram (lane & 7): neighbouring pixels often share a
+    // value, and same-address LDS atomics from one instruction serialise
+    __shared__ uint32_t s_hist[8][3 * 256];
     const int tid = threadIdx.x;
-    for (int i = tid; i < 3 * 256; i += BL_THREADS) s_hist[i] = 0;
+    for (int i = tid; i < 8 * 3 * 256; i += BL_THREADS) (&s_hist[0][0])[i] = 0;
     __syncthreads();
+    uint32_t* const my_hist = s_hist[tid & 7];
     const int bx = blockIdx.x % P->blend_tx, by = blockIdx.x / P->blend_tx;
     const unsigned long long cand = P->cand[by * P->blend_tx + bx];
     const int W = P->canvas_w, H = P->canvas_h, Wp = P->Wp;
@@ -1201,9 +1205,9 @@ __global__ __launch_bounds__(BL_THREADS) void k_blend(const DevPlan* __restrict_
                     o2 = round8(__builtin_fmaf(thi, ti - tj, tj));
                 }
                 if (nh > 0) {
-                    atomicAdd(&s_hist[o0], 1u);
-                    atomicAdd(&s_hist[256 + o1], 1u);
-                    atomicAdd(&s_hist[512 + o2], 1u);
+                    atomicAdd(&my_hist[o0], 1u);
+                    atomicAdd(&my_hist[256 + o1], 1u);
+                    atomicAdd(&my_hist[512 + o2], 1u);
                 }
             }
             ob[q * 3 + 0] = o0;
@@ -1227,7 +1231,9 @@ __global__ __launch_bounds__(BL_THREADS) void k_blend(const DevPlan* __restrict_
     __syncthreads();
     uint32_t* gh = &P->acc->pano_hist[0][0];
     for (int i = tid; i < 3 * 256; i += BL_THREADS) {
-        uint32_t h = s_hist[i];
+        uint32_t h = 0;
+#pragma unroll
+        for (int k = 0; k < 8; ++k) h += s_hist[k][i];
         if (h) atomicAdd(&gh[i], h);
     }
 }
