@@ -87,6 +87,10 @@ def main():
     ap.add_argument("--seq", type=int, default=60, help="distinct frames generated (cycled)")
     ap.add_argument("--cpu-frames", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--batch", action="store_true",
+                    help="the 6-stream batched workload (2x1280x720, 2x1920x1080, 2x2560x1440, "
+                         "3-4 cameras each) through one captured graph, instead of the ring")
+    ap.add_argument("--autotune", action="store_true", help="autotune the flow kernel first (batch)")
     ap.add_argument("--copy-calibration-mb", type=int, default=0,
                     help="also run one plain device-to-device copy of this many MiB (a "
                          "counter reference for rocprofv3 byte counters)")
@@ -100,6 +104,9 @@ def main():
 
     from paper_2308_09209_amd import vstitch as V
     from paper_2308_09209_amd.scenes import WORKLOADS, scene_for
+
+    if args.batch:
+        return bench_batch(args)
 
     wl = WORKLOADS[args.workload]
     t_gen = time.perf_counter()
@@ -183,6 +190,54 @@ def main():
         out["cpu_baseline"] = cpu_baseline(scene, host_frames, min(args.cpu_frames, seq))
     else:
         out["cpu_baseline"] = None
+    print(json.dumps(out), flush=True)
+
+
+def bench_batch(args):
+    import torch
+
+    from paper_2308_09209_amd import vstitch as V
+    from paper_2308_09209_amd.scenes import BATCH_STREAMS, batch_scenes
+
+    t_gen = time.perf_counter()
+    scenes = batch_scenes()
+    seq = max(1, args.seq)
+    dev = torch.device("cuda:0")
+    frames = [[[torch.from_numpy(f).to(dev) for f in sc.frames(t)] for sc in scenes] for t in range(seq)]
+    print(f"# generated {seq} frames of {len(scenes)} streams in {time.perf_counter() - t_gen:.1f} s",
+          file=sys.stderr, flush=True)
+    sts = [V.Stitcher(sc.rig()) for sc in scenes]
+    batch = V.Batch(sts)
+    panos = [st.new_pano(dev) for st in sts]
+    px = sum(st.canvas[0] * st.canvas[1] for st in sts)
+    choice = [int(v) for v in sts[0].flow_variants()]
+    if args.autotune:
+        choice, _ = batch.autotune(frames[0], panos, reps=3)
+    for i in range(args.warmup):
+        batch.run(frames[i % seq], panos)
+    torch.cuda.synchronize()
+    K = args.steps
+    starts = [torch.cuda.Event(enable_timing=True) for _ in range(K)]
+    ends = [torch.cuda.Event(enable_timing=True) for _ in range(K)]
+    t0 = time.perf_counter()
+    for i in range(K):
+        starts[i].record()
+        batch.run(frames[(args.warmup + i) % seq], panos)
+        ends[i].record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    lat = np.array([starts[i].elapsed_time(ends[i]) for i in range(K)])
+    out = dict(metric="panorama Mpix/s (6 uneven streams, one graph per frame step)",
+               value=round(K * px / wall / 1e6, 2), unit="Mpix/s", n_gpus=1, steps=K,
+               warmup=args.warmup, ms_per_step=round(wall / K * 1e3, 4), higher_is_better=True,
+               scaling="weak", vs_baseline=None, dtype="f32", data="synthetic",
+               config=dict(workload="6stream_batch",
+                           streams=[f"{s['n_cams']}x{s['W']}x{s['H']}" for s in BATCH_STREAMS],
+                           panorama_mpix_per_step=round(px / 1e6, 3), seq_frames=seq,
+                           flow_variant_per_level=choice, autotuned=bool(args.autotune),
+                           parallelism="single GPU"),
+               p50_ms=round(float(np.percentile(lat, 50)), 4),
+               p99_ms=round(float(np.percentile(lat, 99)), 4))
     print(json.dumps(out), flush=True)
 
 

@@ -215,6 +215,101 @@ vs_status vs_debug_tap(vs_ctx* c, int tap, int pair, int sub, void* dst, size_t 
 vs_status vs_set_timing(vs_ctx* c, int on);
 vs_status vs_get_timing(vs_ctx* c, double ms[6], uint32_t* frames);
 
+/* Flow-kernel variant of one pyramid level: 0 = generic kernel (16 x 16
+ * pixel tiles, any radius), 1, 2 or 4 = the 9x9-window kernel (radius 4) with
+ * that many vertically adjacent pixels per thread.  Results are identical for
+ * every variant; only speed differs.  vs_create picks one per level; the
+ * autotuner below measures them. */
+vs_status vs_set_flow_variant(vs_ctx* c, int level, int variant);
+vs_status vs_get_flow_variant(const vs_ctx* c, int32_t variant[VS_MAX_LEVELS]);
+
+/* Batches (several streams per frame step, uneven rigs and resolutions):
+ * vs_batch_create captures one HIP graph that runs the whole per-frame path
+ * of up to 8 contexts, each step as one launch over the tiles of every
+ * context.  The contexts keep their own plans, workspaces and colour states
+ * and must share lk_levels and lk_radius; while in a batch they must not be
+ * stitched concurrently through vs_stitch.  The graph does not depend on the
+ * frame or panorama addresses.
+ * vs_batch_run: frames[c][k] = camera k of context c (device), panos[c] =
+ * context c's panorama (device); asynchronous on stream.  A device error
+ * marks every context of the batch sticky. */
+typedef struct vs_batch vs_batch;
+vs_status vs_batch_create(vs_ctx* const ctxs[], int n, vs_batch** out);
+vs_status vs_batch_run(vs_batch* b, const uint8_t* const* const frames[], uint8_t* const panos[], void* stream);
+vs_status vs_batch_destroy(vs_batch* b);
+const char* vs_batch_last_error(const vs_batch* b);
+
+/* Autotuner: for every pyramid level, run the batch on the given frames with
+ * each 9x9 flow-kernel variant (1, 2, 4 pixels per thread), `reps` timed runs
+ * each, and keep the fastest.  ms[l][i] receives the mean frame time of
+ * variant {1, 2, 4}[i] at level l (may be NULL); choice[l] the variant kept.
+ * The colour states are restored afterwards.  Synchronous. */
+vs_status vs_batch_autotune(vs_batch* b, const uint8_t* const* const frames[], uint8_t* const panos[], int reps,
+                            float ms[VS_MAX_LEVELS][3], int32_t choice[VS_MAX_LEVELS]);
+
+/* ------------------------------------------------------------------------
+ * Learned flow surrogate (an addition to the paper's method): a small 3x3
+ * convolution network in BF16 with FP32 accumulation, trained on flows of the
+ * plain estimator.  Building blocks with device pointers, NHWC activations
+ * (16 or 32 channels, BF16 stored as uint16_t) and weights [Cout][tap][Cin]
+ * (tap = 3 ky + kx, zero padding).  A launch covers up to 64 images of
+ * possibly different sizes stored back to back.
+ * ------------------------------------------------------------------------ */
+#define VS_NN_MAX_IMAGES 64
+enum { VS_CONV_LRELU = 0, VS_CONV_LINEAR = 1, VS_CONV_F32 = 2 };
+typedef struct {
+    int32_t n;
+    int32_t w[VS_NN_MAX_IMAGES], h[VS_NN_MAX_IMAGES];
+} vs_nn_images;
+
+/* y = act(conv3x3(x, w) + bias) on the matrix cores.  (cin, cout) in
+ * {(16,32), (32,32), (32,16), (16,16)}; mode VS_CONV_LRELU (BF16 out, leaky
+ * ReLU slope alpha), VS_CONV_LINEAR (BF16 out) or VS_CONV_F32 (FP32 out);
+ * bias may be NULL. */
+vs_status vs_nn_conv3x3(const uint16_t* x, int cin, const uint16_t* w, const float* bias, void* y, int cout,
+                        const vs_nn_images* imgs, int mode, float alpha, void* stream);
+/* Weight and bias gradient of that convolution: dwb[Cout][9][Cin] followed by
+ * db[Cout] (FP32), from the layer input x and the pre-activation gradient dz.
+ * scratch: device FP32 workspace of vs_nn_wgrad_scratch_bytes bytes (per-block
+ * partial sums, added in block order: deterministic). */
+size_t vs_nn_wgrad_scratch_bytes(int cin, int cout, const vs_nn_images* imgs);
+vs_status vs_nn_conv3x3_wgrad(const uint16_t* x, int cin, const uint16_t* dz, int cout, const vs_nn_images* imgs,
+                              float* scratch, size_t scratch_bytes, float* dwb, void* stream);
+/* wf[Cin][tap][Cout] = w[Cout][8 - tap][Cin]: the data gradient is
+ * vs_nn_conv3x3(dz, cout, wf, NULL, dx, cin, ..., VS_CONV_LINEAR). */
+vs_status vs_nn_flip_weights(const uint16_t* w, uint16_t* wf, int cin, int cout, void* stream);
+/* dz = dh * (h > 0 ? 1 : alpha) elementwise (h = leaky ReLU output). */
+vs_status vs_nn_lrelu_bwd(const uint16_t* dh, const uint16_t* h, uint16_t* dz, int64_t n, float alpha, void* stream);
+/* 16-channel network input from a template / moving luma pair (FP32):
+ * channel 0 = (yt - 128) / 64, channel 1 = (ym - 128) / 64, others 0. */
+vs_status vs_nn_pack_pair(const float* yt, const float* ym, uint16_t* x, int64_t npix, void* stream);
+/* Mean end-point error of channels 0-1 of pred (FP32, 16 channels) against
+ * label (FP32, 2 channels); dz (BF16, 16 channels) receives its gradient and
+ * block_loss[ceil(npix / 256)] the per-block sums of the pixel errors. */
+vs_status vs_nn_epe_loss(const float* pred, const float* label, uint16_t* dz, float* block_loss, int64_t npix,
+                         void* stream);
+/* Adam step (bias-corrected, step >= 1) on FP32 master parameters; w_bf16 (may
+ * be NULL) receives their BF16 rounding. */
+vs_status vs_nn_adam(float* w, float* m, float* v, const float* g, uint16_t* w_bf16, int64_t n, float lr, float b1,
+                     float b2, float eps, int step, void* stream);
+vs_status vs_nn_to_bf16(const float* a, uint16_t* b, int64_t n, void* stream);
+/* One 16x16x16 BF16 matrix-core product of a[16][16] and b[16][16]; out[64][4]
+ * receives each lane's accumulator fragment (a layout check). */
+vs_status vs_nn_mfma_probe(const uint16_t* a, const uint16_t* b, float* out, void* stream);
+
+/* Plain estimator on caller image pairs (training labels, tests): a context
+ * for w x h luma images; vs_flow_run computes, on the whole image, the
+ * pyramidal flow of vs_stitch for template yt and moving ym (P_m(x + f) ~
+ * P_t(x)) into flow_tm and the reverse flow into flow_mt (FP32 [h][w][2],
+ * either may be NULL).  Inputs and outputs are device pointers. */
+typedef struct vs_flow vs_flow;
+vs_status vs_flow_create(int w, int h, const vs_params* p, vs_flow** out);
+vs_status vs_flow_run(vs_flow* f, const float* yt, const float* ym, float* flow_tm, float* flow_mt, void* stream);
+vs_status vs_flow_destroy(vs_flow* f);
+/* Pyramid level `level` of the last run's template and moving images (FP32,
+ * device; either may be NULL) and its size. */
+vs_status vs_flow_level(vs_flow* f, int level, float* yt, float* ym, int32_t* w, int32_t* h, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

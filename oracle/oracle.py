@@ -92,6 +92,10 @@ def lib():
         L.vso_bilinear.argtypes = [C.c_void_p, C.c_int, C.c_int, C.c_int, C.c_int, C.c_float,
                                    C.c_float]
         L.vso_round8.argtypes = [C.c_float]
+        vp, i = C.c_void_p, C.c_int
+        L.vso_conv3x3.argtypes = [vp, i, i, i, i, vp, vp, i, vp]
+        L.vso_conv3x3_bwd_data.argtypes = [vp, i, i, i, i, vp, i, vp]
+        L.vso_conv3x3_bwd_weight.argtypes = [vp, vp, i, i, i, i, i, vp, vp]
         _lib = L
     return _lib
 
@@ -328,3 +332,38 @@ def bilinear(F, ch, u, v) -> float:
 
 def round8(r) -> int:
     return lib().vso_round8(float(r))
+
+
+# ---- learned surrogate: FP64 convolution references -----------------------
+
+def conv3x3(x, wt, b=None):
+    """x (n, h, w, cin), wt (cout, 9, cin), b (cout,) -> (n, h, w, cout), float64"""
+    x = np.ascontiguousarray(x, np.float64)
+    wt = np.ascontiguousarray(wt, np.float64)
+    n, h, w, cin = x.shape
+    cout = wt.shape[0]
+    y = np.zeros((n, h, w, cout), np.float64)
+    bb = None if b is None else np.ascontiguousarray(b, np.float64)
+    lib().vso_conv3x3(_ptr(x), n, h, w, cin, _ptr(wt), None if bb is None else _ptr(bb), cout, _ptr(y))
+    return y
+
+
+def conv3x3_bwd_data(dy, wt):
+    dy = np.ascontiguousarray(dy, np.float64)
+    wt = np.ascontiguousarray(wt, np.float64)
+    n, h, w, cout = dy.shape
+    cin = wt.shape[2]
+    dx = np.zeros((n, h, w, cin), np.float64)
+    lib().vso_conv3x3_bwd_data(_ptr(dy), n, h, w, cout, _ptr(wt), cin, _ptr(dx))
+    return dx
+
+
+def conv3x3_bwd_weight(x, dy):
+    x = np.ascontiguousarray(x, np.float64)
+    dy = np.ascontiguousarray(dy, np.float64)
+    n, h, w, cin = x.shape
+    cout = dy.shape[3]
+    dw = np.zeros((cout, 9, cin), np.float64)
+    db = np.zeros(cout, np.float64)
+    lib().vso_conv3x3_bwd_weight(_ptr(x), _ptr(dy), n, h, w, cin, cout, _ptr(dw), _ptr(db))
+    return dw, db

@@ -1131,3 +1131,76 @@ int vso_get(const vso_ctx* c, int tap, int p, int sub, void* dst, size_t nbytes)
         return VSO_E_INVAL;
     }
 }
+
+/* ------------------------------------------------------------------------ */
+/* The learned flow surrogate (not in the paper): FP64 references of its     */
+/* 3x3 convolutions, NHWC, weights [cout][tap][cin], tap = 3 ky + kx, zero    */
+/* padding.  Written as the definitions, one output value at a time.          */
+/* ------------------------------------------------------------------------ */
+
+/* y[p][co] = b[co] + sum_tap sum_ci x[p + tap - (1,1)][ci] w[co][tap][ci] */
+void vso_conv3x3(const double* x, int n, int h, int w, int cin, const double* wt, const double* b, int cout,
+                 double* y)
+{
+#pragma omp parallel for schedule(static)
+    for (int img = 0; img < n; ++img)
+        for (int yy = 0; yy < h; ++yy)
+            for (int xx = 0; xx < w; ++xx)
+                for (int co = 0; co < cout; ++co) {
+                    double acc = b ? b[co] : 0.0;
+                    for (int tap = 0; tap < 9; ++tap) {
+                        int sy = yy + tap / 3 - 1, sx = xx + tap % 3 - 1;
+                        if (sy < 0 || sy >= h || sx < 0 || sx >= w) continue;
+                        const double* src = x + (((size_t)img * h + sy) * w + sx) * cin;
+                        for (int ci = 0; ci < cin; ++ci) acc += src[ci] * wt[((size_t)co * 9 + tap) * cin + ci];
+                    }
+                    y[(((size_t)img * h + yy) * w + xx) * cout + co] = acc;
+                }
+}
+
+/* dx[p][ci] = sum over the outputs q that read p: dy[q][co] w[co][tap][ci] */
+void vso_conv3x3_bwd_data(const double* dy, int n, int h, int w, int cout, const double* wt, int cin, double* dx)
+{
+#pragma omp parallel for schedule(static)
+    for (int img = 0; img < n; ++img)
+        for (int yy = 0; yy < h; ++yy)
+            for (int xx = 0; xx < w; ++xx)
+                for (int ci = 0; ci < cin; ++ci) {
+                    double acc = 0.0;
+                    for (int tap = 0; tap < 9; ++tap) {
+                        /* output (oy, ox) reads (yy, xx) through tap when oy + ky - 1 = yy */
+                        int oy = yy - (tap / 3 - 1), ox = xx - (tap % 3 - 1);
+                        if (oy < 0 || oy >= h || ox < 0 || ox >= w) continue;
+                        const double* g = dy + (((size_t)img * h + oy) * w + ox) * cout;
+                        for (int co = 0; co < cout; ++co) acc += g[co] * wt[((size_t)co * 9 + tap) * cin + ci];
+                    }
+                    dx[(((size_t)img * h + yy) * w + xx) * cin + ci] = acc;
+                }
+}
+
+/* dw[co][tap][ci] = sum_p dy[p][co] x[p + tap - (1,1)][ci];  db[co] = sum_p dy[p][co] */
+void vso_conv3x3_bwd_weight(const double* x, const double* dy, int n, int h, int w, int cin, int cout, double* dw,
+                            double* db)
+{
+#pragma omp parallel for schedule(static)
+    for (int co = 0; co < cout; ++co) {
+        for (int tap = 0; tap < 9; ++tap)
+            for (int ci = 0; ci < cin; ++ci) {
+                double acc = 0.0;
+                for (int img = 0; img < n; ++img)
+                    for (int yy = 0; yy < h; ++yy)
+                        for (int xx = 0; xx < w; ++xx) {
+                            int sy = yy + tap / 3 - 1, sx = xx + tap % 3 - 1;
+                            if (sy < 0 || sy >= h || sx < 0 || sx >= w) continue;
+                            acc += dy[(((size_t)img * h + yy) * w + xx) * cout + co] *
+                                   x[(((size_t)img * h + sy) * w + sx) * cin + ci];
+                        }
+                dw[((size_t)co * 9 + tap) * cin + ci] = acc;
+            }
+        if (db) {
+            double acc = 0.0;
+            for (size_t p = 0; p < (size_t)n * h * w; ++p) acc += dy[p * cout + co];
+            db[co] = acc;
+        }
+    }
+}

@@ -124,4 +124,12 @@ int vso_hom_valid(const float h[9], float x, float y, int W, int H, float* u, fl
 float vso_bilinear(const uint8_t* F, int pitch, int W, int H, int ch, float u, float v);
 int vso_round8(float r);
 
+/* learned surrogate: FP64 3x3 convolution references (NHWC, weights
+ * [cout][tap][cin], zero padding) */
+void vso_conv3x3(const double* x, int n, int h, int w, int cin, const double* wt, const double* b, int cout,
+                 double* y);
+void vso_conv3x3_bwd_data(const double* dy, int n, int h, int w, int cout, const double* wt, int cin, double* dx);
+void vso_conv3x3_bwd_weight(const double* x, const double* dy, int n, int h, int w, int cin, int cout, double* dw,
+                            double* db);
+
 #endif

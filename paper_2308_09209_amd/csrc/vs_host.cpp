@@ -7,6 +7,7 @@
 #include <cstring>
 #include <new>
 #include <string>
+#include <vector>
 
 #include "vs_internal.h"
 
@@ -110,6 +111,25 @@ void free_ctx(vs_ctx* c)
     if (c->dp) (void)hipFree(c->dp);
     if (c->pano_pre) (void)hipFree(c->pano_pre);
     delete c;
+}
+
+// Choose the flow-kernel variant of one level (0: generic 16x16 kernel;
+// 1, 2, 4: 9x9-window kernel with that many pixels per thread) and rebuild
+// that level's tile table; the caller re-uploads the plan.
+void set_lk_tiles(DevPlan& h, int l, int P)
+{
+    int tx = LK_T, ty = LK_T;
+    h.lk_P[l] = P;
+    if (P > 0) {
+        tx = LKW_TX;
+        ty = 4 * P;
+    }
+    h.lk_off[l][0] = 0;
+    for (int f = 0; f < 2 * h.n_pairs; ++f) {
+        const int p = f >> 1;
+        h.lk_tx[l][f] = (h.lw[p][l] + tx - 1) / tx;
+        h.lk_off[l][f + 1] = h.lk_off[l][f] + h.lk_tx[l][f] * ((h.lh[p][l] + ty - 1) / ty);
+    }
 }
 
 }  // namespace
@@ -293,27 +313,12 @@ vs_status vs_create(const vs_rig* rig, const vs_params* prm, vs_ctx** out)
         }
         // flow kernel: the 9x9-window kernel with 4 px per thread where that still
         // gives >= 1024 blocks, else 1 px per thread; other radii use the generic kernel
-        auto tiles = [&](int tx, int ty) {
-            int n = 0;
-            for (int f = 0; f < 2 * h.n_pairs; ++f) {
-                const int p = f >> 1;
-                n += ((h.lw[p][l] + tx - 1) / tx) * ((h.lh[p][l] + ty - 1) / ty);
-            }
-            return n;
-        };
-        int tx = LK_T, ty = LK_T;
-        h.lk_P[l] = 0;
-        if (P.lk_radius == LK_R_MAX) {
-            h.lk_P[l] = tiles(LKW_TX, 16) >= 1024 ? 4 : 1;
-            tx = LKW_TX;
-            ty = 4 * h.lk_P[l];
-        }
-        h.lk_off[l][0] = 0;
+        int n16 = 0;
         for (int f = 0; f < 2 * h.n_pairs; ++f) {
-            const int p = f >> 1, w = h.lw[p][l], hh = h.lh[p][l];
-            h.lk_tx[l][f] = (w + tx - 1) / tx;
-            h.lk_off[l][f + 1] = h.lk_off[l][f] + h.lk_tx[l][f] * ((hh + ty - 1) / ty);
+            const int p = f >> 1;
+            n16 += ((h.lw[p][l] + LKW_TX - 1) / LKW_TX) * ((h.lh[p][l] + 15) / 16);
         }
+        set_lk_tiles(h, l, P.lk_radius == LK_R_MAX ? (n16 >= 1024 ? 4 : 1) : 0);
     }
     // ---- workspace arena ----
     size_t off = 0;
@@ -498,17 +503,79 @@ vs_status vs_state_get(vs_ctx* c, vs_color_state* out)
     return VS_OK;
 }
 
+}  // extern "C"
+
+namespace {
+
+// The per-frame launch sequence for a group of contexts (one context for
+// vs_stitch, several for a batch).  ev (7 events) brackets the steps when
+// non-null; pre (single context only) receives a copy of the pre-balance
+// panorama.
+hipError_t enqueue_frame(const Group& g, hipStream_t s, hipEvent_t* ev, uint8_t* pre, const uint8_t* pano,
+                         size_t pano_bytes, const char** where)
+{
+    hipError_t e;
+#define VS_STEP(call, name)              \
+    do {                                 \
+        if ((e = (call)) != hipSuccess) { \
+            *where = name;               \
+            return e;                    \
+        }                                \
+    } while (0)
+    int levels = 0;
+    for (int c = 0; c < g.n; ++c) levels = std::max(levels, (int)g.hp[c]->levels);
+    if (ev) VS_STEP(hipEventRecord(ev[0], s), "hipEventRecord");
+    VS_STEP(launch_zero(g, s), "zero");
+    VS_STEP(launch_strips(g, s), "strips");
+    VS_STEP(launch_lut(g, s), "lut");
+    VS_STEP(launch_moments_b(g, s), "moments");
+    VS_STEP(launch_solve(g, s), "solve");
+    if (ev) VS_STEP(hipEventRecord(ev[1], s), "hipEventRecord");
+    VS_STEP(launch_pyr0(g, s), "pyr0");
+    for (int l = 0; l + 1 < levels; ++l) VS_STEP(launch_pyr_down(g, l, s), "pyr_down");
+    if (ev) VS_STEP(hipEventRecord(ev[2], s), "hipEventRecord");
+    for (int l = levels - 1; l >= 0; --l) VS_STEP(launch_lk(g, l, s), "flow");
+    if (ev) VS_STEP(hipEventRecord(ev[3], s), "hipEventRecord");
+    VS_STEP(launch_blend(g, s), "blend");
+    if (pre) VS_STEP(hipMemcpyAsync(pre, pano, pano_bytes, hipMemcpyDeviceToDevice, s), "pano_pre copy");
+    if (ev) VS_STEP(hipEventRecord(ev[4], s), "hipEventRecord");
+    VS_STEP(launch_balance_lut(g, s), "balance lut");
+    VS_STEP(launch_balance_apply(g, s), "balance apply");
+    if (ev) {
+        VS_STEP(hipEventRecord(ev[5], s), "hipEventRecord");
+        VS_STEP(hipEventRecord(ev[6], s), "hipEventRecord");
+    }
+#undef VS_STEP
+    return hipSuccess;
+}
+
+Group single(vs_ctx* c)
+{
+    Group g;
+    std::memset(&g, 0, sizeof g);
+    g.n = 1;
+    g.dp[0] = c->dp;
+    g.hp[0] = &c->hp;
+    return g;
+}
+
+}  // namespace
+
+extern "C" {
+
 vs_status vs_stitch(vs_ctx* c, const uint8_t* const frames[], const vs_color_state* in, uint8_t* pano,
                     vs_color_state* out, vs_frame_info* info, void* stream)
 {
     if (!c || !frames || !pano) return VS_E_INVAL;
     if (c->sticky) return VS_E_DEVICE;
     const DevPlan& h = c->hp;
-    FrameSet fs;
-    std::memset(&fs, 0, sizeof fs);
+    FrameIO io;
+    std::memset(&io, 0, sizeof io);
+    io.plan[0] = c->dp;
+    io.pano[0] = pano;
     for (int k = 0; k < h.n_cams; ++k) {
         if (!frames[k]) return fail(c, VS_E_INVAL, "null frame pointer");
-        fs.f[k] = frames[k];
+        io.frame[0][k] = frames[k];
     }
     hipStream_t s = (hipStream_t)stream;
     if (in) {
@@ -525,32 +592,10 @@ vs_status vs_stitch(vs_ctx* c, const uint8_t* const frames[], const vs_color_sta
         ev = c->ev[i];
         c->slot_used[i] = 1;
     }
-    if (ev) VS_CHECK(hipEventRecord(ev[0], s), "hipEventRecord");
-    VS_CHECK(launch_zero(c->dp, h.acc, s), "zero");
-    VS_CHECK(launch_strips(c->dp, h, fs, s), "strips");
-    VS_CHECK(launch_lut(c->dp, h, s), "lut");
-    VS_CHECK(launch_moments_b(c->dp, h, s), "moments");
-    VS_CHECK(launch_solve(c->dp, s), "solve");
-    if (ev) VS_CHECK(hipEventRecord(ev[1], s), "hipEventRecord");
-    if (h.use_flow) {
-        VS_CHECK(launch_pyr0(c->dp, h, s), "pyr0");
-        for (int l = 0; l + 1 < h.levels; ++l) VS_CHECK(launch_pyr_down(c->dp, h, l, s), "pyr_down");
-    }
-    if (ev) VS_CHECK(hipEventRecord(ev[2], s), "hipEventRecord");
-    if (h.use_flow)
-        for (int l = h.levels - 1; l >= 0; --l) VS_CHECK(launch_lk(c->dp, h, l, s), "flow");
-    if (ev) VS_CHECK(hipEventRecord(ev[3], s), "hipEventRecord");
-    VS_CHECK(launch_blend(c->dp, h, fs, pano, s), "blend");
-    if (c->pano_pre)
-        VS_CHECK(hipMemcpyAsync(c->pano_pre, pano, (size_t)h.canvas_h * h.pano_pitch, hipMemcpyDeviceToDevice, s),
-                 "hipMemcpyAsync pano_pre");
-    if (ev) VS_CHECK(hipEventRecord(ev[4], s), "hipEventRecord");
-    VS_CHECK(launch_balance_lut(c->dp, s), "balance lut");
-    if (h.balance) VS_CHECK(launch_balance_apply(c->dp, h, pano, s), "balance apply");
-    if (ev) {
-        VS_CHECK(hipEventRecord(ev[5], s), "hipEventRecord");
-        VS_CHECK(hipEventRecord(ev[6], s), "hipEventRecord");
-    }
+    VS_CHECK(launch_set_io(io, 1, s), "set io");
+    const char* where = "";
+    hipError_t e = enqueue_frame(single(c), s, ev, c->pano_pre, pano, (size_t)h.canvas_h * h.pano_pitch, &where);
+    if (e != hipSuccess) return dev_fail(c, e, where);
     if (out || info) {
         VS_CHECK(hipStreamSynchronize(s), "hipStreamSynchronize");
         if (out) VS_CHECK(hipMemcpy(out, h.state, sizeof *out, hipMemcpyDeviceToHost), "hipMemcpy state");
@@ -569,6 +614,397 @@ vs_status vs_stitch(vs_ctx* c, const uint8_t* const frames[], const vs_color_sta
         }
     }
     return VS_OK;
+}
+
+vs_status vs_set_flow_variant(vs_ctx* c, int level, int variant)
+{
+    if (!c || level < 0 || level >= c->hp.levels) return VS_E_INVAL;
+    if (c->sticky) return VS_E_DEVICE;
+    if (!(variant == 0 || variant == 1 || variant == 2 || variant == 4)) return VS_E_INVAL;
+    if (variant > 0 && c->hp.lk_radius != LK_R_MAX) return fail(c, VS_E_UNSUPPORTED, "9x9 kernel needs lk_radius 4");
+    if (variant == 0 && c->hp.lk_qcap[level] > 0) {
+        // the generic kernel finishes every pixel itself; nothing else changes
+    }
+    if (variant > 0 && c->hp.lk_qcap[level] == 0) return fail(c, VS_E_UNSUPPORTED, "no deferral queue for this level");
+    VS_CHECK(hipDeviceSynchronize(), "hipDeviceSynchronize");
+    set_lk_tiles(c->hp, level, variant);
+    VS_CHECK(hipMemcpy(c->dp, &c->hp, sizeof(DevPlan), hipMemcpyHostToDevice), "hipMemcpy plan");
+    return VS_OK;
+}
+
+vs_status vs_get_flow_variant(const vs_ctx* c, int32_t variant[VS_MAX_LEVELS])
+{
+    if (!c || !variant) return VS_E_INVAL;
+    for (int l = 0; l < VS_MAX_LEVELS; ++l) variant[l] = l < c->hp.levels ? c->hp.lk_P[l] : 0;
+    return VS_OK;
+}
+
+
+// ---------------------------------------------------------------------------
+// Batches: several contexts (uneven rigs / resolutions) stitched by one graph
+// ---------------------------------------------------------------------------
+
+}  // extern "C"
+
+struct vs_batch {
+    int n = 0;
+    vs_ctx* ctx[MAXB] = {};
+    Group g;
+    hipStream_t cap = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    std::string err;
+};
+
+namespace {
+
+void drop_graph(vs_batch* b)
+{
+    if (b->exec) (void)hipGraphExecDestroy(b->exec);
+    if (b->graph) (void)hipGraphDestroy(b->graph);
+    b->exec = nullptr;
+    b->graph = nullptr;
+}
+
+// Capture the group's frame sequence once; replays read this frame's buffers
+// from the device plans (k_set_io runs before every replay, outside the graph).
+vs_status capture(vs_batch* b)
+{
+    drop_graph(b);
+    hipError_t e = hipStreamBeginCapture(b->cap, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) {
+        b->err = std::string("hipStreamBeginCapture: ") + hipGetErrorString(e);
+        return VS_E_DEVICE;
+    }
+    const char* where = "";
+    hipError_t e1 = enqueue_frame(b->g, b->cap, nullptr, nullptr, nullptr, 0, &where);
+    hipGraph_t graph = nullptr;
+    e = hipStreamEndCapture(b->cap, &graph);
+    if (e1 != hipSuccess || e != hipSuccess) {
+        if (graph) (void)hipGraphDestroy(graph);
+        b->err = std::string("capture: ") + where + ": " + hipGetErrorString(e1 != hipSuccess ? e1 : e);
+        return VS_E_DEVICE;
+    }
+    b->graph = graph;
+    e = hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0);
+    if (e != hipSuccess) {
+        b->err = std::string("hipGraphInstantiate: ") + hipGetErrorString(e);
+        return VS_E_DEVICE;
+    }
+    return VS_OK;
+}
+
+vs_status set_variant_all(vs_batch* b, int level, int variant)
+{
+    for (int c = 0; c < b->n; ++c) {
+        vs_status st = vs_set_flow_variant(b->ctx[c], level, variant);
+        if (st != VS_OK) return st;
+    }
+    return VS_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+vs_status vs_batch_create(vs_ctx* const ctxs[], int n, vs_batch** out)
+{
+    if (!out || !ctxs || n < 1 || n > MAXB) return VS_E_INVAL;
+    *out = nullptr;
+    for (int c = 0; c < n; ++c) {
+        if (!ctxs[c]) return VS_E_INVAL;
+        if (ctxs[c]->sticky) return VS_E_DEVICE;
+        for (int d = 0; d < c; ++d)
+            if (ctxs[d] == ctxs[c]) return VS_E_INVAL;
+        if (ctxs[c]->hp.levels != ctxs[0]->hp.levels || ctxs[c]->hp.lk_radius != ctxs[0]->hp.lk_radius)
+            return VS_E_UNSUPPORTED;
+    }
+    vs_batch* b = new (std::nothrow) vs_batch();
+    if (!b) return VS_E_NOMEM;
+    b->n = n;
+    std::memset(&b->g, 0, sizeof b->g);
+    b->g.n = n;
+    for (int c = 0; c < n; ++c) {
+        b->ctx[c] = ctxs[c];
+        b->g.dp[c] = ctxs[c]->dp;
+        b->g.hp[c] = &ctxs[c]->hp;
+    }
+    // one flow-kernel variant per level for the whole batch (same rule as a
+    // single context, applied to the batch's total tile count)
+    const DevPlan& h0 = ctxs[0]->hp;
+    for (int l = 0; l < h0.levels; ++l) {
+        int variant = 0;
+        if (h0.lk_radius == LK_R_MAX) {
+            int n16 = 0;
+            for (int c = 0; c < n; ++c) {
+                const DevPlan& h = ctxs[c]->hp;
+                for (int f = 0; f < 2 * h.n_pairs; ++f) {
+                    const int p = f >> 1;
+                    n16 += ((h.lw[p][l] + LKW_TX - 1) / LKW_TX) * ((h.lh[p][l] + 15) / 16);
+                }
+            }
+            variant = n16 >= 1024 ? 4 : 1;
+        }
+        vs_status st = set_variant_all(b, l, variant);
+        if (st != VS_OK) {
+            delete b;
+            return st;
+        }
+    }
+    if (hipStreamCreate(&b->cap) != hipSuccess) {
+        delete b;
+        return VS_E_DEVICE;
+    }
+    vs_status st = capture(b);
+    if (st != VS_OK) {
+        vs_batch_destroy(b);
+        return st;
+    }
+    *out = b;
+    return VS_OK;
+}
+
+vs_status vs_batch_destroy(vs_batch* b)
+{
+    if (!b) return VS_E_INVAL;
+    drop_graph(b);
+    if (b->cap) (void)hipStreamDestroy(b->cap);
+    delete b;
+    return VS_OK;
+}
+
+const char* vs_batch_last_error(const vs_batch* b) { return b ? b->err.c_str() : "null batch"; }
+
+vs_status vs_batch_run(vs_batch* b, const uint8_t* const* const frames[], uint8_t* const panos[], void* stream)
+{
+    if (!b || !frames || !panos || !b->exec) return VS_E_INVAL;
+    FrameIO io;
+    std::memset(&io, 0, sizeof io);
+    for (int c = 0; c < b->n; ++c) {
+        if (b->ctx[c]->sticky) return VS_E_DEVICE;
+        if (!frames[c] || !panos[c]) return VS_E_INVAL;
+        io.plan[c] = b->ctx[c]->dp;
+        io.pano[c] = panos[c];
+        for (int k = 0; k < b->ctx[c]->hp.n_cams; ++k) {
+            if (!frames[c][k]) return VS_E_INVAL;
+            io.frame[c][k] = frames[c][k];
+        }
+    }
+    hipStream_t s = (hipStream_t)stream;
+    hipError_t e = launch_set_io(io, b->n, s);
+    if (e == hipSuccess) e = hipGraphLaunch(b->exec, s);
+    if (e != hipSuccess) {
+        b->err = std::string("batch run: ") + hipGetErrorString(e);
+        for (int c = 0; c < b->n; ++c) b->ctx[c]->sticky = 1;
+        return VS_E_DEVICE;
+    }
+    return VS_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Autotuner: per pyramid level, time each flow-kernel variant on real frames
+// and keep the fastest.  The colour state is saved and restored around it.
+// ---------------------------------------------------------------------------
+
+vs_status vs_batch_autotune(vs_batch* b, const uint8_t* const* const frames[], uint8_t* const panos[], int reps,
+                            float ms_out[VS_MAX_LEVELS][3], int32_t choice[VS_MAX_LEVELS])
+{
+    if (!b || reps < 1 || !choice) return VS_E_INVAL;
+    const int levels = b->ctx[0]->hp.levels;
+    if (b->ctx[0]->hp.lk_radius != LK_R_MAX) {
+        for (int l = 0; l < VS_MAX_LEVELS; ++l) choice[l] = 0;
+        return VS_OK;
+    }
+    std::vector<vs_color_state> saved(b->n);
+    for (int c = 0; c < b->n; ++c) {
+        vs_status st = vs_state_get(b->ctx[c], &saved[c]);
+        if (st != VS_OK) return st;
+    }
+    hipEvent_t e0, e1;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) return VS_E_DEVICE;
+    const int variants[3] = {1, 2, 4};
+    vs_status st = VS_OK;
+    for (int l = 0; l < levels && st == VS_OK; ++l) {
+        float best = 1e30f;
+        int best_v = b->ctx[0]->hp.lk_P[l];
+        for (int vi = 0; vi < 3 && st == VS_OK; ++vi) {
+            st = set_variant_all(b, l, variants[vi]);
+            if (st == VS_OK) st = capture(b);
+            if (st != VS_OK) break;
+            st = vs_batch_run(b, frames, panos, nullptr);   // warm
+            if (st != VS_OK) break;
+            (void)hipEventRecord(e0, nullptr);
+            for (int r = 0; r < reps && st == VS_OK; ++r) st = vs_batch_run(b, frames, panos, nullptr);
+            (void)hipEventRecord(e1, nullptr);
+            if (hipEventSynchronize(e1) != hipSuccess) st = VS_E_DEVICE;
+            float ms = 0.0f;
+            (void)hipEventElapsedTime(&ms, e0, e1);
+            ms /= (float)reps;
+            if (ms_out) ms_out[l][vi] = ms;
+            if (ms < best) {
+                best = ms;
+                best_v = variants[vi];
+            }
+        }
+        if (st == VS_OK) st = set_variant_all(b, l, best_v);
+        choice[l] = best_v;
+    }
+    for (int l = levels; l < VS_MAX_LEVELS; ++l) choice[l] = 0;
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (st == VS_OK) st = capture(b);
+    for (int c = 0; c < b->n && st == VS_OK; ++c) st = vs_state_set(b->ctx[c], &saved[c]);
+    return st;
+}
+
+
+// ---------------------------------------------------------------------------
+// The plain estimator on caller image pairs (labels for the surrogate)
+// ---------------------------------------------------------------------------
+
+}  // extern "C"
+
+struct vs_flow {
+    DevPlan hp;
+    DevPlan* dp = nullptr;
+    void* arena = nullptr;
+};
+
+extern "C" {
+
+vs_status vs_flow_destroy(vs_flow* f)
+{
+    if (!f) return VS_E_INVAL;
+    if (f->arena) (void)hipFree(f->arena);
+    if (f->dp) (void)hipFree(f->dp);
+    delete f;
+    return VS_OK;
+}
+
+vs_status vs_flow_create(int w, int h, const vs_params* prm, vs_flow** out)
+{
+    if (!out || w < 2 || h < 2 || w > 65535 || h > 65535) return VS_E_INVAL;
+    *out = nullptr;
+    vs_params P;
+    if (prm) P = *prm;
+    else vs_default_params(&P);
+    if (P.lk_levels < 1 || P.lk_levels > VS_MAX_LEVELS || P.lk_iters < 0 || P.lk_radius < 0 ||
+        P.lk_radius > LK_R_MAX || !std::isfinite(P.lk_lambda))
+        return VS_E_INVAL;
+    vs_flow* f = new (std::nothrow) vs_flow();
+    if (!f) return VS_E_NOMEM;
+    DevPlan& d = f->hp;
+    std::memset(&d, 0, sizeof d);
+    d.n_cams = 2;
+    d.n_pairs = 1;
+    d.levels = P.lk_levels;
+    d.use_flow = 1;
+    d.lk_radius = P.lk_radius;
+    d.lk_iters = P.lk_iters;
+    d.lk_lambda = P.lk_lambda;
+    d.pj[0] = 0;
+    d.pi[0] = 1;
+    d.sw[0] = w;
+    d.sh[0] = h;
+    int ww = w, hh = h;
+    for (int l = 0; l < d.levels; ++l) {
+        d.lw[0][l] = ww;
+        d.lh[0][l] = hh;
+        ww = (ww + 1) / 2;
+        hh = (hh + 1) / 2;
+    }
+    for (int l = 0; l < d.levels; ++l) {
+        d.pyr_off[l][0] = 0;
+        for (int fl = 0; fl < 2; ++fl) {
+            d.pyr_tx[l][fl] = (d.lw[0][l] + PYR_TX - 1) / PYR_TX;
+            d.pyr_off[l][fl + 1] = d.pyr_off[l][fl] + d.pyr_tx[l][fl] * ((d.lh[0][l] + PYR_TY - 1) / PYR_TY);
+        }
+        const int n16 = 2 * ((d.lw[0][l] + LKW_TX - 1) / LKW_TX) * ((d.lh[0][l] + 15) / 16);
+        set_lk_tiles(d, l, P.lk_radius == LK_R_MAX ? (n16 >= 1024 ? 4 : 1) : 0);
+    }
+    size_t off = 0, o_pyr[2][MAXL], o_flow[2][MAXL], o_need[MAXL], o_queue[MAXL];
+    for (int l = 0; l < d.levels; ++l) {
+        const size_t n = (size_t)d.lw[0][l] * d.lh[0][l];
+        o_need[l] = off;
+        off = align_up(off + n, 256);
+        for (int k = 0; k < 2; ++k) {
+            o_pyr[k][l] = off;
+            off = align_up(off + n * 4, 256);
+            o_flow[k][l] = off;
+            off = align_up(off + n * 8, 256);
+        }
+        d.lk_qcap[l] = d.lk_P[l] > 0 ? (int32_t)(2 * n) : 0;
+        o_queue[l] = off;
+        off = align_up(off + (size_t)d.lk_qcap[l] * 16, 256);
+    }
+    const size_t o_acc = off;
+    off = align_up(off + sizeof(Accum), 256);
+    const size_t o_res = off;
+    off = align_up(off + sizeof(Results), 256);
+    const size_t o_state = off;
+    off = align_up(off + sizeof(vs_color_state), 256);
+    if (hipMalloc(&f->arena, off) != hipSuccess || hipMalloc((void**)&f->dp, sizeof(DevPlan)) != hipSuccess) {
+        vs_flow_destroy(f);
+        return VS_E_NOMEM;
+    }
+    uint8_t* base = (uint8_t*)f->arena;
+    for (int l = 0; l < d.levels; ++l) {
+        d.need[0][l] = base + o_need[l];
+        d.lk_queue[l] = (uint4*)(base + o_queue[l]);
+        for (int k = 0; k < 2; ++k) {
+            d.pyr[0][k][l] = (float*)(base + o_pyr[k][l]);
+            d.flow[0][k][l] = (float2*)(base + o_flow[k][l]);
+        }
+    }
+    d.acc = (Accum*)(base + o_acc);
+    d.res = (Results*)(base + o_res);
+    d.state = (vs_color_state*)(base + o_state);
+    bool ok = hipMemset(f->arena, 0, off) == hipSuccess;
+    for (int l = 0; l < d.levels && ok; ++l)   // the whole image is the flow domain
+        ok = hipMemset(d.need[0][l], 1, (size_t)d.lw[0][l] * d.lh[0][l]) == hipSuccess;
+    ok = ok && hipMemcpy(f->dp, &d, sizeof d, hipMemcpyHostToDevice) == hipSuccess;
+    ok = ok && hipDeviceSynchronize() == hipSuccess;
+    if (!ok) {
+        vs_flow_destroy(f);
+        return VS_E_DEVICE;
+    }
+    *out = f;
+    return VS_OK;
+}
+
+vs_status vs_flow_run(vs_flow* f, const float* yt, const float* ym, float* flow_tm, float* flow_mt, void* stream)
+{
+    if (!f || !yt || !ym) return VS_E_INVAL;
+    const DevPlan& d = f->hp;
+    hipStream_t s = (hipStream_t)stream;
+    const size_t n = (size_t)d.sw[0] * d.sh[0];
+    Group g;
+    std::memset(&g, 0, sizeof g);
+    g.n = 1;
+    g.dp[0] = f->dp;
+    g.hp[0] = &f->hp;
+    hipError_t e = hipMemcpyAsync(d.pyr[0][0][0], yt, n * 4, hipMemcpyDeviceToDevice, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(d.pyr[0][1][0], ym, n * 4, hipMemcpyDeviceToDevice, s);
+    if (e == hipSuccess) e = launch_zero(g, s);
+    for (int l = 0; l + 1 < d.levels && e == hipSuccess; ++l) e = launch_pyr_down(g, l, s);
+    for (int l = d.levels - 1; l >= 0 && e == hipSuccess; --l) e = launch_lk(g, l, s);
+    if (e == hipSuccess && flow_tm) e = hipMemcpyAsync(flow_tm, d.flow[0][0][0], n * 8, hipMemcpyDeviceToDevice, s);
+    if (e == hipSuccess && flow_mt) e = hipMemcpyAsync(flow_mt, d.flow[0][1][0], n * 8, hipMemcpyDeviceToDevice, s);
+    return e == hipSuccess ? VS_OK : VS_E_DEVICE;
+}
+
+vs_status vs_flow_level(vs_flow* f, int level, float* yt, float* ym, int32_t* w_out, int32_t* h_out, void* stream)
+{
+    if (!f || level < 0 || level >= f->hp.levels) return VS_E_INVAL;
+    const DevPlan& d = f->hp;
+    if (w_out) *w_out = d.lw[0][level];
+    if (h_out) *h_out = d.lh[0][level];
+    const size_t n = (size_t)d.lw[0][level] * d.lh[0][level] * 4;
+    hipStream_t s = (hipStream_t)stream;
+    hipError_t e = hipSuccess;
+    if (yt) e = hipMemcpyAsync(yt, d.pyr[0][0][level], n, hipMemcpyDeviceToDevice, s);
+    if (e == hipSuccess && ym) e = hipMemcpyAsync(ym, d.pyr[0][1][level], n, hipMemcpyDeviceToDevice, s);
+    return e == hipSuccess ? VS_OK : VS_E_DEVICE;
 }
 
 vs_status vs_debug_tap(vs_ctx* c, int tap, int p, int sub, void* dst, size_t nbytes)

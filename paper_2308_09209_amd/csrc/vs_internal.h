@@ -11,6 +11,7 @@ namespace vs {
 constexpr int MAXC = VS_MAX_CAMS;
 constexpr int MAXP = VS_MAX_PAIRS;
 constexpr int MAXL = VS_MAX_LEVELS;
+constexpr int MAXB = 8;                       // contexts in one batched launch
 
 // Tile shapes.
 constexpr int STRIP_TX = 64, STRIP_TY = 32;   // strip kernels: 256 threads, 8 rows each
@@ -76,10 +77,30 @@ struct DevPlan {
     Accum* acc;
     Results* res;
     vs_color_state* state;
+    // this frame's inputs and output (caller-owned), set by k_set_io
+    const uint8_t* frame[MAXC];
+    uint8_t* pano;
 };
 
-struct FrameSet {
-    const uint8_t* f[MAXC];
+// One launch over several contexts: block b of the grid belongs to context c
+// with off[c] <= b < off[c + 1] and is that context's block b - off[c].
+struct Batch {
+    int32_t n;
+    int32_t off[MAXB + 1];
+    const DevPlan* plan[MAXB];
+};
+
+struct FrameIO {
+    DevPlan* plan[MAXB];
+    const uint8_t* frame[MAXB][MAXC];
+    uint8_t* pano[MAXB];
+};
+
+// host view of a group of contexts launched together
+struct Group {
+    int n;
+    DevPlan* dp[MAXB];
+    const DevPlan* hp[MAXB];
 };
 
 // plan-time output of the coverage kernel
@@ -91,17 +112,18 @@ struct PlanScan {
 
 // launchers (vs_kernels.hip); all return hipGetLastError() of the launch
 hipError_t launch_plan_scan(const DevPlan* dp, const DevPlan& hp, PlanScan* scan, hipStream_t s);
-hipError_t launch_zero(const DevPlan* dp, Accum* acc, hipStream_t s);
-hipError_t launch_strips(const DevPlan* dp, const DevPlan& hp, FrameSet fs, hipStream_t s);
-hipError_t launch_lut(const DevPlan* dp, const DevPlan& hp, hipStream_t s);
-hipError_t launch_moments_b(const DevPlan* dp, const DevPlan& hp, hipStream_t s);
-hipError_t launch_solve(const DevPlan* dp, hipStream_t s);
-hipError_t launch_pyr0(const DevPlan* dp, const DevPlan& hp, hipStream_t s);
-hipError_t launch_pyr_down(const DevPlan* dp, const DevPlan& hp, int level, hipStream_t s);
-hipError_t launch_lk(const DevPlan* dp, const DevPlan& hp, int level, hipStream_t s);
 hipError_t launch_need(const DevPlan* dp, const DevPlan& hp, hipStream_t s);
-hipError_t launch_blend(const DevPlan* dp, const DevPlan& hp, FrameSet fs, uint8_t* pano, hipStream_t s);
-hipError_t launch_balance_lut(const DevPlan* dp, hipStream_t s);
-hipError_t launch_balance_apply(const DevPlan* dp, const DevPlan& hp, uint8_t* pano, hipStream_t s);
+hipError_t launch_set_io(const FrameIO& io, int n, hipStream_t s);
+hipError_t launch_zero(const Group& g, hipStream_t s);
+hipError_t launch_strips(const Group& g, hipStream_t s);
+hipError_t launch_lut(const Group& g, hipStream_t s);
+hipError_t launch_moments_b(const Group& g, hipStream_t s);
+hipError_t launch_solve(const Group& g, hipStream_t s);
+hipError_t launch_pyr0(const Group& g, hipStream_t s);
+hipError_t launch_pyr_down(const Group& g, int level, hipStream_t s);
+hipError_t launch_lk(const Group& g, int level, hipStream_t s);
+hipError_t launch_blend(const Group& g, hipStream_t s);
+hipError_t launch_balance_lut(const Group& g, hipStream_t s);
+hipError_t launch_balance_apply(const Group& g, hipStream_t s);
 
 }  // namespace vs

@@ -81,6 +81,13 @@ __device__ __forceinline__ float capply(const float s[3], const float* __restric
     return clampf(t, 0.0f, 255.0f);
 }
 
+__device__ __forceinline__ int batch_block(const Batch& B, int b, int& c)
+{
+    c = 0;
+    while (c + 1 < B.n && b >= B.off[c + 1]) ++c;
+    return b - B.off[c];
+}
+
 __device__ __forceinline__ uint32_t wave_sum(uint32_t v)
 {
 #pragma unroll
@@ -189,18 +196,25 @@ hipError_t launch_plan_scan(const DevPlan* dp, const DevPlan& hp, PlanScan* scan
 // Per-frame accumulators <- 0 (a fill kernel, no memset node)
 // ---------------------------------------------------------------------------
 
-__global__ __launch_bounds__(256) void k_zero(uint4* p, int n16)
+__global__ __launch_bounds__(256) void k_zero(const Batch B)
 {
-    int i = blockIdx.x * 256 + threadIdx.x;
-    if (i < n16) p[i] = make_uint4(0, 0, 0, 0);
+    int c;
+    const int b = batch_block(B, blockIdx.x, c);
+    uint4* p = (uint4*)B.plan[c]->acc;
+    const int i = b * 256 + threadIdx.x;
+    if (i < (int)(sizeof(Accum) / 16)) p[i] = make_uint4(0, 0, 0, 0);
 }
 
-hipError_t launch_zero(const DevPlan*, Accum* acc, hipStream_t s)
+// Frame and panorama pointers of every context of the group, written into its
+// device plan before the frame's kernels run (they read them from there, so a
+// captured frame graph replays for any input buffers).
+__global__ void k_set_io(const FrameIO io)
 {
-    static_assert(sizeof(Accum) % 16 == 0, "Accum must be a multiple of 16 bytes");
-    int n16 = (int)(sizeof(Accum) / 16);
-    hipLaunchKernelGGL(k_zero, dim3((n16 + 255) / 256), dim3(256), 0, s, (uint4*)acc, n16);
-    return hipGetLastError();
+    const int c = blockIdx.x;
+    const int k = threadIdx.x;
+    DevPlan* P = io.plan[c];
+    if (k < MAXC) P->frame[k] = io.frame[c][k];
+    if (k == 0) P->pano = io.pano[c];
 }
 
 // ---------------------------------------------------------------------------
@@ -215,13 +229,13 @@ __device__ __forceinline__ int find_field(const int32_t* off, int n, int b)
     return f;
 }
 
-__global__ __launch_bounds__(256) void k_strips(const DevPlan* __restrict__ P, FrameSet fs)
+__device__ __forceinline__ void strips_body(const DevPlan* __restrict__ P, const int bid)
 {
     __shared__ uint32_t s_hist[4][2 * 3 * 256];   // 4 copies (lane & 3) against same-value conflicts
     __shared__ uint32_t s_red[4][7];
     const int tid = threadIdx.x;
-    const int p = find_field(P->strip_off, P->n_pairs, blockIdx.x);
-    const int t = blockIdx.x - P->strip_off[p];
+    const int p = find_field(P->strip_off, P->n_pairs, bid);
+    const int t = bid - P->strip_off[p];
     const int sw = P->sw[p], sh = P->sh[p];
     const int tx0 = (t % P->strip_tx[p]) * STRIP_TX, ty0 = (t / P->strip_tx[p]) * STRIP_TY;
     for (int i = tid; i < 4 * 2 * 3 * 256; i += 256) (&s_hist[0][0])[i] = 0;
@@ -240,10 +254,10 @@ __global__ __launch_bounds__(256) void k_strips(const DevPlan* __restrict__ P, F
         const int X = P->sx0[p] + lx, Y = P->sy0[p] + ly;
         float u, v, rgb[3];
         bool okj = hom(P->hinv[kj], (float)X, (float)Y, P->cam_w[kj], P->cam_h[kj], u, v);
-        bilin3(fs.f[kj], P->cam_pitch[kj], P->cam_w[kj], P->cam_h[kj], u, v, rgb);
+        bilin3(P->frame[kj], P->cam_pitch[kj], P->cam_w[kj], P->cam_h[kj], u, v, rgb);
         uint32_t cj0 = round8(rgb[0]), cj1 = round8(rgb[1]), cj2 = round8(rgb[2]);
         bool oki = hom(P->hinv[ki], (float)(X - shift_i), (float)Y, P->cam_w[ki], P->cam_h[ki], u, v);
-        bilin3(fs.f[ki], P->cam_pitch[ki], P->cam_w[ki], P->cam_h[ki], u, v, rgb);
+        bilin3(P->frame[ki], P->cam_pitch[ki], P->cam_w[ki], P->cam_h[ki], u, v, rgb);
         uint32_t ci0 = round8(rgb[0]), ci1 = round8(rgb[1]), ci2 = round8(rgb[2]);
         const size_t q = (size_t)ly * sw + lx;
         strip[q] = cj0 | (cj1 << 8) | (cj2 << 16);
@@ -289,20 +303,22 @@ __global__ __launch_bounds__(256) void k_strips(const DevPlan* __restrict__ P, F
     }
 }
 
-hipError_t launch_strips(const DevPlan* dp, const DevPlan& hp, FrameSet fs, hipStream_t s)
+__global__ __launch_bounds__(256) void k_strips(const Batch B)
 {
-    hipLaunchKernelGGL(k_strips, dim3(hp.strip_off[hp.n_pairs]), dim3(256), 0, s, dp, fs);
-    return hipGetLastError();
+    int c;
+    const int b = batch_block(B, blockIdx.x, c);
+    strips_body(B.plan[c], b);
 }
+
 
 // ---------------------------------------------------------------------------
 // Section 2.1 step 3: histogram specification LUT(v) = min{w : C_j(w) >= C_i(v)}
 // ---------------------------------------------------------------------------
 
-__global__ __launch_bounds__(256) void k_lut(const DevPlan* __restrict__ P)
+__device__ __forceinline__ void lut_body(const DevPlan* __restrict__ P, const int bid)
 {
     __shared__ uint32_t Ci[3][256], Cj[3][256];
-    const int p = blockIdx.x, v = threadIdx.x;
+    const int p = bid, v = threadIdx.x;
     const Accum* acc = P->acc;
     for (int c = 0; c < 3; ++c) {
         Cj[c][v] = acc->hist[p][0][c][v];
@@ -334,23 +350,25 @@ __global__ __launch_bounds__(256) void k_lut(const DevPlan* __restrict__ P)
     }
 }
 
-hipError_t launch_lut(const DevPlan* dp, const DevPlan& hp, hipStream_t s)
+__global__ __launch_bounds__(256) void k_lut(const Batch B)
 {
-    hipLaunchKernelGGL(k_lut, dim3(hp.n_pairs), dim3(256), 0, s, dp);
-    return hipGetLastError();
+    int c;
+    const int b = batch_block(B, blockIdx.x, c);
+    lut_body(B.plan[c], b);
 }
+
 
 // ---------------------------------------------------------------------------
 // Eq. (1) B = I_i^T I_j with I_j = LUT(I_i) (the histogram-specified image i)
 // ---------------------------------------------------------------------------
 
-__global__ __launch_bounds__(256) void k_moments_b(const DevPlan* __restrict__ P)
+__device__ __forceinline__ void moments_b_body(const DevPlan* __restrict__ P, const int bid)
 {
     __shared__ uint8_t s_lut[3][256];
     __shared__ uint32_t s_red[4][9];
     const int tid = threadIdx.x;
-    const int p = find_field(P->strip_off, P->n_pairs, blockIdx.x);
-    const int t = blockIdx.x - P->strip_off[p];
+    const int p = find_field(P->strip_off, P->n_pairs, bid);
+    const int t = bid - P->strip_off[p];
     const int sw = P->sw[p], sh = P->sh[p];
     const int tx0 = (t % P->strip_tx[p]) * STRIP_TX, ty0 = (t / P->strip_tx[p]) * STRIP_TY;
     for (int i = tid; i < 3 * 256; i += 256) (&s_lut[0][0])[i] = (&P->res->lut[p][0][0])[i];
@@ -385,11 +403,13 @@ __global__ __launch_bounds__(256) void k_moments_b(const DevPlan* __restrict__ P
     }
 }
 
-hipError_t launch_moments_b(const DevPlan* dp, const DevPlan& hp, hipStream_t s)
+__global__ __launch_bounds__(256) void k_moments_b(const Batch B)
 {
-    hipLaunchKernelGGL(k_moments_b, dim3(hp.strip_off[hp.n_pairs]), dim3(256), 0, s, dp);
-    return hipGetLastError();
+    int c;
+    const int b = batch_block(B, blockIdx.x, c);
+    moments_b_body(B.plan[c], b);
 }
+
 
 // ---------------------------------------------------------------------------
 // Eqs. (2)-(4): 3D-M solve (FP64) per pair, chain composition, state shift
@@ -445,7 +465,7 @@ __device__ int solve3(const double* A, const double* B, double ridge, double* M)
     return 0;
 }
 
-__global__ __launch_bounds__(64) void k_solve(const DevPlan* __restrict__ P)
+__device__ __forceinline__ void solve_body(const DevPlan* __restrict__ P, const int bid)
 {
     __shared__ double s_M[MAXP][9];
     const int tid = threadIdx.x;
@@ -513,21 +533,23 @@ __global__ __launch_bounds__(64) void k_solve(const DevPlan* __restrict__ P)
     }
 }
 
-hipError_t launch_solve(const DevPlan* dp, hipStream_t s)
+__global__ __launch_bounds__(64) void k_solve(const Batch B)
 {
-    hipLaunchKernelGGL(k_solve, dim3(1), dim3(64), 0, s, dp);
-    return hipGetLastError();
+    int c;
+    const int b = batch_block(B, blockIdx.x, c);
+    solve_body(B.plan[c], b);
 }
+
 
 // ---------------------------------------------------------------------------
 // Flow input: luma of the colour-corrected strips, then the 2x pyramid
 // ---------------------------------------------------------------------------
 
-__global__ __launch_bounds__(256) void k_pyr0(const DevPlan* __restrict__ P)
+__device__ __forceinline__ void pyr0_body(const DevPlan* __restrict__ P, const int bid)
 {
-    const int f = find_field(P->pyr_off[0], 2 * P->n_pairs, blockIdx.x);
+    const int f = find_field(P->pyr_off[0], 2 * P->n_pairs, bid);
     const int p = f >> 1, cam = f & 1;
-    const int t = blockIdx.x - P->pyr_off[0][f];
+    const int t = bid - P->pyr_off[0][f];
     const int w = P->sw[p], h = P->sh[p];
     const int tx0 = (t % P->pyr_tx[0][f]) * PYR_TX, ty0 = (t / P->pyr_tx[0][f]) * PYR_TY;
     const float* M = P->res->Mk[cam == 0 ? P->pj[p] : P->pi[p]];
@@ -544,22 +566,24 @@ __global__ __launch_bounds__(256) void k_pyr0(const DevPlan* __restrict__ P)
     }
 }
 
-hipError_t launch_pyr0(const DevPlan* dp, const DevPlan& hp, hipStream_t s)
+__global__ __launch_bounds__(256) void k_pyr0(const Batch B)
 {
-    hipLaunchKernelGGL(k_pyr0, dim3(hp.pyr_off[0][2 * hp.n_pairs]), dim3(256), 0, s, dp);
-    return hipGetLastError();
+    int c;
+    const int b = batch_block(B, blockIdx.x, c);
+    pyr0_body(B.plan[c], b);
 }
+
 
 __device__ __forceinline__ int clampi(int v, int lo, int hi) { return v < lo ? lo : (v > hi ? hi : v); }
 
 // level l -> l + 1: separable [1 4 6 4 1] / 16, horizontal first, clamped,
 // even positions; each pass ((((a0 + 4 a1) + 6 a2) + 4 a3) + a4) / 16
-__global__ __launch_bounds__(256) void k_pyr_down(const DevPlan* __restrict__ P, int l)
+__device__ __forceinline__ void pyr_down_body(const DevPlan* __restrict__ P, const int bid, int l)
 {
     const int lo = l + 1;
-    const int f = find_field(P->pyr_off[lo], 2 * P->n_pairs, blockIdx.x);
+    const int f = find_field(P->pyr_off[lo], 2 * P->n_pairs, bid);
     const int p = f >> 1, cam = f & 1;
-    const int t = blockIdx.x - P->pyr_off[lo][f];
+    const int t = bid - P->pyr_off[lo][f];
     const int ws = P->lw[p][l], hs = P->lh[p][l];
     const int wd = P->lw[p][lo], hd = P->lh[p][lo];
     const int tx0 = (t % P->pyr_tx[lo][f]) * PYR_TX, ty0 = (t / P->pyr_tx[lo][f]) * PYR_TY;
@@ -589,11 +613,13 @@ __global__ __launch_bounds__(256) void k_pyr_down(const DevPlan* __restrict__ P,
     }
 }
 
-hipError_t launch_pyr_down(const DevPlan* dp, const DevPlan& hp, int level, hipStream_t s)
+__global__ __launch_bounds__(256) void k_pyr_down(const Batch B, int l)
 {
-    hipLaunchKernelGGL(k_pyr_down, dim3(hp.pyr_off[level + 1][2 * hp.n_pairs]), dim3(256), 0, s, dp, level);
-    return hipGetLastError();
+    int c;
+    const int b = batch_block(B, blockIdx.x, c);
+    pyr_down_body(B.plan[c], b, l);
 }
+
 
 // ---------------------------------------------------------------------------
 // Section 3.2 dense flow: pyramidal Lucas-Kanade at one level, every field
@@ -610,15 +636,15 @@ constexpr int LK_GW = LK_T + 2 * LK_R_MAX;       // 24
 constexpr int LK_HM = LK_R_MAX + LK_D + 1;       // 13
 constexpr int LK_MW = LK_T + 2 * LK_HM;          // 42
 
-__global__ __launch_bounds__(256) void k_lk(const DevPlan* __restrict__ P, int l)
+__device__ __forceinline__ void lk_body(const DevPlan* __restrict__ P, const int bid, int l)
 {
     __shared__ float sT[LK_TW][LK_TW];
     __shared__ float sIx[LK_GW][LK_GW];
     __shared__ float sIy[LK_GW][LK_GW];
     __shared__ float sM[LK_MW][LK_MW];
-    const int f = find_field(P->lk_off[l], 2 * P->n_pairs, blockIdx.x);
+    const int f = find_field(P->lk_off[l], 2 * P->n_pairs, bid);
     const int p = f >> 1, dir = f & 1;
-    const int t = blockIdx.x - P->lk_off[l][f];
+    const int t = bid - P->lk_off[l][f];
     const int w = P->lw[p][l], h = P->lh[p][l];
     const int x0 = (t % P->lk_tx[l][f]) * LK_T, y0 = (t / P->lk_tx[l][f]) * LK_T;
     const float* __restrict__ Tm = P->pyr[p][dir == 0 ? 0 : 1][l];
@@ -736,6 +762,13 @@ __global__ __launch_bounds__(256) void k_lk(const DevPlan* __restrict__ P, int l
     P->flow[p][dir][l][(size_t)y * w + x] = make_float2(ux, uy);
 }
 
+__global__ __launch_bounds__(256) void k_lk(const Batch B, int l)
+{
+    int c;
+    const int b = batch_block(B, blockIdx.x, c);
+    lk_body(B.plan[c], b, l);
+}
+
 // 9x9-window form of the same estimator (radius 4), P vertically adjacent
 // pixels per thread, a 64 x 4P block tile.  Identical arithmetic in identical
 // order; what changes is data movement:
@@ -747,7 +780,7 @@ __global__ __launch_bounds__(256) void k_lk(const DevPlan* __restrict__ P, int l
 //    window in registers: the bottom row of window row r is the top row of
 //    window row r + 1, so each tap costs ~1.1 moving-image LDS reads.
 template <int P>
-__global__ __launch_bounds__(256) void k_lk_w9(const DevPlan* __restrict__ Pl, int l)
+__device__ __forceinline__ void lk_w9_body(const DevPlan* __restrict__ Pl, const int bid, int l)
 {
     constexpr int R = LK_R_MAX, NW = 2 * R + 1;
     constexpr int TX = LKW_TX, TY = 4 * P;
@@ -759,9 +792,9 @@ __global__ __launch_bounds__(256) void k_lk_w9(const DevPlan* __restrict__ Pl, i
     __shared__ float sT[TSH * TSW];
     __shared__ float sM[MH * MW];
 
-    const int f = find_field(Pl->lk_off[l], 2 * Pl->n_pairs, blockIdx.x);
+    const int f = find_field(Pl->lk_off[l], 2 * Pl->n_pairs, bid);
     const int p = f >> 1, dir = f & 1;
-    const int t = blockIdx.x - Pl->lk_off[l][f];
+    const int t = bid - Pl->lk_off[l][f];
     const int w = Pl->lw[p][l], h = Pl->lh[p][l];
     const int x0 = (t % Pl->lk_tx[l][f]) * TX, y0 = (t / Pl->lk_tx[l][f]) * TY;
     const float* __restrict__ Tm = Pl->pyr[p][dir == 0 ? 0 : 1][l];
@@ -928,17 +961,29 @@ __global__ __launch_bounds__(256) void k_lk_w9(const DevPlan* __restrict__ Pl, i
         if (act[q]) Pl->flow[p][dir][l][(size_t)(yb + q) * w + x] = make_float2(ux[q], uy[q]);
 }
 
+template <int P>
+__global__ __launch_bounds__(256) void k_lk_w9(const Batch B, int l)
+{
+    int c;
+    const int b = batch_block(B, blockIdx.x, c);
+    lk_w9_body<P>(B.plan[c], b, l);
+}
+
 // Pixels whose displacement left the staged tile finish here, one pixel per
 // lane, every tap read from global memory with clamped indices (gradients 0
 // outside the level, as in the staged kernel, so the row-major sums are the
 // same).  Each window row issues all of its loads before using them: the
 // kernel is latency-bound on about one round trip per window row.
-__global__ __launch_bounds__(256) void k_lk_tail(const DevPlan* __restrict__ Pl, int l)
+__global__ __launch_bounds__(256) void k_lk_tail(const Batch B, int l)
 {
     constexpr int R = LK_R_MAX, NW = 2 * R + 1;
+    int c;
+    const int b = batch_block(B, blockIdx.x, c);
+    const int nb = B.off[c + 1] - B.off[c];          // this context's blocks
+    const DevPlan* __restrict__ Pl = B.plan[c];
     const uint32_t n = min(Pl->acc->lk_qn[l], (uint32_t)Pl->lk_qcap[l]);
     const int iters = Pl->lk_iters;
-    for (uint32_t i = blockIdx.x * 256 + threadIdx.x; i < n; i += gridDim.x * 256) {
+    for (uint32_t i = b * 256 + threadIdx.x; i < n; i += nb * 256) {
         const uint4 ent = Pl->lk_queue[l][i];
         const int f = (int)(ent.x & 255u), it0 = (int)(ent.x >> 8);
         const int x = (int)(ent.y & 0xffffu), y = (int)(ent.y >> 16);
@@ -1089,37 +1134,13 @@ hipError_t launch_need(const DevPlan* dp, const DevPlan& hp, hipStream_t s)
     return hipGetLastError();
 }
 
-hipError_t launch_lk(const DevPlan* dp, const DevPlan& hp, int level, hipStream_t s)
-{
-    const dim3 grid(hp.lk_off[level][2 * hp.n_pairs]);
-    switch (hp.lk_P[level]) {
-    case 4:
-        hipLaunchKernelGGL(k_lk_w9<4>, grid, dim3(256), 0, s, dp, level);
-        break;
-    case 2:
-        hipLaunchKernelGGL(k_lk_w9<2>, grid, dim3(256), 0, s, dp, level);
-        break;
-    case 1:
-        hipLaunchKernelGGL(k_lk_w9<1>, grid, dim3(256), 0, s, dp, level);
-        break;
-    default:
-        hipLaunchKernelGGL(k_lk, grid, dim3(256), 0, s, dp, level);
-        break;
-    }
-    if (hp.lk_P[level] > 0) {
-        // persistent grid-stride launch; the deferred count is read on the device
-        const int blocks = std::min(1024, (hp.lk_qcap[level] + 255) / 256);   // 1 pixel per lane
-        hipLaunchKernelGGL(k_lk_tail, dim3(std::max(1, blocks)), dim3(256), 0, s, dp, level);
-    }
-    return hipGetLastError();
-}
 
 // ---------------------------------------------------------------------------
 // Eqs. (15)-(18): per canvas pixel resample, local warp and weighted fusion,
 // plus the histogram of the covered output (input of section 2.2)
 // ---------------------------------------------------------------------------
 
-__global__ __launch_bounds__(BL_THREADS) void k_blend(const DevPlan* __restrict__ P, FrameSet fs, uint8_t* __restrict__ pano)
+__device__ __forceinline__ void blend_body(const DevPlan* __restrict__ P, const int bid)
 {
     // 8 copies of the histogram (lane & 7): neighbouring pixels often share a
     // value, and same-address LDS atomics from one instruction serialise
@@ -1128,7 +1149,7 @@ __global__ __launch_bounds__(BL_THREADS) void k_blend(const DevPlan* __restrict_
     for (int i = tid; i < 8 * 3 * 256; i += BL_THREADS) (&s_hist[0][0])[i] = 0;
     __syncthreads();
     uint32_t* const my_hist = s_hist[tid & 7];
-    const int bx = blockIdx.x % P->blend_tx, by = blockIdx.x / P->blend_tx;
+    const int bx = bid % P->blend_tx, by = bid / P->blend_tx;
     const unsigned long long cand = P->cand[by * P->blend_tx + bx];
     const int W = P->canvas_w, H = P->canvas_h, Wp = P->Wp;
     const int xq = bx * BL_TX + (tid & 63) * 4;
@@ -1161,7 +1182,7 @@ __global__ __launch_bounds__(BL_THREADS) void k_blend(const DevPlan* __restrict_
                 if (nh == 1) {
                     const int k = hc[0];
                     float s[3];
-                    bilin3(fs.f[k], P->cam_pitch[k], P->cam_w[k], P->cam_h[k], hu[0], hv[0], s);
+                    bilin3(P->frame[k], P->cam_pitch[k], P->cam_w[k], P->cam_h[k], hu[0], hv[0], s);
                     const float* M = P->res->Mk[k];
                     o0 = round8(capply(s, M, 0));
                     o1 = round8(capply(s, M, 1));
@@ -1188,9 +1209,9 @@ __global__ __launch_bounds__(BL_THREADS) void k_blend(const DevPlan* __restrict_
                     const float Yj = __builtin_fmaf(thi, fji.y, (float)y);
                     float u, v, si[3], sj[3];
                     hom(P->hinv[ki], Xi, Yi, P->cam_w[ki], P->cam_h[ki], u, v);
-                    bilin3(fs.f[ki], P->cam_pitch[ki], P->cam_w[ki], P->cam_h[ki], u, v, si);
+                    bilin3(P->frame[ki], P->cam_pitch[ki], P->cam_w[ki], P->cam_h[ki], u, v, si);
                     hom(P->hinv[kj], Xj, Yj, P->cam_w[kj], P->cam_h[kj], u, v);
-                    bilin3(fs.f[kj], P->cam_pitch[kj], P->cam_w[kj], P->cam_h[kj], u, v, sj);
+                    bilin3(P->frame[kj], P->cam_pitch[kj], P->cam_w[kj], P->cam_h[kj], u, v, sj);
                     const float* Mi = P->res->Mk[ki];
                     const float* Mj = P->res->Mk[kj];
                     float ti, tj;
@@ -1214,7 +1235,7 @@ __global__ __launch_bounds__(BL_THREADS) void k_blend(const DevPlan* __restrict_
             ob[q * 3 + 1] = o1;
             ob[q * 3 + 2] = o2;
         }
-        uint8_t* row = pano + (size_t)y * P->pano_pitch + (size_t)xq * 3;
+        uint8_t* row = P->pano + (size_t)y * P->pano_pitch + (size_t)xq * 3;
         if (vec && xq + 3 < W) {
             uint32_t* r32 = (uint32_t*)row;
             r32[0] = ob[0] | (ob[1] << 8) | (ob[2] << 16) | (ob[3] << 24);
@@ -1238,17 +1259,19 @@ __global__ __launch_bounds__(BL_THREADS) void k_blend(const DevPlan* __restrict_
     }
 }
 
-hipError_t launch_blend(const DevPlan* dp, const DevPlan& hp, FrameSet fs, uint8_t* pano, hipStream_t s)
+__global__ __launch_bounds__(BL_THREADS) void k_blend(const Batch B)
 {
-    hipLaunchKernelGGL(k_blend, dim3(hp.blend_tx * hp.blend_ty), dim3(BL_THREADS), 0, s, dp, fs, pano);
-    return hipGetLastError();
+    int c;
+    const int b = batch_block(B, blockIdx.x, c);
+    blend_body(B.plan[c], b);
 }
+
 
 // ---------------------------------------------------------------------------
 // Section 2.2, eqs. (5)-(7): thresholds, 3-frame mean, piecewise LUT
 // ---------------------------------------------------------------------------
 
-__global__ __launch_bounds__(256) void k_balance_lut(const DevPlan* __restrict__ P)
+__device__ __forceinline__ void balance_lut_body(const DevPlan* __restrict__ P, const int bid)
 {
     __shared__ uint32_t C[3][256];
     __shared__ double s_m[3][2];
@@ -1329,19 +1352,21 @@ __global__ __launch_bounds__(256) void k_balance_lut(const DevPlan* __restrict__
     }
 }
 
-hipError_t launch_balance_lut(const DevPlan* dp, hipStream_t s)
+__global__ __launch_bounds__(256) void k_balance_lut(const Batch B)
 {
-    hipLaunchKernelGGL(k_balance_lut, dim3(1), dim3(256), 0, s, dp);
-    return hipGetLastError();
+    int c;
+    const int b = batch_block(B, blockIdx.x, c);
+    balance_lut_body(B.plan[c], b);
 }
 
-__global__ __launch_bounds__(BL_THREADS) void k_balance_apply(const DevPlan* __restrict__ P, uint8_t* __restrict__ pano)
+
+__device__ __forceinline__ void balance_apply_body(const DevPlan* __restrict__ P, const int bid)
 {
     __shared__ uint8_t s_lut[3][256];
     const int tid = threadIdx.x;
     for (int i = tid; i < 3 * 256; i += BL_THREADS) (&s_lut[0][0])[i] = (&P->res->bal_lut[0][0])[i];
     __syncthreads();
-    const int bx = blockIdx.x % P->blend_tx, by = blockIdx.x / P->blend_tx;
+    const int bx = bid % P->blend_tx, by = bid / P->blend_tx;
     const int W = P->canvas_w, H = P->canvas_h;
     const int xq = bx * BL_TX + (tid & 63) * 4;
     const bool vec = (W & 3) == 0;
@@ -1350,7 +1375,7 @@ __global__ __launch_bounds__(BL_THREADS) void k_balance_apply(const DevPlan* __r
         if (y >= H || xq >= W) continue;
         const uint32_t bits = (P->cover[(size_t)y * P->cover_words + (xq >> 5)] >> (xq & 31)) & 15u;
         if (!bits) continue;
-        uint8_t* row = pano + (size_t)y * P->pano_pitch + (size_t)xq * 3;
+        uint8_t* row = P->pano + (size_t)y * P->pano_pitch + (size_t)xq * 3;
         if (vec && xq + 3 < W) {
             uint32_t* r32 = (uint32_t*)row;
             uint32_t w3[3] = {r32[0], r32[1], r32[2]};
@@ -1374,9 +1399,145 @@ __global__ __launch_bounds__(BL_THREADS) void k_balance_apply(const DevPlan* __r
     }
 }
 
-hipError_t launch_balance_apply(const DevPlan* dp, const DevPlan& hp, uint8_t* pano, hipStream_t s)
+__global__ __launch_bounds__(BL_THREADS) void k_balance_apply(const Batch B)
 {
-    hipLaunchKernelGGL(k_balance_apply, dim3(hp.blend_tx * hp.blend_ty), dim3(BL_THREADS), 0, s, dp, pano);
+    int c;
+    const int b = batch_block(B, blockIdx.x, c);
+    balance_apply_body(B.plan[c], b);
+}
+
+
+// ---------------------------------------------------------------------------
+// Launchers: one grid over the tiles of every context of the group
+// ---------------------------------------------------------------------------
+
+namespace {
+
+template <typename F>
+bool make_batch(const Group& g, Batch& B, F blocks_of)
+{
+    B.n = g.n;
+    B.off[0] = 0;
+    for (int c = 0; c < g.n; ++c) {
+        B.plan[c] = g.dp[c];
+        B.off[c + 1] = B.off[c] + blocks_of(*g.hp[c]);
+    }
+    for (int c = g.n + 1; c <= MAXB; ++c) B.off[c] = B.off[g.n];
+    return B.off[g.n] > 0;
+}
+
+}  // namespace
+
+hipError_t launch_set_io(const FrameIO& io, int n, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_set_io, dim3(n), dim3(64), 0, s, io);
+    return hipGetLastError();
+}
+
+hipError_t launch_zero(const Group& g, hipStream_t s)
+{
+    Batch B;
+    const int per = (int)((sizeof(Accum) / 16 + 255) / 256);
+    if (make_batch(g, B, [&](const DevPlan&) { return per; }))
+        hipLaunchKernelGGL(k_zero, dim3(B.off[B.n]), dim3(256), 0, s, B);
+    return hipGetLastError();
+}
+
+hipError_t launch_strips(const Group& g, hipStream_t s)
+{
+    Batch B;
+    if (make_batch(g, B, [](const DevPlan& h) { return h.strip_off[h.n_pairs]; }))
+        hipLaunchKernelGGL(k_strips, dim3(B.off[B.n]), dim3(256), 0, s, B);
+    return hipGetLastError();
+}
+
+hipError_t launch_lut(const Group& g, hipStream_t s)
+{
+    Batch B;
+    if (make_batch(g, B, [](const DevPlan& h) { return h.n_pairs; }))
+        hipLaunchKernelGGL(k_lut, dim3(B.off[B.n]), dim3(256), 0, s, B);
+    return hipGetLastError();
+}
+
+hipError_t launch_moments_b(const Group& g, hipStream_t s)
+{
+    Batch B;
+    if (make_batch(g, B, [](const DevPlan& h) { return h.strip_off[h.n_pairs]; }))
+        hipLaunchKernelGGL(k_moments_b, dim3(B.off[B.n]), dim3(256), 0, s, B);
+    return hipGetLastError();
+}
+
+hipError_t launch_solve(const Group& g, hipStream_t s)
+{
+    Batch B;
+    if (make_batch(g, B, [](const DevPlan&) { return 1; }))
+        hipLaunchKernelGGL(k_solve, dim3(B.off[B.n]), dim3(64), 0, s, B);
+    return hipGetLastError();
+}
+
+hipError_t launch_pyr0(const Group& g, hipStream_t s)
+{
+    Batch B;
+    if (make_batch(g, B, [](const DevPlan& h) { return h.use_flow ? h.pyr_off[0][2 * h.n_pairs] : 0; }))
+        hipLaunchKernelGGL(k_pyr0, dim3(B.off[B.n]), dim3(256), 0, s, B);
+    return hipGetLastError();
+}
+
+hipError_t launch_pyr_down(const Group& g, int l, hipStream_t s)
+{
+    Batch B;
+    if (make_batch(g, B, [l](const DevPlan& h) {
+            return h.use_flow && l + 1 < h.levels ? h.pyr_off[l + 1][2 * h.n_pairs] : 0; }))
+        hipLaunchKernelGGL(k_pyr_down, dim3(B.off[B.n]), dim3(256), 0, s, B, l);
+    return hipGetLastError();
+}
+
+hipError_t launch_lk(const Group& g, int l, hipStream_t s)
+{
+    // every context of a group runs the same flow-kernel variant at a level
+    const int P = g.hp[0]->lk_P[l];
+    for (int c = 1; c < g.n; ++c)
+        if (g.hp[c]->lk_P[l] != P) return hipErrorInvalidValue;
+    Batch B;
+    if (make_batch(g, B, [l](const DevPlan& h) { return h.use_flow && l < h.levels ? h.lk_off[l][2 * h.n_pairs] : 0; })) {
+        const dim3 grid(B.off[B.n]);
+        switch (P) {
+        case 4: hipLaunchKernelGGL(k_lk_w9<4>, grid, dim3(256), 0, s, B, l); break;
+        case 2: hipLaunchKernelGGL(k_lk_w9<2>, grid, dim3(256), 0, s, B, l); break;
+        case 1: hipLaunchKernelGGL(k_lk_w9<1>, grid, dim3(256), 0, s, B, l); break;
+        default: hipLaunchKernelGGL(k_lk, grid, dim3(256), 0, s, B, l); break;
+        }
+    }
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess || P == 0) return e;
+    // deferred pixels: the device-side count bounds the grid-stride loop
+    if (make_batch(g, B, [l](const DevPlan& h) {
+            return h.use_flow && l < h.levels ? std::min(1024, std::max(1, (h.lk_qcap[l] + 255) / 256)) : 0; }))
+        hipLaunchKernelGGL(k_lk_tail, dim3(B.off[B.n]), dim3(256), 0, s, B, l);
+    return hipGetLastError();
+}
+
+hipError_t launch_blend(const Group& g, hipStream_t s)
+{
+    Batch B;
+    if (make_batch(g, B, [](const DevPlan& h) { return h.blend_tx * h.blend_ty; }))
+        hipLaunchKernelGGL(k_blend, dim3(B.off[B.n]), dim3(BL_THREADS), 0, s, B);
+    return hipGetLastError();
+}
+
+hipError_t launch_balance_lut(const Group& g, hipStream_t s)
+{
+    Batch B;
+    if (make_batch(g, B, [](const DevPlan&) { return 1; }))
+        hipLaunchKernelGGL(k_balance_lut, dim3(B.off[B.n]), dim3(256), 0, s, B);
+    return hipGetLastError();
+}
+
+hipError_t launch_balance_apply(const Group& g, hipStream_t s)
+{
+    Batch B;
+    if (make_batch(g, B, [](const DevPlan& h) { return h.balance ? h.blend_tx * h.blend_ty : 0; }))
+        hipLaunchKernelGGL(k_balance_apply, dim3(B.off[B.n]), dim3(BL_THREADS), 0, s, B);
     return hipGetLastError();
 }
 

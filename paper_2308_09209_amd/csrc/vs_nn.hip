@@ -1,0 +1,396 @@
+// vs_nn.hip -- the learned flow surrogate: a small 3x3 convolution network in
+// BF16 with FP32 accumulation, forward and backward on the matrix cores
+// (v_mfma_f32_16x16x16_bf16, wave64), plus the pointwise, loss and optimiser
+// kernels its training needs.  Activations are NHWC with 16 or 32 channels;
+// weights are [Cout][tap][Cin] (tap = 3 ky + kx).
+#include <algorithm>
+
+#include "vs_nn.h"
+
+namespace vs {
+namespace nn {
+
+typedef short bf16x4 __attribute__((ext_vector_type(4)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ uint16_t f2bf(float f)
+{
+    // round to nearest even (finite inputs)
+    uint32_t u = __float_as_uint(f);
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return (uint16_t)(u >> 16);
+}
+
+__device__ __forceinline__ float bf2f(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
+
+__device__ __forceinline__ int find_img(const ImgTable& T, int b)
+{
+    int i = 0;
+    while (i + 1 < T.n && b >= T.tile_off[i + 1]) ++i;
+    return i;
+}
+
+// ---------------------------------------------------------------------------
+// 3x3 convolution, zero padding, as an implicit GEMM on the matrix cores:
+// D[pixel][cout] = sum_{tap, cin} X[pixel + tap][cin] W[cout][tap][cin].
+// A block computes 64 consecutive pixels of one image (16 per wavefront) for
+// every output channel.  MFMA 16x16x16 BF16 fragments: lane l holds
+// A[m = l % 16][k = 4 (l / 16) + i], B[k = 4 (l / 16) + i][n = l % 16] and
+// D[m = 4 (l / 16) + i][n = l % 16], i = 0..3.
+// ---------------------------------------------------------------------------
+template <int CIN, int COUT, int MODE>
+__global__ __launch_bounds__(256) void k_conv3x3(const uint16_t* __restrict__ X, const uint16_t* __restrict__ Wt,
+                                                 const float* __restrict__ bias, void* __restrict__ Y,
+                                                 const ImgTable T, float alpha)
+{
+    static_assert(CIN % 16 == 0 && COUT % 16 == 0, "channels in multiples of 16");
+    constexpr int NT = COUT / 16, NC = CIN / 16;
+    __shared__ bf16x4 sW[COUT * 9 * CIN / 4];
+    const int tid = threadIdx.x;
+    const bf16x4* Wv = reinterpret_cast<const bf16x4*>(Wt);
+    for (int i = tid; i < COUT * 9 * CIN / 4; i += 256) sW[i] = Wv[i];
+    __syncthreads();
+
+    const int img = find_img(T, blockIdx.x);
+    const int W = T.w[img], H = T.h[img], npix = W * H;
+    const long base = T.pix_off[img];
+    const int lane = tid & 63, wv = tid >> 6;
+    const int m = lane & 15, kg = lane >> 4;
+    const int q0 = (blockIdx.x - T.tile_off[img]) * 64 + wv * 16;
+    const int q = q0 + m;
+    const bool valid = q < npix;
+    const int y = valid ? q / W : 0, x = valid ? q % W : 0;
+    f32x4 acc[NT];
+#pragma unroll
+    for (int t = 0; t < NT; ++t) acc[t] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+    for (int tap = 0; tap < 9; ++tap) {
+        const int yy = y + tap / 3 - 1, xx = x + tap % 3 - 1;
+        const bool inb = valid && yy >= 0 && yy < H && xx >= 0 && xx < W;
+        const bf16x4* src = reinterpret_cast<const bf16x4*>(X + (base + (long)yy * W + xx) * CIN);
+#pragma unroll
+        for (int c = 0; c < NC; ++c) {
+            const bf16x4 a = inb ? src[c * 4 + kg] : bf16x4{0, 0, 0, 0};
+#pragma unroll
+            for (int t = 0; t < NT; ++t) {
+                const bf16x4 b = sW[((t * 16 + m) * 9 + tap) * (CIN / 4) + c * 4 + kg];
+                acc[t] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, acc[t], 0, 0, 0);
+            }
+        }
+    }
+#pragma unroll
+    for (int t = 0; t < NT; ++t) {
+        const int co = t * 16 + m;
+        const float bb = bias ? bias[co] : 0.0f;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int qq = q0 + kg * 4 + i;
+            if (qq >= npix) continue;
+            float v = acc[t][i] + bb;
+            if (MODE == CONV_LRELU) v = v > 0.0f ? v : alpha * v;
+            const long o = (base + qq) * COUT + co;
+            if (MODE == CONV_F32) static_cast<float*>(Y)[o] = v;
+            else static_cast<uint16_t*>(Y)[o] = f2bf(v);
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Weight gradient: dW[cout][tap][cin] = sum_pixels dZ[p][cout] X[p + tap][cin],
+// db[cout] = sum_pixels dZ[p][cout].  Each block reduces 256 pixels of one
+// image on the matrix cores (M = cout, N = cin, K = pixels) and writes its
+// partial sums; k_reduce_partials adds the partials in block order, so the
+// result does not depend on scheduling.  Wavefront w takes taps w, w+4, w+8.
+// ---------------------------------------------------------------------------
+constexpr int WG_PIX = 256;
+
+template <int CIN, int COUT>
+__global__ __launch_bounds__(256) void k_conv3x3_wgrad(const uint16_t* __restrict__ X, const uint16_t* __restrict__ dZ,
+                                                       float* __restrict__ part, const ImgTable T)
+{
+    constexpr int MT = COUT / 16, NC = CIN / 16, NPAR = COUT * 9 * CIN + COUT;
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const int m = lane & 15, kg = lane >> 4;
+    const int img = find_img(T, blockIdx.x);
+    const int W = T.w[img], H = T.h[img], npix = W * H;
+    const long base = T.pix_off[img];
+    const int p0 = (blockIdx.x - T.tile_off[img]) * WG_PIX;
+    float* out = part + (long)blockIdx.x * NPAR;
+    for (int tap = wv; tap < 9; tap += 4) {
+        const int dy = tap / 3 - 1, dx = tap % 3 - 1;
+        f32x4 acc[MT][NC];
+#pragma unroll
+        for (int a = 0; a < MT; ++a)
+#pragma unroll
+            for (int c = 0; c < NC; ++c) acc[a][c] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+        for (int kb = 0; kb < WG_PIX; kb += 16) {
+            bf16x4 af[MT], bfr[NC];
+            short av[MT][4], bv[NC][4];
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int p = p0 + kb + kg * 4 + i;
+                const bool pv = p < npix;
+                const int y = pv ? p / W : 0, x = pv ? p % W : 0;
+                const int yy = y + dy, xx = x + dx;
+                const bool inb = pv && yy >= 0 && yy < H && xx >= 0 && xx < W;
+#pragma unroll
+                for (int a = 0; a < MT; ++a) av[a][i] = pv ? (short)dZ[(base + p) * COUT + a * 16 + m] : (short)0;
+#pragma unroll
+                for (int c = 0; c < NC; ++c)
+                    bv[c][i] = inb ? (short)X[(base + (long)yy * W + xx) * CIN + c * 16 + m] : (short)0;
+            }
+#pragma unroll
+            for (int a = 0; a < MT; ++a) af[a] = bf16x4{av[a][0], av[a][1], av[a][2], av[a][3]};
+#pragma unroll
+            for (int c = 0; c < NC; ++c) bfr[c] = bf16x4{bv[c][0], bv[c][1], bv[c][2], bv[c][3]};
+#pragma unroll
+            for (int a = 0; a < MT; ++a)
+#pragma unroll
+                for (int c = 0; c < NC; ++c)
+                    acc[a][c] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(af[a], bfr[c], acc[a][c], 0, 0, 0);
+        }
+#pragma unroll
+        for (int a = 0; a < MT; ++a)
+#pragma unroll
+            for (int c = 0; c < NC; ++c)
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    const int co = a * 16 + kg * 4 + i, ci = c * 16 + m;
+                    out[((long)co * 9 + tap) * CIN + ci] = acc[a][c][i];
+                }
+    }
+    // bias gradient: thread co sums its channel over the block's pixels in order
+    if (tid < COUT) {
+        float s = 0.0f;
+        for (int k = 0; k < WG_PIX; ++k) {
+            const int p = p0 + k;
+            if (p < npix) s += bf2f(dZ[(base + p) * COUT + tid]);
+        }
+        out[COUT * 9 * CIN + tid] = s;
+    }
+}
+
+__global__ __launch_bounds__(256) void k_reduce_partials(const float* __restrict__ part, int nblocks, int n,
+                                                         float* __restrict__ out)
+{
+    const int j = blockIdx.x * 256 + threadIdx.x;
+    if (j >= n) return;
+    float s = 0.0f;
+    for (int b = 0; b < nblocks; ++b) s += part[(long)b * n + j];
+    out[j] = s;
+}
+
+// W'[cin][tap][cout] = W[cout][8 - tap][cin]: the data-gradient convolution
+// is the forward convolution with these weights.
+__global__ __launch_bounds__(256) void k_flip_weights(const uint16_t* __restrict__ W, uint16_t* __restrict__ Wf,
+                                                      int cin, int cout)
+{
+    const int j = blockIdx.x * 256 + threadIdx.x;
+    if (j >= cin * 9 * cout) return;
+    const int co = j % cout, tap = (j / cout) % 9, ci = j / (cout * 9);
+    Wf[j] = W[((long)co * 9 + (8 - tap)) * cin + ci];
+}
+
+// dZ = dH * lrelu'(Z), with the sign of Z read from H = lrelu(Z) (alpha > 0)
+__global__ __launch_bounds__(256) void k_lrelu_bwd(const uint16_t* __restrict__ dH, const uint16_t* __restrict__ Hh,
+                                                   uint16_t* __restrict__ dZ, long n, float alpha)
+{
+    const long j = (long)blockIdx.x * 256 + threadIdx.x;
+    if (j >= n) return;
+    const float g = bf2f(dH[j]);
+    dZ[j] = f2bf(bf2f(Hh[j]) > 0.0f ? g : alpha * g);
+}
+
+// ---------------------------------------------------------------------------
+// Input packing: level luma images of a template / moving pair -> 16-channel
+// BF16 (channel 0 template, 1 moving, rest 0), normalised (Y - 128) / 64.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_pack_pair(const float* __restrict__ Yt, const float* __restrict__ Ym,
+                                                   uint16_t* __restrict__ X, long npix)
+{
+    const long p = (long)blockIdx.x * 256 + threadIdx.x;
+    if (p >= npix) return;
+    uint16_t v[16];
+    v[0] = f2bf((Yt[p] - 128.0f) * (1.0f / 64.0f));
+    v[1] = f2bf((Ym[p] - 128.0f) * (1.0f / 64.0f));
+#pragma unroll
+    for (int c = 2; c < 16; ++c) v[c] = 0;
+    uint4* d = reinterpret_cast<uint4*>(X + p * 16);
+    d[0] = make_uint4(v[0] | (uint32_t)v[1] << 16, 0u, 0u, 0u);
+    d[1] = make_uint4(0u, 0u, 0u, 0u);
+}
+
+// ---------------------------------------------------------------------------
+// Loss: mean end-point error of channels 0-1 of the FP32 prediction against
+// the label flow, with its gradient (BF16, 16 channels, 2..15 zero) and one
+// partial sum per block.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_epe_loss(const float* __restrict__ pred, const float* __restrict__ label,
+                                                  uint16_t* __restrict__ dZ, float* __restrict__ block_loss, long npix,
+                                                  float inv_n)
+{
+    __shared__ float s_red[4];
+    const long p = (long)blockIdx.x * 256 + threadIdx.x;
+    float e = 0.0f;
+    uint16_t g0 = 0, g1 = 0;
+    if (p < npix) {
+        const float dx = pred[p * 16] - label[p * 2], dy = pred[p * 16 + 1] - label[p * 2 + 1];
+        e = sqrtf(dx * dx + dy * dy + 1e-6f);
+        g0 = f2bf(dx / e * inv_n);
+        g1 = f2bf(dy / e * inv_n);
+        uint4* d = reinterpret_cast<uint4*>(dZ + p * 16);
+        d[0] = make_uint4(g0 | (uint32_t)g1 << 16, 0u, 0u, 0u);
+        d[1] = make_uint4(0u, 0u, 0u, 0u);
+    }
+    for (int o = 32; o > 0; o >>= 1) e += __shfl_xor(e, o, 64);
+    if ((threadIdx.x & 63) == 0) s_red[threadIdx.x >> 6] = e;
+    __syncthreads();
+    if (threadIdx.x == 0) block_loss[blockIdx.x] = ((s_red[0] + s_red[1]) + s_red[2]) + s_red[3];
+}
+
+// Adam on FP32 master parameters, with a BF16 copy of the weights
+__global__ __launch_bounds__(256) void k_adam(float* __restrict__ w, float* __restrict__ m, float* __restrict__ v,
+                                              const float* __restrict__ g, uint16_t* __restrict__ w_bf16, long n,
+                                              float lr, float b1, float b2, float eps, float c1, float c2)
+{
+    const long j = (long)blockIdx.x * 256 + threadIdx.x;
+    if (j >= n) return;
+    const float gj = g[j];
+    const float mj = b1 * m[j] + (1.0f - b1) * gj;
+    const float vj = b2 * v[j] + (1.0f - b2) * gj * gj;
+    m[j] = mj;
+    v[j] = vj;
+    const float wj = w[j] - lr * (mj / c1) / (sqrtf(vj / c2) + eps);
+    w[j] = wj;
+    if (w_bf16) w_bf16[j] = f2bf(wj);
+}
+
+__global__ __launch_bounds__(256) void k_to_bf16(const float* __restrict__ a, uint16_t* __restrict__ b, long n)
+{
+    const long j = (long)blockIdx.x * 256 + threadIdx.x;
+    if (j < n) b[j] = f2bf(a[j]);
+}
+
+// One MFMA on fixed fragments: out[l][i] = D fragment of lane l for
+// A[m][k] = a[m * 16 + k], B[k][n] = b[k * 16 + n] (a lane-layout check).
+__global__ void k_mfma_probe(const uint16_t* __restrict__ a, const uint16_t* __restrict__ b, float* __restrict__ out)
+{
+    const int l = threadIdx.x, m = l & 15, kg = l >> 4;
+    bf16x4 af, bf;
+    for (int i = 0; i < 4; ++i) {
+        af[i] = (short)a[m * 16 + kg * 4 + i];
+        bf[i] = (short)b[(kg * 4 + i) * 16 + m];
+    }
+    f32x4 d = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(af, bf, f32x4{0.0f, 0.0f, 0.0f, 0.0f}, 0, 0, 0);
+    for (int i = 0; i < 4; ++i) out[l * 4 + i] = d[i];
+}
+
+// ---------------------------------------------------------------------------
+// launchers
+// ---------------------------------------------------------------------------
+
+template <int CIN, int COUT>
+static hipError_t conv_mode(const uint16_t* X, const uint16_t* W, const float* b, void* Y, const ImgTable& T,
+                            int mode, float alpha, hipStream_t s)
+{
+    const dim3 g(T.tile_off[T.n]), blk(256);
+    switch (mode) {
+    case CONV_LRELU: hipLaunchKernelGGL((k_conv3x3<CIN, COUT, CONV_LRELU>), g, blk, 0, s, X, W, b, Y, T, alpha); break;
+    case CONV_LINEAR: hipLaunchKernelGGL((k_conv3x3<CIN, COUT, CONV_LINEAR>), g, blk, 0, s, X, W, b, Y, T, alpha); break;
+    case CONV_F32: hipLaunchKernelGGL((k_conv3x3<CIN, COUT, CONV_F32>), g, blk, 0, s, X, W, b, Y, T, alpha); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t conv3x3(const uint16_t* X, int cin, const uint16_t* W, const float* b, void* Y, int cout,
+                   const ImgTable& T, int mode, float alpha, hipStream_t s)
+{
+    if (T.tile_off[T.n] <= 0) return hipSuccess;
+    if (cin == 16 && cout == 32) return conv_mode<16, 32>(X, W, b, Y, T, mode, alpha, s);
+    if (cin == 32 && cout == 32) return conv_mode<32, 32>(X, W, b, Y, T, mode, alpha, s);
+    if (cin == 32 && cout == 16) return conv_mode<32, 16>(X, W, b, Y, T, mode, alpha, s);
+    if (cin == 16 && cout == 16) return conv_mode<16, 16>(X, W, b, Y, T, mode, alpha, s);
+    return hipErrorInvalidValue;
+}
+
+int wgrad_blocks(const ImgTable& T)
+{
+    int n = 0;
+    for (int i = 0; i < T.n; ++i) n += (T.w[i] * T.h[i] + WG_PIX - 1) / WG_PIX;
+    return n;
+}
+
+hipError_t conv3x3_wgrad(const uint16_t* X, int cin, const uint16_t* dZ, int cout, const ImgTable& T, float* part,
+                         float* dWb, hipStream_t s)
+{
+    ImgTable G = T;   // tiles of WG_PIX pixels
+    G.tile_off[0] = 0;
+    for (int i = 0; i < T.n; ++i) G.tile_off[i + 1] = G.tile_off[i] + (T.w[i] * T.h[i] + WG_PIX - 1) / WG_PIX;
+    const int nb = G.tile_off[G.n];
+    if (nb <= 0) return hipSuccess;
+    if (cin == 16 && cout == 32) hipLaunchKernelGGL((k_conv3x3_wgrad<16, 32>), dim3(nb), dim3(256), 0, s, X, dZ, part, G);
+    else if (cin == 32 && cout == 32) hipLaunchKernelGGL((k_conv3x3_wgrad<32, 32>), dim3(nb), dim3(256), 0, s, X, dZ, part, G);
+    else if (cin == 32 && cout == 16) hipLaunchKernelGGL((k_conv3x3_wgrad<32, 16>), dim3(nb), dim3(256), 0, s, X, dZ, part, G);
+    else return hipErrorInvalidValue;
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    const int npar = cout * 9 * cin + cout;
+    hipLaunchKernelGGL(k_reduce_partials, dim3((npar + 255) / 256), dim3(256), 0, s, part, nb, npar, dWb);
+    return hipGetLastError();
+}
+
+hipError_t flip_weights(const uint16_t* W, uint16_t* Wf, int cin, int cout, hipStream_t s)
+{
+    const int n = cin * 9 * cout;
+    hipLaunchKernelGGL(k_flip_weights, dim3((n + 255) / 256), dim3(256), 0, s, W, Wf, cin, cout);
+    return hipGetLastError();
+}
+
+hipError_t lrelu_bwd(const uint16_t* dH, const uint16_t* H, uint16_t* dZ, long n, float alpha, hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_lrelu_bwd, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, dH, H, dZ, n, alpha);
+    return hipGetLastError();
+}
+
+hipError_t pack_pair(const float* Yt, const float* Ym, uint16_t* X, long npix, hipStream_t s)
+{
+    if (npix <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_pack_pair, dim3((unsigned)((npix + 255) / 256)), dim3(256), 0, s, Yt, Ym, X, npix);
+    return hipGetLastError();
+}
+
+hipError_t epe_loss(const float* pred, const float* label, uint16_t* dZ, float* block_loss, long npix, hipStream_t s)
+{
+    if (npix <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_epe_loss, dim3((unsigned)((npix + 255) / 256)), dim3(256), 0, s, pred, label, dZ, block_loss,
+                       npix, 1.0f / (float)npix);
+    return hipGetLastError();
+}
+
+hipError_t adam(float* w, float* m, float* v, const float* g, uint16_t* w_bf16, long n, float lr, float b1, float b2,
+                float eps, int step, hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    const float c1 = 1.0f - powf(b1, (float)step), c2 = 1.0f - powf(b2, (float)step);
+    hipLaunchKernelGGL(k_adam, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, w, m, v, g, w_bf16, n, lr, b1, b2,
+                       eps, c1, c2);
+    return hipGetLastError();
+}
+
+hipError_t to_bf16(const float* a, uint16_t* b, long n, hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_to_bf16, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, a, b, n);
+    return hipGetLastError();
+}
+
+hipError_t mfma_probe(const uint16_t* a, const uint16_t* b, float* out, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_mfma_probe, dim3(1), dim3(64), 0, s, a, b, out);
+    return hipGetLastError();
+}
+
+}  // namespace nn
+}  // namespace vs

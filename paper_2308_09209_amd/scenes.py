@@ -233,6 +233,25 @@ class Scene:
         return [self.frame(k, t) for k in range(self.n_cams)]
 
 
+# Six uneven streams stitched together (3 or 4 cameras, 20 % overlap chains).
+BATCH_STREAMS = [
+    dict(n_cams=3, W=1280, H=720), dict(n_cams=4, W=1280, H=720),
+    dict(n_cams=3, W=1920, H=1080), dict(n_cams=4, W=1920, H=1080),
+    dict(n_cams=3, W=2560, H=1440), dict(n_cams=4, W=2560, H=1440),
+]
+
+
+def batch_scenes(streams=None, config: int = 3) -> list:
+    """The 6-stream batched workload: one Scene per stream (chain, 20 % overlap,
+    exposure drift 0.01 per frame), seeds 1000 * config + 10 * stream + camera."""
+    out = []
+    for i, spec in enumerate(streams or BATCH_STREAMS):
+        out.append(Scene(n_cams=spec["n_cams"], W=spec["W"], H=spec["H"], overlap=0.20, ring=False,
+                         tex_h=int(round(spec["H"] * 10 / 9)), tex_w=None, drift=0.01, resid=3.0,
+                         config=config, stream=i))
+    return out
+
+
 def scene_for(workload: str, stream: int = 0, **over) -> Scene:
     p = dict(WORKLOADS[workload])
     p.update(over)

@@ -33,7 +33,12 @@ TAP = dict(strip=1, mask=2, hist=3, lut=4, mom=5, mpair=6, mk=7, flags=8, pyr=9,
 # every symbol include/vstitch.h declares
 EXPORTS = ["vs_abi_version", "vs_status_str", "vs_default_params", "vs_compose_homographies",
            "vs_create", "vs_destroy", "vs_query", "vs_last_error", "vs_stitch", "vs_state_get",
-           "vs_state_set", "vs_debug_tap", "vs_set_timing", "vs_get_timing"]
+           "vs_state_set", "vs_debug_tap", "vs_set_timing", "vs_get_timing",
+           "vs_set_flow_variant", "vs_get_flow_variant", "vs_batch_create", "vs_batch_run",
+           "vs_batch_destroy", "vs_batch_last_error", "vs_batch_autotune",
+           "vs_nn_conv3x3", "vs_nn_wgrad_scratch_bytes", "vs_nn_conv3x3_wgrad", "vs_nn_flip_weights",
+           "vs_nn_lrelu_bwd", "vs_nn_pack_pair", "vs_nn_epe_loss", "vs_nn_adam", "vs_nn_to_bf16",
+           "vs_nn_mfma_probe", "vs_flow_create", "vs_flow_run", "vs_flow_destroy", "vs_flow_level"]
 
 
 class Rig(C.Structure):
@@ -73,6 +78,24 @@ class PlanInfo(C.Structure):
                 ("state_bytes", C.c_uint32)]
 
 
+NN_MAX_IMAGES = 64
+CONV_LRELU, CONV_LINEAR, CONV_F32 = 0, 1, 2
+
+
+class NNImages(C.Structure):
+    _fields_ = [("n", C.c_int32), ("w", C.c_int32 * NN_MAX_IMAGES), ("h", C.c_int32 * NN_MAX_IMAGES)]
+
+
+def nn_images(sizes):
+    """vs_nn_images for a list of (h, w) image sizes stored back to back."""
+    t = NNImages()
+    t.n = len(sizes)
+    for i, (h, w) in enumerate(sizes):
+        t.h[i] = h
+        t.w[i] = w
+    return t
+
+
 class FrameInfo(C.Structure):
     _fields_ = [("Mk", (C.c_float * 9) * MAX_CAMS), ("Mpair", (C.c_double * 9) * MAX_PAIRS),
                 ("flags", C.c_int32 * MAX_PAIRS), ("quant", (C.c_int32 * 2) * 3),
@@ -107,6 +130,32 @@ def lib():
         L.vs_debug_tap.argtypes = [C.c_void_p, C.c_int, C.c_int, C.c_int, C.c_void_p, C.c_size_t]
         L.vs_set_timing.argtypes = [C.c_void_p, C.c_int]
         L.vs_get_timing.argtypes = [C.c_void_p, C.c_void_p, C.POINTER(C.c_uint32)]
+        L.vs_set_flow_variant.argtypes = [C.c_void_p, C.c_int, C.c_int]
+        L.vs_get_flow_variant.argtypes = [C.c_void_p, C.c_void_p]
+        L.vs_batch_create.argtypes = [C.c_void_p, C.c_int, C.POINTER(C.c_void_p)]
+        L.vs_batch_run.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]
+        L.vs_batch_destroy.argtypes = [C.c_void_p]
+        L.vs_batch_last_error.restype = C.c_char_p
+        L.vs_batch_last_error.argtypes = [C.c_void_p]
+        L.vs_batch_autotune.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int, C.c_void_p,
+                                        C.c_void_p]
+        vp, i32, i64, f32 = C.c_void_p, C.c_int, C.c_int64, C.c_float
+        imgs = C.POINTER(NNImages)
+        L.vs_nn_conv3x3.argtypes = [vp, i32, vp, vp, vp, i32, imgs, i32, f32, vp]
+        L.vs_nn_wgrad_scratch_bytes.restype = C.c_size_t
+        L.vs_nn_wgrad_scratch_bytes.argtypes = [i32, i32, imgs]
+        L.vs_nn_conv3x3_wgrad.argtypes = [vp, i32, vp, i32, imgs, vp, C.c_size_t, vp, vp]
+        L.vs_nn_flip_weights.argtypes = [vp, vp, i32, i32, vp]
+        L.vs_nn_lrelu_bwd.argtypes = [vp, vp, vp, i64, f32, vp]
+        L.vs_nn_pack_pair.argtypes = [vp, vp, vp, i64, vp]
+        L.vs_nn_epe_loss.argtypes = [vp, vp, vp, vp, i64, vp]
+        L.vs_nn_adam.argtypes = [vp, vp, vp, vp, vp, i64, f32, f32, f32, f32, i32, vp]
+        L.vs_nn_to_bf16.argtypes = [vp, vp, i64, vp]
+        L.vs_nn_mfma_probe.argtypes = [vp, vp, vp, vp]
+        L.vs_flow_create.argtypes = [i32, i32, C.POINTER(Params), C.POINTER(C.c_void_p)]
+        L.vs_flow_run.argtypes = [vp, vp, vp, vp, vp, vp]
+        L.vs_flow_destroy.argtypes = [vp]
+        L.vs_flow_level.argtypes = [vp, i32, vp, vp, C.POINTER(C.c_int32), C.POINTER(C.c_int32), vp]
         _lib = L
     return _lib
 
@@ -268,6 +317,16 @@ class Stitcher:
             self._err(st, "vs_get_timing")
         return ms, n.value
 
+    def flow_variants(self):
+        v = np.zeros(MAX_LEVELS, np.int32)
+        lib().vs_get_flow_variant(self.h, v.ctypes.data_as(C.c_void_p))
+        return v[:self.info.lk_levels].tolist()
+
+    def set_flow_variant(self, level: int, variant: int):
+        st = lib().vs_set_flow_variant(self.h, level, variant)
+        if st != 0:
+            self._err(st, "vs_set_flow_variant")
+
     def tap(self, name: str, pair: int = 0, sub: int = 0) -> np.ndarray:
         I = self.info
         H, W = self.canvas
@@ -303,3 +362,111 @@ def state_from_bytes(b: bytes) -> ColorState:
     s = ColorState()
     C.memmove(C.addressof(s), b, C.sizeof(s))
     return s
+
+
+class Batch:
+    """Several stitching contexts run by one captured per-frame graph."""
+
+    def __init__(self, stitchers):
+        self.stitchers = list(stitchers)
+        arr = (C.c_void_p * len(self.stitchers))(*[st.h.value for st in self.stitchers])
+        h = C.c_void_p()
+        st = lib().vs_batch_create(arr, len(self.stitchers), C.byref(h))
+        if st != 0:
+            raise VSError(st, "vs_batch_create")
+        self.h = h
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().vs_batch_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        self.close()
+
+    def _ptrs(self, frames, panos):
+        n = len(self.stitchers)
+        if len(frames) != n or len(panos) != n:
+            raise ValueError("one frame list and one panorama per context")
+        rows = []
+        for st, fr, pano in zip(self.stitchers, frames, panos):
+            if len(fr) != st.n_cams:
+                raise ValueError("one frame per camera")
+            for k, f in enumerate(fr):
+                if (f.dtype != torch.uint8 or not f.is_cuda or not f.is_contiguous()
+                        or tuple(f.shape) != st.cam_shape[k] + (3,)):
+                    raise ValueError("frames: contiguous cuda uint8 (H, W, 3)")
+            H, W = st.canvas
+            if pano.dtype != torch.uint8 or tuple(pano.shape) != (H, W, 3) or not pano.is_contiguous():
+                raise ValueError("pano: contiguous uint8 (canvas_h, canvas_w, 3)")
+            rows.append((C.c_void_p * st.n_cams)(*[f.data_ptr() for f in fr]))
+        self._keep = rows
+        fr_arr = (C.c_void_p * n)(*[C.cast(r, C.c_void_p).value for r in rows])
+        pano_arr = (C.c_void_p * n)(*[p.data_ptr() for p in panos])
+        return fr_arr, pano_arr
+
+    def run(self, frames, panos, stream=None):
+        fr_arr, pano_arr = self._ptrs(frames, panos)
+        st = lib().vs_batch_run(self.h, fr_arr, pano_arr, _stream_handle(stream))
+        if st != 0:
+            raise VSError(st, lib().vs_batch_last_error(self.h).decode())
+        return panos
+
+    def autotune(self, frames, panos, reps=5):
+        fr_arr, pano_arr = self._ptrs(frames, panos)
+        ms = np.zeros((MAX_LEVELS, 3), np.float32)
+        choice = np.zeros(MAX_LEVELS, np.int32)
+        st = lib().vs_batch_autotune(self.h, fr_arr, pano_arr, reps, ms.ctypes.data_as(C.c_void_p),
+                                     choice.ctypes.data_as(C.c_void_p))
+        if st != 0:
+            raise VSError(st, lib().vs_batch_last_error(self.h).decode())
+        L = self.stitchers[0].info.lk_levels
+        return choice[:L].tolist(), ms[:L]
+
+
+def _p(t):
+    return C.c_void_p(t.data_ptr()) if t is not None else None
+
+
+def check(status, what):
+    if status != 0:
+        raise VSError(status, what)
+
+
+class PlainFlow:
+    """The plain pyramidal flow on caller luma pairs (device float32 [h][w])."""
+
+    def __init__(self, w: int, h: int, **params):
+        self.w, self.h = w, h
+        prm = default_params(**params)
+        hnd = C.c_void_p()
+        check(lib().vs_flow_create(w, h, C.byref(prm), C.byref(hnd)), "vs_flow_create")
+        self.hnd = hnd
+
+    def close(self):
+        if getattr(self, "hnd", None):
+            lib().vs_flow_destroy(self.hnd)
+            self.hnd = None
+
+    def __del__(self):
+        self.close()
+
+    def __call__(self, yt, ym, stream=None):
+        """(flow of template yt vs moving ym, the reverse flow), float32 [h][w][2]"""
+        for t in (yt, ym):
+            if t.dtype != torch.float32 or not t.is_cuda or tuple(t.shape) != (self.h, self.w) or not t.is_contiguous():
+                raise ValueError("luma: contiguous cuda float32 (h, w)")
+        ftm = torch.empty((self.h, self.w, 2), dtype=torch.float32, device=yt.device)
+        fmt = torch.empty_like(ftm)
+        check(lib().vs_flow_run(self.hnd, _p(yt), _p(ym), _p(ftm), _p(fmt), _stream_handle(stream)), "vs_flow_run")
+        return ftm, fmt
+
+    def level(self, level: int, stream=None):
+        """(template, moving) luma at a pyramid level of the last run"""
+        w, h = C.c_int32(), C.c_int32()
+        check(lib().vs_flow_level(self.hnd, level, None, None, C.byref(w), C.byref(h), None), "vs_flow_level")
+        yt = torch.empty((h.value, w.value), dtype=torch.float32, device="cuda")
+        ym = torch.empty_like(yt)
+        check(lib().vs_flow_level(self.hnd, level, _p(yt), _p(ym), None, None, _stream_handle(stream)),
+              "vs_flow_level")
+        return yt, ym
