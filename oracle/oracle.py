@@ -19,7 +19,10 @@ MAX_CAMS = 16
 MAX_PAIRS = 16
 
 TAP = dict(strip=1, mask=2, hist=3, lut=4, mom=5, mpair=6, mk=7, flags=8, pyr=9, flow=10,
-           pano_pre=11, pano_hist=12, bal_lut=13, quant=14, mbar=15, cover=16, need=17)
+           pano_pre=11, pano_hist=12, bal_lut=13, quant=14, mbar=15, cover=16, need=17,
+           surr_pred=18, fb=19, surr_ok=20)
+
+FLOW_PLAIN, FLOW_SURROGATE, FLOW_FALLBACK = 0, 1, 2
 
 
 def build(verbose: bool = False) -> str:
@@ -96,6 +99,10 @@ def lib():
         L.vso_conv3x3.argtypes = [vp, i, i, i, i, vp, vp, i, vp]
         L.vso_conv3x3_bwd_data.argtypes = [vp, i, i, i, i, vp, i, vp]
         L.vso_conv3x3_bwd_weight.argtypes = [vp, vp, i, i, i, i, i, vp, vp]
+        L.vso_set_surrogate.argtypes = [vp, vp, C.c_size_t, i, C.c_float]
+        L.vso_surrogate_net.argtypes = [vp, C.c_size_t, vp, vp, i, i, vp]
+        L.vso_surr_upsample.argtypes = [vp, i, i, vp, i, i, vp]
+        L.vso_fb_check.argtypes = [vp, vp, i, i, vp, i, i, C.POINTER(C.c_ulonglong), C.POINTER(C.c_ulonglong)]
         _lib = L
     return _lib
 
@@ -186,6 +193,17 @@ class Oracle:
             raise OracleError(f"vso_stitch failed: {st}")
         return pano
 
+    def set_surrogate(self, blob: bytes | None, mode: int, tau: float = 0.0):
+        """Load a surrogate weight file (None keeps the loaded one) and pick the
+        flow mode (FLOW_PLAIN / FLOW_SURROGATE / FLOW_FALLBACK, threshold tau px)."""
+        if blob is None:
+            st = lib().vso_set_surrogate(self.h, None, 0, mode, tau)
+        else:
+            buf = C.create_string_buffer(bytes(blob), len(blob))
+            st = lib().vso_set_surrogate(self.h, buf, len(blob), mode, tau)
+        if st != 0:
+            raise OracleError(f"vso_set_surrogate failed: {st}")
+
     def reset(self):
         lib().vso_reset(self.h)
 
@@ -220,6 +238,15 @@ class Oracle:
             out = np.zeros((h, w), np.float32 if name == "pyr" else np.uint8)
         elif name == "flow":
             out = np.zeros((sh, sw, 2), np.float32)
+        elif name == "surr_pred":
+            w, h = sw, sh
+            for _ in range(2):
+                w, h = (w + 1) // 2, (h + 1) // 2
+            out = np.zeros((h, w, 2), np.float32)
+        elif name == "fb":
+            out = np.zeros((P.n_pairs, 2), np.uint64)
+        elif name == "surr_ok":
+            out = np.zeros(P.n_pairs, np.int32)
         elif name == "pano_pre":
             out = np.zeros((H, W, 3), np.uint8)
         elif name == "pano_hist":
@@ -367,3 +394,37 @@ def conv3x3_bwd_weight(x, dy):
     db = np.zeros(cout, np.float64)
     lib().vso_conv3x3_bwd_weight(_ptr(x), _ptr(dy), n, h, w, cin, cout, _ptr(dw), _ptr(db))
     return dw, db
+
+
+# ---- learned surrogate inside the frame ------------------------------------
+
+def surrogate_net(blob: bytes, yt, ym) -> np.ndarray:
+    """the network on one luma pair (h, w) -> channels 0-1 of its output (h, w, 2)"""
+    yt = np.ascontiguousarray(yt, np.float32)
+    ym = np.ascontiguousarray(ym, np.float32)
+    h, w = yt.shape
+    out = np.zeros((h, w, 2), np.float32)
+    buf = C.create_string_buffer(bytes(blob), len(blob))
+    if lib().vso_surrogate_net(buf, len(blob), _ptr(yt), _ptr(ym), w, h, _ptr(out)) != 0:
+        raise OracleError("vso_surrogate_net: bad weight file")
+    return out
+
+
+def surr_upsample(pred, need0) -> np.ndarray:
+    pred = np.ascontiguousarray(pred, np.float32)
+    need0 = np.ascontiguousarray(need0, np.uint8)
+    h0, w0 = need0.shape
+    out = np.zeros((h0, w0, 2), np.float32)
+    lib().vso_surr_upsample(_ptr(pred), pred.shape[1], pred.shape[0], _ptr(need0), w0, h0, _ptr(out))
+    return out
+
+
+def fb_check(pred_ij, pred_ji, need0):
+    """(sum of the per-pixel forward-backward errors in 1/256 px, pixel count)"""
+    a = np.ascontiguousarray(pred_ij, np.float32)
+    b = np.ascontiguousarray(pred_ji, np.float32)
+    need0 = np.ascontiguousarray(need0, np.uint8)
+    s, n = C.c_ulonglong(), C.c_ulonglong()
+    lib().vso_fb_check(_ptr(a), _ptr(b), a.shape[1], a.shape[0], _ptr(need0), need0.shape[1], need0.shape[0],
+                       C.byref(s), C.byref(n))
+    return s.value, n.value

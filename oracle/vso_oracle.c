@@ -116,6 +116,14 @@ struct vso_ctx {
     uint8_t* need[VSO_MAX_PAIRS][VSO_MAX_LEVELS];
     int pw[VSO_MAX_PAIRS][VSO_MAX_LEVELS], ph[VSO_MAX_PAIRS][VSO_MAX_LEVELS];
     float* flow[VSO_MAX_PAIRS][2];
+    /* learned flow surrogate (mode 0: the plain estimator only) */
+    int surr_mode;
+    unsigned long long surr_tau_fix;          /* fallback threshold, 1/256 px */
+    void* surr_blob;
+    size_t surr_blob_n;
+    float* surr_pred[VSO_MAX_PAIRS][2];       /* level-2 prediction, 2 channels */
+    unsigned long long fb[VSO_MAX_PAIRS][2];  /* fixed-point error sum, pixel count */
+    int surr_ok[VSO_MAX_PAIRS];
     uint8_t* pano_pre;
     uint32_t pano_hist[3][256];
     uint8_t bal_lut[3][256];
@@ -320,7 +328,10 @@ static void free_ctx(vso_ctx* c)
         for (int k = 0; k < 2; ++k)
             for (int l = 0; l < VSO_MAX_LEVELS; ++l) free(c->pyr[p][k][l]);
         for (int l = 0; l < VSO_MAX_LEVELS; ++l) free(c->need[p][l]);
+        free(c->surr_pred[p][0]);
+        free(c->surr_pred[p][1]);
     }
+    free(c->surr_blob);
     free(c->pano_pre);
     free(c);
 }
@@ -847,6 +858,8 @@ static void build_need(vso_ctx* c, int p)
 
 /* flow_ij satisfies P_i(x + flow_ij(x)) ~ P_j(x): template j, moving i;
  * flow_ji the other way round.  Coarse to fine. */
+static int surrogate_pair(vso_ctx* c, int p);
+
 static void step_flow(vso_ctx* c)
 {
     const vso_plan_info* P = &c->plan;
@@ -854,6 +867,8 @@ static void step_flow(vso_ctx* c)
     for (int p = 0; p < P->n_pairs; ++p) {
         size_t n0 = (size_t)P->strip_w[p] * P->strip_h[p];
         build_need(c, p);
+        c->surr_ok[p] = 0;
+        if (c->prm.flow && c->surr_mode && surrogate_pair(c, p)) continue;
         for (int dir = 0; dir < 2; ++dir) {
             if (!c->prm.flow) {
                 memset(c->flow[p][dir], 0, n0 * 2 * sizeof(float));
@@ -875,6 +890,247 @@ static void step_flow(vso_ctx* c)
             }
         }
     }
+}
+
+/* ------------------------------------------------------------------------ */
+/* The learned flow surrogate inside the frame (not in the paper).            */
+/*                                                                            */
+/* A chain of 3x3 convolutions maps the level-2 luma pair of a field          */
+/* (template, moving) to the field's flow in level-2 pixels.  Network input:  */
+/* channel 0 = bf16((Y_t - 128) / 64), channel 1 = bf16((Y_m - 128) / 64),     */
+/* other channels 0.  Each layer: the exact sum of its BF16 products and the  */
+/* bias (FP64, rounded once to FP32); hidden layers apply a leaky ReLU in     */
+/* FP32 and store BF16 (round to nearest even); the last layer stays FP32 and */
+/* its channels 0-1 are the flow.  The level-0 flow is the bilinear          */
+/* upsampling x4 (level-0 x maps to level-2 x / 4 - 3 / 8).  A pair keeps     */
+/* the surrogate's flows when its forward-backward error                      */
+/*   e(x) = | U_ij(x) + U_ji(x + U_ij(x)) |  (U the upsampled fields)          */
+/* averaged over the overlap, in 1/256 px fixed point, is below the           */
+/* threshold; otherwise the plain estimator runs for that pair.               */
+/* ------------------------------------------------------------------------ */
+
+#define SURR_LEVEL 2
+#define SURR_MAX_LAYERS 8
+
+static float bf16_round(float v)
+{
+    uint32_t u;
+    memcpy(&u, &v, 4);
+    u += 0x7fffu + ((u >> 16) & 1u);
+    u &= 0xffff0000u;
+    float r;
+    memcpy(&r, &u, 4);
+    return r;
+}
+
+typedef struct {
+    int nl;
+    float alpha;
+    int ci[SURR_MAX_LAYERS], co[SURR_MAX_LAYERS];
+    const int16_t* w[SURR_MAX_LAYERS];   /* [co][9][ci] BF16 bits */
+    const float* b[SURR_MAX_LAYERS];
+} net_view;
+
+/* Weight file: "VSNN", u32 version (1), u32 layers, f32 leaky-ReLU slope,
+ * per layer u32 cin, u32 cout, then per layer int16 w[cout][9][cin] (BF16
+ * bits) and f32 bias[cout], little endian, packed. */
+static int parse_net(const void* blob, size_t n, net_view* v)
+{
+    const uint8_t* b = (const uint8_t*)blob;
+    if (!b || n < 16 || memcmp(b, "VSNN", 4) != 0) return VSO_E_INVAL;
+    uint32_t version, nl;
+    memcpy(&version, b + 4, 4);
+    memcpy(&nl, b + 8, 4);
+    memcpy(&v->alpha, b + 12, 4);
+    if (version != 1 || nl < 1 || nl > SURR_MAX_LAYERS || !isfinite(v->alpha)) return VSO_E_INVAL;
+    v->nl = (int)nl;
+    size_t off = 16;
+    if (n < off + 8 * (size_t)nl) return VSO_E_INVAL;
+    for (int l = 0; l < v->nl; ++l) {
+        uint32_t ci, co;
+        memcpy(&ci, b + off, 4);
+        memcpy(&co, b + off + 4, 4);
+        off += 8;
+        if (ci < 1 || co < 1 || ci > 256 || co > 256) return VSO_E_INVAL;
+        v->ci[l] = (int)ci;
+        v->co[l] = (int)co;
+    }
+    if (v->ci[0] < 2 || v->co[v->nl - 1] < 2) return VSO_E_INVAL;
+    for (int l = 1; l < v->nl; ++l)
+        if (v->ci[l] != v->co[l - 1]) return VSO_E_INVAL;
+    for (int l = 0; l < v->nl; ++l) {
+        size_t nw = (size_t)v->co[l] * 9 * v->ci[l];
+        if (n < off + 2 * nw + 4 * (size_t)v->co[l]) return VSO_E_INVAL;
+        v->w[l] = (const int16_t*)(b + off);
+        off += 2 * nw;
+        v->b[l] = (const float*)(b + off);
+        off += 4 * (size_t)v->co[l];
+    }
+    return off == n ? VSO_OK : VSO_E_INVAL;
+}
+
+static double bf16_bits_to_double(int16_t h)
+{
+    uint32_t u = (uint32_t)(uint16_t)h << 16;
+    float f;
+    memcpy(&f, &u, 4);
+    return (double)f;
+}
+
+/* The network on one luma pair (w x h, FP32); pred receives channels 0-1 of
+ * the last layer, [h][w][2]. */
+static void net_forward(const net_view* v, const float* Yt, const float* Ym, int w, int h, float* pred)
+{
+    size_t npx = (size_t)w * h;
+    int cmax = v->ci[0];
+    for (int l = 0; l < v->nl; ++l) cmax = v->co[l] > cmax ? v->co[l] : cmax;
+    double* x = (double*)calloc(npx * cmax, sizeof(double));
+    double* y = (double*)calloc(npx * cmax, sizeof(double));
+    double* wt = (double*)malloc((size_t)256 * 9 * 256 * sizeof(double));
+    int cin = v->ci[0];
+    for (size_t q = 0; q < npx; ++q) {
+        x[q * cin + 0] = (double)bf16_round((Yt[q] - 128.0f) * (1.0f / 64.0f));
+        x[q * cin + 1] = (double)bf16_round((Ym[q] - 128.0f) * (1.0f / 64.0f));
+    }
+    for (int l = 0; l < v->nl; ++l) {
+        int ci = v->ci[l], co = v->co[l];
+        for (size_t i = 0; i < (size_t)co * 9 * ci; ++i) wt[i] = bf16_bits_to_double(v->w[l][i]);
+        /* the exact sums of products (each product of two BF16 values is exact
+         * in FP64), plus the bias */
+        double bias[256];
+        for (int o = 0; o < co; ++o) bias[o] = (double)v->b[l][o];
+        vso_conv3x3(x, 1, h, w, ci, wt, bias, co, y);
+        const int last = l == v->nl - 1;
+#pragma omp parallel for schedule(static)
+        for (long long q = 0; q < (long long)npx; ++q)
+            for (int o = 0; o < co; ++o) {
+                float t = (float)y[(size_t)q * co + o];
+                if (last) {
+                    if (o < 2) pred[(size_t)q * 2 + o] = t;
+                } else {
+                    t = t > 0.0f ? t : v->alpha * t;
+                    y[(size_t)q * co + o] = (double)bf16_round(t);
+                }
+            }
+        double* tmp = x;
+        x = y;
+        y = tmp;
+    }
+    free(x);
+    free(y);
+    free(wt);
+}
+
+int vso_surrogate_net(const void* blob, size_t n, const float* yt, const float* ym, int w, int h, float* pred)
+{
+    net_view v;
+    if (parse_net(blob, n, &v) != VSO_OK || w < 1 || h < 1) return VSO_E_INVAL;
+    net_forward(&v, yt, ym, w, h, pred);
+    return VSO_OK;
+}
+
+/* the x4 upsampled level-2 field at level-0 position (X, Y); the clamp
+ * takes a non-finite position (a non-finite displacement) to the border */
+static void up_sample(const float* pred, int w2, int h2, float X, float Y, float* fx_out, float* fy_out)
+{
+    float cx = fminf(fmaxf(fmaf(X, 0.25f, -0.375f), 0.0f), (float)(w2 - 1));
+    float cy = fminf(fmaxf(fmaf(Y, 0.25f, -0.375f), 0.0f), (float)(h2 - 1));
+    float flx = floorf(cx), fly = floorf(cy);
+    int xa = (int)flx, ya = (int)fly;
+    float fx = cx - flx, fy = cy - fly;
+    int xb = xa + 1 < w2 ? xa + 1 : w2 - 1;
+    int yb = ya + 1 < h2 ? ya + 1 : h2 - 1;
+    const float* p00 = pred + ((size_t)ya * w2 + xa) * 2;
+    const float* p10 = pred + ((size_t)ya * w2 + xb) * 2;
+    const float* p01 = pred + ((size_t)yb * w2 + xa) * 2;
+    const float* p11 = pred + ((size_t)yb * w2 + xb) * 2;
+    float r[2];
+    for (int k = 0; k < 2; ++k) {
+        float a = fmaf(fx, p10[k] - p00[k], p00[k]);
+        float b = fmaf(fx, p11[k] - p01[k], p01[k]);
+        r[k] = 4.0f * fmaf(fy, b - a, a);
+    }
+    *fx_out = r[0];
+    *fy_out = r[1];
+}
+
+void vso_surr_upsample(const float* pred, int w2, int h2, const uint8_t* need0, int w0, int h0, float* flow0)
+{
+    for (int y = 0; y < h0; ++y)
+        for (int x = 0; x < w0; ++x) {
+            size_t q = (size_t)y * w0 + x;
+            float fx = 0.0f, fy = 0.0f;
+            if (!need0 || need0[q]) up_sample(pred, w2, h2, (float)x, (float)y, &fx, &fy);
+            flow0[q * 2] = fx;
+            flow0[q * 2 + 1] = fy;
+        }
+}
+
+/* per-pixel error in 1/256 px, saturated at 2^20 (a non-finite error too) */
+static unsigned fb_fixed(float ex, float ey)
+{
+    float e = sqrtf(ex * ex + ey * ey);
+    return (unsigned)floorf(fminf(e * 256.0f, 1048576.0f) + 0.5f);
+}
+
+void vso_fb_check(const float* pred_ij, const float* pred_ji, int w2, int h2, const uint8_t* need0, int w0, int h0,
+                  unsigned long long* sum, unsigned long long* count)
+{
+    unsigned long long s = 0, n = 0;
+    for (int y = 0; y < h0; ++y)
+        for (int x = 0; x < w0; ++x) {
+            if (need0 && !need0[(size_t)y * w0 + x]) continue;
+            float ux, uy, vx, vy;
+            up_sample(pred_ij, w2, h2, (float)x, (float)y, &ux, &uy);
+            up_sample(pred_ji, w2, h2, (float)x + ux, (float)y + uy, &vx, &vy);
+            s += fb_fixed(ux + vx, uy + vy);
+            n += 1;
+        }
+    *sum = s;
+    *count = n;
+}
+
+int vso_set_surrogate(vso_ctx* c, const void* blob, size_t n, int mode, float tau)
+{
+    if (!c || mode < 0 || mode > 2 || !(tau >= 0.0f) || tau > 1e6f) return VSO_E_INVAL;
+    if (blob) {
+        net_view v;
+        if (parse_net(blob, n, &v) != VSO_OK) return VSO_E_INVAL;
+        void* cp = malloc(n);
+        if (!cp) return VSO_E_NOMEM;
+        memcpy(cp, blob, n);
+        free(c->surr_blob);
+        c->surr_blob = cp;
+        c->surr_blob_n = n;
+    }
+    if (mode != 0 && (!c->surr_blob || c->prm.lk_levels <= SURR_LEVEL)) return VSO_E_INVAL;
+    c->surr_mode = mode;
+    c->surr_tau_fix = (unsigned long long)llround((double)tau * 256.0);
+    return VSO_OK;
+}
+
+/* Surrogate flows of pair p in both directions (template j / moving i and the
+ * reverse, as in step_flow); returns 1 when the pair keeps them. */
+static int surrogate_pair(vso_ctx* c, int p)
+{
+    net_view v;
+    parse_net(c->surr_blob, c->surr_blob_n, &v);
+    const int w2 = c->pw[p][SURR_LEVEL], h2 = c->ph[p][SURR_LEVEL];
+    const int w0 = c->pw[p][0], h0 = c->ph[p][0];
+    for (int dir = 0; dir < 2; ++dir) {
+        free(c->surr_pred[p][dir]);
+        c->surr_pred[p][dir] = (float*)malloc((size_t)w2 * h2 * 2 * sizeof(float));
+        int tmpl = dir == 0 ? 0 : 1, mov = 1 - tmpl;
+        net_forward(&v, c->pyr[p][tmpl][SURR_LEVEL], c->pyr[p][mov][SURR_LEVEL], w2, h2, c->surr_pred[p][dir]);
+    }
+    vso_fb_check(c->surr_pred[p][0], c->surr_pred[p][1], w2, h2, c->need[p][0], w0, h0, &c->fb[p][0], &c->fb[p][1]);
+    int ok = c->surr_mode == 1 || (c->fb[p][1] > 0 && c->fb[p][0] < c->surr_tau_fix * c->fb[p][1]);
+    c->surr_ok[p] = ok;
+    if (ok) {
+        vso_surr_upsample(c->surr_pred[p][0], w2, h2, c->need[p][0], w0, h0, c->flow[p][0]);
+        vso_surr_upsample(c->surr_pred[p][1], w2, h2, c->need[p][0], w0, h0, c->flow[p][1]);
+    }
+    return ok;
 }
 
 /* ------------------------------------------------------------------------ */
@@ -1127,6 +1383,14 @@ int vso_get(const vso_ctx* c, int tap, int p, int sub, void* dst, size_t nbytes)
     case VSO_TAP_NEED:
         if (!pair_ok || sub < 0 || sub >= c->prm.lk_levels) return VSO_E_INVAL;
         return copy_out(dst, nbytes, c->need[p][sub], (size_t)c->pw[p][sub] * c->ph[p][sub]);
+    case VSO_TAP_SURR_PRED:
+        if (!pair_ok || sub < 0 || sub > 1 || !c->surr_pred[p][sub]) return VSO_E_INVAL;
+        return copy_out(dst, nbytes, c->surr_pred[p][sub],
+                        (size_t)c->pw[p][SURR_LEVEL] * c->ph[p][SURR_LEVEL] * 2 * sizeof(float));
+    case VSO_TAP_FB:
+        return copy_out(dst, nbytes, c->fb, (size_t)P->n_pairs * 2 * sizeof(unsigned long long));
+    case VSO_TAP_SURR_OK:
+        return copy_out(dst, nbytes, c->surr_ok, (size_t)P->n_pairs * sizeof(int));
     default:
         return VSO_E_INVAL;
     }
@@ -1142,7 +1406,7 @@ int vso_get(const vso_ctx* c, int tap, int p, int sub, void* dst, size_t nbytes)
 void vso_conv3x3(const double* x, int n, int h, int w, int cin, const double* wt, const double* b, int cout,
                  double* y)
 {
-#pragma omp parallel for schedule(static)
+#pragma omp parallel for collapse(2) schedule(static)
     for (int img = 0; img < n; ++img)
         for (int yy = 0; yy < h; ++yy)
             for (int xx = 0; xx < w; ++xx)

@@ -104,6 +104,9 @@ enum {
     VSO_TAP_MBAR = 15,     /* [3][2] f64 */
     VSO_TAP_COVER = 16,    /* canvas_h*canvas_w u8 : number of covering cameras */
     VSO_TAP_NEED = 17,     /* pair, sub = level : w_l*h_l u8, 1 where the flow is estimated */
+    VSO_TAP_SURR_PRED = 18,/* pair, sub 0=ij 1=ji : level-2 surrogate prediction w_2*h_2*2 f32 */
+    VSO_TAP_FB = 19,       /* [n_pairs][2] u64 : forward-backward error sum (1/256 px), pixel count */
+    VSO_TAP_SURR_OK = 20,  /* [n_pairs] i32 : 1 where the pair kept the surrogate's flows */
 };
 int vso_get(const vso_ctx* c, int tap, int pair, int sub, void* dst, size_t nbytes);
 
@@ -132,4 +135,16 @@ void vso_conv3x3_bwd_data(const double* dy, int n, int h, int w, int cout, const
 void vso_conv3x3_bwd_weight(const double* x, const double* dy, int n, int h, int w, int cin, int cout, double* dw,
                             double* db);
 
+/* The learned flow surrogate inside the frame (an addition to the paper's
+ * method).  blob: weight file ("VSNN" v1, see vso_oracle.c), copied; may be
+ * NULL to keep the loaded one.  mode 0: plain flow; 1: the surrogate's flows
+ * for every pair; 2: the surrogate's flows where the pair's mean
+ * forward-backward error is below tau px (fixed point 1/256 px), the plain
+ * estimator elsewhere.  Needs lk_levels >= 3. */
+int vso_set_surrogate(vso_ctx* c, const void* blob, size_t n, int mode, float tau);
+/* its steps, exposed for the pins */
+int vso_surrogate_net(const void* blob, size_t n, const float* yt, const float* ym, int w, int h, float* pred);
+void vso_surr_upsample(const float* pred, int w2, int h2, const uint8_t* need0, int w0, int h0, float* flow0);
+void vso_fb_check(const float* pred_ij, const float* pred_ji, int w2, int h2, const uint8_t* need0, int w0, int h0,
+                  unsigned long long* sum, unsigned long long* count);
 #endif

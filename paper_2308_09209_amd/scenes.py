@@ -266,3 +266,42 @@ def small_scene(n_cams=2, W=96, H=64, overlap=0.35, ring=False, seed_config=90, 
     """A tiny scene with the same recipe, for parity tests that span a few tiles."""
     return Scene(n_cams=n_cams, W=W, H=H, overlap=overlap, ring=ring,
                  tex_h=int(H * 1.2), tex_w=None, config=seed_config, **kw)
+
+
+# ---- synthetic weights of the learned flow surrogate ------------------------
+# Weight file ("VSNN" v1): magic, u32 version, u32 layers, f32 leaky-ReLU
+# slope, per layer u32 cin / u32 cout, then per layer int16 w[cout][9][cin]
+# (BF16 bit patterns) and f32 bias[cout]; little endian, packed.
+
+SURROGATE_LAYERS = ((16, 32), (32, 32), (32, 32), (32, 32), (32, 16))
+
+
+def bf16_bits(x) -> np.ndarray:
+    """float values -> BF16 bit patterns (round to nearest even), int16"""
+    u = np.ascontiguousarray(x, np.float32).view(np.uint32).astype(np.uint64)
+    u = (u + 0x7FFF + ((u >> 16) & 1)) >> 16
+    return u.astype(np.uint16).view(np.int16)
+
+
+def nn_blob(weights, biases, alpha: float = 0.1) -> bytes:
+    """weights[l]: float [cout][9][cin] (rounded to BF16 here), biases[l]: [cout]"""
+    import struct
+    out = [b"VSNN", struct.pack("<IIf", 1, len(weights), alpha)]
+    for w in weights:
+        out.append(struct.pack("<II", w.shape[2], w.shape[0]))
+    for w, b in zip(weights, biases):
+        out.append(bf16_bits(w).tobytes())
+        out.append(np.ascontiguousarray(b, np.float32).tobytes())
+    return b"".join(out)
+
+
+def random_net(seed: int, layers=SURROGATE_LAYERS, out_scale: float = 0.5, alpha: float = 0.1):
+    """Seeded random weights (He-scaled normal, the last layer scaled by
+    out_scale, small random biases): (weights, biases) lists."""
+    rng = np.random.default_rng(seed)
+    ws, bs = [], []
+    for li, (ci, co) in enumerate(layers):
+        std = math.sqrt(2.0 / (9 * ci)) * (out_scale if li == len(layers) - 1 else 1.0)
+        ws.append(rng.normal(size=(co, 9, ci)) * std)
+        bs.append(rng.normal(size=co) * 0.05)
+    return ws, bs
