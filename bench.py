@@ -25,7 +25,10 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 FP32_VECTOR_PEAK_TFLOPS = 157.3   # MI355X published FP32 vector peak
+BF16_MFMA_PEAK_TFLOPS = 2500.0    # MI355X published dense BF16 matrix peak
 HBM_PEAK_GBS = 8000.0
+DEFAULT_WEIGHTS = os.path.join(ROOT, "paper_2308_09209_amd", "weights", "flow_surrogate.vsnn")
+FLOW_MODES = {"plain": 0, "surrogate": 1, "fallback": 2}
 
 
 def window_sum(n, r):
@@ -62,6 +65,57 @@ def load_pmc(kernel, workload):
     return rec.get("bytes_per_launch")
 
 
+def surrogate_flops_per_frame(info, layers):
+    """matrix-core flops of the surrogate network per frame: 2 * 9 * cin * cout
+    per level-2 pixel and layer, both directions of every pair"""
+    per_px = sum(2 * 9 * ci * co for ci, co in layers)
+    total = 0
+    for p in range(info.n_pairs):
+        w, h = info.strip_w[p], info.strip_h[p]
+        for _ in range(2):
+            w, h = (w + 1) // 2, (h + 1) // 2
+        total += 2 * w * h * per_px
+    return total
+
+
+def blob_layers(blob):
+    import struct
+    nl = struct.unpack_from("<I", blob, 8)[0]
+    return [struct.unpack_from("<II", blob, 16 + 8 * i) for i in range(nl)]
+
+
+def time_frames(st, frames, pano, start, K):
+    import torch
+    starts = [torch.cuda.Event(enable_timing=True) for _ in range(K)]
+    ends = [torch.cuda.Event(enable_timing=True) for _ in range(K)]
+    st.set_timing(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(K):
+        starts[i].record()
+        st.stitch(frames[(start + i) % len(frames)], pano=pano)
+        ends[i].record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    lat = np.array([starts[i].elapsed_time(ends[i]) for i in range(K)])
+    step_ms, nfr = st.timing()
+    st.set_timing(False)
+    return wall, lat, step_ms, nfr
+
+
+def flow_epe(st_a, st_b):
+    """mean end-point error between two contexts' level-0 flows over the
+    overlap pixels, both directions of every pair (px), and its 99th percentile"""
+    errs = []
+    for p in range(st_a.n_pairs):
+        need = st_a.tap("need", p, 0).astype(bool)
+        for d in (0, 1):
+            a, b = st_a.tap("flow", p, d), st_b.tap("flow", p, d)
+            errs.append(np.sqrt(((a.astype(np.float64) - b) ** 2).sum(-1))[need])
+    e = np.concatenate(errs)
+    return float(e.mean()), float(np.percentile(e, 99))
+
+
 def cpu_baseline(scene, frames_list, n_frames):
     from oracle import oracle as O
     rig = scene.rig()
@@ -91,6 +145,13 @@ def main():
                     help="the 6-stream batched workload (2x1280x720, 2x1920x1080, 2x2560x1440, "
                          "3-4 cameras each) through one captured graph, instead of the ring")
     ap.add_argument("--autotune", action="store_true", help="autotune the flow kernel first (batch)")
+    ap.add_argument("--flow", choices=sorted(FLOW_MODES), default=None,
+                    help="flow mode of the surrogate leg (default fallback; plain: no surrogate leg); "
+                         "with --batch the flow mode of every stream (default plain)")
+    ap.add_argument("--fb-tau", type=float, default=0.5,
+                    help="forward-backward threshold (px) of the fallback mode")
+    ap.add_argument("--weights", default=DEFAULT_WEIGHTS, help="surrogate weight file")
+    ap.add_argument("--epe-frames", type=int, default=3, help="frames compared for the surrogate's EPE")
     ap.add_argument("--copy-calibration-mb", type=int, default=0,
                     help="also run one plain device-to-device copy of this many MiB (a "
                          "counter reference for rocprofv3 byte counters)")
@@ -106,7 +167,9 @@ def main():
     from paper_2308_09209_amd.scenes import WORKLOADS, scene_for
 
     if args.batch:
+        args.flow = args.flow or "plain"
         return bench_batch(args)
+    args.flow = args.flow or "fallback"
 
     wl = WORKLOADS[args.workload]
     t_gen = time.perf_counter()
@@ -142,21 +205,7 @@ def main():
     print(f"# warmup done ({args.warmup} frames)", file=sys.stderr, flush=True)
 
     K = args.steps
-    st.set_timing(True)
-    starts = [torch.cuda.Event(enable_timing=True) for _ in range(K)]
-    ends = [torch.cuda.Event(enable_timing=True) for _ in range(K)]
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for i in range(K):
-        starts[i].record()
-        st.stitch(frames[(args.warmup + i) % seq], pano=pano)
-        ends[i].record()
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    wall = t1 - t0
-    lat = np.array([starts[i].elapsed_time(ends[i]) for i in range(K)])
-    step_ms, nfr = st.timing()
-    st.set_timing(False)
+    wall, lat, step_ms, nfr = time_frames(st, frames, pano, args.warmup, K)
     print(f"# timed {K} frames in {wall:.3f} s", file=sys.stderr, flush=True)
 
     mpix = K * H * W / wall / 1e6
@@ -185,12 +234,59 @@ def main():
                p99_ms=round(float(np.percentile(lat, 99)), 4),
                step_ms={n: round(v / nfr, 5) for n, v in zip(names, step_ms)},
                roofline=roofline)
+    if args.flow != "plain" and os.path.exists(args.weights):
+        out["surrogate"] = surrogate_leg(args, V, rig, frames, st, K, H, W, mpix, float(np.percentile(lat, 99)))
     if not args.no_cpu_baseline:
         print(f"# timing the CPU oracle on {args.cpu_frames} frames", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(scene, host_frames, min(args.cpu_frames, seq))
     else:
         out["cpu_baseline"] = None
     print(json.dumps(out), flush=True)
+
+
+def surrogate_leg(args, V, rig, frames, st_plain, K, H, W, mpix_plain, p99_plain):
+    """The same frames with the learned flow surrogate: throughput, latency, its
+    flows' end-point error against the plain path's, and the matrix-core rate."""
+    import torch
+    blob = open(args.weights, "rb").read()
+    mode, tau = FLOW_MODES[args.flow], args.fb_tau
+    ss = V.Stitcher(rig)
+    ss.load_weights(blob)
+    ss.set_flow_mode(mode, tau)
+    pano = ss.new_pano()
+    # EPE against the plain path: both contexts fed the same frames from T = 0
+    ref = V.Stitcher(rig)
+    epes, p99s, kept, pairs = [], [], 0, 0
+    for t in range(args.epe_frames):
+        ref.stitch(frames[t], pano=pano)
+        _, _, info = ss.stitch(frames[t], pano=pano, want_info=True)
+        e, e99 = flow_epe(ss, ref)
+        epes.append(e)
+        p99s.append(e99)
+        kept += sum(info.surr_ok[p] for p in range(ss.n_pairs))
+        pairs += ss.n_pairs
+    del ref
+    for i in range(args.warmup):
+        ss.stitch(frames[i % len(frames)], pano=pano)
+    torch.cuda.synchronize()
+    wall, lat, step_ms, nfr = time_frames(ss, frames, pano, args.warmup, K)
+    print(f"# surrogate ({args.flow}): timed {K} frames in {wall:.3f} s", file=sys.stderr, flush=True)
+    mpix = K * H * W / wall / 1e6
+    fl = surrogate_flops_per_frame(ss.info, blob_layers(blob))
+    flow_ms = step_ms[2] / nfr
+    names = V.Stitcher.TIMING_STEPS
+    return dict(mode=args.flow, fb_tau_px=tau if mode == 2 else None, weights=os.path.basename(args.weights),
+                value=round(mpix, 2), unit="Mpix/s", ms_per_step=round(wall / K * 1e3, 4),
+                p50_ms=round(float(np.percentile(lat, 50)), 4), p99_ms=round(float(np.percentile(lat, 99)), 4),
+                speedup_vs_plain=round(mpix / mpix_plain, 3),
+                p99_vs_plain=round(float(np.percentile(lat, 99)) / p99_plain, 3),
+                epe_vs_plain_px=round(float(np.mean(epes)), 4), epe_p99_px=round(float(np.mean(p99s)), 4),
+                epe_frames=args.epe_frames, pairs_kept=f"{kept}/{pairs}",
+                step_ms={n: round(v / nfr, 5) for n, v in zip(names, step_ms)},
+                mfma=dict(flops_per_frame=fl, flow_step_ms=round(flow_ms, 5),
+                          achieved=round(fl / (flow_ms * 1e-3) / 1e12, 3), peak=BF16_MFMA_PEAK_TFLOPS,
+                          unit="TFLOP/s", note="network flops over the whole flow step (pack, 5 "
+                          "convolutions, upsampling, forward-backward check, fallback)"))
 
 
 def bench_batch(args):
@@ -207,6 +303,12 @@ def bench_batch(args):
     print(f"# generated {seq} frames of {len(scenes)} streams in {time.perf_counter() - t_gen:.1f} s",
           file=sys.stderr, flush=True)
     sts = [V.Stitcher(sc.rig()) for sc in scenes]
+    use_surr = args.flow != "plain" and os.path.exists(args.weights)
+    if use_surr:
+        blob = open(args.weights, "rb").read()
+        for st in sts:
+            st.load_weights(blob)
+            st.set_flow_mode(FLOW_MODES[args.flow], args.fb_tau)
     batch = V.Batch(sts)
     panos = [st.new_pano(dev) for st in sts]
     px = sum(st.canvas[0] * st.canvas[1] for st in sts)
@@ -235,6 +337,8 @@ def bench_batch(args):
                            streams=[f"{s['n_cams']}x{s['W']}x{s['H']}" for s in BATCH_STREAMS],
                            panorama_mpix_per_step=round(px / 1e6, 3), seq_frames=seq,
                            flow_variant_per_level=choice, autotuned=bool(args.autotune),
+                           flow=args.flow if use_surr else "plain",
+                           fb_tau_px=args.fb_tau if use_surr and args.flow == "fallback" else None,
                            parallelism="single GPU"),
                p50_ms=round(float(np.percentile(lat, 50)), 4),
                p99_ms=round(float(np.percentile(lat, 99)), 4))

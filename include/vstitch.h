@@ -133,6 +133,8 @@ typedef struct {
     int32_t quant[3][2];                /* m1, m2 per channel of this frame */
     double mbar[3][2];                  /* their 3-frame means (eqs. (6)-(7)) */
     uint32_t frames_seen;               /* T after this frame */
+    int32_t surr_ok[VS_MAX_PAIRS];      /* learned surrogate: 1 = the pair kept its flows, 0 = plain flow */
+    float fb_err[VS_MAX_PAIRS];         /* its mean forward-backward error in px (-1: surrogate off) */
 } vs_frame_info;
 
 typedef struct vs_ctx vs_ctx;
@@ -194,12 +196,17 @@ vs_status vs_state_set(vs_ctx* c, const vs_color_state* in);
  *                   pixels the finer level's initialisation samples); 0 elsewhere
  *                   and the flow there is 0
  *  VS_TAP_DEFERRED  sub = level: u32, flow pixels of that level finished by the
- *                   global-memory tail kernel (displacement beyond the staged tile) */
+ *                   global-memory tail kernel (displacement beyond the staged tile)
+ *  VS_TAP_SURR_PRED pair, sub 0 = ij, 1 = ji: the surrogate's level-2 flow,
+ *                   h_2 x w_2 x 2 f32 (needs loaded weights)
+ *  VS_TAP_FB        [n_pairs][2] u64: forward-backward error sum (1/256 px), pixels
+ *  VS_TAP_SURR_OK   [n_pairs] i32: 1 where the pair kept the surrogate's flows */
 enum {
     VS_TAP_STRIP = 1, VS_TAP_MASK = 2, VS_TAP_HIST = 3, VS_TAP_LUT = 4, VS_TAP_MOM = 5,
     VS_TAP_MPAIR = 6, VS_TAP_MK = 7, VS_TAP_FLAGS = 8, VS_TAP_PYR = 9, VS_TAP_FLOW = 10,
     VS_TAP_PANO_PRE = 11, VS_TAP_PANO_HIST = 12, VS_TAP_BAL_LUT = 13, VS_TAP_QUANT = 14,
-    VS_TAP_MBAR = 15, VS_TAP_COVER = 16, VS_TAP_NEED = 17, VS_TAP_DEFERRED = 18
+    VS_TAP_MBAR = 15, VS_TAP_COVER = 16, VS_TAP_NEED = 17, VS_TAP_DEFERRED = 18,
+    VS_TAP_SURR_PRED = 19, VS_TAP_FB = 20, VS_TAP_SURR_OK = 21
 };
 vs_status vs_debug_tap(vs_ctx* c, int tap, int pair, int sub, void* dst, size_t nbytes);
 
@@ -296,6 +303,29 @@ vs_status vs_nn_to_bf16(const float* a, uint16_t* b, int64_t n, void* stream);
 /* One 16x16x16 BF16 matrix-core product of a[16][16] and b[16][16]; out[64][4]
  * receives each lane's accumulator fragment (a layout check). */
 vs_status vs_nn_mfma_probe(const uint16_t* a, const uint16_t* b, float* out, void* stream);
+
+/* The learned surrogate inside the frame.  vs_load_weights copies a weight
+ * file into the context: "VSNN", u32 version 1, u32 layers (1..8), f32
+ * leaky-ReLU slope, per layer u32 cin and u32 cout, then per layer int16
+ * w[cout][9][cin] (BF16 bits) and f32 bias[cout], little endian, packed.  The
+ * first layer takes 16 channels, the last gives 16 (channels 0-1: flow),
+ * every (cin, cout) is one of vs_nn_conv3x3's.  The network runs on pyramid
+ * level 2 of each overlap field (needs flow = 1 and lk_levels >= 3); the
+ * input is (Y - 128) / 64 of the template and moving luma in channels 0-1,
+ * the output channels 0-1 the flow in level-2 pixels, upsampled x4 to the
+ * strip (level-0 x reads level-2 x / 4 - 3 / 8).  Synchronous.
+ * vs_set_flow_mode: VS_FLOW_PLAIN (the paper's path), VS_FLOW_SURROGATE (the
+ * network's flows for every pair; the plain estimator is not run) or
+ * VS_FLOW_SURROGATE_FALLBACK (a pair keeps the network's flows when its mean
+ * forward-backward error |U_ij(x) + U_ji(x + U_ij(x))| over the overlap,
+ * in 1/256 px fixed point, is below fb_tau_px, 0 <= fb_tau_px <= 1e6; the
+ * plain estimator recomputes the other pairs: fb_tau_px = 0 gives the plain
+ * path's output bit for bit).  VS_E_UNSUPPORTED without loaded weights.
+ * Both calls wait for the device; a batch holding the context recaptures its
+ * graph at its next run. */
+enum { VS_FLOW_PLAIN = 0, VS_FLOW_SURROGATE = 1, VS_FLOW_SURROGATE_FALLBACK = 2 };
+vs_status vs_load_weights(vs_ctx* c, const void* blob, size_t nbytes);
+vs_status vs_set_flow_mode(vs_ctx* c, int mode, float fb_tau_px);
 
 /* Plain estimator on caller image pairs (training labels, tests): a context
  * for w x h luma images; vs_flow_run computes, on the whole image, the

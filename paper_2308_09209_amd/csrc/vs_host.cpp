@@ -33,6 +33,13 @@ struct vs_ctx {
     int next_slot = 0;
     double ms_sum[6] = {};
     uint32_t timed_frames = 0;
+    // learned surrogate
+    void* surr_mem = nullptr;
+    SurrNet net;
+    int surr_loaded = 0;
+    // bumped whenever the launch sequence changes (flow variant, surrogate):
+    // a batch holding this context recaptures its graph
+    uint32_t gen = 0;
 };
 
 namespace {
@@ -110,6 +117,7 @@ void free_ctx(vs_ctx* c)
     if (c->plan_mem) (void)hipFree(c->plan_mem);
     if (c->dp) (void)hipFree(c->dp);
     if (c->pano_pre) (void)hipFree(c->pano_pre);
+    if (c->surr_mem) (void)hipFree(c->surr_mem);
     delete c;
 }
 
@@ -534,6 +542,7 @@ hipError_t enqueue_frame(const Group& g, hipStream_t s, hipEvent_t* ev, uint8_t*
     VS_STEP(launch_pyr0(g, s), "pyr0");
     for (int l = 0; l + 1 < levels; ++l) VS_STEP(launch_pyr_down(g, l, s), "pyr_down");
     if (ev) VS_STEP(hipEventRecord(ev[2], s), "hipEventRecord");
+    VS_STEP(launch_surrogate(g, s), "surrogate");
     for (int l = levels - 1; l >= 0; --l) VS_STEP(launch_lk(g, l, s), "flow");
     if (ev) VS_STEP(hipEventRecord(ev[3], s), "hipEventRecord");
     VS_STEP(launch_blend(g, s), "blend");
@@ -556,6 +565,7 @@ Group single(vs_ctx* c)
     g.n = 1;
     g.dp[0] = c->dp;
     g.hp[0] = &c->hp;
+    g.net[0] = c->surr_loaded ? &c->net : nullptr;
     return g;
 }
 
@@ -611,6 +621,13 @@ vs_status vs_stitch(vs_ctx* c, const uint8_t* const frames[], const vs_color_sta
             std::memcpy(info->quant, r.quant, sizeof info->quant);
             std::memcpy(info->mbar, r.mbar, sizeof info->mbar);
             info->frames_seen = st.frames_seen;
+            const bool surr = h.use_flow && h.flow_mode != VS_FLOW_PLAIN;
+            for (int p = 0; p < VS_MAX_PAIRS; ++p) {
+                info->surr_ok[p] = surr && p < h.n_pairs ? r.surr_ok[p] : 0;
+                info->fb_err[p] = surr && p < h.n_pairs && r.fb[p][1] > 0
+                                      ? (float)((double)r.fb[p][0] / 256.0 / (double)r.fb[p][1])
+                                      : -1.0f;
+            }
         }
     }
     return VS_OK;
@@ -629,6 +646,122 @@ vs_status vs_set_flow_variant(vs_ctx* c, int level, int variant)
     VS_CHECK(hipDeviceSynchronize(), "hipDeviceSynchronize");
     set_lk_tiles(c->hp, level, variant);
     VS_CHECK(hipMemcpy(c->dp, &c->hp, sizeof(DevPlan), hipMemcpyHostToDevice), "hipMemcpy plan");
+    c->gen += 1;
+    return VS_OK;
+}
+
+// ---------------------------------------------------------------------------
+// The learned surrogate: weights and flow mode
+// ---------------------------------------------------------------------------
+
+vs_status vs_load_weights(vs_ctx* c, const void* blob, size_t nbytes)
+{
+    if (!c || !blob) return VS_E_INVAL;
+    if (c->sticky) return VS_E_DEVICE;
+    DevPlan& h = c->hp;
+    if (!h.use_flow || h.levels <= SURR_LEVEL)
+        return fail(c, VS_E_UNSUPPORTED, "the surrogate needs flow = 1 and lk_levels >= 3");
+    // header
+    const uint8_t* b = (const uint8_t*)blob;
+    uint32_t version = 0, nl = 0;
+    float alpha = 0.0f;
+    if (nbytes < 16 || std::memcmp(b, "VSNN", 4) != 0) return fail(c, VS_E_INVAL, "not a surrogate weight file");
+    std::memcpy(&version, b + 4, 4);
+    std::memcpy(&nl, b + 8, 4);
+    std::memcpy(&alpha, b + 12, 4);
+    if (version != 1 || nl < 1 || nl > SURR_MAX_LAYERS || !std::isfinite(alpha))
+        return fail(c, VS_E_INVAL, "weight file: version / layer count / slope");
+    SurrNet net;
+    std::memset(&net, 0, sizeof net);
+    net.nl = (int)nl;
+    net.alpha = alpha;
+    size_t off = 16;
+    if (nbytes < off + 8 * (size_t)nl) return fail(c, VS_E_INVAL, "weight file truncated");
+    for (int l = 0; l < net.nl; ++l) {
+        uint32_t ci, co;
+        std::memcpy(&ci, b + off, 4);
+        std::memcpy(&co, b + off + 4, 4);
+        off += 8;
+        const bool shape = (ci == 16 && co == 32) || (ci == 32 && co == 32) || (ci == 32 && co == 16) ||
+                           (ci == 16 && co == 16);
+        if (!shape || (l == 0 && ci != 16) || (l > 0 && (int)ci != net.co[l - 1]) || (l == net.nl - 1 && co != 16))
+            return fail(c, VS_E_INVAL, "weight file: unsupported layer shapes");
+        net.ci[l] = (int)ci;
+        net.co[l] = (int)co;
+    }
+    size_t wbytes[SURR_MAX_LAYERS], woff[SURR_MAX_LAYERS], dev_w = 0;
+    for (int l = 0; l < net.nl; ++l) {
+        wbytes[l] = (size_t)net.co[l] * 9 * net.ci[l] * 2 + (size_t)net.co[l] * 4;
+        woff[l] = off;
+        off += wbytes[l];
+        dev_w += align_up(wbytes[l], 256);
+    }
+    if (off != nbytes) return fail(c, VS_E_INVAL, "weight file size");
+    // one image per field at the surrogate's level
+    nn::ImgTable& T = net.tbl;
+    const int nf = 2 * h.n_pairs;
+    T.n = nf;
+    T.pix_off[0] = 0;
+    T.tile_off[0] = 0;
+    for (int f = 0; f < nf; ++f) {
+        const int p = f >> 1;
+        T.w[f] = h.lw[p][SURR_LEVEL];
+        T.h[f] = h.lh[p][SURR_LEVEL];
+        const long np = (long)T.w[f] * T.h[f];
+        T.pix_off[f + 1] = T.pix_off[f] + np;
+        T.tile_off[f + 1] = T.tile_off[f] + (int)((np + 63) / 64);
+    }
+    for (int i = nf + 1; i <= nn::MAXI; ++i) {
+        T.pix_off[i] = T.pix_off[nf];
+        T.tile_off[i] = T.tile_off[nf];
+    }
+    const size_t npx = (size_t)T.pix_off[nf];
+    const size_t o_x = dev_w, o_h0 = align_up(o_x + npx * 16 * 2, 256), o_h1 = align_up(o_h0 + npx * 32 * 2, 256),
+                 o_pred = align_up(o_h1 + npx * 32 * 2, 256), total = align_up(o_pred + npx * 16 * 4, 256);
+    VS_CHECK(hipDeviceSynchronize(), "hipDeviceSynchronize");
+    void* mem = nullptr;
+    if (hipMalloc(&mem, total) != hipSuccess) return fail(c, VS_E_NOMEM, "surrogate buffers");
+    uint8_t* base = (uint8_t*)mem;
+    size_t wo = 0;
+    hipError_t e = hipSuccess;
+    for (int l = 0; l < net.nl && e == hipSuccess; ++l) {
+        const size_t nw = (size_t)net.co[l] * 9 * net.ci[l];
+        net.w[l] = (const uint16_t*)(base + wo);
+        net.b[l] = (const float*)(base + wo + nw * 2);
+        e = hipMemcpy(base + wo, b + woff[l], wbytes[l], hipMemcpyHostToDevice);
+        wo += align_up(wbytes[l], 256);
+    }
+    if (e == hipSuccess) e = hipMemset(base + o_x, 0, total - o_x);
+    if (e != hipSuccess) {
+        (void)hipFree(mem);
+        return dev_fail(c, e, "surrogate upload");
+    }
+    net.x = (uint16_t*)(base + o_x);
+    net.h[0] = (uint16_t*)(base + o_h0);
+    net.h[1] = (uint16_t*)(base + o_h1);
+    net.pred = (float*)(base + o_pred);
+    if (c->surr_mem) (void)hipFree(c->surr_mem);
+    c->surr_mem = mem;
+    c->net = net;
+    c->surr_loaded = 1;
+    for (int f = 0; f <= nf; ++f) h.surr_pix[f] = T.pix_off[f];
+    h.surr_pred = net.pred;
+    VS_CHECK(hipMemcpy(c->dp, &h, sizeof(DevPlan), hipMemcpyHostToDevice), "hipMemcpy plan");
+    c->gen += 1;
+    return VS_OK;
+}
+
+vs_status vs_set_flow_mode(vs_ctx* c, int mode, float fb_tau_px)
+{
+    if (!c || mode < VS_FLOW_PLAIN || mode > VS_FLOW_SURROGATE_FALLBACK || !(fb_tau_px >= 0.0f) || fb_tau_px > 1e6f)
+        return VS_E_INVAL;
+    if (c->sticky) return VS_E_DEVICE;
+    if (mode != VS_FLOW_PLAIN && !c->surr_loaded) return fail(c, VS_E_UNSUPPORTED, "no surrogate weights loaded");
+    VS_CHECK(hipDeviceSynchronize(), "hipDeviceSynchronize");
+    c->hp.flow_mode = mode;
+    c->hp.fb_tau_fix = (unsigned long long)std::llround((double)fb_tau_px * 256.0);
+    VS_CHECK(hipMemcpy(c->dp, &c->hp, sizeof(DevPlan), hipMemcpyHostToDevice), "hipMemcpy plan");
+    c->gen += 1;
     return VS_OK;
 }
 
@@ -649,6 +782,7 @@ vs_status vs_get_flow_variant(const vs_ctx* c, int32_t variant[VS_MAX_LEVELS])
 struct vs_batch {
     int n = 0;
     vs_ctx* ctx[MAXB] = {};
+    uint32_t gen[MAXB] = {};   // each context's generation at capture
     Group g;
     hipStream_t cap = nullptr;
     hipGraph_t graph = nullptr;
@@ -671,6 +805,10 @@ void drop_graph(vs_batch* b)
 vs_status capture(vs_batch* b)
 {
     drop_graph(b);
+    for (int c = 0; c < b->n; ++c) {
+        b->g.net[c] = b->ctx[c]->surr_loaded ? &b->ctx[c]->net : nullptr;
+        b->gen[c] = b->ctx[c]->gen;
+    }
     hipError_t e = hipStreamBeginCapture(b->cap, hipStreamCaptureModeThreadLocal);
     if (e != hipSuccess) {
         b->err = std::string("hipStreamBeginCapture: ") + hipGetErrorString(e);
@@ -790,6 +928,12 @@ vs_status vs_batch_run(vs_batch* b, const uint8_t* const* const frames[], uint8_
             io.frame[c][k] = frames[c][k];
         }
     }
+    for (int c = 0; c < b->n; ++c)
+        if (b->gen[c] != b->ctx[c]->gen) {   // a context changed its launch sequence
+            vs_status st = capture(b);
+            if (st != VS_OK) return st;
+            break;
+        }
     hipStream_t s = (hipStream_t)stream;
     hipError_t e = launch_set_io(io, b->n, s);
     if (e == hipSuccess) e = hipGraphLaunch(b->exec, s);
@@ -1079,6 +1223,26 @@ vs_status vs_debug_tap(vs_ctx* c, int tap, int p, int sub, void* dst, size_t nby
     case VS_TAP_DEFERRED:
         if (sub < 0 || sub >= h.levels) return VS_E_INVAL;
         return copy(&h.acc->lk_qn[sub], 4);
+    case VS_TAP_SURR_PRED: {
+        if (!pair_ok || sub < 0 || sub > 1) return VS_E_INVAL;
+        if (!c->surr_loaded) return fail(c, VS_E_UNSUPPORTED, "no surrogate weights loaded");
+        const int f = 2 * p + sub;
+        const size_t np = (size_t)(h.surr_pix[f + 1] - h.surr_pix[f]);
+        if (nbytes != np * 8) return fail(c, VS_E_INVAL, "tap size mismatch");
+        std::vector<float> tmp(np * 16);
+        VS_CHECK(hipDeviceSynchronize(), "hipDeviceSynchronize");
+        VS_CHECK(hipMemcpy(tmp.data(), c->net.pred + h.surr_pix[f] * 16, np * 64, hipMemcpyDeviceToHost), "hipMemcpy tap");
+        float* d = (float*)dst;
+        for (size_t q = 0; q < np; ++q) {
+            d[2 * q] = tmp[16 * q];
+            d[2 * q + 1] = tmp[16 * q + 1];
+        }
+        return VS_OK;
+    }
+    case VS_TAP_FB:
+        return copy(&h.res->fb[0][0], (size_t)h.n_pairs * 16);
+    case VS_TAP_SURR_OK:
+        return copy(&h.res->surr_ok[0], (size_t)h.n_pairs * 4);
     case VS_TAP_COVER: {
         const size_t npx = (size_t)h.canvas_w * h.canvas_h;
         if (nbytes != npx) return fail(c, VS_E_INVAL, "tap size mismatch");

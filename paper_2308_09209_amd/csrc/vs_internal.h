@@ -5,6 +5,7 @@
 #include <stdint.h>
 
 #include "../../include/vstitch.h"
+#include "vs_nn.h"
 
 namespace vs {
 
@@ -12,6 +13,8 @@ constexpr int MAXC = VS_MAX_CAMS;
 constexpr int MAXP = VS_MAX_PAIRS;
 constexpr int MAXL = VS_MAX_LEVELS;
 constexpr int MAXB = 8;                       // contexts in one batched launch
+constexpr int SURR_LEVEL = 2;                 // pyramid level the learned surrogate works at
+constexpr int SURR_MAX_LAYERS = 8;
 
 // Tile shapes.
 constexpr int STRIP_TX = 64, STRIP_TY = 32;   // strip kernels: 256 threads, 8 rows each
@@ -32,8 +35,10 @@ struct Accum {
     unsigned long long n[MAXP];
     uint32_t pano_hist[3][256];
     uint32_t lk_qn[8];                // flow pixels deferred to the tail kernel, per level
+    unsigned long long fb[MAXP][2];   // surrogate forward-backward error (1/256 px) sum, pixel count
 };
 static_assert(MAXL <= 8, "one deferral counter per level");
+static_assert(sizeof(Accum) % 16 == 0, "k_zero clears whole 16-byte words");
 
 // Per-frame results (also the taps).
 struct Results {
@@ -45,6 +50,8 @@ struct Results {
     uint8_t bal_lut[3][256];
     int32_t quant[3][2];
     double mbar[3][2];
+    int32_t surr_ok[MAXP];            // 1: the pair keeps the surrogate's flows this frame
+    unsigned long long fb[MAXP][2];
 };
 
 struct DevPlan {
@@ -64,6 +71,11 @@ struct DevPlan {
     int32_t lk_off[MAXL][2 * MAXP + 1], lk_tx[MAXL][2 * MAXP];     // field f = 2 p + dir
     int32_t lk_P[MAXL];               // 0: generic kernel (16 x 16 tiles); 1, 2, 4: 9x9 kernel, P px per thread
     int32_t blend_tx, blend_ty, cover_words;
+    // learned surrogate (VS_FLOW_PLAIN: not used)
+    int32_t flow_mode;
+    unsigned long long fb_tau_fix;     // fallback threshold in 1/256 px
+    int64_t surr_pix[2 * MAXP + 1];    // field f's level-2 pixels start at surr_pix[f] (NHWC buffers)
+    const float* surr_pred;            // [pixels][16] FP32 network output
     // device buffers
     uint32_t* strip[MAXP];             // [2][sh][sw] packed R | G << 8 | B << 16
     uint8_t* mask[MAXP];               // [sh][sw]
@@ -96,11 +108,25 @@ struct FrameIO {
     uint8_t* pano[MAXB];
 };
 
+// host view of a context's loaded surrogate network (device buffers)
+struct SurrNet {
+    int nl;
+    float alpha;
+    int ci[SURR_MAX_LAYERS], co[SURR_MAX_LAYERS];
+    const uint16_t* w[SURR_MAX_LAYERS];   // [co][9][ci] BF16
+    const float* b[SURR_MAX_LAYERS];
+    uint16_t* x;                          // [pixels][16] packed input
+    uint16_t* h[2];                       // [pixels][32] hidden activations (ping-pong)
+    float* pred;                          // [pixels][16] output
+    nn::ImgTable tbl;                     // one image per field, level-2 sizes
+};
+
 // host view of a group of contexts launched together
 struct Group {
     int n;
     DevPlan* dp[MAXB];
     const DevPlan* hp[MAXB];
+    const SurrNet* net[MAXB];             // null: no surrogate loaded
 };
 
 // plan-time output of the coverage kernel
@@ -122,6 +148,7 @@ hipError_t launch_solve(const Group& g, hipStream_t s);
 hipError_t launch_pyr0(const Group& g, hipStream_t s);
 hipError_t launch_pyr_down(const Group& g, int level, hipStream_t s);
 hipError_t launch_lk(const Group& g, int level, hipStream_t s);
+hipError_t launch_surrogate(const Group& g, hipStream_t s);   // vs_surr.hip
 hipError_t launch_blend(const Group& g, hipStream_t s);
 hipError_t launch_balance_lut(const Group& g, hipStream_t s);
 hipError_t launch_balance_apply(const Group& g, hipStream_t s);

@@ -644,6 +644,7 @@ __device__ __forceinline__ void lk_body(const DevPlan* __restrict__ P, const int
     __shared__ float sM[LK_MW][LK_MW];
     const int f = find_field(P->lk_off[l], 2 * P->n_pairs, bid);
     const int p = f >> 1, dir = f & 1;
+    if (P->flow_mode != VS_FLOW_PLAIN && P->res->surr_ok[p]) return;   // the pair keeps the surrogate's flows
     const int t = bid - P->lk_off[l][f];
     const int w = P->lw[p][l], h = P->lh[p][l];
     const int x0 = (t % P->lk_tx[l][f]) * LK_T, y0 = (t / P->lk_tx[l][f]) * LK_T;
@@ -794,6 +795,7 @@ __device__ __forceinline__ void lk_w9_body(const DevPlan* __restrict__ Pl, const
 
     const int f = find_field(Pl->lk_off[l], 2 * Pl->n_pairs, bid);
     const int p = f >> 1, dir = f & 1;
+    if (Pl->flow_mode != VS_FLOW_PLAIN && Pl->res->surr_ok[p]) return;   // the pair keeps the surrogate's flows
     const int t = bid - Pl->lk_off[l][f];
     const int w = Pl->lw[p][l], h = Pl->lh[p][l];
     const int x0 = (t % Pl->lk_tx[l][f]) * TX, y0 = (t / Pl->lk_tx[l][f]) * TY;
@@ -1486,8 +1488,10 @@ hipError_t launch_pyr0(const Group& g, hipStream_t s)
 hipError_t launch_pyr_down(const Group& g, int l, hipStream_t s)
 {
     Batch B;
+    // the surrogate alone reads no level beyond its own
     if (make_batch(g, B, [l](const DevPlan& h) {
-            return h.use_flow && l + 1 < h.levels ? h.pyr_off[l + 1][2 * h.n_pairs] : 0; }))
+            const int top = h.flow_mode == VS_FLOW_SURROGATE ? SURR_LEVEL + 1 : h.levels;
+            return h.use_flow && l + 1 < top ? h.pyr_off[l + 1][2 * h.n_pairs] : 0; }))
         hipLaunchKernelGGL(k_pyr_down, dim3(B.off[B.n]), dim3(256), 0, s, B, l);
     return hipGetLastError();
 }
@@ -1499,7 +1503,9 @@ hipError_t launch_lk(const Group& g, int l, hipStream_t s)
     for (int c = 1; c < g.n; ++c)
         if (g.hp[c]->lk_P[l] != P) return hipErrorInvalidValue;
     Batch B;
-    if (make_batch(g, B, [l](const DevPlan& h) { return h.use_flow && l < h.levels ? h.lk_off[l][2 * h.n_pairs] : 0; })) {
+    // a context whose flows all come from the surrogate launches no flow blocks
+    auto plain = [](const DevPlan& h) { return h.use_flow && h.flow_mode != VS_FLOW_SURROGATE; };
+    if (make_batch(g, B, [&](const DevPlan& h) { return plain(h) && l < h.levels ? h.lk_off[l][2 * h.n_pairs] : 0; })) {
         const dim3 grid(B.off[B.n]);
         switch (P) {
         case 4: hipLaunchKernelGGL(k_lk_w9<4>, grid, dim3(256), 0, s, B, l); break;
@@ -1511,8 +1517,8 @@ hipError_t launch_lk(const Group& g, int l, hipStream_t s)
     hipError_t e = hipGetLastError();
     if (e != hipSuccess || P == 0) return e;
     // deferred pixels: the device-side count bounds the grid-stride loop
-    if (make_batch(g, B, [l](const DevPlan& h) {
-            return h.use_flow && l < h.levels ? std::min(1024, std::max(1, (h.lk_qcap[l] + 255) / 256)) : 0; }))
+    if (make_batch(g, B, [&](const DevPlan& h) {
+            return plain(h) && l < h.levels ? std::min(1024, std::max(1, (h.lk_qcap[l] + 255) / 256)) : 0; }))
         hipLaunchKernelGGL(k_lk_tail, dim3(B.off[B.n]), dim3(256), 0, s, B, l);
     return hipGetLastError();
 }

@@ -1,0 +1,160 @@
+// vs_surr.hip -- the learned flow surrogate inside the frame (an addition to
+// the paper's method, which estimates the overlap flow with a plain
+// estimator, section 3.2).
+//
+// Per frame, for every field f = 2 p + dir of a context (pair p, direction
+// dir: template = camera j / moving = camera i, and the reverse):
+//  1. pack: the level-2 luma of the field's template and moving strips into
+//     the 16-channel BF16 network input, (Y - 128) / 64 in channels 0-1;
+//  2. the network's 3x3 convolutions on the matrix cores (vs_nn.hip), one
+//     launch per layer over all fields;
+//  3. up: per overlap pixel of the strip, the x4 bilinear upsampling of both
+//     directions' level-2 predictions into the level-0 flow buffers, and the
+//     forward-backward error e = |U_ij(x) + U_ji(x + U_ij(x))| summed per pair
+//     in 1/256 px fixed point (exact integer sums, order free);
+//  4. decide: a pair keeps the surrogate's flows when the mode is
+//     VS_FLOW_SURROGATE, or when its mean error is below the threshold; the
+//     plain estimator's kernels skip the kept pairs and overwrite the others.
+#include "vs_internal.h"
+
+namespace vs {
+namespace {
+
+__device__ __forceinline__ uint32_t bf16_rne(float f)
+{
+    uint32_t u = __float_as_uint(f);
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return u >> 16;
+}
+
+__global__ __launch_bounds__(256) void k_surr_pack(const DevPlan* __restrict__ P, uint16_t* __restrict__ X)
+{
+    const int nf = 2 * P->n_pairs;
+    const long q = (long)blockIdx.x * 256 + threadIdx.x;
+    if (q >= P->surr_pix[nf]) return;
+    int f = 0;
+    while (f + 1 < nf && q >= P->surr_pix[f + 1]) ++f;
+    const int p = f >> 1, dir = f & 1;
+    const long i = q - P->surr_pix[f];
+    const float yt = P->pyr[p][dir == 0 ? 0 : 1][SURR_LEVEL][i];
+    const float ym = P->pyr[p][dir == 0 ? 1 : 0][SURR_LEVEL][i];
+    const uint32_t a = bf16_rne((yt - 128.0f) * (1.0f / 64.0f));
+    const uint32_t b = bf16_rne((ym - 128.0f) * (1.0f / 64.0f));
+    uint4* d = reinterpret_cast<uint4*>(X + q * 16);
+    d[0] = make_uint4(a | b << 16, 0u, 0u, 0u);
+    d[1] = make_uint4(0u, 0u, 0u, 0u);
+}
+
+// the x4 upsampled level-2 field (channels 0-1 of pred, 16 floats per pixel)
+// at level-0 position (X, Y); a non-finite position clamps to the border
+__device__ __forceinline__ float2 up_at(const float* __restrict__ pred, int w2, int h2, float X, float Y)
+{
+    const float cx = fminf(fmaxf(__builtin_fmaf(X, 0.25f, -0.375f), 0.0f), (float)(w2 - 1));
+    const float cy = fminf(fmaxf(__builtin_fmaf(Y, 0.25f, -0.375f), 0.0f), (float)(h2 - 1));
+    const float flx = floorf(cx), fly = floorf(cy);
+    const int xa = (int)flx, ya = (int)fly;
+    const float fx = cx - flx, fy = cy - fly;
+    const int xb = xa + 1 < w2 ? xa + 1 : w2 - 1;
+    const int yb = ya + 1 < h2 ? ya + 1 : h2 - 1;
+    const float2 p00 = *reinterpret_cast<const float2*>(pred + ((long)ya * w2 + xa) * 16);
+    const float2 p10 = *reinterpret_cast<const float2*>(pred + ((long)ya * w2 + xb) * 16);
+    const float2 p01 = *reinterpret_cast<const float2*>(pred + ((long)yb * w2 + xa) * 16);
+    const float2 p11 = *reinterpret_cast<const float2*>(pred + ((long)yb * w2 + xb) * 16);
+    float a = __builtin_fmaf(fx, p10.x - p00.x, p00.x);
+    float b = __builtin_fmaf(fx, p11.x - p01.x, p01.x);
+    const float rx = 4.0f * __builtin_fmaf(fy, b - a, a);
+    a = __builtin_fmaf(fx, p10.y - p00.y, p00.y);
+    b = __builtin_fmaf(fx, p11.y - p01.y, p01.y);
+    const float ry = 4.0f * __builtin_fmaf(fy, b - a, a);
+    return make_float2(rx, ry);
+}
+
+__device__ __forceinline__ unsigned long long wave_sum64(unsigned long long v)
+{
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+// one block per strip tile (64 x 32 px, 8 rows per thread)
+__global__ __launch_bounds__(256) void k_surr_up(const DevPlan* __restrict__ P)
+{
+    const int tid = threadIdx.x;
+    int p = 0;
+    while (p + 1 < P->n_pairs && (int)blockIdx.x >= P->strip_off[p + 1]) ++p;
+    const int t = blockIdx.x - P->strip_off[p];
+    const int sw = P->sw[p], sh = P->sh[p];
+    const int w2 = P->lw[p][SURR_LEVEL], h2 = P->lh[p][SURR_LEVEL];
+    const float* __restrict__ pij = P->surr_pred + P->surr_pix[2 * p] * 16;
+    const float* __restrict__ pji = P->surr_pred + P->surr_pix[2 * p + 1] * 16;
+    const uint8_t* __restrict__ need = P->need[p][0];
+    float2* __restrict__ fij = P->flow[p][0][0];
+    float2* __restrict__ fji = P->flow[p][1][0];
+    const int lx = (t % P->strip_tx[p]) * STRIP_TX + (tid & 63);
+    const int ty0 = (t / P->strip_tx[p]) * STRIP_TY;
+    unsigned long long esum = 0, cnt = 0;
+    if (lx < sw) {
+        for (int r = tid >> 6; r < STRIP_TY; r += 4) {
+            const int ly = ty0 + r;
+            if (ly >= sh) break;
+            const long q = (long)ly * sw + lx;
+            if (!need[q]) continue;
+            const float2 u = up_at(pij, w2, h2, (float)lx, (float)ly);
+            fij[q] = u;
+            fji[q] = up_at(pji, w2, h2, (float)lx, (float)ly);
+            const float2 v = up_at(pji, w2, h2, (float)lx + u.x, (float)ly + u.y);
+            const float ex = u.x + v.x, ey = u.y + v.y;
+            const float e = sqrtf(ex * ex + ey * ey);
+            esum += (unsigned)floorf(fminf(e * 256.0f, 1048576.0f) + 0.5f);
+            cnt += 1;
+        }
+    }
+    esum = wave_sum64(esum);
+    cnt = wave_sum64(cnt);
+    if ((tid & 63) == 0 && cnt > 0) {
+        atomicAdd(&P->acc->fb[p][0], esum);
+        atomicAdd(&P->acc->fb[p][1], cnt);
+    }
+}
+
+__global__ __launch_bounds__(64) void k_surr_decide(const DevPlan* __restrict__ P)
+{
+    const int p = threadIdx.x;
+    if (p >= P->n_pairs) return;
+    const unsigned long long s = P->acc->fb[p][0], n = P->acc->fb[p][1];
+    const int ok = P->flow_mode == VS_FLOW_SURROGATE || (n > 0 && s < P->fb_tau_fix * n);
+    P->res->surr_ok[p] = ok;
+    P->res->fb[p][0] = s;
+    P->res->fb[p][1] = n;
+}
+
+}  // namespace
+
+hipError_t launch_surrogate(const Group& g, hipStream_t s)
+{
+    for (int c = 0; c < g.n; ++c) {
+        const DevPlan& h = *g.hp[c];
+        const SurrNet* net = g.net[c];
+        if (!h.use_flow || h.flow_mode == VS_FLOW_PLAIN) continue;
+        if (!net) return hipErrorInvalidValue;
+        const long npx = h.surr_pix[2 * h.n_pairs];
+        hipLaunchKernelGGL(k_surr_pack, dim3((unsigned)((npx + 255) / 256)), dim3(256), 0, s, g.dp[c], net->x);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+        const uint16_t* in = net->x;
+        for (int l = 0; l < net->nl; ++l) {
+            const bool last = l == net->nl - 1;
+            void* out = last ? (void*)net->pred : (void*)net->h[l & 1];
+            e = nn::conv3x3(in, net->ci[l], net->w[l], net->b[l], out, net->co[l], net->tbl,
+                            last ? nn::CONV_F32 : nn::CONV_LRELU, net->alpha, s);
+            if (e != hipSuccess) return e;
+            in = net->h[l & 1];
+        }
+        hipLaunchKernelGGL(k_surr_up, dim3(h.strip_off[h.n_pairs]), dim3(256), 0, s, g.dp[c]);
+        hipLaunchKernelGGL(k_surr_decide, dim3(1), dim3(64), 0, s, g.dp[c]);
+        e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+}  // namespace vs

@@ -28,13 +28,15 @@ STATUS = {0: "VS_OK", -1: "VS_E_INVAL", -2: "VS_E_GEOMETRY", -3: "VS_E_NOMEM", -
           -5: "VS_E_STATE", -6: "VS_E_UNSUPPORTED"}
 TAP = dict(strip=1, mask=2, hist=3, lut=4, mom=5, mpair=6, mk=7, flags=8, pyr=9, flow=10,
            pano_pre=11, pano_hist=12, bal_lut=13, quant=14, mbar=15, cover=16, need=17,
-           deferred=18)
+           deferred=18, surr_pred=19, fb=20, surr_ok=21)
+FLOW_PLAIN, FLOW_SURROGATE, FLOW_SURROGATE_FALLBACK = 0, 1, 2
 
 # every symbol include/vstitch.h declares
 EXPORTS = ["vs_abi_version", "vs_status_str", "vs_default_params", "vs_compose_homographies",
            "vs_create", "vs_destroy", "vs_query", "vs_last_error", "vs_stitch", "vs_state_get",
            "vs_state_set", "vs_debug_tap", "vs_set_timing", "vs_get_timing",
-           "vs_set_flow_variant", "vs_get_flow_variant", "vs_batch_create", "vs_batch_run",
+           "vs_set_flow_variant", "vs_get_flow_variant", "vs_load_weights", "vs_set_flow_mode",
+           "vs_batch_create", "vs_batch_run",
            "vs_batch_destroy", "vs_batch_last_error", "vs_batch_autotune",
            "vs_nn_conv3x3", "vs_nn_wgrad_scratch_bytes", "vs_nn_conv3x3_wgrad", "vs_nn_flip_weights",
            "vs_nn_lrelu_bwd", "vs_nn_pack_pair", "vs_nn_epe_loss", "vs_nn_adam", "vs_nn_to_bf16",
@@ -99,7 +101,8 @@ def nn_images(sizes):
 class FrameInfo(C.Structure):
     _fields_ = [("Mk", (C.c_float * 9) * MAX_CAMS), ("Mpair", (C.c_double * 9) * MAX_PAIRS),
                 ("flags", C.c_int32 * MAX_PAIRS), ("quant", (C.c_int32 * 2) * 3),
-                ("mbar", (C.c_double * 2) * 3), ("frames_seen", C.c_uint32)]
+                ("mbar", (C.c_double * 2) * 3), ("frames_seen", C.c_uint32),
+                ("surr_ok", C.c_int32 * MAX_PAIRS), ("fb_err", C.c_float * MAX_PAIRS)]
 
 
 _lib = None
@@ -132,6 +135,8 @@ def lib():
         L.vs_get_timing.argtypes = [C.c_void_p, C.c_void_p, C.POINTER(C.c_uint32)]
         L.vs_set_flow_variant.argtypes = [C.c_void_p, C.c_int, C.c_int]
         L.vs_get_flow_variant.argtypes = [C.c_void_p, C.c_void_p]
+        L.vs_load_weights.argtypes = [C.c_void_p, C.c_void_p, C.c_size_t]
+        L.vs_set_flow_mode.argtypes = [C.c_void_p, C.c_int, C.c_float]
         L.vs_batch_create.argtypes = [C.c_void_p, C.c_int, C.POINTER(C.c_void_p)]
         L.vs_batch_run.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]
         L.vs_batch_destroy.argtypes = [C.c_void_p]
@@ -327,6 +332,19 @@ class Stitcher:
         if st != 0:
             self._err(st, "vs_set_flow_variant")
 
+    def load_weights(self, blob: bytes):
+        """Copy a surrogate weight file ("VSNN" v1) into the context."""
+        buf = C.create_string_buffer(bytes(blob), len(blob))
+        st = lib().vs_load_weights(self.h, buf, len(blob))
+        if st != 0:
+            self._err(st, "vs_load_weights")
+
+    def set_flow_mode(self, mode: int, fb_tau_px: float = 0.0):
+        """FLOW_PLAIN, FLOW_SURROGATE or FLOW_SURROGATE_FALLBACK (threshold in px)."""
+        st = lib().vs_set_flow_mode(self.h, mode, fb_tau_px)
+        if st != 0:
+            self._err(st, "vs_set_flow_mode")
+
     def tap(self, name: str, pair: int = 0, sub: int = 0) -> np.ndarray:
         I = self.info
         H, W = self.canvas
@@ -338,12 +356,16 @@ class Stitcher:
                       pano_pre=((H, W, 3), np.uint8), pano_hist=((3, 256), np.uint32),
                       bal_lut=((3, 256), np.uint8), quant=((3, 2), np.int32),
                       mbar=((3, 2), np.float64), cover=((H, W), np.uint8),
-                      deferred=((1,), np.uint32))
-        if name in ("pyr", "need"):
+                      deferred=((1,), np.uint32), fb=((I.n_pairs, 2), np.uint64),
+                      surr_ok=((I.n_pairs,), np.int32))
+        if name in ("pyr", "need", "surr_pred"):
             w, h = sw, sh
-            for _ in range(sub % 8):
+            for _ in range(sub % 8 if name != "surr_pred" else 2):
                 w, h = (w + 1) // 2, (h + 1) // 2
-            shape, dt = (h, w), (np.float32 if name == "pyr" else np.uint8)
+            if name == "surr_pred":
+                shape, dt = (h, w, 2), np.float32
+            else:
+                shape, dt = (h, w), (np.float32 if name == "pyr" else np.uint8)
         else:
             shape, dt = shapes[name]
         out = np.zeros(shape, dt)
