@@ -228,7 +228,7 @@ def main():
                data="synthetic",
                config=dict(workload=args.workload, cams=wl["n_cams"], frame=f"{wl['W']}x{wl['H']}",
                            overlap=wl["overlap"], ring=wl["ring"], panorama=f"{W}x{H}",
-                           seq_frames=seq, flow="plain pyramidal LK (L=4, K=5, r=4)",
+                           seq_frames=seq, flow="plain pyramidal LK (L=4, K=5, r=4, lambda=256)",
                            parallelism="single GPU"),
                p50_ms=round(float(np.percentile(lat, 50)), 4),
                p99_ms=round(float(np.percentile(lat, 99)), 4),

@@ -82,7 +82,7 @@ typedef struct {
     int32_t lk_levels;      /* pyramid levels, 1..VS_MAX_LEVELS (4) */
     int32_t lk_iters;       /* Gauss-Newton steps per level (5) */
     int32_t lk_radius;      /* window half-size r, window (2r+1)^2, 0..4 (4) */
-    float lk_lambda;        /* Tikhonov weight per window pixel (1.0) */
+    float lk_lambda;        /* Tikhonov weight per window pixel (256) */
     int32_t balance;        /* 1: apply the balancing LUT to covered pixels (1) */
     int32_t lambda_pct;     /* balancing quantile in percent, 1..49 (5) */
     int32_t debug_taps;     /* 1: keep a copy of the pre-balance panorama for vs_debug_tap (0) */
@@ -263,7 +263,7 @@ vs_status vs_batch_autotune(vs_batch* b, const uint8_t* const* const frames[], u
  * possibly different sizes stored back to back.
  * ------------------------------------------------------------------------ */
 #define VS_NN_MAX_IMAGES 64
-enum { VS_CONV_LRELU = 0, VS_CONV_LINEAR = 1, VS_CONV_F32 = 2 };
+enum { VS_CONV_LRELU = 0, VS_CONV_LINEAR = 1, VS_CONV_F32 = 2, VS_CONV_FLOW2 = 3 };
 typedef struct {
     int32_t n;
     int32_t w[VS_NN_MAX_IMAGES], h[VS_NN_MAX_IMAGES];
@@ -271,7 +271,8 @@ typedef struct {
 
 /* y = act(conv3x3(x, w) + bias) on the matrix cores.  (cin, cout) in
  * {(16,32), (32,32), (32,16), (16,16)}; mode VS_CONV_LRELU (BF16 out, leaky
- * ReLU slope alpha), VS_CONV_LINEAR (BF16 out) or VS_CONV_F32 (FP32 out);
+ * ReLU slope alpha), VS_CONV_LINEAR (BF16 out), VS_CONV_F32 (FP32 out) or
+ * VS_CONV_FLOW2 (FP32 channels 0-1 only, y is [pixels][2]);
  * bias may be NULL. */
 vs_status vs_nn_conv3x3(const uint16_t* x, int cin, const uint16_t* w, const float* bias, void* y, int cout,
                         const vs_nn_images* imgs, int mode, float alpha, void* stream);

@@ -140,7 +140,7 @@ void vso_default_params(vso_params* p)
     p->lk_levels = 4;
     p->lk_iters = 5;
     p->lk_radius = 4;
-    p->lk_lambda = 1.0f;
+    p->lk_lambda = 256.0f;
     p->balance = 1;
     p->lambda_pct = 5;
 }

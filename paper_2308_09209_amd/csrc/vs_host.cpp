@@ -164,7 +164,7 @@ vs_status vs_default_params(vs_params* p)
     p->lk_levels = 4;
     p->lk_iters = 5;
     p->lk_radius = 4;
-    p->lk_lambda = 1.0f;
+    p->lk_lambda = 256.0f;
     p->balance = 1;
     p->lambda_pct = 5;
     p->debug_taps = 0;
@@ -716,8 +716,10 @@ vs_status vs_load_weights(vs_ctx* c, const void* blob, size_t nbytes)
         T.tile_off[i] = T.tile_off[nf];
     }
     const size_t npx = (size_t)T.pix_off[nf];
+    const size_t nblk = (size_t)h.strip_off[h.n_pairs] * SURR_UP_SUB;
     const size_t o_x = dev_w, o_h0 = align_up(o_x + npx * 16 * 2, 256), o_h1 = align_up(o_h0 + npx * 32 * 2, 256),
-                 o_pred = align_up(o_h1 + npx * 32 * 2, 256), total = align_up(o_pred + npx * 16 * 4, 256);
+                 o_pred = align_up(o_h1 + npx * 32 * 2, 256), o_part = align_up(o_pred + npx * 2 * 4, 256),
+                 total = align_up(o_part + nblk * 16, 256);
     VS_CHECK(hipDeviceSynchronize(), "hipDeviceSynchronize");
     void* mem = nullptr;
     if (hipMalloc(&mem, total) != hipSuccess) return fail(c, VS_E_NOMEM, "surrogate buffers");
@@ -740,12 +742,14 @@ vs_status vs_load_weights(vs_ctx* c, const void* blob, size_t nbytes)
     net.h[0] = (uint16_t*)(base + o_h0);
     net.h[1] = (uint16_t*)(base + o_h1);
     net.pred = (float*)(base + o_pred);
+    net.part = (unsigned long long*)(base + o_part);
     if (c->surr_mem) (void)hipFree(c->surr_mem);
     c->surr_mem = mem;
     c->net = net;
     c->surr_loaded = 1;
     for (int f = 0; f <= nf; ++f) h.surr_pix[f] = T.pix_off[f];
     h.surr_pred = net.pred;
+    h.surr_part = net.part;
     VS_CHECK(hipMemcpy(c->dp, &h, sizeof(DevPlan), hipMemcpyHostToDevice), "hipMemcpy plan");
     c->gen += 1;
     return VS_OK;
@@ -1228,16 +1232,7 @@ vs_status vs_debug_tap(vs_ctx* c, int tap, int p, int sub, void* dst, size_t nby
         if (!c->surr_loaded) return fail(c, VS_E_UNSUPPORTED, "no surrogate weights loaded");
         const int f = 2 * p + sub;
         const size_t np = (size_t)(h.surr_pix[f + 1] - h.surr_pix[f]);
-        if (nbytes != np * 8) return fail(c, VS_E_INVAL, "tap size mismatch");
-        std::vector<float> tmp(np * 16);
-        VS_CHECK(hipDeviceSynchronize(), "hipDeviceSynchronize");
-        VS_CHECK(hipMemcpy(tmp.data(), c->net.pred + h.surr_pix[f] * 16, np * 64, hipMemcpyDeviceToHost), "hipMemcpy tap");
-        float* d = (float*)dst;
-        for (size_t q = 0; q < np; ++q) {
-            d[2 * q] = tmp[16 * q];
-            d[2 * q + 1] = tmp[16 * q + 1];
-        }
-        return VS_OK;
+        return copy(c->net.pred + h.surr_pix[f] * 2, np * 8);
     }
     case VS_TAP_FB:
         return copy(&h.res->fb[0][0], (size_t)h.n_pairs * 16);

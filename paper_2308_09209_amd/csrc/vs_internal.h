@@ -26,6 +26,8 @@ constexpr int LKW_TX = 64;                    // 9x9-window flow kernel: 64 px w
                                               // P vertically adjacent pixels per thread
 constexpr int BL_TX = 256, BL_TY = 32;        // blend / balance tile: 256 x 32 px
 constexpr int BL_THREADS = 1024;              // 64 quads of 4 px x 16 rows, 2 rows per thread
+constexpr int SURR_UP_ROWS = 4;               // surrogate upsampling: 64 x 4 px per block, one per thread
+constexpr int SURR_UP_SUB = STRIP_TY / SURR_UP_ROWS;   // upsampling blocks per strip tile
 
 // Per-frame accumulators, zeroed at the start of every frame.
 struct Accum {
@@ -35,7 +37,6 @@ struct Accum {
     unsigned long long n[MAXP];
     uint32_t pano_hist[3][256];
     uint32_t lk_qn[8];                // flow pixels deferred to the tail kernel, per level
-    unsigned long long fb[MAXP][2];   // surrogate forward-backward error (1/256 px) sum, pixel count
 };
 static_assert(MAXL <= 8, "one deferral counter per level");
 static_assert(sizeof(Accum) % 16 == 0, "k_zero clears whole 16-byte words");
@@ -75,7 +76,8 @@ struct DevPlan {
     int32_t flow_mode;
     unsigned long long fb_tau_fix;     // fallback threshold in 1/256 px
     int64_t surr_pix[2 * MAXP + 1];    // field f's level-2 pixels start at surr_pix[f] (NHWC buffers)
-    const float* surr_pred;            // [pixels][16] FP32 network output
+    const float* surr_pred;            // [pixels][2] FP32 network output (flow, level-2 px)
+    unsigned long long* surr_part;     // [upsampling block][2] forward-backward error sum, pixel count
     // device buffers
     uint32_t* strip[MAXP];             // [2][sh][sw] packed R | G << 8 | B << 16
     uint8_t* mask[MAXP];               // [sh][sw]
@@ -117,7 +119,8 @@ struct SurrNet {
     const float* b[SURR_MAX_LAYERS];
     uint16_t* x;                          // [pixels][16] packed input
     uint16_t* h[2];                       // [pixels][32] hidden activations (ping-pong)
-    float* pred;                          // [pixels][16] output
+    float* pred;                          // [pixels][2] output (channels 0-1)
+    unsigned long long* part;             // per-block forward-backward partial sums
     nn::ImgTable tbl;                     // one image per field, level-2 sizes
 };
 

@@ -8,11 +8,12 @@ namespace nn {
 
 constexpr int MAXI = 64;   // images per launch
 
-enum { CONV_LRELU = 0, CONV_LINEAR = 1, CONV_F32 = 2 };
+enum { CONV_LRELU = 0, CONV_LINEAR = 1, CONV_F32 = 2, CONV_FLOW2 = 3 };
 
 // A launch over MAXI images of possibly different sizes stored back to back
 // (NHWC): image i has w[i] x h[i] pixels starting at pixel pix_off[i], and
-// owns blocks tile_off[i] .. tile_off[i + 1] - 1 (64 pixels per block).
+// owns blocks tile_off[i] .. tile_off[i + 1] - 1 (each launcher rebuilds
+// tile_off for its own pixels per block).
 struct ImgTable {
     int32_t n;
     int32_t w[MAXI], h[MAXI];

@@ -33,11 +33,17 @@ __device__ __forceinline__ int find_img(const ImgTable& T, int b)
 // ---------------------------------------------------------------------------
 // 3x3 convolution, zero padding, as an implicit GEMM on the matrix cores:
 // D[pixel][cout] = sum_{tap, cin} X[pixel + tap][cin] W[cout][tap][cin].
-// A block computes 64 consecutive pixels of one image (16 per wavefront) for
-// every output channel.  MFMA 16x16x16 BF16 fragments: lane l holds
+// A block computes CONV_PX consecutive pixels of one image for every output
+// channel: each wavefront CONV_G groups of 16 pixels at once (independent
+// accumulator chains hide the matrix-core latency), the block's weights
+// staged once in LDS.  Every accumulator sums its products in (tap, cin
+// chunk) order.  MFMA 16x16x16 BF16 fragments: lane l holds
 // A[m = l % 16][k = 4 (l / 16) + i], B[k = 4 (l / 16) + i][n = l % 16] and
 // D[m = 4 (l / 16) + i][n = l % 16], i = 0..3.
 // ---------------------------------------------------------------------------
+constexpr int CONV_G = 4;
+constexpr int CONV_PX = 4 * 16 * CONV_G;
+
 template <int CIN, int COUT, int MODE>
 __global__ __launch_bounds__(256) void k_conv3x3(const uint16_t* __restrict__ X, const uint16_t* __restrict__ Wt,
                                                  const float* __restrict__ bias, void* __restrict__ Y,
@@ -56,43 +62,68 @@ __global__ __launch_bounds__(256) void k_conv3x3(const uint16_t* __restrict__ X,
     const long base = T.pix_off[img];
     const int lane = tid & 63, wv = tid >> 6;
     const int m = lane & 15, kg = lane >> 4;
-    const int q0 = (blockIdx.x - T.tile_off[img]) * 64 + wv * 16;
-    const int q = q0 + m;
-    const bool valid = q < npix;
-    const int y = valid ? q / W : 0, x = valid ? q % W : 0;
-    f32x4 acc[NT];
+    const int qb = (blockIdx.x - T.tile_off[img]) * CONV_PX + wv * (16 * CONV_G);
+    int py[CONV_G], px[CONV_G];
+    bool pv[CONV_G];
 #pragma unroll
-    for (int t = 0; t < NT; ++t) acc[t] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+    for (int g = 0; g < CONV_G; ++g) {
+        const int q = qb + g * 16 + m;
+        pv[g] = q < npix;
+        py[g] = pv[g] ? q / W : 0;
+        px[g] = pv[g] ? q % W : 0;
+    }
+    f32x4 acc[CONV_G][NT];
+#pragma unroll
+    for (int g = 0; g < CONV_G; ++g)
+#pragma unroll
+        for (int t = 0; t < NT; ++t) acc[g][t] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll
     for (int tap = 0; tap < 9; ++tap) {
-        const int yy = y + tap / 3 - 1, xx = x + tap % 3 - 1;
-        const bool inb = valid && yy >= 0 && yy < H && xx >= 0 && xx < W;
-        const bf16x4* src = reinterpret_cast<const bf16x4*>(X + (base + (long)yy * W + xx) * CIN);
+        const int dy = tap / 3 - 1, dx = tap % 3 - 1;
+        const bf16x4* src[CONV_G];
+        bool inb[CONV_G];
+#pragma unroll
+        for (int g = 0; g < CONV_G; ++g) {
+            const int yy = py[g] + dy, xx = px[g] + dx;
+            inb[g] = pv[g] && yy >= 0 && yy < H && xx >= 0 && xx < W;
+            src[g] = reinterpret_cast<const bf16x4*>(X + (base + (long)yy * W + xx) * CIN);
+        }
 #pragma unroll
         for (int c = 0; c < NC; ++c) {
-            const bf16x4 a = inb ? src[c * 4 + kg] : bf16x4{0, 0, 0, 0};
+            bf16x4 a[CONV_G];
+#pragma unroll
+            for (int g = 0; g < CONV_G; ++g) a[g] = inb[g] ? src[g][c * 4 + kg] : bf16x4{0, 0, 0, 0};
 #pragma unroll
             for (int t = 0; t < NT; ++t) {
                 const bf16x4 b = sW[((t * 16 + m) * 9 + tap) * (CIN / 4) + c * 4 + kg];
-                acc[t] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, acc[t], 0, 0, 0);
+#pragma unroll
+                for (int g = 0; g < CONV_G; ++g)
+                    acc[g][t] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a[g], b, acc[g][t], 0, 0, 0);
             }
         }
     }
 #pragma unroll
-    for (int t = 0; t < NT; ++t) {
-        const int co = t * 16 + m;
-        const float bb = bias ? bias[co] : 0.0f;
+    for (int g = 0; g < CONV_G; ++g)
 #pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            const int qq = q0 + kg * 4 + i;
-            if (qq >= npix) continue;
-            float v = acc[t][i] + bb;
-            if (MODE == CONV_LRELU) v = v > 0.0f ? v : alpha * v;
-            const long o = (base + qq) * COUT + co;
-            if (MODE == CONV_F32) static_cast<float*>(Y)[o] = v;
-            else static_cast<uint16_t*>(Y)[o] = f2bf(v);
+        for (int t = 0; t < NT; ++t) {
+            const int co = t * 16 + m;
+            const float bb = bias ? bias[co] : 0.0f;
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int qq = qb + g * 16 + kg * 4 + i;
+                if (qq >= npix) continue;
+                float v = acc[g][t][i] + bb;
+                if (MODE == CONV_LRELU) v = v > 0.0f ? v : alpha * v;
+                const long o = (base + qq) * COUT + co;
+                if (MODE == CONV_FLOW2) {
+                    if (co < 2) static_cast<float*>(Y)[(base + qq) * 2 + co] = v;
+                } else if (MODE == CONV_F32) {
+                    static_cast<float*>(Y)[o] = v;
+                } else {
+                    static_cast<uint16_t*>(Y)[o] = f2bf(v);
+                }
+            }
         }
-    }
 }
 
 // ---------------------------------------------------------------------------
@@ -290,14 +321,19 @@ __global__ void k_mfma_probe(const uint16_t* __restrict__ a, const uint16_t* __r
 // ---------------------------------------------------------------------------
 
 template <int CIN, int COUT>
-static hipError_t conv_mode(const uint16_t* X, const uint16_t* W, const float* b, void* Y, const ImgTable& T,
+static hipError_t conv_mode(const uint16_t* X, const uint16_t* W, const float* b, void* Y, const ImgTable& T0,
                             int mode, float alpha, hipStream_t s)
 {
+    ImgTable T = T0;   // blocks of CONV_PX pixels
+    T.tile_off[0] = 0;
+    for (int i = 0; i < T.n; ++i) T.tile_off[i + 1] = T.tile_off[i] + (T.w[i] * T.h[i] + CONV_PX - 1) / CONV_PX;
+    for (int i = T.n + 1; i <= MAXI; ++i) T.tile_off[i] = T.tile_off[T.n];
     const dim3 g(T.tile_off[T.n]), blk(256);
     switch (mode) {
     case CONV_LRELU: hipLaunchKernelGGL((k_conv3x3<CIN, COUT, CONV_LRELU>), g, blk, 0, s, X, W, b, Y, T, alpha); break;
     case CONV_LINEAR: hipLaunchKernelGGL((k_conv3x3<CIN, COUT, CONV_LINEAR>), g, blk, 0, s, X, W, b, Y, T, alpha); break;
     case CONV_F32: hipLaunchKernelGGL((k_conv3x3<CIN, COUT, CONV_F32>), g, blk, 0, s, X, W, b, Y, T, alpha); break;
+    case CONV_FLOW2: hipLaunchKernelGGL((k_conv3x3<CIN, COUT, CONV_FLOW2>), g, blk, 0, s, X, W, b, Y, T, alpha); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();

@@ -46,7 +46,7 @@ vs_status vs_nn_conv3x3(const uint16_t* x, int cin, const uint16_t* w, const flo
                         const vs_nn_images* imgs, int mode, float alpha, void* stream)
 {
     nn::ImgTable T;
-    if (!x || !w || !y || !shape_ok(cin, cout) || mode < 0 || mode > 2 || !make_table(imgs, T)) return VS_E_INVAL;
+    if (!x || !w || !y || !shape_ok(cin, cout) || mode < 0 || mode > 3 || !make_table(imgs, T)) return VS_E_INVAL;
     return st(nn::conv3x3(x, cin, w, bias, y, cout, T, mode, alpha, (hipStream_t)stream));
 }
 

@@ -10,9 +10,10 @@
 //     launch per layer over all fields;
 //  3. up: per overlap pixel of the strip, the x4 bilinear upsampling of both
 //     directions' level-2 predictions into the level-0 flow buffers, and the
-//     forward-backward error e = |U_ij(x) + U_ji(x + U_ij(x))| summed per pair
-//     in 1/256 px fixed point (exact integer sums, order free);
-//  4. decide: a pair keeps the surrogate's flows when the mode is
+//     forward-backward error e = |U_ij(x) + U_ji(x + U_ij(x))| in 1/256 px
+//     fixed point, summed per block (exact integer sums);
+//  4. decide: the pair's block sums are added, and the pair keeps the
+//     surrogate's flows when the mode is
 //     VS_FLOW_SURROGATE, or when its mean error is below the threshold; the
 //     plain estimator's kernels skip the kept pairs and overwrite the others.
 #include "vs_internal.h"
@@ -45,9 +46,9 @@ __global__ __launch_bounds__(256) void k_surr_pack(const DevPlan* __restrict__ P
     d[1] = make_uint4(0u, 0u, 0u, 0u);
 }
 
-// the x4 upsampled level-2 field (channels 0-1 of pred, 16 floats per pixel)
-// at level-0 position (X, Y); a non-finite position clamps to the border
-__device__ __forceinline__ float2 up_at(const float* __restrict__ pred, int w2, int h2, float X, float Y)
+// the x4 upsampled level-2 field (pred: [pixels][2]) at level-0 position
+// (X, Y); a non-finite position clamps to the border
+__device__ __forceinline__ float2 up_at(const float2* __restrict__ pred, int w2, int h2, float X, float Y)
 {
     const float cx = fminf(fmaxf(__builtin_fmaf(X, 0.25f, -0.375f), 0.0f), (float)(w2 - 1));
     const float cy = fminf(fmaxf(__builtin_fmaf(Y, 0.25f, -0.375f), 0.0f), (float)(h2 - 1));
@@ -56,10 +57,8 @@ __device__ __forceinline__ float2 up_at(const float* __restrict__ pred, int w2, 
     const float fx = cx - flx, fy = cy - fly;
     const int xb = xa + 1 < w2 ? xa + 1 : w2 - 1;
     const int yb = ya + 1 < h2 ? ya + 1 : h2 - 1;
-    const float2 p00 = *reinterpret_cast<const float2*>(pred + ((long)ya * w2 + xa) * 16);
-    const float2 p10 = *reinterpret_cast<const float2*>(pred + ((long)ya * w2 + xb) * 16);
-    const float2 p01 = *reinterpret_cast<const float2*>(pred + ((long)yb * w2 + xa) * 16);
-    const float2 p11 = *reinterpret_cast<const float2*>(pred + ((long)yb * w2 + xb) * 16);
+    const float2 p00 = pred[(long)ya * w2 + xa], p10 = pred[(long)ya * w2 + xb];
+    const float2 p01 = pred[(long)yb * w2 + xa], p11 = pred[(long)yb * w2 + xb];
     float a = __builtin_fmaf(fx, p10.x - p00.x, p00.x);
     float b = __builtin_fmaf(fx, p11.x - p01.x, p01.x);
     const float rx = 4.0f * __builtin_fmaf(fy, b - a, a);
@@ -69,62 +68,83 @@ __device__ __forceinline__ float2 up_at(const float* __restrict__ pred, int w2, 
     return make_float2(rx, ry);
 }
 
-__device__ __forceinline__ unsigned long long wave_sum64(unsigned long long v)
+__device__ __forceinline__ uint32_t wave_sum(uint32_t v)
 {
     for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
     return v;
 }
 
-// one block per strip tile (64 x 32 px, 8 rows per thread)
+// one overlap pixel per thread (64 x 4 px per block, SURR_UP_SUB blocks per
+// strip tile); each block writes its error sum and pixel count (exact
+// integers, at most 2^20 * 256 per block)
 __global__ __launch_bounds__(256) void k_surr_up(const DevPlan* __restrict__ P)
 {
+    __shared__ uint32_t s_red[2][4];
     const int tid = threadIdx.x;
+    const int tile = blockIdx.x / SURR_UP_SUB, sub = blockIdx.x % SURR_UP_SUB;
     int p = 0;
-    while (p + 1 < P->n_pairs && (int)blockIdx.x >= P->strip_off[p + 1]) ++p;
-    const int t = blockIdx.x - P->strip_off[p];
+    while (p + 1 < P->n_pairs && tile >= P->strip_off[p + 1]) ++p;
+    const int t = tile - P->strip_off[p];
     const int sw = P->sw[p], sh = P->sh[p];
     const int w2 = P->lw[p][SURR_LEVEL], h2 = P->lh[p][SURR_LEVEL];
-    const float* __restrict__ pij = P->surr_pred + P->surr_pix[2 * p] * 16;
-    const float* __restrict__ pji = P->surr_pred + P->surr_pix[2 * p + 1] * 16;
-    const uint8_t* __restrict__ need = P->need[p][0];
-    float2* __restrict__ fij = P->flow[p][0][0];
-    float2* __restrict__ fji = P->flow[p][1][0];
+    const float2* __restrict__ pij = reinterpret_cast<const float2*>(P->surr_pred) + P->surr_pix[2 * p];
+    const float2* __restrict__ pji = reinterpret_cast<const float2*>(P->surr_pred) + P->surr_pix[2 * p + 1];
     const int lx = (t % P->strip_tx[p]) * STRIP_TX + (tid & 63);
-    const int ty0 = (t / P->strip_tx[p]) * STRIP_TY;
-    unsigned long long esum = 0, cnt = 0;
-    if (lx < sw) {
-        for (int r = tid >> 6; r < STRIP_TY; r += 4) {
-            const int ly = ty0 + r;
-            if (ly >= sh) break;
-            const long q = (long)ly * sw + lx;
-            if (!need[q]) continue;
+    const int ly = (t / P->strip_tx[p]) * STRIP_TY + sub * SURR_UP_ROWS + (tid >> 6);
+    uint32_t esum = 0, cnt = 0;
+    if (lx < sw && ly < sh) {
+        const long q = (long)ly * sw + lx;
+        if (P->need[p][0][q]) {
             const float2 u = up_at(pij, w2, h2, (float)lx, (float)ly);
-            fij[q] = u;
-            fji[q] = up_at(pji, w2, h2, (float)lx, (float)ly);
+            P->flow[p][0][0][q] = u;
+            P->flow[p][1][0][q] = up_at(pji, w2, h2, (float)lx, (float)ly);
             const float2 v = up_at(pji, w2, h2, (float)lx + u.x, (float)ly + u.y);
             const float ex = u.x + v.x, ey = u.y + v.y;
             const float e = sqrtf(ex * ex + ey * ey);
-            esum += (unsigned)floorf(fminf(e * 256.0f, 1048576.0f) + 0.5f);
-            cnt += 1;
+            esum = (uint32_t)floorf(fminf(e * 256.0f, 1048576.0f) + 0.5f);
+            cnt = 1;
         }
     }
-    esum = wave_sum64(esum);
-    cnt = wave_sum64(cnt);
-    if ((tid & 63) == 0 && cnt > 0) {
-        atomicAdd(&P->acc->fb[p][0], esum);
-        atomicAdd(&P->acc->fb[p][1], cnt);
+    esum = wave_sum(esum);
+    cnt = wave_sum(cnt);
+    if ((tid & 63) == 0) {
+        s_red[0][tid >> 6] = esum;
+        s_red[1][tid >> 6] = cnt;
+    }
+    __syncthreads();
+    if (tid == 0) {
+        P->surr_part[2 * blockIdx.x] = (unsigned long long)s_red[0][0] + s_red[0][1] + s_red[0][2] + s_red[0][3];
+        P->surr_part[2 * blockIdx.x + 1] = (unsigned long long)s_red[1][0] + s_red[1][1] + s_red[1][2] + s_red[1][3];
     }
 }
 
-__global__ __launch_bounds__(64) void k_surr_decide(const DevPlan* __restrict__ P)
+// one block per pair: add the pair's block partials, decide
+__global__ __launch_bounds__(256) void k_surr_decide(const DevPlan* __restrict__ P)
 {
-    const int p = threadIdx.x;
-    if (p >= P->n_pairs) return;
-    const unsigned long long s = P->acc->fb[p][0], n = P->acc->fb[p][1];
-    const int ok = P->flow_mode == VS_FLOW_SURROGATE || (n > 0 && s < P->fb_tau_fix * n);
-    P->res->surr_ok[p] = ok;
-    P->res->fb[p][0] = s;
-    P->res->fb[p][1] = n;
+    __shared__ unsigned long long s_e[256], s_n[256];
+    const int p = blockIdx.x, tid = threadIdx.x;
+    const int b0 = P->strip_off[p] * SURR_UP_SUB, b1 = P->strip_off[p + 1] * SURR_UP_SUB;
+    unsigned long long e = 0, n = 0;
+    for (int b = b0 + tid; b < b1; b += 256) {
+        e += P->surr_part[2 * b];
+        n += P->surr_part[2 * b + 1];
+    }
+    s_e[tid] = e;
+    s_n[tid] = n;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if (tid < o) {
+            s_e[tid] += s_e[tid + o];
+            s_n[tid] += s_n[tid + o];
+        }
+        __syncthreads();
+    }
+    if (tid == 0) {
+        const unsigned long long s = s_e[0], c = s_n[0];
+        P->res->surr_ok[p] = P->flow_mode == VS_FLOW_SURROGATE || (c > 0 && s < P->fb_tau_fix * c);
+        P->res->fb[p][0] = s;
+        P->res->fb[p][1] = c;
+    }
 }
 
 }  // namespace
@@ -145,12 +165,12 @@ hipError_t launch_surrogate(const Group& g, hipStream_t s)
             const bool last = l == net->nl - 1;
             void* out = last ? (void*)net->pred : (void*)net->h[l & 1];
             e = nn::conv3x3(in, net->ci[l], net->w[l], net->b[l], out, net->co[l], net->tbl,
-                            last ? nn::CONV_F32 : nn::CONV_LRELU, net->alpha, s);
+                            last ? nn::CONV_FLOW2 : nn::CONV_LRELU, net->alpha, s);
             if (e != hipSuccess) return e;
             in = net->h[l & 1];
         }
-        hipLaunchKernelGGL(k_surr_up, dim3(h.strip_off[h.n_pairs]), dim3(256), 0, s, g.dp[c]);
-        hipLaunchKernelGGL(k_surr_decide, dim3(1), dim3(64), 0, s, g.dp[c]);
+        hipLaunchKernelGGL(k_surr_up, dim3(h.strip_off[h.n_pairs] * SURR_UP_SUB), dim3(256), 0, s, g.dp[c]);
+        hipLaunchKernelGGL(k_surr_decide, dim3(h.n_pairs), dim3(256), 0, s, g.dp[c]);
         e = hipGetLastError();
         if (e != hipSuccess) return e;
     }

@@ -81,7 +81,7 @@ class PlanInfo(C.Structure):
 
 
 NN_MAX_IMAGES = 64
-CONV_LRELU, CONV_LINEAR, CONV_F32 = 0, 1, 2
+CONV_LRELU, CONV_LINEAR, CONV_F32, CONV_FLOW2 = 0, 1, 2, 3
 
 
 class NNImages(C.Structure):
@@ -245,7 +245,10 @@ class Stitcher:
             self.h = None
 
     def __del__(self):
-        self.close()
+        try:
+            self.close()
+        except Exception:  # interpreter shutdown: module globals already gone
+            pass
 
     @property
     def canvas(self):
@@ -404,7 +407,10 @@ class Batch:
             self.h = None
 
     def __del__(self):
-        self.close()
+        try:
+            self.close()
+        except Exception:  # interpreter shutdown: module globals already gone
+            pass
 
     def _ptrs(self, frames, panos):
         n = len(self.stitchers)
@@ -471,7 +477,10 @@ class PlainFlow:
             self.hnd = None
 
     def __del__(self):
-        self.close()
+        try:
+            self.close()
+        except Exception:  # interpreter shutdown: module globals already gone
+            pass
 
     def __call__(self, yt, ym, stream=None):
         """(flow of template yt vs moving ym, the reverse flow), float32 [h][w][2]"""

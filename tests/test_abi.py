@@ -51,7 +51,7 @@ def test_struct_layouts_match_the_header(tmp_path):
 def test_default_params_are_the_papers():
     p = V.default_params()
     assert p.lambda_pct == 5 and p.color_window == 3
-    assert (p.lk_levels, p.lk_iters, p.lk_radius, p.lk_lambda) == (4, 5, 4, 1.0)
+    assert (p.lk_levels, p.lk_iters, p.lk_radius, p.lk_lambda) == (4, 5, 4, 256.0)
     assert V.lib().vs_status_str(-2) == b"geometry"
 
 

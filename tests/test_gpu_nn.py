@@ -177,8 +177,9 @@ def test_plain_flow_context_matches_oracle():
     T = np.round(T).astype(np.float32)
     pf = V.PlainFlow(200, 96)
     ftm, fmt = pf(dev(T), dev(M))
-    want_tm = O.pyramid_flow(_pyr(T), _pyr(M))
-    want_mt = O.pyramid_flow(_pyr(M), _pyr(T))
+    lam = V.default_params().lk_lambda
+    want_tm = O.pyramid_flow(_pyr(T), _pyr(M), lam=lam)
+    want_mt = O.pyramid_flow(_pyr(M), _pyr(T), lam=lam)
     np.testing.assert_array_equal(ftm.cpu().numpy(), want_tm)
     np.testing.assert_array_equal(fmt.cpu().numpy(), want_mt)
     yt2, ym2 = pf.level(2)

@@ -145,7 +145,53 @@ def test_flow_domain_restriction_keeps_the_overlap_flow():
         for d in (0, 1):
             T = [o.tap("pyr", p, (d * 8) + l) for l in range(4)]
             M = [o.tap("pyr", p, ((1 - d) * 8) + l) for l in range(4)]
-            full = O.pyramid_flow(T, M)
+            full = O.pyramid_flow(T, M, lam=o.params.lk_lambda)
             got = o.tap("flow", p, d)
             np.testing.assert_array_equal(got[m], full[m])
             assert np.all(got[~m] == 0)
+
+
+def _truth_flows(scene, o, p):
+    """the generator's relative displacement between the pair's strips:
+    camera k's strip at canvas X shows the texture at X + d_k(H_k^-1 X), so
+    flow_ij(X) = d_j - d_i and flow_ji(X) = d_i - d_j (to first order)"""
+    from scipy import ndimage
+    P = o.plan
+    j, i, si = P.pair_j[p], P.pair_i[p], P.pair_si[p]
+    x0, y0, w, h = o.strip_box(p)
+    ys, xs = np.mgrid[0:h, 0:w].astype(np.float64)
+
+    def resid(k, X, Y):
+        Hi = np.linalg.inv(scene.cams[k].H_true)
+        wq = Hi[2, 0] * X + Hi[2, 1] * Y + Hi[2, 2]
+        u = (Hi[0, 0] * X + Hi[0, 1] * Y + Hi[0, 2]) / wq
+        v = (Hi[1, 0] * X + Hi[1, 1] * Y + Hi[1, 2]) / wq
+        return np.stack([ndimage.map_coordinates(scene.cams[k].resid[..., c], [v, u], order=1, mode="nearest")
+                         for c in (0, 1)], -1)
+
+    dj = resid(j, xs + x0, ys + y0)
+    di = resid(i, xs + x0 - si * P.ring_period, ys + y0)
+    return dj - di, di - dj
+
+
+def test_default_tikhonov_weight_against_planted_truth():
+    """The estimator's Tikhonov weight is this implementation's choice (the
+    paper does not define its flow): the default beats weights 16x weaker and
+    stronger, and the paper-agnostic lambda = 1, in mean end-point error
+    against the generator's planted displacements."""
+    from paper_2308_09209_amd.scenes import small_scene
+    sc = small_scene(n_cams=3, W=480, H=270, overlap=0.25, ring=True, seed_config=95)
+    fr = sc.frames(0)
+    lam0 = O.default_params().lk_lambda
+    err = {}
+    for lam in (1.0, lam0 / 16, lam0, lam0 * 16):
+        o = O.Oracle(sc.rig(), lk_lambda=lam)
+        o.stitch(fr)
+        es = []
+        for p in range(o.n_pairs):
+            need = o.tap("need", p, 0).astype(bool)
+            for d, t in enumerate(_truth_flows(sc, o, p)):
+                es.append(np.sqrt(((o.tap("flow", p, d) - t) ** 2).sum(-1))[need])
+        err[lam] = float(np.concatenate(es).mean())
+    assert err[lam0] == min(err.values()), err
+    assert err[lam0] < 0.6, err
