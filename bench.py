@@ -137,13 +137,16 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=300)
     ap.add_argument("--warmup", type=int, default=10)
-    ap.add_argument("--workload", default="4x1920x1080_ring")
-    ap.add_argument("--seq", type=int, default=60, help="distinct frames generated (cycled)")
-    ap.add_argument("--cpu-frames", type=int, default=3)
+    ap.add_argument("--workload", default=None, help="default 4x1920x1080_ring")
+    ap.add_argument("--seq", type=int, default=None,
+                    help="distinct frames generated and cycled (default 60; 4 for the 8 x 3840x2160 ring, whose "
+                         "frames take seconds each to synthesise)")
+    ap.add_argument("--cpu-frames", type=int, default=None, help="oracle frames timed (default 3; 1 at 8 x 4K)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--batch", action="store_true",
                     help="the 6-stream batched workload (2x1280x720, 2x1920x1080, 2x2560x1440, "
-                         "3-4 cameras each) through one captured graph, instead of the ring")
+                         "3-4 cameras each) through one captured graph, instead of the ring; with an "
+                         "explicit --workload, that one workload through the captured graph")
     ap.add_argument("--autotune", action="store_true", help="autotune the flow kernel first (batch)")
     ap.add_argument("--flow", choices=sorted(FLOW_MODES), default=None,
                     help="flow mode of the surrogate leg (default fallback; plain: no surrogate leg); "
@@ -166,9 +169,15 @@ def main():
     from paper_2308_09209_amd import vstitch as V
     from paper_2308_09209_amd.scenes import WORKLOADS, scene_for
 
+    big = args.workload == "8x3840x2160_ring"
+    if args.seq is None:
+        args.seq = 4 if big else 60
+    if args.cpu_frames is None:
+        args.cpu_frames = 1 if big else 3
     if args.batch:
         args.flow = args.flow or "plain"
         return bench_batch(args)
+    args.workload = args.workload or "4x1920x1080_ring"
     args.flow = args.flow or "fallback"
 
     wl = WORKLOADS[args.workload]
@@ -293,10 +302,10 @@ def bench_batch(args):
     import torch
 
     from paper_2308_09209_amd import vstitch as V
-    from paper_2308_09209_amd.scenes import BATCH_STREAMS, batch_scenes
+    from paper_2308_09209_amd.scenes import BATCH_STREAMS, WORKLOADS, batch_scenes, scene_for
 
     t_gen = time.perf_counter()
-    scenes = batch_scenes()
+    scenes = [scene_for(args.workload)] if args.workload else batch_scenes()
     seq = max(1, args.seq)
     dev = torch.device("cuda:0")
     frames = [[[torch.from_numpy(f).to(dev) for f in sc.frames(t)] for sc in scenes] for t in range(seq)]
@@ -329,12 +338,17 @@ def bench_batch(args):
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     lat = np.array([starts[i].elapsed_time(ends[i]) for i in range(K)])
-    out = dict(metric="panorama Mpix/s (6 uneven streams, one graph per frame step)",
+    if args.workload:
+        wl = WORKLOADS[args.workload]
+        streams = [f"{wl['n_cams']}x{wl['W']}x{wl['H']}" + ("_ring" if wl["ring"] else "")]
+    else:
+        streams = [f"{s['n_cams']}x{s['W']}x{s['H']}" for s in BATCH_STREAMS]
+    out = dict(metric="panorama Mpix/s (one graph per frame step)" if args.workload else
+               "panorama Mpix/s (6 uneven streams, one graph per frame step)",
                value=round(K * px / wall / 1e6, 2), unit="Mpix/s", n_gpus=1, steps=K,
                warmup=args.warmup, ms_per_step=round(wall / K * 1e3, 4), higher_is_better=True,
                scaling="weak", vs_baseline=None, dtype="f32", data="synthetic",
-               config=dict(workload="6stream_batch",
-                           streams=[f"{s['n_cams']}x{s['W']}x{s['H']}" for s in BATCH_STREAMS],
+               config=dict(workload=args.workload or "6stream_batch", streams=streams,
                            panorama_mpix_per_step=round(px / 1e6, 3), seq_frames=seq,
                            flow_variant_per_level=choice, autotuned=bool(args.autotune),
                            flow=args.flow if use_surr else "plain",

@@ -20,7 +20,7 @@ struct vs_ctx {
     DevPlan* dp = nullptr;   // device copy
     void* arena = nullptr;   // per-frame workspace
     size_t arena_bytes = 0;
-    void* plan_mem = nullptr;  // coverage bits + candidates + scan
+    void* plan_mem = nullptr;  // coverage bits + candidates + pixel codes + scan
     uint8_t* pano_pre = nullptr;
     vs_plan_info info;
     int sticky = 0;
@@ -255,8 +255,9 @@ vs_status vs_create(const vs_rig* rig, const vs_params* prm, vs_ctx** out)
     // ---- plan scan on the device: coverage, candidates, strip boxes ----
     const size_t cover_bytes = align_up((size_t)h.canvas_h * h.cover_words * 4, 256);
     const size_t cand_bytes = align_up((size_t)h.blend_tx * h.blend_ty * 8, 256);
+    const size_t code_bytes = align_up((size_t)h.canvas_w * h.canvas_h * 2, 256);
     const size_t scan_bytes = align_up(sizeof(PlanScan), 256);
-    hipError_t e = hipMalloc(&c->plan_mem, cover_bytes + cand_bytes + scan_bytes);
+    hipError_t e = hipMalloc(&c->plan_mem, cover_bytes + cand_bytes + code_bytes + scan_bytes);
     if (e != hipSuccess) {
         free_ctx(c);
         return VS_E_NOMEM;
@@ -268,7 +269,8 @@ vs_status vs_create(const vs_rig* rig, const vs_params* prm, vs_ctx** out)
     }
     h.cover = (uint32_t*)c->plan_mem;
     h.cand = (unsigned long long*)((uint8_t*)c->plan_mem + cover_bytes);
-    PlanScan* dscan = (PlanScan*)((uint8_t*)c->plan_mem + cover_bytes + cand_bytes);
+    h.pix_code = (uint16_t*)((uint8_t*)c->plan_mem + cover_bytes + cand_bytes);
+    PlanScan* dscan = (PlanScan*)((uint8_t*)c->plan_mem + cover_bytes + cand_bytes + code_bytes);
     PlanScan scan;
     std::memset(&scan, 0, sizeof scan);
     for (int p = 0; p < MAXP; ++p) {
@@ -421,7 +423,7 @@ vs_status vs_create(const vs_rig* rig, const vs_params* prm, vs_ctx** out)
         I.strip_h[p] = h.sh[p];
     }
     I.n_covered = (int64_t)scan.n_covered;
-    I.workspace_bytes = c->arena_bytes + cover_bytes + cand_bytes + scan_bytes + sizeof(DevPlan);
+    I.workspace_bytes = c->arena_bytes + cover_bytes + cand_bytes + code_bytes + scan_bytes + sizeof(DevPlan);
     I.state_bytes = sizeof(vs_color_state);
     *out = c;
     return VS_OK;

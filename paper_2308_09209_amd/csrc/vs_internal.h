@@ -24,8 +24,8 @@ constexpr int LK_R_MAX = 4;                   // window half-size limit of the s
 constexpr int LK_D = 8;                       // displacement the staged moving tile covers
 constexpr int LKW_TX = 64;                    // 9x9-window flow kernel: 64 px wide, 4 * P rows,
                                               // P vertically adjacent pixels per thread
-constexpr int BL_TX = 256, BL_TY = 32;        // blend / balance tile: 256 x 32 px
-constexpr int BL_THREADS = 1024;              // 64 quads of 4 px x 16 rows, 2 rows per thread
+constexpr int BL_TX = 256, BL_TY = 8;         // blend / balance tile: 256 x 8 px
+constexpr int BL_THREADS = 256;               // 64 quads of 4 px x 4 rows, 2 rows per thread
 constexpr int SURR_UP_ROWS = 4;               // surrogate upsampling: 64 x 4 px per block, one per thread
 constexpr int SURR_UP_SUB = STRIP_TY / SURR_UP_ROWS;   // upsampling blocks per strip tile
 
@@ -88,6 +88,9 @@ struct DevPlan {
     int32_t lk_qcap[MAXL];
     uint32_t* cover;                   // [canvas_h][cover_words] coverage bits
     unsigned long long* cand;          // [blend_ty][blend_tx] (camera, shift) candidates
+    uint16_t* pix_code;                // [canvas_h][canvas_w] covering candidates: bits 0-5 and 6-11 the
+                                       // first and second as 3 camera + shift + 1 (shift -1, 0, 1 periods),
+                                       // bits 12-13 their count
     Accum* acc;
     Results* res;
     vs_color_state* state;

@@ -140,6 +140,12 @@ __global__ __launch_bounds__(256) void k_plan_scan(const DevPlan* __restrict__ P
                     }
                 }
             }
+            {
+                const int n2 = nh < 2 ? nh : 2;
+                const uint32_t code = (n2 > 0 ? (uint32_t)(hc[0] * 3 + hm[0] + 1) : 0u) |
+                                      (n2 > 1 ? (uint32_t)(hc[1] * 3 + hm[1] + 1) << 6 : 0u) | (uint32_t)n2 << 12;
+                P->pix_code[(size_t)y * P->canvas_w + x] = (uint16_t)code;
+            }
             if (nh > 0) bits |= 1u << (x - x0);
             if (nh > 2) err |= 1u;
             if (nh == 2) {
@@ -1147,12 +1153,25 @@ __device__ __forceinline__ void blend_body(const DevPlan* __restrict__ P, const 
     // 8 copies of the histogram (lane & 7): neighbouring pixels often share a
     // value, and same-address LDS atomics from one instruction serialise
     __shared__ uint32_t s_hist[8][3 * 256];
+    // per-camera constants of the frame, indexed by each lane's own camera
+    __shared__ float s_hinv[MAXC][9], s_M[MAXC][9];
+    __shared__ int s_cw[MAXC], s_ch[MAXC], s_cp[MAXC];
+    __shared__ const uint8_t* s_fr[MAXC];
     const int tid = threadIdx.x;
     for (int i = tid; i < 8 * 3 * 256; i += BL_THREADS) (&s_hist[0][0])[i] = 0;
+    for (int i = tid; i < P->n_cams * 9; i += BL_THREADS) {
+        (&s_hinv[0][0])[i] = (&P->hinv[0][0])[i];
+        (&s_M[0][0])[i] = (&P->res->Mk[0][0])[i];
+    }
+    if (tid < P->n_cams) {
+        s_cw[tid] = P->cam_w[tid];
+        s_ch[tid] = P->cam_h[tid];
+        s_cp[tid] = P->cam_pitch[tid];
+        s_fr[tid] = P->frame[tid];
+    }
     __syncthreads();
     uint32_t* const my_hist = s_hist[tid & 7];
     const int bx = bid % P->blend_tx, by = bid / P->blend_tx;
-    const unsigned long long cand = P->cand[by * P->blend_tx + bx];
     const int W = P->canvas_w, H = P->canvas_h, Wp = P->Wp;
     const int xq = bx * BL_TX + (tid & 63) * 4;
     const bool vec = (W & 3) == 0;
@@ -1164,28 +1183,27 @@ __device__ __forceinline__ void blend_body(const DevPlan* __restrict__ P, const 
         for (int q = 0; q < 4; ++q) {
             const int x = xq + q;
             uint32_t o0 = 0, o1 = 0, o2 = 0;
-            if (x < W && cand) {
-                int nh = 0, hc[2] = {0, 0}, hm[2] = {0, 0};
+            const uint32_t code = x < W ? P->pix_code[(size_t)y * W + x] : 0u;
+            const int nh = (int)(code >> 12);
+            if (nh > 0) {
+                // the covering (camera, shift) candidates found at plan time, in
+                // the coverage scan's order; their positions are evaluated again
+                int hc[2] = {0, 0}, hm[2] = {0, 0};
                 float hu[2] = {0, 0}, hv[2] = {0, 0};
-                for (unsigned long long m = cand; m; m &= m - 1) {
-                    const int bit = __ffsll((long long)m) - 1;
+#pragma unroll
+                for (int e = 0; e < 2; ++e) {
+                    if (e >= nh) break;
+                    const int bit = (int)((code >> (6 * e)) & 63u);   // 3 camera + shift + 1
                     const int k = bit / 3, sh = bit % 3 - 1;
-                    float u, v;
-                    if (hom(P->hinv[k], (float)(x + sh * Wp), (float)y, P->cam_w[k], P->cam_h[k], u, v)) {
-                        if (nh < 2) {
-                            hc[nh] = k;
-                            hm[nh] = sh;
-                            hu[nh] = u;
-                            hv[nh] = v;
-                        }
-                        ++nh;
-                    }
+                    hc[e] = k;
+                    hm[e] = sh;
+                    hom(s_hinv[k], (float)(x + sh * Wp), (float)y, s_cw[k], s_ch[k], hu[e], hv[e]);
                 }
                 if (nh == 1) {
                     const int k = hc[0];
                     float s[3];
-                    bilin3(P->frame[k], P->cam_pitch[k], P->cam_w[k], P->cam_h[k], hu[0], hv[0], s);
-                    const float* M = P->res->Mk[k];
+                    bilin3(s_fr[k], s_cp[k], s_cw[k], s_ch[k], hu[0], hv[0], s);
+                    const float* M = s_M[k];
                     o0 = round8(capply(s, M, 0));
                     o1 = round8(capply(s, M, 1));
                     o2 = round8(capply(s, M, 2));
@@ -1194,8 +1212,8 @@ __device__ __forceinline__ void blend_body(const DevPlan* __restrict__ P, const 
                     const int ji = hc[0] == P->pj[p] ? 0 : 1;
                     const int kj = hc[ji], ki = hc[1 - ji];
                     const int mj = hm[ji], mi = hm[1 - ji];
-                    float dj = fminf(hu[ji], (float)(P->cam_w[kj] - 1) - hu[ji]);
-                    float di = fminf(hu[1 - ji], (float)(P->cam_w[ki] - 1) - hu[1 - ji]);
+                    float dj = fminf(hu[ji], (float)(s_cw[kj] - 1) - hu[ji]);
+                    float di = fminf(hu[1 - ji], (float)(s_cw[ki] - 1) - hu[1 - ji]);
                     if (dj < 0.0f) dj = 0.0f;
                     if (di < 0.0f) di = 0.0f;
                     const float sum = di + dj;
@@ -1210,12 +1228,12 @@ __device__ __forceinline__ void blend_body(const DevPlan* __restrict__ P, const 
                     const float Xj = __builtin_fmaf(thi, fji.x, (float)(x + mj * Wp));
                     const float Yj = __builtin_fmaf(thi, fji.y, (float)y);
                     float u, v, si[3], sj[3];
-                    hom(P->hinv[ki], Xi, Yi, P->cam_w[ki], P->cam_h[ki], u, v);
-                    bilin3(P->frame[ki], P->cam_pitch[ki], P->cam_w[ki], P->cam_h[ki], u, v, si);
-                    hom(P->hinv[kj], Xj, Yj, P->cam_w[kj], P->cam_h[kj], u, v);
-                    bilin3(P->frame[kj], P->cam_pitch[kj], P->cam_w[kj], P->cam_h[kj], u, v, sj);
-                    const float* Mi = P->res->Mk[ki];
-                    const float* Mj = P->res->Mk[kj];
+                    hom(s_hinv[ki], Xi, Yi, s_cw[ki], s_ch[ki], u, v);
+                    bilin3(s_fr[ki], s_cp[ki], s_cw[ki], s_ch[ki], u, v, si);
+                    hom(s_hinv[kj], Xj, Yj, s_cw[kj], s_ch[kj], u, v);
+                    bilin3(s_fr[kj], s_cp[kj], s_cw[kj], s_ch[kj], u, v, sj);
+                    const float* Mi = s_M[ki];
+                    const float* Mj = s_M[kj];
                     float ti, tj;
                     ti = capply(si, Mi, 0);
                     tj = capply(sj, Mj, 0);

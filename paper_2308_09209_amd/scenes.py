@@ -29,8 +29,14 @@ in for it, with the shapes of the workloads the stitcher is measured on):
   U[0.8, 1.2], off-diagonal U[-0.05, 0.05], gamma_k U[0.9, 1.1]; the exposure
   gain g_k starts at 1 and, for drifting scenes, takes a Gaussian random-walk
   step of sigma 0.01 per frame.  Stored as uint8 = floor(255 c + 0.5).
+* Moving occluders (optional): flat-coloured ellipses in canvas space
+  (semi-axes U[0.02, 0.06] * H, colour U[0, 1]^3) drawn over the texture until
+  they cover the given fraction of the canvas, each translating at U[2, 10]
+  px per frame in a direction U[0, 2 pi) (wrapping around the canvas); every
+  camera sees them where it sees the canvas point, so overlapping views agree.
 * Seeds: seed = 1000 * config + 10 * stream + camera (camera-level draws);
-  the texture uses seed = 1000 * config + 10 * stream + 9.
+  the texture uses seed = 1000 * config + 10 * stream + 9, the occluders
+  1000 * config + 10 * stream + 8.
 """
 from __future__ import annotations
 
@@ -47,6 +53,8 @@ WORKLOADS = {
                             tex_w=1200, tex_h=400, frames=8, drift=0.0, resid=3.0),
     "4x1920x1080_ring": dict(config=2, n_cams=4, W=1920, H=1080, overlap=0.20, ring=True,
                              tex_w=None, tex_h=1200, frames=60, drift=0.01, resid=3.0),
+    "8x3840x2160_ring": dict(config=5, n_cams=8, W=3840, H=2160, overlap=0.20, ring=True,
+                             tex_w=None, tex_h=2400, frames=30, drift=0.01, resid=3.0, occluders=0.05),
 }
 
 
@@ -136,7 +144,7 @@ class Scene:
     def __init__(self, n_cams: int, W: int, H: int, overlap: float, ring: bool,
                  tex_h: int, tex_w: int | None = None, drift: float = 0.0,
                  resid: float = 3.0, config: int = 0, stream: int = 0,
-                 perturb: bool = True, colour: bool = True):
+                 perturb: bool = True, colour: bool = True, occluders: float = 0.0):
         self.n_cams, self.W, self.H, self.ring = n_cams, W, H, ring
         self.step = int(round(W * (1.0 - overlap)))
         if ring:
@@ -186,6 +194,18 @@ class Scene:
             cam._rng = rng  # drift draws continue this camera's stream
             self.cams.append(cam)
         self._base_rgb: list[np.ndarray | None] = [None] * n_cams
+        # moving occluders: (cx, cy, a, b, vx, vy, colour) in canvas pixels
+        self.occ = []
+        if occluders > 0:
+            orng = np.random.default_rng(base + 8)
+            area, covered = occluders * self.canvas_w * self.canvas_h, 0.0
+            while covered < area:
+                a, b = orng.uniform(0.02, 0.06, 2) * H
+                cxo, cyo = orng.uniform(0.0, self.canvas_w), orng.uniform(0.0, H)
+                speed, ang = orng.uniform(2.0, 10.0), orng.uniform(0.0, 2.0 * math.pi)
+                col = orng.uniform(0.0, 1.0, 3)
+                self.occ.append((cxo, cyo, a, b, speed * math.cos(ang), speed * math.sin(ang), col))
+                covered += math.pi * a * b
 
     # --- what the stitcher is told ---------------------------------------
     def rig(self) -> dict:
@@ -223,9 +243,43 @@ class Scene:
             cam.gains.append(cam.gains[-1] + step)
         return cam.gains[t]
 
+    def _paint_occluders(self, k: int, t: int, rgb: np.ndarray) -> None:
+        """draw frame t's occluders into camera k's linear RGB image"""
+        h = self.cams[k].H_true
+        hinv = np.linalg.inv(h)
+        d = self.cams[k].resid
+        m = 4.0   # margin for the residual displacement (<= 3 px)
+        for (cx0, cy0, a, b, vx, vy, col) in self.occ:
+            cy = np.mod(cy0 + vy * t, self.canvas_h)
+            cx = np.mod(cx0 + vx * t, self.canvas_w)
+            for sh in (-self.canvas_w, 0.0, self.canvas_w):   # occluders wrap around the canvas
+                ex = cx + sh
+                cx_c = np.array([ex - a - m, ex + a + m, ex - a - m, ex + a + m])
+                cy_c = np.array([cy - b - m, cy - b - m, cy + b + m, cy + b + m])
+                w = hinv[2, 0] * cx_c + hinv[2, 1] * cy_c + hinv[2, 2]
+                if np.any(w <= 0):
+                    continue
+                u = (hinv[0, 0] * cx_c + hinv[0, 1] * cy_c + hinv[0, 2]) / w
+                v = (hinv[1, 0] * cx_c + hinv[1, 1] * cy_c + hinv[1, 2]) / w
+                u0, u1 = max(0, int(np.floor(u.min())) - 2), min(self.W - 1, int(np.ceil(u.max())) + 2)
+                v0, v1 = max(0, int(np.floor(v.min())) - 2), min(self.H - 1, int(np.ceil(v.max())) + 2)
+                if u0 > u1 or v0 > v1:
+                    continue
+                U, V = np.meshgrid(np.arange(u0, u1 + 1, dtype=np.float64), np.arange(v0, v1 + 1, dtype=np.float64))
+                ww = h[2, 0] * U + h[2, 1] * V + h[2, 2]
+                X = (h[0, 0] * U + h[0, 1] * V + h[0, 2]) / ww + d[v0:v1 + 1, u0:u1 + 1, 0]
+                Y = (h[1, 0] * U + h[1, 1] * V + h[1, 2]) / ww + d[v0:v1 + 1, u0:u1 + 1, 1]
+                inside = ((X - ex) / a) ** 2 + ((Y - cy) / b) ** 2 <= 1.0
+                if inside.any():
+                    sub_img = rgb[v0:v1 + 1, u0:u1 + 1]
+                    sub_img[inside] = col
+
     def frame(self, k: int, t: int) -> np.ndarray:
         cam = self.cams[k]
         rgb = self.base_rgb(k)
+        if self.occ:
+            rgb = rgb.copy()
+            self._paint_occluders(k, t, rgb)
         c = np.clip(self.gain(k, t) * (rgb @ cam.C.T), 0.0, 1.0) ** cam.gamma
         return np.floor(255.0 * c + 0.5).astype(np.uint8)
 
@@ -259,7 +313,8 @@ def scene_for(workload: str, stream: int = 0, **over) -> Scene:
     return Scene(n_cams=p["n_cams"], W=p["W"], H=p["H"], overlap=p["overlap"], ring=p["ring"],
                  tex_h=p["tex_h"], tex_w=p["tex_w"], drift=p["drift"], resid=p["resid"],
                  config=p["config"], stream=stream,
-                 perturb=p.get("perturb", True), colour=p.get("colour", True))
+                 perturb=p.get("perturb", True), colour=p.get("colour", True),
+                 occluders=p.get("occluders", 0.0))
 
 
 def small_scene(n_cams=2, W=96, H=64, overlap=0.35, ring=False, seed_config=90, **kw) -> Scene:
