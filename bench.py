@@ -59,7 +59,7 @@ def load_pmc(kernel, workload):
     if not os.path.exists(path):
         return None
     rec = json.load(open(path))
-    src = open(os.path.join(ROOT, "paper_2308_09209_amd", "csrc", "vs_kernels.hip"), "rb").read()
+    src = open(os.path.join(ROOT, "paper_2308_09209_amd", "csrc", "vs_flow.hip"), "rb").read()
     if rec.get("kernels_sha256") != hashlib.sha256(src).hexdigest():
         return None
     return rec.get("bytes_per_launch")
@@ -188,6 +188,7 @@ def main():
     host_frames = []
     for t in range(seq):
         host_frames.append(scene.frames(t))
+        print(f"# frame {t} generated ({time.perf_counter() - t_gen:.1f} s)", file=sys.stderr, flush=True)
     print(f"# generated {seq} frames in {time.perf_counter() - t_gen:.1f} s", file=sys.stderr, flush=True)
     dev = torch.device("cuda:0")
     frames = [[torch.from_numpy(f).to(dev) for f in fr] for fr in host_frames]
@@ -308,7 +309,10 @@ def bench_batch(args):
     scenes = [scene_for(args.workload)] if args.workload else batch_scenes()
     seq = max(1, args.seq)
     dev = torch.device("cuda:0")
-    frames = [[[torch.from_numpy(f).to(dev) for f in sc.frames(t)] for sc in scenes] for t in range(seq)]
+    frames = []
+    for t in range(seq):
+        frames.append([[torch.from_numpy(f).to(dev) for f in sc.frames(t)] for sc in scenes])
+        print(f"# frame {t} generated ({time.perf_counter() - t_gen:.1f} s)", file=sys.stderr, flush=True)
     print(f"# generated {seq} frames of {len(scenes)} streams in {time.perf_counter() - t_gen:.1f} s",
           file=sys.stderr, flush=True)
     sts = [V.Stitcher(sc.rig()) for sc in scenes]

@@ -147,7 +147,8 @@ vs_status vs_default_params(vs_params* p);
 
 /* Host-only helper (no device work): the camera-to-canvas homographies
  * H_k = H_ref H_pair[1] ... H_pair[k] in FP64 and their canvas-to-camera
- * inverses (adjugate scaled so its last entry is 1) rounded to FP32, exactly
+ * inverses (a positive multiple of H_k^-1: the adjugate over |adjugate[8]|
+ * with the sign of det, so its last entry is +1 or -1) rounded to FP32, exactly
  * as vs_create computes them.  Hk and Hinv hold n_cams x 9 entries. */
 vs_status vs_compose_homographies(const vs_rig* rig, double* Hk, float* Hinv);
 

@@ -172,7 +172,11 @@ static int hom_inverse(const double a[9], double inv[9])
     adj[8] = a[0] * a[4] - a[1] * a[3];
     double det = (a[0] * adj[0] + a[1] * adj[3]) + a[2] * adj[6];
     if (!isfinite(det) || det == 0.0 || adj[8] == 0.0 || !isfinite(adj[8])) return -1;
-    for (int i = 0; i < 9; ++i) inv[i] = adj[i] / adj[8];
+    /* a positive multiple of H^-1 (so that w > 0 keeps meaning "in front of
+     * the camera") whose last entry is +-1: the adjugate over |adj[8]| with the
+     * sign of det */
+    const double den = ((det > 0.0) == (adj[8] > 0.0)) ? adj[8] : -adj[8];
+    for (int i = 0; i < 9; ++i) inv[i] = adj[i] / den;
     return 0;
 }
 

@@ -57,7 +57,9 @@ void mat3_mul(const double* a, const double* b, double* c)
     std::memcpy(c, t, sizeof t);
 }
 
-// inverse = adjugate / adjugate[8] (last entry exactly 1)
+// inverse = a positive multiple of H^-1 (w > 0 keeps meaning "in front of
+// the camera"): the adjugate over |adjugate[8]| with the sign of det, so the
+// last entry is exactly +1 or -1
 bool hom_inverse(const double* a, double* inv)
 {
     double adj[9];
@@ -72,7 +74,8 @@ bool hom_inverse(const double* a, double* inv)
     adj[8] = a[0] * a[4] - a[1] * a[3];
     const double det = (a[0] * adj[0] + a[1] * adj[3]) + a[2] * adj[6];
     if (!std::isfinite(det) || det == 0.0 || adj[8] == 0.0 || !std::isfinite(adj[8])) return false;
-    for (int i = 0; i < 9; ++i) inv[i] = adj[i] / adj[8];
+    const double den = ((det > 0.0) == (adj[8] > 0.0)) ? adj[8] : -adj[8];
+    for (int i = 0; i < 9; ++i) inv[i] = adj[i] / den;
     return true;
 }
 

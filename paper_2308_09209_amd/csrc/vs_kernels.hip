@@ -9,91 +9,9 @@
 // are exact integers (order-independent atomics).
 #include <algorithm>
 
-#include "vs_internal.h"
+#include "vs_device.h"
 
 namespace vs {
-
-// ---------------------------------------------------------------------------
-// Conventions (section 3.1 pre-warp; section 2.1 eq. (4) colour application)
-// ---------------------------------------------------------------------------
-
-__device__ __forceinline__ float clampf(float v, float lo, float hi)
-{
-    return v < lo ? lo : (v > hi ? hi : v);
-}
-
-// round half up to a byte
-__device__ __forceinline__ uint32_t round8(float r)
-{
-    float f = floorf(r + 0.5f);
-    f = f < 0.0f ? 0.0f : f;
-    f = f > 255.0f ? 255.0f : f;
-    return (uint32_t)(int)f;
-}
-
-// canvas -> camera homography; valid iff w > 0 and inside [0, W-1] x [0, H-1];
-// position (0, 0) when w <= 0
-__device__ __forceinline__ bool hom(const float* __restrict__ h, float x, float y, int W, int H,
-                                    float& u, float& v)
-{
-    float nu = __builtin_fmaf(h[0], x, __builtin_fmaf(h[1], y, h[2]));
-    float nv = __builtin_fmaf(h[3], x, __builtin_fmaf(h[4], y, h[5]));
-    float w = __builtin_fmaf(h[6], x, __builtin_fmaf(h[7], y, h[8]));
-    if (!(w > 0.0f)) {
-        u = 0.0f;
-        v = 0.0f;
-        return false;
-    }
-    u = nu / w;
-    v = nv / w;
-    return (u >= 0.0f) && (u <= (float)(W - 1)) && (v >= 0.0f) && (v <= (float)(H - 1));
-}
-
-// bilinear resample of an HWC RGB byte image, position clamped into the image
-__device__ __forceinline__ void bilin3(const uint8_t* __restrict__ F, int pitch, int W, int H,
-                                       float u, float v, float out[3])
-{
-    float uc = clampf(u, 0.0f, (float)(W - 1));
-    float vc = clampf(v, 0.0f, (float)(H - 1));
-    float flx = floorf(uc), fly = floorf(vc);
-    int x0 = (int)flx, y0 = (int)fly;
-    float fx = uc - flx, fy = vc - fly;
-    int x1 = x0 + 1 < W ? x0 + 1 : W - 1;
-    int y1 = y0 + 1 < H ? y0 + 1 : H - 1;
-    const uint8_t* r0 = F + (size_t)y0 * pitch;
-    const uint8_t* r1 = F + (size_t)y1 * pitch;
-#pragma unroll
-    for (int c = 0; c < 3; ++c) {
-        float p00 = (float)r0[x0 * 3 + c];
-        float p10 = (float)r0[x1 * 3 + c];
-        float p01 = (float)r1[x0 * 3 + c];
-        float p11 = (float)r1[x1 * 3 + c];
-        float a = __builtin_fmaf(fx, p10 - p00, p00);
-        float b = __builtin_fmaf(fx, p11 - p01, p01);
-        out[c] = __builtin_fmaf(fy, b - a, a);
-    }
-}
-
-// t_c = s . M[:, c] (row-vector convention), clamped to [0, 255]
-__device__ __forceinline__ float capply(const float s[3], const float* __restrict__ M, int c)
-{
-    float t = __builtin_fmaf(s[0], M[c], __builtin_fmaf(s[1], M[3 + c], s[2] * M[6 + c]));
-    return clampf(t, 0.0f, 255.0f);
-}
-
-__device__ __forceinline__ int batch_block(const Batch& B, int b, int& c)
-{
-    c = 0;
-    while (c + 1 < B.n && b >= B.off[c + 1]) ++c;
-    return b - B.off[c];
-}
-
-__device__ __forceinline__ uint32_t wave_sum(uint32_t v)
-{
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-    return v;
-}
 
 // ---------------------------------------------------------------------------
 // Plan: coverage of every canvas pixel (section 2.1 step 1, section 3)
@@ -228,12 +146,6 @@ __global__ void k_set_io(const FrameIO io)
 // the exact moment A = sum p p^T of camera i's overlap pixels
 // ---------------------------------------------------------------------------
 
-__device__ __forceinline__ int find_field(const int32_t* off, int n, int b)
-{
-    int f = 0;
-    while (f + 1 < n && b >= off[f + 1]) ++f;
-    return f;
-}
 
 __device__ __forceinline__ void strips_body(const DevPlan* __restrict__ P, const int bid)
 {
@@ -580,7 +492,6 @@ __global__ __launch_bounds__(256) void k_pyr0(const Batch B)
 }
 
 
-__device__ __forceinline__ int clampi(int v, int lo, int hi) { return v < lo ? lo : (v > hi ? hi : v); }
 
 // level l -> l + 1: separable [1 4 6 4 1] / 16, horizontal first, clamped,
 // even positions; each pass ((((a0 + 4 a1) + 6 a2) + 4 a3) + a4) / 16
@@ -624,522 +535,6 @@ __global__ __launch_bounds__(256) void k_pyr_down(const Batch B, int l)
     int c;
     const int b = batch_block(B, blockIdx.x, c);
     pyr_down_body(B.plan[c], b, l);
-}
-
-
-// ---------------------------------------------------------------------------
-// Section 3.2 dense flow: pyramidal Lucas-Kanade at one level, every field
-// (pair x direction), 16 x 16 pixels per block.  The template, its gradients
-// and the moving image (with a halo for windows and displacements up to
-// LK_D px) are staged in LDS with clamp-replicated borders; a pixel whose
-// displacement leaves the staged tile reads the same clamped values from
-// global memory instead.
-// ---------------------------------------------------------------------------
-
-constexpr int LK_HT = LK_R_MAX + 1;              // template halo (window + gradient)
-constexpr int LK_TW = LK_T + 2 * LK_HT;          // 26
-constexpr int LK_GW = LK_T + 2 * LK_R_MAX;       // 24
-constexpr int LK_HM = LK_R_MAX + LK_D + 1;       // 13
-constexpr int LK_MW = LK_T + 2 * LK_HM;          // 42
-
-__device__ __forceinline__ void lk_body(const DevPlan* __restrict__ P, const int bid, int l)
-{
-    __shared__ float sT[LK_TW][LK_TW];
-    __shared__ float sIx[LK_GW][LK_GW];
-    __shared__ float sIy[LK_GW][LK_GW];
-    __shared__ float sM[LK_MW][LK_MW];
-    const int f = find_field(P->lk_off[l], 2 * P->n_pairs, bid);
-    const int p = f >> 1, dir = f & 1;
-    if (P->flow_mode != VS_FLOW_PLAIN && P->res->surr_ok[p]) return;   // the pair keeps the surrogate's flows
-    const int t = bid - P->lk_off[l][f];
-    const int w = P->lw[p][l], h = P->lh[p][l];
-    const int x0 = (t % P->lk_tx[l][f]) * LK_T, y0 = (t / P->lk_tx[l][f]) * LK_T;
-    const float* __restrict__ Tm = P->pyr[p][dir == 0 ? 0 : 1][l];
-    const float* __restrict__ Mv = P->pyr[p][dir == 0 ? 1 : 0][l];
-    const int tid = threadIdx.x;
-
-    for (int i = tid; i < LK_TW * LK_TW; i += 256) {
-        int yy = clampi(y0 - LK_HT + i / LK_TW, 0, h - 1), xx = clampi(x0 - LK_HT + i % LK_TW, 0, w - 1);
-        sT[i / LK_TW][i % LK_TW] = Tm[(size_t)yy * w + xx];
-    }
-    for (int i = tid; i < LK_MW * LK_MW; i += 256) {
-        int yy = clampi(y0 - LK_HM + i / LK_MW, 0, h - 1), xx = clampi(x0 - LK_HM + i % LK_MW, 0, w - 1);
-        sM[i / LK_MW][i % LK_MW] = Mv[(size_t)yy * w + xx];
-    }
-    __syncthreads();
-    for (int i = tid; i < LK_GW * LK_GW; i += 256) {
-        // central differences at (x0 - R + gx, y0 - R + gy); the tile is
-        // clamp-replicated, so its neighbours are the clamped neighbours
-        const int gy = i / LK_GW, gx = i % LK_GW;
-        const int cx = gx + 1, cy = gy + 1;  // position in sT
-        sIx[gy][gx] = 0.5f * (sT[cy][cx + 1] - sT[cy][cx - 1]);
-        sIy[gy][gx] = 0.5f * (sT[cy + 1][cx] - sT[cy - 1][cx]);
-    }
-    __syncthreads();
-
-    const int tx = tid & (LK_T - 1), ty = tid / LK_T;
-    const int x = x0 + tx, y = y0 + ty;
-    if (x >= w || y >= h) return;
-    if (!P->need[p][l][(size_t)y * w + x]) return;   // flow not estimated here (stays 0)
-
-    float ux = 0.0f, uy = 0.0f;
-    if (l + 1 < P->levels) {
-        const int wc = P->lw[p][l + 1], hc = P->lh[p][l + 1];
-        const float2* __restrict__ uc = P->flow[p][dir][l + 1];
-        float cx = clampf(__builtin_fmaf((float)x, 0.5f, -0.25f), 0.0f, (float)(wc - 1));
-        float cy = clampf(__builtin_fmaf((float)y, 0.5f, -0.25f), 0.0f, (float)(hc - 1));
-        float flx = floorf(cx), fly = floorf(cy);
-        int xa = (int)flx, ya = (int)fly;
-        float fx = cx - flx, fy = cy - fly;
-        int xb = xa + 1 < wc ? xa + 1 : wc - 1;
-        int yb = ya + 1 < hc ? ya + 1 : hc - 1;
-        float2 p00 = uc[(size_t)ya * wc + xa], p10 = uc[(size_t)ya * wc + xb];
-        float2 p01 = uc[(size_t)yb * wc + xa], p11 = uc[(size_t)yb * wc + xb];
-        float a = __builtin_fmaf(fx, p10.x - p00.x, p00.x);
-        float b = __builtin_fmaf(fx, p11.x - p01.x, p01.x);
-        float cxv = __builtin_fmaf(fy, b - a, a);
-        a = __builtin_fmaf(fx, p10.y - p00.y, p00.y);
-        b = __builtin_fmaf(fx, p11.y - p01.y, p01.y);
-        float cyv = __builtin_fmaf(fy, b - a, a);
-        ux = 2.0f * cxv;
-        uy = 2.0f * cyv;
-    }
-    const int r = P->lk_radius;
-    const int wx0 = x - r < 0 ? 0 : x - r, wx1 = x + r > w - 1 ? w - 1 : x + r;
-    const int wy0 = y - r < 0 ? 0 : y - r, wy1 = y + r > h - 1 ? h - 1 : y + r;
-    float g00 = 0.0f, g01 = 0.0f, g11 = 0.0f;
-    for (int yy = wy0; yy <= wy1; ++yy)
-        for (int xx = wx0; xx <= wx1; ++xx) {
-            float ix = sIx[yy - y0 + LK_R_MAX][xx - x0 + LK_R_MAX];
-            float iy = sIy[yy - y0 + LK_R_MAX][xx - x0 + LK_R_MAX];
-            g00 = __builtin_fmaf(ix, ix, g00);
-            g01 = __builtin_fmaf(ix, iy, g01);
-            g11 = __builtin_fmaf(iy, iy, g11);
-        }
-    const float reg = P->lk_lambda * (float)((wy1 - wy0 + 1) * (wx1 - wx0 + 1));
-    g00 = g00 + reg;
-    g11 = g11 + reg;
-    const float det = g00 * g11 - g01 * g01;
-    const int iters = P->lk_iters;
-    for (int it = 0; it < iters; ++it) {
-        const float flx = floorf(ux), fly = floorf(uy);
-        const int ox = (int)flx, oy = (int)fly;
-        const float fx = ux - flx, fy = uy - fly;
-        float bu = 0.0f, bv = 0.0f;
-        const bool fast = ox >= -(LK_D + 1) && ox <= LK_D && oy >= -(LK_D + 1) && oy <= LK_D;
-        if (fast) {
-            for (int yy = wy0; yy <= wy1; ++yy) {
-                const float* m0 = sM[yy + oy - y0 + LK_HM];
-                const float* m1 = sM[yy + oy + 1 - y0 + LK_HM];
-                const float* tr = sT[yy - y0 + LK_HT];
-                const float* gxr = sIx[yy - y0 + LK_R_MAX];
-                const float* gyr = sIy[yy - y0 + LK_R_MAX];
-                for (int xx = wx0; xx <= wx1; ++xx) {
-                    const int cx = xx + ox - x0 + LK_HM;
-                    float p00 = m0[cx], p10 = m0[cx + 1], p01 = m1[cx], p11 = m1[cx + 1];
-                    float a = __builtin_fmaf(fx, p10 - p00, p00);
-                    float b = __builtin_fmaf(fx, p11 - p01, p01);
-                    float m = __builtin_fmaf(fy, b - a, a);
-                    float e = m - tr[xx - x0 + LK_HT];
-                    bu = __builtin_fmaf(gxr[xx - x0 + LK_R_MAX], e, bu);
-                    bv = __builtin_fmaf(gyr[xx - x0 + LK_R_MAX], e, bv);
-                }
-            }
-        } else {
-            for (int yy = wy0; yy <= wy1; ++yy) {
-                const float* m0 = Mv + (size_t)clampi(yy + oy, 0, h - 1) * w;
-                const float* m1 = Mv + (size_t)clampi(yy + oy + 1, 0, h - 1) * w;
-                for (int xx = wx0; xx <= wx1; ++xx) {
-                    const int xa = clampi(xx + ox, 0, w - 1), xb = clampi(xx + ox + 1, 0, w - 1);
-                    float p00 = m0[xa], p10 = m0[xb], p01 = m1[xa], p11 = m1[xb];
-                    float a = __builtin_fmaf(fx, p10 - p00, p00);
-                    float b = __builtin_fmaf(fx, p11 - p01, p01);
-                    float m = __builtin_fmaf(fy, b - a, a);
-                    float e = m - sT[yy - y0 + LK_HT][xx - x0 + LK_HT];
-                    bu = __builtin_fmaf(sIx[yy - y0 + LK_R_MAX][xx - x0 + LK_R_MAX], e, bu);
-                    bv = __builtin_fmaf(sIy[yy - y0 + LK_R_MAX][xx - x0 + LK_R_MAX], e, bv);
-                }
-            }
-        }
-        const float du = (g01 * bv - g11 * bu) / det;
-        const float dv = (g01 * bu - g00 * bv) / det;
-        ux = ux + du;
-        uy = uy + dv;
-    }
-    P->flow[p][dir][l][(size_t)y * w + x] = make_float2(ux, uy);
-}
-
-__global__ __launch_bounds__(256) void k_lk(const Batch B, int l)
-{
-    int c;
-    const int b = batch_block(B, blockIdx.x, c);
-    lk_body(B.plan[c], b, l);
-}
-
-// 9x9-window form of the same estimator (radius 4), P vertically adjacent
-// pixels per thread, a 64 x 4P block tile.  Identical arithmetic in identical
-// order; what changes is data movement:
-//  - (T, Ix, Iy) of every window position sit in one float4 in LDS, with
-//    Ix = Iy = 0 outside the level, so a clipped window needs no predicate:
-//    such a tap adds fma(0, e, acc) = acc exactly (acc is never -0);
-//  - the P pixels of a thread share each (T, Ix, Iy) row they have in common;
-//  - per pixel the horizontally interpolated moving-image rows slide down the
-//    window in registers: the bottom row of window row r is the top row of
-//    window row r + 1, so each tap costs ~1.1 moving-image LDS reads.
-template <int P>
-__device__ __forceinline__ void lk_w9_body(const DevPlan* __restrict__ Pl, const int bid, int l)
-{
-    constexpr int R = LK_R_MAX, NW = 2 * R + 1;
-    constexpr int TX = LKW_TX, TY = 4 * P;
-    constexpr int TIW = TX + 2 * R, TIH = TY + 2 * R;       // (T, Ix, Iy) window positions
-    constexpr int TSW = TIW + 2, TSH = TIH + 2;             // template + gradient halo
-    constexpr int HM = R + LK_D + 1;                        // moving-image halo
-    constexpr int MW = TX + 2 * HM, MH = TY + 2 * HM;
-    __shared__ float4 sTI[TIH * TIW];
-    __shared__ float sT[TSH * TSW];
-    __shared__ float sM[MH * MW];
-
-    const int f = find_field(Pl->lk_off[l], 2 * Pl->n_pairs, bid);
-    const int p = f >> 1, dir = f & 1;
-    if (Pl->flow_mode != VS_FLOW_PLAIN && Pl->res->surr_ok[p]) return;   // the pair keeps the surrogate's flows
-    const int t = bid - Pl->lk_off[l][f];
-    const int w = Pl->lw[p][l], h = Pl->lh[p][l];
-    const int x0 = (t % Pl->lk_tx[l][f]) * TX, y0 = (t / Pl->lk_tx[l][f]) * TY;
-    const float* __restrict__ Tm = Pl->pyr[p][dir == 0 ? 0 : 1][l];
-    const float* __restrict__ Mv = Pl->pyr[p][dir == 0 ? 1 : 0][l];
-    const int tid = threadIdx.x;
-
-    for (int i = tid; i < TSH * TSW; i += 256) {
-        const int yy = clampi(y0 - R - 1 + i / TSW, 0, h - 1), xx = clampi(x0 - R - 1 + i % TSW, 0, w - 1);
-        sT[i] = Tm[(size_t)yy * w + xx];
-    }
-    for (int i = tid; i < MH * MW; i += 256) {
-        const int yy = clampi(y0 - HM + i / MW, 0, h - 1), xx = clampi(x0 - HM + i % MW, 0, w - 1);
-        sM[i] = Mv[(size_t)yy * w + xx];
-    }
-    __syncthreads();
-    for (int i = tid; i < TIH * TIW; i += 256) {
-        const int gy = i / TIW, gx = i % TIW;
-        const int X = x0 - R + gx, Y = y0 - R + gy;
-        const int c = (gy + 1) * TSW + gx + 1;
-        const bool in = X >= 0 && X < w && Y >= 0 && Y < h;
-        const float ix = in ? 0.5f * (sT[c + 1] - sT[c - 1]) : 0.0f;
-        const float iy = in ? 0.5f * (sT[c + TSW] - sT[c - TSW]) : 0.0f;
-        sTI[i] = make_float4(sT[c], ix, iy, 0.0f);
-    }
-    __syncthreads();
-
-    const int lane = tid & 63, wv = tid >> 6;
-    const int x = x0 + lane;
-    const int yb = y0 + wv * P;
-    const bool has_coarse = l + 1 < Pl->levels;
-    const int ncx = min(x + R, w - 1) - max(x - R, 0) + 1;
-    const uint8_t* __restrict__ need = Pl->need[p][l];
-    float ux[P], uy[P], g00[P], g01[P], g11[P], det[P];
-    bool act[P];
-#pragma unroll
-    for (int q = 0; q < P; ++q) {
-        const int y = yb + q;
-        act[q] = x < w && y < h && need[(size_t)y * w + x] != 0;
-        ux[q] = 0.0f;
-        uy[q] = 0.0f;
-        if (has_coarse && act[q]) {
-            const int wc = Pl->lw[p][l + 1], hc = Pl->lh[p][l + 1];
-            const float2* __restrict__ uc = Pl->flow[p][dir][l + 1];
-            const float cx = clampf(__builtin_fmaf((float)x, 0.5f, -0.25f), 0.0f, (float)(wc - 1));
-            const float cy = clampf(__builtin_fmaf((float)y, 0.5f, -0.25f), 0.0f, (float)(hc - 1));
-            const float flx = floorf(cx), fly = floorf(cy);
-            const int xa = (int)flx, ya = (int)fly;
-            const float fx = cx - flx, fy = cy - fly;
-            const int xb = xa + 1 < wc ? xa + 1 : wc - 1;
-            const int ybb = ya + 1 < hc ? ya + 1 : hc - 1;
-            const float2 p00 = uc[(size_t)ya * wc + xa], p10 = uc[(size_t)ya * wc + xb];
-            const float2 p01 = uc[(size_t)ybb * wc + xa], p11 = uc[(size_t)ybb * wc + xb];
-            float a = __builtin_fmaf(fx, p10.x - p00.x, p00.x);
-            float b = __builtin_fmaf(fx, p11.x - p01.x, p01.x);
-            ux[q] = 2.0f * __builtin_fmaf(fy, b - a, a);
-            a = __builtin_fmaf(fx, p10.y - p00.y, p00.y);
-            b = __builtin_fmaf(fx, p11.y - p01.y, p01.y);
-            uy[q] = 2.0f * __builtin_fmaf(fy, b - a, a);
-        }
-        g00[q] = 0.0f;
-        g01[q] = 0.0f;
-        g11[q] = 0.0f;
-    }
-    // normal matrix: rows shared by the P pixels, row-major within each window
-#pragma unroll 1
-    for (int j = 0; j < P + 2 * R; ++j) {
-        float4 ti[NW];
-#pragma unroll
-        for (int c = 0; c < NW; ++c) ti[c] = sTI[(wv * P + j) * TIW + lane + c];
-#pragma unroll
-        for (int q = 0; q < P; ++q) {
-            if (j - q < 0 || j - q > 2 * R) continue;
-#pragma unroll
-            for (int c = 0; c < NW; ++c) {
-                g00[q] = __builtin_fmaf(ti[c].y, ti[c].y, g00[q]);
-                g01[q] = __builtin_fmaf(ti[c].y, ti[c].z, g01[q]);
-                g11[q] = __builtin_fmaf(ti[c].z, ti[c].z, g11[q]);
-            }
-        }
-    }
-#pragma unroll
-    for (int q = 0; q < P; ++q) {
-        const int y = yb + q;
-        const int ncy = min(y + R, h - 1) - max(y - R, 0) + 1;
-        const float reg = act[q] ? Pl->lk_lambda * (float)(ncy * ncx) : 1.0f;
-        g00[q] = g00[q] + reg;
-        g11[q] = g11[q] + reg;
-        det[q] = g00[q] * g11[q] - g01[q] * g01[q];
-    }
-    const int iters = Pl->lk_iters;
-    for (int it = 0; it < iters; ++it) {
-        float fx[P], fy[P], bu[P], bv[P];
-        int mb[P];
-#pragma unroll
-        for (int q = 0; q < P; ++q) {
-            const float flx = floorf(ux[q]), fly = floorf(uy[q]);
-            int ox = (int)flx, oy = (int)fly;
-            fx[q] = ux[q] - flx;
-            fy[q] = uy[q] - fly;
-            bu[q] = 0.0f;
-            bv[q] = 0.0f;
-            if (act[q] && !(ox >= -(LK_D + 1) && ox <= LK_D && oy >= -(LK_D + 1) && oy <= LK_D)) {
-                // the displacement leaves the staged tile: hand the pixel, with its
-                // state at the start of this step, to the tail kernel
-                const uint32_t slot = atomicAdd(&Pl->acc->lk_qn[l], 1u);
-                if (slot < (uint32_t)Pl->lk_qcap[l])
-                    Pl->lk_queue[l][slot] = make_uint4((uint32_t)f | ((uint32_t)it << 8),
-                                                       (uint32_t)x | ((uint32_t)(yb + q) << 16),
-                                                       __float_as_uint(ux[q]), __float_as_uint(uy[q]));
-                act[q] = false;
-            }
-            if (!act[q]) {
-                ox = 0;
-                oy = 0;
-            }
-            mb[q] = (wv * P + q - R + HM + oy) * MW + (lane - R + HM + ox);
-        }
-        float hp[P][NW];
-#pragma unroll 1
-        for (int j = 0; j < P + 2 * R; ++j) {
-            float4 ti[NW];
-#pragma unroll
-            for (int c = 0; c < NW; ++c) ti[c] = sTI[(wv * P + j) * TIW + lane + c];
-#pragma unroll
-            for (int q = 0; q < P; ++q) {
-                const int jr = j - q;
-                if (jr < 0 || jr > 2 * R) continue;
-                if (jr == 0) {
-                    const float* m0 = sM + mb[q];
-                    float v0 = m0[0];
-#pragma unroll
-                    for (int c = 0; c < NW; ++c) {
-                        const float v1 = m0[c + 1];
-                        hp[q][c] = __builtin_fmaf(fx[q], v1 - v0, v0);
-                        v0 = v1;
-                    }
-                }
-                const float* m1 = sM + mb[q] + (jr + 1) * MW;
-                float v0 = m1[0];
-#pragma unroll
-                for (int c = 0; c < NW; ++c) {
-                    const float v1 = m1[c + 1];
-                    const float hb = __builtin_fmaf(fx[q], v1 - v0, v0);
-                    v0 = v1;
-                    const float m = __builtin_fmaf(fy[q], hb - hp[q][c], hp[q][c]);
-                    const float e = m - ti[c].x;
-                    bu[q] = __builtin_fmaf(ti[c].y, e, bu[q]);
-                    bv[q] = __builtin_fmaf(ti[c].z, e, bv[q]);
-                    hp[q][c] = hb;
-                }
-            }
-        }
-#pragma unroll
-        for (int q = 0; q < P; ++q) {
-            if (!act[q]) continue;
-            const float du = (g01[q] * bv[q] - g11[q] * bu[q]) / det[q];
-            const float dv = (g01[q] * bu[q] - g00[q] * bv[q]) / det[q];
-            ux[q] = ux[q] + du;
-            uy[q] = uy[q] + dv;
-        }
-    }
-#pragma unroll
-    for (int q = 0; q < P; ++q)
-        if (act[q]) Pl->flow[p][dir][l][(size_t)(yb + q) * w + x] = make_float2(ux[q], uy[q]);
-}
-
-template <int P>
-__global__ __launch_bounds__(256) void k_lk_w9(const Batch B, int l)
-{
-    int c;
-    const int b = batch_block(B, blockIdx.x, c);
-    lk_w9_body<P>(B.plan[c], b, l);
-}
-
-// Pixels whose displacement left the staged tile finish here, one pixel per
-// lane, every tap read from global memory with clamped indices (gradients 0
-// outside the level, as in the staged kernel, so the row-major sums are the
-// same).  Each window row issues all of its loads before using them: the
-// kernel is latency-bound on about one round trip per window row.
-__global__ __launch_bounds__(256) void k_lk_tail(const Batch B, int l)
-{
-    constexpr int R = LK_R_MAX, NW = 2 * R + 1;
-    int c;
-    const int b = batch_block(B, blockIdx.x, c);
-    const int nb = B.off[c + 1] - B.off[c];          // this context's blocks
-    const DevPlan* __restrict__ Pl = B.plan[c];
-    const uint32_t n = min(Pl->acc->lk_qn[l], (uint32_t)Pl->lk_qcap[l]);
-    const int iters = Pl->lk_iters;
-    for (uint32_t i = b * 256 + threadIdx.x; i < n; i += nb * 256) {
-        const uint4 ent = Pl->lk_queue[l][i];
-        const int f = (int)(ent.x & 255u), it0 = (int)(ent.x >> 8);
-        const int x = (int)(ent.y & 0xffffu), y = (int)(ent.y >> 16);
-        float ux = __uint_as_float(ent.z), uy = __uint_as_float(ent.w);
-        const int p = f >> 1, dir = f & 1;
-        const int w = Pl->lw[p][l], h = Pl->lh[p][l];
-        const float* __restrict__ Tm = Pl->pyr[p][dir == 0 ? 0 : 1][l];
-        const float* __restrict__ Mv = Pl->pyr[p][dir == 0 ? 1 : 0][l];
-        int cxm[NW + 2];   // clamped columns x - R - 1 .. x + R + 1
-        bool cin[NW];
-#pragma unroll
-        for (int k = 0; k < NW + 2; ++k) cxm[k] = clampi(x - R - 1 + k, 0, w - 1);
-#pragma unroll
-        for (int c = 0; c < NW; ++c) cin[c] = x - R + c >= 0 && x - R + c < w;
-        float g00 = 0.0f, g01 = 0.0f, g11 = 0.0f;
-#pragma unroll
-        for (int jr = 0; jr < NW; ++jr) {
-            const int yy = y - R + jr;
-            const bool rin = yy >= 0 && yy < h;
-            const float* t0 = Tm + (size_t)clampi(yy - 1, 0, h - 1) * w;
-            const float* t1 = Tm + (size_t)clampi(yy, 0, h - 1) * w;
-            const float* t2 = Tm + (size_t)clampi(yy + 1, 0, h - 1) * w;
-            float a[NW + 2], up[NW], dn[NW];
-#pragma unroll
-            for (int k = 0; k < NW + 2; ++k) a[k] = t1[cxm[k]];
-#pragma unroll
-            for (int c = 0; c < NW; ++c) {
-                up[c] = t0[cxm[c + 1]];
-                dn[c] = t2[cxm[c + 1]];
-            }
-#pragma unroll
-            for (int c = 0; c < NW; ++c) {
-                const bool in = rin && cin[c];
-                const float ix = in ? 0.5f * (a[c + 2] - a[c]) : 0.0f;
-                const float iy = in ? 0.5f * (dn[c] - up[c]) : 0.0f;
-                g00 = __builtin_fmaf(ix, ix, g00);
-                g01 = __builtin_fmaf(ix, iy, g01);
-                g11 = __builtin_fmaf(iy, iy, g11);
-            }
-        }
-        const int ncx = min(x + R, w - 1) - max(x - R, 0) + 1;
-        const int ncy = min(y + R, h - 1) - max(y - R, 0) + 1;
-        const float reg = Pl->lk_lambda * (float)(ncy * ncx);
-        g00 = g00 + reg;
-        g11 = g11 + reg;
-        const float det = g00 * g11 - g01 * g01;
-        for (int it = it0; it < iters; ++it) {
-            const float flx = floorf(ux), fly = floorf(uy);
-            const int ox = (int)flx, oy = (int)fly;
-            const float fx = ux - flx, fy = uy - fly;
-            int mx[NW + 1];
-#pragma unroll
-            for (int k = 0; k < NW + 1; ++k) mx[k] = clampi(x - R + ox + k, 0, w - 1);
-            float bu = 0.0f, bv = 0.0f;
-#pragma unroll
-            for (int jr = 0; jr < NW; ++jr) {
-                const int yy = y - R + jr;
-                const bool rin = yy >= 0 && yy < h;
-                const float* t0 = Tm + (size_t)clampi(yy - 1, 0, h - 1) * w;
-                const float* t1 = Tm + (size_t)clampi(yy, 0, h - 1) * w;
-                const float* t2 = Tm + (size_t)clampi(yy + 1, 0, h - 1) * w;
-                const float* m0 = Mv + (size_t)clampi(yy + oy, 0, h - 1) * w;
-                const float* m1 = Mv + (size_t)clampi(yy + oy + 1, 0, h - 1) * w;
-                float a[NW + 2], up[NW], dn[NW], ra[NW + 1], rb[NW + 1];
-#pragma unroll
-                for (int k = 0; k < NW + 2; ++k) a[k] = t1[cxm[k]];
-#pragma unroll
-                for (int c = 0; c < NW; ++c) {
-                    up[c] = t0[cxm[c + 1]];
-                    dn[c] = t2[cxm[c + 1]];
-                }
-#pragma unroll
-                for (int k = 0; k < NW + 1; ++k) {
-                    ra[k] = m0[mx[k]];
-                    rb[k] = m1[mx[k]];
-                }
-#pragma unroll
-                for (int c = 0; c < NW; ++c) {
-                    const bool in = rin && cin[c];
-                    const float ix = in ? 0.5f * (a[c + 2] - a[c]) : 0.0f;
-                    const float iy = in ? 0.5f * (dn[c] - up[c]) : 0.0f;
-                    const float ta = __builtin_fmaf(fx, ra[c + 1] - ra[c], ra[c]);
-                    const float tb = __builtin_fmaf(fx, rb[c + 1] - rb[c], rb[c]);
-                    const float e = __builtin_fmaf(fy, tb - ta, ta) - a[c + 1];
-                    bu = __builtin_fmaf(ix, e, bu);
-                    bv = __builtin_fmaf(iy, e, bv);
-                }
-            }
-            const float du = (g01 * bv - g11 * bu) / det;
-            const float dv = (g01 * bu - g00 * bv) / det;
-            ux = ux + du;
-            uy = uy + dv;
-        }
-        Pl->flow[p][dir][l][(size_t)y * w + x] = make_float2(ux, uy);
-    }
-}
-
-// Static flow domain (plan time): level 0 = the overlap of the pair's cameras
-// on the strip; level l + 1 = the bilinear footprints sampled by the needed
-// pixels of level l when initialising from the coarser flow.
-__global__ __launch_bounds__(256) void k_need0(const DevPlan* __restrict__ P)
-{
-    const int tid = threadIdx.x;
-    const int p = find_field(P->strip_off, P->n_pairs, blockIdx.x);
-    const int t = blockIdx.x - P->strip_off[p];
-    const int sw = P->sw[p], sh = P->sh[p];
-    const int tx0 = (t % P->strip_tx[p]) * STRIP_TX, ty0 = (t / P->strip_tx[p]) * STRIP_TY;
-    const int kj = P->pj[p], ki = P->pi[p];
-    const int lx = tx0 + (tid & 63);
-    for (int r = tid >> 6; r < STRIP_TY; r += 4) {
-        const int ly = ty0 + r;
-        if (lx >= sw || ly >= sh) continue;
-        const int X = P->sx0[p] + lx, Y = P->sy0[p] + ly;
-        float u, v;
-        const bool okj = hom(P->hinv[kj], (float)X, (float)Y, P->cam_w[kj], P->cam_h[kj], u, v);
-        const bool oki = hom(P->hinv[ki], (float)(X - P->psi[p] * P->Wp), (float)Y, P->cam_w[ki], P->cam_h[ki], u, v);
-        P->need[p][0][(size_t)ly * sw + lx] = (okj && oki) ? 1 : 0;
-    }
-}
-
-__global__ __launch_bounds__(256) void k_need_down(const DevPlan* __restrict__ P, int p, int l)
-{
-    const int w = P->lw[p][l], h = P->lh[p][l], wc = P->lw[p][l + 1], hc = P->lh[p][l + 1];
-    const int i = blockIdx.x * 256 + threadIdx.x;
-    if (i >= w * h) return;
-    const int x = i % w, y = i / w;
-    if (!P->need[p][l][i]) return;
-    const float cx = clampf(__builtin_fmaf((float)x, 0.5f, -0.25f), 0.0f, (float)(wc - 1));
-    const float cy = clampf(__builtin_fmaf((float)y, 0.5f, -0.25f), 0.0f, (float)(hc - 1));
-    const int xa = (int)floorf(cx), ya = (int)floorf(cy);
-    const int xb = xa + 1 < wc ? xa + 1 : wc - 1;
-    const int yc = ya + 1 < hc ? ya + 1 : hc - 1;
-    uint8_t* dst = P->need[p][l + 1];
-    dst[(size_t)ya * wc + xa] = 1;
-    dst[(size_t)ya * wc + xb] = 1;
-    dst[(size_t)yc * wc + xa] = 1;
-    dst[(size_t)yc * wc + xb] = 1;
-}
-
-hipError_t launch_need(const DevPlan* dp, const DevPlan& hp, hipStream_t s)
-{
-    hipLaunchKernelGGL(k_need0, dim3(hp.strip_off[hp.n_pairs]), dim3(256), 0, s, dp);
-    for (int l = 0; l + 1 < hp.levels; ++l)
-        for (int p = 0; p < hp.n_pairs; ++p) {
-            const int n = hp.lw[p][l] * hp.lh[p][l];
-            hipLaunchKernelGGL(k_need_down, dim3((n + 255) / 256), dim3(256), 0, s, dp, p, l);
-        }
-    return hipGetLastError();
 }
 
 
@@ -1431,22 +826,6 @@ __global__ __launch_bounds__(BL_THREADS) void k_balance_apply(const Batch B)
 // Launchers: one grid over the tiles of every context of the group
 // ---------------------------------------------------------------------------
 
-namespace {
-
-template <typename F>
-bool make_batch(const Group& g, Batch& B, F blocks_of)
-{
-    B.n = g.n;
-    B.off[0] = 0;
-    for (int c = 0; c < g.n; ++c) {
-        B.plan[c] = g.dp[c];
-        B.off[c + 1] = B.off[c] + blocks_of(*g.hp[c]);
-    }
-    for (int c = g.n + 1; c <= MAXB; ++c) B.off[c] = B.off[g.n];
-    return B.off[g.n] > 0;
-}
-
-}  // namespace
 
 hipError_t launch_set_io(const FrameIO& io, int n, hipStream_t s)
 {
@@ -1514,32 +893,6 @@ hipError_t launch_pyr_down(const Group& g, int l, hipStream_t s)
     return hipGetLastError();
 }
 
-hipError_t launch_lk(const Group& g, int l, hipStream_t s)
-{
-    // every context of a group runs the same flow-kernel variant at a level
-    const int P = g.hp[0]->lk_P[l];
-    for (int c = 1; c < g.n; ++c)
-        if (g.hp[c]->lk_P[l] != P) return hipErrorInvalidValue;
-    Batch B;
-    // a context whose flows all come from the surrogate launches no flow blocks
-    auto plain = [](const DevPlan& h) { return h.use_flow && h.flow_mode != VS_FLOW_SURROGATE; };
-    if (make_batch(g, B, [&](const DevPlan& h) { return plain(h) && l < h.levels ? h.lk_off[l][2 * h.n_pairs] : 0; })) {
-        const dim3 grid(B.off[B.n]);
-        switch (P) {
-        case 4: hipLaunchKernelGGL(k_lk_w9<4>, grid, dim3(256), 0, s, B, l); break;
-        case 2: hipLaunchKernelGGL(k_lk_w9<2>, grid, dim3(256), 0, s, B, l); break;
-        case 1: hipLaunchKernelGGL(k_lk_w9<1>, grid, dim3(256), 0, s, B, l); break;
-        default: hipLaunchKernelGGL(k_lk, grid, dim3(256), 0, s, B, l); break;
-        }
-    }
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess || P == 0) return e;
-    // deferred pixels: the device-side count bounds the grid-stride loop
-    if (make_batch(g, B, [&](const DevPlan& h) {
-            return plain(h) && l < h.levels ? std::min(1024, std::max(1, (h.lk_qcap[l] + 255) / 256)) : 0; }))
-        hipLaunchKernelGGL(k_lk_tail, dim3(B.off[B.n]), dim3(256), 0, s, B, l);
-    return hipGetLastError();
-}
 
 hipError_t launch_blend(const Group& g, hipStream_t s)
 {

@@ -33,16 +33,17 @@ __device__ __forceinline__ int find_img(const ImgTable& T, int b)
 // ---------------------------------------------------------------------------
 // 3x3 convolution, zero padding, as an implicit GEMM on the matrix cores:
 // D[pixel][cout] = sum_{tap, cin} X[pixel + tap][cin] W[cout][tap][cin].
-// A block computes CONV_PX consecutive pixels of one image for every output
-// channel: each wavefront CONV_G groups of 16 pixels at once (independent
-// accumulator chains hide the matrix-core latency), the block's weights
-// staged once in LDS.  Every accumulator sums its products in (tap, cin
-// chunk) order.  MFMA 16x16x16 BF16 fragments: lane l holds
-// A[m = l % 16][k = 4 (l / 16) + i], B[k = 4 (l / 16) + i][n = l % 16] and
-// D[m = 4 (l / 16) + i][n = l % 16], i = 0..3.
+// A block computes a CONV_T x CONV_T pixel tile of one image for every output
+// channel.  The tile and its one-pixel halo are read from global memory once
+// (coalesced rows) into LDS with a padded pixel stride, the block's weights
+// are staged in LDS, and every tap reads its A fragments from LDS; each
+// wavefront computes 4 rows of 16 pixels at once (independent accumulator
+// chains).  Every accumulator sums its products in (tap, cin chunk) order.
+// MFMA 16x16x16 BF16 fragments: lane l holds A[m = l % 16][k = 4 (l / 16) + i],
+// B[k = 4 (l / 16) + i][n = l % 16] and D[m = 4 (l / 16) + i][n = l % 16].
 // ---------------------------------------------------------------------------
-constexpr int CONV_G = 4;
-constexpr int CONV_PX = 4 * 16 * CONV_G;
+constexpr int CONV_T = 16;                  // tile side (pixels)
+constexpr int CONV_H = CONV_T + 2;          // tile with halo
 
 template <int CIN, int COUT, int MODE>
 __global__ __launch_bounds__(256) void k_conv3x3(const uint16_t* __restrict__ X, const uint16_t* __restrict__ Wt,
@@ -51,68 +52,73 @@ __global__ __launch_bounds__(256) void k_conv3x3(const uint16_t* __restrict__ X,
 {
     static_assert(CIN % 16 == 0 && COUT % 16 == 0, "channels in multiples of 16");
     constexpr int NT = COUT / 16, NC = CIN / 16;
+    constexpr int PS = CIN / 4 + 2;                     // LDS pixel stride in 8-byte units (padded)
     __shared__ bf16x4 sW[COUT * 9 * CIN / 4];
+    __shared__ uint2 sX[CONV_H * CONV_H * PS];
     const int tid = threadIdx.x;
-    const bf16x4* Wv = reinterpret_cast<const bf16x4*>(Wt);
-    for (int i = tid; i < COUT * 9 * CIN / 4; i += 256) sW[i] = Wv[i];
+    const int img = find_img(T, blockIdx.x);
+    const int W = T.w[img], H = T.h[img];
+    const long base = T.pix_off[img];
+    const int ntx = (W + CONV_T - 1) / CONV_T;
+    const int t = blockIdx.x - T.tile_off[img];
+    const int x0 = (t % ntx) * CONV_T, y0 = (t / ntx) * CONV_T;
+    {
+        const bf16x4* Wv = reinterpret_cast<const bf16x4*>(Wt);
+        for (int i = tid; i < COUT * 9 * CIN / 4; i += 256) sW[i] = Wv[i];
+        // tile + halo, 8 bytes (4 channels) at a time; zeros outside the image
+        const uint2* Xv = reinterpret_cast<const uint2*>(X);
+        for (int i = tid; i < CONV_H * CONV_H * (CIN / 4); i += 256) {
+            const int px = i / (CIN / 4), ch = i % (CIN / 4);
+            const int yy = y0 - 1 + px / CONV_H, xx = x0 - 1 + px % CONV_H;
+            uint2 v = make_uint2(0u, 0u);
+            if (yy >= 0 && yy < H && xx >= 0 && xx < W) v = Xv[(base + (long)yy * W + xx) * (CIN / 4) + ch];
+            sX[px * PS + ch] = v;
+        }
+    }
     __syncthreads();
 
-    const int img = find_img(T, blockIdx.x);
-    const int W = T.w[img], H = T.h[img], npix = W * H;
-    const long base = T.pix_off[img];
     const int lane = tid & 63, wv = tid >> 6;
     const int m = lane & 15, kg = lane >> 4;
-    const int qb = (blockIdx.x - T.tile_off[img]) * CONV_PX + wv * (16 * CONV_G);
-    int py[CONV_G], px[CONV_G];
-    bool pv[CONV_G];
+    f32x4 acc[4][NT];
 #pragma unroll
-    for (int g = 0; g < CONV_G; ++g) {
-        const int q = qb + g * 16 + m;
-        pv[g] = q < npix;
-        py[g] = pv[g] ? q / W : 0;
-        px[g] = pv[g] ? q % W : 0;
-    }
-    f32x4 acc[CONV_G][NT];
+    for (int g = 0; g < 4; ++g)
 #pragma unroll
-    for (int g = 0; g < CONV_G; ++g)
-#pragma unroll
-        for (int t = 0; t < NT; ++t) acc[g][t] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+        for (int tt = 0; tt < NT; ++tt) acc[g][tt] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll
     for (int tap = 0; tap < 9; ++tap) {
-        const int dy = tap / 3 - 1, dx = tap % 3 - 1;
-        const bf16x4* src[CONV_G];
-        bool inb[CONV_G];
-#pragma unroll
-        for (int g = 0; g < CONV_G; ++g) {
-            const int yy = py[g] + dy, xx = px[g] + dx;
-            inb[g] = pv[g] && yy >= 0 && yy < H && xx >= 0 && xx < W;
-            src[g] = reinterpret_cast<const bf16x4*>(X + (base + (long)yy * W + xx) * CIN);
-        }
+        const int dy = tap / 3, dx = tap % 3;           // halo offsets 0..2
 #pragma unroll
         for (int c = 0; c < NC; ++c) {
-            bf16x4 a[CONV_G];
+            bf16x4 a[4];
 #pragma unroll
-            for (int g = 0; g < CONV_G; ++g) a[g] = inb[g] ? src[g][c * 4 + kg] : bf16x4{0, 0, 0, 0};
+            for (int g = 0; g < 4; ++g) {
+                const int r = wv * 4 + g;
+                const uint2 v = sX[((r + dy) * CONV_H + m + dx) * PS + c * 4 + kg];
+                a[g] = __builtin_bit_cast(bf16x4, v);
+            }
 #pragma unroll
-            for (int t = 0; t < NT; ++t) {
-                const bf16x4 b = sW[((t * 16 + m) * 9 + tap) * (CIN / 4) + c * 4 + kg];
+            for (int tt = 0; tt < NT; ++tt) {
+                const bf16x4 b = sW[((tt * 16 + m) * 9 + tap) * (CIN / 4) + c * 4 + kg];
 #pragma unroll
-                for (int g = 0; g < CONV_G; ++g)
-                    acc[g][t] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a[g], b, acc[g][t], 0, 0, 0);
+                for (int g = 0; g < 4; ++g)
+                    acc[g][tt] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a[g], b, acc[g][tt], 0, 0, 0);
             }
         }
     }
 #pragma unroll
-    for (int g = 0; g < CONV_G; ++g)
+    for (int g = 0; g < 4; ++g) {
+        const int y = y0 + wv * 4 + g;
+        if (y >= H) continue;
 #pragma unroll
-        for (int t = 0; t < NT; ++t) {
-            const int co = t * 16 + m;
+        for (int tt = 0; tt < NT; ++tt) {
+            const int co = tt * 16 + m;
             const float bb = bias ? bias[co] : 0.0f;
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
-                const int qq = qb + g * 16 + kg * 4 + i;
-                if (qq >= npix) continue;
-                float v = acc[g][t][i] + bb;
+                const int x = x0 + kg * 4 + i;
+                if (x >= W) continue;
+                const long qq = (long)y * W + x;
+                float v = acc[g][tt][i] + bb;
                 if (MODE == CONV_LRELU) v = v > 0.0f ? v : alpha * v;
                 const long o = (base + qq) * COUT + co;
                 if (MODE == CONV_FLOW2) {
@@ -124,6 +130,7 @@ __global__ __launch_bounds__(256) void k_conv3x3(const uint16_t* __restrict__ X,
                 }
             }
         }
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -324,9 +331,10 @@ template <int CIN, int COUT>
 static hipError_t conv_mode(const uint16_t* X, const uint16_t* W, const float* b, void* Y, const ImgTable& T0,
                             int mode, float alpha, hipStream_t s)
 {
-    ImgTable T = T0;   // blocks of CONV_PX pixels
+    ImgTable T = T0;   // blocks of CONV_T x CONV_T pixels
     T.tile_off[0] = 0;
-    for (int i = 0; i < T.n; ++i) T.tile_off[i + 1] = T.tile_off[i] + (T.w[i] * T.h[i] + CONV_PX - 1) / CONV_PX;
+    for (int i = 0; i < T.n; ++i)
+        T.tile_off[i + 1] = T.tile_off[i] + ((T.w[i] + CONV_T - 1) / CONV_T) * ((T.h[i] + CONV_T - 1) / CONV_T);
     for (int i = T.n + 1; i <= MAXI; ++i) T.tile_off[i] = T.tile_off[T.n];
     const dim3 g(T.tile_off[T.n]), blk(256);
     switch (mode) {

@@ -169,3 +169,43 @@ def test_deterministic():
     a = O.Oracle(rig).stitch(frames)
     b = O.Oracle(rig).stitch(frames)
     np.testing.assert_array_equal(a, b)
+
+
+def strong_perspective_rig(p1=-0.004):
+    """three 200 x 120 cameras 160 px apart; camera 2 has a perspective term
+    so strong that the top-left 2 x 2 block of its camera-to-canvas matrix has
+    a negative determinant while the matrix itself does not (adj[8] < 0 < det)"""
+    W, H, step = 200, 120, 160
+    cx, cy = (W - 1) / 2, (H - 1) / 2
+
+    def T(tx, ty):
+        return np.array([[1, 0, tx], [0, 1, ty], [0, 0, 1.0]])
+
+    Hs = []
+    for k in range(3):
+        P = np.eye(3)
+        if k == 2:
+            P[2, 0] = p1
+        Hk = T(k * step, 0) @ T(cx, cy) @ P @ T(-cx, -cy)
+        Hs.append(Hk / Hk[2, 2])
+    H_pair = [np.eye(3)] + [np.linalg.inv(Hs[k - 1]) @ Hs[k] for k in (1, 2)]
+    return Hs, dict(n_cams=3, W=W, H=H, ring=0, ring_period=0, canvas_w=560, canvas_h=H, H_pair=H_pair,
+                    H_ref=Hs[0])
+
+
+def test_inverse_keeps_the_front_of_the_camera_when_adj8_is_negative():
+    """The canvas-to-camera inverse is a positive multiple of H^-1 (last entry
+    +-1), so every pixel of a camera maps back to itself with w > 0 even where
+    adj[8] and det differ in sign; dividing by adj[8] alone would flip w."""
+    Hs, rig = strong_perspective_rig()
+    a = Hs[2]
+    assert a[0, 0] * a[1, 1] - a[0, 1] * a[1, 0] < 0 < np.linalg.det(a)
+    o = O.Oracle(rig)
+    assert o.n_pairs == 2 and o.strip_box(1)[2] > 0
+    hinv = np.array(o.plan.hinv[2]).reshape(3, 3)
+    assert abs(hinv[2, 2]) == 1.0
+    for u in range(2, 198, 13):
+        for v in range(2, 118, 11):
+            q = a @ np.array([u, v, 1.0])
+            ok, uu, vv = O.hom_valid(hinv, q[0] / q[2], q[1] / q[2], 200, 120)
+            assert ok and abs(uu - u) < 0.05 and abs(vv - v) < 0.05, (u, v, uu, vv)
