@@ -232,7 +232,10 @@ def main():
                     traffic=traffic, avg_launch_ms=round(lk_launch_ms, 5),
                     flops_per_launch=int(flops / levels))
     names = V.Stitcher.TIMING_STEPS
-    out = dict(metric="panorama Mpix/s (4x1080p ring)", value=round(mpix, 2), unit="Mpix/s", n_gpus=1,
+    metric = ("panorama Mpix/s + p99 frame ms, 4x1080p; surrogate vs plain flow @EPE<=0.5px"
+              if args.workload == "4x1920x1080_ring" else
+              f"panorama Mpix/s + p99 frame ms, {args.workload}; surrogate vs plain flow @EPE<=0.5px")
+    out = dict(metric=metric, value=round(mpix, 2), unit="Mpix/s", n_gpus=1,
                steps=K, warmup=args.warmup, ms_per_step=round(wall / K * 1e3, 4),
                higher_is_better=True, scaling="weak", vs_baseline=None, dtype="f32",
                data="synthetic",
