@@ -525,7 +525,7 @@ namespace {
 // non-null; pre (single context only) receives a copy of the pre-balance
 // panorama.
 hipError_t enqueue_frame(const Group& g, hipStream_t s, hipEvent_t* ev, uint8_t* pre, const uint8_t* pano,
-                         size_t pano_bytes, const char** where)
+                         size_t pano_bytes, const char** where, const Fork* fk = nullptr)
 {
     hipError_t e;
 #define VS_STEP(call, name)              \
@@ -547,7 +547,22 @@ hipError_t enqueue_frame(const Group& g, hipStream_t s, hipEvent_t* ev, uint8_t*
     VS_STEP(launch_pyr0(g, s), "pyr0");
     for (int l = 0; l + 1 < levels; ++l) VS_STEP(launch_pyr_down(g, l, s), "pyr_down");
     if (ev) VS_STEP(hipEventRecord(ev[2], s), "hipEventRecord");
-    VS_STEP(launch_surrogate(g, s), "surrogate");
+    int n_surr = 0;
+    for (int c = 0; c < g.n; ++c) n_surr += surrogate_active(g, c) ? 1 : 0;
+    if (fk && n_surr > 1) {
+        // the contexts' surrogate chains are independent small launches: run
+        // them side by side
+        VS_STEP(hipEventRecord(fk->fork, s), "fork");
+        for (int c = 0; c < g.n; ++c) {
+            if (!surrogate_active(g, c)) continue;
+            VS_STEP(hipStreamWaitEvent(fk->side[c], fk->fork, 0), "fork wait");
+            VS_STEP(launch_surrogate_ctx(g, c, fk->side[c]), "surrogate");
+            VS_STEP(hipEventRecord(fk->join[c], fk->side[c]), "join");
+            VS_STEP(hipStreamWaitEvent(s, fk->join[c], 0), "join wait");
+        }
+    } else {
+        VS_STEP(launch_surrogate(g, s), "surrogate");
+    }
     for (int l = levels - 1; l >= 0; --l) VS_STEP(launch_lk(g, l, s), "flow");
     if (ev) VS_STEP(hipEventRecord(ev[3], s), "hipEventRecord");
     VS_STEP(launch_blend(g, s), "blend");
@@ -794,6 +809,7 @@ struct vs_batch {
     uint32_t gen[MAXB] = {};   // each context's generation at capture
     Group g;
     hipStream_t cap = nullptr;
+    Fork fk = {};
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     std::string err;
@@ -824,7 +840,7 @@ vs_status capture(vs_batch* b)
         return VS_E_DEVICE;
     }
     const char* where = "";
-    hipError_t e1 = enqueue_frame(b->g, b->cap, nullptr, nullptr, nullptr, 0, &where);
+    hipError_t e1 = enqueue_frame(b->g, b->cap, nullptr, nullptr, nullptr, 0, &where, &b->fk);
     hipGraph_t graph = nullptr;
     e = hipStreamEndCapture(b->cap, &graph);
     if (e1 != hipSuccess || e != hipSuccess) {
@@ -898,8 +914,13 @@ vs_status vs_batch_create(vs_ctx* const ctxs[], int n, vs_batch** out)
             return st;
         }
     }
-    if (hipStreamCreate(&b->cap) != hipSuccess) {
-        delete b;
+    bool ok = hipStreamCreate(&b->cap) == hipSuccess &&
+              hipEventCreateWithFlags(&b->fk.fork, hipEventDisableTiming) == hipSuccess;
+    for (int c = 0; c < n && ok; ++c)
+        ok = hipStreamCreate(&b->fk.side[c]) == hipSuccess &&
+             hipEventCreateWithFlags(&b->fk.join[c], hipEventDisableTiming) == hipSuccess;
+    if (!ok) {
+        vs_batch_destroy(b);
         return VS_E_DEVICE;
     }
     vs_status st = capture(b);
@@ -916,6 +937,11 @@ vs_status vs_batch_destroy(vs_batch* b)
     if (!b) return VS_E_INVAL;
     drop_graph(b);
     if (b->cap) (void)hipStreamDestroy(b->cap);
+    for (int c = 0; c < MAXB; ++c) {
+        if (b->fk.side[c]) (void)hipStreamDestroy(b->fk.side[c]);
+        if (b->fk.join[c]) (void)hipEventDestroy(b->fk.join[c]);
+    }
+    if (b->fk.fork) (void)hipEventDestroy(b->fk.fork);
     delete b;
     return VS_OK;
 }

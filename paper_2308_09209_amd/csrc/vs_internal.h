@@ -155,6 +155,17 @@ hipError_t launch_pyr0(const Group& g, hipStream_t s);
 hipError_t launch_pyr_down(const Group& g, int level, hipStream_t s);
 hipError_t launch_lk(const Group& g, int level, hipStream_t s);
 hipError_t launch_surrogate(const Group& g, hipStream_t s);   // vs_surr.hip
+bool surrogate_active(const Group& g, int c);
+hipError_t launch_surrogate_ctx(const Group& g, int c, hipStream_t s);
+
+// side streams of a batch: each context's surrogate chain runs on its own
+// stream between a fork and a join event (captured into the graph as
+// parallel branches)
+struct Fork {
+    hipStream_t side[MAXB];
+    hipEvent_t fork;
+    hipEvent_t join[MAXB];
+};
 hipError_t launch_blend(const Group& g, hipStream_t s);
 hipError_t launch_balance_lut(const Group& g, hipStream_t s);
 hipError_t launch_balance_apply(const Group& g, hipStream_t s);

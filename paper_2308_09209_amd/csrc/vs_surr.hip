@@ -149,29 +149,40 @@ __global__ __launch_bounds__(256) void k_surr_decide(const DevPlan* __restrict__
 
 }  // namespace
 
+bool surrogate_active(const Group& g, int c)
+{
+    const DevPlan& h = *g.hp[c];
+    return h.use_flow && h.flow_mode != VS_FLOW_PLAIN;
+}
+
+hipError_t launch_surrogate_ctx(const Group& g, int c, hipStream_t s)
+{
+    const DevPlan& h = *g.hp[c];
+    const SurrNet* net = g.net[c];
+    if (!surrogate_active(g, c)) return hipSuccess;
+    if (!net) return hipErrorInvalidValue;
+    const long npx = h.surr_pix[2 * h.n_pairs];
+    hipLaunchKernelGGL(k_surr_pack, dim3((unsigned)((npx + 255) / 256)), dim3(256), 0, s, g.dp[c], net->x);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    const uint16_t* in = net->x;
+    for (int l = 0; l < net->nl; ++l) {
+        const bool last = l == net->nl - 1;
+        void* out = last ? (void*)net->pred : (void*)net->h[l & 1];
+        e = nn::conv3x3(in, net->ci[l], net->w[l], net->b[l], out, net->co[l], net->tbl,
+                        last ? nn::CONV_FLOW2 : nn::CONV_LRELU, net->alpha, s);
+        if (e != hipSuccess) return e;
+        in = net->h[l & 1];
+    }
+    hipLaunchKernelGGL(k_surr_up, dim3(h.strip_off[h.n_pairs] * SURR_UP_SUB), dim3(256), 0, s, g.dp[c]);
+    hipLaunchKernelGGL(k_surr_decide, dim3(h.n_pairs), dim3(256), 0, s, g.dp[c]);
+    return hipGetLastError();
+}
+
 hipError_t launch_surrogate(const Group& g, hipStream_t s)
 {
     for (int c = 0; c < g.n; ++c) {
-        const DevPlan& h = *g.hp[c];
-        const SurrNet* net = g.net[c];
-        if (!h.use_flow || h.flow_mode == VS_FLOW_PLAIN) continue;
-        if (!net) return hipErrorInvalidValue;
-        const long npx = h.surr_pix[2 * h.n_pairs];
-        hipLaunchKernelGGL(k_surr_pack, dim3((unsigned)((npx + 255) / 256)), dim3(256), 0, s, g.dp[c], net->x);
-        hipError_t e = hipGetLastError();
-        if (e != hipSuccess) return e;
-        const uint16_t* in = net->x;
-        for (int l = 0; l < net->nl; ++l) {
-            const bool last = l == net->nl - 1;
-            void* out = last ? (void*)net->pred : (void*)net->h[l & 1];
-            e = nn::conv3x3(in, net->ci[l], net->w[l], net->b[l], out, net->co[l], net->tbl,
-                            last ? nn::CONV_FLOW2 : nn::CONV_LRELU, net->alpha, s);
-            if (e != hipSuccess) return e;
-            in = net->h[l & 1];
-        }
-        hipLaunchKernelGGL(k_surr_up, dim3(h.strip_off[h.n_pairs] * SURR_UP_SUB), dim3(256), 0, s, g.dp[c]);
-        hipLaunchKernelGGL(k_surr_decide, dim3(h.n_pairs), dim3(256), 0, s, g.dp[c]);
-        e = hipGetLastError();
+        const hipError_t e = launch_surrogate_ctx(g, c, s);
         if (e != hipSuccess) return e;
     }
     return hipSuccess;

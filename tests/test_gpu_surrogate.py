@@ -281,3 +281,26 @@ def test_trained_surrogate_gain_on_the_4x1080p_ring():
         f"(flow step {times['plain'][2]:.4f} -> {times['surrogate'][2]:.4f} ms)")
     assert e.mean() <= 0.5
     assert times["surrogate"][5] < times["plain"][5]
+
+
+def test_batch_of_surrogate_contexts_runs_their_chains_side_by_side(blob):
+    """Three contexts with the surrogate in one graph: their network chains are
+    captured as parallel branches; every replay equals the single contexts."""
+    scs = [S.small_scene(n_cams=3, W=200, H=120, overlap=0.35, ring=True, seed_config=98),
+           S.small_scene(n_cams=2, W=160, H=96, overlap=0.3, seed_config=99),
+           S.small_scene(n_cams=4, W=180, H=100, overlap=0.3, seed_config=100)]
+    modes = [(V.FLOW_SURROGATE, 0.0), (V.FLOW_SURROGATE_FALLBACK, 0.0), (V.FLOW_SURROGATE_FALLBACK, 1e6)]
+    ref = [gpu_run(sc, 3, blob, m, tau)[1] for sc, (m, tau) in zip(scs, modes)]
+    sts = []
+    for sc, (m, tau) in zip(scs, modes):
+        st = V.Stitcher(sc.rig())
+        st.load_weights(blob)
+        st.set_flow_mode(m, tau)
+        sts.append(st)
+    b = V.Batch(sts)
+    panos = [st.new_pano() for st in sts]
+    for t in range(3):
+        b.run([dev(sc.frames(t)) for sc in scs], panos)
+        torch.cuda.synchronize()
+        for i in range(3):
+            assert np.array_equal(panos[i].cpu().numpy(), ref[i][t]), (t, i)
