@@ -688,33 +688,33 @@ __global__ __launch_bounds__(BL_THREADS) void k_blend(const Batch B)
 
 __device__ __forceinline__ void balance_lut_body(const DevPlan* __restrict__ P, const int bid)
 {
+    // one thread per (channel, level): tid = 256 c + v
     __shared__ uint32_t C[3][256];
     __shared__ double s_m[3][2];
     __shared__ int s_q[3][2];
-    const int v = threadIdx.x;
+    const int tid = threadIdx.x, c = tid >> 8, v = tid & 255;
     vs_color_state* st = P->state;
     Results* res = P->res;
-    for (int c = 0; c < 3; ++c) C[c][v] = P->acc->pano_hist[c][v];
+    C[c][v] = P->acc->pano_hist[c][v];
     __syncthreads();
     for (int o = 1; o < 256; o <<= 1) {
-        uint32_t t[3];
-        for (int c = 0; c < 3; ++c) t[c] = v >= o ? C[c][v - o] : 0;
+        const uint32_t t = v >= o ? C[c][v - o] : 0;
         __syncthreads();
-        for (int c = 0; c < 3; ++c) C[c][v] += t[c];
+        C[c][v] += t;
         __syncthreads();
     }
+    // q1, q2: the first levels whose cumulative counts reach lambda n and
+    // (1 - lambda) n (the cumulative counts never decrease, so exactly one
+    // level satisfies "reached here, not before")
     const int pct = P->lambda_pct;
-    if (v < 3) {
-        const int c = v;
-        const unsigned long long n = C[c][255];
-        int q1 = -1, q2 = -1;
-        for (int k = 0; k < 256; ++k) {
-            const unsigned long long Cv = C[c][k];
-            if (q1 < 0 && 100ull * Cv >= (unsigned long long)pct * n) q1 = k;
-            if (q2 < 0 && 100ull * Cv >= (unsigned long long)(100 - pct) * n) q2 = k;
-        }
-        if (q1 < 0) q1 = 0;
-        if (q2 < 0) q2 = 255;
+    const unsigned long long n = C[c][255];
+    const unsigned long long Cv = C[c][v], Cp = v > 0 ? C[c][v - 1] : 0ull;
+    const unsigned long long lo = (unsigned long long)pct * n, hi = (unsigned long long)(100 - pct) * n;
+    if (100ull * Cv >= lo && (v == 0 || 100ull * Cp < lo)) s_q[c][0] = v;
+    if (100ull * Cv >= hi && (v == 0 || 100ull * Cp < hi)) s_q[c][1] = v;
+    __syncthreads();
+    if (v == 0) {
+        const int q1 = s_q[c][0], q2 = s_q[c][1];
         const int T = (int)st->frames_seen;
         int s1 = q1, s2 = q2, cnt = 1;
         for (int d = 1; d <= 2 && d <= T; ++d) {
@@ -722,8 +722,6 @@ __device__ __forceinline__ void balance_lut_body(const DevPlan* __restrict__ P, 
             s2 += st->q[d - 1][c][1];
             ++cnt;
         }
-        s_q[c][0] = q1;
-        s_q[c][1] = q2;
         s_m[c][0] = (double)s1 / (double)cnt;
         s_m[c][1] = (double)s2 / (double)cnt;
         res->quant[c][0] = q1;
@@ -734,7 +732,7 @@ __device__ __forceinline__ void balance_lut_body(const DevPlan* __restrict__ P, 
     __syncthreads();
     const double lam = (double)pct / 100.0;
     const double t1 = 255.0 * lam, t2 = 255.0 * (1.0 - lam);
-    for (int c = 0; c < 3; ++c) {
+    {
         const double m1 = s_m[c][0], m2 = s_m[c][1];
         uint8_t out;
         if (m2 - m1 < 1.0) {
@@ -756,18 +754,18 @@ __device__ __forceinline__ void balance_lut_body(const DevPlan* __restrict__ P, 
         res->bal_lut[c][v] = out;
     }
     __syncthreads();
-    if (v == 0) {
-        for (int c = 0; c < 3; ++c) {
-            st->q[1][c][0] = st->q[0][c][0];
-            st->q[1][c][1] = st->q[0][c][1];
-            st->q[0][c][0] = s_q[c][0];
-            st->q[0][c][1] = s_q[c][1];
+    if (tid == 0) {
+        for (int ch = 0; ch < 3; ++ch) {
+            st->q[1][ch][0] = st->q[0][ch][0];
+            st->q[1][ch][1] = st->q[0][ch][1];
+            st->q[0][ch][0] = s_q[ch][0];
+            st->q[0][ch][1] = s_q[ch][1];
         }
         st->frames_seen = st->frames_seen + 1;
     }
 }
 
-__global__ __launch_bounds__(256) void k_balance_lut(const Batch B)
+__global__ __launch_bounds__(768) void k_balance_lut(const Batch B)
 {
     int c;
     const int b = batch_block(B, blockIdx.x, c);
@@ -906,7 +904,7 @@ hipError_t launch_balance_lut(const Group& g, hipStream_t s)
 {
     Batch B;
     if (make_batch(g, B, [](const DevPlan&) { return 1; }))
-        hipLaunchKernelGGL(k_balance_lut, dim3(B.off[B.n]), dim3(256), 0, s, B);
+        hipLaunchKernelGGL(k_balance_lut, dim3(B.off[B.n]), dim3(768), 0, s, B);
     return hipGetLastError();
 }
 

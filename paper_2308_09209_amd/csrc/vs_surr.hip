@@ -118,21 +118,22 @@ __global__ __launch_bounds__(256) void k_surr_up(const DevPlan* __restrict__ P)
     }
 }
 
-// one block per pair: add the pair's block partials, decide
-__global__ __launch_bounds__(256) void k_surr_decide(const DevPlan* __restrict__ P)
+// one block per pair: add the pair's block partials (exact integers, so the
+// order does not matter), decide
+__global__ __launch_bounds__(1024) void k_surr_decide(const DevPlan* __restrict__ P)
 {
-    __shared__ unsigned long long s_e[256], s_n[256];
+    __shared__ unsigned long long s_e[1024], s_n[1024];
     const int p = blockIdx.x, tid = threadIdx.x;
     const int b0 = P->strip_off[p] * SURR_UP_SUB, b1 = P->strip_off[p + 1] * SURR_UP_SUB;
     unsigned long long e = 0, n = 0;
-    for (int b = b0 + tid; b < b1; b += 256) {
+    for (int b = b0 + tid; b < b1; b += 1024) {
         e += P->surr_part[2 * b];
         n += P->surr_part[2 * b + 1];
     }
     s_e[tid] = e;
     s_n[tid] = n;
     __syncthreads();
-    for (int o = 128; o > 0; o >>= 1) {
+    for (int o = 512; o > 0; o >>= 1) {
         if (tid < o) {
             s_e[tid] += s_e[tid + o];
             s_n[tid] += s_n[tid + o];
@@ -175,7 +176,7 @@ hipError_t launch_surrogate_ctx(const Group& g, int c, hipStream_t s)
         in = net->h[l & 1];
     }
     hipLaunchKernelGGL(k_surr_up, dim3(h.strip_off[h.n_pairs] * SURR_UP_SUB), dim3(256), 0, s, g.dp[c]);
-    hipLaunchKernelGGL(k_surr_decide, dim3(h.n_pairs), dim3(256), 0, s, g.dp[c]);
+    hipLaunchKernelGGL(k_surr_decide, dim3(h.n_pairs), dim3(1024), 0, s, g.dp[c]);
     return hipGetLastError();
 }
 
