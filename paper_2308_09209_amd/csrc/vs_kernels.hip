@@ -295,12 +295,22 @@ __device__ __forceinline__ void moments_b_body(const DevPlan* __restrict__ P, co
     const uint8_t* __restrict__ mask = P->mask[p];
     const int lx = tx0 + (tid & 63);
     uint32_t b[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
-    for (int r = tid >> 6; r < STRIP_TY; r += 4) {
-        const int ly = ty0 + r;
-        if (lx >= sw || ly >= sh) continue;
+    // every row's mask and pixel loads issued before any is used
+    constexpr int NR = STRIP_TY / 4;
+    uint32_t px[NR];
+    uint8_t mk[NR];
+#pragma unroll
+    for (int k = 0; k < NR; ++k) {
+        const int ly = ty0 + (tid >> 6) + 4 * k;
+        const bool in = lx < sw && ly < sh;
         const size_t q = (size_t)ly * sw + lx;
-        if (!mask[q]) continue;
-        uint32_t pix = strip_i[q];
+        px[k] = in ? strip_i[q] : 0u;
+        mk[k] = in ? mask[q] : (uint8_t)0;
+    }
+#pragma unroll
+    for (int k = 0; k < NR; ++k) {
+        if (!mk[k]) continue;
+        const uint32_t pix = px[k];
         uint32_t pv[3] = {pix & 255u, (pix >> 8) & 255u, (pix >> 16) & 255u};
         uint32_t qv[3] = {s_lut[0][pv[0]], s_lut[1][pv[1]], s_lut[2][pv[2]]};
 #pragma unroll
@@ -474,11 +484,19 @@ __device__ __forceinline__ void pyr0_body(const DevPlan* __restrict__ P, const i
     const uint32_t* __restrict__ src = P->strip[p] + (size_t)cam * h * w;
     float* __restrict__ dst = P->pyr[p][cam][0];
     const int x = tx0 + (threadIdx.x & 63);
-    for (int r = threadIdx.x >> 6; r < PYR_TY; r += 4) {
-        const int y = ty0 + r;
+    // every row's load issued before any is used
+    constexpr int NR = PYR_TY / 4;
+    uint32_t pix[NR];
+#pragma unroll
+    for (int k = 0; k < NR; ++k) {
+        const int y = ty0 + (threadIdx.x >> 6) + 4 * k;
+        pix[k] = (x < w && y < h) ? src[(size_t)y * w + x] : 0u;
+    }
+#pragma unroll
+    for (int k = 0; k < NR; ++k) {
+        const int y = ty0 + (threadIdx.x >> 6) + 4 * k;
         if (x >= w || y >= h) continue;
-        uint32_t pix = src[(size_t)y * w + x];
-        float s[3] = {(float)(pix & 255u), (float)((pix >> 8) & 255u), (float)((pix >> 16) & 255u)};
+        float s[3] = {(float)(pix[k] & 255u), (float)((pix[k] >> 8) & 255u), (float)((pix[k] >> 16) & 255u)};
         uint32_t c0 = round8(capply(s, M, 0)), c1 = round8(capply(s, M, 1)), c2 = round8(capply(s, M, 2));
         dst[(size_t)y * w + x] = (float)((77u * c0 + 150u * c1 + 29u * c2 + 128u) >> 8);
     }
@@ -509,9 +527,11 @@ __device__ __forceinline__ void pyr_down_body(const DevPlan* __restrict__ P, con
     const int x = tx0 + (threadIdx.x & 63);
     const int xs[5] = {clampi(2 * x - 2, 0, ws - 1), clampi(2 * x - 1, 0, ws - 1), clampi(2 * x, 0, ws - 1),
                        clampi(2 * x + 1, 0, ws - 1), clampi(2 * x + 2, 0, ws - 1)};
+    // every source index is clamped into the level, so all rows are computed
+    // (their loads scheduled together) and only the stores are predicated
+#pragma unroll
     for (int r = threadIdx.x >> 6; r < PYR_TY; r += 4) {
         const int y = ty0 + r;
-        if (x >= wd || y >= hd) continue;
         float rows[5];
 #pragma unroll
         for (int k = 0; k < 5; ++k) {
@@ -526,7 +546,7 @@ __device__ __forceinline__ void pyr_down_body(const DevPlan* __restrict__ P, con
         acc = acc + 6.0f * rows[2];
         acc = acc + 4.0f * rows[3];
         acc = acc + rows[4];
-        dst[(size_t)y * wd + x] = acc * 0.0625f;
+        if (x < wd && y < hd) dst[(size_t)y * wd + x] = acc * 0.0625f;
     }
 }
 
