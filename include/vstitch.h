@@ -274,7 +274,10 @@ typedef struct {
  * {(16,32), (32,32), (32,16), (16,16)}; mode VS_CONV_LRELU (BF16 out, leaky
  * ReLU slope alpha), VS_CONV_LINEAR (BF16 out), VS_CONV_F32 (FP32 out) or
  * VS_CONV_FLOW2 (FP32 channels 0-1 only, y is [pixels][2]);
- * bias may be NULL. */
+ * bias may be NULL.  x, w and y must be 16-byte aligned (VS_E_INVAL
+ * otherwise); x and y must not overlap.  The kernel's grid is persistent (as
+ * many blocks as the device holds), each accumulator sums in (tap, cin)
+ * order, so results do not depend on the grid. */
 vs_status vs_nn_conv3x3(const uint16_t* x, int cin, const uint16_t* w, const float* bias, void* y, int cout,
                         const vs_nn_images* imgs, int mode, float alpha, void* stream);
 /* Weight and bias gradient of that convolution: dwb[Cout][9][Cin] followed by
@@ -305,6 +308,9 @@ vs_status vs_nn_to_bf16(const float* a, uint16_t* b, int64_t n, void* stream);
 /* One 16x16x16 BF16 matrix-core product of a[16][16] and b[16][16]; out[64][4]
  * receives each lane's accumulator fragment (a layout check). */
 vs_status vs_nn_mfma_probe(const uint16_t* a, const uint16_t* b, float* out, void* stream);
+/* One 16x16x32 BF16 matrix-core product (the instruction of vs_nn_conv3x3) of
+ * a[16][32] and b[32][16]; out[64][4] as above. */
+vs_status vs_nn_mfma_probe_k32(const uint16_t* a, const uint16_t* b, float* out, void* stream);
 
 /* The learned surrogate inside the frame.  vs_load_weights copies a weight
  * file into the context: "VSNN", u32 version 1, u32 layers (1..8), f32

@@ -34,6 +34,7 @@ hipError_t adam(float* w, float* m, float* v, const float* g, uint16_t* w_bf16, 
                 float eps, int step, hipStream_t s);
 hipError_t to_bf16(const float* a, uint16_t* b, long n, hipStream_t s);
 hipError_t mfma_probe(const uint16_t* a, const uint16_t* b, float* out, hipStream_t s);
+hipError_t mfma_probe_k32(const uint16_t* a, const uint16_t* b, float* out, hipStream_t s);
 
 }  // namespace nn
 }  // namespace vs

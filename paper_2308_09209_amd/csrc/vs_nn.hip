@@ -1,9 +1,11 @@
 // vs_nn.hip -- the learned flow surrogate: a small 3x3 convolution network in
 // BF16 with FP32 accumulation, forward and backward on the matrix cores
-// (v_mfma_f32_16x16x16_bf16, wave64), plus the pointwise, loss and optimiser
+// (v_mfma_f32_16x16x32_bf16 forward, v_mfma_f32_16x16x16_bf16 weight
+// gradient; wave64), plus the pointwise, loss and optimiser
 // kernels its training needs.  Activations are NHWC with 16 or 32 channels;
 // weights are [Cout][tap][Cin] (tap = 3 ky + kx).
 #include <algorithm>
+#include <atomic>
 
 #include "vs_nn.h"
 
@@ -31,19 +33,46 @@ __device__ __forceinline__ int find_img(const ImgTable& T, int b)
 }
 
 // ---------------------------------------------------------------------------
-// 3x3 convolution, zero padding, as an implicit GEMM on the matrix cores:
-// D[pixel][cout] = sum_{tap, cin} X[pixel + tap][cin] W[cout][tap][cin].
-// A block computes a CONV_T x CONV_T pixel tile of one image for every output
-// channel.  The tile and its one-pixel halo are read from global memory once
-// (coalesced rows) into LDS with a padded pixel stride, the block's weights
-// are staged in LDS, and every tap reads its A fragments from LDS; each
-// wavefront computes 4 rows of 16 pixels at once (independent accumulator
-// chains).  Every accumulator sums its products in (tap, cin chunk) order.
-// MFMA 16x16x16 BF16 fragments: lane l holds A[m = l % 16][k = 4 (l / 16) + i],
-// B[k = 4 (l / 16) + i][n = l % 16] and D[m = 4 (l / 16) + i][n = l % 16].
+// 3x3 convolution, zero padding, as an implicit GEMM on the matrix cores with
+// the weights as the A operand:
+//   D[cout][pixel] = sum_k W[cout][k] X[pixel + off(tap)][cin],  k = tap CIN + cin,
+// in 32-long k chunks (v_mfma_f32_16x16x32_bf16).  The grid is persistent: a
+// block walks the CONV_T x CONV_T pixel tiles t = blockIdx.x, + gridDim.x, ...
+// Each wavefront loads its A fragments (the weights, at most 72 VGPRs) once;
+// per tile the block stages the tile and its one-pixel halo in LDS (16-byte
+// vectors, pixel stride padded by one vector so that the 16 pixels a
+// fragment read touches fall in distinct banks) and, while it multiplies,
+// already holds the next tile's loads in flight.  A wavefront computes 4 rows
+// of 16 pixels for every output channel (independent accumulator chains);
+// every accumulator sums its chunks in k order.
+// MFMA 16x16x32 BF16 fragments: lane l holds A[m = l % 16][k = 8 (l / 16) + i],
+// B[k = 8 (l / 16) + i][n = l % 16] (i < 8) and D[m = 4 (l / 16) + i][n = l % 16]
+// (i < 4): here m is the output channel and n the pixel, so a lane ends with
+// 4 consecutive channels of one pixel.
 // ---------------------------------------------------------------------------
 constexpr int CONV_T = 16;                  // tile side (pixels)
 constexpr int CONV_H = CONV_T + 2;          // tile with halo
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+
+struct ConvTile {
+    int x0, y0, W, H;
+    long base;
+};
+
+__device__ __forceinline__ ConvTile conv_tile(const ImgTable& T, int t)
+{
+    const int img = find_img(T, t);
+    ConvTile c;
+    c.W = T.w[img];
+    c.H = T.h[img];
+    c.base = T.pix_off[img];
+    const int ntx = (c.W + CONV_T - 1) / CONV_T;
+    const int r = t - T.tile_off[img];
+    c.x0 = (r % ntx) * CONV_T;
+    c.y0 = (r / ntx) * CONV_T;
+    return c;
+}
 
 template <int CIN, int COUT, int MODE>
 __global__ __launch_bounds__(256) void k_conv3x3(const uint16_t* __restrict__ X, const uint16_t* __restrict__ Wt,
@@ -51,82 +80,110 @@ __global__ __launch_bounds__(256) void k_conv3x3(const uint16_t* __restrict__ X,
                                                  const ImgTable T, float alpha)
 {
     static_assert(CIN % 16 == 0 && COUT % 16 == 0, "channels in multiples of 16");
-    constexpr int NT = COUT / 16, NC = CIN / 16;
-    constexpr int PS = CIN / 4 + 2;                     // LDS pixel stride in 8-byte units (padded)
-    __shared__ bf16x4 sW[COUT * 9 * CIN / 4];
-    __shared__ uint2 sX[CONV_H * CONV_H * PS];
-    const int tid = threadIdx.x;
-    const int img = find_img(T, blockIdx.x);
-    const int W = T.w[img], H = T.h[img];
-    const long base = T.pix_off[img];
-    const int ntx = (W + CONV_T - 1) / CONV_T;
-    const int t = blockIdx.x - T.tile_off[img];
-    const int x0 = (t % ntx) * CONV_T, y0 = (t / ntx) * CONV_T;
-    {
-        const bf16x4* Wv = reinterpret_cast<const bf16x4*>(Wt);
-        for (int i = tid; i < COUT * 9 * CIN / 4; i += 256) sW[i] = Wv[i];
-        // tile + halo, 8 bytes (4 channels) at a time; zeros outside the image
-        const uint2* Xv = reinterpret_cast<const uint2*>(X);
-        for (int i = tid; i < CONV_H * CONV_H * (CIN / 4); i += 256) {
-            const int px = i / (CIN / 4), ch = i % (CIN / 4);
-            const int yy = y0 - 1 + px / CONV_H, xx = x0 - 1 + px % CONV_H;
-            uint2 v = make_uint2(0u, 0u);
-            if (yy >= 0 && yy < H && xx >= 0 && xx < W) v = Xv[(base + (long)yy * W + xx) * (CIN / 4) + ch];
-            sX[px * PS + ch] = v;
-        }
-    }
-    __syncthreads();
-
-    const int lane = tid & 63, wv = tid >> 6;
+    constexpr int NT = COUT / 16;                  // 16-channel output groups
+    constexpr int KT = 9 * CIN;                    // reduction length
+    constexpr int NK = (KT + 31) / 32;             // 32-long chunks (the last one padded with zeros)
+    constexpr int PV = CIN / 8;                    // 16-byte vectors per pixel
+    constexpr int PSV = PV + 1;                    // LDS pixel stride in vectors
+    constexpr int NV = CONV_H * CONV_H * PV;       // vectors per tile with halo
+    constexpr int NL = (NV + 255) / 256;           // of them per thread
+    __shared__ uint4 sX[CONV_H * CONV_H * PSV];
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     const int m = lane & 15, kg = lane >> 4;
-    f32x4 acc[4][NT];
+    const int ntiles = T.tile_off[T.n];
+    const uint4* __restrict__ Xv = reinterpret_cast<const uint4*>(X);
+
+    bf16x8 wa[NT][NK];
 #pragma unroll
-    for (int g = 0; g < 4; ++g)
+    for (int tt = 0; tt < NT; ++tt)
 #pragma unroll
-        for (int tt = 0; tt < NT; ++tt) acc[g][tt] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+        for (int kc = 0; kc < NK; ++kc) {
+            const int k0 = kc * 32 + 8 * kg;
+            uint4 v = make_uint4(0u, 0u, 0u, 0u);
+            if (k0 < KT) v = *reinterpret_cast<const uint4*>(Wt + (long)(tt * 16 + m) * KT + k0);
+            wa[tt][kc] = __builtin_bit_cast(bf16x8, v);
+        }
+    float bb[NT][4];
 #pragma unroll
-    for (int tap = 0; tap < 9; ++tap) {
-        const int dy = tap / 3, dx = tap % 3;           // halo offsets 0..2
+    for (int tt = 0; tt < NT; ++tt)
 #pragma unroll
-        for (int c = 0; c < NC; ++c) {
-            bf16x4 a[4];
+        for (int i = 0; i < 4; ++i) bb[tt][i] = bias ? bias[tt * 16 + 4 * kg + i] : 0.0f;
+
+    uint4 pf[NL];
+    auto fetch = [&](int t) {
+        const ConvTile c = conv_tile(T, t);
+#pragma unroll
+        for (int j = 0; j < NL; ++j) {
+            const int e = tid + j * 256;
+            uint4 v = make_uint4(0u, 0u, 0u, 0u);
+            if (e < NV) {
+                const int px = e / PV, cv = e % PV;
+                const int yy = c.y0 - 1 + px / CONV_H, xx = c.x0 - 1 + px % CONV_H;
+                if (yy >= 0 && yy < c.H && xx >= 0 && xx < c.W) v = Xv[(c.base + (long)yy * c.W + xx) * PV + cv];
+            }
+            pf[j] = v;
+        }
+    };
+
+    if ((int)blockIdx.x < ntiles) fetch(blockIdx.x);
+    for (int t = blockIdx.x; t < ntiles; t += gridDim.x) {
+        __syncthreads();                           // every wavefront is done with the previous tile
+#pragma unroll
+        for (int j = 0; j < NL; ++j) {
+            const int e = tid + j * 256;
+            if (e < NV) sX[(e / PV) * PSV + e % PV] = pf[j];
+        }
+        __syncthreads();
+        if (t + (int)gridDim.x < ntiles) fetch(t + gridDim.x);
+
+        f32x4 acc[4][NT];
+#pragma unroll
+        for (int g = 0; g < 4; ++g)
+#pragma unroll
+            for (int tt = 0; tt < NT; ++tt) acc[g][tt] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+        for (int kc = 0; kc < NK; ++kc) {
+            const int k0 = kc * 32 + 8 * kg;
+            const bool kin = k0 < KT;
+            const int tap = kin ? k0 / CIN : 8, cv = (k0 % CIN) / 8;
+            const int dy = tap / 3, dx = tap % 3;          // halo offsets 0..2
 #pragma unroll
             for (int g = 0; g < 4; ++g) {
                 const int r = wv * 4 + g;
-                const uint2 v = sX[((r + dy) * CONV_H + m + dx) * PS + c * 4 + kg];
-                a[g] = __builtin_bit_cast(bf16x4, v);
-            }
+                uint4 v = sX[((r + dy) * CONV_H + m + dx) * PSV + cv];
+                if (!kin) v = make_uint4(0u, 0u, 0u, 0u);
+                const bf16x8 b = __builtin_bit_cast(bf16x8, v);
 #pragma unroll
-            for (int tt = 0; tt < NT; ++tt) {
-                const bf16x4 b = sW[((tt * 16 + m) * 9 + tap) * (CIN / 4) + c * 4 + kg];
-#pragma unroll
-                for (int g = 0; g < 4; ++g)
-                    acc[g][tt] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a[g], b, acc[g][tt], 0, 0, 0);
+                for (int tt = 0; tt < NT; ++tt)
+                    acc[g][tt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wa[tt][kc], b, acc[g][tt], 0, 0, 0);
             }
         }
-    }
+
+        const ConvTile c = conv_tile(T, t);
+        const int x = c.x0 + m;
 #pragma unroll
-    for (int g = 0; g < 4; ++g) {
-        const int y = y0 + wv * 4 + g;
-        if (y >= H) continue;
+        for (int g = 0; g < 4; ++g) {
+            const int y = c.y0 + wv * 4 + g;
+            if (y >= c.H || x >= c.W) continue;
+            const long q = c.base + (long)y * c.W + x;
 #pragma unroll
-        for (int tt = 0; tt < NT; ++tt) {
-            const int co = tt * 16 + m;
-            const float bb = bias ? bias[co] : 0.0f;
+            for (int tt = 0; tt < NT; ++tt) {
+                float v[4];
 #pragma unroll
-            for (int i = 0; i < 4; ++i) {
-                const int x = x0 + kg * 4 + i;
-                if (x >= W) continue;
-                const long qq = (long)y * W + x;
-                float v = acc[g][tt][i] + bb;
-                if (MODE == CONV_LRELU) v = v > 0.0f ? v : alpha * v;
-                const long o = (base + qq) * COUT + co;
+                for (int i = 0; i < 4; ++i) {
+                    v[i] = acc[g][tt][i] + bb[tt][i];
+                    if (MODE == CONV_LRELU) v[i] = v[i] > 0.0f ? v[i] : alpha * v[i];
+                }
+                const int co = tt * 16 + 4 * kg;
                 if (MODE == CONV_FLOW2) {
-                    if (co < 2) static_cast<float*>(Y)[(base + qq) * 2 + co] = v;
+                    if (co == 0) reinterpret_cast<float2*>(Y)[q] = make_float2(v[0], v[1]);
                 } else if (MODE == CONV_F32) {
-                    static_cast<float*>(Y)[o] = v;
+                    reinterpret_cast<float4*>(static_cast<float*>(Y) + q * COUT + co)[0] =
+                        make_float4(v[0], v[1], v[2], v[3]);
                 } else {
-                    static_cast<uint16_t*>(Y)[o] = f2bf(v);
+                    reinterpret_cast<uint2*>(static_cast<uint16_t*>(Y) + q * COUT + co)[0] =
+                        make_uint2((uint32_t)f2bf(v[0]) | (uint32_t)f2bf(v[1]) << 16,
+                                   (uint32_t)f2bf(v[2]) | (uint32_t)f2bf(v[3]) << 16);
                 }
             }
         }
@@ -323,6 +380,21 @@ __global__ void k_mfma_probe(const uint16_t* __restrict__ a, const uint16_t* __r
     for (int i = 0; i < 4; ++i) out[l * 4 + i] = d[i];
 }
 
+// the same for v_mfma_f32_16x16x32_bf16: a[16][32], b[32][16]
+__global__ void k_mfma_probe_k32(const uint16_t* __restrict__ a, const uint16_t* __restrict__ b,
+                                 float* __restrict__ out)
+{
+    const int l = threadIdx.x, m = l & 15, kg = l >> 4;
+    uint16_t av[8], bv[8];
+    for (int i = 0; i < 8; ++i) {
+        av[i] = a[m * 32 + kg * 8 + i];
+        bv[i] = b[(kg * 8 + i) * 16 + m];
+    }
+    const bf16x8 af = __builtin_bit_cast(bf16x8, av), bf = __builtin_bit_cast(bf16x8, bv);
+    f32x4 d = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af, bf, f32x4{0.0f, 0.0f, 0.0f, 0.0f}, 0, 0, 0);
+    for (int i = 0; i < 4; ++i) out[l * 4 + i] = d[i];
+}
+
 // ---------------------------------------------------------------------------
 // launchers
 // ---------------------------------------------------------------------------
@@ -331,12 +403,28 @@ template <int CIN, int COUT>
 static hipError_t conv_mode(const uint16_t* X, const uint16_t* W, const float* b, void* Y, const ImgTable& T0,
                             int mode, float alpha, hipStream_t s)
 {
-    ImgTable T = T0;   // blocks of CONV_T x CONV_T pixels
+    // 16-byte vector loads and stores
+    const bool vec_ok = ((uintptr_t)X | (uintptr_t)W | (uintptr_t)Y) % 16 == 0;
+    if (!vec_ok) return hipErrorInvalidValue;
+    ImgTable T = T0;   // tiles of CONV_T x CONV_T pixels
     T.tile_off[0] = 0;
     for (int i = 0; i < T.n; ++i)
         T.tile_off[i + 1] = T.tile_off[i] + ((T.w[i] + CONV_T - 1) / CONV_T) * ((T.h[i] + CONV_T - 1) / CONV_T);
     for (int i = T.n + 1; i <= MAXI; ++i) T.tile_off[i] = T.tile_off[T.n];
-    const dim3 g(T.tile_off[T.n]), blk(256);
+    // persistent grid: as many blocks as the device holds at once
+    static std::atomic<int> resident_blocks{0};
+    int resident = resident_blocks.load(std::memory_order_relaxed);
+    if (resident == 0) {
+        int dev = 0, ncu = 0, per_cu = 0;
+        hipError_t e = hipGetDevice(&dev);
+        if (e == hipSuccess) e = hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
+        if (e == hipSuccess)
+            e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_conv3x3<CIN, COUT, CONV_LRELU>, 256, 0);
+        if (e != hipSuccess) return e;
+        resident = std::max(1, ncu * std::max(1, per_cu));
+        resident_blocks.store(resident, std::memory_order_relaxed);
+    }
+    const dim3 g(std::min(T.tile_off[T.n], resident)), blk(256);
     switch (mode) {
     case CONV_LRELU: hipLaunchKernelGGL((k_conv3x3<CIN, COUT, CONV_LRELU>), g, blk, 0, s, X, W, b, Y, T, alpha); break;
     case CONV_LINEAR: hipLaunchKernelGGL((k_conv3x3<CIN, COUT, CONV_LINEAR>), g, blk, 0, s, X, W, b, Y, T, alpha); break;
@@ -433,6 +521,12 @@ hipError_t to_bf16(const float* a, uint16_t* b, long n, hipStream_t s)
 hipError_t mfma_probe(const uint16_t* a, const uint16_t* b, float* out, hipStream_t s)
 {
     hipLaunchKernelGGL(k_mfma_probe, dim3(1), dim3(64), 0, s, a, b, out);
+    return hipGetLastError();
+}
+
+hipError_t mfma_probe_k32(const uint16_t* a, const uint16_t* b, float* out, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_mfma_probe_k32, dim3(1), dim3(64), 0, s, a, b, out);
     return hipGetLastError();
 }
 

@@ -111,4 +111,10 @@ vs_status vs_nn_mfma_probe(const uint16_t* a, const uint16_t* b, float* out, voi
     return st(nn::mfma_probe(a, b, out, (hipStream_t)stream));
 }
 
+vs_status vs_nn_mfma_probe_k32(const uint16_t* a, const uint16_t* b, float* out, void* stream)
+{
+    if (!a || !b || !out) return VS_E_INVAL;
+    return st(nn::mfma_probe_k32(a, b, out, (hipStream_t)stream));
+}
+
 }  // extern "C"

@@ -40,7 +40,7 @@ EXPORTS = ["vs_abi_version", "vs_status_str", "vs_default_params", "vs_compose_h
            "vs_batch_destroy", "vs_batch_last_error", "vs_batch_autotune",
            "vs_nn_conv3x3", "vs_nn_wgrad_scratch_bytes", "vs_nn_conv3x3_wgrad", "vs_nn_flip_weights",
            "vs_nn_lrelu_bwd", "vs_nn_pack_pair", "vs_nn_epe_loss", "vs_nn_adam", "vs_nn_to_bf16",
-           "vs_nn_mfma_probe", "vs_flow_create", "vs_flow_run", "vs_flow_destroy", "vs_flow_level"]
+           "vs_nn_mfma_probe", "vs_nn_mfma_probe_k32", "vs_flow_create", "vs_flow_run", "vs_flow_destroy", "vs_flow_level"]
 
 
 class Rig(C.Structure):
@@ -157,6 +157,7 @@ def lib():
         L.vs_nn_adam.argtypes = [vp, vp, vp, vp, vp, i64, f32, f32, f32, f32, i32, vp]
         L.vs_nn_to_bf16.argtypes = [vp, vp, i64, vp]
         L.vs_nn_mfma_probe.argtypes = [vp, vp, vp, vp]
+        L.vs_nn_mfma_probe_k32.argtypes = [vp, vp, vp, vp]
         L.vs_flow_create.argtypes = [i32, i32, C.POINTER(Params), C.POINTER(C.c_void_p)]
         L.vs_flow_run.argtypes = [vp, vp, vp, vp, vp, vp]
         L.vs_flow_destroy.argtypes = [vp]

@@ -68,6 +68,82 @@ def test_mfma_fragment_layout():
             assert abs(got[l, i] - D[4 * (l // 16) + i, l % 16]) <= 1e-5 * (1 + abs(D[4 * (l // 16) + i, l % 16]))
 
 
+def test_mfma_k32_fragment_layout():
+    rng = np.random.default_rng(1)
+    a = to_bf16(rng.normal(size=(16, 32)))
+    b = to_bf16(rng.normal(size=(32, 16)))
+    out = torch.zeros(256, dtype=torch.float32, device="cuda:0")
+    da, db = dev(a), dev(b)
+    V.check(V.lib().vs_nn_mfma_probe_k32(C.c_void_p(da.data_ptr()), C.c_void_p(db.data_ptr()),
+                                         C.c_void_p(out.data_ptr()), None), "probe k32")
+    torch.cuda.synchronize()
+    got = out.cpu().numpy().reshape(64, 4)
+    D = from_bf16(a) @ from_bf16(b)
+    for l in range(64):
+        for i in range(4):
+            assert abs(got[l, i] - D[4 * (l // 16) + i, l % 16]) <= 1e-5 * (1 + abs(D[4 * (l // 16) + i, l % 16]))
+
+
+def conv_call(x, cin, w, b, y, cout, imgs, mode):
+    return V.lib().vs_nn_conv3x3(C.c_void_p(x.data_ptr()), cin, C.c_void_p(w.data_ptr()),
+                                 None if b is None else C.c_void_p(b.data_ptr()), C.c_void_p(y.data_ptr()), cout,
+                                 C.byref(imgs), mode, 0.1, None)
+
+
+@pytest.mark.parametrize("cin,cout", [(32, 32), (16, 32), (32, 16)])
+def test_conv_many_tiles_per_block_elementwise(cin, cout):
+    """more 16x16 tiles than the persistent grid holds blocks (each block walks
+    several tiles), ragged edges, a 1x1 image: every FP32 output within the
+    worst-case bound of an FP32 sum of 9 cin + 1 terms, |y - ref| <= n u / (1 - n u)
+    * (sum |w x| + |b|); the BF16 leaky-ReLU output and the flow output are the
+    FP32 output's own activation (rounded to nearest even) and channels 0-1, bit
+    for bit"""
+    sizes = [(600, 600), (37, 250), (1, 1)]
+    rng = np.random.default_rng(7 * cin + cout)
+    P = sum(h * w for h, w in sizes)
+    x = to_bf16(rng.normal(size=(P, cin)))
+    w = to_bf16(rng.normal(size=(cout, 9, cin)) * 0.2)
+    b = rng.normal(size=cout).astype(np.float32)
+    imgs = V.nn_images(sizes)
+    xd, wd, bd = dev(x), dev(w), dev(b)
+    y32 = torch.empty((P, cout), dtype=torch.float32, device="cuda:0")
+    y16 = torch.empty((P, cout), dtype=torch.int16, device="cuda:0")
+    yf = torch.empty((P, 2), dtype=torch.float32, device="cuda:0")
+    say(f"[conv {cin}->{cout}] {len(sizes)} images, {P} pixels")
+    V.check(conv_call(xd, cin, wd, bd, y32, cout, imgs, V.CONV_F32), "conv f32")
+    V.check(conv_call(xd, cin, wd, bd, y16, cout, imgs, V.CONV_LRELU), "conv lrelu")
+    V.check(conv_call(xd, cin, wd, bd, yf, cout, imgs, V.CONV_FLOW2), "conv flow2")
+    xs, off = [], 0
+    for (h, ww) in sizes:
+        xs.append(from_bf16(x)[off:off + h * ww].reshape(1, h, ww, cin))
+        off += h * ww
+    ref = np.concatenate([O.conv3x3(xi, from_bf16(w), b.astype(np.float64)).reshape(-1, cout) for xi in xs])
+    mag = np.concatenate([O.conv3x3(np.abs(xi), np.abs(from_bf16(w))).reshape(-1, cout) for xi in xs])
+    mag += np.abs(b.astype(np.float64))
+    n = 9 * cin + 1
+    u = 2.0 ** -24
+    bound = n * u / (1 - n * u) * mag
+    got = y32.cpu().numpy().astype(np.float64)
+    err = np.abs(got - ref)
+    say(f"[conv {cin}->{cout}] max |err| / bound = {float((err / np.maximum(bound, 1e-300)).max()):.3f}")
+    assert (err <= bound).all()
+    lre = np.where(got > 0, got, np.float32(0.1) * got.astype(np.float32))
+    np.testing.assert_array_equal(y16.cpu().numpy(), to_bf16(lre))
+    np.testing.assert_array_equal(yf.cpu().numpy(), y32.cpu().numpy()[:, :2])
+
+
+def test_conv_rejects_misaligned_pointers():
+    imgs = V.nn_images([(16, 16)])
+    x = torch.zeros(16 * 16 * 32 + 8, dtype=torch.int16, device="cuda:0")
+    w = torch.zeros(32 * 9 * 32, dtype=torch.int16, device="cuda:0")
+    y = torch.zeros(16 * 16 * 32 + 8, dtype=torch.int16, device="cuda:0")
+    xv = x[1:]                                      # 2 bytes past a 16-byte boundary
+    assert V.STATUS[conv_call(xv, 32, w, None, y, 32, imgs, V.CONV_LINEAR)] == "VS_E_INVAL"
+    assert V.STATUS[conv_call(x, 32, w, None, y[4:], 32, imgs, V.CONV_LINEAR)] == "VS_E_INVAL"
+    V.check(conv_call(x, 32, w, None, y[8:], 32, imgs, V.CONV_LINEAR), "aligned")
+    torch.cuda.synchronize()
+
+
 @pytest.mark.parametrize("cin,cout", [(16, 32), (32, 32), (32, 16)])
 def test_conv_forward_matches_oracle(cin, cout):
     rng = np.random.default_rng(cin * 100 + cout)
