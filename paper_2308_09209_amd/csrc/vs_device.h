@@ -11,18 +11,18 @@ namespace vs {
 // Conventions (section 3.1 pre-warp; section 2.1 eq. (4) colour application)
 // ---------------------------------------------------------------------------
 
+// v clamped to [lo, hi] (lo <= hi, v finite): the median of the three, one
+// v_med3_f32; a zero of either sign may come back for v = -0
 __device__ __forceinline__ float clampf(float v, float lo, float hi)
 {
-    return v < lo ? lo : (v > hi ? hi : v);
+    return __builtin_amdgcn_fmed3f(v, lo, hi);
 }
 
-// round half up to a byte
+// round half up to a byte: floor(r + 1/2) clamped to [0, 255] (the clamp
+// commutes with the floor for integer bounds)
 __device__ __forceinline__ uint32_t round8(float r)
 {
-    float f = floorf(r + 0.5f);
-    f = f < 0.0f ? 0.0f : f;
-    f = f > 255.0f ? 255.0f : f;
-    return (uint32_t)(int)f;
+    return (uint32_t)(int)floorf(__builtin_amdgcn_fmed3f(r + 0.5f, 0.0f, 255.0f));
 }
 
 // canvas -> camera homography; valid iff w > 0 and inside [0, W-1] x [0, H-1];
@@ -43,7 +43,24 @@ __device__ __forceinline__ bool hom(const float* __restrict__ h, float x, float 
     return (u >= 0.0f) && (u <= (float)(W - 1)) && (v >= 0.0f) && (v <= (float)(H - 1));
 }
 
-// bilinear resample of an HWC RGB byte image, position clamped into the image
+// the 6 bytes at A (a pixel pair of an RGB row) as two words: bytes 0-3 and
+// 4-5; three aligned 32-bit loads, each holding at least one of the 6 bytes
+// (the third is the second again unless the pair starts at byte 3 of a word)
+__device__ __forceinline__ void load_pair6(const uint8_t* A, uint32_t& lo, uint32_t& hi)
+{
+    const uintptr_t a = (uintptr_t)A;
+    const uint32_t* w = (const uint32_t*)(a & ~(uintptr_t)3);
+    const uint32_t w0 = w[0], w1 = w[1], w2 = *(const uint32_t*)((a + 5) & ~(uintptr_t)3);
+    const uint32_t sh = (uint32_t)(a & 3);
+    lo = __builtin_amdgcn_alignbyte(w1, w0, sh);
+    hi = __builtin_amdgcn_alignbyte(w2, w1, sh);
+}
+
+// bilinear resample of an HWC RGB byte image (W >= 2), position clamped into
+// the image; a = p00 + fx (p10 - p00), b likewise on the next row, out =
+// a + fy (b - a), each an FMA.  At the right border (x0 = W - 1, fx = 0) the
+// pair (W - 2, W - 1) with fx = 1 gives the same values exactly (byte-valued
+// samples), so every row pair is two in-row pixels.
 __device__ __forceinline__ void bilin3(const uint8_t* __restrict__ F, int pitch, int W, int H,
                                        float u, float v, float out[3])
 {
@@ -52,18 +69,22 @@ __device__ __forceinline__ void bilin3(const uint8_t* __restrict__ F, int pitch,
     float flx = floorf(uc), fly = floorf(vc);
     int x0 = (int)flx, y0 = (int)fly;
     float fx = uc - flx, fy = vc - fly;
-    int x1 = x0 + 1 < W ? x0 + 1 : W - 1;
+    if (x0 == W - 1) {
+        x0 = W - 2;
+        fx = 1.0f;
+    }
     int y1 = y0 + 1 < H ? y0 + 1 : H - 1;
-    const uint8_t* r0 = F + (size_t)y0 * pitch;
-    const uint8_t* r1 = F + (size_t)y1 * pitch;
+    uint32_t l0, h0, l1, h1;
+    load_pair6(F + (size_t)y0 * pitch + x0 * 3, l0, h0);
+    load_pair6(F + (size_t)y1 * pitch + x0 * 3, l1, h1);
+    const float p00[3] = {(float)(l0 & 255u), (float)((l0 >> 8) & 255u), (float)((l0 >> 16) & 255u)};
+    const float p10[3] = {(float)(l0 >> 24), (float)(h0 & 255u), (float)((h0 >> 8) & 255u)};
+    const float p01[3] = {(float)(l1 & 255u), (float)((l1 >> 8) & 255u), (float)((l1 >> 16) & 255u)};
+    const float p11[3] = {(float)(l1 >> 24), (float)(h1 & 255u), (float)((h1 >> 8) & 255u)};
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
-        float p00 = (float)r0[x0 * 3 + c];
-        float p10 = (float)r0[x1 * 3 + c];
-        float p01 = (float)r1[x0 * 3 + c];
-        float p11 = (float)r1[x1 * 3 + c];
-        float a = __builtin_fmaf(fx, p10 - p00, p00);
-        float b = __builtin_fmaf(fx, p11 - p01, p01);
+        float a = __builtin_fmaf(fx, p10[c] - p00[c], p00[c]);
+        float b = __builtin_fmaf(fx, p11[c] - p01[c], p01[c]);
         out[c] = __builtin_fmaf(fy, b - a, a);
     }
 }
