@@ -43,14 +43,23 @@ __device__ __forceinline__ bool hom(const float* __restrict__ h, float x, float 
     return (u >= 0.0f) && (u <= (float)(W - 1)) && (v >= 0.0f) && (v <= (float)(H - 1));
 }
 
+// a pointer into device (global) memory as such: its loads and stores become
+// global_* instructions, which count against the vector-memory counter only
+// (flat ones also hold back the waits of LDS operations)
+template <typename T>
+__device__ __forceinline__ __attribute__((address_space(1))) T* gmem(T* p)
+{
+    return (__attribute__((address_space(1))) T*)p;
+}
+
 // the 6 bytes at A (a pixel pair of an RGB row) as two words: bytes 0-3 and
 // 4-5; three aligned 32-bit loads, each holding at least one of the 6 bytes
 // (the third is the second again unless the pair starts at byte 3 of a word)
 __device__ __forceinline__ void load_pair6(const uint8_t* A, uint32_t& lo, uint32_t& hi)
 {
     const uintptr_t a = (uintptr_t)A;
-    const uint32_t* w = (const uint32_t*)(a & ~(uintptr_t)3);
-    const uint32_t w0 = w[0], w1 = w[1], w2 = *(const uint32_t*)((a + 5) & ~(uintptr_t)3);
+    const auto* w = gmem((const uint32_t*)(a & ~(uintptr_t)3));
+    const uint32_t w0 = w[0], w1 = w[1], w2 = *gmem((const uint32_t*)((a + 5) & ~(uintptr_t)3));
     const uint32_t sh = (uint32_t)(a & 3);
     lo = __builtin_amdgcn_alignbyte(w1, w0, sh);
     hi = __builtin_amdgcn_alignbyte(w2, w1, sh);

@@ -25,7 +25,7 @@ constexpr int LK_D = 8;                       // displacement the staged moving 
 constexpr int LKW_TX = 64;                    // 9x9-window flow kernel: 64 px wide, 4 * P rows,
                                               // P vertically adjacent pixels per thread
 constexpr int BL_TX = 256, BL_TY = 8;         // blend / balance tile: 256 x 8 px
-constexpr int BL_THREADS = 256;               // 64 quads of 4 px x 4 rows, 2 rows per thread
+constexpr int BL_THREADS = 256;               // 4 px per thread, 2 rows per thread
 constexpr int SURR_UP_ROWS = 4;               // surrogate upsampling: 64 x 4 px per block, one per thread
 constexpr int SURR_UP_SUB = STRIP_TY / SURR_UP_ROWS;   // upsampling blocks per strip tile
 

@@ -588,9 +588,14 @@ __device__ __forceinline__ void blend_body(const DevPlan* __restrict__ P, const 
     uint32_t* const my_hist = s_hist[tid & 7];
     const int bx = bid % P->blend_tx, by = bid / P->blend_tx;
     const int W = P->canvas_w, H = P->canvas_h, Wp = P->Wp;
-    const int xq = bx * BL_TX + (tid & 63) * 4;
+    // wavefront w takes the 64 columns [64 w, 64 w + 64) of the tile, 16 lanes
+    // of 4 pixels per row, 4 rows at a time: a wavefront's pixels lie in one
+    // narrow band, so few of them straddle the edge of an overlap (where both
+    // the one-camera and the two-camera code would run)
+    static_assert(BL_TX == 64 * (BL_THREADS / 64) && BL_TY % 4 == 0, "blend tile = 4 x 64-column bands");
+    const int xq = bx * BL_TX + (tid >> 6) * 64 + (tid & 15) * 4;
     const bool vec = (W & 3) == 0;
-    for (int r = tid >> 6; r < BL_TY; r += BL_THREADS / 64) {
+    for (int r = (tid & 63) >> 4; r < BL_TY; r += 4) {
         const int y = by * BL_TY + r;
         if (y >= H || xq >= W) continue;
         uint32_t ob[12];
@@ -598,7 +603,7 @@ __device__ __forceinline__ void blend_body(const DevPlan* __restrict__ P, const 
         for (int q = 0; q < 4; ++q) {
             const int x = xq + q;
             uint32_t o0 = 0, o1 = 0, o2 = 0;
-            const uint32_t code = x < W ? P->pix_code[(size_t)y * W + x] : 0u;
+            const uint32_t code = x < W ? gmem(P->pix_code)[(size_t)y * W + x] : 0u;
             const int nh = (int)(code >> 12);
             if (nh > 0) {
                 // the covering (camera, shift) candidates found at plan time, in
@@ -636,8 +641,9 @@ __device__ __forceinline__ void blend_body(const DevPlan* __restrict__ P, const 
                     const float thj = 1.0f - thi;
                     const int lx = x + mj * Wp - P->sx0[p], ly = y - P->sy0[p];
                     const size_t qf = (size_t)ly * P->sw[p] + lx;
-                    const float2 fij = P->flow[p][0][0][qf];
-                    const float2 fji = P->flow[p][1][0][qf];
+                    typedef float f2v __attribute__((ext_vector_type(2)));
+                    const f2v fij = gmem((const f2v*)P->flow[p][0][0])[qf];
+                    const f2v fji = gmem((const f2v*)P->flow[p][1][0])[qf];
                     const float Xi = __builtin_fmaf(thj, fij.x, (float)(x + mi * Wp));
                     const float Yi = __builtin_fmaf(thj, fij.y, (float)y);
                     const float Xj = __builtin_fmaf(thi, fji.x, (float)(x + mj * Wp));
@@ -670,9 +676,10 @@ __device__ __forceinline__ void blend_body(const DevPlan* __restrict__ P, const 
             ob[q * 3 + 1] = o1;
             ob[q * 3 + 2] = o2;
         }
-        uint8_t* row = P->pano + (size_t)y * P->pano_pitch + (size_t)xq * 3;
+        uint8_t* const prow = P->pano + (size_t)y * P->pano_pitch + (size_t)xq * 3;
+        auto* row = gmem(prow);
         if (vec && xq + 3 < W) {
-            uint32_t* r32 = (uint32_t*)row;
+            auto* r32 = gmem((uint32_t*)prow);
             r32[0] = ob[0] | (ob[1] << 8) | (ob[2] << 16) | (ob[3] << 24);
             r32[1] = ob[4] | (ob[5] << 8) | (ob[6] << 16) | (ob[7] << 24);
             r32[2] = ob[8] | (ob[9] << 8) | (ob[10] << 16) | (ob[11] << 24);
