@@ -1199,6 +1199,20 @@ vs_status vs_debug_tap(vs_ctx* c, int tap, int p, int sub, void* dst, size_t nby
         VS_CHECK(hipMemcpy(dst, src, have, hipMemcpyDeviceToHost), "hipMemcpy tap");
         return VS_OK;
     };
+    // a sum kept in `copies` consecutive copies of `words` 32-bit counters
+    auto copy_summed = [&](const uint32_t* src, size_t words, int copies) -> vs_status {
+        if (nbytes != words * 4) return fail(c, VS_E_INVAL, "tap size mismatch");
+        std::vector<uint32_t> all(words * copies);
+        VS_CHECK(hipDeviceSynchronize(), "hipDeviceSynchronize");
+        VS_CHECK(hipMemcpy(all.data(), src, all.size() * 4, hipMemcpyDeviceToHost), "hipMemcpy tap");
+        uint32_t* d = (uint32_t*)dst;
+        for (size_t i = 0; i < words; ++i) {
+            uint32_t t = 0;
+            for (int k = 0; k < copies; ++k) t += all[(size_t)k * words + i];
+            d[i] = t;
+        }
+        return VS_OK;
+    };
     switch (tap) {
     case VS_TAP_STRIP: {
         if (!pair_ok || sub < 0 || sub > 1) return VS_E_INVAL;
@@ -1220,7 +1234,7 @@ vs_status vs_debug_tap(vs_ctx* c, int tap, int p, int sub, void* dst, size_t nby
         return copy(h.mask[p], n);
     case VS_TAP_HIST:
         if (!pair_ok) return VS_E_INVAL;
-        return copy(&h.acc->hist[p][0][0][0], sizeof(uint32_t) * 2 * 3 * 256);
+        return copy_summed(&h.acc->hist[p][0][0][0][0], 2 * 3 * 256, HIST_SPREAD);
     case VS_TAP_LUT:
         if (!pair_ok) return VS_E_INVAL;
         return copy(&h.res->lut[p][0][0], 3 * 256);
@@ -1245,7 +1259,7 @@ vs_status vs_debug_tap(vs_ctx* c, int tap, int p, int sub, void* dst, size_t nby
         if (!c->pano_pre) return fail(c, VS_E_UNSUPPORTED, "pre-balance panorama needs debug_taps = 1");
         return copy(c->pano_pre, (size_t)h.canvas_h * h.pano_pitch);
     case VS_TAP_PANO_HIST:
-        return copy(&h.acc->pano_hist[0][0], 3 * 256 * 4);
+        return copy_summed(&h.acc->pano_hist[0][0][0], 3 * 256, PANO_SPREAD);
     case VS_TAP_BAL_LUT:
         return copy(&h.res->bal_lut[0][0], 3 * 256);
     case VS_TAP_QUANT:

@@ -30,13 +30,17 @@ constexpr int SURR_UP_ROWS = 4;               // surrogate upsampling: 64 x 4 px
 constexpr int SURR_UP_SUB = STRIP_TY / SURR_UP_ROWS;   // upsampling blocks per strip tile
 
 // Per-frame accumulators, zeroed at the start of every frame.
+// Sums that many blocks add to are kept in several copies (tile t adds to copy
+// t % SPREAD, the consumer adds the copies): device-scope atomics on one
+// address from every block of a large grid serialise in the memory system.
+constexpr int HIST_SPREAD = 16, MOM_SPREAD = 32, PANO_SPREAD = 32;
+constexpr int SOLVE_THREADS = 256;
+enum { MOM_A = 0, MOM_N = 6, MOM_B = 7 };   // mom[][][]: A (6), n, B (9): 16 sums, one 128-byte line
 struct Accum {
-    uint32_t hist[MAXP][2][3][256];   // [pair][0 = camera j, 1 = camera i][channel][level]
-    unsigned long long A[MAXP][6];
-    unsigned long long B[MAXP][9];
-    unsigned long long n[MAXP];
-    uint32_t pano_hist[3][256];
-    uint32_t lk_qn[8];                // flow pixels deferred to the tail kernel, per level
+    uint32_t hist[MAXP][HIST_SPREAD][2][3][256];   // [pair][copy][0 = camera j, 1 = camera i][channel][level]
+    unsigned long long mom[MAXP][MOM_SPREAD][16];
+    uint32_t pano_hist[PANO_SPREAD][3][256];
+    uint32_t lk_qn[8];                             // flow pixels deferred to the tail kernel, per level
 };
 static_assert(MAXL <= 8, "one deferral counter per level");
 static_assert(sizeof(Accum) % 16 == 0, "k_zero clears whole 16-byte words");

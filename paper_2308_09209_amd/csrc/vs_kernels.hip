@@ -207,14 +207,11 @@ __device__ __forceinline__ void strips_body(const DevPlan* __restrict__ P, const
     }
     __syncthreads();
     Accum* acc = P->acc;
-    if (tid < 7) {
+    if (tid < 7) {   // A (6) then n: mom slots 0-6
         unsigned long long s = (unsigned long long)s_red[0][tid] + s_red[1][tid] + s_red[2][tid] + s_red[3][tid];
-        if (s) {
-            if (tid < 6) atomicAdd(&acc->A[p][tid], s);
-            else atomicAdd(&acc->n[p], s);
-        }
+        if (s) atomicAdd(&acc->mom[p][t % MOM_SPREAD][MOM_A + tid], s);
     }
-    uint32_t* gh = &acc->hist[p][0][0][0];
+    uint32_t* gh = &acc->hist[p][t % HIST_SPREAD][0][0][0];
     for (int i = tid; i < 2 * 3 * 256; i += 256) {
         const uint32_t h = s_hist[0][i] + s_hist[1][i] + s_hist[2][i] + s_hist[3][i];
         if (h) atomicAdd(&gh[i], h);
@@ -239,8 +236,13 @@ __device__ __forceinline__ void lut_body(const DevPlan* __restrict__ P, const in
     const int p = bid, v = threadIdx.x;
     const Accum* acc = P->acc;
     for (int c = 0; c < 3; ++c) {
-        Cj[c][v] = acc->hist[p][0][c][v];
-        Ci[c][v] = acc->hist[p][1][c][v];
+        uint32_t sj = 0, si = 0;
+        for (int k = 0; k < HIST_SPREAD; ++k) {
+            sj += acc->hist[p][k][0][c][v];
+            si += acc->hist[p][k][1][c][v];
+        }
+        Cj[c][v] = sj;
+        Ci[c][v] = si;
     }
     __syncthreads();
     for (int o = 1; o < 256; o <<= 1) {
@@ -327,7 +329,7 @@ __device__ __forceinline__ void moments_b_body(const DevPlan* __restrict__ P, co
     __syncthreads();
     if (tid < 9) {
         unsigned long long s = (unsigned long long)s_red[0][tid] + s_red[1][tid] + s_red[2][tid] + s_red[3][tid];
-        if (s) atomicAdd(&P->acc->B[p][tid], s);
+        if (s) atomicAdd(&P->acc->mom[p][t % MOM_SPREAD][MOM_B + tid], s);
     }
 }
 
@@ -396,16 +398,27 @@ __device__ int solve3(const double* A, const double* B, double ridge, double* M)
 __device__ __forceinline__ void solve_body(const DevPlan* __restrict__ P, const int bid)
 {
     __shared__ double s_M[MAXP][9];
+    __shared__ unsigned long long s_mom[MAXP][16];
     const int tid = threadIdx.x;
     Accum* acc = P->acc;
     Results* res = P->res;
     vs_color_state* st = P->state;
+    // the copies of each sum, one (pair, sum) per thread
+    static_assert(MAXP * 16 <= SOLVE_THREADS, "one thread per (pair, sum)");
+    if (tid < P->n_pairs * 16) {
+        const int p = tid >> 4, j = tid & 15;
+        unsigned long long s = 0;
+#pragma unroll 8
+        for (int k = 0; k < MOM_SPREAD; ++k) s += acc->mom[p][k][j];
+        s_mom[p][j] = s;
+    }
+    __syncthreads();
     if (tid < P->n_pairs) {
         const int p = tid;
         unsigned long long A[6], B[9], n;
-        for (int i = 0; i < 6; ++i) A[i] = acc->A[p][i];
-        for (int i = 0; i < 9; ++i) B[i] = acc->B[p][i];
-        n = acc->n[p];
+        for (int i = 0; i < 6; ++i) A[i] = s_mom[p][MOM_A + i];
+        for (int i = 0; i < 9; ++i) B[i] = s_mom[p][MOM_B + i];
+        n = s_mom[p][MOM_N];
         for (int i = 0; i < 6; ++i) res->mom[p][i] = A[i];
         for (int i = 0; i < 9; ++i) res->mom[p][6 + i] = B[i];
         res->mom[p][15] = n;
@@ -461,7 +474,7 @@ __device__ __forceinline__ void solve_body(const DevPlan* __restrict__ P, const 
     }
 }
 
-__global__ __launch_bounds__(64) void k_solve(const Batch B)
+__global__ __launch_bounds__(SOLVE_THREADS) void k_solve(const Batch B)
 {
     int c;
     const int b = batch_block(B, blockIdx.x, c);
@@ -692,7 +705,7 @@ __device__ __forceinline__ void blend_body(const DevPlan* __restrict__ P, const 
         }
     }
     __syncthreads();
-    uint32_t* gh = &P->acc->pano_hist[0][0];
+    uint32_t* gh = &P->acc->pano_hist[bid % PANO_SPREAD][0][0];
     for (int i = tid; i < 3 * 256; i += BL_THREADS) {
         uint32_t h = 0;
 #pragma unroll
@@ -722,7 +735,9 @@ __device__ __forceinline__ void balance_lut_body(const DevPlan* __restrict__ P, 
     const int tid = threadIdx.x, c = tid >> 8, v = tid & 255;
     vs_color_state* st = P->state;
     Results* res = P->res;
-    C[c][v] = P->acc->pano_hist[c][v];
+    uint32_t hs = 0;
+    for (int k = 0; k < PANO_SPREAD; ++k) hs += P->acc->pano_hist[k][c][v];
+    C[c][v] = hs;
     __syncthreads();
     for (int o = 1; o < 256; o <<= 1) {
         const uint32_t t = v >= o ? C[c][v - o] : 0;
@@ -895,7 +910,7 @@ hipError_t launch_solve(const Group& g, hipStream_t s)
 {
     Batch B;
     if (make_batch(g, B, [](const DevPlan&) { return 1; }))
-        hipLaunchKernelGGL(k_solve, dim3(B.off[B.n]), dim3(64), 0, s, B);
+        hipLaunchKernelGGL(k_solve, dim3(B.off[B.n]), dim3(SOLVE_THREADS), 0, s, B);
     return hipGetLastError();
 }
 
