@@ -186,7 +186,9 @@ vs_status vs_state_set(vs_ctx* c, const vs_color_state* in);
  *  VS_TAP_LUT       pair: [3][256] u8 histogram-specification LUT
  *  VS_TAP_MOM       pair: 16 u64 = A[6], B[9], n of this frame
  *  VS_TAP_MPAIR     [n_pairs][9] f64;  VS_TAP_MK [n_cams][9] f32;  VS_TAP_FLAGS [n_pairs] i32
- *  VS_TAP_PYR       pair, sub = cam * 8 + level: level image f32
+ *  VS_TAP_PYR       pair, sub = cam * 8 + level: level image f32 (with
+ *                   VS_FLOW_SURROGATE_FALLBACK, levels above 2 of a pair that
+ *                   kept the surrogate's flows are not computed that frame)
  *  VS_TAP_FLOW      pair, sub 0 = flow_ij, 1 = flow_ji: strip_h x strip_w x 2 f32
  *  VS_TAP_PANO_PRE  canvas_h x canvas_w x 3 u8 (needs debug_taps = 1)
  *  VS_TAP_PANO_HIST [3][256] u32;  VS_TAP_BAL_LUT [3][256] u8

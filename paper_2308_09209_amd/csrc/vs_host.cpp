@@ -545,7 +545,8 @@ hipError_t enqueue_frame(const Group& g, hipStream_t s, hipEvent_t* ev, uint8_t*
     VS_STEP(launch_solve(g, s), "solve");
     if (ev) VS_STEP(hipEventRecord(ev[1], s), "hipEventRecord");
     VS_STEP(launch_pyr0(g, s), "pyr0");
-    for (int l = 0; l + 1 < levels; ++l) VS_STEP(launch_pyr_down(g, l, s), "pyr_down");
+    // the levels the surrogate reads; the ones above it follow its decisions
+    for (int l = 0; l + 1 < levels && l < SURR_LEVEL; ++l) VS_STEP(launch_pyr_down(g, l, s), "pyr_down");
     if (ev) VS_STEP(hipEventRecord(ev[2], s), "hipEventRecord");
     int n_surr = 0;
     for (int c = 0; c < g.n; ++c) n_surr += surrogate_active(g, c) ? 1 : 0;
@@ -563,6 +564,7 @@ hipError_t enqueue_frame(const Group& g, hipStream_t s, hipEvent_t* ev, uint8_t*
     } else {
         VS_STEP(launch_surrogate(g, s), "surrogate");
     }
+    for (int l = SURR_LEVEL; l + 1 < levels; ++l) VS_STEP(launch_pyr_down(g, l, s), "pyr_down");
     for (int l = levels - 1; l >= 0; --l) VS_STEP(launch_lk(g, l, s), "flow");
     if (ev) VS_STEP(hipEventRecord(ev[3], s), "hipEventRecord");
     VS_STEP(launch_blend(g, s), "blend");

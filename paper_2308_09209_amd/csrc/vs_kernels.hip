@@ -531,6 +531,9 @@ __device__ __forceinline__ void pyr_down_body(const DevPlan* __restrict__ P, con
     const int lo = l + 1;
     const int f = find_field(P->pyr_off[lo], 2 * P->n_pairs, bid);
     const int p = f >> 1, cam = f & 1;
+    // levels above the surrogate's are read by the plain estimator only: a
+    // pair that keeps the surrogate's flows skips them
+    if (lo > SURR_LEVEL && P->flow_mode == VS_FLOW_SURROGATE_FALLBACK && P->res->surr_ok[p]) return;
     const int t = bid - P->pyr_off[lo][f];
     const int ws = P->lw[p][l], hs = P->lh[p][l];
     const int wd = P->lw[p][lo], hd = P->lh[p][lo];
