@@ -120,6 +120,13 @@ __device__ __forceinline__ uint32_t wave_sum(uint32_t v)
 }
 
 
+// the pair keeps the surrogate's flows this frame (the plain estimator and
+// the pyramid levels only it reads skip the pair)
+__device__ __forceinline__ bool kept_by_surrogate(const DevPlan* __restrict__ P, int p)
+{
+    return P->flow_mode == VS_FLOW_SURROGATE_FALLBACK && P->res->surr_ok[p];
+}
+
 __device__ __forceinline__ int find_field(const int32_t* off, int n, int b)
 {
     int f = 0;

@@ -317,6 +317,13 @@ vs_status vs_create(const vs_rig* rig, const vs_params* prm, vs_ctx** out)
         h.strip_tx[p] = (h.sw[p] + STRIP_TX - 1) / STRIP_TX;
         h.strip_off[p + 1] = h.strip_off[p] + h.strip_tx[p] * ((h.sh[p] + STRIP_TY - 1) / STRIP_TY);
     }
+    h.pyrf_off[0] = 0;
+    for (int f = 0; f < 2 * h.n_pairs; ++f) {
+        const int p = f >> 1;
+        const int w2 = h.levels >= 3 ? h.lw[p][2] : 0, h2 = h.levels >= 3 ? h.lh[p][2] : 0;
+        h.pyrf_tx[f] = (w2 + PF_TX - 1) / PF_TX;
+        h.pyrf_off[f + 1] = h.pyrf_off[f] + h.pyrf_tx[f] * ((h2 + PF_TY - 1) / PF_TY);
+    }
     for (int l = 0; l < h.levels; ++l) {
         h.pyr_off[l][0] = 0;
         for (int f = 0; f < 2 * h.n_pairs; ++f) {
@@ -544,9 +551,11 @@ hipError_t enqueue_frame(const Group& g, hipStream_t s, hipEvent_t* ev, uint8_t*
     VS_STEP(launch_moments_b(g, s), "moments");
     VS_STEP(launch_solve(g, s), "solve");
     if (ev) VS_STEP(hipEventRecord(ev[1], s), "hipEventRecord");
-    VS_STEP(launch_pyr0(g, s), "pyr0");
-    // the levels the surrogate reads; the ones above it follow its decisions
-    for (int l = 0; l + 1 < levels && l < SURR_LEVEL; ++l) VS_STEP(launch_pyr_down(g, l, s), "pyr_down");
+    // pyramids of 3+ levels: levels 0-2 in one pass (plain flow: all three
+    // written; surrogate modes: level 2, its input); fewer levels: level by level
+    VS_STEP(launch_pyr0(g, PYR_UNFUSED, s), "pyr0");
+    for (int l = 0; l + 1 < levels; ++l) VS_STEP(launch_pyr_down(g, l, PYR_UNFUSED, s), "pyr_down");
+    VS_STEP(launch_pyr_fused(g, s), "pyr_fused");
     if (ev) VS_STEP(hipEventRecord(ev[2], s), "hipEventRecord");
     int n_surr = 0;
     for (int c = 0; c < g.n; ++c) n_surr += surrogate_active(g, c) ? 1 : 0;
@@ -564,7 +573,9 @@ hipError_t enqueue_frame(const Group& g, hipStream_t s, hipEvent_t* ev, uint8_t*
     } else {
         VS_STEP(launch_surrogate(g, s), "surrogate");
     }
-    for (int l = SURR_LEVEL; l + 1 < levels; ++l) VS_STEP(launch_pyr_down(g, l, s), "pyr_down");
+    // what the plain estimator still needs, after the surrogate's decisions
+    VS_STEP(launch_pyr0(g, PYR_AFTER, s), "pyr0");
+    for (int l = 0; l + 1 < levels; ++l) VS_STEP(launch_pyr_down(g, l, PYR_AFTER, s), "pyr_down");
     for (int l = levels - 1; l >= 0; --l) VS_STEP(launch_lk(g, l, s), "flow");
     if (ev) VS_STEP(hipEventRecord(ev[3], s), "hipEventRecord");
     VS_STEP(launch_blend(g, s), "blend");
@@ -1167,7 +1178,7 @@ vs_status vs_flow_run(vs_flow* f, const float* yt, const float* ym, float* flow_
     hipError_t e = hipMemcpyAsync(d.pyr[0][0][0], yt, n * 4, hipMemcpyDeviceToDevice, s);
     if (e == hipSuccess) e = hipMemcpyAsync(d.pyr[0][1][0], ym, n * 4, hipMemcpyDeviceToDevice, s);
     if (e == hipSuccess) e = launch_zero(g, s);
-    for (int l = 0; l + 1 < d.levels && e == hipSuccess; ++l) e = launch_pyr_down(g, l, s);
+    for (int l = 0; l + 1 < d.levels && e == hipSuccess; ++l) e = launch_pyr_down(g, l, PYR_ALL, s);
     for (int l = d.levels - 1; l >= 0 && e == hipSuccess; --l) e = launch_lk(g, l, s);
     if (e == hipSuccess && flow_tm) e = hipMemcpyAsync(flow_tm, d.flow[0][0][0], n * 8, hipMemcpyDeviceToDevice, s);
     if (e == hipSuccess && flow_mt) e = hipMemcpyAsync(flow_mt, d.flow[0][1][0], n * 8, hipMemcpyDeviceToDevice, s);

@@ -486,10 +486,13 @@ __global__ __launch_bounds__(SOLVE_THREADS) void k_solve(const Batch B)
 // Flow input: luma of the colour-corrected strips, then the 2x pyramid
 // ---------------------------------------------------------------------------
 
-__device__ __forceinline__ void pyr0_body(const DevPlan* __restrict__ P, const int bid)
+// skip_kept: launched after the surrogate's decisions, for the plain
+// estimator of the pairs that did not keep its flows
+__device__ __forceinline__ void pyr0_body(const DevPlan* __restrict__ P, const int bid, int skip_kept)
 {
     const int f = find_field(P->pyr_off[0], 2 * P->n_pairs, bid);
     const int p = f >> 1, cam = f & 1;
+    if (skip_kept && kept_by_surrogate(P, p)) return;
     const int t = bid - P->pyr_off[0][f];
     const int w = P->sw[p], h = P->sh[p];
     const int tx0 = (t % P->pyr_tx[0][f]) * PYR_TX, ty0 = (t / P->pyr_tx[0][f]) * PYR_TY;
@@ -515,25 +518,23 @@ __device__ __forceinline__ void pyr0_body(const DevPlan* __restrict__ P, const i
     }
 }
 
-__global__ __launch_bounds__(256) void k_pyr0(const Batch B)
+__global__ __launch_bounds__(256) void k_pyr0(const Batch B, int skip_kept)
 {
     int c;
     const int b = batch_block(B, blockIdx.x, c);
-    pyr0_body(B.plan[c], b);
+    pyr0_body(B.plan[c], b, skip_kept);
 }
 
 
 
 // level l -> l + 1: separable [1 4 6 4 1] / 16, horizontal first, clamped,
 // even positions; each pass ((((a0 + 4 a1) + 6 a2) + 4 a3) + a4) / 16
-__device__ __forceinline__ void pyr_down_body(const DevPlan* __restrict__ P, const int bid, int l)
+__device__ __forceinline__ void pyr_down_body(const DevPlan* __restrict__ P, const int bid, int l, int skip_kept)
 {
     const int lo = l + 1;
     const int f = find_field(P->pyr_off[lo], 2 * P->n_pairs, bid);
     const int p = f >> 1, cam = f & 1;
-    // levels above the surrogate's are read by the plain estimator only: a
-    // pair that keeps the surrogate's flows skips them
-    if (lo > SURR_LEVEL && P->flow_mode == VS_FLOW_SURROGATE_FALLBACK && P->res->surr_ok[p]) return;
+    if (skip_kept && kept_by_surrogate(P, p)) return;
     const int t = bid - P->pyr_off[lo][f];
     const int ws = P->lw[p][l], hs = P->lh[p][l];
     const int wd = P->lw[p][lo], hd = P->lh[p][lo];
@@ -566,11 +567,135 @@ __device__ __forceinline__ void pyr_down_body(const DevPlan* __restrict__ P, con
     }
 }
 
-__global__ __launch_bounds__(256) void k_pyr_down(const Batch B, int l)
+__global__ __launch_bounds__(256) void k_pyr_down(const Batch B, int l, int skip_kept)
 {
     int c;
     const int b = batch_block(B, blockIdx.x, c);
-    pyr_down_body(B.plan[c], b, l);
+    pyr_down_body(B.plan[c], b, l, skip_kept);
+}
+
+// Levels 0-2 in one pass (pyramids of 3 or more levels).  A block takes a
+// PF_TX x PF_TY tile of level 2 of one field.  The level-0 luma of the tile's
+// footprint at clamped positions (4 PF_TX + 9 columns, 4 PF_TY + 9 rows)
+// goes to LDS as bytes, level 1 at the footprint's clamped positions is
+// reduced from it, level 2 from that: every horizontal and vertical sum is
+// the one pyr0 / pyr_down compute, with the same operands in the same order,
+// done once per block instead of once per output row.  The tile interiors of
+// levels 0 and 1 are written too when the plain estimator reads them this
+// frame (VS_FLOW_PLAIN); otherwise only level 2, the surrogate's input.
+constexpr int PF_W1 = 2 * PF_TX + 3, PF_H1 = 2 * PF_TY + 3;     // level-1 footprint
+constexpr int PF_W0 = 4 * PF_TX + 9, PF_H0 = 4 * PF_TY + 9;     // level-0 footprint
+
+__device__ __forceinline__ float tap5(float a0, float a1, float a2, float a3, float a4)
+{
+    float acc = a0 + 4.0f * a1;
+    acc = acc + 6.0f * a2;
+    acc = acc + 4.0f * a3;
+    acc = acc + a4;
+    return acc * 0.0625f;
+}
+
+__device__ __forceinline__ void pyr_fused_body(const DevPlan* __restrict__ P, const int bid)
+{
+    __shared__ uint8_t s0[PF_H0][PF_W0 + 3];
+    __shared__ float sh[PF_H0 * PF_W1];    // level-0 rows at level-1 columns; then level-1 rows at level-2 columns
+    __shared__ float s1[PF_H1][PF_W1];
+    const int tid = threadIdx.x;
+    const int f = find_field(P->pyrf_off, 2 * P->n_pairs, bid);
+    const int p = f >> 1, cam = f & 1;
+    const int t = bid - P->pyrf_off[f];
+    const int w0 = P->lw[p][0], h0 = P->lh[p][0];
+    const int w1 = P->lw[p][1], h1 = P->lh[p][1];
+    const int w2 = P->lw[p][2], h2 = P->lh[p][2];
+    const int X0 = (t % P->pyrf_tx[f]) * PF_TX, Y0 = (t / P->pyrf_tx[f]) * PF_TY;
+    const int bx0 = 4 * X0 - 6, by0 = 4 * Y0 - 6;       // footprint origins, before clamping
+    const int bx1 = 2 * X0 - 2, by1 = 2 * Y0 - 2;
+    const bool write01 = P->flow_mode == VS_FLOW_PLAIN;
+    const float* M = P->res->Mk[cam == 0 ? P->pj[p] : P->pi[p]];
+    const uint32_t* __restrict__ src = P->strip[p] + (size_t)cam * h0 * w0;
+    float* __restrict__ L0 = P->pyr[p][cam][0];
+    float* __restrict__ L1 = P->pyr[p][cam][1];
+    float* __restrict__ L2 = P->pyr[p][cam][2];
+
+    // level 0: luma of the colour-corrected strip, 8 loads in flight per thread
+    constexpr int N0 = PF_H0 * PF_W0, NB = 8;
+    for (int i0 = 0; i0 < N0; i0 += 256 * NB) {
+        uint32_t pix[NB];
+#pragma unroll
+        for (int k = 0; k < NB; ++k) {
+            const int i = i0 + k * 256 + tid;
+            pix[k] = 0u;
+            if (i < N0) {
+                const int yy = clampi(by0 + i / PF_W0, 0, h0 - 1), xx = clampi(bx0 + i % PF_W0, 0, w0 - 1);
+                pix[k] = src[(size_t)yy * w0 + xx];
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < NB; ++k) {
+            const int i = i0 + k * 256 + tid;
+            if (i >= N0) continue;
+            const float s[3] = {(float)(pix[k] & 255u), (float)((pix[k] >> 8) & 255u),
+                                (float)((pix[k] >> 16) & 255u)};
+            const uint32_t c0 = round8(capply(s, M, 0)), c1 = round8(capply(s, M, 1)), c2 = round8(capply(s, M, 2));
+            const uint32_t Y = (77u * c0 + 150u * c1 + 29u * c2 + 128u) >> 8;
+            const int r = i / PF_W0, c = i % PF_W0;
+            s0[r][c] = (uint8_t)Y;
+            if (write01 && r >= 6 && r < 6 + 4 * PF_TY && c >= 6 && c < 6 + 4 * PF_TX) {
+                const int yy = by0 + r, xx = bx0 + c;
+                if (yy < h0 && xx < w0) L0[(size_t)yy * w0 + xx] = (float)Y;
+            }
+        }
+    }
+    __syncthreads();
+    // level 1, horizontal: footprint rows at level-1 columns clamp(bx1 + i)
+    for (int i = tid; i < PF_H0 * PF_W1; i += 256) {
+        const int r = i / PF_W1, c1 = clampi(bx1 + i % PF_W1, 0, w1 - 1);
+        const uint8_t* row = s0[r];
+        float a[5];
+#pragma unroll
+        for (int k = 0; k < 5; ++k) a[k] = (float)row[clampi(2 * c1 - 2 + k, 0, w0 - 1) - bx0];
+        sh[i] = tap5(a[0], a[1], a[2], a[3], a[4]);
+    }
+    __syncthreads();
+    // level 1, vertical: at level-1 rows clamp(by1 + j)
+    for (int i = tid; i < PF_H1 * PF_W1; i += 256) {
+        const int j = i / PF_W1, c = i % PF_W1;
+        const int r1 = clampi(by1 + j, 0, h1 - 1);
+        float a[5];
+#pragma unroll
+        for (int k = 0; k < 5; ++k) a[k] = sh[(clampi(2 * r1 - 2 + k, 0, h0 - 1) - by0) * PF_W1 + c];
+        const float v = tap5(a[0], a[1], a[2], a[3], a[4]);
+        s1[j][c] = v;
+        if (write01 && j >= 2 && j < 2 + 2 * PF_TY && c >= 2 && c < 2 + 2 * PF_TX) {
+            const int yy = by1 + j, xx = bx1 + c;
+            if (yy < h1 && xx < w1) L1[(size_t)yy * w1 + xx] = v;
+        }
+    }
+    __syncthreads();
+    // level 2, horizontal (into sh, free again)
+    for (int i = tid; i < PF_H1 * PF_TX; i += 256) {
+        const int j = i / PF_TX, x2 = X0 + i % PF_TX;
+        float a[5];
+#pragma unroll
+        for (int k = 0; k < 5; ++k) a[k] = s1[j][clampi(2 * x2 - 2 + k, 0, w1 - 1) - bx1];
+        sh[i] = tap5(a[0], a[1], a[2], a[3], a[4]);
+    }
+    __syncthreads();
+    // level 2, vertical
+    for (int i = tid; i < PF_TY * PF_TX; i += 256) {
+        const int y2 = Y0 + i / PF_TX, xi = i % PF_TX, x2 = X0 + xi;
+        float a[5];
+#pragma unroll
+        for (int k = 0; k < 5; ++k) a[k] = sh[(clampi(2 * y2 - 2 + k, 0, h1 - 1) - by1) * PF_TX + xi];
+        if (x2 < w2 && y2 < h2) L2[(size_t)y2 * w2 + x2] = tap5(a[0], a[1], a[2], a[3], a[4]);
+    }
+}
+
+__global__ __launch_bounds__(256) void k_pyr_fused(const Batch B)
+{
+    int c;
+    const int b = batch_block(B, blockIdx.x, c);
+    pyr_fused_body(B.plan[c], b);
 }
 
 
@@ -917,22 +1042,47 @@ hipError_t launch_solve(const Group& g, hipStream_t s)
     return hipGetLastError();
 }
 
-hipError_t launch_pyr0(const Group& g, hipStream_t s)
+// Which contexts a pyramid launch covers: PYR_ALL every flow context (the
+// label context); PYR_UNFUSED those with fewer than 3 levels, before the
+// surrogate; PYR_AFTER, after the surrogate's decisions, the levels the fused
+// kernel did not write that the plain estimator reads (levels 0 and 1 of a
+// fallback context, levels above 2 of any context with plain flow), pairs
+// that kept the surrogate's flows skipping them.
+static bool pyr_level_launched(const DevPlan& h, int lo, int phase)
+{
+    if (!h.use_flow || lo >= h.levels) return false;
+    if (phase == PYR_ALL) return true;
+    const bool fused = h.levels >= 3;
+    if (phase == PYR_UNFUSED) return !fused;
+    if (!fused) return false;
+    if (lo <= 1) return h.flow_mode == VS_FLOW_SURROGATE_FALLBACK;
+    if (lo == 2) return false;
+    return h.flow_mode != VS_FLOW_SURROGATE;
+}
+
+hipError_t launch_pyr0(const Group& g, int phase, hipStream_t s)
 {
     Batch B;
-    if (make_batch(g, B, [](const DevPlan& h) { return h.use_flow ? h.pyr_off[0][2 * h.n_pairs] : 0; }))
-        hipLaunchKernelGGL(k_pyr0, dim3(B.off[B.n]), dim3(256), 0, s, B);
+    if (make_batch(g, B, [&](const DevPlan& h) {
+            return pyr_level_launched(h, 0, phase) ? h.pyr_off[0][2 * h.n_pairs] : 0; }))
+        hipLaunchKernelGGL(k_pyr0, dim3(B.off[B.n]), dim3(256), 0, s, B, phase == PYR_AFTER ? 1 : 0);
     return hipGetLastError();
 }
 
-hipError_t launch_pyr_down(const Group& g, int l, hipStream_t s)
+hipError_t launch_pyr_fused(const Group& g, hipStream_t s)
 {
     Batch B;
-    // the surrogate alone reads no level beyond its own
-    if (make_batch(g, B, [l](const DevPlan& h) {
-            const int top = h.flow_mode == VS_FLOW_SURROGATE ? SURR_LEVEL + 1 : h.levels;
-            return h.use_flow && l + 1 < top ? h.pyr_off[l + 1][2 * h.n_pairs] : 0; }))
-        hipLaunchKernelGGL(k_pyr_down, dim3(B.off[B.n]), dim3(256), 0, s, B, l);
+    if (make_batch(g, B, [](const DevPlan& h) { return h.use_flow && h.levels >= 3 ? h.pyrf_off[2 * h.n_pairs] : 0; }))
+        hipLaunchKernelGGL(k_pyr_fused, dim3(B.off[B.n]), dim3(256), 0, s, B);
+    return hipGetLastError();
+}
+
+hipError_t launch_pyr_down(const Group& g, int l, int phase, hipStream_t s)
+{
+    Batch B;
+    if (make_batch(g, B, [&](const DevPlan& h) {
+            return pyr_level_launched(h, l + 1, phase) ? h.pyr_off[l + 1][2 * h.n_pairs] : 0; }))
+        hipLaunchKernelGGL(k_pyr_down, dim3(B.off[B.n]), dim3(256), 0, s, B, l, phase == PYR_AFTER ? 1 : 0);
     return hipGetLastError();
 }
 
