@@ -315,7 +315,7 @@ vs_status vs_nn_mfma_probe(const uint16_t* a, const uint16_t* b, float* out, voi
 vs_status vs_nn_mfma_probe_k32(const uint16_t* a, const uint16_t* b, float* out, void* stream);
 
 /* The learned surrogate inside the frame.  vs_load_weights copies a weight
- * file into the context: "VSNN", u32 version 1, u32 layers (1..8), f32
+ * file into the context: "VSNN", u32 version 1, u32 layers (2..8), f32
  * leaky-ReLU slope, per layer u32 cin and u32 cout, then per layer int16
  * w[cout][9][cin] (BF16 bits) and f32 bias[cout], little endian, packed.  The
  * first layer takes 16 channels, the last gives 16 (channels 0-1: flow),

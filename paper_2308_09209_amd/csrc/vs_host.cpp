@@ -717,7 +717,8 @@ vs_status vs_load_weights(vs_ctx* c, const void* blob, size_t nbytes)
         off += 8;
         const bool shape = (ci == 16 && co == 32) || (ci == 32 && co == 32) || (ci == 32 && co == 16) ||
                            (ci == 16 && co == 16);
-        if (!shape || (l == 0 && ci != 16) || (l > 0 && (int)ci != net.co[l - 1]) || (l == net.nl - 1 && co != 16))
+        if (!shape || (l == 0 && ci != 16) || (l > 0 && (int)ci != net.co[l - 1]) || (l == net.nl - 1 && co != 16) ||
+            nl < 2)
             return fail(c, VS_E_INVAL, "weight file: unsupported layer shapes");
         net.ci[l] = (int)ci;
         net.co[l] = (int)co;
@@ -750,7 +751,13 @@ vs_status vs_load_weights(vs_ctx* c, const void* blob, size_t nbytes)
     }
     const size_t npx = (size_t)T.pix_off[nf];
     const size_t nblk = (size_t)h.strip_off[h.n_pairs] * SURR_UP_SUB;
-    const size_t o_x = dev_w, o_h0 = align_up(o_x + npx * 16 * 2, 256), o_h1 = align_up(o_h0 + npx * 32 * 2, 256),
+    // the first layer's weights on the two non-zero input channels, k = 2 tap + channel
+    std::vector<uint16_t> w0p((size_t)net.co[0] * 32, 0);
+    for (int co = 0; co < net.co[0]; ++co)
+        for (int tap = 0; tap < 9; ++tap)
+            for (int ch = 0; ch < 2; ++ch)
+                std::memcpy(&w0p[(size_t)co * 32 + 2 * tap + ch], b + woff[0] + (((size_t)co * 9 + tap) * 16 + ch) * 2, 2);
+    const size_t o_w0p = dev_w, o_h0 = align_up(o_w0p + w0p.size() * 2, 256), o_h1 = align_up(o_h0 + npx * 32 * 2, 256),
                  o_pred = align_up(o_h1 + npx * 32 * 2, 256), o_part = align_up(o_pred + npx * 2 * 4, 256),
                  total = align_up(o_part + nblk * 16, 256);
     VS_CHECK(hipDeviceSynchronize(), "hipDeviceSynchronize");
@@ -766,12 +773,13 @@ vs_status vs_load_weights(vs_ctx* c, const void* blob, size_t nbytes)
         e = hipMemcpy(base + wo, b + woff[l], wbytes[l], hipMemcpyHostToDevice);
         wo += align_up(wbytes[l], 256);
     }
-    if (e == hipSuccess) e = hipMemset(base + o_x, 0, total - o_x);
+    if (e == hipSuccess) e = hipMemcpy(base + o_w0p, w0p.data(), w0p.size() * 2, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemset(base + o_h0, 0, total - o_h0);
     if (e != hipSuccess) {
         (void)hipFree(mem);
         return dev_fail(c, e, "surrogate upload");
     }
-    net.x = (uint16_t*)(base + o_x);
+    net.w0p = (const uint16_t*)(base + o_w0p);
     net.h[0] = (uint16_t*)(base + o_h0);
     net.h[1] = (uint16_t*)(base + o_h1);
     net.pred = (float*)(base + o_pred);

@@ -126,7 +126,7 @@ struct SurrNet {
     int ci[SURR_MAX_LAYERS], co[SURR_MAX_LAYERS];
     const uint16_t* w[SURR_MAX_LAYERS];   // [co][9][ci] BF16
     const float* b[SURR_MAX_LAYERS];
-    uint16_t* x;                          // [pixels][16] packed input
+    const uint16_t* w0p;                  // first layer [co][32] BF16: k = 2 tap + channel (0-1), zeros from k = 18
     uint16_t* h[2];                       // [pixels][32] hidden activations (ping-pong)
     float* pred;                          // [pixels][2] output (channels 0-1)
     unsigned long long* part;             // per-block forward-backward partial sums

@@ -4,10 +4,13 @@
 //
 // Per frame, for every field f = 2 p + dir of a context (pair p, direction
 // dir: template = camera j / moving = camera i, and the reverse):
-//  1. pack: the level-2 luma of the field's template and moving strips into
-//     the 16-channel BF16 network input, (Y - 128) / 64 in channels 0-1;
-//  2. the network's 3x3 convolutions on the matrix cores (vs_nn.hip), one
-//     launch per layer over all fields;
+//  1. the first layer: its input is the level-2 luma of the field's template
+//     and moving strips as BF16 (Y - 128) / 64 in channels 0-1 and zeros in
+//     channels 2-15, so k_surr_in reads the two luma images directly and
+//     contracts only the 9 taps x 2 channels (one 32-long matrix-core chunk,
+//     zero padded) with the layer's weights repacked at load time;
+//  2. the other 3x3 convolutions on the matrix cores (vs_nn.hip), one launch
+//     per layer over all fields;
 //  3. up: per overlap pixel of the strip, the x4 bilinear upsampling of both
 //     directions' level-2 predictions into the level-0 flow buffers, and the
 //     forward-backward error e = |U_ij(x) + U_ji(x + U_ij(x))| in 1/256 px
@@ -28,22 +31,80 @@ __device__ __forceinline__ uint32_t bf16_rne(float f)
     return u >> 16;
 }
 
-__global__ __launch_bounds__(256) void k_surr_pack(const DevPlan* __restrict__ P, uint16_t* __restrict__ X)
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+// First layer, 16 x 16 pixels of one field per block (image f of T, whose
+// tile_off counts 16 x 16 tiles).  LDS holds the tile and its one-pixel halo
+// as (template, moving) BF16 pairs, zero outside the image (the convolution's
+// zero padding).  Reduction index k = 2 tap + channel: lane group kg = l / 16
+// holds taps 4 kg .. 4 kg + 3 of its pixel (tap 8 and zeros for kg = 2, zeros
+// for kg = 3); W0 is [COUT][32] in that order.  Output: leaky ReLU, BF16,
+// NHWC [pixels][COUT], as the general convolution writes it.
+template <int COUT>
+__global__ __launch_bounds__(256) void k_surr_in(const DevPlan* __restrict__ P, const uint16_t* __restrict__ W0,
+                                                 const float* __restrict__ bias, uint16_t* __restrict__ Hout,
+                                                 const nn::ImgTable T, float alpha)
 {
-    const int nf = 2 * P->n_pairs;
-    const long q = (long)blockIdx.x * 256 + threadIdx.x;
-    if (q >= P->surr_pix[nf]) return;
+    constexpr int NT = COUT / 16, TS = 16, TH = TS + 2;
+    __shared__ uint32_t sX[TH * TH];
+    const int tid = threadIdx.x;
     int f = 0;
-    while (f + 1 < nf && q >= P->surr_pix[f + 1]) ++f;
+    while (f + 1 < T.n && (int)blockIdx.x >= T.tile_off[f + 1]) ++f;
     const int p = f >> 1, dir = f & 1;
-    const long i = q - P->surr_pix[f];
-    const float yt = P->pyr[p][dir == 0 ? 0 : 1][SURR_LEVEL][i];
-    const float ym = P->pyr[p][dir == 0 ? 1 : 0][SURR_LEVEL][i];
-    const uint32_t a = bf16_rne((yt - 128.0f) * (1.0f / 64.0f));
-    const uint32_t b = bf16_rne((ym - 128.0f) * (1.0f / 64.0f));
-    uint4* d = reinterpret_cast<uint4*>(X + q * 16);
-    d[0] = make_uint4(a | b << 16, 0u, 0u, 0u);
-    d[1] = make_uint4(0u, 0u, 0u, 0u);
+    const int W = T.w[f], H = T.h[f];
+    const long base = T.pix_off[f];
+    const int ntx = (W + TS - 1) / TS, t = blockIdx.x - T.tile_off[f];
+    const int x0 = (t % ntx) * TS, y0 = (t / ntx) * TS;
+    const float* __restrict__ yt = P->pyr[p][dir == 0 ? 0 : 1][SURR_LEVEL];
+    const float* __restrict__ ym = P->pyr[p][dir == 0 ? 1 : 0][SURR_LEVEL];
+    for (int i = tid; i < TH * TH; i += 256) {
+        const int yy = y0 - 1 + i / TH, xx = x0 - 1 + i % TH;
+        uint32_t v = 0u;
+        if (yy >= 0 && yy < H && xx >= 0 && xx < W) {
+            const long q = (long)yy * W + xx;
+            v = bf16_rne((yt[q] - 128.0f) * (1.0f / 64.0f)) | bf16_rne((ym[q] - 128.0f) * (1.0f / 64.0f)) << 16;
+        }
+        sX[i] = v;
+    }
+    const int lane = tid & 63, wv = tid >> 6, m = lane & 15, kg = lane >> 4;
+    bf16x8 wa[NT];
+    float bb[NT][4];
+#pragma unroll
+    for (int tt = 0; tt < NT; ++tt) {
+        wa[tt] = __builtin_bit_cast(bf16x8, *reinterpret_cast<const uint4*>(W0 + (tt * 16 + m) * 32 + 8 * kg));
+#pragma unroll
+        for (int i = 0; i < 4; ++i) bb[tt][i] = bias[tt * 16 + 4 * kg + i];
+    }
+    __syncthreads();
+    const int x = x0 + m;
+#pragma unroll
+    for (int g = 0; g < 4; ++g) {
+        const int r = wv * 4 + g;
+        uint32_t bw[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int tap = 4 * kg + i;
+            bw[i] = tap < 9 ? sX[(r + tap / 3) * TH + m + tap % 3] : 0u;
+        }
+        const bf16x8 b = __builtin_bit_cast(bf16x8, make_uint4(bw[0], bw[1], bw[2], bw[3]));
+        const int y = y0 + r;
+#pragma unroll
+        for (int tt = 0; tt < NT; ++tt) {
+            const f32x4 acc =
+                __builtin_amdgcn_mfma_f32_16x16x32_bf16(wa[tt], b, f32x4{0.0f, 0.0f, 0.0f, 0.0f}, 0, 0, 0);
+            if (y >= H || x >= W) continue;
+            uint32_t o[4];
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                float v = acc[i] + bb[tt][i];
+                v = v > 0.0f ? v : alpha * v;
+                o[i] = bf16_rne(v);
+            }
+            reinterpret_cast<uint2*>(Hout + (base + (long)y * W + x) * COUT + tt * 16 + 4 * kg)[0] =
+                make_uint2(o[0] | o[1] << 16, o[2] | o[3] << 16);
+        }
+    }
 }
 
 // the x4 upsampled level-2 field (pred: [pixels][2]) at level-0 position
@@ -162,12 +223,23 @@ hipError_t launch_surrogate_ctx(const Group& g, int c, hipStream_t s)
     const SurrNet* net = g.net[c];
     if (!surrogate_active(g, c)) return hipSuccess;
     if (!net) return hipErrorInvalidValue;
-    const long npx = h.surr_pix[2 * h.n_pairs];
-    hipLaunchKernelGGL(k_surr_pack, dim3((unsigned)((npx + 255) / 256)), dim3(256), 0, s, g.dp[c], net->x);
+    if (net->nl < 2 || net->ci[0] != 16) return hipErrorInvalidValue;
+    nn::ImgTable T = net->tbl;   // 16 x 16 tiles
+    T.tile_off[0] = 0;
+    for (int i = 0; i < T.n; ++i) T.tile_off[i + 1] = T.tile_off[i] + ((T.w[i] + 15) / 16) * ((T.h[i] + 15) / 16);
+    for (int i = T.n + 1; i <= nn::MAXI; ++i) T.tile_off[i] = T.tile_off[T.n];
+    if (T.tile_off[T.n] > 0) {
+        if (net->co[0] == 32)
+            hipLaunchKernelGGL(k_surr_in<32>, dim3(T.tile_off[T.n]), dim3(256), 0, s, g.dp[c], net->w0p, net->b[0],
+                               net->h[0], T, net->alpha);
+        else
+            hipLaunchKernelGGL(k_surr_in<16>, dim3(T.tile_off[T.n]), dim3(256), 0, s, g.dp[c], net->w0p, net->b[0],
+                               net->h[0], T, net->alpha);
+    }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    const uint16_t* in = net->x;
-    for (int l = 0; l < net->nl; ++l) {
+    const uint16_t* in = net->h[0];
+    for (int l = 1; l < net->nl; ++l) {
         const bool last = l == net->nl - 1;
         void* out = last ? (void*)net->pred : (void*)net->h[l & 1];
         e = nn::conv3x3(in, net->ci[l], net->w[l], net->b[l], out, net->co[l], net->tbl,
