@@ -67,8 +67,9 @@ def load_pmc(kernel, workload):
 
 def surrogate_flops_per_frame(info, layers):
     """matrix-core flops of the surrogate network per frame: 2 * 9 * cin * cout
-    per level-2 pixel and layer, both directions of every pair"""
-    per_px = sum(2 * 9 * ci * co for ci, co in layers)
+    per level-2 pixel and layer, both directions of every pair; the first
+    layer counts its 2 non-zero input channels (the luma pair)"""
+    per_px = sum(2 * 9 * (2 if i == 0 else ci) * co for i, (ci, co) in enumerate(layers))
     total = 0
     for p in range(info.n_pairs):
         w, h = info.strip_w[p], info.strip_h[p]
@@ -298,8 +299,9 @@ def surrogate_leg(args, V, rig, frames, st_plain, K, H, W, mpix_plain, p99_plain
                 step_ms={n: round(v / nfr, 5) for n, v in zip(names, step_ms)},
                 mfma=dict(flops_per_frame=fl, flow_step_ms=round(flow_ms, 5),
                           achieved=round(fl / (flow_ms * 1e-3) / 1e12, 3), peak=BF16_MFMA_PEAK_TFLOPS,
-                          unit="TFLOP/s", note="network flops over the whole flow step (pack, 5 "
-                          "convolutions, upsampling, forward-backward check, fallback)"))
+                          unit="TFLOP/s", note="network flops (first layer on its 2 non-zero input "
+                          "channels) over the whole flow step (5 convolutions, upsampling, "
+                          "forward-backward check, fallback)"))
 
 
 def bench_batch(args):
