@@ -54,6 +54,7 @@ constexpr int CONV_T = 16;                  // tile side (pixels)
 constexpr int CONV_H = CONV_T + 2;          // tile with halo
 
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
 
 struct ConvTile {
     int x0, y0, W, H;
@@ -109,32 +110,44 @@ __global__ __launch_bounds__(256) void k_conv3x3(const uint16_t* __restrict__ X,
 #pragma unroll
         for (int i = 0; i < 4; ++i) bb[tt][i] = bias ? bias[tt * 16 + 4 * kg + i] : 0.0f;
 
+    // this thread's staging vectors, the same for every tile: halo row and
+    // column and 16-byte vector of the pixel (packed r << 16 | c << 8 | v)
+    int st[NL];
+#pragma unroll
+    for (int j = 0; j < NL; ++j) {
+        const int e = tid + j * 256, px = e / PV;
+        st[j] = e < NV ? (px / CONV_H) << 16 | (px % CONV_H) << 8 | (e % PV) : -1;
+    }
     uint4 pf[NL];
-    auto fetch = [&](int t) {
-        const ConvTile c = conv_tile(T, t);
+    auto fetch = [&](const ConvTile& c) {
 #pragma unroll
         for (int j = 0; j < NL; ++j) {
-            const int e = tid + j * 256;
             uint4 v = make_uint4(0u, 0u, 0u, 0u);
-            if (e < NV) {
-                const int px = e / PV, cv = e % PV;
-                const int yy = c.y0 - 1 + px / CONV_H, xx = c.x0 - 1 + px % CONV_H;
-                if (yy >= 0 && yy < c.H && xx >= 0 && xx < c.W) v = Xv[(c.base + (long)yy * c.W + xx) * PV + cv];
+            if (st[j] >= 0) {
+                const int yy = c.y0 - 1 + (st[j] >> 16), xx = c.x0 - 1 + ((st[j] >> 8) & 255);
+                if (yy >= 0 && yy < c.H && xx >= 0 && xx < c.W)
+                    v = Xv[(c.base + (long)yy * c.W + xx) * PV + (st[j] & 255)];
             }
             pf[j] = v;
         }
     };
 
-    if ((int)blockIdx.x < ntiles) fetch(blockIdx.x);
+    ConvTile cur;
+    if ((int)blockIdx.x < ntiles) {
+        cur = conv_tile(T, blockIdx.x);
+        fetch(cur);
+    }
     for (int t = blockIdx.x; t < ntiles; t += gridDim.x) {
         __syncthreads();                           // every wavefront is done with the previous tile
 #pragma unroll
-        for (int j = 0; j < NL; ++j) {
-            const int e = tid + j * 256;
-            if (e < NV) sX[(e / PV) * PSV + e % PV] = pf[j];
-        }
+        for (int j = 0; j < NL; ++j)
+            if (st[j] >= 0) sX[((st[j] >> 16) * CONV_H + ((st[j] >> 8) & 255)) * PSV + (st[j] & 255)] = pf[j];
         __syncthreads();
-        if (t + (int)gridDim.x < ntiles) fetch(t + gridDim.x);
+        const ConvTile c = cur;
+        if (t + (int)gridDim.x < ntiles) {
+            cur = conv_tile(T, t + gridDim.x);
+            fetch(cur);                            // the next tile's loads overlap this tile's products
+        }
 
         f32x4 acc[4][NT];
 #pragma unroll
@@ -159,7 +172,6 @@ __global__ __launch_bounds__(256) void k_conv3x3(const uint16_t* __restrict__ X,
             }
         }
 
-        const ConvTile c = conv_tile(T, t);
         const int x = c.x0 + m;
 #pragma unroll
         for (int g = 0; g < 4; ++g) {
@@ -181,9 +193,10 @@ __global__ __launch_bounds__(256) void k_conv3x3(const uint16_t* __restrict__ X,
                     reinterpret_cast<float4*>(static_cast<float*>(Y) + q * COUT + co)[0] =
                         make_float4(v[0], v[1], v[2], v[3]);
                 } else {
+                    // round to nearest even (v_cvt_pk_bf16_f32)
+                    const bf16x2 lo = {(__bf16)v[0], (__bf16)v[1]}, hi = {(__bf16)v[2], (__bf16)v[3]};
                     reinterpret_cast<uint2*>(static_cast<uint16_t*>(Y) + q * COUT + co)[0] =
-                        make_uint2((uint32_t)f2bf(v[0]) | (uint32_t)f2bf(v[1]) << 16,
-                                   (uint32_t)f2bf(v[2]) | (uint32_t)f2bf(v[3]) << 16);
+                        make_uint2(__builtin_bit_cast(uint32_t, lo), __builtin_bit_cast(uint32_t, hi));
                 }
             }
         }
