@@ -149,14 +149,16 @@ __global__ void k_set_io(const FrameIO io)
 
 __device__ __forceinline__ void strips_body(const DevPlan* __restrict__ P, const int bid)
 {
-    __shared__ uint32_t s_hist[4][2 * 3 * 256];   // 4 copies (lane & 3) against same-value conflicts
+    // 4 copies (lane & 3) against same-address serialisation, each one word
+    // longer than the 6 x 256 bins so that a bin's copies sit in different banks
+    __shared__ uint32_t s_hist[4][2 * 3 * 256 + 1];
     __shared__ uint32_t s_red[4][7];
     const int tid = threadIdx.x;
     const int p = find_field(P->strip_off, P->n_pairs, bid);
     const int t = bid - P->strip_off[p];
     const int sw = P->sw[p], sh = P->sh[p];
     const int tx0 = (t % P->strip_tx[p]) * STRIP_TX, ty0 = (t / P->strip_tx[p]) * STRIP_TY;
-    for (int i = tid; i < 4 * 2 * 3 * 256; i += 256) (&s_hist[0][0])[i] = 0;
+    for (int i = tid; i < 4 * (2 * 3 * 256 + 1); i += 256) (&s_hist[0][0])[i] = 0;
     __syncthreads();
     uint32_t* const my_hist = s_hist[tid & 3];
 
@@ -708,13 +710,13 @@ __device__ __forceinline__ void blend_body(const DevPlan* __restrict__ P, const 
 {
     // 8 copies of the histogram (lane & 7): neighbouring pixels often share a
     // value, and same-address LDS atomics from one instruction serialise
-    __shared__ uint32_t s_hist[8][3 * 256];
+    __shared__ uint32_t s_hist[8][3 * 256 + 1];   // + 1: a bin's copies in different banks
     // per-camera constants of the frame, indexed by each lane's own camera
     __shared__ float s_hinv[MAXC][9], s_M[MAXC][9];
     __shared__ int s_cw[MAXC], s_ch[MAXC], s_cp[MAXC];
     __shared__ const uint8_t* s_fr[MAXC];
     const int tid = threadIdx.x;
-    for (int i = tid; i < 8 * 3 * 256; i += BL_THREADS) (&s_hist[0][0])[i] = 0;
+    for (int i = tid; i < 8 * (3 * 256 + 1); i += BL_THREADS) (&s_hist[0][0])[i] = 0;
     for (int i = tid; i < P->n_cams * 9; i += BL_THREADS) {
         (&s_hinv[0][0])[i] = (&P->hinv[0][0])[i];
         (&s_M[0][0])[i] = (&P->res->Mk[0][0])[i];
