@@ -14,6 +14,7 @@ CPU oracle timed on a bounded sample of the same workload.
 from __future__ import annotations
 
 import argparse
+import ctypes
 import json
 import os
 import sys
@@ -128,15 +129,40 @@ def cpu_baseline(scene, frames_list, n_frames):
     dt = time.perf_counter() - t0
     threads = int(os.environ.get("OMP_NUM_THREADS", "0")) or len(os.sched_getaffinity(0))
     threads = min(threads, len(os.sched_getaffinity(0)))
-    return dict(value=round(n_frames * H * W / dt / 1e6, 4), unit="Mpix/s", cores=threads,
-                kind="oracle", sample=f"{n_frames} consecutive frames of the same workload, every step "
-                                      f"({dt:.1f} s on {threads} OpenMP threads)")
+    out = dict(value=round(n_frames * H * W / dt / 1e6, 4), unit="Mpix/s", cores=threads,
+               kind="oracle", sample=f"{n_frames} consecutive frames of the same workload, every step "
+                                     f"({dt:.1f} s on {threads} OpenMP threads)",
+               cpu_model=cpu_model(), nproc=os.cpu_count())
+    # the next frame on one thread (the oracle's OpenMP regions follow this thread's setting)
+    try:
+        gomp = ctypes.CDLL("libgomp.so.1")
+    except OSError:
+        gomp = None
+    if gomp is not None and len(frames_list) > n_frames and H * W <= 8_000_000:   # ~10-20 s of one core
+        gomp.omp_set_num_threads(1)
+        t0 = time.perf_counter()
+        orc.stitch(frames_list[n_frames])
+        dt1 = time.perf_counter() - t0
+        gomp.omp_set_num_threads(threads)
+        out["single_thread"] = dict(value=round(H * W / dt1 / 1e6, 4), unit="Mpix/s",
+                                    sample=f"1 frame ({dt1:.1f} s)")
+    return out
+
+
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
 
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=300)
+    ap.add_argument("--steps", type=int, default=600)
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--workload", default=None, help="default 4x1920x1080_ring")
     ap.add_argument("--seq", type=int, default=None,
