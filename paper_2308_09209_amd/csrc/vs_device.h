@@ -124,7 +124,7 @@ __device__ __forceinline__ uint32_t wave_sum(uint32_t v)
 // the pyramid levels only it reads skip the pair)
 __device__ __forceinline__ bool kept_by_surrogate(const DevPlan* __restrict__ P, int p)
 {
-    return P->flow_mode == VS_FLOW_SURROGATE_FALLBACK && P->res->surr_ok[p];
+    return P->flow_mode == VS_FLOW_SURROGATE_FALLBACK && P->surr_kept[p];
 }
 
 __device__ __forceinline__ int find_field(const int32_t* off, int n, int b)

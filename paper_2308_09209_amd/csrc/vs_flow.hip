@@ -30,7 +30,7 @@ __device__ __forceinline__ void lk_body(const DevPlan* __restrict__ P, const int
     __shared__ float sM[LK_MW][LK_MW];
     const int f = find_field(P->lk_off[l], 2 * P->n_pairs, bid);
     const int p = f >> 1, dir = f & 1;
-    if (P->flow_mode != VS_FLOW_PLAIN && P->res->surr_ok[p]) return;   // the pair keeps the surrogate's flows
+    if (kept_by_surrogate(P, p)) return;   // the pair keeps the surrogate's flows
     const int t = bid - P->lk_off[l][f];
     const int w = P->lw[p][l], h = P->lh[p][l];
     const int x0 = (t % P->lk_tx[l][f]) * LK_T, y0 = (t / P->lk_tx[l][f]) * LK_T;
@@ -181,7 +181,7 @@ __device__ __forceinline__ void lk_w9_body(const DevPlan* __restrict__ Pl, const
 
     const int f = find_field(Pl->lk_off[l], 2 * Pl->n_pairs, bid);
     const int p = f >> 1, dir = f & 1;
-    if (Pl->flow_mode != VS_FLOW_PLAIN && Pl->res->surr_ok[p]) return;   // the pair keeps the surrogate's flows
+    if (kept_by_surrogate(Pl, p)) return;   // the pair keeps the surrogate's flows
     const int t = bid - Pl->lk_off[l][f];
     const int w = Pl->lw[p][l], h = Pl->lh[p][l];
     const int x0 = (t % Pl->lk_tx[l][f]) * TX, y0 = (t / Pl->lk_tx[l][f]) * TY;

@@ -555,7 +555,7 @@ hipError_t enqueue_frame(const Group& g, hipStream_t s, hipEvent_t* ev, uint8_t*
     // written; surrogate modes: level 2, its input); fewer levels: level by level
     VS_STEP(launch_pyr0(g, PYR_UNFUSED, s), "pyr0");
     for (int l = 0; l + 1 < levels; ++l) VS_STEP(launch_pyr_down(g, l, PYR_UNFUSED, s), "pyr_down");
-    VS_STEP(launch_pyr_fused(g, s), "pyr_fused");
+    VS_STEP(launch_pyr_fused(g, PYR_UNFUSED, s), "pyr_fused");
     if (ev) VS_STEP(hipEventRecord(ev[2], s), "hipEventRecord");
     int n_surr = 0;
     for (int c = 0; c < g.n; ++c) n_surr += surrogate_active(g, c) ? 1 : 0;
@@ -574,7 +574,7 @@ hipError_t enqueue_frame(const Group& g, hipStream_t s, hipEvent_t* ev, uint8_t*
         VS_STEP(launch_surrogate(g, s), "surrogate");
     }
     // what the plain estimator still needs, after the surrogate's decisions
-    VS_STEP(launch_pyr0(g, PYR_AFTER, s), "pyr0");
+    VS_STEP(launch_pyr_fused(g, PYR_AFTER, s), "pyr_fused");
     for (int l = 0; l + 1 < levels; ++l) VS_STEP(launch_pyr_down(g, l, PYR_AFTER, s), "pyr_down");
     for (int l = levels - 1; l >= 0; --l) VS_STEP(launch_lk(g, l, s), "flow");
     if (ev) VS_STEP(hipEventRecord(ev[3], s), "hipEventRecord");

@@ -80,6 +80,8 @@ struct DevPlan {
     int32_t blend_tx, blend_ty, cover_words;
     // learned surrogate (VS_FLOW_PLAIN: not used)
     int32_t flow_mode;
+    alignas(16) uint8_t surr_kept[MAXP];   // this frame: 1 where the pair keeps the surrogate's flows
+                                           // (written by k_surr_decide; read by the skips of later launches)
     unsigned long long fb_tau_fix;     // fallback threshold in 1/256 px
     int64_t surr_pix[2 * MAXP + 1];    // field f's level-2 pixels start at surr_pix[f] (NHWC buffers)
     const float* surr_pred;            // [pixels][2] FP32 network output (flow, level-2 px)
@@ -159,7 +161,7 @@ hipError_t launch_moments_b(const Group& g, hipStream_t s);
 hipError_t launch_solve(const Group& g, hipStream_t s);
 enum { PYR_ALL = 0, PYR_UNFUSED = 1, PYR_AFTER = 2 };
 hipError_t launch_pyr0(const Group& g, int phase, hipStream_t s);
-hipError_t launch_pyr_fused(const Group& g, hipStream_t s);
+hipError_t launch_pyr_fused(const Group& g, int phase, hipStream_t s);
 hipError_t launch_pyr_down(const Group& g, int level, int phase, hipStream_t s);
 hipError_t launch_lk(const Group& g, int level, hipStream_t s);
 hipError_t launch_surrogate(const Group& g, hipStream_t s);   // vs_surr.hip

@@ -597,7 +597,7 @@ __device__ __forceinline__ float tap5(float a0, float a1, float a2, float a3, fl
     return acc * 0.0625f;
 }
 
-__device__ __forceinline__ void pyr_fused_body(const DevPlan* __restrict__ P, const int bid)
+__device__ __forceinline__ void pyr_fused_body(const DevPlan* __restrict__ P, const int bid, int after)
 {
     __shared__ uint8_t s0[PF_H0][PF_W0 + 3];
     __shared__ float sh[PF_H0 * PF_W1];    // level-0 rows at level-1 columns; then level-1 rows at level-2 columns
@@ -605,6 +605,7 @@ __device__ __forceinline__ void pyr_fused_body(const DevPlan* __restrict__ P, co
     const int tid = threadIdx.x;
     const int f = find_field(P->pyrf_off, 2 * P->n_pairs, bid);
     const int p = f >> 1, cam = f & 1;
+    if (after && kept_by_surrogate(P, p)) return;
     const int t = bid - P->pyrf_off[f];
     const int w0 = P->lw[p][0], h0 = P->lh[p][0];
     const int w1 = P->lw[p][1], h1 = P->lh[p][1];
@@ -612,7 +613,7 @@ __device__ __forceinline__ void pyr_fused_body(const DevPlan* __restrict__ P, co
     const int X0 = (t % P->pyrf_tx[f]) * PF_TX, Y0 = (t / P->pyrf_tx[f]) * PF_TY;
     const int bx0 = 4 * X0 - 6, by0 = 4 * Y0 - 6;       // footprint origins, before clamping
     const int bx1 = 2 * X0 - 2, by1 = 2 * Y0 - 2;
-    const bool write01 = P->flow_mode == VS_FLOW_PLAIN;
+    const bool write01 = P->flow_mode == VS_FLOW_PLAIN || after;
     const float* M = P->res->Mk[cam == 0 ? P->pj[p] : P->pi[p]];
     const uint32_t* __restrict__ src = P->strip[p] + (size_t)cam * h0 * w0;
     float* __restrict__ L0 = P->pyr[p][cam][0];
@@ -693,11 +694,13 @@ __device__ __forceinline__ void pyr_fused_body(const DevPlan* __restrict__ P, co
     }
 }
 
-__global__ __launch_bounds__(256) void k_pyr_fused(const Batch B)
+// after: launched after the surrogate's decisions for the pairs that did not
+// keep its flows (levels 0 and 1 written; level 2 again, the same values)
+__global__ __launch_bounds__(256) void k_pyr_fused(const Batch B, int after)
 {
     int c;
     const int b = batch_block(B, blockIdx.x, c);
-    pyr_fused_body(B.plan[c], b);
+    pyr_fused_body(B.plan[c], b, after);
 }
 
 
@@ -1044,12 +1047,13 @@ hipError_t launch_solve(const Group& g, hipStream_t s)
     return hipGetLastError();
 }
 
-// Which contexts a pyramid launch covers: PYR_ALL every flow context (the
-// label context); PYR_UNFUSED those with fewer than 3 levels, before the
-// surrogate; PYR_AFTER, after the surrogate's decisions, the levels the fused
-// kernel did not write that the plain estimator reads (levels 0 and 1 of a
-// fallback context, levels above 2 of any context with plain flow), pairs
-// that kept the surrogate's flows skipping them.
+// Which contexts a level-by-level pyramid launch covers: PYR_ALL every flow
+// context (the label context); PYR_UNFUSED those with fewer than 3 levels,
+// before the surrogate; PYR_AFTER, after the surrogate's decisions, the levels
+// above 2 of any context with plain flow, pairs that kept the surrogate's
+// flows skipping them.  Levels 0-2 of pyramids with 3 or more levels come from
+// k_pyr_fused: before the surrogate (all three for plain flow, level 2 in the
+// surrogate modes) and, in fallback mode, after it for the pairs not kept.
 static bool pyr_level_launched(const DevPlan& h, int lo, int phase)
 {
     if (!h.use_flow || lo >= h.levels) return false;
@@ -1057,8 +1061,7 @@ static bool pyr_level_launched(const DevPlan& h, int lo, int phase)
     const bool fused = h.levels >= 3;
     if (phase == PYR_UNFUSED) return !fused;
     if (!fused) return false;
-    if (lo <= 1) return h.flow_mode == VS_FLOW_SURROGATE_FALLBACK;
-    if (lo == 2) return false;
+    if (lo <= 2) return false;   // levels 0-2: the fused kernel, before and (fallback) after
     return h.flow_mode != VS_FLOW_SURROGATE;
 }
 
@@ -1071,11 +1074,14 @@ hipError_t launch_pyr0(const Group& g, int phase, hipStream_t s)
     return hipGetLastError();
 }
 
-hipError_t launch_pyr_fused(const Group& g, hipStream_t s)
+hipError_t launch_pyr_fused(const Group& g, int phase, hipStream_t s)
 {
     Batch B;
-    if (make_batch(g, B, [](const DevPlan& h) { return h.use_flow && h.levels >= 3 ? h.pyrf_off[2 * h.n_pairs] : 0; }))
-        hipLaunchKernelGGL(k_pyr_fused, dim3(B.off[B.n]), dim3(256), 0, s, B);
+    const bool after = phase == PYR_AFTER;
+    if (make_batch(g, B, [&](const DevPlan& h) {
+            const bool on = h.use_flow && h.levels >= 3 && (!after || h.flow_mode == VS_FLOW_SURROGATE_FALLBACK);
+            return on ? h.pyrf_off[2 * h.n_pairs] : 0; }))
+        hipLaunchKernelGGL(k_pyr_fused, dim3(B.off[B.n]), dim3(256), 0, s, B, after ? 1 : 0);
     return hipGetLastError();
 }
 

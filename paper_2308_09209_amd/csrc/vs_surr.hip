@@ -19,6 +19,8 @@
 //     surrogate's flows when the mode is
 //     VS_FLOW_SURROGATE, or when its mean error is below the threshold; the
 //     plain estimator's kernels skip the kept pairs and overwrite the others.
+#include <cstddef>
+
 #include "vs_internal.h"
 
 namespace vs {
@@ -181,7 +183,7 @@ __global__ __launch_bounds__(256) void k_surr_up(const DevPlan* __restrict__ P)
 
 // one block per pair: add the pair's block partials (exact integers, so the
 // order does not matter), decide
-__global__ __launch_bounds__(1024) void k_surr_decide(const DevPlan* __restrict__ P)
+__global__ __launch_bounds__(1024) void k_surr_decide(const DevPlan* __restrict__ P, uint8_t* __restrict__ kept)
 {
     __shared__ unsigned long long s_e[1024], s_n[1024];
     const int p = blockIdx.x, tid = threadIdx.x;
@@ -203,7 +205,9 @@ __global__ __launch_bounds__(1024) void k_surr_decide(const DevPlan* __restrict_
     }
     if (tid == 0) {
         const unsigned long long s = s_e[0], c = s_n[0];
-        P->res->surr_ok[p] = P->flow_mode == VS_FLOW_SURROGATE || (c > 0 && s < P->fb_tau_fix * c);
+        const bool ok = P->flow_mode == VS_FLOW_SURROGATE || (c > 0 && s < P->fb_tau_fix * c);
+        P->res->surr_ok[p] = ok;
+        kept[p] = ok;
         P->res->fb[p][0] = s;
         P->res->fb[p][1] = c;
     }
@@ -248,7 +252,8 @@ hipError_t launch_surrogate_ctx(const Group& g, int c, hipStream_t s)
         in = net->h[l & 1];
     }
     hipLaunchKernelGGL(k_surr_up, dim3(h.strip_off[h.n_pairs] * SURR_UP_SUB), dim3(256), 0, s, g.dp[c]);
-    hipLaunchKernelGGL(k_surr_decide, dim3(h.n_pairs), dim3(1024), 0, s, g.dp[c]);
+    uint8_t* kept = reinterpret_cast<uint8_t*>(g.dp[c]) + offsetof(DevPlan, surr_kept);
+    hipLaunchKernelGGL(k_surr_decide, dim3(h.n_pairs), dim3(1024), 0, s, g.dp[c], kept);
     return hipGetLastError();
 }
 
