@@ -166,7 +166,15 @@ __global__ __launch_bounds__(256) void k_lk(const Batch B, int l)
 //  - per pixel the horizontally interpolated moving-image rows slide down the
 //    window in registers: the bottom row of window row r is the top row of
 //    window row r + 1, so each tap costs ~1.1 moving-image LDS reads.
-template <int P>
+// INBLOCK: the block finishes its own deferred pixels at its end (the tail
+// kernel's per-pixel routine, same arithmetic) instead of queueing them: the
+// launches of contexts whose pairs may keep the surrogate's flows, where the
+// deferred pixels are few and a tail launch per level would cost more.
+template <int ROWS_UNROLL>
+__device__ __forceinline__ void lk_tail_pixel(const DevPlan* __restrict__ Pl, int l, int f, int x, int y, int it0,
+                                              float ux, float uy);
+
+template <int P, bool INBLOCK>
 __device__ __forceinline__ void lk_w9_body(const DevPlan* __restrict__ Pl, const int bid, int l)
 {
     constexpr int R = LK_R_MAX, NW = 2 * R + 1;
@@ -217,10 +225,12 @@ __device__ __forceinline__ void lk_w9_body(const DevPlan* __restrict__ Pl, const
     const uint8_t* __restrict__ need = Pl->need[p][l];
     float ux[P], uy[P], g00[P], g01[P], g11[P], det[P];
     bool act[P];
+    int dit[P];   // INBLOCK: step at which the pixel was deferred (-1: not deferred)
 #pragma unroll
     for (int q = 0; q < P; ++q) {
         const int y = yb + q;
         act[q] = x < w && y < h && need[(size_t)y * w + x] != 0;
+        dit[q] = -1;
         ux[q] = 0.0f;
         uy[q] = 0.0f;
         if (has_coarse && act[q]) {
@@ -285,13 +295,17 @@ __device__ __forceinline__ void lk_w9_body(const DevPlan* __restrict__ Pl, const
             bu[q] = 0.0f;
             bv[q] = 0.0f;
             if (act[q] && !(ox >= -(LK_D + 1) && ox <= LK_D && oy >= -(LK_D + 1) && oy <= LK_D)) {
-                // the displacement leaves the staged tile: hand the pixel, with its
-                // state at the start of this step, to the tail kernel
-                const uint32_t slot = atomicAdd(&Pl->acc->lk_qn[l], 1u);
-                if (slot < (uint32_t)Pl->lk_qcap[l])
-                    Pl->lk_queue[l][slot] = make_uint4((uint32_t)f | ((uint32_t)it << 8),
-                                                       (uint32_t)x | ((uint32_t)(yb + q) << 16),
-                                                       __float_as_uint(ux[q]), __float_as_uint(uy[q]));
+                // the displacement leaves the staged tile: the pixel, with its state
+                // at the start of this step, goes to the tail (kernel or block end)
+                if (INBLOCK) {
+                    dit[q] = it;
+                } else {
+                    const uint32_t slot = atomicAdd(&Pl->acc->lk_qn[l], 1u);
+                    if (slot < (uint32_t)Pl->lk_qcap[l])
+                        Pl->lk_queue[l][slot] = make_uint4((uint32_t)f | ((uint32_t)it << 8),
+                                                           (uint32_t)x | ((uint32_t)(yb + q) << 16),
+                                                           __float_as_uint(ux[q]), __float_as_uint(uy[q]));
+                }
                 act[q] = false;
             }
             if (!act[q]) {
@@ -347,14 +361,18 @@ __device__ __forceinline__ void lk_w9_body(const DevPlan* __restrict__ Pl, const
 #pragma unroll
     for (int q = 0; q < P; ++q)
         if (act[q]) Pl->flow[p][dir][l][(size_t)(yb + q) * w + x] = make_float2(ux[q], uy[q]);
+    if (INBLOCK) {
+        for (int q = 0; q < P; ++q)
+            if (dit[q] >= 0) lk_tail_pixel<1>(Pl, l, f, x, yb + q, dit[q], ux[q], uy[q]);
+    }
 }
 
-template <int P>
+template <int P, bool INBLOCK>
 __global__ __launch_bounds__(256) void k_lk_w9(const Batch B, int l)
 {
     int c;
     const int b = batch_block(B, blockIdx.x, c);
-    lk_w9_body<P>(B.plan[c], b, l);
+    lk_w9_body<P, INBLOCK>(B.plan[c], b, l);
 }
 
 // Pixels whose displacement left the staged tile finish here, one pixel per
@@ -362,20 +380,16 @@ __global__ __launch_bounds__(256) void k_lk_w9(const Batch B, int l)
 // outside the level, as in the staged kernel, so the row-major sums are the
 // same).  Each window row issues all of its loads before using them: the
 // kernel is latency-bound on about one round trip per window row.
-__global__ __launch_bounds__(256) void k_lk_tail(const Batch B, int l)
+// ROWS_UNROLL: window rows unrolled (the tail kernel, all of a row's loads in
+// flight) or 1 (inside the staged kernel, where registers are scarce); the
+// arithmetic and its order are the same
+template <int ROWS_UNROLL>
+__device__ __forceinline__ void lk_tail_pixel(const DevPlan* __restrict__ Pl, int l, int f, int x, int y, int it0,
+                                              float ux, float uy)
 {
     constexpr int R = LK_R_MAX, NW = 2 * R + 1;
-    int c;
-    const int b = batch_block(B, blockIdx.x, c);
-    const int nb = B.off[c + 1] - B.off[c];          // this context's blocks
-    const DevPlan* __restrict__ Pl = B.plan[c];
-    const uint32_t n = min(Pl->acc->lk_qn[l], (uint32_t)Pl->lk_qcap[l]);
     const int iters = Pl->lk_iters;
-    for (uint32_t i = b * 256 + threadIdx.x; i < n; i += nb * 256) {
-        const uint4 ent = Pl->lk_queue[l][i];
-        const int f = (int)(ent.x & 255u), it0 = (int)(ent.x >> 8);
-        const int x = (int)(ent.y & 0xffffu), y = (int)(ent.y >> 16);
-        float ux = __uint_as_float(ent.z), uy = __uint_as_float(ent.w);
+    {
         const int p = f >> 1, dir = f & 1;
         const int w = Pl->lw[p][l], h = Pl->lh[p][l];
         const float* __restrict__ Tm = Pl->pyr[p][dir == 0 ? 0 : 1][l];
@@ -387,7 +401,7 @@ __global__ __launch_bounds__(256) void k_lk_tail(const Batch B, int l)
 #pragma unroll
         for (int c = 0; c < NW; ++c) cin[c] = x - R + c >= 0 && x - R + c < w;
         float g00 = 0.0f, g01 = 0.0f, g11 = 0.0f;
-#pragma unroll
+#pragma unroll ROWS_UNROLL
         for (int jr = 0; jr < NW; ++jr) {
             const int yy = y - R + jr;
             const bool rin = yy >= 0 && yy < h;
@@ -426,7 +440,7 @@ __global__ __launch_bounds__(256) void k_lk_tail(const Batch B, int l)
 #pragma unroll
             for (int k = 0; k < NW + 1; ++k) mx[k] = clampi(x - R + ox + k, 0, w - 1);
             float bu = 0.0f, bv = 0.0f;
-#pragma unroll
+#pragma unroll ROWS_UNROLL
             for (int jr = 0; jr < NW; ++jr) {
                 const int yy = y - R + jr;
                 const bool rin = yy >= 0 && yy < h;
@@ -466,6 +480,20 @@ __global__ __launch_bounds__(256) void k_lk_tail(const Batch B, int l)
             uy = uy + dv;
         }
         Pl->flow[p][dir][l][(size_t)y * w + x] = make_float2(ux, uy);
+    }
+}
+
+__global__ __launch_bounds__(256) void k_lk_tail(const Batch B, int l)
+{
+    int c;
+    const int b = batch_block(B, blockIdx.x, c);
+    const int nb = B.off[c + 1] - B.off[c];          // this context's blocks
+    const DevPlan* __restrict__ Pl = B.plan[c];
+    const uint32_t n = min(Pl->acc->lk_qn[l], (uint32_t)Pl->lk_qcap[l]);
+    for (uint32_t i = b * 256 + threadIdx.x; i < n; i += nb * 256) {
+        const uint4 ent = Pl->lk_queue[l][i];
+        lk_tail_pixel<2 * LK_R_MAX + 1>(Pl, l, (int)(ent.x & 255u), (int)(ent.y & 0xffffu), (int)(ent.y >> 16),
+                                        (int)(ent.x >> 8), __uint_as_float(ent.z), __uint_as_float(ent.w));
     }
 }
 
@@ -533,17 +561,23 @@ hipError_t launch_lk(const Group& g, int l, hipStream_t s)
     Batch B;
     // a context whose flows all come from the surrogate launches no flow blocks
     auto plain = [](const DevPlan& h) { return h.use_flow && h.flow_mode != VS_FLOW_SURROGATE; };
+    // fallback contexts: deferred pixels finished in-block, no tail launch
+    bool inblock = false;
+    for (int c = 0; c < g.n; ++c) inblock = inblock || g.hp[c]->flow_mode == VS_FLOW_SURROGATE_FALLBACK;
     if (make_batch(g, B, [&](const DevPlan& h) { return plain(h) && l < h.levels ? h.lk_off[l][2 * h.n_pairs] : 0; })) {
         const dim3 grid(B.off[B.n]);
-        switch (P) {
-        case 4: hipLaunchKernelGGL(k_lk_w9<4>, grid, dim3(256), 0, s, B, l); break;
-        case 2: hipLaunchKernelGGL(k_lk_w9<2>, grid, dim3(256), 0, s, B, l); break;
-        case 1: hipLaunchKernelGGL(k_lk_w9<1>, grid, dim3(256), 0, s, B, l); break;
+        switch (P * 2 + (inblock ? 1 : 0)) {
+        case 8: hipLaunchKernelGGL((k_lk_w9<4, false>), grid, dim3(256), 0, s, B, l); break;
+        case 9: hipLaunchKernelGGL((k_lk_w9<4, true>), grid, dim3(256), 0, s, B, l); break;
+        case 4: hipLaunchKernelGGL((k_lk_w9<2, false>), grid, dim3(256), 0, s, B, l); break;
+        case 5: hipLaunchKernelGGL((k_lk_w9<2, true>), grid, dim3(256), 0, s, B, l); break;
+        case 2: hipLaunchKernelGGL((k_lk_w9<1, false>), grid, dim3(256), 0, s, B, l); break;
+        case 3: hipLaunchKernelGGL((k_lk_w9<1, true>), grid, dim3(256), 0, s, B, l); break;
         default: hipLaunchKernelGGL(k_lk, grid, dim3(256), 0, s, B, l); break;
         }
     }
     hipError_t e = hipGetLastError();
-    if (e != hipSuccess || P == 0) return e;
+    if (e != hipSuccess || P == 0 || inblock) return e;
     // deferred pixels: the device-side count bounds the grid-stride loop
     if (make_batch(g, B, [&](const DevPlan& h) {
             return plain(h) && l < h.levels ? std::min(1024, std::max(1, (h.lk_qcap[l] + 255) / 256)) : 0; }))
