@@ -545,7 +545,6 @@ hipError_t enqueue_frame(const Group& g, hipStream_t s, hipEvent_t* ev, uint8_t*
     int levels = 0;
     for (int c = 0; c < g.n; ++c) levels = std::max(levels, (int)g.hp[c]->levels);
     if (ev) VS_STEP(hipEventRecord(ev[0], s), "hipEventRecord");
-    VS_STEP(launch_zero(g, s), "zero");
     VS_STEP(launch_strips(g, s), "strips");
     VS_STEP(launch_lut(g, s), "lut");
     VS_STEP(launch_moments_b(g, s), "moments");

@@ -131,14 +131,20 @@ __global__ __launch_bounds__(256) void k_zero(const Batch B)
 
 // Frame and panorama pointers of every context of the group, written into its
 // device plan before the frame's kernels run (they read them from there, so a
-// captured frame graph replays for any input buffers).
-__global__ void k_set_io(const FrameIO io)
+// captured frame graph replays for any input buffers), and the frame's
+// accumulators cleared (`per` blocks per context; a fill kernel, no memset).
+__global__ __launch_bounds__(256) void k_set_io(const FrameIO io, int per)
 {
-    const int c = blockIdx.x;
+    const int c = blockIdx.x / per, b = blockIdx.x % per;
     const int k = threadIdx.x;
     DevPlan* P = io.plan[c];
-    if (k < MAXC) P->frame[k] = io.frame[c][k];
-    if (k == 0) P->pano = io.pano[c];
+    if (b == 0) {
+        if (k < MAXC) P->frame[k] = io.frame[c][k];
+        if (k == 0) P->pano = io.pano[c];
+    }
+    uint4* a = reinterpret_cast<uint4*>(P->acc);
+    const int i = b * 256 + k;
+    if (i < (int)(sizeof(Accum) / 16)) a[i] = make_uint4(0, 0, 0, 0);
 }
 
 // ---------------------------------------------------------------------------
@@ -1002,7 +1008,8 @@ __global__ __launch_bounds__(BL_THREADS) void k_balance_apply(const Batch B)
 
 hipError_t launch_set_io(const FrameIO& io, int n, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_set_io, dim3(n), dim3(64), 0, s, io);
+    const int per = (int)((sizeof(Accum) / 16 + 255) / 256);
+    hipLaunchKernelGGL(k_set_io, dim3(n * per), dim3(256), 0, s, io, per);
     return hipGetLastError();
 }
 
