@@ -27,8 +27,10 @@ constexpr int LKW_TX = 64;                    // 9x9-window flow kernel: 64 px w
                                               // P vertically adjacent pixels per thread
 constexpr int BL_TX = 256, BL_TY = 8;         // blend / balance tile: 256 x 8 px
 constexpr int BL_THREADS = 256;               // 4 px per thread, 2 rows per thread
-constexpr int SURR_UP_ROWS = 4;               // surrogate upsampling: 64 x 4 px per block, one per thread
+constexpr int SURR_UP_PX = 4;                 // surrogate upsampling: pixels per thread (rows 4 apart)
+constexpr int SURR_UP_ROWS = 4 * SURR_UP_PX;  // 64 x 16 px per block
 constexpr int SURR_UP_SUB = STRIP_TY / SURR_UP_ROWS;   // upsampling blocks per strip tile
+static_assert(STRIP_TY % SURR_UP_ROWS == 0, "whole upsampling blocks per strip tile");
 
 // Per-frame accumulators, zeroed at the start of every frame.
 // Sums that many blocks add to are kept in several copies (tile t adds to copy

@@ -137,9 +137,11 @@ __device__ __forceinline__ uint32_t wave_sum(uint32_t v)
     return v;
 }
 
-// one overlap pixel per thread (64 x 4 px per block, SURR_UP_SUB blocks per
-// strip tile); each block writes its error sum and pixel count (exact
-// integers, at most 2^20 * 256 per block)
+// SURR_UP_PX overlap pixels per thread, rows 4 apart (64 x SURR_UP_ROWS px per
+// block, SURR_UP_SUB blocks per strip tile): the pixels' dependent lookups
+// (mask, upsampled flow, the reverse flow at the displaced position) are in
+// flight together.  Each block writes its error sum and pixel count (exact
+// integers, at most 2^20 * 1024 per block).
 __global__ __launch_bounds__(256) void k_surr_up(const DevPlan* __restrict__ P)
 {
     __shared__ uint32_t s_red[2][4];
@@ -153,20 +155,33 @@ __global__ __launch_bounds__(256) void k_surr_up(const DevPlan* __restrict__ P)
     const float2* __restrict__ pij = reinterpret_cast<const float2*>(P->surr_pred) + P->surr_pix[2 * p];
     const float2* __restrict__ pji = reinterpret_cast<const float2*>(P->surr_pred) + P->surr_pix[2 * p + 1];
     const int lx = (t % P->strip_tx[p]) * STRIP_TX + (tid & 63);
-    const int ly = (t / P->strip_tx[p]) * STRIP_TY + sub * SURR_UP_ROWS + (tid >> 6);
-    uint32_t esum = 0, cnt = 0;
-    if (lx < sw && ly < sh) {
+    const int ly0 = (t / P->strip_tx[p]) * STRIP_TY + sub * SURR_UP_ROWS + (tid >> 6);
+    bool on[SURR_UP_PX];
+#pragma unroll
+    for (int k = 0; k < SURR_UP_PX; ++k) {
+        const int ly = ly0 + 4 * k;
+        on[k] = lx < sw && ly < sh && P->need[p][0][(long)ly * sw + lx] != 0;
+    }
+    float2 u[SURR_UP_PX];
+#pragma unroll
+    for (int k = 0; k < SURR_UP_PX; ++k) {
+        if (!on[k]) continue;
+        const int ly = ly0 + 4 * k;
         const long q = (long)ly * sw + lx;
-        if (P->need[p][0][q]) {
-            const float2 u = up_at(pij, w2, h2, (float)lx, (float)ly);
-            P->flow[p][0][0][q] = u;
-            P->flow[p][1][0][q] = up_at(pji, w2, h2, (float)lx, (float)ly);
-            const float2 v = up_at(pji, w2, h2, (float)lx + u.x, (float)ly + u.y);
-            const float ex = u.x + v.x, ey = u.y + v.y;
-            const float e = sqrtf(ex * ex + ey * ey);
-            esum = (uint32_t)floorf(fminf(e * 256.0f, 1048576.0f) + 0.5f);
-            cnt = 1;
-        }
+        u[k] = up_at(pij, w2, h2, (float)lx, (float)ly);
+        P->flow[p][0][0][q] = u[k];
+        P->flow[p][1][0][q] = up_at(pji, w2, h2, (float)lx, (float)ly);
+    }
+    uint32_t esum = 0, cnt = 0;
+#pragma unroll
+    for (int k = 0; k < SURR_UP_PX; ++k) {
+        if (!on[k]) continue;
+        const int ly = ly0 + 4 * k;
+        const float2 v = up_at(pji, w2, h2, (float)lx + u[k].x, (float)ly + u[k].y);
+        const float ex = u[k].x + v.x, ey = u[k].y + v.y;
+        const float e = sqrtf(ex * ex + ey * ey);
+        esum += (uint32_t)floorf(fminf(e * 256.0f, 1048576.0f) + 0.5f);
+        cnt += 1;
     }
     esum = wave_sum(esum);
     cnt = wave_sum(cnt);
