@@ -317,12 +317,20 @@ vs_status vs_create(const vs_rig* rig, const vs_params* prm, vs_ctx** out)
         h.strip_tx[p] = (h.sw[p] + STRIP_TX - 1) / STRIP_TX;
         h.strip_off[p + 1] = h.strip_off[p] + h.strip_tx[p] * ((h.sh[p] + STRIP_TY - 1) / STRIP_TY);
     }
+    // fused pyramid tiles: 32 x 16 level-2 pixels, or 32 x 8 when that grid
+    // would leave the device with under ~6 blocks per compute unit
+    int n16 = 0;
+    for (int f = 0; f < 2 * h.n_pairs && h.levels >= 3; ++f) {
+        const int p = f >> 1;
+        n16 += ((h.lw[p][2] + PF_TX - 1) / PF_TX) * ((h.lh[p][2] + 15) / 16);
+    }
+    h.pyrf_ty = n16 >= 1536 ? 16 : 8;
     h.pyrf_off[0] = 0;
     for (int f = 0; f < 2 * h.n_pairs; ++f) {
         const int p = f >> 1;
         const int w2 = h.levels >= 3 ? h.lw[p][2] : 0, h2 = h.levels >= 3 ? h.lh[p][2] : 0;
         h.pyrf_tx[f] = (w2 + PF_TX - 1) / PF_TX;
-        h.pyrf_off[f + 1] = h.pyrf_off[f] + h.pyrf_tx[f] * ((h2 + PF_TY - 1) / PF_TY);
+        h.pyrf_off[f + 1] = h.pyrf_off[f] + h.pyrf_tx[f] * ((h2 + h.pyrf_ty - 1) / h.pyrf_ty);
     }
     for (int l = 0; l < h.levels; ++l) {
         h.pyr_off[l][0] = 0;

@@ -19,7 +19,7 @@ constexpr int SURR_MAX_LAYERS = 8;
 // Tile shapes.
 constexpr int STRIP_TX = 64, STRIP_TY = 32;   // strip kernels: 256 threads, 8 rows each
 constexpr int PYR_TX = 64, PYR_TY = 16;       // pyramid kernels: 256 threads, 4 rows each
-constexpr int PF_TX = 32, PF_TY = 16;         // fused levels 0-2: level-2 tile
+constexpr int PF_TX = 32;                     // fused levels 0-2: level-2 tile PF_TX x pyrf_ty (8 or 16)
 constexpr int LK_T = 16;                      // generic flow kernel: 16 x 16 pixels, one per thread
 constexpr int LK_R_MAX = 4;                   // window half-size limit of the staged tiles
 constexpr int LK_D = 8;                       // displacement the staged moving tile covers
@@ -77,6 +77,7 @@ struct DevPlan {
     int32_t strip_off[MAXP + 1], strip_tx[MAXP];
     int32_t pyr_off[MAXL][2 * MAXP + 1], pyr_tx[MAXL][2 * MAXP];   // field f = 2 p + cam
     int32_t pyrf_off[2 * MAXP + 1], pyrf_tx[2 * MAXP];             // fused levels 0-2: level-2 tiles
+    int32_t pyrf_ty;                                               // their height: 16, or 8 for small strips
     int32_t lk_off[MAXL][2 * MAXP + 1], lk_tx[MAXL][2 * MAXP];     // field f = 2 p + dir
     int32_t lk_P[MAXL];               // 0: generic kernel (16 x 16 tiles); 1, 2, 4: 9x9 kernel, P px per thread
     int32_t blend_tx, blend_ty, cover_words;

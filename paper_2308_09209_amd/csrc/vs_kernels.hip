@@ -591,8 +591,6 @@ __global__ __launch_bounds__(256) void k_pyr_down(const Batch B, int l, int skip
 // done once per block instead of once per output row.  The tile interiors of
 // levels 0 and 1 are written too when the plain estimator reads them this
 // frame (VS_FLOW_PLAIN); otherwise only level 2, the surrogate's input.
-constexpr int PF_W1 = 2 * PF_TX + 3, PF_H1 = 2 * PF_TY + 3;     // level-1 footprint
-constexpr int PF_W0 = 4 * PF_TX + 9, PF_H0 = 4 * PF_TY + 9;     // level-0 footprint
 
 __device__ __forceinline__ float tap5(float a0, float a1, float a2, float a3, float a4)
 {
@@ -603,8 +601,11 @@ __device__ __forceinline__ float tap5(float a0, float a1, float a2, float a3, fl
     return acc * 0.0625f;
 }
 
+template <int PF_TY>
 __device__ __forceinline__ void pyr_fused_body(const DevPlan* __restrict__ P, const int bid, int after)
 {
+    constexpr int PF_W1 = 2 * PF_TX + 3, PF_H1 = 2 * PF_TY + 3;     // level-1 footprint
+    constexpr int PF_W0 = 4 * PF_TX + 9, PF_H0 = 4 * PF_TY + 9;     // level-0 footprint
     __shared__ uint8_t s0[PF_H0][PF_W0 + 3];
     __shared__ float sh[PF_H0 * PF_W1];    // level-0 rows at level-1 columns; then level-1 rows at level-2 columns
     __shared__ float s1[PF_H1][PF_W1];
@@ -702,11 +703,12 @@ __device__ __forceinline__ void pyr_fused_body(const DevPlan* __restrict__ P, co
 
 // after: launched after the surrogate's decisions for the pairs that did not
 // keep its flows (levels 0 and 1 written; level 2 again, the same values)
+template <int PF_TY>
 __global__ __launch_bounds__(256) void k_pyr_fused(const Batch B, int after)
 {
     int c;
     const int b = batch_block(B, blockIdx.x, c);
-    pyr_fused_body(B.plan[c], b, after);
+    pyr_fused_body<PF_TY>(B.plan[c], b, after);
 }
 
 
@@ -1083,13 +1085,21 @@ hipError_t launch_pyr0(const Group& g, int phase, hipStream_t s)
 
 hipError_t launch_pyr_fused(const Group& g, int phase, hipStream_t s)
 {
-    Batch B;
     const bool after = phase == PYR_AFTER;
-    if (make_batch(g, B, [&](const DevPlan& h) {
-            const bool on = h.use_flow && h.levels >= 3 && (!after || h.flow_mode == VS_FLOW_SURROGATE_FALLBACK);
-            return on ? h.pyrf_off[2 * h.n_pairs] : 0; }))
-        hipLaunchKernelGGL(k_pyr_fused, dim3(B.off[B.n]), dim3(256), 0, s, B, after ? 1 : 0);
-    return hipGetLastError();
+    // one launch per tile height present in the group
+    for (const int ty : {16, 8}) {
+        Batch B;
+        if (make_batch(g, B, [&](const DevPlan& h) {
+                const bool on = h.use_flow && h.levels >= 3 && h.pyrf_ty == ty &&
+                                (!after || h.flow_mode == VS_FLOW_SURROGATE_FALLBACK);
+                return on ? h.pyrf_off[2 * h.n_pairs] : 0; })) {
+            if (ty == 16) hipLaunchKernelGGL(k_pyr_fused<16>, dim3(B.off[B.n]), dim3(256), 0, s, B, after ? 1 : 0);
+            else hipLaunchKernelGGL(k_pyr_fused<8>, dim3(B.off[B.n]), dim3(256), 0, s, B, after ? 1 : 0);
+        }
+        const hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
 }
 
 hipError_t launch_pyr_down(const Group& g, int l, int phase, hipStream_t s)
