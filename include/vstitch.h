@@ -86,6 +86,8 @@ typedef struct {
     int32_t balance;        /* 1: apply the balancing LUT to covered pixels (1) */
     int32_t lambda_pct;     /* balancing quantile in percent, 1..49 (5) */
     int32_t debug_taps;     /* 1: keep a copy of the pre-balance panorama for vs_debug_tap (0) */
+    int32_t pyr_tile_rows;  /* pyramid levels 0-2 in one pass, level-2 tile height: 8 or 16, or 0:
+                               16 unless that gives under 1536 tiles (0); results do not depend on it */
 } vs_params;
 
 /* Temporal colour state: the only information carried between frames.

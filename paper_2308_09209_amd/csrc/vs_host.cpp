@@ -171,6 +171,7 @@ vs_status vs_default_params(vs_params* p)
     p->balance = 1;
     p->lambda_pct = 5;
     p->debug_taps = 0;
+    p->pyr_tile_rows = 0;
     return VS_OK;
 }
 
@@ -202,7 +203,8 @@ vs_status vs_create(const vs_rig* rig, const vs_params* prm, vs_ctx** out)
     else vs_default_params(&P);
     if (P.lk_levels < 1 || P.lk_levels > VS_MAX_LEVELS || P.lk_iters < 0 || P.lk_radius < 0 ||
         P.lk_radius > LK_R_MAX || P.color_window < 0 || P.color_window > 3 || P.lambda_pct < 1 ||
-        P.lambda_pct > 49 || !(P.ridge >= 0.0) || !std::isfinite(P.lk_lambda))
+        P.lambda_pct > 49 || !(P.ridge >= 0.0) || !std::isfinite(P.lk_lambda) ||
+        (P.pyr_tile_rows != 0 && P.pyr_tile_rows != 8 && P.pyr_tile_rows != 16))
         return VS_E_INVAL;
 
     vs_ctx* c = new (std::nothrow) vs_ctx();
@@ -324,7 +326,7 @@ vs_status vs_create(const vs_rig* rig, const vs_params* prm, vs_ctx** out)
         const int p = f >> 1;
         n16 += ((h.lw[p][2] + PF_TX - 1) / PF_TX) * ((h.lh[p][2] + 15) / 16);
     }
-    h.pyrf_ty = n16 >= 1536 ? 16 : 8;
+    h.pyrf_ty = P.pyr_tile_rows ? P.pyr_tile_rows : (n16 >= 1536 ? 16 : 8);
     h.pyrf_off[0] = 0;
     for (int f = 0; f < 2 * h.n_pairs; ++f) {
         const int p = f >> 1;

@@ -225,3 +225,40 @@ def test_parity_4x1920x1080_ring_full_size():
         say(f"  flow pixels finished by the tail kernel per level: {deferred}")
         check_steps(st, orc, f"4x1080p t={t}", full=(t == 0))
     st.close()
+
+
+@pytest.mark.parametrize("rows", [8, 16])
+def test_fused_pyramid_tile_heights(rows):
+    """levels 0-2 in one pass at either level-2 tile height: every pyramid
+    level of both cameras and the panorama bit for bit against the oracle
+    (plain flow), and the fallback path's rebuild of the levels for pairs not
+    kept (threshold 0: none kept) equal to the plain path's panorama"""
+    s = small_scene(n_cams=3, W=400, H=240, overlap=0.3, ring=True, seed_config=93, drift=0.02)
+    rig = s.rig()
+    st = V.Stitcher(rig, pyr_tile_rows=rows)
+    orc = O.Oracle(rig)
+    for t in range(2):
+        pano = st.stitch(dev(s.frames(t))).cpu().numpy()
+        want = orc.stitch(s.frames(t))
+        say(f"[pyramid tiles {rows} rows] frame {t}: max |gpu - oracle| {lsb(pano, want)} LSB")
+        assert np.array_equal(pano, want), t
+        for p in range(st.n_pairs):
+            for cam in (0, 1):
+                for lvl in range(st.info.lk_levels):
+                    np.testing.assert_array_equal(st.tap("pyr", p, cam * 8 + lvl), orc.tap("pyr", p, cam * 8 + lvl),
+                                                  err_msg=f"rows {rows} pair {p} cam {cam} level {lvl}")
+    from paper_2308_09209_amd import scenes as S
+    fb = V.Stitcher(rig, pyr_tile_rows=rows)
+    fb.load_weights(S.nn_blob(*S.random_net(31)))
+    fb.set_flow_mode(V.FLOW_SURROGATE_FALLBACK, 0.0)
+    ref = V.Stitcher(rig, pyr_tile_rows=rows)
+    for t in range(2):
+        a = fb.stitch(dev(s.frames(t))).cpu().numpy()
+        b = ref.stitch(dev(s.frames(t))).cpu().numpy()
+        assert np.array_equal(a, b), t
+
+
+def test_pyramid_tile_height_parameter_is_checked():
+    s = small_scene(n_cams=2, W=160, H=96, overlap=0.3)
+    with pytest.raises(V.VSError):
+        V.Stitcher(s.rig(), pyr_tile_rows=12)
