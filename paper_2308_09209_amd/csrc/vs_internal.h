@@ -46,7 +46,7 @@ struct Accum {
     uint32_t lk_qn[8];                             // flow pixels deferred to the tail kernel, per level
 };
 static_assert(MAXL <= 8, "one deferral counter per level");
-static_assert(sizeof(Accum) % 16 == 0, "k_zero clears whole 16-byte words");
+static_assert(sizeof(Accum) % 16 == 0, "the fill kernels clear whole 16-byte words");
 
 // Per-frame results (also the taps).
 struct Results {
