@@ -238,47 +238,39 @@ __global__ __launch_bounds__(256) void k_strips(const Batch B)
 // Section 2.1 step 3: histogram specification LUT(v) = min{w : C_j(w) >= C_i(v)}
 // ---------------------------------------------------------------------------
 
+// one thread per (channel, level): tid = 256 c + v
 __device__ __forceinline__ void lut_body(const DevPlan* __restrict__ P, const int bid)
 {
     __shared__ uint32_t Ci[3][256], Cj[3][256];
-    const int p = bid, v = threadIdx.x;
+    const int p = bid, c = threadIdx.x >> 8, v = threadIdx.x & 255;
     const Accum* acc = P->acc;
-    for (int c = 0; c < 3; ++c) {
-        uint32_t sj = 0, si = 0;
-        for (int k = 0; k < HIST_SPREAD; ++k) {
-            sj += acc->hist[p][k][0][c][v];
-            si += acc->hist[p][k][1][c][v];
-        }
-        Cj[c][v] = sj;
-        Ci[c][v] = si;
+    uint32_t sj = 0, si = 0;
+#pragma unroll 8
+    for (int k = 0; k < HIST_SPREAD; ++k) {
+        sj += acc->hist[p][k][0][c][v];
+        si += acc->hist[p][k][1][c][v];
     }
+    Cj[c][v] = sj;
+    Ci[c][v] = si;
     __syncthreads();
     for (int o = 1; o < 256; o <<= 1) {
-        uint32_t ti[3], tj[3];
-        for (int c = 0; c < 3; ++c) {
-            ti[c] = v >= o ? Ci[c][v - o] : 0;
-            tj[c] = v >= o ? Cj[c][v - o] : 0;
-        }
+        const uint32_t ti = v >= o ? Ci[c][v - o] : 0, tj = v >= o ? Cj[c][v - o] : 0;
         __syncthreads();
-        for (int c = 0; c < 3; ++c) {
-            Ci[c][v] += ti[c];
-            Cj[c][v] += tj[c];
-        }
+        Ci[c][v] += ti;
+        Cj[c][v] += tj;
         __syncthreads();
     }
-    for (int c = 0; c < 3; ++c) {
-        uint32_t target = Ci[c][v];
-        int lo = 0, hi = 256;   // first w with Cj[w] >= target
-        while (lo < hi) {
-            int mid = (lo + hi) >> 1;
-            if (Cj[c][mid] < target) lo = mid + 1;
-            else hi = mid;
-        }
-        P->res->lut[p][c][v] = (uint8_t)(lo > 255 ? 255 : lo);
+    const uint32_t target = Ci[c][v];
+    int lo = 0, hi = 256;   // first w with Cj[w] >= target
+    while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if (Cj[c][mid] < target) lo = mid + 1;
+        else hi = mid;
     }
+    P->res->lut[p][c][v] = (uint8_t)(lo > 255 ? 255 : lo);
 }
 
-__global__ __launch_bounds__(256) void k_lut(const Batch B)
+__global__ __launch_bounds__(768) void k_lut(const Batch B)
 {
     int c;
     const int b = batch_block(B, blockIdx.x, c);
@@ -1036,7 +1028,7 @@ hipError_t launch_lut(const Group& g, hipStream_t s)
 {
     Batch B;
     if (make_batch(g, B, [](const DevPlan& h) { return h.n_pairs; }))
-        hipLaunchKernelGGL(k_lut, dim3(B.off[B.n]), dim3(256), 0, s, B);
+        hipLaunchKernelGGL(k_lut, dim3(B.off[B.n]), dim3(768), 0, s, B);
     return hipGetLastError();
 }
 

@@ -95,3 +95,19 @@ def test_batch_autotune_keeps_results():
         for c in range(len(sts)):
             np.testing.assert_array_equal(panos[c].cpu().numpy(), ref[c][t])
     b.close()
+
+
+def test_batch_with_mixed_pyramid_tile_heights():
+    """contexts of one graph with different fused-pyramid tile heights (one
+    fused launch per height) give their single-context results"""
+    scs = scenes()
+    ref = reference(scs, 2)
+    sts = [V.Stitcher(sc.rig(), pyr_tile_rows=rows) for sc, rows in zip(scs, (16, 8, 16))]
+    b = V.Batch(sts)
+    panos = [st.new_pano() for st in sts]
+    for t in range(2):
+        b.run([dev(sc.frames(t)) for sc in scs], panos)
+        torch.cuda.synchronize()
+        for c in range(len(sts)):
+            np.testing.assert_array_equal(panos[c].cpu().numpy(), ref[c][t], err_msg=f"ctx {c} frame {t}")
+    b.close()
