@@ -187,8 +187,8 @@ def main():
                          "counter reference for rocprofv3 byte counters)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py: this build measures one GPU; the path's sharding across GPUs is a design "
-              "only (see DESIGN.md). Run with --gpus 1.", file=sys.stderr)
+        print("bench.py: the stitching path runs on one GPU (how it would shard across GPUs is a "
+              "design, not built). Run with --gpus 1.", file=sys.stderr)
         sys.exit(2)
 
     import torch
