@@ -225,7 +225,7 @@ __device__ __forceinline__ void lk_w9_body(const DevPlan* __restrict__ Pl, const
     const uint8_t* __restrict__ need = Pl->need[p][l];
     float ux[P], uy[P], g00[P], g01[P], g11[P], det[P];
     bool act[P];
-    int dit[P];   // INBLOCK: step at which the pixel was deferred (-1: not deferred)
+    int dit[P];   // step at which the pixel was deferred (-1: not deferred)
 #pragma unroll
     for (int q = 0; q < P; ++q) {
         const int y = yb + q;
@@ -296,16 +296,8 @@ __device__ __forceinline__ void lk_w9_body(const DevPlan* __restrict__ Pl, const
             bv[q] = 0.0f;
             if (act[q] && !(ox >= -(LK_D + 1) && ox <= LK_D && oy >= -(LK_D + 1) && oy <= LK_D)) {
                 // the displacement leaves the staged tile: the pixel, with its state
-                // at the start of this step, goes to the tail (kernel or block end)
-                if (INBLOCK) {
-                    dit[q] = it;
-                } else {
-                    const uint32_t slot = atomicAdd(&Pl->acc->lk_qn[l], 1u);
-                    if (slot < (uint32_t)Pl->lk_qcap[l])
-                        Pl->lk_queue[l][slot] = make_uint4((uint32_t)f | ((uint32_t)it << 8),
-                                                           (uint32_t)x | ((uint32_t)(yb + q) << 16),
-                                                           __float_as_uint(ux[q]), __float_as_uint(uy[q]));
-                }
+                // at the start of this step (kept from here on), goes to the tail
+                dit[q] = it;
                 act[q] = false;
             }
             if (!act[q]) {
@@ -364,6 +356,35 @@ __device__ __forceinline__ void lk_w9_body(const DevPlan* __restrict__ Pl, const
     if (INBLOCK) {
         for (int q = 0; q < P; ++q)
             if (dit[q] >= 0) lk_tail_pixel<1>(Pl, l, f, x, yb + q, dit[q], ux[q], uy[q]);
+    } else {
+        // queue the deferred pixels for the tail kernel: one reservation per
+        // wavefront, after the steps (a reservation returns only after a round
+        // trip to the memory-side counter, which stalled the whole wavefront
+        // when taken inside the steps)
+        unsigned long long mq[P];
+        uint32_t tot = 0;
+#pragma unroll
+        for (int q = 0; q < P; ++q) {
+            mq[q] = __ballot(dit[q] >= 0);
+            tot += (uint32_t)__popcll(mq[q]);
+        }
+        if (tot != 0u) {
+            uint32_t base = 0;
+            if (lane == 0) base = atomicAdd(&Pl->acc->lk_qn[l], tot);
+            base = (uint32_t)__shfl((int)base, 0, 64);
+#pragma unroll
+            for (int q = 0; q < P; ++q) {
+                if (dit[q] >= 0) {
+                    const uint32_t slot =
+                        base + __builtin_amdgcn_mbcnt_hi((uint32_t)(mq[q] >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)mq[q], 0u));
+                    if (slot < (uint32_t)Pl->lk_qcap[l])
+                        Pl->lk_queue[l][slot] = make_uint4((uint32_t)f | ((uint32_t)dit[q] << 8),
+                                                           (uint32_t)x | ((uint32_t)(yb + q) << 16),
+                                                           __float_as_uint(ux[q]), __float_as_uint(uy[q]));
+                }
+                base += (uint32_t)__popcll(mq[q]);
+            }
+        }
     }
 }
 
