@@ -396,13 +396,12 @@ __global__ __launch_bounds__(256) void k_lk_w9(const Batch B, int l)
     lk_w9_body<P, INBLOCK>(B.plan[c], b, l);
 }
 
-// Pixels whose displacement left the staged tile finish here, one pixel per
-// lane, every tap read from global memory with clamped indices (gradients 0
-// outside the level, as in the staged kernel, so the row-major sums are the
-// same).  Each window row issues all of its loads before using them: the
-// kernel is latency-bound on about one round trip per window row.
-// ROWS_UNROLL: window rows unrolled (the tail kernel, all of a row's loads in
-// flight) or 1 (inside the staged kernel, where registers are scarce); the
+// Pixels whose displacement left the staged tile finish here (inside the
+// staged kernel, at its end), one pixel per lane, every tap read from global
+// memory with clamped indices (gradients 0 outside the level, as in the staged
+// kernel, so the row-major sums are the same).  Each window row issues all of
+// its loads before using them: about one memory round trip per window row.
+// ROWS_UNROLL: window rows unrolled, or 1 where registers are scarce; the
 // arithmetic and its order are the same
 template <int ROWS_UNROLL>
 __device__ __forceinline__ void lk_tail_pixel(const DevPlan* __restrict__ Pl, int l, int f, int x, int y, int it0,
@@ -504,17 +503,127 @@ __device__ __forceinline__ void lk_tail_pixel(const DevPlan* __restrict__ Pl, in
     }
 }
 
+// The tail kernel proper: 16 lanes per queued pixel, lane r of a group taking
+// window row r.  Every row's taps of a step are loaded at once (one memory
+// round trip per step instead of one per row); the sums then run through the
+// rows in order, the lane of each row adding its taps to the partial sums it
+// received from the lane of the row above and handing them on, so each sum is
+// the same row-major sequence of fused multiply-adds as in lk_tail_pixel.
+constexpr int LK_TAIL_G = 16;
+
 __global__ __launch_bounds__(256) void k_lk_tail(const Batch B, int l)
 {
-    int c;
-    const int b = batch_block(B, blockIdx.x, c);
-    const int nb = B.off[c + 1] - B.off[c];          // this context's blocks
-    const DevPlan* __restrict__ Pl = B.plan[c];
+    constexpr int R = LK_R_MAX, NW = 2 * R + 1, G = LK_TAIL_G;
+    static_assert(NW + 1 <= G && 256 % G == 0, "one window row per lane, plus the lane that receives the sums");
+    int cx;
+    const int b = batch_block(B, blockIdx.x, cx);
+    const int nb = B.off[cx + 1] - B.off[cx];        // this context's blocks
+    const DevPlan* __restrict__ Pl = B.plan[cx];
     const uint32_t n = min(Pl->acc->lk_qn[l], (uint32_t)Pl->lk_qcap[l]);
-    for (uint32_t i = b * 256 + threadIdx.x; i < n; i += nb * 256) {
+    const int sub = (int)(threadIdx.x % G);
+    const int jr = sub < NW ? sub : NW - 1;           // lanes past the window repeat its last row, unused
+    const int iters = Pl->lk_iters;
+    // a whole group takes the same entry, so the group's lanes stay together
+    for (uint32_t i = (b * 256 + threadIdx.x) / G; i < n; i += (uint32_t)nb * (256 / G)) {
         const uint4 ent = Pl->lk_queue[l][i];
-        lk_tail_pixel<2 * LK_R_MAX + 1>(Pl, l, (int)(ent.x & 255u), (int)(ent.y & 0xffffu), (int)(ent.y >> 16),
-                                        (int)(ent.x >> 8), __uint_as_float(ent.z), __uint_as_float(ent.w));
+        const int f = (int)(ent.x & 255u), it0 = (int)(ent.x >> 8);
+        const int x = (int)(ent.y & 0xffffu), y = (int)(ent.y >> 16);
+        float ux = __uint_as_float(ent.z), uy = __uint_as_float(ent.w);
+        const int p = f >> 1, dir = f & 1;
+        const int w = Pl->lw[p][l], h = Pl->lh[p][l];
+        const float* __restrict__ Tm = Pl->pyr[p][dir == 0 ? 0 : 1][l];
+        const float* __restrict__ Mv = Pl->pyr[p][dir == 0 ? 1 : 0][l];
+        // this lane's window row: template values and gradients (0 outside the level)
+        const int yy = y - R + jr;
+        const bool rin = yy >= 0 && yy < h;
+        float tc[NW], gx[NW], gy[NW];
+        {
+            const float* t0 = Tm + (size_t)clampi(yy - 1, 0, h - 1) * w;
+            const float* t1 = Tm + (size_t)clampi(yy, 0, h - 1) * w;
+            const float* t2 = Tm + (size_t)clampi(yy + 1, 0, h - 1) * w;
+            float a[NW + 2], up[NW], dn[NW];
+#pragma unroll
+            for (int k = 0; k < NW + 2; ++k) a[k] = t1[clampi(x - R - 1 + k, 0, w - 1)];
+#pragma unroll
+            for (int c = 0; c < NW; ++c) {
+                const int xc = clampi(x - R + c, 0, w - 1);
+                up[c] = t0[xc];
+                dn[c] = t2[xc];
+            }
+#pragma unroll
+            for (int c = 0; c < NW; ++c) {
+                const bool in = rin && x - R + c >= 0 && x - R + c < w;
+                gx[c] = in ? 0.5f * (a[c + 2] - a[c]) : 0.0f;
+                gy[c] = in ? 0.5f * (dn[c] - up[c]) : 0.0f;
+                tc[c] = a[c + 1];
+            }
+        }
+        // normal matrix: row r's lane adds its taps at hand-on r
+        float g00 = 0.0f, g01 = 0.0f, g11 = 0.0f;
+#pragma unroll
+        for (int r = 0; r < NW; ++r) {
+            if (sub == r) {
+#pragma unroll
+                for (int c = 0; c < NW; ++c) {
+                    g00 = __builtin_fmaf(gx[c], gx[c], g00);
+                    g01 = __builtin_fmaf(gx[c], gy[c], g01);
+                    g11 = __builtin_fmaf(gy[c], gy[c], g11);
+                }
+            }
+            g00 = __shfl_up(g00, 1, G);
+            g01 = __shfl_up(g01, 1, G);
+            g11 = __shfl_up(g11, 1, G);
+        }
+        g00 = __shfl(g00, NW, G);
+        g01 = __shfl(g01, NW, G);
+        g11 = __shfl(g11, NW, G);
+        const int ncx = min(x + R, w - 1) - max(x - R, 0) + 1;
+        const int ncy = min(y + R, h - 1) - max(y - R, 0) + 1;
+        const float reg = Pl->lk_lambda * (float)(ncy * ncx);
+        g00 = g00 + reg;
+        g11 = g11 + reg;
+        const float det = g00 * g11 - g01 * g01;
+        for (int it = it0; it < iters; ++it) {
+            const float flx = floorf(ux), fly = floorf(uy);
+            const int ox = (int)flx, oy = (int)fly;
+            const float fx = ux - flx, fy = uy - fly;
+            const float* m0 = Mv + (size_t)clampi(yy + oy, 0, h - 1) * w;
+            const float* m1 = Mv + (size_t)clampi(yy + oy + 1, 0, h - 1) * w;
+            float ra[NW + 1], rb[NW + 1];
+#pragma unroll
+            for (int k = 0; k < NW + 1; ++k) {
+                const int xm = clampi(x - R + ox + k, 0, w - 1);
+                ra[k] = m0[xm];
+                rb[k] = m1[xm];
+            }
+            float e[NW];
+#pragma unroll
+            for (int c = 0; c < NW; ++c) {
+                const float ta = __builtin_fmaf(fx, ra[c + 1] - ra[c], ra[c]);
+                const float tb = __builtin_fmaf(fx, rb[c + 1] - rb[c], rb[c]);
+                e[c] = __builtin_fmaf(fy, tb - ta, ta) - tc[c];
+            }
+            float bu = 0.0f, bv = 0.0f;
+#pragma unroll
+            for (int r = 0; r < NW; ++r) {
+                if (sub == r) {
+#pragma unroll
+                    for (int c = 0; c < NW; ++c) {
+                        bu = __builtin_fmaf(gx[c], e[c], bu);
+                        bv = __builtin_fmaf(gy[c], e[c], bv);
+                    }
+                }
+                bu = __shfl_up(bu, 1, G);
+                bv = __shfl_up(bv, 1, G);
+            }
+            bu = __shfl(bu, NW, G);
+            bv = __shfl(bv, NW, G);
+            const float du = (g01 * bv - g11 * bu) / det;
+            const float dv = (g01 * bu - g00 * bv) / det;
+            ux = ux + du;
+            uy = uy + dv;
+        }
+        if (sub == 0) Pl->flow[p][dir][l][(size_t)y * w + x] = make_float2(ux, uy);
     }
 }
 
@@ -601,7 +710,7 @@ hipError_t launch_lk(const Group& g, int l, hipStream_t s)
     if (e != hipSuccess || P == 0 || inblock) return e;
     // deferred pixels: the device-side count bounds the grid-stride loop
     if (make_batch(g, B, [&](const DevPlan& h) {
-            return plain(h) && l < h.levels ? std::min(1024, std::max(1, (h.lk_qcap[l] + 255) / 256)) : 0; }))
+            return plain(h) && l < h.levels ? std::min(4096, std::max(1, (h.lk_qcap[l] + 256 / LK_TAIL_G - 1) / (256 / LK_TAIL_G))) : 0; }))
         hipLaunchKernelGGL(k_lk_tail, dim3(B.off[B.n]), dim3(256), 0, s, B, l);
     return hipGetLastError();
 }
