@@ -27,6 +27,7 @@ sys.path.insert(0, ROOT)
 
 FP32_VECTOR_PEAK_TFLOPS = 157.3   # MI355X published FP32 vector peak
 BF16_MFMA_PEAK_TFLOPS = 2500.0    # MI355X published dense BF16 matrix peak
+HBM_PEAK_TBS = 8.0                # MI355X published HBM3E bandwidth
 HBM_PEAK_GBS = 8000.0
 DEFAULT_WEIGHTS = os.path.join(ROOT, "paper_2308_09209_amd", "weights", "flow_surrogate.vsnn")
 FLOW_MODES = {"plain": 0, "surrogate": 1, "fallback": 2}
@@ -64,6 +65,25 @@ def load_pmc(kernel, workload):
     if rec.get("kernels_sha256") != hashlib.sha256(src).hexdigest():
         return None
     return rec.get("bytes_per_launch")
+
+
+def frame_roofline(wl, pano_h, pano_w, flow_flops, flow_peak_tflops, ms_per_frame):
+    """Frame-level mixed roofline: the time a frame would take if every step ran
+    at its own bound, over the measured time.  Bytes: the compulsory ones (each
+    camera frame read once, the panorama written once, then read and written
+    again by the balance, which needs the frame's own histogram first) at the
+    HBM peak; flops: the flow step's algorithmic count at its unit's peak.  The
+    other steps' arithmetic and the declared intermediates (strips, pyramids,
+    flows) are left out, so this is a lower bound on the frame time."""
+    frames_b = wl["n_cams"] * wl["W"] * wl["H"] * 3
+    pano_b = pano_h * pano_w * 3
+    comp = frames_b + 3 * pano_b
+    t_bytes = comp / (HBM_PEAK_TBS * 1e12) * 1e3
+    t_flops = flow_flops / (flow_peak_tflops * 1e12) * 1e3
+    t_roof = t_bytes + t_flops
+    return dict(t_roof_ms=round(t_roof, 5), t_ms=round(ms_per_frame, 5), frac=round(t_roof / ms_per_frame, 4),
+                compulsory_bytes=comp, bytes_ms=round(t_bytes, 5), flow_flops=int(flow_flops),
+                flow_peak_tflops=flow_peak_tflops, flops_ms=round(t_flops, 5))
 
 
 def surrogate_flops_per_frame(info, layers):
@@ -273,7 +293,8 @@ def main():
                p50_ms=round(float(np.percentile(lat, 50)), 4),
                p99_ms=round(float(np.percentile(lat, 99)), 4),
                step_ms={n: round(v / nfr, 5) for n, v in zip(names, step_ms)},
-               roofline=roofline)
+               roofline=roofline,
+               frame_roofline=frame_roofline(wl, H, W, flops, FP32_VECTOR_PEAK_TFLOPS, wall / K * 1e3))
     if args.flow != "plain" and os.path.exists(args.weights):
         out["surrogate"] = surrogate_leg(args, V, rig, frames, st, K, H, W, mpix, float(np.percentile(lat, 99)))
     if not args.no_cpu_baseline:
@@ -288,6 +309,8 @@ def surrogate_leg(args, V, rig, frames, st_plain, K, H, W, mpix_plain, p99_plain
     """The same frames with the learned flow surrogate: throughput, latency, its
     flows' end-point error against the plain path's, and the matrix-core rate."""
     import torch
+
+    from paper_2308_09209_amd.scenes import WORKLOADS
     blob = open(args.weights, "rb").read()
     mode, tau = FLOW_MODES[args.flow], args.fb_tau
     ss = V.Stitcher(rig)
@@ -323,6 +346,8 @@ def surrogate_leg(args, V, rig, frames, st_plain, K, H, W, mpix_plain, p99_plain
                 epe_vs_plain_px=round(float(np.mean(epes)), 4), epe_p99_px=round(float(np.mean(p99s)), 4),
                 epe_frames=args.epe_frames, pairs_kept=f"{kept}/{pairs}",
                 step_ms={n: round(v / nfr, 5) for n, v in zip(names, step_ms)},
+                frame_roofline=frame_roofline(WORKLOADS[args.workload], H, W, fl, BF16_MFMA_PEAK_TFLOPS,
+                                              wall / K * 1e3),
                 mfma=dict(flops_per_frame=fl, flow_step_ms=round(flow_ms, 5),
                           achieved=round(fl / (flow_ms * 1e-3) / 1e12, 3), peak=BF16_MFMA_PEAK_TFLOPS,
                           unit="TFLOP/s", note="network flops (first layer on its 2 non-zero input "
