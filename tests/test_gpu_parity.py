@@ -227,6 +227,36 @@ def test_parity_4x1920x1080_ring_full_size():
     st.close()
 
 
+def test_deferred_flow_pixels_match_oracle():
+    """Residual displacements of up to 12 px per camera: flow pixels leave the
+    staged tile and finish in the tail kernel (16 lanes per pixel, the sums
+    handed down the row lanes); the flows of every pair and direction bit for
+    bit against the oracle, for the staged kernel + tail and for the generic
+    kernel, which finishes every pixel itself."""
+    sc = small_scene(n_cams=3, W=320, H=160, overlap=0.3, ring=True, seed_config=95, resid=12.0)
+    orc = O.Oracle(sc.rig())
+    frames = sc.frames(0)
+    want = orc.stitch(frames)
+    for variant in (4, 0):
+        st = V.Stitcher(sc.rig(), debug_taps=1)
+        for lvl in range(st.info.lk_levels):
+            st.set_flow_variant(lvl, variant)
+        pano = st.stitch(dev(frames)).cpu().numpy()
+        deferred = [int(st.tap("deferred", 0, lvl)[0]) for lvl in range(st.info.lk_levels)]
+        say(f"[12 px residuals, flow variant {variant}] pixels finished by the tail kernel per level: {deferred}, "
+            f"panorama max diff {lsb(pano, want)} LSB")
+        if variant == 4:
+            assert deferred[0] > 0
+        else:
+            assert sum(deferred) == 0
+        for p in range(orc.n_pairs):
+            for d in (0, 1):
+                np.testing.assert_array_equal(st.tap("flow", p, d), orc.tap("flow", p, d),
+                                              err_msg=f"variant {variant} pair {p} dir {d}")
+        assert lsb(pano, want) <= 1
+        st.close()
+
+
 @pytest.mark.parametrize("rows", [8, 16])
 def test_fused_pyramid_tile_heights(rows):
     """levels 0-2 in one pass at either level-2 tile height: every pyramid
