@@ -124,6 +124,16 @@ void free_ctx(vs_ctx* c)
     delete c;
 }
 
+// Default 9x9 flow-kernel variant of a level, from its count of 64 x 16 tiles
+// (4 px per thread): the most pixels per thread that still gives >= 512
+// blocks, two per compute unit, else 1 px per thread
+int default_lk_P(int n16)
+{
+    for (int P = 4; P > 1; P /= 2)
+        if (n16 * (4 / P) >= 512) return P;
+    return 1;
+}
+
 // Choose the flow-kernel variant of one level (0: generic 16x16 kernel;
 // 1, 2, 4: 9x9-window kernel with that many pixels per thread) and rebuild
 // that level's tile table; the caller re-uploads the plan.
@@ -341,14 +351,14 @@ vs_status vs_create(const vs_rig* rig, const vs_params* prm, vs_ctx** out)
             h.pyr_tx[l][f] = (w + PYR_TX - 1) / PYR_TX;
             h.pyr_off[l][f + 1] = h.pyr_off[l][f] + h.pyr_tx[l][f] * ((hh + PYR_TY - 1) / PYR_TY);
         }
-        // flow kernel: the 9x9-window kernel with 4 px per thread where that still
-        // gives >= 1024 blocks, else 1 px per thread; other radii use the generic kernel
+        // flow kernel: the 9x9-window kernel (pixels per thread from the level's
+        // tile count); other radii use the generic kernel
         int n16 = 0;
         for (int f = 0; f < 2 * h.n_pairs; ++f) {
             const int p = f >> 1;
             n16 += ((h.lw[p][l] + LKW_TX - 1) / LKW_TX) * ((h.lh[p][l] + 15) / 16);
         }
-        set_lk_tiles(h, l, P.lk_radius == LK_R_MAX ? (n16 >= 1024 ? 4 : 1) : 0);
+        set_lk_tiles(h, l, P.lk_radius == LK_R_MAX ? default_lk_P(n16) : 0);
     }
     // ---- workspace arena ----
     size_t off = 0;
@@ -936,7 +946,7 @@ vs_status vs_batch_create(vs_ctx* const ctxs[], int n, vs_batch** out)
                     n16 += ((h.lw[p][l] + LKW_TX - 1) / LKW_TX) * ((h.lh[p][l] + 15) / 16);
                 }
             }
-            variant = n16 >= 1024 ? 4 : 1;
+            variant = default_lk_P(n16);
         }
         vs_status st = set_variant_all(b, l, variant);
         if (st != VS_OK) {
@@ -1129,7 +1139,7 @@ vs_status vs_flow_create(int w, int h, const vs_params* prm, vs_flow** out)
             d.pyr_off[l][fl + 1] = d.pyr_off[l][fl] + d.pyr_tx[l][fl] * ((d.lh[0][l] + PYR_TY - 1) / PYR_TY);
         }
         const int n16 = 2 * ((d.lw[0][l] + LKW_TX - 1) / LKW_TX) * ((d.lh[0][l] + 15) / 16);
-        set_lk_tiles(d, l, P.lk_radius == LK_R_MAX ? (n16 >= 1024 ? 4 : 1) : 0);
+        set_lk_tiles(d, l, P.lk_radius == LK_R_MAX ? default_lk_P(n16) : 0);
     }
     size_t off = 0, o_pyr[2][MAXL], o_flow[2][MAXL], o_need[MAXL], o_queue[MAXL];
     for (int l = 0; l < d.levels; ++l) {
