@@ -170,7 +170,6 @@ __global__ __launch_bounds__(256) void k_lk(const Batch B, int l)
 // kernel's per-pixel routine, same arithmetic) instead of queueing them: the
 // launches of contexts whose pairs may keep the surrogate's flows, where the
 // deferred pixels are few and a tail launch per level would cost more.
-template <int ROWS_UNROLL>
 __device__ __forceinline__ void lk_tail_pixel(const DevPlan* __restrict__ Pl, int l, int f, int x, int y, int it0,
                                               float ux, float uy);
 
@@ -355,7 +354,7 @@ __device__ __forceinline__ void lk_w9_body(const DevPlan* __restrict__ Pl, const
         if (act[q]) Pl->flow[p][dir][l][(size_t)(yb + q) * w + x] = make_float2(ux[q], uy[q]);
     if (INBLOCK) {
         for (int q = 0; q < P; ++q)
-            if (dit[q] >= 0) lk_tail_pixel<1>(Pl, l, f, x, yb + q, dit[q], ux[q], uy[q]);
+            if (dit[q] >= 0) lk_tail_pixel(Pl, l, f, x, yb + q, dit[q], ux[q], uy[q]);
     } else {
         // queue the deferred pixels for the tail kernel: one reservation per
         // wavefront, after the steps (a reservation returns only after a round
@@ -401,9 +400,8 @@ __global__ __launch_bounds__(256) void k_lk_w9(const Batch B, int l)
 // memory with clamped indices (gradients 0 outside the level, as in the staged
 // kernel, so the row-major sums are the same).  Each window row issues all of
 // its loads before using them: about one memory round trip per window row.
-// ROWS_UNROLL: window rows unrolled, or 1 where registers are scarce; the
-// arithmetic and its order are the same
-template <int ROWS_UNROLL>
+// The window rows are not unrolled: the staged kernel's registers are
+// scarce.
 __device__ __forceinline__ void lk_tail_pixel(const DevPlan* __restrict__ Pl, int l, int f, int x, int y, int it0,
                                               float ux, float uy)
 {
@@ -421,7 +419,7 @@ __device__ __forceinline__ void lk_tail_pixel(const DevPlan* __restrict__ Pl, in
 #pragma unroll
         for (int c = 0; c < NW; ++c) cin[c] = x - R + c >= 0 && x - R + c < w;
         float g00 = 0.0f, g01 = 0.0f, g11 = 0.0f;
-#pragma unroll ROWS_UNROLL
+#pragma unroll 1
         for (int jr = 0; jr < NW; ++jr) {
             const int yy = y - R + jr;
             const bool rin = yy >= 0 && yy < h;
@@ -460,7 +458,7 @@ __device__ __forceinline__ void lk_tail_pixel(const DevPlan* __restrict__ Pl, in
 #pragma unroll
             for (int k = 0; k < NW + 1; ++k) mx[k] = clampi(x - R + ox + k, 0, w - 1);
             float bu = 0.0f, bv = 0.0f;
-#pragma unroll ROWS_UNROLL
+#pragma unroll 1
             for (int jr = 0; jr < NW; ++jr) {
                 const int yy = y - R + jr;
                 const bool rin = yy >= 0 && yy < h;
