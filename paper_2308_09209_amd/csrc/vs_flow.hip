@@ -182,9 +182,12 @@ __device__ __forceinline__ void lk_w9_body(const DevPlan* __restrict__ Pl, const
     constexpr int TSW = TIW + 2, TSH = TIH + 2;             // template + gradient halo
     constexpr int HM = R + LK_D + 1;                        // moving-image halo
     constexpr int MW = TX + 2 * HM, MH = TY + 2 * HM;
+    // moving-tile row pitch: a multiple of the 32 LDS banks, so lanes whose
+    // displacements put them one row apart read distinct banks
+    constexpr int MWP = (MW + 31) / 32 * 32;
     __shared__ float4 sTI[TIH * TIW];
     __shared__ float sT[TSH * TSW];
-    __shared__ float sM[MH * MW];
+    __shared__ float sM[MH * MWP];
 
     const int f = find_field(Pl->lk_off[l], 2 * Pl->n_pairs, bid);
     const int p = f >> 1, dir = f & 1;
@@ -202,7 +205,7 @@ __device__ __forceinline__ void lk_w9_body(const DevPlan* __restrict__ Pl, const
     }
     for (int i = tid; i < MH * MW; i += 256) {
         const int yy = clampi(y0 - HM + i / MW, 0, h - 1), xx = clampi(x0 - HM + i % MW, 0, w - 1);
-        sM[i] = Mv[(size_t)yy * w + xx];
+        sM[(i / MW) * MWP + i % MW] = Mv[(size_t)yy * w + xx];
     }
     __syncthreads();
     for (int i = tid; i < TIH * TIW; i += 256) {
@@ -303,7 +306,7 @@ __device__ __forceinline__ void lk_w9_body(const DevPlan* __restrict__ Pl, const
                 ox = 0;
                 oy = 0;
             }
-            mb[q] = (wv * P + q - R + HM + oy) * MW + (lane - R + HM + ox);
+            mb[q] = (wv * P + q - R + HM + oy) * MWP + (lane - R + HM + ox);
         }
         float hp[P][NW];
 #pragma unroll 1
@@ -325,7 +328,7 @@ __device__ __forceinline__ void lk_w9_body(const DevPlan* __restrict__ Pl, const
                         v0 = v1;
                     }
                 }
-                const float* m1 = sM + mb[q] + (jr + 1) * MW;
+                const float* m1 = sM + mb[q] + (jr + 1) * MWP;
                 float v0 = m1[0];
 #pragma unroll
                 for (int c = 0; c < NW; ++c) {
