@@ -61,6 +61,11 @@ class PlanInfo(C.Structure):
                 ("n_covered", C.c_longlong)]
 
 
+class View(C.Structure):
+    _fields_ = [("frame", C.c_void_p), ("pitch", C.c_int), ("W", C.c_int), ("H", C.c_int),
+                ("hinv", C.c_void_p), ("M", C.c_void_p), ("X", C.c_float)]
+
+
 _lib = None
 
 
@@ -95,6 +100,10 @@ def lib():
         L.vso_bilinear.argtypes = [C.c_void_p, C.c_int, C.c_int, C.c_int, C.c_int, C.c_float,
                                    C.c_float]
         L.vso_round8.argtypes = [C.c_float]
+        L.vso_luma.argtypes = [C.c_int, C.c_int, C.c_int]
+        L.vso_chain_colour.argtypes = [C.c_void_p, C.c_int, C.c_void_p]
+        L.vso_fuse_pixel.argtypes = [C.POINTER(View), C.POINTER(View), C.c_float, C.c_void_p, C.c_void_p,
+                                     C.c_void_p]
         vp, i = C.c_void_p, C.c_int
         L.vso_conv3x3.argtypes = [vp, i, i, i, i, vp, vp, i, vp]
         L.vso_conv3x3_bwd_data.argtypes = [vp, i, i, i, i, vp, i, vp]
@@ -355,6 +364,40 @@ def hom_valid(h, x, y, W, H):
 def bilinear(F, ch, u, v) -> float:
     F = np.ascontiguousarray(F, np.uint8)
     return lib().vso_bilinear(_ptr(F), F.shape[1] * 3, F.shape[1], F.shape[0], ch, u, v)
+
+
+def luma(r, g, b) -> int:
+    return int(lib().vso_luma(int(r), int(g), int(b)))
+
+
+def chain_colour(Mpair) -> np.ndarray:
+    """Eq. (4) chained to camera 0: Mpair [n_cams - 1][3][3] -> Mk [n_cams][3][3] (FP64)."""
+    Mp = np.ascontiguousarray(Mpair, dtype=np.float64).reshape(-1, 9)
+    n = Mp.shape[0] + 1
+    out = np.zeros((n, 9), np.float64)
+    lib().vso_chain_colour(_ptr(Mp), n, _ptr(out))
+    return out.reshape(n, 3, 3)
+
+
+def fuse_pixel(frame_j, hinv_j, M_j, X_j, frame_i, hinv_i, M_i, X_i, y, f_ij, f_ji) -> np.ndarray:
+    """Eqs. (16)-(18) at one canvas pixel covered by cameras j (left) and i (right)."""
+    keep = []
+
+    def view(F, h, M, X):
+        F = np.ascontiguousarray(F, dtype=np.uint8)
+        h = np.ascontiguousarray(h, dtype=np.float32).ravel()
+        M = np.ascontiguousarray(M, dtype=np.float32).ravel()
+        keep.extend([F, h, M])
+        return View(F.ctypes.data, F.shape[1] * 3, F.shape[1], F.shape[0], h.ctypes.data, M.ctypes.data,
+                    float(X))
+
+    vj = view(frame_j, hinv_j, M_j, X_j)
+    vi = view(frame_i, hinv_i, M_i, X_i)
+    fij = np.asarray(f_ij, np.float32)
+    fji = np.asarray(f_ji, np.float32)
+    out = np.zeros(3, np.uint8)
+    lib().vso_fuse_pixel(C.byref(vj), C.byref(vi), float(y), _ptr(fij), _ptr(fji), _ptr(out))
+    return out
 
 
 def round8(r) -> int:

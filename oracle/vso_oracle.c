@@ -551,6 +551,19 @@ static void step_moments(vso_ctx* c)
     }
 }
 
+/* Eq. (4) across a chain of cameras: pair k - 1 joins cameras (k - 1, k) and
+ * its matrix takes camera k's colours (row vectors) to camera k - 1's, so
+ * camera k reaches camera 0 through M_k = M_(k-1,k) M_(k-1), M_0 = I (FP64). */
+void vso_chain_colour(const double* Mpair, int n_cams, double* Mk)
+{
+    double acc[9] = {1, 0, 0, 0, 1, 0, 0, 0, 1};
+    memcpy(Mk, acc, sizeof acc);
+    for (int k = 1; k < n_cams; ++k) {
+        mat3_mul(Mpair + (size_t)(k - 1) * 9, acc, acc);
+        memcpy(Mk + (size_t)k * 9, acc, sizeof acc);
+    }
+}
+
 /* Eqs. (2)-(3) (3D-M): the stacked rows of frames T, T-1, T-2 enter the
  * normal equations as summed moments (frames before 0 do not exist), then
  * eq. (4)'s matrix per pair; cameras are chained to camera 0 as
@@ -586,12 +599,10 @@ static void step_solve(vso_ctx* c)
         }
         memcpy(c->Mpair[p], M, sizeof M);
     }
-    double Mk[9] = {1, 0, 0, 0, 1, 0, 0, 0, 1};
-    for (int i = 0; i < 9; ++i) c->Mk[0][i] = (float)Mk[i];
-    for (int k = 1; k < P->n_cams; ++k) {
-        mat3_mul(c->Mpair[k - 1], Mk, Mk);
-        for (int i = 0; i < 9; ++i) c->Mk[k][i] = (float)Mk[i];
-    }
+    double Mk[VSO_MAX_CAMS][9];
+    vso_chain_colour(&c->Mpair[0][0], P->n_cams, &Mk[0][0]);
+    for (int k = 0; k < P->n_cams; ++k)
+        for (int i = 0; i < 9; ++i) c->Mk[k][i] = (float)Mk[k][i];
 }
 
 /* ------------------------------------------------------------------------ */
@@ -807,6 +818,10 @@ void vso_lk_level_f64(const double* T, const double* Mv, int w, int h,
     }
 }
 
+/* Integer luma of an RGB byte triple with the BT.601 weights 0.299, 0.587,
+ * 0.114 in 8-bit fixed point (77, 150, 29 over 256), rounded half up. */
+int vso_luma(int r, int g, int b) { return (77 * r + 150 * g + 29 * b + 128) >> 8; }
+
 /* Flow input: the colour-corrected strips (every strip pixel), reduced to
  * integer luma Y = (77 R + 150 G + 29 B + 128) >> 8, then the pyramid. */
 static void step_pyramids(vso_ctx* c)
@@ -824,7 +839,7 @@ static void step_pyramids(vso_ctx* c)
                 int cc[3];
                 for (int ch = 0; ch < 3; ++ch) px[ch] = (float)c->strip[p][s][(size_t)q * 3 + ch];
                 for (int ch = 0; ch < 3; ++ch) cc[ch] = vso_round8(color_apply(px, M, ch));
-                Y[q] = (float)((77 * cc[0] + 150 * cc[1] + 29 * cc[2] + 128) >> 8);
+                Y[q] = (float)vso_luma(cc[0], cc[1], cc[2]);
             }
             for (int l = 1; l < c->prm.lk_levels; ++l)
                 vso_pyr_down(c->pyr[p][s][l - 1], c->pw[p][l - 1], c->ph[p][l - 1], c->pyr[p][s][l]);
@@ -999,8 +1014,9 @@ static void net_forward(const net_view* v, const float* Yt, const float* Ym, int
     for (int l = 0; l < v->nl; ++l) {
         int ci = v->ci[l], co = v->co[l];
         for (size_t i = 0; i < (size_t)co * 9 * ci; ++i) wt[i] = bf16_bits_to_double(v->w[l][i]);
-        /* the exact sums of products (each product of two BF16 values is exact
-         * in FP64), plus the bias */
+        /* the sums of products accumulated in FP64 (each product of two BF16
+         * values is exact in FP64; the running sum is rounded to FP64), plus
+         * the bias */
         double bias[256];
         for (int o = 0; o < co; ++o) bias[o] = (double)v->b[l][o];
         vso_conv3x3(x, 1, h, w, ci, wt, bias, co, y);
@@ -1141,22 +1157,72 @@ static int surrogate_pair(vso_ctx* c, int p)
 /* Eqs. (15)-(18): local warp and weighted fusion                            */
 /* ------------------------------------------------------------------------ */
 
-static void sample_color(const vso_ctx* c, const uint8_t* const F[], const int pitch[], int k,
-                         float X, float Y, float t[3])
+static void sample_view(const vso_view* v, float X, float Y, float t[3])
 {
-    float u, v;
-    vso_hom_valid(c->plan.hinv[k], X, Y, c->rig.cam_w[k], c->rig.cam_h[k], &u, &v);
+    float u, w;
+    vso_hom_valid(v->hinv, X, Y, v->W, v->H, &u, &w);
     float s[3];
-    for (int ch = 0; ch < 3; ++ch) s[ch] = vso_bilinear(F[k], pitch[k], c->rig.cam_w[k], c->rig.cam_h[k], ch, u, v);
-    for (int ch = 0; ch < 3; ++ch) t[ch] = color_apply(s, c->Mk[k], ch);
+    for (int ch = 0; ch < 3; ++ch) s[ch] = vso_bilinear(v->frame, v->pitch, v->W, v->H, ch, u, w);
+    for (int ch = 0; ch < 3; ++ch) t[ch] = color_apply(s, v->M, ch);
+}
+
+/* One canvas pixel covered by one camera: its colour-corrected resample. */
+static void single_pixel(const vso_view* v, float y, uint8_t out[3])
+{
+    float t[3];
+    sample_view(v, v->X, y, t);
+    for (int ch = 0; ch < 3; ++ch) out[ch] = (uint8_t)vso_round8(t[ch]);
+}
+
+/* One canvas pixel covered by two cameras, j (left) and i (right):
+ *  eq. (16): the weights come from the pixel's distance to each camera's own
+ *    vertical border, measured in that camera's unwarped coordinates,
+ *    d_k = max(0, min(u_k, W_k - 1 - u_k)); theta_i = d_i / (d_i + d_j)
+ *    (1/2 when both are 0) and theta_j = 1 - theta_i, so camera i's weight
+ *    rises from 0 at its own border;
+ *  eq. (17): the local warp meets in the middle -- camera i is sampled at
+ *    x + theta_j flow_ij(x), camera j at x + theta_i flow_ji(x);
+ *  eq. (18): out = round8(theta_i (t_i - t_j) + t_j), t the colour-corrected
+ *    samples of the two camera frames at those points. */
+void vso_fuse_pixel(const vso_view* vj, const vso_view* vi, float y, const float f_ij[2], const float f_ji[2],
+                    uint8_t out[3])
+{
+    float uj, vjv, ui, viv;
+    vso_hom_valid(vj->hinv, vj->X, y, vj->W, vj->H, &uj, &vjv);
+    vso_hom_valid(vi->hinv, vi->X, y, vi->W, vi->H, &ui, &viv);
+    float dj = fminf(uj, (float)(vj->W - 1) - uj);
+    float di = fminf(ui, (float)(vi->W - 1) - ui);
+    if (dj < 0.0f) dj = 0.0f;
+    if (di < 0.0f) di = 0.0f;
+    float sum = di + dj;
+    float th_i = sum > 0.0f ? di / sum : 0.5f;
+    float th_j = 1.0f - th_i;
+    float Xi = fmaf(th_j, f_ij[0], vi->X);
+    float Yi = fmaf(th_j, f_ij[1], y);
+    float Xj = fmaf(th_i, f_ji[0], vj->X);
+    float Yj = fmaf(th_i, f_ji[1], y);
+    float ti[3], tj[3];
+    sample_view(vi, Xi, Yi, ti);
+    sample_view(vj, Xj, Yj, tj);
+    for (int ch = 0; ch < 3; ++ch) out[ch] = (uint8_t)vso_round8(fmaf(th_i, ti[ch] - tj[ch], tj[ch]));
+}
+
+static void make_view(const vso_ctx* c, const uint8_t* const F[], const int pitch[], const hit* h, int x,
+                      vso_view* v)
+{
+    const int k = h->cam;
+    v->frame = F[k];
+    v->pitch = pitch[k];
+    v->W = c->rig.cam_w[k];
+    v->H = c->rig.cam_h[k];
+    v->hinv = c->plan.hinv[k];
+    v->M = c->Mk[k];
+    v->X = (float)(x + h->m * c->plan.ring_period);
 }
 
 /* Per canvas pixel: uncovered -> 0; one camera -> its colour-corrected
- * resample; two cameras (j left, i right) -> eq. (16) weights from the
- * distance to each camera's own vertical border (theta_i + theta_j = 1),
- * eq. (17) displacements that meet in the middle (camera i moved by
- * theta_j flow_ij, camera j by theta_i flow_ji), eq. (18) blend
- * out = round8(theta_i (t_i - t_j) + t_j), t = colour-corrected resamples. */
+ * resample; two cameras -> the fusion of eqs. (16)-(18) with the pair's
+ * flows at the pixel. */
 static void step_blend(vso_ctx* c, const uint8_t* const F[], const int pitch[])
 {
     const vso_plan_info* P = &c->plan;
@@ -1170,35 +1236,19 @@ static void step_blend(vso_ctx* c, const uint8_t* const F[], const int pitch[])
             if (n == 0) {
                 o[0] = o[1] = o[2] = 0;
             } else if (n == 1) {
-                float t[3];
-                sample_color(c, F, pitch, h[0].cam, (float)(x + h[0].m * P->ring_period), (float)y, t);
-                for (int ch = 0; ch < 3; ++ch) o[ch] = (uint8_t)vso_round8(t[ch]);
+                vso_view v;
+                make_view(c, F, pitch, &h[0], x, &v);
+                single_pixel(&v, (float)y, o);
             } else {
                 int jidx;
                 int p = pair_for(P, &h[0], &h[1], &jidx);
-                const hit* hj = &h[jidx];
-                const hit* hi = &h[1 - jidx];
-                int j = hj->cam, i = hi->cam;
-                float dj = fminf(hj->u, (float)(c->rig.cam_w[j] - 1) - hj->u);
-                float di = fminf(hi->u, (float)(c->rig.cam_w[i] - 1) - hi->u);
-                if (dj < 0.0f) dj = 0.0f;
-                if (di < 0.0f) di = 0.0f;
-                float sum = di + dj;
-                float th_i = sum > 0.0f ? di / sum : 0.5f;
-                float th_j = 1.0f - th_i;
-                int X = x + hj->m * P->ring_period;
+                vso_view vj, vi;
+                make_view(c, F, pitch, &h[jidx], x, &vj);
+                make_view(c, F, pitch, &h[1 - jidx], x, &vi);
+                int X = x + h[jidx].m * P->ring_period;
                 int lx = X - P->strip_x0[p], ly = y - P->strip_y0[p];
                 size_t q = ((size_t)ly * P->strip_w[p] + lx) * 2;
-                float fij_x = c->flow[p][0][q], fij_y = c->flow[p][0][q + 1];
-                float fji_x = c->flow[p][1][q], fji_y = c->flow[p][1][q + 1];
-                float Xi = fmaf(th_j, fij_x, (float)(x + hi->m * P->ring_period));
-                float Yi = fmaf(th_j, fij_y, (float)y);
-                float Xj = fmaf(th_i, fji_x, (float)(x + hj->m * P->ring_period));
-                float Yj = fmaf(th_i, fji_y, (float)y);
-                float ti[3], tj[3];
-                sample_color(c, F, pitch, i, Xi, Yi, ti);
-                sample_color(c, F, pitch, j, Xj, Yj, tj);
-                for (int ch = 0; ch < 3; ++ch) o[ch] = (uint8_t)vso_round8(fmaf(th_i, ti[ch] - tj[ch], tj[ch]));
+                vso_fuse_pixel(&vj, &vi, (float)y, c->flow[p][0] + q, c->flow[p][1] + q, o);
             }
         }
     }

@@ -126,6 +126,23 @@ void vso_lk_level_f64(const double* T, const double* Mv, int w, int h,
 int vso_hom_valid(const float h[9], float x, float y, int W, int H, float* u, float* v);
 float vso_bilinear(const uint8_t* F, int pitch, int W, int H, int ch, float u, float v);
 int vso_round8(float r);
+/* integer luma of the flow input: (77 R + 150 G + 29 B + 128) >> 8 */
+int vso_luma(int r, int g, int b);
+/* eq. (4) chained to camera 0: Mpair [n_cams - 1][9] (pair k - 1 = cameras
+ * k - 1, k), Mk [n_cams][9], FP64 */
+void vso_chain_colour(const double* Mpair, int n_cams, double* Mk);
+/* One camera's view of a canvas pixel for the fusion of eqs. (16)-(18). */
+typedef struct {
+    const uint8_t* frame; /* HWC RGB uint8 */
+    int pitch, W, H;      /* row pitch in bytes, image size */
+    const float* hinv;    /* canvas -> camera homography, FP32 */
+    const float* M;       /* the camera's colour matrix (row vectors), FP32 */
+    float X;              /* the pixel's canvas x in this camera's period */
+} vso_view;
+/* eqs. (16)-(18) at one canvas pixel (row y) covered by cameras j (left) and
+ * i (right), with the pair's flows f_ij, f_ji at the pixel */
+void vso_fuse_pixel(const vso_view* vj, const vso_view* vi, float y, const float f_ij[2], const float f_ji[2],
+                    uint8_t out[3]);
 
 /* learned surrogate: FP64 3x3 convolution references (NHWC, weights
  * [cout][tap][cin], zero padding) */
