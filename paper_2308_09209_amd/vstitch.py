@@ -281,11 +281,12 @@ class Stitcher:
                     or not f.is_contiguous()):
                 raise ValueError(f"frame {k}: need a contiguous cuda uint8 tensor of shape "
                                  f"{self.cam_shape[k] + (3,)}")
+        dev = frames[0].device
+        if any(f.device != dev for f in frames):
+            raise ValueError("frames: all on one device")
         if pano is None:
-            pano = self.new_pano(frames[0].device)
-        H, W = self.canvas
-        if pano.dtype != torch.uint8 or tuple(pano.shape) != (H, W, 3) or not pano.is_contiguous():
-            raise ValueError("pano: contiguous uint8 (canvas_h, canvas_w, 3)")
+            pano = self.new_pano(dev)
+        _check_pano(pano, self.canvas, dev)
         ptrs = (C.c_void_p * self.n_cams)(*[f.data_ptr() for f in frames])
         out = ColorState() if want_state else None
         info = FrameInfo() if want_info else None
@@ -425,9 +426,9 @@ class Batch:
                 if (f.dtype != torch.uint8 or not f.is_cuda or not f.is_contiguous()
                         or tuple(f.shape) != st.cam_shape[k] + (3,)):
                     raise ValueError("frames: contiguous cuda uint8 (H, W, 3)")
-            H, W = st.canvas
-            if pano.dtype != torch.uint8 or tuple(pano.shape) != (H, W, 3) or not pano.is_contiguous():
-                raise ValueError("pano: contiguous uint8 (canvas_h, canvas_w, 3)")
+            if any(f.device != fr[0].device for f in fr):
+                raise ValueError("frames: all on one device")
+            _check_pano(pano, st.canvas, fr[0].device)
             rows.append((C.c_void_p * st.n_cams)(*[f.data_ptr() for f in fr]))
         self._keep = rows
         fr_arr = (C.c_void_p * n)(*[C.cast(r, C.c_void_p).value for r in rows])
@@ -451,6 +452,18 @@ class Batch:
             raise VSError(st, lib().vs_batch_last_error(self.h).decode())
         L = self.stitchers[0].info.lk_levels
         return choice[:L].tolist(), ms[:L]
+
+
+def _check_pano(pano, canvas, device):
+    """The panorama is written by the kernels: a contiguous uint8 device tensor
+    of the canvas shape on the frames' device (a host tensor's address would
+    reach the kernels' stores)."""
+    H, W = canvas
+    if (not isinstance(pano, torch.Tensor) or pano.dtype != torch.uint8 or tuple(pano.shape) != (H, W, 3)
+            or not pano.is_contiguous()):
+        raise ValueError("pano: contiguous uint8 (canvas_h, canvas_w, 3)")
+    if not pano.is_cuda or pano.device != device:
+        raise ValueError(f"pano: must be a device tensor on {device} (the frames' device), got {pano.device}")
 
 
 def _p(t):

@@ -99,3 +99,46 @@ def test_invalid_rigs_rejected_before_any_device_work():
         V.Stitcher(rig, lk_radius=9)
     with pytest.raises(V.VSError):
         V.Stitcher(rig, lambda_pct=60)
+
+
+class _FakeDeviceFrame:
+    """Duck-typed stand-in for a device frame tensor (no GPU on the host)."""
+
+    def __init__(self, shape):
+        import torch
+        self.dtype = torch.uint8
+        self.is_cuda = True
+        self.shape = shape
+        self.device = torch.device("cuda", 0)
+
+    def is_contiguous(self):
+        return True
+
+    def data_ptr(self):
+        raise AssertionError("no pointer may be taken before the checks pass")
+
+
+def test_host_tensor_panorama_is_rejected_before_any_library_call(monkeypatch):
+    import torch
+
+    st = object.__new__(V.Stitcher)
+    st.n_cams = 2
+    st.cam_shape = [(8, 16), (8, 16)]
+    st.info = V.PlanInfo()
+    st.info.canvas_h, st.info.canvas_w = 8, 24
+
+    def no_lib():
+        raise AssertionError("library called")
+
+    monkeypatch.setattr(V, "lib", no_lib)
+    frames = [_FakeDeviceFrame((8, 16, 3)) for _ in range(2)]
+    with pytest.raises(ValueError, match="device tensor"):
+        st.stitch(frames, pano=torch.zeros((8, 24, 3), dtype=torch.uint8))
+    with pytest.raises(ValueError, match="device tensor"):
+        V._check_pano(torch.zeros((8, 24, 3), dtype=torch.uint8), (8, 24), torch.device("cuda", 0))
+    with pytest.raises(ValueError, match="canvas"):
+        V._check_pano(torch.zeros((8, 23, 3), dtype=torch.uint8), (8, 24), torch.device("cuda", 0))
+    b = object.__new__(V.Batch)
+    b.stitchers = [st]
+    with pytest.raises(ValueError, match="device tensor"):
+        b._ptrs([frames], [torch.zeros((8, 24, 3), dtype=torch.uint8)])
