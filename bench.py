@@ -33,23 +33,34 @@ DEFAULT_WEIGHTS = os.path.join(ROOT, "paper_2308_09209_amd", "weights", "flow_su
 FLOW_MODES = {"plain": 0, "surrogate": 1, "fallback": 2}
 
 
+FLOPS_PER_TAP_STEP = 12   # algorithmic unit: per window tap and Gauss-Newton step, 4 bilinear MACs,
+                          # the residual and 2 right-hand-side MACs (FMA = 2 flops)
+
+
 def window_sum(n, r):
     """sum over positions of the clipped window length along one axis"""
     return sum(min(x + r, n - 1) - max(x - r, 0) + 1 for x in range(n))
 
 
-def lk_flops_per_frame(info, r, iters):
-    """Algorithmic FP32 flops of the flow kernel per frame (FMA = 2 flops):
-    per window tap 3 FMAs for the normal matrix, then per Gauss-Newton step
-    2 subtractions + 3 FMAs (bilinear), 1 subtraction (residual) and 2 FMAs
-    (right-hand side) = 14 flops; both directions of every pair, every level."""
+def domain_taps(need, r):
+    """Window taps of the flow estimate over a flow domain (uint8 map, 1 where
+    the flow is estimated): the sum over the marked pixels of the (2r+1)^2
+    window clipped to the level."""
+    h, w = need.shape
+    wx = np.array([min(x + r, w - 1) - max(x - r, 0) + 1 for x in range(w)], np.int64)
+    wy = np.array([min(y + r, h - 1) - max(y - r, 0) + 1 for y in range(h)], np.int64)
+    return int((need.astype(bool) * wy[:, None] * wx[None, :]).sum())
+
+
+def lk_flops_per_frame(info, iters, per_tap_step=FLOPS_PER_TAP_STEP, per_tap=0):
+    """Algorithmic FP32 flops of the plain flow per frame: both directions of
+    every pair, every level, over the planned flow domain (info.flow_taps =
+    the clipped window taps of its pixels), per_tap_step flops per tap and
+    Gauss-Newton step (+ per_tap once per tap for the normal matrix)."""
     total = 0
     for p in range(info.n_pairs):
-        w, h = info.strip_w[p], info.strip_h[p]
-        for _ in range(info.lk_levels):
-            taps = window_sum(w, r) * window_sum(h, r)
-            total += 2 * taps * (6 + 14 * iters)
-            w, h = (w + 1) // 2, (h + 1) // 2
+        for l in range(info.lk_levels):
+            total += 2 * int(info.flow_taps[p][l]) * (per_tap + per_tap_step * iters)
     return total
 
 
@@ -152,7 +163,8 @@ def cpu_baseline(scene, frames_list, n_frames):
     out = dict(value=round(n_frames * H * W / dt / 1e6, 4), unit="Mpix/s", cores=threads,
                kind="oracle", sample=f"{n_frames} consecutive frames of the same workload, every step "
                                      f"({dt:.1f} s on {threads} OpenMP threads)",
-               cpu_model=cpu_model(), nproc=os.cpu_count())
+               cpu_model=cpu_model(), nproc=os.cpu_count(),
+               **table4_columns(orc.step_times(), n_frames))
     # the next frame on one thread (the oracle's OpenMP regions follow this thread's setting)
     try:
         gomp = ctypes.CDLL("libgomp.so.1")
@@ -160,13 +172,29 @@ def cpu_baseline(scene, frames_list, n_frames):
         gomp = None
     if gomp is not None and len(frames_list) > n_frames and H * W <= 8_000_000:   # ~10-20 s of one core
         gomp.omp_set_num_threads(1)
+        before = orc.step_times()
         t0 = time.perf_counter()
         orc.stitch(frames_list[n_frames])
         dt1 = time.perf_counter() - t0
+        after = orc.step_times()
         gomp.omp_set_num_threads(threads)
         out["single_thread"] = dict(value=round(H * W / dt1 / 1e6, 4), unit="Mpix/s",
-                                    sample=f"1 frame ({dt1:.1f} s)")
+                                    sample=f"1 frame ({dt1:.1f} s)",
+                                    **table4_columns({k: after[k] - before[k] for k in after}, 1))
     return out
+
+
+def table4_columns(step_s, n_frames):
+    """Per-frame oracle step times (ms), each step and grouped as the paper's
+    per-step timing table: geometric warping (strip pre-warp), colour
+    correction (histogram specification, moments, solve, balancing), local
+    warping (flow input pyramids and flow), image blending."""
+    ms = {k: round(v / n_frames * 1e3, 2) for k, v in step_s.items()}
+    return dict(step_ms=ms, table4_ms=dict(
+        geometric_warping=ms["strips"],
+        color_correction=round(ms["moments"] + ms["solve"] + ms["balance"], 2),
+        local_warping=round(ms["pyramids"] + ms["flow"], 2),
+        image_blending=ms["blend"]))
 
 
 def cpu_model():
@@ -268,7 +296,9 @@ def main():
     mpix = K * H * W / wall / 1e6
     levels = info.lk_levels
     p = st.params
-    flops = lk_flops_per_frame(info, p.lk_radius, p.lk_iters)
+    flops = lk_flops_per_frame(info, p.lk_iters)
+    flops_impl = lk_flops_per_frame(info, p.lk_iters, per_tap_step=14, per_tap=6)
+    taps = sum(int(info.flow_taps[q][l]) for q in range(info.n_pairs) for l in range(levels))
     lk_launch_ms = step_ms[2] / nfr / levels
     achieved = flops / levels / (lk_launch_ms * 1e-3) / 1e12
     traffic = load_pmc("k_lk", args.workload)
@@ -277,7 +307,13 @@ def main():
                     achieved=round(achieved, 3), peak=FP32_VECTOR_PEAK_TFLOPS, unit="TFLOP/s",
                     frac=round(achieved / FP32_VECTOR_PEAK_TFLOPS, 4),
                     traffic=traffic, avg_launch_ms=round(lk_launch_ms, 5),
-                    flops_per_launch=int(flops / levels))
+                    flops_per_launch=int(flops / levels),
+                    unit_flops=f"{FLOPS_PER_TAP_STEP} flop per window tap and Gauss-Newton step over the "
+                               f"flow domain ({taps} taps per direction per frame, {p.lk_iters} steps, "
+                               "2 directions)",
+                    achieved_impl_count=round(flops_impl / levels / (lk_launch_ms * 1e-3) / 1e12, 3),
+                    impl_count="6 flop per tap (normal matrix) + 14 per tap and step, as the kernel "
+                               "issues them")
     names = V.Stitcher.TIMING_STEPS
     metric = ("panorama Mpix/s + p99 frame ms, 4x1080p; surrogate vs plain flow @EPE<=0.5px"
               if args.workload == "4x1920x1080_ring" else

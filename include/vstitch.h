@@ -125,6 +125,13 @@ typedef struct {
     int64_t n_covered;                  /* canvas pixels seen by at least one camera */
     uint64_t workspace_bytes;           /* device bytes owned by the context */
     uint32_t state_bytes;               /* sizeof(vs_color_state) */
+    uint32_t pad0;
+    /* The flow domain of section 3.2 as planned (VS_TAP_NEED): per pair and
+     * level the pixels whose flow is estimated, and the sum over them of their
+     * window clipped to the level ((2r+1)^2 inside).  The plain flow does
+     * lk_iters Gauss-Newton steps over flow_taps per direction. */
+    uint64_t flow_px[VS_MAX_PAIRS][VS_MAX_LEVELS];
+    uint64_t flow_taps[VS_MAX_PAIRS][VS_MAX_LEVELS];
 } vs_plan_info;
 
 /* Per-frame diagnostics (valid after the call returns when requested). */

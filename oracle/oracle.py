@@ -82,6 +82,7 @@ def lib():
         L.vso_stitch.argtypes = [C.c_void_p, C.POINTER(C.c_void_p), C.POINTER(C.c_int), C.c_void_p]
         L.vso_reset.argtypes = [C.c_void_p]
         L.vso_frames_seen.argtypes = [C.c_void_p]
+        L.vso_step_times.argtypes = [C.c_void_p, C.c_void_p]
         L.vso_get.argtypes = [C.c_void_p, C.c_int, C.c_int, C.c_int, C.c_void_p, C.c_size_t]
         L.vso_default_params.argtypes = [C.POINTER(Params)]
         L.vso_histspec_lut.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p]
@@ -218,6 +219,14 @@ class Oracle:
 
     def frames_seen(self) -> int:
         return lib().vso_frames_seen(self.h)
+
+    STEPS = ("strips", "moments", "solve", "pyramids", "flow", "blend", "balance")
+
+    def step_times(self) -> dict:
+        """wall seconds per step, summed over the frames stitched so far"""
+        out = np.zeros(7, np.float64)
+        lib().vso_step_times(self.h, _ptr(out))
+        return dict(zip(self.STEPS, out.tolist()))
 
     def tap(self, name: str, pair: int = 0, sub: int = 0) -> np.ndarray:
         P = self.plan

@@ -15,6 +15,7 @@
 #include <math.h>
 #include <stdlib.h>
 #include <string.h>
+#include <time.h>
 
 #define NCH 3
 
@@ -124,6 +125,7 @@ struct vso_ctx {
     float* surr_pred[VSO_MAX_PAIRS][2];       /* level-2 prediction, 2 channels */
     unsigned long long fb[VSO_MAX_PAIRS][2];  /* fixed-point error sum, pixel count */
     int surr_ok[VSO_MAX_PAIRS];
+    double step_s[7];                        /* wall seconds per step, summed over frames */
     uint8_t* pano_pre;
     uint32_t pano_hist[3][256];
     uint8_t bal_lut[3][256];
@@ -402,6 +404,13 @@ void vso_reset(vso_ctx* c)
 }
 
 int vso_frames_seen(const vso_ctx* c) { return c->T; }
+
+int vso_step_times(const vso_ctx* c, double out[7])
+{
+    if (!c || !out) return VSO_E_INVAL;
+    memcpy(out, c->step_s, sizeof c->step_s);
+    return VSO_OK;
+}
 
 /* ------------------------------------------------------------------------ */
 /* Section 2.1: 3D-M colour transfer                                         */
@@ -1345,18 +1354,35 @@ static void step_balance(vso_ctx* c, uint8_t* pano)
 /* One frame                                                                 */
 /* ------------------------------------------------------------------------ */
 
+static double wall_seconds(void)
+{
+    struct timespec ts;
+    clock_gettime(CLOCK_MONOTONIC, &ts);
+    return (double)ts.tv_sec + 1e-9 * (double)ts.tv_nsec;
+}
+
 int vso_stitch(vso_ctx* c, const uint8_t* const frames[], const int pitch[], uint8_t* pano)
 {
     if (!c || !frames || !pitch || !pano) return VSO_E_INVAL;
     for (int k = 0; k < c->plan.n_cams; ++k)
         if (!frames[k] || pitch[k] < 3 * c->rig.cam_w[k]) return VSO_E_INVAL;
+    double t[8];
+    t[0] = wall_seconds();
     step_strips(c, frames, pitch);
+    t[1] = wall_seconds();
     step_moments(c);
+    t[2] = wall_seconds();
     step_solve(c);
+    t[3] = wall_seconds();
     step_pyramids(c);
+    t[4] = wall_seconds();
     step_flow(c);
+    t[5] = wall_seconds();
     step_blend(c, frames, pitch);
+    t[6] = wall_seconds();
     step_balance(c, pano);
+    t[7] = wall_seconds();
+    for (int i = 0; i < 7; ++i) c->step_s[i] += t[i + 1] - t[i];
     /* state: shift the per-pair moments and the quantiles, T += 1 */
     for (int p = 0; p < c->plan.n_pairs; ++p) {
         c->mom_prev[p][1] = c->mom_prev[p][0];

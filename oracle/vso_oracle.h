@@ -85,6 +85,10 @@ int vso_stitch(vso_ctx* c, const uint8_t* const frames[], const int pitch[], uin
 /* Forget the colour state (next frame is T = 0). */
 void vso_reset(vso_ctx* c);
 int vso_frames_seen(const vso_ctx* c);
+/* Wall seconds spent per step since the context was created, summed over
+ * frames: strips, moments (histogram specification), colour solve,
+ * pyramids, flow, blend, balance.  Timing only; no effect on results. */
+int vso_step_times(const vso_ctx* c, double out[7]);
 
 enum {
     VSO_TAP_STRIP = 1,     /* pair, sub 0=j 1=i : sw*sh*3 u8 */

@@ -453,6 +453,29 @@ vs_status vs_create(const vs_rig* rig, const vs_params* prm, vs_ctx** out)
         I.strip_h[p] = h.sh[p];
     }
     I.n_covered = (int64_t)scan.n_covered;
+    // flow-domain accounting (plan time, from the domain the kernels built)
+    {
+        std::vector<uint8_t> nb;
+        const int r = h.lk_radius;
+        for (int p = 0; p < h.n_pairs; ++p)
+            for (int l = 0; l < h.levels; ++l) {
+                const int w = h.lw[p][l], hh = h.lh[p][l];
+                nb.resize((size_t)w * hh);
+                if ((e = hipMemcpy(nb.data(), h.need[p][l], nb.size(), hipMemcpyDeviceToHost)) != hipSuccess)
+                    return cleanup_dev(e, "flow domain copy");
+                uint64_t px = 0, taps = 0;
+                for (int y = 0; y < hh; ++y) {
+                    const uint64_t wy = (uint64_t)(std::min(y + r, hh - 1) - std::max(y - r, 0) + 1);
+                    for (int x = 0; x < w; ++x) {
+                        if (!nb[(size_t)y * w + x]) continue;
+                        px += 1;
+                        taps += wy * (uint64_t)(std::min(x + r, w - 1) - std::max(x - r, 0) + 1);
+                    }
+                }
+                I.flow_px[p][l] = px;
+                I.flow_taps[p][l] = taps;
+            }
+    }
     I.workspace_bytes = c->arena_bytes + cover_bytes + cand_bytes + code_bytes + scan_bytes + sizeof(DevPlan);
     I.state_bytes = sizeof(vs_color_state);
     *out = c;

@@ -77,7 +77,9 @@ class PlanInfo(C.Structure):
                 ("strip_x0", C.c_int32 * MAX_PAIRS), ("strip_y0", C.c_int32 * MAX_PAIRS),
                 ("strip_w", C.c_int32 * MAX_PAIRS), ("strip_h", C.c_int32 * MAX_PAIRS),
                 ("n_covered", C.c_int64), ("workspace_bytes", C.c_uint64),
-                ("state_bytes", C.c_uint32)]
+                ("state_bytes", C.c_uint32), ("pad0", C.c_uint32),
+                ("flow_px", (C.c_uint64 * MAX_LEVELS) * MAX_PAIRS),
+                ("flow_taps", (C.c_uint64 * MAX_LEVELS) * MAX_PAIRS)]
 
 
 NN_MAX_IMAGES = 64

@@ -1,10 +1,12 @@
 """GPU parity at the benchmark's full sizes, in the launch configurations the
 benchmark times, against the CPU oracle on the same seeded frames: the
-8-camera 3840x2160 ring with moving occluders through vs_stitch, and the six
-uneven streams through one autotuned batch graph.  Bars as in the other parity
+8-camera 3840x2160 ring with moving occluders through vs_stitch (plain, and
+with the trained surrogate in fallback mode), and the six uneven streams
+through one autotuned batch graph for three consecutive steps.  Bars as in the other parity
 tests: 1 LSB max-abs on the panoramas (the kernels follow the oracle's
 operation order, so the test also reports how many pixels are identical),
 exact histograms, LUTs, moments and flags, 1e-3 px mean EPE on the flows."""
+import os
 import sys
 import time
 
@@ -19,6 +21,7 @@ from paper_2308_09209_amd.scenes import batch_scenes, scene_for  # noqa: E402
 from tests.test_gpu_parity import check_steps, lsb  # noqa: E402
 
 pytestmark = pytest.mark.gpu
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 
 def say(*a):
@@ -54,18 +57,20 @@ def test_parity_8x3840x2160_ring_occluders_full_size():
 
 
 def test_six_stream_batch_full_size():
-    """One step of the six uneven streams (720p, 1080p and 1440p chains of 3
-    and 4 cameras) through one graph after the autotuner has chosen the
-    flow-kernel variants: each stream's panorama against its own oracle."""
+    """Three consecutive steps of the six uneven streams (720p, 1080p and 1440p
+    chains of 3 and 4 cameras) through one graph after the autotuner has
+    chosen the flow-kernel variants: each stream's panorama against its own
+    oracle context, so the device-resident colour state of every stream
+    (frames T-1, T-2 of eqs. (2)-(3) and (6)-(7)) passes through the graph."""
     t0 = time.perf_counter()
     scs = batch_scenes()
-    host = [sc.frames(0) for sc in scs]
+    n_steps = 3
+    host = [[sc.frames(t) for sc in scs] for t in range(n_steps)]
     say(f"[6-stream batch] frames generated in {time.perf_counter() - t0:.1f} s")
     sts = [V.Stitcher(sc.rig()) for sc in scs]
     b = V.Batch(sts)
     panos = [st.new_pano() for st in sts]
-    frames = [dev(f) for f in host]
-    choice, _ = b.autotune(frames, panos, reps=1)
+    choice, _ = b.autotune([dev(f) for f in host[0]], panos, reps=1)
     say(f"[6-stream batch] flow variants per level {choice}")
     # the autotuner ran the step several times: start the colour states afresh
     for sc, st in zip(scs, sts):
@@ -73,15 +78,49 @@ def test_six_stream_batch_full_size():
         st.state_set(fresh.state_get())
         fresh.close()
     assert [st.flow_variants() for st in sts] == [list(choice)] * len(sts)
-    b.run(frames, panos)
-    torch.cuda.synchronize()
-    for c, sc in enumerate(scs):
-        want = O.Oracle(sc.rig()).stitch(host[c])
-        got = panos[c].cpu().numpy()
-        d = lsb(got, want)
-        say(f"[6-stream batch] stream {c} ({sc.n_cams} x {sc.W}x{sc.H}): max diff {d} LSB, "
-            f"identical px {np.mean(np.all(got == want, -1)):.6f}")
-        assert d <= 1, c
+    orcs = [O.Oracle(sc.rig()) for sc in scs]
+    for t in range(n_steps):
+        b.run([dev(f) for f in host[t]], panos)
+        torch.cuda.synchronize()
+        for c, sc in enumerate(scs):
+            want = orcs[c].stitch(host[t][c])
+            got = panos[c].cpu().numpy()
+            d = lsb(got, want)
+            say(f"[6-stream batch] step {t} stream {c} ({sc.n_cams} x {sc.W}x{sc.H}): max diff {d} LSB, "
+                f"identical px {np.mean(np.all(got == want, -1)):.6f}")
+            assert d <= 1, (t, c)
+            assert sts[c].state_get().frames_seen == t + 1
     b.close()
     for st in sts:
         st.close()
+
+
+def test_parity_8x3840x2160_surrogate_fallback_full_size():
+    """One frame of the 8 x 4K ring with occluders in the benchmark's surrogate
+    configuration (the trained weights, fallback mode, threshold 0.5 px):
+    the network's predictions, the fallback decisions, the level-0 flows, the
+    pre-balance and the final panorama against the oracle, within the bounds
+    that the FP32 matrix-core sums allow."""
+    from tests.test_gpu_surrogate import check_pano, check_pre, check_vs_oracle
+    wpath = os.path.join(ROOT, "paper_2308_09209_amd", "weights", "flow_surrogate.vsnn")
+    blob = open(wpath, "rb").read()
+    t0 = time.perf_counter()
+    s = scene_for("8x3840x2160_ring")
+    frames = s.frames(0)
+    say(f"[8x4K ring, surrogate] frame generated in {time.perf_counter() - t0:.1f} s")
+    rig = s.rig()
+    st = V.Stitcher(rig, debug_taps=1)
+    st.load_weights(blob)
+    st.set_flow_mode(V.FLOW_SURROGATE_FALLBACK, 0.5)
+    orc = O.Oracle(rig)
+    orc.set_surrogate(blob, O.FLOW_FALLBACK, 0.5)
+    pano = st.stitch(dev(frames)).cpu().numpy()
+    t1 = time.perf_counter()
+    want = orc.stitch(frames)
+    say(f"[8x4K ring, surrogate] oracle frame in {time.perf_counter() - t1:.1f} s, pairs kept "
+        f"{int(orc.tap('surr_ok').sum())}/{orc.n_pairs}")
+    dmax = check_vs_oracle(st, orc, "8x4K surrogate")
+    check_pre(st, orc, dmax, "8x4K surrogate")
+    check_pano(st, orc, pano, want, dmax, "8x4K surrogate")
+    np.testing.assert_array_equal(st.tap("quant"), orc.tap("quant"))
+    st.close()

@@ -17,6 +17,7 @@ from oracle import oracle as O  # noqa: E402
 from paper_2308_09209_amd import vstitch as V  # noqa: E402
 from paper_2308_09209_amd.scenes import scene_for, small_scene  # noqa: E402
 from tests.rigs import crop_rig, smooth_image  # noqa: E402
+import bench  # noqa: E402
 
 pytestmark = pytest.mark.gpu
 
@@ -52,8 +53,12 @@ def check_steps(st, orc, label, full=True, flow=True):
                 a, b = st.tap("pyr", p, cam * 8), orc.tap("pyr", p, cam * 8)
                 np.testing.assert_array_equal(a, b, err_msg=f"{label} luma {p}/{cam}")
             for lvl in range(st.info.lk_levels):
-                np.testing.assert_array_equal(st.tap("need", p, lvl), orc.tap("need", p, lvl),
+                need = orc.tap("need", p, lvl)
+                np.testing.assert_array_equal(st.tap("need", p, lvl), need,
                                               err_msg=f"{label} flow domain {p}/{lvl}")
+                # the plan's domain accounting (the benchmark's flop count)
+                assert st.info.flow_px[p][lvl] == int(need.sum()), (label, p, lvl)
+                assert st.info.flow_taps[p][lvl] == bench.domain_taps(need, st.params.lk_radius), (label, p, lvl)
         for d in (0, 1):
             a, b = st.tap("flow", p, d), orc.tap("flow", p, d)
             epe = np.sqrt(((a.astype(np.float64) - b) ** 2).sum(-1))
@@ -208,12 +213,13 @@ def test_timing_reports_steps():
 
 def test_parity_4x1920x1080_ring_full_size():
     """The headline workload at full size (the launch configuration the
-    benchmark times): two frames, every output pixel against the oracle."""
+    benchmark times): frames 0-2, the first full three-frame window of eqs.
+    (2)-(3) and (6)-(7), every output pixel and step against the oracle."""
     s = scene_for("4x1920x1080_ring")
     rig = s.rig()
     st = V.Stitcher(rig, debug_taps=1)
     orc = O.Oracle(rig)
-    for t in range(2):
+    for t in range(3):
         frames = s.frames(t)
         say(f"[4x1080p ring] frame {t}")
         pano = st.stitch(dev(frames)).cpu().numpy()
@@ -223,7 +229,8 @@ def test_parity_4x1920x1080_ring_full_size():
         assert d <= 1
         deferred = [int(st.tap("deferred", 0, lvl)[0]) for lvl in range(st.info.lk_levels)]
         say(f"  flow pixels finished by the tail kernel per level: {deferred}")
-        check_steps(st, orc, f"4x1080p t={t}", full=(t == 0))
+        check_steps(st, orc, f"4x1080p t={t}", full=True)
+        assert st.state_get().frames_seen == t + 1
     st.close()
 
 

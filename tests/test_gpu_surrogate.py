@@ -86,6 +86,18 @@ def check_pano(st, orc, got, want, dmax, label):
     assert diff.max() <= bound and frac <= 1e-3, (label, int(diff.max()), bound, frac)
 
 
+def check_pre(st, orc, dmax, label):
+    """the pre-balance panorama (needs debug_taps) within the bound a flow
+    difference of dmax px allows before the balancing LUT: ceil(255 g dmax) + 1
+    levels, and 1 LSB on all but 1e-3 of its pixels"""
+    diff = np.abs(st.tap("pano_pre").astype(np.int64) - orc.tap("pano_pre").astype(np.int64))
+    g = float(np.abs(orc.tap("mk")).sum(axis=1).max())
+    bound = int(np.ceil(255.0 * g * dmax)) + 1
+    frac = float((diff > 1).mean())
+    say(f"  {label}: pre-balance max |diff| {int(diff.max())} LSB (bound {bound}), {frac:.2e} of pixels above 1 LSB")
+    assert diff.max() <= bound and frac <= 1e-3, (label, int(diff.max()), bound, frac)
+
+
 def check_vs_oracle(st, orc, label):
     """per-step checks; returns the largest level-0 flow difference (px)"""
     dmax = 0.0
@@ -111,7 +123,7 @@ def check_vs_oracle(st, orc, label):
 @pytest.mark.parametrize("mode", [V.FLOW_SURROGATE, V.FLOW_SURROGATE_FALLBACK])
 def test_surrogate_frames_match_oracle(ring, blob, mode):
     tau = 1e6 if mode == V.FLOW_SURROGATE_FALLBACK else 0.0
-    st = V.Stitcher(ring.rig())
+    st = V.Stitcher(ring.rig(), debug_taps=1)
     st.load_weights(blob)
     st.set_flow_mode(mode, tau)
     orc = O.Oracle(ring.rig())
@@ -122,6 +134,7 @@ def test_surrogate_frames_match_oracle(ring, blob, mode):
         want = orc.stitch(ring.frames(t))
         dmax = check_vs_oracle(st, orc, f"mode {mode} frame {t}")
         np.testing.assert_array_equal(st.tap("quant"), orc.tap("quant"))
+        check_pre(st, orc, dmax, f"mode {mode} frame {t}")
         check_pano(st, orc, pano.cpu().numpy(), want, dmax, f"mode {mode} frame {t}")
         fb = orc.tap("fb")
         for p in range(orc.n_pairs):
@@ -227,7 +240,7 @@ def test_batch_with_surrogate_and_recapture(blob):
 
 def test_surrogate_full_size_ring_frame_matches_oracle(blob):
     sc = S.scene_for("4x1920x1080_ring")
-    st = V.Stitcher(sc.rig())
+    st = V.Stitcher(sc.rig(), debug_taps=1)
     st.load_weights(blob)
     st.set_flow_mode(V.FLOW_SURROGATE)
     orc = O.Oracle(sc.rig())
@@ -237,6 +250,7 @@ def test_surrogate_full_size_ring_frame_matches_oracle(blob):
     torch.cuda.synchronize()
     want = orc.stitch(sc.frames(0))
     dmax = check_vs_oracle(st, orc, "4x1080p")
+    check_pre(st, orc, dmax, "4x1080p")
     check_pano(st, orc, pano.cpu().numpy(), want, dmax, "4x1080p")
 
 
