@@ -1106,37 +1106,20 @@ vs_status vs_batch_autotune(vs_batch* b, const uint8_t* const* const frames[], u
 
 }  // extern "C"
 
-struct vs_flow {
-    DevPlan hp;
-    DevPlan* dp = nullptr;
-    void* arena = nullptr;
-};
+namespace vs {
 
-extern "C" {
-
-vs_status vs_flow_destroy(vs_flow* f)
+// Plan of a plain-flow context on one w x h luma pair: a single "pair" whose
+// strip is the whole image, template = camera j, moving = camera i, every
+// pixel in the flow domain.  Fills the sizes and tile tables of d and the
+// workspace offsets; false on invalid sizes or parameters.
+bool flow_plan(int w, int h, const vs_params& P, DevPlan& d, FlowLayout& L)
 {
-    if (!f) return VS_E_INVAL;
-    if (f->arena) (void)hipFree(f->arena);
-    if (f->dp) (void)hipFree(f->dp);
-    delete f;
-    return VS_OK;
-}
-
-vs_status vs_flow_create(int w, int h, const vs_params* prm, vs_flow** out)
-{
-    if (!out || w < 2 || h < 2 || w > 65535 || h > 65535) return VS_E_INVAL;
-    *out = nullptr;
-    vs_params P;
-    if (prm) P = *prm;
-    else vs_default_params(&P);
+    if (w < 2 || h < 2 || w > 65535 || h > 65535) return false;
     if (P.lk_levels < 1 || P.lk_levels > VS_MAX_LEVELS || P.lk_iters < 0 || P.lk_radius < 0 ||
         P.lk_radius > LK_R_MAX || !std::isfinite(P.lk_lambda))
-        return VS_E_INVAL;
-    vs_flow* f = new (std::nothrow) vs_flow();
-    if (!f) return VS_E_NOMEM;
-    DevPlan& d = f->hp;
+        return false;
     std::memset(&d, 0, sizeof d);
+    std::memset(&L, 0, sizeof L);
     d.n_cams = 2;
     d.n_pairs = 1;
     d.levels = P.lk_levels;
@@ -1164,47 +1147,118 @@ vs_status vs_flow_create(int w, int h, const vs_params* prm, vs_flow** out)
         const int n16 = 2 * ((d.lw[0][l] + LKW_TX - 1) / LKW_TX) * ((d.lh[0][l] + 15) / 16);
         set_lk_tiles(d, l, P.lk_radius == LK_R_MAX ? default_lk_P(n16) : 0);
     }
-    size_t off = 0, o_pyr[2][MAXL], o_flow[2][MAXL], o_need[MAXL], o_queue[MAXL];
+    size_t off = 0;
     for (int l = 0; l < d.levels; ++l) {
         const size_t n = (size_t)d.lw[0][l] * d.lh[0][l];
-        o_need[l] = off;
+        L.need[l] = off;
         off = align_up(off + n, 256);
         for (int k = 0; k < 2; ++k) {
-            o_pyr[k][l] = off;
+            L.pyr[k][l] = off;
             off = align_up(off + n * 4, 256);
-            o_flow[k][l] = off;
+            L.flow[k][l] = off;
             off = align_up(off + n * 8, 256);
         }
         d.lk_qcap[l] = d.lk_P[l] > 0 ? (int32_t)(2 * n) : 0;
-        o_queue[l] = off;
+        L.queue[l] = off;
         off = align_up(off + (size_t)d.lk_qcap[l] * 16, 256);
     }
-    const size_t o_acc = off;
+    L.acc = off;
     off = align_up(off + sizeof(Accum), 256);
-    const size_t o_res = off;
+    L.res = off;
     off = align_up(off + sizeof(Results), 256);
-    const size_t o_state = off;
+    L.state = off;
     off = align_up(off + sizeof(vs_color_state), 256);
-    if (hipMalloc(&f->arena, off) != hipSuccess || hipMalloc((void**)&f->dp, sizeof(DevPlan)) != hipSuccess) {
+    L.bytes = off;
+    return true;
+}
+
+// Point the plan's buffers into a workspace of L.bytes at base.
+void flow_bind(DevPlan& d, const FlowLayout& L, uint8_t* base)
+{
+    for (int l = 0; l < d.levels; ++l) {
+        d.need[0][l] = base + L.need[l];
+        d.lk_queue[l] = (uint4*)(base + L.queue[l]);
+        for (int k = 0; k < 2; ++k) {
+            d.pyr[0][k][l] = (float*)(base + L.pyr[k][l]);
+            d.flow[0][k][l] = (float2*)(base + L.flow[k][l]);
+        }
+    }
+    d.acc = (Accum*)(base + L.acc);
+    d.res = (Results*)(base + L.res);
+    d.state = (vs_color_state*)(base + L.state);
+}
+
+// Mark every pixel of every level as flow domain (a fill kernel, no memset node).
+hipError_t flow_domain_fill(const DevPlan& d, hipStream_t s)
+{
+    hipError_t e = hipSuccess;
+    for (int l = 0; l < d.levels && e == hipSuccess; ++l)
+        e = launch_fill_u8(d.need[0][l], (size_t)d.lw[0][l] * d.lh[0][l], 1, s);
+    return e;
+}
+
+// One run of the plain estimator: the pair into level 0, the pyramids, the
+// flow coarse to fine, the level-0 flows out (every step on stream s).
+hipError_t flow_run(const DevPlan& d, DevPlan* dp, const float* yt, const float* ym, float* flow_tm,
+                    float* flow_mt, hipStream_t s)
+{
+    const size_t n = (size_t)d.sw[0] * d.sh[0];
+    Group g;
+    std::memset(&g, 0, sizeof g);
+    g.n = 1;
+    g.dp[0] = dp;
+    g.hp[0] = &d;
+    hipError_t e = hipMemcpyAsync(d.pyr[0][0][0], yt, n * 4, hipMemcpyDeviceToDevice, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(d.pyr[0][1][0], ym, n * 4, hipMemcpyDeviceToDevice, s);
+    if (e == hipSuccess) e = launch_zero(g, s);
+    for (int l = 0; l + 1 < d.levels && e == hipSuccess; ++l) e = launch_pyr_down(g, l, PYR_ALL, s);
+    for (int l = d.levels - 1; l >= 0 && e == hipSuccess; --l) e = launch_lk(g, l, s);
+    if (e == hipSuccess && flow_tm) e = hipMemcpyAsync(flow_tm, d.flow[0][0][0], n * 8, hipMemcpyDeviceToDevice, s);
+    if (e == hipSuccess && flow_mt) e = hipMemcpyAsync(flow_mt, d.flow[0][1][0], n * 8, hipMemcpyDeviceToDevice, s);
+    return e;
+}
+
+}  // namespace vs
+
+struct vs_flow {
+    DevPlan hp;
+    DevPlan* dp = nullptr;
+    void* arena = nullptr;
+};
+
+extern "C" {
+
+vs_status vs_flow_destroy(vs_flow* f)
+{
+    if (!f) return VS_E_INVAL;
+    if (f->arena) (void)hipFree(f->arena);
+    if (f->dp) (void)hipFree(f->dp);
+    delete f;
+    return VS_OK;
+}
+
+vs_status vs_flow_create(int w, int h, const vs_params* prm, vs_flow** out)
+{
+    if (!out) return VS_E_INVAL;
+    *out = nullptr;
+    vs_params P;
+    if (prm) P = *prm;
+    else vs_default_params(&P);
+    vs_flow* f = new (std::nothrow) vs_flow();
+    if (!f) return VS_E_NOMEM;
+    FlowLayout L;
+    if (!flow_plan(w, h, P, f->hp, L)) {
+        delete f;
+        return VS_E_INVAL;
+    }
+    if (hipMalloc(&f->arena, L.bytes) != hipSuccess || hipMalloc((void**)&f->dp, sizeof(DevPlan)) != hipSuccess) {
         vs_flow_destroy(f);
         return VS_E_NOMEM;
     }
-    uint8_t* base = (uint8_t*)f->arena;
-    for (int l = 0; l < d.levels; ++l) {
-        d.need[0][l] = base + o_need[l];
-        d.lk_queue[l] = (uint4*)(base + o_queue[l]);
-        for (int k = 0; k < 2; ++k) {
-            d.pyr[0][k][l] = (float*)(base + o_pyr[k][l]);
-            d.flow[0][k][l] = (float2*)(base + o_flow[k][l]);
-        }
-    }
-    d.acc = (Accum*)(base + o_acc);
-    d.res = (Results*)(base + o_res);
-    d.state = (vs_color_state*)(base + o_state);
-    bool ok = hipMemset(f->arena, 0, off) == hipSuccess;
-    for (int l = 0; l < d.levels && ok; ++l)   // the whole image is the flow domain
-        ok = hipMemset(d.need[0][l], 1, (size_t)d.lw[0][l] * d.lh[0][l]) == hipSuccess;
-    ok = ok && hipMemcpy(f->dp, &d, sizeof d, hipMemcpyHostToDevice) == hipSuccess;
+    flow_bind(f->hp, L, (uint8_t*)f->arena);
+    bool ok = hipMemset(f->arena, 0, L.bytes) == hipSuccess;
+    ok = ok && flow_domain_fill(f->hp, nullptr) == hipSuccess;   // the whole image is the flow domain
+    ok = ok && hipMemcpy(f->dp, &f->hp, sizeof f->hp, hipMemcpyHostToDevice) == hipSuccess;
     ok = ok && hipDeviceSynchronize() == hipSuccess;
     if (!ok) {
         vs_flow_destroy(f);
@@ -1217,22 +1271,8 @@ vs_status vs_flow_create(int w, int h, const vs_params* prm, vs_flow** out)
 vs_status vs_flow_run(vs_flow* f, const float* yt, const float* ym, float* flow_tm, float* flow_mt, void* stream)
 {
     if (!f || !yt || !ym) return VS_E_INVAL;
-    const DevPlan& d = f->hp;
-    hipStream_t s = (hipStream_t)stream;
-    const size_t n = (size_t)d.sw[0] * d.sh[0];
-    Group g;
-    std::memset(&g, 0, sizeof g);
-    g.n = 1;
-    g.dp[0] = f->dp;
-    g.hp[0] = &f->hp;
-    hipError_t e = hipMemcpyAsync(d.pyr[0][0][0], yt, n * 4, hipMemcpyDeviceToDevice, s);
-    if (e == hipSuccess) e = hipMemcpyAsync(d.pyr[0][1][0], ym, n * 4, hipMemcpyDeviceToDevice, s);
-    if (e == hipSuccess) e = launch_zero(g, s);
-    for (int l = 0; l + 1 < d.levels && e == hipSuccess; ++l) e = launch_pyr_down(g, l, PYR_ALL, s);
-    for (int l = d.levels - 1; l >= 0 && e == hipSuccess; --l) e = launch_lk(g, l, s);
-    if (e == hipSuccess && flow_tm) e = hipMemcpyAsync(flow_tm, d.flow[0][0][0], n * 8, hipMemcpyDeviceToDevice, s);
-    if (e == hipSuccess && flow_mt) e = hipMemcpyAsync(flow_mt, d.flow[0][1][0], n * 8, hipMemcpyDeviceToDevice, s);
-    return e == hipSuccess ? VS_OK : VS_E_DEVICE;
+    return flow_run(f->hp, f->dp, yt, ym, flow_tm, flow_mt, (hipStream_t)stream) == hipSuccess ? VS_OK
+                                                                                              : VS_E_DEVICE;
 }
 
 vs_status vs_flow_level(vs_flow* f, int level, float* yt, float* ym, int32_t* w_out, int32_t* h_out, void* stream)

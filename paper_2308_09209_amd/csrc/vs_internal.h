@@ -180,6 +180,18 @@ struct Fork {
     hipEvent_t join[MAXB];
 };
 hipError_t launch_blend(const Group& g, hipStream_t s);
+hipError_t launch_fill_u8(uint8_t* p, size_t n, uint8_t v, hipStream_t s);
+
+// workspace of a plain-flow context (vs_flow_create, vs_flow_run_noalloc)
+struct FlowLayout {
+    size_t need[MAXL], pyr[2][MAXL], flow[2][MAXL], queue[MAXL], acc, res, state, bytes;
+};
+// vs_host.cpp
+bool flow_plan(int w, int h, const vs_params& P, DevPlan& d, FlowLayout& L);
+void flow_bind(DevPlan& d, const FlowLayout& L, uint8_t* base);
+hipError_t flow_domain_fill(const DevPlan& d, hipStream_t s);
+hipError_t flow_run(const DevPlan& d, DevPlan* dp, const float* yt, const float* ym, float* flow_tm,
+                    float* flow_mt, hipStream_t s);
 hipError_t launch_balance_lut(const Group& g, hipStream_t s);
 hipError_t launch_balance_apply(const Group& g, hipStream_t s);
 

@@ -129,6 +129,22 @@ __global__ __launch_bounds__(256) void k_zero(const Batch B)
     if (i < (int)(sizeof(Accum) / 16)) p[i] = make_uint4(0, 0, 0, 0);
 }
 
+// n bytes at p <- v (grid-stride; a fill kernel where a caller may capture the
+// stream, no memset node)
+__global__ __launch_bounds__(256) void k_fill_u8(uint8_t* p, size_t n, uint8_t v)
+{
+    const size_t stride = (size_t)gridDim.x * 256;
+    for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < n; i += stride) p[i] = v;
+}
+
+hipError_t launch_fill_u8(uint8_t* p, size_t n, uint8_t v, hipStream_t s)
+{
+    if (n == 0) return hipSuccess;
+    const size_t blocks = std::min<size_t>((n + 255) / 256, 2048);
+    hipLaunchKernelGGL(k_fill_u8, dim3((unsigned)blocks), dim3(256), 0, s, p, n, v);
+    return hipGetLastError();
+}
+
 // Frame and panorama pointers of every context of the group, written into its
 // device plan before the frame's kernels run (they read them from there, so a
 // captured frame graph replays for any input buffers), and the frame's
