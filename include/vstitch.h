@@ -359,6 +359,24 @@ vs_status vs_flow_destroy(vs_flow* f);
  * device; either may be NULL) and its size. */
 vs_status vs_flow_level(vs_flow* f, int level, float* yt, float* ym, int32_t* w, int32_t* h, void* stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * estimator of vs_flow_run on one w x h luma pair without a context.  Same
+ * arguments and results as vs_flow_create(w, h, p) followed by vs_flow_run
+ * (p may be NULL: defaults), bit for bit.  Its plan and workspace live in one
+ * static device array of VS_FLOW_NOALLOC_BYTES per GPU, held until the
+ * process ends; at the default 4 levels that is about 77 bytes per pixel, so
+ * w * h up to about 850 000 (1088 x 768, 384 x 2160) fits.  A pair whose
+ * workspace does not fit returns VS_E_INVAL before any device work.  The
+ * call allocates nothing: no hipMalloc, no hipFree, no allocating library
+ * routine.  It runs on the current device; stream must belong to it.  Every
+ * call on a GPU shares that GPU's array and leaves its contents there, so
+ * calls that overlap on one GPU (other streams, other threads) race; calls in
+ * order on one stream do not.  Asynchronous on stream. */
+#define VS_FLOW_NOALLOC_BYTES (64u << 20)
+vs_status vs_flow_run_noalloc(int w, int h, const vs_params* p, const float* yt, const float* ym, float* flow_tm,
+                              float* flow_mt, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

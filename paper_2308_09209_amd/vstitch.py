@@ -40,7 +40,8 @@ EXPORTS = ["vs_abi_version", "vs_status_str", "vs_default_params", "vs_compose_h
            "vs_batch_destroy", "vs_batch_last_error", "vs_batch_autotune",
            "vs_nn_conv3x3", "vs_nn_wgrad_scratch_bytes", "vs_nn_conv3x3_wgrad", "vs_nn_flip_weights",
            "vs_nn_lrelu_bwd", "vs_nn_pack_pair", "vs_nn_epe_loss", "vs_nn_adam", "vs_nn_to_bf16",
-           "vs_nn_mfma_probe", "vs_nn_mfma_probe_k32", "vs_flow_create", "vs_flow_run", "vs_flow_destroy", "vs_flow_level"]
+           "vs_nn_mfma_probe", "vs_nn_mfma_probe_k32", "vs_flow_create", "vs_flow_run", "vs_flow_destroy", "vs_flow_level",
+           "vs_flow_run_noalloc"]
 
 
 class Rig(C.Structure):
@@ -164,6 +165,7 @@ def lib():
         L.vs_flow_run.argtypes = [vp, vp, vp, vp, vp, vp]
         L.vs_flow_destroy.argtypes = [vp]
         L.vs_flow_level.argtypes = [vp, i32, vp, vp, C.POINTER(C.c_int32), C.POINTER(C.c_int32), vp]
+        L.vs_flow_run_noalloc.argtypes = [i32, i32, C.POINTER(Params), vp, vp, vp, vp, vp]
         _lib = L
     return _lib
 
@@ -517,3 +519,28 @@ class PlainFlow:
         check(lib().vs_flow_level(self.hnd, level, _p(yt), _p(ym), None, None, _stream_handle(stream)),
               "vs_flow_level")
         return yt, ym
+
+
+def flow_run_noalloc(yt, ym, flow_tm=None, flow_mt=None, stream=None, **params):
+    """vs_flow_run_noalloc: the plain flow of template yt vs moving ym (device
+    float32 [h][w]) in the library's static workspace, into caller tensors
+    flow_tm / flow_mt (float32 [h][w][2], created here when None; either may
+    be passed as False to skip it).  Returns (flow_tm, flow_mt)."""
+    h, w = tuple(yt.shape)
+    for t in (yt, ym):
+        if t.dtype != torch.float32 or not t.is_cuda or tuple(t.shape) != (h, w) or not t.is_contiguous():
+            raise ValueError("luma: contiguous cuda float32 (h, w), both the same shape")
+    outs = []
+    for f in (flow_tm, flow_mt):
+        if f is None:
+            f = torch.empty((h, w, 2), dtype=torch.float32, device=yt.device)
+        elif f is not False and (f.dtype != torch.float32 or f.device != yt.device or tuple(f.shape) != (h, w, 2)
+                                 or not f.is_contiguous()):
+            raise ValueError("flow: contiguous float32 (h, w, 2) on the luma's device")
+        outs.append(f)
+    prm = default_params(**params)
+    check(lib().vs_flow_run_noalloc(w, h, C.byref(prm), _p(yt), _p(ym),
+                                    _p(outs[0]) if outs[0] is not False else None,
+                                    _p(outs[1]) if outs[1] is not False else None, _stream_handle(stream)),
+          "vs_flow_run_noalloc")
+    return outs[0], outs[1]

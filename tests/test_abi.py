@@ -142,3 +142,14 @@ def test_host_tensor_panorama_is_rejected_before_any_library_call(monkeypatch):
     b.stitchers = [st]
     with pytest.raises(ValueError, match="device tensor"):
         b._ptrs([frames], [torch.zeros((8, 24, 3), dtype=torch.uint8)])
+
+
+def test_noalloc_flow_rejects_oversized_pairs_on_the_host():
+    """vs_flow_run_noalloc refuses a pair whose workspace exceeds its static
+    array before any device call (the pointers are never dereferenced), and
+    NULL inputs; no GPU needed."""
+    L = V.lib()
+    fake = C.c_void_p(16)
+    assert L.vs_flow_run_noalloc(4000, 3000, None, fake, fake, fake, fake, None) == -1
+    assert L.vs_flow_run_noalloc(64, 64, None, None, fake, fake, fake, None) == -1
+    assert L.vs_flow_run_noalloc(1, 64, None, fake, fake, fake, fake, None) == -1
