@@ -235,10 +235,13 @@ vs_status vs_set_timing(vs_ctx* c, int on);
 vs_status vs_get_timing(vs_ctx* c, double ms[6], uint32_t* frames);
 
 /* Flow-kernel variant of one pyramid level: 0 = generic kernel (16 x 16
- * pixel tiles, any radius), 1, 2 or 4 = the 9x9-window kernel (radius 4) with
- * that many vertically adjacent pixels per thread.  Results are identical for
- * every variant; only speed differs.  vs_create picks one per level; the
+ * pixel tiles, any radius), 1, 2, 3 or 4 = the 9x9-window kernel (radius 4)
+ * with that many vertically adjacent pixels per thread, 9, 10, 11 or 12 = the
+ * same with two alternating register sets for the interpolated moving-image
+ * rows (more registers, fewer instructions).  Results are identical for every
+ * variant; only speed differs.  vs_create picks one per level; the
  * autotuner below measures them. */
+#define VS_FLOW_VARIANTS 8   /* 9x9-window variants the autotuner measures: 1, 2, 3, 4, 9, 10, 11, 12 */
 vs_status vs_set_flow_variant(vs_ctx* c, int level, int variant);
 vs_status vs_get_flow_variant(const vs_ctx* c, int32_t variant[VS_MAX_LEVELS]);
 
@@ -259,12 +262,13 @@ vs_status vs_batch_destroy(vs_batch* b);
 const char* vs_batch_last_error(const vs_batch* b);
 
 /* Autotuner: for every pyramid level, run the batch on the given frames with
- * each 9x9 flow-kernel variant (1, 2, 4 pixels per thread), `reps` timed runs
+ * each 9x9 flow-kernel variant (1, 2, 3, 4, 9, 10, 11, 12), `reps` timed runs
  * each, and keep the fastest.  ms[l][i] receives the mean frame time of
- * variant {1, 2, 4}[i] at level l (may be NULL); choice[l] the variant kept.
+ * variant {1, 2, 3, 4, 9, 10, 11, 12}[i] at level l (may be NULL); choice[l]
+ * the variant kept.
  * The colour states are restored afterwards.  Synchronous. */
 vs_status vs_batch_autotune(vs_batch* b, const uint8_t* const* const frames[], uint8_t* const panos[], int reps,
-                            float ms[VS_MAX_LEVELS][3], int32_t choice[VS_MAX_LEVELS]);
+                            float ms[VS_MAX_LEVELS][VS_FLOW_VARIANTS], int32_t choice[VS_MAX_LEVELS]);
 
 /* ------------------------------------------------------------------------
  * Learned flow surrogate (an addition to the paper's method): a small 3x3
@@ -316,12 +320,63 @@ vs_status vs_nn_epe_loss(const float* pred, const float* label, uint16_t* dz, fl
 vs_status vs_nn_adam(float* w, float* m, float* v, const float* g, uint16_t* w_bf16, int64_t n, float lr, float b1,
                      float b2, float eps, int step, void* stream);
 vs_status vs_nn_to_bf16(const float* a, uint16_t* b, int64_t n, void* stream);
-/* One 16x16x16 BF16 matrix-core product of a[16][16] and b[16][16]; out[64][4]
- * receives each lane's accumulator fragment (a layout check). */
-vs_status vs_nn_mfma_probe(const uint16_t* a, const uint16_t* b, float* out, void* stream);
-/* One 16x16x32 BF16 matrix-core product (the instruction of vs_nn_conv3x3) of
- * a[16][32] and b[32][16]; out[64][4] as above. */
-vs_status vs_nn_mfma_probe_k32(const uint16_t* a, const uint16_t* b, float* out, void* stream);
+/* Training labels at a coarser level: flow (FP32 [h][w][2], device) average
+ * pooled over factor x factor blocks (the last block row and column may be
+ * partial: the mean over the pixels they hold) and divided by factor, into out
+ * (FP32 [ceil(h / factor)][ceil(w / factor)][2], device); 1 <= factor <= 64. */
+vs_status vs_nn_pool_flow(const float* flow, int w, int h, int factor, float* out, void* stream);
+
+/* The network as an object: parameters (FP32 master weights and biases),
+ * Adam state, BF16 copies and every training workspace on the device.
+ * Layers are 3x3 convolutions with (cin, cout) in {(16,32), (32,32), (32,16)},
+ * cin[0] = 16, cout[n_layers - 1] = 16, each cin the previous cout; leaky
+ * ReLU (slope alpha) after every layer but the last; the last layer's
+ * channels 0-1 are the flow.  in_live: input channels that carry data (the
+ * first layer's weights on the others start at 0).  max_pixels bounds the
+ * pixels of one forward (all images together): the workspaces are sized for
+ * it at vs_nn_create, and no later call allocates. */
+#define VS_NN_MAX_LAYERS 8
+typedef struct {
+    int32_t n_layers;
+    int32_t cin[VS_NN_MAX_LAYERS], cout[VS_NN_MAX_LAYERS];
+    int32_t in_live;
+    float alpha;
+    int64_t max_pixels;
+} vs_nn_spec;
+typedef struct vs_nn vs_nn;
+/* Weights He-initialised from a splitmix64 / Box-Muller stream of `seed`
+ * (standard deviation sqrt(2 / (9 fan-in)), the last layer's times 0.1),
+ * biases and optimiser state 0.  Synchronous. */
+vs_status vs_nn_create(const vs_nn_spec* spec, uint64_t seed, vs_nn** out);
+vs_status vs_nn_destroy(vs_nn* n);
+/* Forward over the images of imgs (back to back, NHWC): x [pixels][16] BF16
+ * (device, 16-byte aligned; it must stay unchanged until the matching
+ * vs_nn_backward); pred (device, may be NULL) receives the FP32 output
+ * [pixels][16].  The activations stay in the object for the backward pass. */
+vs_status vs_nn_forward(vs_nn* n, const uint16_t* x, const vs_nn_images* imgs, float* pred, void* stream);
+/* Sum over the last forward's pixels of the end-point error
+ * sqrt(dx^2 + dy^2 + 1e-6) of output channels 0-1 against label (FP32
+ * [pixels][2], device) into *loss_sum (one FP32 on the device).  VS_E_STATE
+ * without a forward. */
+vs_status vs_nn_loss(vs_nn* n, const float* label, float* loss_sum, void* stream);
+/* Backward of the mean of that error over the pixels: every parameter's
+ * gradient into the object's gradient buffer (overwritten, not accumulated);
+ * loss_sum (device, may be NULL) as vs_nn_loss. */
+vs_status vs_nn_backward(vs_nn* n, const float* label, float* loss_sum, void* stream);
+/* One Adam step (bias-corrected; the object counts the steps) on the
+ * gradients of the last backward, then the BF16 copies are refreshed. */
+vs_status vs_nn_adam_step(vs_nn* n, float lr, float b1, float b2, float eps, void* stream);
+/* Copies of the FP32 parameters and of the last backward's gradients (layer
+ * by layer: w [cout][9][cin] then b [cout]) into caller device buffers of
+ * *count floats (either may be NULL; count may be NULL); asynchronous. */
+vs_status vs_nn_params(vs_nn* n, float* params, float* grads, size_t* count, void* stream);
+/* The weight file of vs_load_weights (BF16 weights, FP32 biases) into a host
+ * buffer of cap bytes; *nbytes receives its size (blob NULL: size only).
+ * vs_nn_load reads one whose layer list equals the object's: the master
+ * weights become the stored BF16 values, the Adam state restarts.  Both
+ * synchronous. */
+vs_status vs_nn_save(vs_nn* n, void* blob, size_t cap, size_t* nbytes);
+vs_status vs_nn_load(vs_nn* n, const void* blob, size_t nbytes);
 
 /* The learned surrogate inside the frame.  vs_load_weights copies a weight
  * file into the context: "VSNN", u32 version 1, u32 layers (2..8), f32

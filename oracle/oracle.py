@@ -480,3 +480,51 @@ def fb_check(pred_ij, pred_ji, need0):
     lib().vso_fb_check(_ptr(a), _ptr(b), a.shape[1], a.shape[0], _ptr(need0), need0.shape[1], need0.shape[0],
                        C.byref(s), C.byref(n))
     return s.value, n.value
+
+
+# ---- learned surrogate: FP64 training step of the whole network -----------
+
+def nn_train_step(ws, bs, x, label, sizes, alpha):
+    """One training step's forward and backward in FP64: a chain of 3x3
+    convolutions (weights ws[l] (cout, 9, cin), biases bs[l]) with leaky ReLU
+    (slope alpha) after every layer but the last, on the images of `sizes`
+    ((h, w) each) stored back to back in x (pixels, cin0); the loss is the mean
+    over all pixels of the end-point error sqrt(dx^2 + dy^2 + 1e-6) of output
+    channels 0-1 against label (pixels, 2).  Returns (loss, pred (pixels,
+    cout), [dL/dw], [dL/db])."""
+    x = np.asarray(x, np.float64)
+    label = np.asarray(label, np.float64)
+    P = x.shape[0]
+    offs = np.cumsum([0] + [h * w for h, w in sizes])
+
+    def per_image(a):
+        return [a[offs[i]:offs[i + 1]].reshape(1, h, w, a.shape[1]) for i, (h, w) in enumerate(sizes)]
+
+    def join(parts):
+        return np.concatenate([p.reshape(-1, p.shape[-1]) for p in parts])
+
+    L = len(ws)
+    hs, zs = [x], []
+    for li in range(L):
+        z = join([conv3x3(a, ws[li], bs[li]) for a in per_image(hs[-1])])
+        zs.append(z)
+        hs.append(z if li == L - 1 else np.where(z > 0, z, alpha * z))
+    pred = hs[-1]
+    d = pred[:, :2] - label
+    e = np.sqrt(d[:, 0] ** 2 + d[:, 1] ** 2 + 1e-6)
+    loss = float(e.mean())
+    dz = np.zeros_like(pred)
+    dz[:, :2] = d / e[:, None] / P
+    gw, gb = [None] * L, [None] * L
+    for li in range(L - 1, -1, -1):
+        gw[li] = np.zeros_like(np.asarray(ws[li], np.float64))
+        gb[li] = np.zeros(np.asarray(ws[li]).shape[0])
+        for a, g in zip(per_image(hs[li]), per_image(dz)):
+            dw, db = conv3x3_bwd_weight(a, g)
+            gw[li] += dw
+            gb[li] += db
+        if li == 0:
+            break
+        dh = join([conv3x3_bwd_data(g, ws[li]) for g in per_image(dz)])
+        dz = np.where(zs[li - 1] > 0, dh, alpha * dh)
+    return loss, pred, gw, gb

@@ -16,6 +16,23 @@ namespace vs {
 // global memory instead.
 // ---------------------------------------------------------------------------
 
+// Origin of flow tile `bid` (field f) of level l: from the plan's tile list
+// (tiles that follow the flow domain), else the box grid.
+__device__ __forceinline__ void tile_origin(const DevPlan* __restrict__ P, int l, int f, int bid, int tx, int ty,
+                                            int& x0, int& y0)
+{
+    const uint32_t* __restrict__ list = P->lk_tiles[l];
+    if (list) {
+        const uint32_t e = list[bid];
+        x0 = (int)(e & 0xffffu);
+        y0 = (int)(e >> 16);
+    } else {
+        const int t = bid - P->lk_off[l][f];
+        x0 = (t % P->lk_tx[l][f]) * tx;
+        y0 = (t / P->lk_tx[l][f]) * ty;
+    }
+}
+
 constexpr int LK_HT = LK_R_MAX + 1;              // template halo (window + gradient)
 constexpr int LK_TW = LK_T + 2 * LK_HT;          // 26
 constexpr int LK_GW = LK_T + 2 * LK_R_MAX;       // 24
@@ -31,9 +48,9 @@ __device__ __forceinline__ void lk_body(const DevPlan* __restrict__ P, const int
     const int f = find_field(P->lk_off[l], 2 * P->n_pairs, bid);
     const int p = f >> 1, dir = f & 1;
     if (kept_by_surrogate(P, p)) return;   // the pair keeps the surrogate's flows
-    const int t = bid - P->lk_off[l][f];
     const int w = P->lw[p][l], h = P->lh[p][l];
-    const int x0 = (t % P->lk_tx[l][f]) * LK_T, y0 = (t / P->lk_tx[l][f]) * LK_T;
+    int x0, y0;
+    tile_origin(P, l, f, bid, LK_T, LK_T, x0, y0);
     const float* __restrict__ Tm = P->pyr[p][dir == 0 ? 0 : 1][l];
     const float* __restrict__ Mv = P->pyr[p][dir == 0 ? 1 : 0][l];
     const int tid = threadIdx.x;
@@ -173,7 +190,53 @@ __global__ __launch_bounds__(256) void k_lk(const Batch B, int l)
 __device__ __forceinline__ void lk_tail_pixel(const DevPlan* __restrict__ Pl, int l, int f, int x, int y, int it0,
                                               float ux, float uy);
 
-template <int P, bool INBLOCK>
+// One row j of the P pixels' windows in a Gauss-Newton step: pixel q takes
+// window row jr = j - q.  prev[q] holds the moving image's horizontally
+// interpolated window row jr of pixel q (computed here for jr = 0), next[q]
+// receives row jr + 1; then for each column the vertical interpolation, the
+// residual against the template and the two sums b, in row-major order.
+// prev and next may be the same array.
+template <int P, int TIW, int MWP>
+__device__ __forceinline__ void lk_window_row(int j, const float4* __restrict__ ti_base, const float* __restrict__ sM,
+                                              const int (&mb)[P], const float (&fx)[P], const float (&fy)[P],
+                                              float (&prev)[P][2 * LK_R_MAX + 1], float (&next)[P][2 * LK_R_MAX + 1],
+                                              float (&bu)[P], float (&bv)[P])
+{
+    constexpr int R = LK_R_MAX, NW = 2 * R + 1;
+    float4 ti[NW];
+#pragma unroll
+    for (int c = 0; c < NW; ++c) ti[c] = ti_base[j * TIW + c];
+#pragma unroll
+    for (int q = 0; q < P; ++q) {
+        const int jr = j - q;
+        if (jr < 0 || jr > 2 * R) continue;
+        if (jr == 0) {
+            const float* m0 = sM + mb[q];
+            float v0 = m0[0];
+#pragma unroll
+            for (int c = 0; c < NW; ++c) {
+                const float v1 = m0[c + 1];
+                prev[q][c] = __builtin_fmaf(fx[q], v1 - v0, v0);
+                v0 = v1;
+            }
+        }
+        const float* m1 = sM + mb[q] + (jr + 1) * MWP;
+        float v0 = m1[0];
+#pragma unroll
+        for (int c = 0; c < NW; ++c) {
+            const float v1 = m1[c + 1];
+            const float hb = __builtin_fmaf(fx[q], v1 - v0, v0);
+            v0 = v1;
+            const float m = __builtin_fmaf(fy[q], hb - prev[q][c], prev[q][c]);
+            const float e = m - ti[c].x;
+            bu[q] = __builtin_fmaf(ti[c].y, e, bu[q]);
+            bv[q] = __builtin_fmaf(ti[c].z, e, bv[q]);
+            next[q][c] = hb;
+        }
+    }
+}
+
+template <int P, bool INBLOCK, bool ALT>
 __device__ __forceinline__ void lk_w9_body(const DevPlan* __restrict__ Pl, const int bid, int l)
 {
     constexpr int R = LK_R_MAX, NW = 2 * R + 1;
@@ -192,9 +255,9 @@ __device__ __forceinline__ void lk_w9_body(const DevPlan* __restrict__ Pl, const
     const int f = find_field(Pl->lk_off[l], 2 * Pl->n_pairs, bid);
     const int p = f >> 1, dir = f & 1;
     if (kept_by_surrogate(Pl, p)) return;   // the pair keeps the surrogate's flows
-    const int t = bid - Pl->lk_off[l][f];
     const int w = Pl->lw[p][l], h = Pl->lh[p][l];
-    const int x0 = (t % Pl->lk_tx[l][f]) * TX, y0 = (t / Pl->lk_tx[l][f]) * TY;
+    int x0, y0;
+    tile_origin(Pl, l, f, bid, TX, TY, x0, y0);
     const float* __restrict__ Tm = Pl->pyr[p][dir == 0 ? 0 : 1][l];
     const float* __restrict__ Mv = Pl->pyr[p][dir == 0 ? 1 : 0][l];
     const int tid = threadIdx.x;
@@ -258,6 +321,11 @@ __device__ __forceinline__ void lk_w9_body(const DevPlan* __restrict__ Pl, const
         g01[q] = 0.0f;
         g11[q] = 0.0f;
     }
+    // a wavefront without a flow-domain pixel has nothing to do (no barrier follows)
+    bool any_act = false;
+#pragma unroll
+    for (int q = 0; q < P; ++q) any_act = any_act || act[q];
+    if (!__any(any_act)) return;
     // normal matrix: rows shared by the P pixels, row-major within each window
 #pragma unroll 1
     for (int j = 0; j < P + 2 * R; ++j) {
@@ -308,38 +376,52 @@ __device__ __forceinline__ void lk_w9_body(const DevPlan* __restrict__ Pl, const
             }
             mb[q] = (wv * P + q - R + HM + oy) * MWP + (lane - R + HM + ox);
         }
-        float hp[P][NW];
+        // window rows j of the thread's P pixels; ALT alternates two register
+        // sets for the interpolated moving-image rows (no copies between rows)
+        constexpr int NJ = P + 2 * R;
+        float hA[P][NW];
+        if (ALT) {
+            float hB[P][NW];
 #pragma unroll 1
-        for (int j = 0; j < P + 2 * R; ++j) {
-            float4 ti[NW];
+            for (int j = 0; j + 1 < NJ; j += 2) {
+                lk_window_row<P, TIW, MWP>(j, sTI + wv * P * TIW + lane, sM, mb, fx, fy, hA, hB, bu, bv);
+                lk_window_row<P, TIW, MWP>(j + 1, sTI + wv * P * TIW + lane, sM, mb, fx, fy, hB, hA, bu, bv);
+            }
+            if (NJ % 2) lk_window_row<P, TIW, MWP>(NJ - 1, sTI + wv * P * TIW + lane, sM, mb, fx, fy, hA, hB, bu, bv);
+        } else {
+            // one register set: each new row is copied over the previous one
+#pragma unroll 1
+            for (int j = 0; j < NJ; ++j) {
+                float4 ti[NW];
 #pragma unroll
-            for (int c = 0; c < NW; ++c) ti[c] = sTI[(wv * P + j) * TIW + lane + c];
+                for (int c = 0; c < NW; ++c) ti[c] = sTI[(wv * P + j) * TIW + lane + c];
 #pragma unroll
-            for (int q = 0; q < P; ++q) {
-                const int jr = j - q;
-                if (jr < 0 || jr > 2 * R) continue;
-                if (jr == 0) {
-                    const float* m0 = sM + mb[q];
-                    float v0 = m0[0];
+                for (int q = 0; q < P; ++q) {
+                    const int jr = j - q;
+                    if (jr < 0 || jr > 2 * R) continue;
+                    if (jr == 0) {
+                        const float* m0 = sM + mb[q];
+                        float v0 = m0[0];
+#pragma unroll
+                        for (int c = 0; c < NW; ++c) {
+                            const float v1 = m0[c + 1];
+                            hA[q][c] = __builtin_fmaf(fx[q], v1 - v0, v0);
+                            v0 = v1;
+                        }
+                    }
+                    const float* m1 = sM + mb[q] + (jr + 1) * MWP;
+                    float v0 = m1[0];
 #pragma unroll
                     for (int c = 0; c < NW; ++c) {
-                        const float v1 = m0[c + 1];
-                        hp[q][c] = __builtin_fmaf(fx[q], v1 - v0, v0);
+                        const float v1 = m1[c + 1];
+                        const float hb = __builtin_fmaf(fx[q], v1 - v0, v0);
                         v0 = v1;
+                        const float m = __builtin_fmaf(fy[q], hb - hA[q][c], hA[q][c]);
+                        const float e = m - ti[c].x;
+                        bu[q] = __builtin_fmaf(ti[c].y, e, bu[q]);
+                        bv[q] = __builtin_fmaf(ti[c].z, e, bv[q]);
+                        hA[q][c] = hb;
                     }
-                }
-                const float* m1 = sM + mb[q] + (jr + 1) * MWP;
-                float v0 = m1[0];
-#pragma unroll
-                for (int c = 0; c < NW; ++c) {
-                    const float v1 = m1[c + 1];
-                    const float hb = __builtin_fmaf(fx[q], v1 - v0, v0);
-                    v0 = v1;
-                    const float m = __builtin_fmaf(fy[q], hb - hp[q][c], hp[q][c]);
-                    const float e = m - ti[c].x;
-                    bu[q] = __builtin_fmaf(ti[c].y, e, bu[q]);
-                    bv[q] = __builtin_fmaf(ti[c].z, e, bv[q]);
-                    hp[q][c] = hb;
                 }
             }
         }
@@ -390,12 +472,12 @@ __device__ __forceinline__ void lk_w9_body(const DevPlan* __restrict__ Pl, const
     }
 }
 
-template <int P, bool INBLOCK>
+template <int P, bool INBLOCK, bool ALT = false>
 __global__ __launch_bounds__(256) void k_lk_w9(const Batch B, int l)
 {
     int c;
     const int b = batch_block(B, blockIdx.x, c);
-    lk_w9_body<P, INBLOCK>(B.plan[c], b, l);
+    lk_w9_body<P, INBLOCK, ALT>(B.plan[c], b, l);
 }
 
 // Pixels whose displacement left the staged tile finish here (inside the
@@ -685,7 +767,8 @@ hipError_t launch_need(const DevPlan* dp, const DevPlan& hp, hipStream_t s)
 
 hipError_t launch_lk(const Group& g, int l, hipStream_t s)
 {
-    // every context of a group runs the same flow-kernel variant at a level
+    // every context of a group runs the same flow-kernel variant at a level:
+    // 0 generic, else pixels per thread (1, 2, 4) plus 8 for alternating row registers
     const int P = g.hp[0]->lk_P[l];
     for (int c = 1; c < g.n; ++c)
         if (g.hp[c]->lk_P[l] != P) return hipErrorInvalidValue;
@@ -702,8 +785,18 @@ hipError_t launch_lk(const Group& g, int l, hipStream_t s)
         case 9: hipLaunchKernelGGL((k_lk_w9<4, true>), grid, dim3(256), 0, s, B, l); break;
         case 4: hipLaunchKernelGGL((k_lk_w9<2, false>), grid, dim3(256), 0, s, B, l); break;
         case 5: hipLaunchKernelGGL((k_lk_w9<2, true>), grid, dim3(256), 0, s, B, l); break;
+        case 6: hipLaunchKernelGGL((k_lk_w9<3, false>), grid, dim3(256), 0, s, B, l); break;
+        case 7: hipLaunchKernelGGL((k_lk_w9<3, true>), grid, dim3(256), 0, s, B, l); break;
+        case 22: hipLaunchKernelGGL((k_lk_w9<3, false, true>), grid, dim3(256), 0, s, B, l); break;
+        case 23: hipLaunchKernelGGL((k_lk_w9<3, true, true>), grid, dim3(256), 0, s, B, l); break;
         case 2: hipLaunchKernelGGL((k_lk_w9<1, false>), grid, dim3(256), 0, s, B, l); break;
         case 3: hipLaunchKernelGGL((k_lk_w9<1, true>), grid, dim3(256), 0, s, B, l); break;
+        case 24: hipLaunchKernelGGL((k_lk_w9<4, false, true>), grid, dim3(256), 0, s, B, l); break;
+        case 25: hipLaunchKernelGGL((k_lk_w9<4, true, true>), grid, dim3(256), 0, s, B, l); break;
+        case 20: hipLaunchKernelGGL((k_lk_w9<2, false, true>), grid, dim3(256), 0, s, B, l); break;
+        case 21: hipLaunchKernelGGL((k_lk_w9<2, true, true>), grid, dim3(256), 0, s, B, l); break;
+        case 18: hipLaunchKernelGGL((k_lk_w9<1, false, true>), grid, dim3(256), 0, s, B, l); break;
+        case 19: hipLaunchKernelGGL((k_lk_w9<1, true, true>), grid, dim3(256), 0, s, B, l); break;
         default: hipLaunchKernelGGL(k_lk, grid, dim3(256), 0, s, B, l); break;
         }
     }

@@ -22,6 +22,10 @@ struct vs_ctx {
     size_t arena_bytes = 0;
     void* plan_mem = nullptr;  // coverage bits + candidates + pixel codes + scan
     uint8_t* pano_pre = nullptr;
+    // the flow domain on the host (plan time) and the flow-tile lists built from it
+    std::vector<uint8_t> need_h[MAXP][MAXL];
+    uint32_t* tiles = nullptr;           // device: per level, tiles_cap[l] entries from tiles_off[l]
+    size_t tiles_off[MAXL] = {}, tiles_cap[MAXL] = {};
     vs_plan_info info;
     int sticky = 0;
     std::string err;
@@ -121,17 +125,48 @@ void free_ctx(vs_ctx* c)
     if (c->dp) (void)hipFree(c->dp);
     if (c->pano_pre) (void)hipFree(c->pano_pre);
     if (c->surr_mem) (void)hipFree(c->surr_mem);
+    if (c->tiles) (void)hipFree(c->tiles);
     delete c;
 }
 
 // Default 9x9 flow-kernel variant of a level, from its count of 64 x 16 tiles
-// (4 px per thread): the most pixels per thread that still gives >= 512
-// blocks, two per compute unit, else 1 px per thread
-int default_lk_P(int n16)
+// (n16) and the blocks the device holds at once (`resident`, three staged
+// flow blocks per compute unit): the most pixels per thread P (4, 3, 2, 1;
+// n16 * 4 / P blocks) whose last wave of blocks is at least three quarters
+// full, else the P that fills its waves best (ties: more pixels per thread).
+// One or two pixels per thread take the alternating-register form (+8),
+// which their register budget allows.
+int default_lk_P(int n16, int resident)
 {
-    for (int P = 4; P > 1; P /= 2)
-        if (n16 * (4 / P) >= 512) return P;
-    return 1;
+    int best = 1;
+    double best_fill = -1.0;
+    for (int P = 4; P >= 1; --P) {
+        const long blocks = ((long)n16 * 4 + P - 1) / P;
+        const long waves = (blocks + resident - 1) / resident;
+        const double fill = waves > 0 ? (double)blocks / (double)(waves * resident) : 0.0;
+        if (fill >= 0.75) {
+            best = P;
+            break;
+        }
+        if (fill > best_fill + 1e-9) {
+            best_fill = fill;
+            best = P;
+        }
+    }
+    return best <= 2 ? best + 8 : best;
+}
+
+// blocks of the staged flow kernel the current device holds at once
+int lk_resident_blocks()
+{
+    static int cached = 0;
+    if (cached) return cached;
+    int dev = 0, ncu = 0;
+    if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        ncu <= 0)
+        ncu = 256;
+    cached = 3 * ncu;
+    return cached;
 }
 
 // Choose the flow-kernel variant of one level (0: generic 16x16 kernel;
@@ -141,9 +176,10 @@ void set_lk_tiles(DevPlan& h, int l, int P)
 {
     int tx = LK_T, ty = LK_T;
     h.lk_P[l] = P;
+    h.lk_tiles[l] = nullptr;
     if (P > 0) {
         tx = LKW_TX;
-        ty = 4 * P;
+        ty = 4 * (P & 7);
     }
     h.lk_off[l][0] = 0;
     for (int f = 0; f < 2 * h.n_pairs; ++f) {
@@ -151,6 +187,71 @@ void set_lk_tiles(DevPlan& h, int l, int P)
         h.lk_tx[l][f] = (h.lw[p][l] + tx - 1) / tx;
         h.lk_off[l][f + 1] = h.lk_off[l][f] + h.lk_tx[l][f] * ((h.lh[p][l] + ty - 1) / ty);
     }
+}
+
+// The most flow tiles any variant lists for a level: a band never holds more
+// tiles than a row of the box grid.
+size_t lk_tile_cap(const DevPlan& h, int l)
+{
+    size_t n = 0;
+    for (int f = 0; f < 2 * h.n_pairs; ++f) {
+        const size_t w = (size_t)h.lw[f >> 1][l], hh = (size_t)h.lh[f >> 1][l];
+        n += std::max(((w + LKW_TX - 1) / LKW_TX) * ((hh + 3) / 4), ((w + LK_T - 1) / LK_T) * ((hh + LK_T - 1) / LK_T));
+    }
+    return n;
+}
+
+// Flow tiles of one level that follow the flow domain: per band of tile rows,
+// tiles from the band's first domain column to its last.  The overlap of two
+// rotated cameras slants across its bounding box, so a box-grid tile at the
+// slant's edge holds few domain pixels; a band's tiles start where its domain
+// starts.  Sets lk_off and lk_tiles and uploads the list (the caller uploads
+// the plan).  Strips wider or taller than 16 bits keep the box grid.
+hipError_t band_tiles(vs_ctx* c, int l)
+{
+    DevPlan& h = c->hp;
+    if (!c->tiles) return hipSuccess;
+    int tx = LK_T, ty = LK_T;
+    if (h.lk_P[l] > 0) {
+        tx = LKW_TX;
+        ty = 4 * (h.lk_P[l] & 7);
+    }
+    for (int p = 0; p < h.n_pairs; ++p)
+        if (h.lw[p][l] > 65535 || h.lh[p][l] > 65535 || c->need_h[p][l].size() != (size_t)h.lw[p][l] * h.lh[p][l]) {
+            h.lk_tiles[l] = nullptr;   // set_lk_tiles' grid stays
+            return hipSuccess;
+        }
+    std::vector<uint32_t> list;
+    int32_t off[2 * MAXP + 1];
+    off[0] = 0;
+    for (int f = 0; f < 2 * h.n_pairs; ++f) {
+        const int p = f >> 1, w = h.lw[p][l], hh = h.lh[p][l];
+        const uint8_t* nd = c->need_h[p][l].data();
+        for (int y0 = 0; y0 < hh; y0 += ty) {
+            int xa = w, xb = -1;
+            for (int y = y0; y < std::min(y0 + ty, hh); ++y) {
+                const uint8_t* row = nd + (size_t)y * w;
+                int x = 0;
+                while (x < w && !row[x]) ++x;
+                if (x == w) continue;
+                xa = std::min(xa, x);
+                x = w - 1;
+                while (!row[x]) --x;
+                xb = std::max(xb, x);
+            }
+            for (int x0 = xa; x0 <= xb; x0 += tx) list.push_back((uint32_t)x0 | ((uint32_t)y0 << 16));
+        }
+        off[f + 1] = (int32_t)list.size();
+    }
+    if (list.size() > c->tiles_cap[l]) return hipErrorInvalidValue;
+    uint32_t* dst = c->tiles + c->tiles_off[l];
+    if (!list.empty()) {
+        const hipError_t e = hipMemcpy(dst, list.data(), list.size() * 4, hipMemcpyHostToDevice);
+        if (e != hipSuccess) return e;
+    }
+    for (int f = 0; f <= 2 * h.n_pairs; ++f) h.lk_off[l][f] = off[f];
+    h.lk_tiles[l] = dst;
+    return hipSuccess;
 }
 
 }  // namespace
@@ -358,7 +459,7 @@ vs_status vs_create(const vs_rig* rig, const vs_params* prm, vs_ctx** out)
             const int p = f >> 1;
             n16 += ((h.lw[p][l] + LKW_TX - 1) / LKW_TX) * ((h.lh[p][l] + 15) / 16);
         }
-        set_lk_tiles(h, l, P.lk_radius == LK_R_MAX ? default_lk_P(n16) : 0);
+        set_lk_tiles(h, l, P.lk_radius == LK_R_MAX ? default_lk_P(n16, lk_resident_blocks()) : 0);
     }
     // ---- workspace arena ----
     size_t off = 0;
@@ -455,11 +556,11 @@ vs_status vs_create(const vs_rig* rig, const vs_params* prm, vs_ctx** out)
     I.n_covered = (int64_t)scan.n_covered;
     // flow-domain accounting (plan time, from the domain the kernels built)
     {
-        std::vector<uint8_t> nb;
         const int r = h.lk_radius;
         for (int p = 0; p < h.n_pairs; ++p)
             for (int l = 0; l < h.levels; ++l) {
                 const int w = h.lw[p][l], hh = h.lh[p][l];
+                std::vector<uint8_t>& nb = c->need_h[p][l];
                 nb.resize((size_t)w * hh);
                 if ((e = hipMemcpy(nb.data(), h.need[p][l], nb.size(), hipMemcpyDeviceToHost)) != hipSuccess)
                     return cleanup_dev(e, "flow domain copy");
@@ -476,7 +577,24 @@ vs_status vs_create(const vs_rig* rig, const vs_params* prm, vs_ctx** out)
                 I.flow_taps[p][l] = taps;
             }
     }
-    I.workspace_bytes = c->arena_bytes + cover_bytes + cand_bytes + code_bytes + scan_bytes + sizeof(DevPlan);
+    // flow tiles that follow the domain, every level
+    size_t tiles_n = 0;
+    for (int l = 0; l < h.levels; ++l) {
+        c->tiles_off[l] = tiles_n;
+        c->tiles_cap[l] = lk_tile_cap(h, l);
+        tiles_n += c->tiles_cap[l];
+    }
+    if (h.use_flow && tiles_n > 0) {
+        if (hipMalloc((void**)&c->tiles, tiles_n * 4) != hipSuccess) {
+            free_ctx(c);
+            return VS_E_NOMEM;
+        }
+        for (int l = 0; l < h.levels; ++l)
+            if ((e = band_tiles(c, l)) != hipSuccess) return cleanup_dev(e, "flow tiles");
+        if ((e = hipMemcpy(c->dp, &h, sizeof h, hipMemcpyHostToDevice)) != hipSuccess) return cleanup_dev(e, "hipMemcpy");
+    }
+    I.workspace_bytes = c->arena_bytes + cover_bytes + cand_bytes + code_bytes + scan_bytes + sizeof(DevPlan) +
+                        tiles_n * 4;
     I.state_bytes = sizeof(vs_color_state);
     *out = c;
     return VS_OK;
@@ -712,7 +830,7 @@ vs_status vs_set_flow_variant(vs_ctx* c, int level, int variant)
 {
     if (!c || level < 0 || level >= c->hp.levels) return VS_E_INVAL;
     if (c->sticky) return VS_E_DEVICE;
-    if (!(variant == 0 || variant == 1 || variant == 2 || variant == 4)) return VS_E_INVAL;
+    if (!(variant == 0 || ((variant & 7) >= 1 && (variant & 7) <= 4 && (variant & ~15) == 0))) return VS_E_INVAL;
     if (variant > 0 && c->hp.lk_radius != LK_R_MAX) return fail(c, VS_E_UNSUPPORTED, "9x9 kernel needs lk_radius 4");
     if (variant == 0 && c->hp.lk_qcap[level] > 0) {
         // the generic kernel finishes every pixel itself; nothing else changes
@@ -720,6 +838,7 @@ vs_status vs_set_flow_variant(vs_ctx* c, int level, int variant)
     if (variant > 0 && c->hp.lk_qcap[level] == 0) return fail(c, VS_E_UNSUPPORTED, "no deferral queue for this level");
     VS_CHECK(hipDeviceSynchronize(), "hipDeviceSynchronize");
     set_lk_tiles(c->hp, level, variant);
+    VS_CHECK(band_tiles(c, level), "flow tiles");
     VS_CHECK(hipMemcpy(c->dp, &c->hp, sizeof(DevPlan), hipMemcpyHostToDevice), "hipMemcpy plan");
     c->gen += 1;
     return VS_OK;
@@ -969,7 +1088,7 @@ vs_status vs_batch_create(vs_ctx* const ctxs[], int n, vs_batch** out)
                     n16 += ((h.lw[p][l] + LKW_TX - 1) / LKW_TX) * ((h.lh[p][l] + 15) / 16);
                 }
             }
-            variant = default_lk_P(n16);
+            variant = default_lk_P(n16, lk_resident_blocks());
         }
         vs_status st = set_variant_all(b, l, variant);
         if (st != VS_OK) {
@@ -1049,7 +1168,7 @@ vs_status vs_batch_run(vs_batch* b, const uint8_t* const* const frames[], uint8_
 // ---------------------------------------------------------------------------
 
 vs_status vs_batch_autotune(vs_batch* b, const uint8_t* const* const frames[], uint8_t* const panos[], int reps,
-                            float ms_out[VS_MAX_LEVELS][3], int32_t choice[VS_MAX_LEVELS])
+                            float ms_out[VS_MAX_LEVELS][VS_FLOW_VARIANTS], int32_t choice[VS_MAX_LEVELS])
 {
     if (!b || reps < 1 || !choice) return VS_E_INVAL;
     const int levels = b->ctx[0]->hp.levels;
@@ -1064,12 +1183,12 @@ vs_status vs_batch_autotune(vs_batch* b, const uint8_t* const* const frames[], u
     }
     hipEvent_t e0, e1;
     if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) return VS_E_DEVICE;
-    const int variants[3] = {1, 2, 4};
+    const int variants[VS_FLOW_VARIANTS] = {1, 2, 3, 4, 9, 10, 11, 12};
     vs_status st = VS_OK;
     for (int l = 0; l < levels && st == VS_OK; ++l) {
         float best = 1e30f;
         int best_v = b->ctx[0]->hp.lk_P[l];
-        for (int vi = 0; vi < 3 && st == VS_OK; ++vi) {
+        for (int vi = 0; vi < VS_FLOW_VARIANTS && st == VS_OK; ++vi) {
             st = set_variant_all(b, l, variants[vi]);
             if (st == VS_OK) st = capture(b);
             if (st != VS_OK) break;
@@ -1145,7 +1264,7 @@ bool flow_plan(int w, int h, const vs_params& P, DevPlan& d, FlowLayout& L)
             d.pyr_off[l][fl + 1] = d.pyr_off[l][fl] + d.pyr_tx[l][fl] * ((d.lh[0][l] + PYR_TY - 1) / PYR_TY);
         }
         const int n16 = 2 * ((d.lw[0][l] + LKW_TX - 1) / LKW_TX) * ((d.lh[0][l] + 15) / 16);
-        set_lk_tiles(d, l, P.lk_radius == LK_R_MAX ? default_lk_P(n16) : 0);
+        set_lk_tiles(d, l, P.lk_radius == LK_R_MAX ? default_lk_P(n16, lk_resident_blocks()) : 0);
     }
     size_t off = 0;
     for (int l = 0; l < d.levels; ++l) {

@@ -80,6 +80,10 @@ struct DevPlan {
     int32_t pyrf_ty;                                               // their height: 16, or 8 for small strips
     int32_t lk_off[MAXL][2 * MAXP + 1], lk_tx[MAXL][2 * MAXP];     // field f = 2 p + dir
     int32_t lk_P[MAXL];               // 0: generic kernel (16 x 16 tiles); 1, 2, 4: 9x9 kernel, P px per thread
+    // flow tiles of a level as a list: tile b (fields back to back, from
+    // lk_off) has its origin at x0 = lk_tiles[l][b] & 0xffff, y0 = lk_tiles[l][b] >> 16;
+    // null: the box grid, lk_tx tiles per row
+    const uint32_t* lk_tiles[MAXL];
     int32_t blend_tx, blend_ty, cover_words;
     // learned surrogate (VS_FLOW_PLAIN: not used)
     int32_t flow_mode;

@@ -33,8 +33,10 @@ hipError_t epe_loss(const float* pred, const float* label, uint16_t* dZ, float* 
 hipError_t adam(float* w, float* m, float* v, const float* g, uint16_t* w_bf16, long n, float lr, float b1, float b2,
                 float eps, int step, hipStream_t s);
 hipError_t to_bf16(const float* a, uint16_t* b, long n, hipStream_t s);
-hipError_t mfma_probe(const uint16_t* a, const uint16_t* b, float* out, hipStream_t s);
-hipError_t mfma_probe_k32(const uint16_t* a, const uint16_t* b, float* out, hipStream_t s);
+hipError_t sum_blocks(const float* part, int n, float* out, hipStream_t s);
+hipError_t pool_flow(const float* flow, int w, int h, int f, float* out, hipStream_t s);
+// weight-gradient scratch for any image table of at most npix pixels in nimg images
+size_t wgrad_scratch_bound(long npix, int nimg, int cin, int cout);
 
 }  // namespace nn
 }  // namespace vs

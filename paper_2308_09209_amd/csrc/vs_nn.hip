@@ -379,33 +379,41 @@ __global__ __launch_bounds__(256) void k_to_bf16(const float* __restrict__ a, ui
     if (j < n) b[j] = f2bf(a[j]);
 }
 
-// One MFMA on fixed fragments: out[l][i] = D fragment of lane l for
-// A[m][k] = a[m * 16 + k], B[k][n] = b[k * 16 + n] (a lane-layout check).
-__global__ void k_mfma_probe(const uint16_t* __restrict__ a, const uint16_t* __restrict__ b, float* __restrict__ out)
+// Sum of n per-block partial sums into one value (one block, fixed order:
+// each thread adds a strided subset in index order, then a fixed tree).
+__global__ __launch_bounds__(256) void k_sum_blocks(const float* __restrict__ part, int n, float* __restrict__ out)
 {
-    const int l = threadIdx.x, m = l & 15, kg = l >> 4;
-    bf16x4 af, bf;
-    for (int i = 0; i < 4; ++i) {
-        af[i] = (short)a[m * 16 + kg * 4 + i];
-        bf[i] = (short)b[(kg * 4 + i) * 16 + m];
+    __shared__ float s_red[256];
+    float acc = 0.0f;
+    for (int i = threadIdx.x; i < n; i += 256) acc += part[i];
+    s_red[threadIdx.x] = acc;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if ((int)threadIdx.x < o) s_red[threadIdx.x] += s_red[threadIdx.x + o];
+        __syncthreads();
     }
-    f32x4 d = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(af, bf, f32x4{0.0f, 0.0f, 0.0f, 0.0f}, 0, 0, 0);
-    for (int i = 0; i < 4; ++i) out[l * 4 + i] = d[i];
+    if (threadIdx.x == 0) *out = s_red[0];
 }
 
-// the same for v_mfma_f32_16x16x32_bf16: a[16][32], b[32][16]
-__global__ void k_mfma_probe_k32(const uint16_t* __restrict__ a, const uint16_t* __restrict__ b,
-                                 float* __restrict__ out)
+// Average pooling of a flow field by f x f blocks (the last row and column of
+// blocks may be partial: the mean over the pixels they hold), divided by f
+// so the result is in pooled-grid pixels: training labels of a coarser level.
+__global__ __launch_bounds__(256) void k_pool_flow(const float* __restrict__ flow, int w, int h, int f,
+                                                   float* __restrict__ out, int wo, int ho)
 {
-    const int l = threadIdx.x, m = l & 15, kg = l >> 4;
-    uint16_t av[8], bv[8];
-    for (int i = 0; i < 8; ++i) {
-        av[i] = a[m * 32 + kg * 8 + i];
-        bv[i] = b[(kg * 8 + i) * 16 + m];
-    }
-    const bf16x8 af = __builtin_bit_cast(bf16x8, av), bf = __builtin_bit_cast(bf16x8, bv);
-    f32x4 d = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af, bf, f32x4{0.0f, 0.0f, 0.0f, 0.0f}, 0, 0, 0);
-    for (int i = 0; i < 4; ++i) out[l * 4 + i] = d[i];
+    const int j = blockIdx.x * 256 + threadIdx.x;
+    if (j >= wo * ho) return;
+    const int X = j % wo, Y = j / wo;
+    const int x1 = min(w, (X + 1) * f), y1 = min(h, (Y + 1) * f);
+    float sx = 0.0f, sy = 0.0f;
+    for (int y = Y * f; y < y1; ++y)
+        for (int x = X * f; x < x1; ++x) {
+            sx += flow[((long)y * w + x) * 2];
+            sy += flow[((long)y * w + x) * 2 + 1];
+        }
+    const float n = (float)((x1 - X * f) * (y1 - Y * f));
+    out[(long)j * 2] = sx / n / (float)f;
+    out[(long)j * 2 + 1] = sy / n / (float)f;
 }
 
 // ---------------------------------------------------------------------------
@@ -531,16 +539,22 @@ hipError_t to_bf16(const float* a, uint16_t* b, long n, hipStream_t s)
     return hipGetLastError();
 }
 
-hipError_t mfma_probe(const uint16_t* a, const uint16_t* b, float* out, hipStream_t s)
+hipError_t sum_blocks(const float* part, int n, float* out, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_mfma_probe, dim3(1), dim3(64), 0, s, a, b, out);
+    hipLaunchKernelGGL(k_sum_blocks, dim3(1), dim3(256), 0, s, part, n, out);
     return hipGetLastError();
 }
 
-hipError_t mfma_probe_k32(const uint16_t* a, const uint16_t* b, float* out, hipStream_t s)
+hipError_t pool_flow(const float* flow, int w, int h, int f, float* out, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_mfma_probe_k32, dim3(1), dim3(64), 0, s, a, b, out);
+    const int wo = (w + f - 1) / f, ho = (h + f - 1) / f;
+    hipLaunchKernelGGL(k_pool_flow, dim3((unsigned)((wo * ho + 255) / 256)), dim3(256), 0, s, flow, w, h, f, out, wo, ho);
     return hipGetLastError();
+}
+
+size_t wgrad_scratch_bound(long npix, int nimg, int cin, int cout)
+{
+    return ((size_t)(npix + WG_PIX - 1) / WG_PIX + (size_t)nimg) * (size_t)(cout * 9 * cin + cout) * sizeof(float);
 }
 
 }  // namespace nn

@@ -105,16 +105,10 @@ vs_status vs_nn_to_bf16(const float* a, uint16_t* b, int64_t n, void* stream)
     return st(nn::to_bf16(a, b, (long)n, (hipStream_t)stream));
 }
 
-vs_status vs_nn_mfma_probe(const uint16_t* a, const uint16_t* b, float* out, void* stream)
+vs_status vs_nn_pool_flow(const float* flow, int w, int h, int factor, float* out, void* stream)
 {
-    if (!a || !b || !out) return VS_E_INVAL;
-    return st(nn::mfma_probe(a, b, out, (hipStream_t)stream));
-}
-
-vs_status vs_nn_mfma_probe_k32(const uint16_t* a, const uint16_t* b, float* out, void* stream)
-{
-    if (!a || !b || !out) return VS_E_INVAL;
-    return st(nn::mfma_probe_k32(a, b, out, (hipStream_t)stream));
+    if (!flow || !out || w < 1 || h < 1 || factor < 1 || factor > 64) return VS_E_INVAL;
+    return st(nn::pool_flow(flow, w, h, factor, out, (hipStream_t)stream));
 }
 
 }  // extern "C"

@@ -11,15 +11,13 @@ Network: five 3x3 layers, channels 16 -> 32 -> 32 -> 32 -> 32 -> 16, leaky
 ReLU (slope 0.1) after the first four; the input carries the two normalised
 luma images in channels 0-1 (the other channels are 0) and the output's
 channels 0-1 are the flow in level-2 pixels.  Loss: mean end-point error.
-Optimiser: Adam on FP32 master weights.
+Optimiser: Adam on FP32 master weights.  The parameters, optimiser state and
+workspaces are the library's network object (vs_nn_* in include/vstitch.h).
 """
 from __future__ import annotations
 
 import ctypes as C
-import math
-import struct
 
-import numpy as np
 import torch
 
 from . import vstitch as V
@@ -27,8 +25,6 @@ from . import vstitch as V
 LAYERS = ((16, 32), (32, 32), (32, 32), (32, 32), (32, 16))
 ALPHA = 0.1
 LEVEL = 2
-MAGIC = b"VSNN"
-VERSION = 1
 
 
 def _p(t):
@@ -40,117 +36,81 @@ def _s():
 
 
 class Net:
-    def __init__(self, seed: int = 0, device: str = "cuda"):
+    """The network through the library's vs_nn object: parameters, Adam state
+    and training workspaces live on the device and every step is a library
+    call; this class only marshals arguments."""
+
+    def __init__(self, seed: int = 0, device: str = "cuda", max_pixels: int = 1 << 19):
         self.device = device
-        g = torch.Generator().manual_seed(seed)
-        self.w, self.b = [], []
-        for li, (ci, co) in enumerate(LAYERS):
-            fan = 9 * (2 if li == 0 else ci)
-            std = math.sqrt(2.0 / fan) * (0.1 if li == len(LAYERS) - 1 else 1.0)
-            w = torch.randn(co, 9, ci, generator=g) * std
-            if li == 0:
-                w[:, :, 2:] = 0.0
-            self.w.append(w.to(device).contiguous())
-            self.b.append(torch.zeros(co).to(device))
-        self.params = [t for pair in zip(self.w, self.b) for t in pair]
-        self.m = [torch.zeros_like(t) for t in self.params]
-        self.v = [torch.zeros_like(t) for t in self.params]
-        self.step_n = 0
-        self.w16 = [torch.empty(t.shape, dtype=torch.int16, device=device) for t in self.w]
-        self.wf16 = [torch.empty((ci, 9, co), dtype=torch.int16, device=device) for (ci, co) in LAYERS]
-        self.refresh()
+        self.max_pixels = max_pixels
+        spec = V.nn_spec(LAYERS, in_live=2, alpha=ALPHA, max_pixels=max_pixels)
+        h = C.c_void_p()
+        V.check(V.lib().vs_nn_create(C.byref(spec), seed, C.byref(h)), "vs_nn_create")
+        self.h = h
+        self.loss_sum = torch.zeros((), dtype=torch.float32, device=device)
 
-    def refresh(self):
-        """BF16 copies of the master weights and their flipped transposes."""
-        for (ci, co), w, w16, wf in zip(LAYERS, self.w, self.w16, self.wf16):
-            V.check(V.lib().vs_nn_to_bf16(_p(w), _p(w16), w.numel(), _s()), "to_bf16")
-            V.check(V.lib().vs_nn_flip_weights(_p(w16), _p(wf), ci, co, _s()), "flip")
+    def close(self):
+        if getattr(self, "h", None):
+            V.lib().vs_nn_destroy(self.h)
+            self.h = None
 
-    # ---- forward / backward ------------------------------------------------
-    def forward(self, x16, imgs):
-        """x16: int16 [P, 16] packed input; returns (activations, FP32 prediction [P, 16])"""
-        P = x16.shape[0]
-        acts = [x16]
-        h = x16
-        for li, (ci, co) in enumerate(LAYERS[:-1]):
-            out = torch.empty((P, co), dtype=torch.int16, device=self.device)
-            V.check(V.lib().vs_nn_conv3x3(_p(h), ci, _p(self.w16[li]), _p(self.b[li]), _p(out), co,
-                                          C.byref(imgs), V.CONV_LRELU, ALPHA, _s()), "conv")
-            acts.append(out)
-            h = out
-        ci, co = LAYERS[-1]
-        pred = torch.empty((P, co), dtype=torch.float32, device=self.device)
-        V.check(V.lib().vs_nn_conv3x3(_p(h), ci, _p(self.w16[-1]), _p(self.b[-1]), _p(pred), co,
-                                      C.byref(imgs), V.CONV_F32, ALPHA, _s()), "conv")
-        return acts, pred
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:  # interpreter shutdown
+            pass
 
-    def backward(self, acts, dz, imgs):
-        """dz: int16 [P, 16] gradient of the loss at the output; returns FP32 grads
-        in the order of self.params"""
-        grads = [None] * len(self.params)
-        P = dz.shape[0]
-        for li in range(len(LAYERS) - 1, -1, -1):
-            ci, co = LAYERS[li]
-            x = acts[li]
-            nbytes = V.lib().vs_nn_wgrad_scratch_bytes(ci, co, C.byref(imgs))
-            scratch = torch.empty(nbytes // 4 + 1, dtype=torch.float32, device=self.device)
-            dwb = torch.empty(co * 9 * ci + co, dtype=torch.float32, device=self.device)
-            V.check(V.lib().vs_nn_conv3x3_wgrad(_p(x), ci, _p(dz), co, C.byref(imgs), _p(scratch),
-                                                nbytes, _p(dwb), _s()), "wgrad")
-            grads[2 * li] = dwb[:co * 9 * ci].view(co, 9, ci)
-            grads[2 * li + 1] = dwb[co * 9 * ci:]
-            if li == 0:
-                break
-            dh = torch.empty((P, ci), dtype=torch.int16, device=self.device)
-            V.check(V.lib().vs_nn_conv3x3(_p(dz), co, _p(self.wf16[li]), None, _p(dh), ci, C.byref(imgs),
-                                          V.CONV_LINEAR, ALPHA, _s()), "conv bwd data")
-            dzp = torch.empty_like(dh)
-            V.check(V.lib().vs_nn_lrelu_bwd(_p(dh), _p(acts[li]), _p(dzp), dh.numel(), ALPHA, _s()), "lrelu bwd")
-            dz = dzp
-        return grads
+    def forward(self, x16, imgs, pred=None):
+        """x16: int16 [P, 16] packed input (kept by the caller until backward);
+        returns the FP32 prediction [P, 16]"""
+        if pred is None:
+            pred = torch.empty((x16.shape[0], 16), dtype=torch.float32, device=self.device)
+        V.check(V.lib().vs_nn_forward(self.h, _p(x16), C.byref(imgs), _p(pred), _s()), "vs_nn_forward")
+        return pred
 
-    def adam(self, grads, lr=1e-3, b1=0.9, b2=0.999, eps=1e-8):
-        self.step_n += 1
-        for t, m, v, g in zip(self.params, self.m, self.v, grads):
-            g = g.contiguous()   # bound to a name: the pointer must outlive the launch
-            V.check(V.lib().vs_nn_adam(_p(t), _p(m), _p(v), _p(g), None, t.numel(), lr, b1, b2,
-                                       eps, self.step_n, _s()), "adam")
-        self.refresh()
+    def backward(self, label):
+        """gradients of the mean EPE of the last forward against label [P, 2];
+        returns the device sum of the pixel errors (a 0-d tensor, valid after
+        the stream reaches it)"""
+        V.check(V.lib().vs_nn_backward(self.h, _p(label), _p(self.loss_sum), _s()), "vs_nn_backward")
+        return self.loss_sum
+
+    def loss(self, label, out=None):
+        """device sum of the last forward's pixel errors against label"""
+        out = self.loss_sum if out is None else out
+        V.check(V.lib().vs_nn_loss(self.h, _p(label), _p(out), _s()), "vs_nn_loss")
+        return out
+
+    def adam(self, lr=1e-3, b1=0.9, b2=0.999, eps=1e-8):
+        V.check(V.lib().vs_nn_adam_step(self.h, lr, b1, b2, eps, _s()), "vs_nn_adam_step")
+
+    def params(self):
+        """(FP32 parameters, gradients of the last backward): device copies,
+        layer by layer w [cout][9][cin] then b [cout]"""
+        n = C.c_size_t()
+        V.check(V.lib().vs_nn_params(self.h, None, None, C.byref(n), None), "vs_nn_params")
+        p = torch.empty(n.value, dtype=torch.float32, device=self.device)
+        g = torch.empty_like(p)
+        V.check(V.lib().vs_nn_params(self.h, _p(p), _p(g), None, _s()), "vs_nn_params")
+        return p, g
 
     # ---- persistence ---------------------------------------------------------
     def blob(self) -> bytes:
-        out = [MAGIC, struct.pack("<IIf", VERSION, len(LAYERS), ALPHA)]
-        for (ci, co) in LAYERS:
-            out.append(struct.pack("<II", ci, co))
-        for w16, b in zip(self.w16, self.b):
-            out.append(w16.cpu().numpy().astype(np.int16).tobytes())
-            out.append(b.cpu().numpy().astype(np.float32).tobytes())
-        return b"".join(out)
+        n = C.c_size_t()
+        V.check(V.lib().vs_nn_save(self.h, None, 0, C.byref(n)), "vs_nn_save")
+        buf = C.create_string_buffer(n.value)
+        V.check(V.lib().vs_nn_save(self.h, buf, n.value, C.byref(n)), "vs_nn_save")
+        return buf.raw[:n.value]
 
     def save(self, path):
         with open(path, "wb") as f:
             f.write(self.blob())
 
     @classmethod
-    def from_blob(cls, data: bytes, device="cuda"):
-        assert data[:4] == MAGIC, "not a surrogate weight file"
-        version, nl, alpha = struct.unpack_from("<IIf", data, 4)
-        assert version == VERSION and nl == len(LAYERS) and abs(alpha - ALPHA) < 1e-7
-        off = 16
-        for (ci, co) in LAYERS:
-            assert struct.unpack_from("<II", data, off) == (ci, co)
-            off += 8
-        net = cls(device=device)
-        for li, (ci, co) in enumerate(LAYERS):
-            n = co * 9 * ci
-            w16 = np.frombuffer(data, np.int16, n, off).reshape(co, 9, ci)
-            off += 2 * n
-            b = np.frombuffer(data, np.float32, co, off)
-            off += 4 * co
-            w = (w16.astype(np.uint16).astype(np.uint32) << 16).view(np.float32)
-            net.w[li].copy_(torch.from_numpy(w.copy()))
-            net.b[li].copy_(torch.from_numpy(b.copy()))
-        net.refresh()
+    def from_blob(cls, data: bytes, device="cuda", max_pixels: int = 1 << 19):
+        net = cls(device=device, max_pixels=max_pixels)
+        buf = C.create_string_buffer(bytes(data), len(data))
+        V.check(V.lib().vs_nn_load(net.h, buf, len(data)), "vs_nn_load: not a weight file of this network")
         return net
 
 

@@ -69,6 +69,13 @@ def synth_pairs(n, H, W, max_disp, gen, device="cuda"):
     return torch.stack(out_t), torch.stack(out_m)
 
 
+def pool_label(flow, w, h, f):
+    """level-0 flow [h][w][2] -> its f x f block means in level pixels (vs_nn_pool_flow)"""
+    out = torch.empty(((h + f - 1) // f, (w + f - 1) // f, 2), dtype=torch.float32, device=flow.device)
+    V.check(V.lib().vs_nn_pool_flow(S._p(flow), w, h, f, S._p(out), S._s()), "vs_nn_pool_flow")
+    return out
+
+
 def build_dataset(n_pairs, H=1080, W=256, max_disp=8.0, seed=0, chunk=64, log=print):
     """(level-2 template, level-2 moving, level-2 label, level-0 label) tensors"""
     gen = torch.Generator().manual_seed(seed)
@@ -83,8 +90,7 @@ def build_dataset(n_pairs, H=1080, W=256, max_disp=8.0, seed=0, chunk=64, log=pr
             yt2, ym2 = pf.level(S.LEVEL)
             t2l.append(yt2)
             m2l.append(ym2)
-            f2 = F.avg_pool2d(ftm.permute(2, 0, 1)[None], 4, 4, ceil_mode=True)[0].permute(1, 2, 0) / 4.0
-            lab2.append(f2.contiguous())
+            lab2.append(pool_label(ftm, W, H, 1 << S.LEVEL))
             if len(lab0) < 64:
                 lab0.append(ftm)
         if start == 0 or (start // chunk) % 20 == 0:
@@ -105,12 +111,14 @@ def evaluate(net, data, first, last):
     T2, M2, L2, _ = data
     h2, w2 = T2.shape[1], T2.shape[2]
     vimgs = V.nn_images([(h2, w2)])
-    tot = torch.zeros((), dtype=torch.float64, device=T2.device)
+    sums = torch.zeros(max(1, last - first), dtype=torch.float32, device=T2.device)
     for i in range(first, last):
-        _, pred = net.forward(S.pack(T2[i:i + 1], M2[i:i + 1]), vimgs)
-        d = pred[:, :2] - L2[i].reshape(-1, 2)
-        tot += d.norm(dim=1).mean().double()
-    return float(tot) / max(1, last - first)
+        x = S.pack(T2[i:i + 1], M2[i:i + 1])
+        net.forward(x, vimgs)
+        net.loss(L2[i].reshape(-1, 2), out=sums[i - first])
+    # per-pair mean errors (library sums over each pair's pixels), averaged on the host
+    per_pair = sums.cpu().double().numpy() / (h2 * w2)
+    return float(per_pair[:last - first].mean()) if last > first else 0.0
 
 
 def train(net, data, steps, batch=16, lr=2e-3, log=print, val=256):
@@ -124,23 +132,22 @@ def train(net, data, steps, batch=16, lr=2e-3, log=print, val=256):
     gen = torch.Generator(device="cuda").manual_seed(1)
     t0 = time.time()
     hist = []
-    run = torch.zeros((), dtype=torch.float64, device=T2.device)
+    interval = 100
+    sums = torch.zeros(interval, dtype=torch.float32, device=T2.device)
     run_n = 0
     for step in range(1, steps + 1):
         idx = torch.randint(0, n_tr, (batch,), generator=gen, device="cuda")
         x = S.pack(T2[idx], M2[idx])
         lab = L2[idx].reshape(-1, 2).contiguous()
-        acts, pred = net.forward(x, imgs)
-        bl, dz = S.loss_and_grad(pred, lab)
-        grads = net.backward(acts, dz, imgs)
+        net.forward(x, imgs)
+        sums[run_n].copy_(net.backward(lab))
         cur_lr = lr * 0.5 * (1 + math.cos(math.pi * step / steps))
-        net.adam(grads, lr=cur_lr)
-        run += bl.sum().double() / lab.shape[0]
+        net.adam(lr=cur_lr)
         run_n += 1
-        if step % 100 == 0 or step == steps:
-            loss = float(run) / run_n
+        if step % interval == 0 or step == steps:
+            # mean training error of the interval's batches (library sums per batch)
+            loss = float(sums[:run_n].cpu().double().numpy().mean()) / lab.shape[0]
             hist.append((step, loss))
-            run.zero_()
             run_n = 0
             log(f"# step {step}/{steps} train EPE(level 2) {loss:.4f} px ({time.time() - t0:.1f} s)")
     val_epe = evaluate(net, data, n_tr, n)

@@ -30,6 +30,8 @@ TAP = dict(strip=1, mask=2, hist=3, lut=4, mom=5, mpair=6, mk=7, flags=8, pyr=9,
            pano_pre=11, pano_hist=12, bal_lut=13, quant=14, mbar=15, cover=16, need=17,
            deferred=18, surr_pred=19, fb=20, surr_ok=21)
 FLOW_PLAIN, FLOW_SURROGATE, FLOW_SURROGATE_FALLBACK = 0, 1, 2
+FLOW_VARIANTS = 8   # 9x9 flow-kernel variants the autotuner measures: 1, 2, 3, 4, 9, 10, 11, 12
+FLOW_VARIANT_CODES = (1, 2, 3, 4, 9, 10, 11, 12)
 
 # every symbol include/vstitch.h declares
 EXPORTS = ["vs_abi_version", "vs_status_str", "vs_default_params", "vs_compose_homographies",
@@ -40,7 +42,8 @@ EXPORTS = ["vs_abi_version", "vs_status_str", "vs_default_params", "vs_compose_h
            "vs_batch_destroy", "vs_batch_last_error", "vs_batch_autotune",
            "vs_nn_conv3x3", "vs_nn_wgrad_scratch_bytes", "vs_nn_conv3x3_wgrad", "vs_nn_flip_weights",
            "vs_nn_lrelu_bwd", "vs_nn_pack_pair", "vs_nn_epe_loss", "vs_nn_adam", "vs_nn_to_bf16",
-           "vs_nn_mfma_probe", "vs_nn_mfma_probe_k32", "vs_flow_create", "vs_flow_run", "vs_flow_destroy", "vs_flow_level",
+           "vs_nn_pool_flow", "vs_nn_create", "vs_nn_destroy", "vs_nn_forward", "vs_nn_loss", "vs_nn_backward",
+           "vs_nn_adam_step", "vs_nn_params", "vs_nn_save", "vs_nn_load", "vs_flow_create", "vs_flow_run", "vs_flow_destroy", "vs_flow_level",
            "vs_flow_run_noalloc"]
 
 
@@ -101,6 +104,23 @@ def nn_images(sizes):
     return t
 
 
+NN_MAX_LAYERS = 8
+
+
+class NNSpec(C.Structure):
+    _fields_ = [("n_layers", C.c_int32), ("cin", C.c_int32 * NN_MAX_LAYERS), ("cout", C.c_int32 * NN_MAX_LAYERS),
+                ("in_live", C.c_int32), ("alpha", C.c_float), ("max_pixels", C.c_int64)]
+
+
+def nn_spec(layers, in_live, alpha, max_pixels) -> NNSpec:
+    sp = NNSpec()
+    sp.n_layers = len(layers)
+    for i, (ci, co) in enumerate(layers):
+        sp.cin[i], sp.cout[i] = ci, co
+    sp.in_live, sp.alpha, sp.max_pixels = in_live, alpha, max_pixels
+    return sp
+
+
 class FrameInfo(C.Structure):
     _fields_ = [("Mk", (C.c_float * 9) * MAX_CAMS), ("Mpair", (C.c_double * 9) * MAX_PAIRS),
                 ("flags", C.c_int32 * MAX_PAIRS), ("quant", (C.c_int32 * 2) * 3),
@@ -159,8 +179,16 @@ def lib():
         L.vs_nn_epe_loss.argtypes = [vp, vp, vp, vp, i64, vp]
         L.vs_nn_adam.argtypes = [vp, vp, vp, vp, vp, i64, f32, f32, f32, f32, i32, vp]
         L.vs_nn_to_bf16.argtypes = [vp, vp, i64, vp]
-        L.vs_nn_mfma_probe.argtypes = [vp, vp, vp, vp]
-        L.vs_nn_mfma_probe_k32.argtypes = [vp, vp, vp, vp]
+        L.vs_nn_pool_flow.argtypes = [vp, i32, i32, i32, vp, vp]
+        L.vs_nn_create.argtypes = [C.POINTER(NNSpec), C.c_uint64, C.POINTER(C.c_void_p)]
+        L.vs_nn_destroy.argtypes = [vp]
+        L.vs_nn_forward.argtypes = [vp, vp, imgs, vp, vp]
+        L.vs_nn_loss.argtypes = [vp, vp, vp, vp]
+        L.vs_nn_backward.argtypes = [vp, vp, vp, vp]
+        L.vs_nn_adam_step.argtypes = [vp, f32, f32, f32, f32, vp]
+        L.vs_nn_params.argtypes = [vp, vp, vp, C.POINTER(C.c_size_t), vp]
+        L.vs_nn_save.argtypes = [vp, vp, C.c_size_t, C.POINTER(C.c_size_t)]
+        L.vs_nn_load.argtypes = [vp, vp, C.c_size_t]
         L.vs_flow_create.argtypes = [i32, i32, C.POINTER(Params), C.POINTER(C.c_void_p)]
         L.vs_flow_run.argtypes = [vp, vp, vp, vp, vp, vp]
         L.vs_flow_destroy.argtypes = [vp]
@@ -448,7 +476,7 @@ class Batch:
 
     def autotune(self, frames, panos, reps=5):
         fr_arr, pano_arr = self._ptrs(frames, panos)
-        ms = np.zeros((MAX_LEVELS, 3), np.float32)
+        ms = np.zeros((MAX_LEVELS, FLOW_VARIANTS), np.float32)
         choice = np.zeros(MAX_LEVELS, np.int32)
         st = lib().vs_batch_autotune(self.h, fr_arr, pano_arr, reps, ms.ctypes.data_as(C.c_void_p),
                                      choice.ctypes.data_as(C.c_void_p))

@@ -1,7 +1,8 @@
 """GPU: the learned surrogate's matrix-core kernels against the FP64 oracle on
 identical BF16 operands (forward, data gradient, weight gradient), its loss
-and optimiser kernels, the plain-flow label context, and a training smoke
-test."""
+and optimiser kernels, the network object (vs_nn_*: forward, backward, Adam,
+save / load) against the oracle's FP64 training step, the label pooling, the
+plain-flow label context, and a training smoke test."""
 import ctypes as C
 import sys
 
@@ -50,38 +51,6 @@ def split_images(flat, c):
         out.append(flat[off:off + h * w].reshape(1, h, w, c))
         off += h * w
     return out
-
-
-def test_mfma_fragment_layout():
-    rng = np.random.default_rng(0)
-    a = to_bf16(rng.normal(size=(16, 16)))
-    b = to_bf16(rng.normal(size=(16, 16)))
-    out = torch.zeros(256, dtype=torch.float32, device="cuda:0")
-    da, db = dev(a), dev(b)          # held until the kernel has run
-    V.check(V.lib().vs_nn_mfma_probe(C.c_void_p(da.data_ptr()), C.c_void_p(db.data_ptr()),
-                                     C.c_void_p(out.data_ptr()), None), "probe")
-    torch.cuda.synchronize()
-    got = out.cpu().numpy().reshape(64, 4)
-    D = from_bf16(a) @ from_bf16(b)
-    for l in range(64):
-        for i in range(4):
-            assert abs(got[l, i] - D[4 * (l // 16) + i, l % 16]) <= 1e-5 * (1 + abs(D[4 * (l // 16) + i, l % 16]))
-
-
-def test_mfma_k32_fragment_layout():
-    rng = np.random.default_rng(1)
-    a = to_bf16(rng.normal(size=(16, 32)))
-    b = to_bf16(rng.normal(size=(32, 16)))
-    out = torch.zeros(256, dtype=torch.float32, device="cuda:0")
-    da, db = dev(a), dev(b)
-    V.check(V.lib().vs_nn_mfma_probe_k32(C.c_void_p(da.data_ptr()), C.c_void_p(db.data_ptr()),
-                                         C.c_void_p(out.data_ptr()), None), "probe k32")
-    torch.cuda.synchronize()
-    got = out.cpu().numpy().reshape(64, 4)
-    D = from_bf16(a) @ from_bf16(b)
-    for l in range(64):
-        for i in range(4):
-            assert abs(got[l, i] - D[4 * (l // 16) + i, l % 16]) <= 1e-5 * (1 + abs(D[4 * (l // 16) + i, l % 16]))
 
 
 def conv_call(x, cin, w, b, y, cout, imgs, mode):
@@ -273,6 +242,142 @@ def test_training_reduces_the_loss():
         f"{hist[0][1]:.4f} -> {hist[-1][1]:.4f}")
     assert after < 0.8 * before
     # weights survive a save / load round trip bit for bit
-    net2 = S.Net.from_blob(net.blob())
-    for a, b in zip(net.w16, net2.w16):
-        assert torch.equal(a, b)
+    blob = net.blob()
+    net2 = S.Net.from_blob(blob)
+    assert net2.blob() == blob
+
+
+NET_LAYERS = ((16, 32), (32, 32), (32, 16))
+NET_SIZES = [(23, 41), (16, 16), (5, 70)]
+
+
+def _net_state(h):
+    """master parameters and gradients of network object h, FP64 per layer:
+    ([w], [b], [dw], [db])"""
+    n = C.c_size_t()
+    V.check(V.lib().vs_nn_params(h, None, None, C.byref(n), None), "params count")
+    tp = torch.empty(n.value, dtype=torch.float32, device="cuda:0")
+    tg = torch.empty_like(tp)
+    V.check(V.lib().vs_nn_params(h, C.c_void_p(tp.data_ptr()), C.c_void_p(tg.data_ptr()), None, None), "params")
+    torch.cuda.synchronize()
+    flat_p, flat_g = tp.cpu().numpy().astype(np.float64), tg.cpu().numpy().astype(np.float64)
+    ws, bs, dws, dbs, off = [], [], [], [], 0
+    for ci, co in NET_LAYERS:
+        nw = co * 9 * ci
+        ws.append(flat_p[off:off + nw].reshape(co, 9, ci))
+        dws.append(flat_g[off:off + nw].reshape(co, 9, ci))
+        bs.append(flat_p[off + nw:off + nw + co])
+        dbs.append(flat_g[off + nw:off + nw + co])
+        off += nw + co
+    assert off == n.value
+    return ws, bs, dws, dbs
+
+
+def _make_net(seed=3):
+    spec = V.nn_spec(NET_LAYERS, in_live=16, alpha=0.1, max_pixels=4096)
+    h = C.c_void_p()
+    V.check(V.lib().vs_nn_create(C.byref(spec), seed, C.byref(h)), "vs_nn_create")
+    return h
+
+
+def test_network_forward_backward_matches_oracle_step():
+    """One training step through the C ABI (vs_nn_forward + vs_nn_backward)
+    against the oracle's FP64 step on the same BF16 weights, FP32 biases and
+    inputs: prediction, loss and every layer's gradients.  The kernels keep
+    hidden activations and back-propagated gradients in BF16 (unit roundoff
+    2^-9), the oracle in FP64, so the bars are relative L2 errors a few such
+    roundings allow: 1e-2 on the prediction and the loss, 3e-2 on gradients."""
+    h = _make_net()
+    rng = np.random.default_rng(8)
+    P = sum(a * b for a, b in NET_SIZES)
+    x = to_bf16(rng.normal(size=(P, 16)))
+    lab = rng.normal(size=(P, 2)).astype(np.float32) * 0.3
+    imgs = V.nn_images(NET_SIZES)
+    xd, ld = dev(x), dev(lab)
+    pred = torch.empty((P, 16), dtype=torch.float32, device="cuda:0")
+    loss = torch.zeros((), dtype=torch.float32, device="cuda:0")
+    V.check(V.lib().vs_nn_forward(h, C.c_void_p(xd.data_ptr()), C.byref(imgs), C.c_void_p(pred.data_ptr()), None), "fwd")
+    V.check(V.lib().vs_nn_backward(h, C.c_void_p(ld.data_ptr()), C.c_void_p(loss.data_ptr()), None), "bwd")
+    torch.cuda.synchronize()
+    ws, bs, dws, dbs = _net_state(h)
+    wq = [from_bf16(to_bf16(w)).reshape(w.shape) for w in ws]   # the kernels multiply BF16 weights
+    r_loss, r_pred, r_dw, r_db = O.nn_train_step(wq, bs, from_bf16(x).reshape(P, 16), lab, NET_SIZES, 0.1)
+    e_pred = rel_l2(pred.cpu().numpy().astype(np.float64), r_pred)
+    e_loss = abs(float(loss.cpu()) / P - r_loss) / r_loss
+    say(f"[network step] rel L2 prediction {e_pred:.2e}, loss {e_loss:.2e}")
+    assert e_pred <= 1e-2 and e_loss <= 1e-2
+    for li in range(len(NET_LAYERS)):
+        e_w, e_b = rel_l2(dws[li], r_dw[li]), rel_l2(dbs[li], r_db[li])
+        say(f"  layer {li}: rel L2 weight gradient {e_w:.2e}, bias gradient {e_b:.2e}")
+        assert e_w <= 3e-2 and e_b <= 3e-2, li
+    V.lib().vs_nn_destroy(h)
+
+
+def test_network_adam_save_load():
+    """vs_nn_adam_step against Adam written out in numpy on the object's own
+    gradients; the weight file survives vs_nn_save / vs_nn_load byte for byte
+    and gives the same prediction bit for bit; a file of another layer list is
+    refused."""
+    h = _make_net(4)
+    rng = np.random.default_rng(9)
+    P = 16 * 16
+    imgs = V.nn_images([(16, 16)])
+    x = dev(to_bf16(rng.normal(size=(P, 16))))
+    lab = dev(rng.normal(size=(P, 2)).astype(np.float32))
+    m = v = None
+    for step in (1, 2):
+        V.check(V.lib().vs_nn_forward(h, C.c_void_p(x.data_ptr()), C.byref(imgs), None, None), "fwd")
+        V.check(V.lib().vs_nn_backward(h, C.c_void_p(lab.data_ptr()), None, None), "bwd")
+        torch.cuda.synchronize()
+        ws, bs, dws, dbs = _net_state(h)
+        p0 = np.concatenate([np.concatenate([w.ravel(), b]) for w, b in zip(ws, bs)])
+        g = np.concatenate([np.concatenate([w.ravel(), b]) for w, b in zip(dws, dbs)])
+        m = 0.1 * g if m is None else 0.9 * m + 0.1 * g
+        v = 0.001 * g ** 2 if v is None else 0.999 * v + 0.001 * g ** 2
+        want = p0 - 1e-2 * (m / (1 - 0.9 ** step)) / (np.sqrt(v / (1 - 0.999 ** step)) + 1e-8)
+        V.check(V.lib().vs_nn_adam_step(h, 1e-2, 0.9, 0.999, 1e-8, None), "adam")
+        torch.cuda.synchronize()
+        ws2, bs2, _, _ = _net_state(h)
+        got = np.concatenate([np.concatenate([w.ravel(), b]) for w, b in zip(ws2, bs2)])
+        np.testing.assert_allclose(got, want, rtol=1e-5, atol=1e-6)
+    n = C.c_size_t()
+    V.check(V.lib().vs_nn_save(h, None, 0, C.byref(n)), "size")
+    buf = C.create_string_buffer(n.value)
+    V.check(V.lib().vs_nn_save(h, buf, n.value, C.byref(n)), "save")
+    blob = buf.raw
+    h2 = _make_net(99)
+    V.check(V.lib().vs_nn_load(h2, blob, len(blob)), "load")
+    buf2 = C.create_string_buffer(n.value)
+    V.check(V.lib().vs_nn_save(h2, buf2, n.value, C.byref(n)), "save 2")
+    assert buf2.raw == blob
+    p1 = torch.empty((P, 16), dtype=torch.float32, device="cuda:0")
+    p2 = torch.empty_like(p1)
+    V.check(V.lib().vs_nn_forward(h, C.c_void_p(x.data_ptr()), C.byref(imgs), C.c_void_p(p1.data_ptr()), None), "f1")
+    V.check(V.lib().vs_nn_forward(h2, C.c_void_p(x.data_ptr()), C.byref(imgs), C.c_void_p(p2.data_ptr()), None), "f2")
+    torch.cuda.synchronize()
+    assert torch.equal(p1, p2)
+    # the surrogate's production network: another layer list, refused
+    prod = S.Net(seed=1, max_pixels=4096)
+    assert V.lib().vs_nn_load(h2, prod.blob(), len(prod.blob())) == -1
+    prod.close()
+    V.lib().vs_nn_destroy(h)
+    V.lib().vs_nn_destroy(h2)
+
+
+def test_pool_flow_block_means():
+    """vs_nn_pool_flow against block means written out in numpy (ragged last
+    block row and column) for factors 1, 3 and 4."""
+    rng = np.random.default_rng(10)
+    h, w = 37, 50
+    flow = rng.normal(size=(h, w, 2)).astype(np.float32) * 4
+    fd = dev(flow)
+    for f in (1, 3, 4):
+        ho, wo = -(-h // f), -(-w // f)
+        out = torch.empty((ho, wo, 2), dtype=torch.float32, device="cuda:0")
+        V.check(V.lib().vs_nn_pool_flow(C.c_void_p(fd.data_ptr()), w, h, f, C.c_void_p(out.data_ptr()), None), "pool")
+        torch.cuda.synchronize()
+        want = np.zeros((ho, wo, 2))
+        for Y in range(ho):
+            for X in range(wo):
+                want[Y, X] = flow[Y * f:(Y + 1) * f, X * f:(X + 1) * f].reshape(-1, 2).astype(np.float64).mean(0) / f
+        np.testing.assert_allclose(out.cpu().numpy(), want, rtol=1e-5, atol=1e-6)
