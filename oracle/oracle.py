@@ -47,7 +47,10 @@ class Params(C.Structure):
     _fields_ = [("color_window", C.c_int), ("ridge", C.c_double), ("min_pixels", C.c_int),
                 ("flow", C.c_int), ("lk_levels", C.c_int), ("lk_iters", C.c_int),
                 ("lk_radius", C.c_int), ("lk_lambda", C.c_float), ("balance", C.c_int),
-                ("lambda_pct", C.c_int)]
+                ("lambda_pct", C.c_int), ("readings", C.c_int)]
+
+
+READ_OVERLAP_ONLY, READ_LITERAL_EQ17, READ_NEAREST_CDF = 1, 2, 4
 
 
 class PlanInfo(C.Structure):
@@ -86,6 +89,7 @@ def lib():
         L.vso_get.argtypes = [C.c_void_p, C.c_int, C.c_int, C.c_int, C.c_void_p, C.c_size_t]
         L.vso_default_params.argtypes = [C.POINTER(Params)]
         L.vso_histspec_lut.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p]
+        L.vso_histspec_lut_nearest.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p]
         L.vso_solve_color.argtypes = [C.c_void_p, C.c_void_p, C.c_double, C.c_void_p]
         L.vso_quantiles.argtypes = [C.c_void_p, C.c_longlong, C.c_int, C.POINTER(C.c_int),
                                     C.POINTER(C.c_int)]
@@ -104,6 +108,8 @@ def lib():
         L.vso_luma.argtypes = [C.c_int, C.c_int, C.c_int]
         L.vso_chain_colour.argtypes = [C.c_void_p, C.c_int, C.c_void_p]
         L.vso_fuse_pixel.argtypes = [C.POINTER(View), C.POINTER(View), C.c_float, C.c_void_p, C.c_void_p,
+                                     C.c_void_p]
+        L.vso_fuse_pixel_literal.argtypes = [C.POINTER(View), C.POINTER(View), C.c_float, C.c_void_p, C.c_void_p,
                                      C.c_void_p]
         vp, i = C.c_void_p, C.c_int
         L.vso_conv3x3.argtypes = [vp, i, i, i, i, vp, vp, i, vp]
@@ -287,11 +293,11 @@ class Oracle:
 
 # ---- single steps --------------------------------------------------------
 
-def histspec_lut(Gi, Gj) -> np.ndarray:
+def histspec_lut(Gi, Gj, nearest=False) -> np.ndarray:
     Gi = np.ascontiguousarray(Gi, np.uint32)
     Gj = np.ascontiguousarray(Gj, np.uint32)
     out = np.zeros(256, np.uint8)
-    lib().vso_histspec_lut(_ptr(Gi), _ptr(Gj), _ptr(out))
+    (lib().vso_histspec_lut_nearest if nearest else lib().vso_histspec_lut)(_ptr(Gi), _ptr(Gj), _ptr(out))
     return out
 
 
@@ -388,8 +394,9 @@ def chain_colour(Mpair) -> np.ndarray:
     return out.reshape(n, 3, 3)
 
 
-def fuse_pixel(frame_j, hinv_j, M_j, X_j, frame_i, hinv_i, M_i, X_i, y, f_ij, f_ji) -> np.ndarray:
-    """Eqs. (16)-(18) at one canvas pixel covered by cameras j (left) and i (right)."""
+def fuse_pixel(frame_j, hinv_j, M_j, X_j, frame_i, hinv_i, M_i, X_i, y, f_ij, f_ji, literal=False) -> np.ndarray:
+    """Eqs. (16)-(18) at one canvas pixel covered by cameras j (left) and i
+    (right); literal: eq. (17) as printed."""
     keep = []
 
     def view(F, h, M, X):
@@ -405,7 +412,8 @@ def fuse_pixel(frame_j, hinv_j, M_j, X_j, frame_i, hinv_i, M_i, X_i, y, f_ij, f_
     fij = np.asarray(f_ij, np.float32)
     fji = np.asarray(f_ji, np.float32)
     out = np.zeros(3, np.uint8)
-    lib().vso_fuse_pixel(C.byref(vj), C.byref(vi), float(y), _ptr(fij), _ptr(fji), _ptr(out))
+    fn = lib().vso_fuse_pixel_literal if literal else lib().vso_fuse_pixel
+    fn(C.byref(vj), C.byref(vi), float(y), _ptr(fij), _ptr(fji), _ptr(out))
     return out
 
 

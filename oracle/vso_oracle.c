@@ -112,6 +112,7 @@ struct vso_ctx {
     moments mom[VSO_MAX_PAIRS];
     double Mpair[VSO_MAX_PAIRS][9];
     float Mk[VSO_MAX_CAMS][9];
+    float Mpf[VSO_MAX_PAIRS][9];   /* the pair matrices in FP32 (overlap-only reading) */
     int flags[VSO_MAX_PAIRS];
     float* pyr[VSO_MAX_PAIRS][2][VSO_MAX_LEVELS];
     uint8_t* need[VSO_MAX_PAIRS][VSO_MAX_LEVELS];
@@ -145,6 +146,7 @@ void vso_default_params(vso_params* p)
     p->lk_lambda = 256.0f;
     p->balance = 1;
     p->lambda_pct = 5;
+    p->readings = 0;
 }
 
 /* 3x3 product c = a b, each entry ((a_r0 b_0c + a_r1 b_1c) + a_r2 b_2c). */
@@ -436,6 +438,33 @@ void vso_histspec_lut(const uint32_t Gi[256], const uint32_t Gj[256], uint8_t lu
     }
 }
 
+/* Step 3 read with the nearest cumulative count (VSO_READ_NEAREST_CDF):
+ *   LUT(v) = the smallest w minimising |C_j(w) - C_i(v)|, by brute force. */
+void vso_histspec_lut_nearest(const uint32_t Gi[256], const uint32_t Gj[256], uint8_t lut[256])
+{
+    long long Ci[256], Cj[256];
+    long long si = 0, sj = 0;
+    for (int v = 0; v < 256; ++v) {
+        si += Gi[v];
+        sj += Gj[v];
+        Ci[v] = si;
+        Cj[v] = sj;
+    }
+    for (int v = 0; v < 256; ++v) {
+        int best = 0;
+        long long bd = -1;
+        for (int w = 0; w < 256; ++w) {
+            long long d = Cj[w] - Ci[v];
+            if (d < 0) d = -d;
+            if (bd < 0 || d < bd) {
+                bd = d;
+                best = w;
+            }
+        }
+        lut[v] = (uint8_t)best;
+    }
+}
+
 /* Eq. (1)/(3): M = [I_i^T I_i]^-1 I_i^T I_j with the 3D stacking of eq. (2)
  * entering as summed moments.  Solved as (A + eps I) M = B + eps I with
  * eps = ridge * trace(A) (a small pull toward the identity that keeps A = B
@@ -535,7 +564,12 @@ static void step_moments(vso_ctx* c)
 {
     const vso_plan_info* P = &c->plan;
     for (int p = 0; p < P->n_pairs; ++p) {
-        for (int ch = 0; ch < 3; ++ch) vso_histspec_lut(c->hist[p][1][ch], c->hist[p][0][ch], c->lut[p][ch]);
+        for (int ch = 0; ch < 3; ++ch) {
+            if (c->prm.readings & VSO_READ_NEAREST_CDF)
+                vso_histspec_lut_nearest(c->hist[p][1][ch], c->hist[p][0][ch], c->lut[p][ch]);
+            else
+                vso_histspec_lut(c->hist[p][1][ch], c->hist[p][0][ch], c->lut[p][ch]);
+        }
         moments m;
         memset(&m, 0, sizeof m);
         size_t N = (size_t)P->strip_w[p] * P->strip_h[p];
@@ -612,6 +646,13 @@ static void step_solve(vso_ctx* c)
     vso_chain_colour(&c->Mpair[0][0], P->n_cams, &Mk[0][0]);
     for (int k = 0; k < P->n_cams; ++k)
         for (int i = 0; i < 9; ++i) c->Mk[k][i] = (float)Mk[k][i];
+    /* eq. (4)'s text read literally: no whole-frame (composed) correction;
+     * each pair's own matrix applies to camera i inside that overlap */
+    for (int p = 0; p < P->n_pairs; ++p)
+        for (int i = 0; i < 9; ++i) c->Mpf[p][i] = (float)c->Mpair[p][i];
+    if (c->prm.readings & VSO_READ_OVERLAP_ONLY)
+        for (int k = 0; k < P->n_cams; ++k)
+            for (int i = 0; i < 9; ++i) c->Mk[k][i] = (i % 4 == 0) ? 1.0f : 0.0f;
 }
 
 /* ------------------------------------------------------------------------ */
@@ -841,13 +882,15 @@ static void step_pyramids(vso_ctx* c)
         int cams[2] = {P->pair_j[p], P->pair_i[p]};
         for (int s = 0; s < 2; ++s) {
             const float* M = c->Mk[cams[s]];
+            const int ovl = (c->prm.readings & VSO_READ_OVERLAP_ONLY) && s == 1;
             float* Y = c->pyr[p][s][0];
 #pragma omp parallel for schedule(static)
             for (int q = 0; q < sw * sh; ++q) {
                 float px[3];
                 int cc[3];
+                const float* Mq = (ovl && c->mask[p][q]) ? c->Mpf[p] : M;
                 for (int ch = 0; ch < 3; ++ch) px[ch] = (float)c->strip[p][s][(size_t)q * 3 + ch];
-                for (int ch = 0; ch < 3; ++ch) cc[ch] = vso_round8(color_apply(px, M, ch));
+                for (int ch = 0; ch < 3; ++ch) cc[ch] = vso_round8(color_apply(px, Mq, ch));
                 Y[q] = (float)vso_luma(cc[0], cc[1], cc[2]);
             }
             for (int l = 1; l < c->prm.lk_levels; ++l)
@@ -1216,6 +1259,31 @@ void vso_fuse_pixel(const vso_view* vj, const vso_view* vi, float y, const float
     for (int ch = 0; ch < 3; ++ch) out[ch] = (uint8_t)vso_round8(fmaf(th_i, ti[ch] - tj[ch], tj[ch]));
 }
 
+/* Eq. (17) as printed: camera i at x + theta_i flow_ij(x), camera j at
+ * x + theta_j flow_ji(x); eqs. (16) and (18) as in vso_fuse_pixel. */
+void vso_fuse_pixel_literal(const vso_view* vj, const vso_view* vi, float y, const float f_ij[2],
+                            const float f_ji[2], uint8_t out[3])
+{
+    float uj, vjv, ui, viv;
+    vso_hom_valid(vj->hinv, vj->X, y, vj->W, vj->H, &uj, &vjv);
+    vso_hom_valid(vi->hinv, vi->X, y, vi->W, vi->H, &ui, &viv);
+    float dj = fminf(uj, (float)(vj->W - 1) - uj);
+    float di = fminf(ui, (float)(vi->W - 1) - ui);
+    if (dj < 0.0f) dj = 0.0f;
+    if (di < 0.0f) di = 0.0f;
+    float sum = di + dj;
+    float th_i = sum > 0.0f ? di / sum : 0.5f;
+    float th_j = 1.0f - th_i;
+    float Xi = fmaf(th_i, f_ij[0], vi->X);
+    float Yi = fmaf(th_i, f_ij[1], y);
+    float Xj = fmaf(th_j, f_ji[0], vj->X);
+    float Yj = fmaf(th_j, f_ji[1], y);
+    float ti[3], tj[3];
+    sample_view(vi, Xi, Yi, ti);
+    sample_view(vj, Xj, Yj, tj);
+    for (int ch = 0; ch < 3; ++ch) out[ch] = (uint8_t)vso_round8(fmaf(th_i, ti[ch] - tj[ch], tj[ch]));
+}
+
 static void make_view(const vso_ctx* c, const uint8_t* const F[], const int pitch[], const hit* h, int x,
                       vso_view* v)
 {
@@ -1254,10 +1322,14 @@ static void step_blend(vso_ctx* c, const uint8_t* const F[], const int pitch[])
                 vso_view vj, vi;
                 make_view(c, F, pitch, &h[jidx], x, &vj);
                 make_view(c, F, pitch, &h[1 - jidx], x, &vi);
+                if (c->prm.readings & VSO_READ_OVERLAP_ONLY) vi.M = c->Mpf[p];
                 int X = x + h[jidx].m * P->ring_period;
                 int lx = X - P->strip_x0[p], ly = y - P->strip_y0[p];
                 size_t q = ((size_t)ly * P->strip_w[p] + lx) * 2;
-                vso_fuse_pixel(&vj, &vi, (float)y, c->flow[p][0] + q, c->flow[p][1] + q, o);
+                if (c->prm.readings & VSO_READ_LITERAL_EQ17)
+                    vso_fuse_pixel_literal(&vj, &vi, (float)y, c->flow[p][0] + q, c->flow[p][1] + q, o);
+                else
+                    vso_fuse_pixel(&vj, &vi, (float)y, c->flow[p][0] + q, c->flow[p][1] + q, o);
             }
         }
     }

@@ -55,7 +55,22 @@ typedef struct {
     float lk_lambda;
     int balance;        /* 0: skip the balancing LUT apply; 1: apply */
     int lambda_pct;     /* balancing quantile, percent (5 -> lambda = 0.05) */
+    int readings;       /* the literal readings the default ones replace, a bit mask of
+                           VSO_READ_*; 0: the adopted readings */
 } vso_params;
+
+/* Literal readings of passages the default path reads otherwise:
+ *  OVERLAP_ONLY  eq. (4)'s text: each pair's matrix corrects camera i only
+ *                inside that pair's overlap, uncomposed; every other pixel
+ *                keeps its raw colour (default: the matrices chained to
+ *                camera 0 correct whole frames);
+ *  LITERAL_EQ17  eq. (17) as printed: camera i is displaced by theta_i flow_ij
+ *                and camera j by theta_j flow_ji (default: theta_j flow_ij and
+ *                theta_i flow_ji, the warps meeting in the middle);
+ *  NEAREST_CDF   section 2.1 step 3 with the level whose cumulative count is
+ *                nearest, ties to the lower level (default: the first level
+ *                whose cumulative count reaches it). */
+enum { VSO_READ_OVERLAP_ONLY = 1, VSO_READ_LITERAL_EQ17 = 2, VSO_READ_NEAREST_CDF = 4 };
 
 void vso_default_params(vso_params* p);
 
@@ -116,6 +131,7 @@ int vso_get(const vso_ctx* c, int tap, int pair, int sub, void* dst, size_t nbyt
 
 /* ---- individual steps, exposed for the pins ---- */
 void vso_histspec_lut(const uint32_t Gi[256], const uint32_t Gj[256], uint8_t lut[256]);
+void vso_histspec_lut_nearest(const uint32_t Gi[256], const uint32_t Gj[256], uint8_t lut[256]);
 /* (A + eps I) M = B + eps I, eps = ridge * trace(A); returns 0 ok, 1 singular */
 int vso_solve_color(const double A[9], const double B[9], double ridge, double M[9]);
 void vso_quantiles(const uint32_t hist[256], long long n, int lambda_pct, int* q1, int* q2);
@@ -147,6 +163,9 @@ typedef struct {
  * i (right), with the pair's flows f_ij, f_ji at the pixel */
 void vso_fuse_pixel(const vso_view* vj, const vso_view* vi, float y, const float f_ij[2], const float f_ji[2],
                     uint8_t out[3]);
+/* the same with eq. (17) as printed (VSO_READ_LITERAL_EQ17) */
+void vso_fuse_pixel_literal(const vso_view* vj, const vso_view* vi, float y, const float f_ij[2],
+                            const float f_ji[2], uint8_t out[3]);
 
 /* learned surrogate: FP64 3x3 convolution references (NHWC, weights
  * [cout][tap][cin], zero padding) */
