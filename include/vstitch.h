@@ -88,7 +88,22 @@ typedef struct {
     int32_t debug_taps;     /* 1: keep a copy of the pre-balance panorama for vs_debug_tap (0) */
     int32_t pyr_tile_rows;  /* pyramid levels 0-2 in one pass, level-2 tile height: 8 or 16, or 0:
                                16 unless that gives under 1536 tiles (0); results do not depend on it */
+    int32_t readings;       /* literal readings replacing adopted ones, a mask of VS_READ_* (0) */
 } vs_params;
+
+/* Literal readings of passages the default path reads otherwise (options,
+ * for measuring what the adopted readings change):
+ *  VS_READ_OVERLAP_ONLY  eq. (4)'s text: each pair's matrix corrects camera i
+ *      only inside that pair's overlap, uncomposed (the ring's closing pair
+ *      included); pixels one camera sees keep their raw colour.  Default: the
+ *      pair matrices chained to camera 0 correct every camera's whole frame.
+ *  VS_READ_LITERAL_EQ17  eq. (17) as printed: camera i is displaced by
+ *      theta_i flow_ij, camera j by theta_j flow_ji.  Default: theta_j flow_ij
+ *      and theta_i flow_ji (the two warps meet in the middle).
+ *  VS_READ_NEAREST_CDF   section 2.1 step 3 with the level whose cumulative
+ *      count is nearest (ties: the lower level).  Default: the first level
+ *      whose cumulative count reaches it. */
+enum { VS_READ_OVERLAP_ONLY = 1, VS_READ_LITERAL_EQ17 = 2, VS_READ_NEAREST_CDF = 4 };
 
 /* Temporal colour state: the only information carried between frames.
  * mom[p][0] / mom[p][1] hold the overlap moments of pair p at frames T-1 and

@@ -283,6 +283,7 @@ vs_status vs_default_params(vs_params* p)
     p->lambda_pct = 5;
     p->debug_taps = 0;
     p->pyr_tile_rows = 0;
+    p->readings = 0;
     return VS_OK;
 }
 
@@ -315,7 +316,7 @@ vs_status vs_create(const vs_rig* rig, const vs_params* prm, vs_ctx** out)
     if (P.lk_levels < 1 || P.lk_levels > VS_MAX_LEVELS || P.lk_iters < 0 || P.lk_radius < 0 ||
         P.lk_radius > LK_R_MAX || P.color_window < 0 || P.color_window > 3 || P.lambda_pct < 1 ||
         P.lambda_pct > 49 || !(P.ridge >= 0.0) || !std::isfinite(P.lk_lambda) ||
-        (P.pyr_tile_rows != 0 && P.pyr_tile_rows != 8 && P.pyr_tile_rows != 16))
+        (P.pyr_tile_rows != 0 && P.pyr_tile_rows != 8 && P.pyr_tile_rows != 16) || (P.readings & ~7) != 0)
         return VS_E_INVAL;
 
     vs_ctx* c = new (std::nothrow) vs_ctx();
@@ -340,6 +341,7 @@ vs_status vs_create(const vs_rig* rig, const vs_params* prm, vs_ctx** out)
     h.lk_radius = P.lk_radius;
     h.lk_iters = P.lk_iters;
     h.lk_lambda = P.lk_lambda;
+    h.readings = P.readings;
     h.ridge = P.ridge;
     double Hk[VS_MAX_CAMS * 9];
     float Hinv[VS_MAX_CAMS * 9];

@@ -53,6 +53,7 @@ struct Results {
     uint8_t lut[MAXP][3][256];
     double Mpair[MAXP][9];
     float Mk[MAXC][9];
+    float Mpf[MAXP][9];               // the pair matrices in FP32 (VS_READ_OVERLAP_ONLY)
     int32_t flags[MAXP];
     unsigned long long mom[MAXP][16];
     uint8_t bal_lut[3][256];
@@ -65,6 +66,7 @@ struct Results {
 struct DevPlan {
     int32_t n_cams, n_pairs, canvas_w, canvas_h, ring, Wp, levels, pano_pitch;
     int32_t color_window, min_pixels, use_flow, balance, lambda_pct, lk_radius, lk_iters;
+    int32_t readings;                 // VS_READ_* mask
     float lk_lambda;
     double ridge;
     int32_t cam_w[MAXC], cam_h[MAXC], cam_pitch[MAXC];

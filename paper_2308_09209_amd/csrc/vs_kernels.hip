@@ -283,6 +283,25 @@ __device__ __forceinline__ void lut_body(const DevPlan* __restrict__ P, const in
         if (Cj[c][mid] < target) lo = mid + 1;
         else hi = mid;
     }
+    if (P->readings & VS_READ_NEAREST_CDF) {
+        // the nearest cumulative count, ties to the lower level: Cj is
+        // non-decreasing, so it is Cj[lo] (the first at or above the target)
+        // or the first level holding the value just below it
+        int w = lo > 255 ? 255 : lo;
+        if (lo > 0) {
+            const uint32_t below = Cj[c][lo - 1];
+            if (lo > 255 || target - below <= Cj[c][lo] - target) {
+                int a = 0, b = lo - 1;   // first w with Cj[w] >= below
+                while (a < b) {
+                    const int mid = (a + b) >> 1;
+                    if (Cj[c][mid] < below) a = mid + 1;
+                    else b = mid;
+                }
+                w = a;
+            }
+        }
+        lo = w;
+    }
     P->res->lut[p][c][v] = (uint8_t)(lo > 255 ? 255 : lo);
 }
 
@@ -487,6 +506,13 @@ __device__ __forceinline__ void solve_body(const DevPlan* __restrict__ P, const 
                 res->Mk[k][i] = (float)t[i];
             }
         }
+        // eq. (4)'s text read literally: no whole-frame (composed) correction;
+        // each pair's own matrix corrects camera i inside that overlap
+        for (int p = 0; p < P->n_pairs; ++p)
+            for (int i = 0; i < 9; ++i) res->Mpf[p][i] = (float)s_M[p][i];
+        if (P->readings & VS_READ_OVERLAP_ONLY)
+            for (int k = 0; k < P->n_cams; ++k)
+                for (int i = 0; i < 9; ++i) res->Mk[k][i] = (i % 4 == 0) ? 1.0f : 0.0f;
     }
 }
 
@@ -513,6 +539,9 @@ __device__ __forceinline__ void pyr0_body(const DevPlan* __restrict__ P, const i
     const int w = P->sw[p], h = P->sh[p];
     const int tx0 = (t % P->pyr_tx[0][f]) * PYR_TX, ty0 = (t / P->pyr_tx[0][f]) * PYR_TY;
     const float* M = P->res->Mk[cam == 0 ? P->pj[p] : P->pi[p]];
+    // overlap-only reading: camera i's pair matrix inside the overlap mask
+    const float* Mo = (cam == 1 && (P->readings & VS_READ_OVERLAP_ONLY)) ? P->res->Mpf[p] : nullptr;
+    const uint8_t* __restrict__ mk = P->mask[p];
     const uint32_t* __restrict__ src = P->strip[p] + (size_t)cam * h * w;
     float* __restrict__ dst = P->pyr[p][cam][0];
     const int x = tx0 + (threadIdx.x & 63);
@@ -529,7 +558,8 @@ __device__ __forceinline__ void pyr0_body(const DevPlan* __restrict__ P, const i
         const int y = ty0 + (threadIdx.x >> 6) + 4 * k;
         if (x >= w || y >= h) continue;
         float s[3] = {(float)(pix[k] & 255u), (float)((pix[k] >> 8) & 255u), (float)((pix[k] >> 16) & 255u)};
-        uint32_t c0 = round8(capply(s, M, 0)), c1 = round8(capply(s, M, 1)), c2 = round8(capply(s, M, 2));
+        const float* Mx = (Mo && mk[(size_t)y * w + x]) ? Mo : M;
+        uint32_t c0 = round8(capply(s, Mx, 0)), c1 = round8(capply(s, Mx, 1)), c2 = round8(capply(s, Mx, 2));
         dst[(size_t)y * w + x] = (float)((77u * c0 + 150u * c1 + 29u * c2 + 128u) >> 8);
     }
 }
@@ -630,6 +660,9 @@ __device__ __forceinline__ void pyr_fused_body(const DevPlan* __restrict__ P, co
     const int bx1 = 2 * X0 - 2, by1 = 2 * Y0 - 2;
     const bool write01 = P->flow_mode == VS_FLOW_PLAIN || after;
     const float* M = P->res->Mk[cam == 0 ? P->pj[p] : P->pi[p]];
+    // overlap-only reading: camera i's pair matrix inside the overlap mask
+    const float* Mo = (cam == 1 && (P->readings & VS_READ_OVERLAP_ONLY)) ? P->res->Mpf[p] : nullptr;
+    const uint8_t* __restrict__ mk = P->mask[p];
     const uint32_t* __restrict__ src = P->strip[p] + (size_t)cam * h0 * w0;
     float* __restrict__ L0 = P->pyr[p][cam][0];
     float* __restrict__ L1 = P->pyr[p][cam][1];
@@ -639,13 +672,16 @@ __device__ __forceinline__ void pyr_fused_body(const DevPlan* __restrict__ P, co
     constexpr int N0 = PF_H0 * PF_W0, NB = 8;
     for (int i0 = 0; i0 < N0; i0 += 256 * NB) {
         uint32_t pix[NB];
+        bool inm[NB];
 #pragma unroll
         for (int k = 0; k < NB; ++k) {
             const int i = i0 + k * 256 + tid;
             pix[k] = 0u;
+            inm[k] = false;
             if (i < N0) {
                 const int yy = clampi(by0 + i / PF_W0, 0, h0 - 1), xx = clampi(bx0 + i % PF_W0, 0, w0 - 1);
                 pix[k] = src[(size_t)yy * w0 + xx];
+                if (Mo) inm[k] = mk[(size_t)yy * w0 + xx] != 0;
             }
         }
 #pragma unroll
@@ -654,7 +690,8 @@ __device__ __forceinline__ void pyr_fused_body(const DevPlan* __restrict__ P, co
             if (i >= N0) continue;
             const float s[3] = {(float)(pix[k] & 255u), (float)((pix[k] >> 8) & 255u),
                                 (float)((pix[k] >> 16) & 255u)};
-            const uint32_t c0 = round8(capply(s, M, 0)), c1 = round8(capply(s, M, 1)), c2 = round8(capply(s, M, 2));
+            const float* Mx = inm[k] ? Mo : M;
+            const uint32_t c0 = round8(capply(s, Mx, 0)), c1 = round8(capply(s, Mx, 1)), c2 = round8(capply(s, Mx, 2));
             const uint32_t Y = (77u * c0 + 150u * c1 + 29u * c2 + 128u) >> 8;
             const int r = i / PF_W0, c = i % PF_W0;
             s0[r][c] = (uint8_t)Y;
@@ -806,16 +843,21 @@ __device__ __forceinline__ void blend_body(const DevPlan* __restrict__ P, const 
                     typedef float f2v __attribute__((ext_vector_type(2)));
                     const f2v fij = gmem((const f2v*)P->flow[p][0][0])[qf];
                     const f2v fji = gmem((const f2v*)P->flow[p][1][0])[qf];
-                    const float Xi = __builtin_fmaf(thj, fij.x, (float)(x + mi * Wp));
-                    const float Yi = __builtin_fmaf(thj, fij.y, (float)y);
-                    const float Xj = __builtin_fmaf(thi, fji.x, (float)(x + mj * Wp));
-                    const float Yj = __builtin_fmaf(thi, fji.y, (float)y);
+                    // eq. (17): camera i moves by theta_j flow_ij, camera j by theta_i
+                    // flow_ji (as printed: theta_i and theta_j, VS_READ_LITERAL_EQ17)
+                    const bool lit = (P->readings & VS_READ_LITERAL_EQ17) != 0;
+                    const float wi = lit ? thi : thj, wj = lit ? thj : thi;
+                    const float Xi = __builtin_fmaf(wi, fij.x, (float)(x + mi * Wp));
+                    const float Yi = __builtin_fmaf(wi, fij.y, (float)y);
+                    const float Xj = __builtin_fmaf(wj, fji.x, (float)(x + mj * Wp));
+                    const float Yj = __builtin_fmaf(wj, fji.y, (float)y);
                     float u, v, si[3], sj[3];
                     hom(s_hinv[ki], Xi, Yi, s_cw[ki], s_ch[ki], u, v);
                     bilin3(s_fr[ki], s_cp[ki], s_cw[ki], s_ch[ki], u, v, si);
                     hom(s_hinv[kj], Xj, Yj, s_cw[kj], s_ch[kj], u, v);
                     bilin3(s_fr[kj], s_cp[kj], s_cw[kj], s_ch[kj], u, v, sj);
-                    const float* Mi = s_M[ki];
+                    // overlap-only reading: camera i's own pair matrix (camera j's is I)
+                    const float* Mi = (P->readings & VS_READ_OVERLAP_ONLY) ? P->res->Mpf[p] : s_M[ki];
                     const float* Mj = s_M[kj];
                     float ti, tj;
                     ti = capply(si, Mi, 0);

@@ -286,6 +286,29 @@ class Scene:
     def frames(self, t: int) -> list[np.ndarray]:
         return [self.frame(k, t) for k in range(self.n_cams)]
 
+    def truth(self, t: int, ref: int = 0) -> np.ndarray:
+        """The panorama an ideal stitch would give at time t: the texture at
+        every canvas pixel (canvas coordinates are texture coordinates; no
+        residual displacement; occluders drawn where they are at t) through
+        camera `ref`'s colour response of frame t, as uint8 HWC.  Colour
+        correction chained to camera 0 aims at ref = 0."""
+        cam = self.cams[ref]
+        out = np.empty((self.canvas_h, self.canvas_w, 3), dtype=np.uint8)
+        xs = np.arange(self.canvas_w, dtype=np.float64)
+        for y0 in range(0, self.canvas_h, 64):
+            ys = np.arange(y0, min(y0 + 64, self.canvas_h), dtype=np.float64)
+            X, Y = np.meshgrid(xs, ys)
+            rgb = self.texture(X, Y)
+            for (cx0, cy0, a, b, vx, vy, col) in self.occ:
+                cy = np.mod(cy0 + vy * t, self.canvas_h)
+                cx = np.mod(cx0 + vx * t, self.canvas_w)
+                for sh in (-self.canvas_w, 0.0, self.canvas_w):
+                    inside = ((X - (cx + sh)) / a) ** 2 + ((Y - cy) / b) ** 2 <= 1.0
+                    rgb[inside] = col
+            c = np.clip(self.gain(ref, t) * (rgb @ cam.C.T), 0.0, 1.0) ** cam.gamma
+            out[y0:y0 + len(ys)] = np.floor(255.0 * c + 0.5).astype(np.uint8)
+        return out
+
 
 # Six uneven streams stitched together (3 or 4 cameras, 20 % overlap chains).
 BATCH_STREAMS = [

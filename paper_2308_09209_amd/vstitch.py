@@ -59,7 +59,11 @@ class Params(C.Structure):
     _fields_ = [("color_window", C.c_int32), ("ridge", C.c_double), ("min_pixels", C.c_int32),
                 ("flow", C.c_int32), ("lk_levels", C.c_int32), ("lk_iters", C.c_int32),
                 ("lk_radius", C.c_int32), ("lk_lambda", C.c_float), ("balance", C.c_int32),
-                ("lambda_pct", C.c_int32), ("debug_taps", C.c_int32), ("pyr_tile_rows", C.c_int32)]
+                ("lambda_pct", C.c_int32), ("debug_taps", C.c_int32), ("pyr_tile_rows", C.c_int32),
+                ("readings", C.c_int32)]
+
+
+READ_OVERLAP_ONLY, READ_LITERAL_EQ17, READ_NEAREST_CDF = 1, 2, 4
 
 
 class Moments(C.Structure):

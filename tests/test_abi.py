@@ -153,3 +153,14 @@ def test_noalloc_flow_rejects_oversized_pairs_on_the_host():
     assert L.vs_flow_run_noalloc(4000, 3000, None, fake, fake, fake, fake, None) == -1
     assert L.vs_flow_run_noalloc(64, 64, None, None, fake, fake, fake, None) == -1
     assert L.vs_flow_run_noalloc(1, 64, None, fake, fake, fake, fake, None) == -1
+
+
+def test_create_rejects_unknown_readings():
+    """vs_params.readings outside the VS_READ_* mask is refused before any
+    device work."""
+    from paper_2308_09209_amd.scenes import small_scene
+    rig = V.make_rig(small_scene().rig())
+    p = V.default_params(readings=8)
+    h = C.c_void_p()
+    assert V.lib().vs_create(C.byref(rig), C.byref(p), C.byref(h)) == -1
+    assert not h.value
