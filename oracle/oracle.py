@@ -14,6 +14,7 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "liboracle.so")
 SRC = os.path.join(HERE, "vso_oracle.c")
+SRC_CALIB = os.path.join(HERE, "vso_calib.c")
 
 MAX_CAMS = 16
 MAX_PAIRS = 16
@@ -28,7 +29,7 @@ FLOW_PLAIN, FLOW_SURROGATE, FLOW_FALLBACK = 0, 1, 2
 def build(verbose: bool = False) -> str:
     """Compile liboracle.so with gcc (no FP contraction, OpenMP)."""
     cmd = ["gcc", "-O2", "-ffp-contract=off", "-fopenmp", "-fPIC", "-shared", "-Wall",
-           "-o", LIB_PATH + ".tmp", SRC, "-lm"]
+           "-o", LIB_PATH + ".tmp", SRC, SRC_CALIB, "-lm"]
     if verbose:
         print(" ".join(cmd))
     subprocess.run(cmd, check=True)
@@ -105,6 +106,17 @@ def lib():
         L.vso_bilinear.argtypes = [C.c_void_p, C.c_int, C.c_int, C.c_int, C.c_int, C.c_float,
                                    C.c_float]
         L.vso_round8.argtypes = [C.c_float]
+        dbl = C.c_double
+        L.vso_calib_intrinsics.argtypes = [dbl] * 7 + [C.c_void_p]
+        L.vso_calib_plane_homography.argtypes = [C.c_void_p] * 4
+        L.vso_calib_pair.argtypes = [C.c_void_p] * 3
+        L.vso_calib_refine.argtypes = [C.c_void_p] * 3
+        L.vso_calib_harris.argtypes = [C.c_void_p, C.c_int, C.c_int, C.c_int]
+        L.vso_calib_harris.restype = C.c_float
+        L.vso_calib_ncc.argtypes = [C.c_void_p, C.c_int, C.c_int, C.c_int, C.c_void_p, C.c_int, C.c_int, C.c_int]
+        L.vso_calib_ncc.restype = C.c_float
+        L.vso_calib_estimate.argtypes = [C.c_void_p, C.c_int, C.c_int, C.c_int, C.c_void_p, C.c_int, C.c_int, C.c_int,
+                                         C.c_void_p, C.c_int, C.c_int, C.c_void_p, C.c_void_p, C.c_void_p]
         L.vso_luma.argtypes = [C.c_int, C.c_int, C.c_int]
         L.vso_chain_colour.argtypes = [C.c_void_p, C.c_int, C.c_void_p]
         L.vso_fuse_pixel.argtypes = [C.POINTER(View), C.POINTER(View), C.c_float, C.c_void_p, C.c_void_p,
@@ -536,3 +548,63 @@ def nn_train_step(ws, bs, x, label, sizes, alpha):
         dh = join([conv3x3_bwd_data(g, ws[li]) for g in per_image(dz)])
         dz = np.where(zs[li - 1] > 0, dh, alpha * dh)
     return loss, pred, gw, gb
+
+
+# ---- section 3.1 set-up: calibration homographies and their revision --------
+
+def _d9(a):
+    return np.ascontiguousarray(np.asarray(a, np.float64).reshape(9))
+
+
+def calib_intrinsics(f, dx, dy, cx, cy, u0, v0) -> np.ndarray:
+    K = np.zeros(9)
+    lib().vso_calib_intrinsics(*(C.c_double(v) for v in (f, dx, dy, cx, cy, u0, v0)), _ptr(K))
+    return K.reshape(3, 3)
+
+
+def calib_plane_homography(K, R, t) -> np.ndarray:
+    H = np.zeros(9)
+    tt = np.ascontiguousarray(np.asarray(t, np.float64).reshape(3))
+    Kd, Rd = _d9(K), _d9(R)
+    lib().vso_calib_plane_homography(_ptr(Kd), _ptr(Rd), _ptr(tt), _ptr(H))
+    return H.reshape(3, 3)
+
+
+def calib_pair(Ha, Hb) -> np.ndarray:
+    H = np.zeros(9)
+    a, b = _d9(Ha), _d9(Hb)
+    if lib().vso_calib_pair(_ptr(a), _ptr(b), _ptr(H)) != 0:
+        raise OracleError("singular homography")
+    return H.reshape(3, 3)
+
+
+def calib_refine(H, p) -> np.ndarray:
+    out = np.zeros(9)
+    h = _d9(H)
+    pp = np.ascontiguousarray(np.asarray(p, np.float64).reshape(4))
+    lib().vso_calib_refine(_ptr(h), _ptr(pp), _ptr(out))
+    return out.reshape(3, 3)
+
+
+def calib_harris(Y, x, y) -> float:
+    Y = np.ascontiguousarray(Y, np.float32)
+    return float(lib().vso_calib_harris(_ptr(Y), Y.shape[1], x, y))
+
+
+def calib_ncc(A, xa, ya, B, xb, yb) -> float:
+    A = np.ascontiguousarray(A, np.float32)
+    B = np.ascontiguousarray(B, np.float32)
+    return float(lib().vso_calib_ncc(_ptr(A), A.shape[1], xa, ya, _ptr(B), B.shape[1], xb, yb))
+
+
+def calib_estimate(frame_a, frame_b, H, margin=16, radius=4):
+    """((tx, ty, sx, sy), matches, inliers) or None"""
+    Fa = np.ascontiguousarray(frame_a, np.uint8)
+    Fb = np.ascontiguousarray(frame_b, np.uint8)
+    h = _d9(H)
+    out = np.zeros(4)
+    nm, ni = C.c_int(), C.c_int()
+    st = lib().vso_calib_estimate(_ptr(Fa), Fa.shape[1] * 3, Fa.shape[1], Fa.shape[0], _ptr(Fb), Fb.shape[1] * 3,
+                                  Fb.shape[1], Fb.shape[0], _ptr(h), margin, radius, _ptr(out), C.byref(nm),
+                                  C.byref(ni))
+    return (out, nm.value, ni.value) if st == 0 else (None, nm.value, ni.value)

@@ -187,4 +187,16 @@ int vso_surrogate_net(const void* blob, size_t n, const float* yt, const float* 
 void vso_surr_upsample(const float* pred, int w2, int h2, const uint8_t* need0, int w0, int h0, float* flow0);
 void vso_fb_check(const float* pred_ij, const float* pred_ji, int w2, int h2, const uint8_t* need0, int w0, int h0,
                   unsigned long long* sum, unsigned long long* count);
+
+/* Section 3.1 set-up (vso_calib.c): camera parameters -> homographies
+ * (eqs. (8)-(12)), the revision of eqs. (13)-(14) and its estimation from
+ * matched points.  Readings in vso_calib.c. */
+void vso_calib_intrinsics(double f, double dx, double dy, double cx, double cy, double u0, double v0, double K[9]);
+void vso_calib_plane_homography(const double K[9], const double R[9], const double t[3], double H[9]);
+int vso_calib_pair(const double Ha[9], const double Hb[9], double Hab[9]);
+void vso_calib_refine(const double H[9], const double p[4], double Hr[9]);
+float vso_calib_harris(const float* Y, int w, int x, int y);
+float vso_calib_ncc(const float* A, int wa, int xa, int ya, const float* B, int wb, int xb, int yb);
+int vso_calib_estimate(const uint8_t* Fa, int pa, int wa, int ha, const uint8_t* Fb, int pb, int wb, int hb,
+                       const double H[9], int margin, int radius, double out[4], int* n_matches, int* n_inliers);
 #endif
