@@ -15,6 +15,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "liboracle.so")
 SRC = os.path.join(HERE, "vso_oracle.c")
 SRC_CALIB = os.path.join(HERE, "vso_calib.c")
+SRC_VAR = os.path.join(HERE, "vso_var.c")
 
 MAX_CAMS = 16
 MAX_PAIRS = 16
@@ -29,7 +30,7 @@ FLOW_PLAIN, FLOW_SURROGATE, FLOW_FALLBACK = 0, 1, 2
 def build(verbose: bool = False) -> str:
     """Compile liboracle.so with gcc (no FP contraction, OpenMP)."""
     cmd = ["gcc", "-O2", "-ffp-contract=off", "-fopenmp", "-fPIC", "-shared", "-Wall",
-           "-o", LIB_PATH + ".tmp", SRC, SRC_CALIB, "-lm"]
+           "-o", LIB_PATH + ".tmp", SRC, SRC_CALIB, SRC_VAR, "-lm"]
     if verbose:
         print(" ".join(cmd))
     subprocess.run(cmd, check=True)
@@ -48,7 +49,8 @@ class Params(C.Structure):
     _fields_ = [("color_window", C.c_int), ("ridge", C.c_double), ("min_pixels", C.c_int),
                 ("flow", C.c_int), ("lk_levels", C.c_int), ("lk_iters", C.c_int),
                 ("lk_radius", C.c_int), ("lk_lambda", C.c_float), ("balance", C.c_int),
-                ("lambda_pct", C.c_int), ("readings", C.c_int)]
+                ("lambda_pct", C.c_int), ("readings", C.c_int), ("var_alpha", C.c_float),
+                ("var_gamma", C.c_float), ("var_outer", C.c_int), ("var_inner", C.c_int)]
 
 
 READ_OVERLAP_ONLY, READ_LITERAL_EQ17, READ_NEAREST_CDF = 1, 2, 4
@@ -106,6 +108,10 @@ def lib():
         L.vso_bilinear.argtypes = [C.c_void_p, C.c_int, C.c_int, C.c_int, C.c_int, C.c_float,
                                    C.c_float]
         L.vso_round8.argtypes = [C.c_float]
+        L.vso_var_level.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int, C.c_int, C.c_float, C.c_float,
+                                    C.c_int, C.c_int, C.c_void_p]
+        L.vso_var_pyramid.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int,
+                                      C.c_float, C.c_float, C.c_int, C.c_int, C.c_void_p]
         dbl = C.c_double
         L.vso_calib_intrinsics.argtypes = [dbl] * 7 + [C.c_void_p]
         L.vso_calib_plane_homography.argtypes = [C.c_void_p] * 4
@@ -608,3 +614,32 @@ def calib_estimate(frame_a, frame_b, H, margin=16, radius=4):
                                   Fb.shape[1], Fb.shape[0], _ptr(h), margin, radius, _ptr(out), C.byref(nm),
                                   C.byref(ni))
     return (out, nm.value, ni.value) if st == 0 else (None, nm.value, ni.value)
+
+
+# ---- the variational flow alternative (vso_var.c) ---------------------------
+
+def var_level(T, Mv, flow0=None, need=None, alpha=128.0, gamma=16.0, outer=3, inner=10) -> np.ndarray:
+    """one level of the variational estimator from flow0 (zeros if None)"""
+    T = np.ascontiguousarray(T, np.float32)
+    Mv = np.ascontiguousarray(Mv, np.float32)
+    h, w = T.shape
+    f = np.zeros((h, w, 2), np.float32) if flow0 is None else np.array(flow0, np.float32, copy=True, order="C")
+    nd = None if need is None else np.ascontiguousarray(need, np.uint8)
+    lib().vso_var_level(_ptr(T), _ptr(Mv), None if nd is None else _ptr(nd), w, h, alpha, gamma, outer, inner, _ptr(f))
+    return f
+
+
+def var_pyramid(T, Mv, levels=4, alpha=128.0, gamma=16.0, outer=3, inner=10) -> np.ndarray:
+    """coarse-to-fine variational flow of template T vs moving Mv (whole images)"""
+    Tp, Mp = [np.ascontiguousarray(T, np.float32)], [np.ascontiguousarray(Mv, np.float32)]
+    for _ in range(levels - 1):
+        Tp.append(pyr_down(Tp[-1]))
+        Mp.append(pyr_down(Mp[-1]))
+    h, w = Tp[0].shape
+    out = np.zeros((h, w, 2), np.float32)
+    PA = C.c_void_p * levels
+    ws = (C.c_int * levels)(*[t.shape[1] for t in Tp])
+    hs = (C.c_int * levels)(*[t.shape[0] for t in Tp])
+    lib().vso_var_pyramid(PA(*[t.ctypes.data for t in Tp]), PA(*[m.ctypes.data for m in Mp]), None, ws, hs, levels,
+                          alpha, gamma, outer, inner, _ptr(out))
+    return out

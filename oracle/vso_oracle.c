@@ -147,6 +147,10 @@ void vso_default_params(vso_params* p)
     p->balance = 1;
     p->lambda_pct = 5;
     p->readings = 0;
+    p->var_alpha = 128.0f;
+    p->var_gamma = 16.0f;
+    p->var_outer = 3;
+    p->var_inner = 10;
 }
 
 /* 3x3 product c = a b, each entry ((a_r0 b_0c + a_r1 b_1c) + a_r2 b_2c). */
@@ -947,6 +951,19 @@ static void step_flow(vso_ctx* c)
             }
             int tmpl = dir == 0 ? 0 : 1; /* 0 = camera j, 1 = camera i */
             int mov = 1 - tmpl;
+            if (c->prm.flow == 2) {
+                const float* Tl[VSO_MAX_LEVELS];
+                const float* Ml[VSO_MAX_LEVELS];
+                const uint8_t* Nl[VSO_MAX_LEVELS];
+                for (int l = 0; l < L; ++l) {
+                    Tl[l] = c->pyr[p][tmpl][l];
+                    Ml[l] = c->pyr[p][mov][l];
+                    Nl[l] = c->need[p][l];
+                }
+                vso_var_pyramid(Tl, Ml, Nl, c->pw[p], c->ph[p], L, c->prm.var_alpha, c->prm.var_gamma,
+                                c->prm.var_outer, c->prm.var_inner, c->flow[p][dir]);
+                continue;
+            }
             float* prev = NULL;
             int pwc = 0, phc = 0;
             for (int l = L - 1; l >= 0; --l) {

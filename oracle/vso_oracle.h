@@ -50,13 +50,17 @@ typedef struct {
     int color_window;   /* 0: no colour transfer; 1: 2D-M (frame T only); 2..3: 3D-M window */
     double ridge;       /* relative ridge of the colour solve (x trace) */
     int min_pixels;     /* fewer overlap samples than this -> M = I */
-    int flow;           /* 0: zero flow; 1: pyramidal Lucas-Kanade */
+    int flow;           /* 0: zero flow; 1: pyramidal Lucas-Kanade; 2: variational (vso_var.c) */
     int lk_levels, lk_iters, lk_radius;
     float lk_lambda;
     int balance;        /* 0: skip the balancing LUT apply; 1: apply */
     int lambda_pct;     /* balancing quantile, percent (5 -> lambda = 0.05) */
     int readings;       /* the literal readings the default ones replace, a bit mask of
                            VSO_READ_*; 0: the adopted readings */
+    float var_alpha;    /* flow = 2 (variational): smoothness weight */
+    float var_gamma;    /*   gradient-constancy weight */
+    int var_outer;      /*   warps per level */
+    int var_inner;      /*   Jacobi steps per warp */
 } vso_params;
 
 /* Literal readings of passages the default path reads otherwise:
@@ -199,4 +203,11 @@ float vso_calib_harris(const float* Y, int w, int x, int y);
 float vso_calib_ncc(const float* A, int wa, int xa, int ya, const float* B, int wb, int xb, int yb);
 int vso_calib_estimate(const uint8_t* Fa, int pa, int wa, int ha, const uint8_t* Fb, int pb, int wb, int hb,
                        const double H[9], int margin, int radius, double out[4], int* n_matches, int* n_inliers);
+
+/* The variational flow alternative (vso_var.c): one level on flow (in: the
+ * initial flow, out: the result, [h][w][2]), and the coarse-to-fine driver. */
+void vso_var_level(const float* T, const float* Mv, const uint8_t* need, int w, int h, float alpha, float gamma,
+                   int outer, int inner, float* flow);
+void vso_var_pyramid(const float* const* T, const float* const* Mv, const uint8_t* const* need, const int* w,
+                     const int* h, int levels, float alpha, float gamma, int outer, int inner, float* flow0);
 #endif
