@@ -78,7 +78,9 @@ typedef struct {
     int32_t color_window;   /* 0: no colour transfer (M = I); 1: 2D-M; 2-3: 3D-M window (3) */
     double ridge;           /* relative ridge of the colour solve, x trace(A) (1e-9) */
     int32_t min_pixels;     /* fewer overlap samples over the window -> M = I (64) */
-    int32_t flow;           /* 0: zero flow; 1: dense pyramidal Lucas-Kanade (1) */
+    int32_t flow;           /* 0: zero flow; 1: dense pyramidal Lucas-Kanade (1); 2: variational
+                               (coarse-to-fine warping, brightness + gradient constancy, Charbonnier
+                               smoothness, Jacobi steps; the var_* fields) */
     int32_t lk_levels;      /* pyramid levels, 1..VS_MAX_LEVELS (4) */
     int32_t lk_iters;       /* Gauss-Newton steps per level (5) */
     int32_t lk_radius;      /* window half-size r, window (2r+1)^2, 0..4 (4) */
@@ -89,6 +91,10 @@ typedef struct {
     int32_t pyr_tile_rows;  /* pyramid levels 0-2 in one pass, level-2 tile height: 8 or 16, or 0:
                                16 unless that gives under 1536 tiles (0); results do not depend on it */
     int32_t readings;       /* literal readings replacing adopted ones, a mask of VS_READ_* (0) */
+    float var_alpha;        /* flow = 2: smoothness weight (128) */
+    float var_gamma;        /* flow = 2: gradient-constancy weight (16) */
+    int32_t var_outer;      /* flow = 2: warps per level (3) */
+    int32_t var_inner;      /* flow = 2: Jacobi steps per warp, even (10) */
 } vs_params;
 
 /* Literal readings of passages the default path reads otherwise (options,
@@ -415,6 +421,43 @@ vs_status vs_nn_load(vs_nn* n, const void* blob, size_t nbytes);
 enum { VS_FLOW_PLAIN = 0, VS_FLOW_SURROGATE = 1, VS_FLOW_SURROGATE_FALLBACK = 2 };
 vs_status vs_load_weights(vs_ctx* c, const void* blob, size_t nbytes);
 vs_status vs_set_flow_mode(vs_ctx* c, int mode, float fb_tau_px);
+
+/* ------------------------------------------------------------------------
+ * Set-up of section 3.1 (host, FP64, once per rig): the coarse pairwise
+ * homography from camera parameters and its revision by a skew and a scale
+ * matrix estimated on the widened overlap.  Readings of the garbled
+ * equations:
+ *  - eq. (8): K = [f/dx, 0, cx/dx + u0; 0, f/dy, cy/dy + v0; 0, 0, 1] (the
+ *    zero fourth column dropped, the second u0 read as v0);
+ *  - eq. (11) on the world plane Z_W = 0: H = K [r1 r2 t], plane coordinates
+ *    (X_W, Y_W, 1) to pixels (R row-major, r1 r2 its first two columns);
+ *  - eq. (12): H_ab = H_a H_b^-1 maps camera b's pixels to camera a's (so a
+ *    rig's H_pair[k] is vs_calib_pair(H_(k-1), H_k));
+ *  - eq. (14): H' = M H N with N = diag(s_x, s_y, 1) on the source pixel and M
+ *    the translation (t_x, t_y) of the result; p = (t_x, t_y, s_x, s_y).
+ * All return VS_E_INVAL on NULL or singular input. */
+vs_status vs_calib_intrinsics(double f, double dx, double dy, double cx, double cy, double u0, double v0, double K[9]);
+vs_status vs_calib_plane_homography(const double K[9], const double R[9], const double t[3], double H[9]);
+vs_status vs_calib_pair(const double Ha[9], const double Hb[9], double Hab[9]);
+vs_status vs_calib_refine(const double H[9], const double p[4], double Hr[9]);
+/* Estimate p of eq. (13) for the pre-warp H (camera a pixels -> camera b
+ * pixels) from two RGB frames (device pointers, HWC bytes, row pitch):
+ * Harris corners of a's BT.601 luma (5 x 5 box of central-difference
+ * products, k = 0.04) at pixels 8 + radius inside a whose H-image lies in b
+ * widened by `margin` px and, rounded, 6 + radius inside b; strict 3 x 3
+ * maxima, the 256 strongest; each matched to the integer position within
+ * +-radius of its rounded H-image with the best 11 x 11 normalised
+ * cross-correlation (kept at correlation >= 0.7), refined to the parabola
+ * vertex of its neighbours' scores; two-point RANSAC over every pair of the
+ * first 64 matches (Gauss-Newton, inliers within 2 px) and a final
+ * Gauss-Newton on the inliers.  The paper matches SURF features instead
+ * (the pre-warp leaves a few pixels to find, so a local correlation search
+ * does).  1 <= radius <= 7; frames at least 32 x 32.  Synchronous on stream;
+ * allocates its scratch.  VS_E_INVAL with fewer than 2 matches or no model
+ * (*n_matches, *n_inliers still set). */
+vs_status vs_calib_estimate(const uint8_t* frame_a, int pitch_a, int wa, int ha, const uint8_t* frame_b, int pitch_b,
+                            int wb, int hb, const double H[9], int margin, int radius, double p[4], int32_t* n_matches,
+                            int32_t* n_inliers, void* stream);
 
 /* Plain estimator on caller image pairs (training labels, tests): a context
  * for w x h luma images; vs_flow_run computes, on the whole image, the

@@ -10,7 +10,7 @@ import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 SOURCES = [os.path.join(HERE, "csrc", n) for n in
-           ("vs_host.cpp", "vs_kernels.hip", "vs_flow.hip", "vs_surr.hip", "vs_nn.hip", "vs_nn_host.cpp", "vs_nn_net.cpp", "vs_noalloc.hip")]
+           ("vs_host.cpp", "vs_kernels.hip", "vs_flow.hip", "vs_surr.hip", "vs_nn.hip", "vs_nn_host.cpp", "vs_nn_net.cpp", "vs_calib.hip", "vs_var.hip", "vs_noalloc.hip")]
 OUT = os.path.join(HERE, "libvstitch.so")
 
 # -ffp-contract=off: every fused multiply-add in the kernels is explicit, so

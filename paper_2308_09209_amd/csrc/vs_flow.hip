@@ -774,7 +774,7 @@ hipError_t launch_lk(const Group& g, int l, hipStream_t s)
         if (g.hp[c]->lk_P[l] != P) return hipErrorInvalidValue;
     Batch B;
     // a context whose flows all come from the surrogate launches no flow blocks
-    auto plain = [](const DevPlan& h) { return h.use_flow && h.flow_mode != VS_FLOW_SURROGATE; };
+    auto plain = [](const DevPlan& h) { return h.use_flow == 1 && h.flow_mode != VS_FLOW_SURROGATE; };
     // fallback contexts: deferred pixels finished in-block, no tail launch
     bool inblock = false;
     for (int c = 0; c < g.n; ++c) inblock = inblock || g.hp[c]->flow_mode == VS_FLOW_SURROGATE_FALLBACK;

@@ -39,6 +39,7 @@ struct vs_ctx {
     uint32_t timed_frames = 0;
     // learned surrogate
     void* surr_mem = nullptr;
+    void* var_mem = nullptr;             // variational flow workspace (flow = 2)
     SurrNet net;
     int surr_loaded = 0;
     // bumped whenever the launch sequence changes (flow variant, surrogate):
@@ -126,6 +127,7 @@ void free_ctx(vs_ctx* c)
     if (c->pano_pre) (void)hipFree(c->pano_pre);
     if (c->surr_mem) (void)hipFree(c->surr_mem);
     if (c->tiles) (void)hipFree(c->tiles);
+    if (c->var_mem) (void)hipFree(c->var_mem);
     delete c;
 }
 
@@ -187,6 +189,43 @@ void set_lk_tiles(DevPlan& h, int l, int P)
         h.lk_tx[l][f] = (h.lw[p][l] + tx - 1) / tx;
         h.lk_off[l][f + 1] = h.lk_off[l][f] + h.lk_tx[l][f] * ((h.lh[p][l] + ty - 1) / ty);
     }
+}
+
+bool var_params_ok(const vs_params& P)
+{
+    return std::isfinite(P.var_alpha) && P.var_alpha > 0.0f && std::isfinite(P.var_gamma) && P.var_gamma >= 0.0f &&
+           P.var_outer >= 0 && P.var_outer <= 64 && P.var_inner >= 0 && P.var_inner <= 1024 && P.var_inner % 2 == 0;
+}
+
+// Variational-flow blocks and workspace of a plan (its sizes set): per level
+// the 256-pixel blocks of every field; the derivative planes per camera, the
+// coefficients and increments per direction.  Returns the bytes needed and,
+// with base non-null, points the plan's buffers into them.
+size_t var_layout(DevPlan& h, uint8_t* base)
+{
+    size_t off = 0;
+    auto take = [&](size_t b) {
+        const size_t o = off;
+        off = (off + b + 255) / 256 * 256;
+        return base ? base + o : nullptr;
+    };
+    for (int l = 0; l < h.levels; ++l) {
+        h.var_off[l][0] = 0;
+        for (int f = 0; f < 2 * h.n_pairs; ++f) {
+            const int p = f >> 1;
+            h.var_off[l][f + 1] = h.var_off[l][f] + (int32_t)(((size_t)h.lw[p][l] * h.lh[p][l] + 255) / 256);
+        }
+    }
+    for (int p = 0; p < h.n_pairs; ++p)
+        for (int k = 0; k < 2; ++k)
+            for (int l = 0; l < h.levels; ++l) {
+                const size_t n = (size_t)h.lw[p][l] * h.lh[p][l];
+                h.var_D[p][k][l] = (float*)take(n * 5 * 4);
+                h.var_co[p][k][l] = (float*)take(n * 8 * 4);
+                h.var_dd[p][k][l][0] = (float2*)take(n * 8);
+                h.var_dd[p][k][l][1] = (float2*)take(n * 8);
+            }
+    return off;
 }
 
 // The most flow tiles any variant lists for a level: a band never holds more
@@ -284,6 +323,10 @@ vs_status vs_default_params(vs_params* p)
     p->debug_taps = 0;
     p->pyr_tile_rows = 0;
     p->readings = 0;
+    p->var_alpha = 128.0f;
+    p->var_gamma = 16.0f;
+    p->var_outer = 3;
+    p->var_inner = 10;
     return VS_OK;
 }
 
@@ -316,7 +359,8 @@ vs_status vs_create(const vs_rig* rig, const vs_params* prm, vs_ctx** out)
     if (P.lk_levels < 1 || P.lk_levels > VS_MAX_LEVELS || P.lk_iters < 0 || P.lk_radius < 0 ||
         P.lk_radius > LK_R_MAX || P.color_window < 0 || P.color_window > 3 || P.lambda_pct < 1 ||
         P.lambda_pct > 49 || !(P.ridge >= 0.0) || !std::isfinite(P.lk_lambda) ||
-        (P.pyr_tile_rows != 0 && P.pyr_tile_rows != 8 && P.pyr_tile_rows != 16) || (P.readings & ~7) != 0)
+        (P.pyr_tile_rows != 0 && P.pyr_tile_rows != 8 && P.pyr_tile_rows != 16) || (P.readings & ~7) != 0 ||
+        P.flow < 0 || P.flow > 2 || !var_params_ok(P))
         return VS_E_INVAL;
 
     vs_ctx* c = new (std::nothrow) vs_ctx();
@@ -342,6 +386,10 @@ vs_status vs_create(const vs_rig* rig, const vs_params* prm, vs_ctx** out)
     h.lk_iters = P.lk_iters;
     h.lk_lambda = P.lk_lambda;
     h.readings = P.readings;
+    h.var_alpha = P.var_alpha;
+    h.var_gamma = P.var_gamma;
+    h.var_outer = P.var_outer;
+    h.var_inner = P.var_inner;
     h.ridge = P.ridge;
     double Hk[VS_MAX_CAMS * 9];
     float Hinv[VS_MAX_CAMS * 9];
@@ -520,6 +568,16 @@ vs_status vs_create(const vs_rig* rig, const vs_params* prm, vs_ctx** out)
     h.res = (Results*)(base + o_res);
     h.state = (vs_color_state*)(base + o_state);
     if ((e = hipMemset(c->arena, 0, off)) != hipSuccess) return cleanup_dev(e, "hipMemset");
+    if (h.use_flow == 2) {
+        const size_t vb = var_layout(h, nullptr);
+        if (hipMalloc(&c->var_mem, vb) != hipSuccess) {
+            free_ctx(c);
+            return VS_E_NOMEM;
+        }
+        var_layout(h, (uint8_t*)c->var_mem);
+        if ((e = hipMemset(c->var_mem, 0, vb)) != hipSuccess) return cleanup_dev(e, "hipMemset");
+        c->arena_bytes += vb;
+    }
     if (P.debug_taps) {
         if (hipMalloc((void**)&c->pano_pre, (size_t)h.canvas_h * h.pano_pitch) != hipSuccess) {
             free_ctx(c);
@@ -738,7 +796,10 @@ hipError_t enqueue_frame(const Group& g, hipStream_t s, hipEvent_t* ev, uint8_t*
     // what the plain estimator still needs, after the surrogate's decisions
     VS_STEP(launch_pyr_fused(g, PYR_AFTER, s), "pyr_fused");
     for (int l = 0; l + 1 < levels; ++l) VS_STEP(launch_pyr_down(g, l, PYR_AFTER, s), "pyr_down");
-    for (int l = levels - 1; l >= 0; --l) VS_STEP(launch_lk(g, l, s), "flow");
+    for (int l = levels - 1; l >= 0; --l) {
+        VS_STEP(launch_lk(g, l, s), "flow");
+        VS_STEP(launch_var(g, l, s), "variational flow");
+    }
     if (ev) VS_STEP(hipEventRecord(ev[3], s), "hipEventRecord");
     VS_STEP(launch_blend(g, s), "blend");
     if (pre) VS_STEP(hipMemcpyAsync(pre, pano, pano_bytes, hipMemcpyDeviceToDevice, s), "pano_pre copy");
@@ -1237,14 +1298,18 @@ bool flow_plan(int w, int h, const vs_params& P, DevPlan& d, FlowLayout& L)
 {
     if (w < 2 || h < 2 || w > 65535 || h > 65535) return false;
     if (P.lk_levels < 1 || P.lk_levels > VS_MAX_LEVELS || P.lk_iters < 0 || P.lk_radius < 0 ||
-        P.lk_radius > LK_R_MAX || !std::isfinite(P.lk_lambda))
+        P.lk_radius > LK_R_MAX || !std::isfinite(P.lk_lambda) || !(P.flow == 1 || P.flow == 2) || !var_params_ok(P))
         return false;
     std::memset(&d, 0, sizeof d);
     std::memset(&L, 0, sizeof L);
     d.n_cams = 2;
     d.n_pairs = 1;
     d.levels = P.lk_levels;
-    d.use_flow = 1;
+    d.use_flow = P.flow;
+    d.var_alpha = P.var_alpha;
+    d.var_gamma = P.var_gamma;
+    d.var_outer = P.var_outer;
+    d.var_inner = P.var_inner;
     d.lk_radius = P.lk_radius;
     d.lk_iters = P.lk_iters;
     d.lk_lambda = P.lk_lambda;
@@ -1283,6 +1348,10 @@ bool flow_plan(int w, int h, const vs_params& P, DevPlan& d, FlowLayout& L)
         L.queue[l] = off;
         off = align_up(off + (size_t)d.lk_qcap[l] * 16, 256);
     }
+    if (d.use_flow == 2) {
+        L.var = off;
+        off = align_up(off + var_layout(d, nullptr), 256);
+    }
     L.acc = off;
     off = align_up(off + sizeof(Accum), 256);
     L.res = off;
@@ -1307,6 +1376,7 @@ void flow_bind(DevPlan& d, const FlowLayout& L, uint8_t* base)
     d.acc = (Accum*)(base + L.acc);
     d.res = (Results*)(base + L.res);
     d.state = (vs_color_state*)(base + L.state);
+    if (d.use_flow == 2) var_layout(d, base + L.var);
 }
 
 // Mark every pixel of every level as flow domain (a fill kernel, no memset node).
@@ -1333,7 +1403,10 @@ hipError_t flow_run(const DevPlan& d, DevPlan* dp, const float* yt, const float*
     if (e == hipSuccess) e = hipMemcpyAsync(d.pyr[0][1][0], ym, n * 4, hipMemcpyDeviceToDevice, s);
     if (e == hipSuccess) e = launch_zero(g, s);
     for (int l = 0; l + 1 < d.levels && e == hipSuccess; ++l) e = launch_pyr_down(g, l, PYR_ALL, s);
-    for (int l = d.levels - 1; l >= 0 && e == hipSuccess; --l) e = launch_lk(g, l, s);
+    for (int l = d.levels - 1; l >= 0 && e == hipSuccess; --l) {
+        e = launch_lk(g, l, s);
+        if (e == hipSuccess) e = launch_var(g, l, s);
+    }
     if (e == hipSuccess && flow_tm) e = hipMemcpyAsync(flow_tm, d.flow[0][0][0], n * 8, hipMemcpyDeviceToDevice, s);
     if (e == hipSuccess && flow_mt) e = hipMemcpyAsync(flow_mt, d.flow[0][1][0], n * 8, hipMemcpyDeviceToDevice, s);
     return e;

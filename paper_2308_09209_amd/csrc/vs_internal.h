@@ -67,6 +67,11 @@ struct DevPlan {
     int32_t n_cams, n_pairs, canvas_w, canvas_h, ring, Wp, levels, pano_pitch;
     int32_t color_window, min_pixels, use_flow, balance, lambda_pct, lk_radius, lk_iters;
     int32_t readings;                 // VS_READ_* mask
+    // variational flow (use_flow = 2): weights, steps, and per level the
+    // 256-pixel blocks of every field (prefix sums over fields 2 p + d)
+    float var_alpha, var_gamma;
+    int32_t var_outer, var_inner;
+    int32_t var_off[MAXL][2 * MAXP + 1];
     float lk_lambda;
     double ridge;
     int32_t cam_w[MAXC], cam_h[MAXC], cam_pitch[MAXC];
@@ -101,6 +106,9 @@ struct DevPlan {
     float* pyr[MAXP][2][MAXL];         // [h_l][w_l]
     float2* flow[MAXP][2][MAXL];       // [h_l][w_l], [0] = flow_ij, [1] = flow_ji
     uint8_t* need[MAXP][MAXL];         // [h_l][w_l] 1 where the flow is estimated (static)
+    float* var_D[MAXP][2][MAXL];       // flow = 2: per camera, 5 planes [h_l][w_l]: Dx Dy Dxx Dxy Dyy
+    float* var_co[MAXP][2][MAXL];      // flow = 2: per direction, 8 planes: Iz Ix Iy Ixz Iyz Ixx Ixy Iyy
+    float2* var_dd[MAXP][2][MAXL][2];  // flow = 2: per direction, the increments (ping-pong)
     uint4* lk_queue[MAXL];             // deferred flow pixels: {field | iter << 8, x | y << 16, ux, uy}
     int32_t lk_qcap[MAXL];
     uint32_t* cover;                   // [canvas_h][cover_words] coverage bits
@@ -173,6 +181,7 @@ hipError_t launch_pyr0(const Group& g, int phase, hipStream_t s);
 hipError_t launch_pyr_fused(const Group& g, int phase, hipStream_t s);
 hipError_t launch_pyr_down(const Group& g, int level, int phase, hipStream_t s);
 hipError_t launch_lk(const Group& g, int level, hipStream_t s);
+hipError_t launch_var(const Group& g, int level, hipStream_t s);   // vs_var.hip
 hipError_t launch_surrogate(const Group& g, hipStream_t s);   // vs_surr.hip
 bool surrogate_active(const Group& g, int c);
 hipError_t launch_surrogate_ctx(const Group& g, int c, hipStream_t s);
@@ -190,7 +199,7 @@ hipError_t launch_fill_u8(uint8_t* p, size_t n, uint8_t v, hipStream_t s);
 
 // workspace of a plain-flow context (vs_flow_create, vs_flow_run_noalloc)
 struct FlowLayout {
-    size_t need[MAXL], pyr[2][MAXL], flow[2][MAXL], queue[MAXL], acc, res, state, bytes;
+    size_t need[MAXL], pyr[2][MAXL], flow[2][MAXL], queue[MAXL], var, acc, res, state, bytes;
 };
 // vs_host.cpp
 bool flow_plan(int w, int h, const vs_params& P, DevPlan& d, FlowLayout& L);

@@ -1,0 +1,275 @@
+// vs_var.hip -- the variational alternative of the section 3.2 flow (flow = 2):
+// coarse-to-fine warping with brightness and gradient constancy, a
+// Charbonnier smoothness term and lagged Jacobi steps, on the same pyramids
+// and flow domain as the plain estimator.  Every kernel is one pixel per
+// thread over every field (pair x direction, or pair x camera for the
+// derivatives) of every context in the group; FP32 in one prescribed order,
+// correctly rounded division and square root.
+#include "vs_device.h"
+
+namespace vs {
+namespace {
+
+constexpr float VAR_EPS2 = 0.01f;   // Charbonnier epsilon^2 (epsilon = 0.1 luma)
+
+// field f of level l for block b (fields of 256-pixel blocks, var_off)
+__device__ __forceinline__ bool var_pixel(const DevPlan* __restrict__ P, int l, int b, int& f, int& x, int& y,
+                                          int& w, int& h)
+{
+    f = find_field(P->var_off[l], 2 * P->n_pairs, b);
+    const int p = f >> 1;
+    w = P->lw[p][l];
+    h = P->lh[p][l];
+    const int i = (b - P->var_off[l][f]) * 256 + (int)threadIdx.x;
+    if (i >= w * h) return false;
+    x = i % w;
+    y = i / w;
+    return true;
+}
+
+__device__ __forceinline__ float at_clamped(const float* __restrict__ a, int w, int h, int x, int y)
+{
+    return a[(size_t)clampi(y, 0, h - 1) * w + clampi(x, 0, w - 1)];
+}
+
+__device__ __forceinline__ float cdx(const float* __restrict__ a, int w, int h, int x, int y)
+{
+    return 0.5f * (at_clamped(a, w, h, x + 1, y) - at_clamped(a, w, h, x - 1, y));
+}
+
+__device__ __forceinline__ float cdy(const float* __restrict__ a, int w, int h, int x, int y)
+{
+    return 0.5f * (at_clamped(a, w, h, x, y + 1) - at_clamped(a, w, h, x, y - 1));
+}
+
+// bilinear sample of a level plane at (X, Y), the position clamped into it
+__device__ __forceinline__ float bil(const float* __restrict__ a, int w, int h, float X, float Y)
+{
+    const float cx = clampf(X, 0.0f, (float)(w - 1)), cy = clampf(Y, 0.0f, (float)(h - 1));
+    const float flx = floorf(cx), fly = floorf(cy);
+    const int x0 = (int)flx, y0 = (int)fly;
+    const float fx = cx - flx, fy = cy - fly;
+    const int x1 = x0 + 1 < w ? x0 + 1 : w - 1, y1 = y0 + 1 < h ? y0 + 1 : h - 1;
+    const float p00 = a[(size_t)y0 * w + x0], p10 = a[(size_t)y0 * w + x1];
+    const float p01 = a[(size_t)y1 * w + x0], p11 = a[(size_t)y1 * w + x1];
+    const float t = __builtin_fmaf(fx, p10 - p00, p00);
+    const float b = __builtin_fmaf(fx, p11 - p01, p01);
+    return __builtin_fmaf(fy, b - t, t);
+}
+
+// Derivative planes of each camera's level image (field f = 2 p + camera):
+// Dx, Dy central differences with clamped indices; Dxx, Dxy the central
+// differences of Dx, Dyy of Dy (the first differences taken at the clamped
+// neighbours, as the planes they are differences of).
+__global__ __launch_bounds__(256) void k_var_deriv(const Batch B, int l)
+{
+    int c;
+    const int b = batch_block(B, blockIdx.x, c);
+    const DevPlan* __restrict__ P = B.plan[c];
+    int f, x, y, w, h;
+    if (!var_pixel(P, l, b, f, x, y, w, h)) return;
+    const int p = f >> 1, cam = f & 1;
+    if (kept_by_surrogate(P, p)) return;
+    const float* __restrict__ I = P->pyr[p][cam][l];
+    float* __restrict__ D = P->var_D[p][cam][l];
+    const size_t n = (size_t)w * h, q = (size_t)y * w + x;
+    const int xm = clampi(x - 1, 0, w - 1), xp = clampi(x + 1, 0, w - 1);
+    const int ym = clampi(y - 1, 0, h - 1), yp = clampi(y + 1, 0, h - 1);
+    D[q] = cdx(I, w, h, x, y);
+    D[n + q] = cdy(I, w, h, x, y);
+    D[2 * n + q] = 0.5f * (cdx(I, w, h, xp, y) - cdx(I, w, h, xm, y));
+    D[3 * n + q] = 0.5f * (cdx(I, w, h, x, yp) - cdx(I, w, h, x, ym));
+    D[4 * n + q] = 0.5f * (cdy(I, w, h, x, yp) - cdy(I, w, h, x, ym));
+}
+
+// Level start: the flow is 0 at the coarsest level, else 2 x the bilinear
+// sample of the coarser level's flow at (x / 2 - 1/4, y / 2 - 1/4).
+__global__ __launch_bounds__(256) void k_var_init(const Batch B, int l)
+{
+    int c;
+    const int b = batch_block(B, blockIdx.x, c);
+    const DevPlan* __restrict__ P = B.plan[c];
+    int f, x, y, w, h;
+    if (!var_pixel(P, l, b, f, x, y, w, h)) return;
+    const int p = f >> 1, dir = f & 1;
+    if (kept_by_surrogate(P, p)) return;
+    float ux = 0.0f, uy = 0.0f;
+    if (l + 1 < P->levels) {
+        const int wc = P->lw[p][l + 1], hc = P->lh[p][l + 1];
+        const float2* __restrict__ uc = P->flow[p][dir][l + 1];
+        const float cx = clampf(__builtin_fmaf((float)x, 0.5f, -0.25f), 0.0f, (float)(wc - 1));
+        const float cy = clampf(__builtin_fmaf((float)y, 0.5f, -0.25f), 0.0f, (float)(hc - 1));
+        const float flx = floorf(cx), fly = floorf(cy);
+        const int xa = (int)flx, ya = (int)fly;
+        const float fx = cx - flx, fy = cy - fly;
+        const int xb = xa + 1 < wc ? xa + 1 : wc - 1, yb = ya + 1 < hc ? ya + 1 : hc - 1;
+        const float2 p00 = uc[(size_t)ya * wc + xa], p10 = uc[(size_t)ya * wc + xb];
+        const float2 p01 = uc[(size_t)yb * wc + xa], p11 = uc[(size_t)yb * wc + xb];
+        float a = __builtin_fmaf(fx, p10.x - p00.x, p00.x);
+        float bb = __builtin_fmaf(fx, p11.x - p01.x, p01.x);
+        ux = 2.0f * __builtin_fmaf(fy, bb - a, a);
+        a = __builtin_fmaf(fx, p10.y - p00.y, p00.y);
+        bb = __builtin_fmaf(fx, p11.y - p01.y, p01.y);
+        uy = 2.0f * __builtin_fmaf(fy, bb - a, a);
+    }
+    P->flow[p][dir][l][(size_t)y * w + x] = make_float2(ux, uy);
+}
+
+// One warp: the moving image and its derivatives sampled at x + (u, v), the
+// data and gradient terms' coefficients (Iz Ix Iy Ixz Iyz Ixx Ixy Iyy), and
+// the increments reset.  With `fold` the previous warp's increments are first
+// added to the flow.
+__global__ __launch_bounds__(256) void k_var_warp(const Batch B, int l, int fold)
+{
+    int c;
+    const int b = batch_block(B, blockIdx.x, c);
+    const DevPlan* __restrict__ P = B.plan[c];
+    int f, x, y, w, h;
+    if (!var_pixel(P, l, b, f, x, y, w, h)) return;
+    const int p = f >> 1, dir = f & 1;
+    if (kept_by_surrogate(P, p)) return;
+    const int tc = dir == 0 ? 0 : 1, mc = 1 - tc;
+    const size_t n = (size_t)w * h, q = (size_t)y * w + x;
+    float2* __restrict__ U = P->flow[p][dir][l];
+    float2* __restrict__ dd = P->var_dd[p][dir][l][0];
+    float2 u = U[q];
+    if (fold) {
+        const float2 d = dd[q];
+        u = make_float2(u.x + d.x, u.y + d.y);
+        U[q] = u;
+    }
+    const float X = (float)x + u.x, Y = (float)y + u.y;
+    const float* __restrict__ Mv = P->pyr[p][mc][l];
+    const float* __restrict__ MD = P->var_D[p][mc][l];
+    const float* __restrict__ TD = P->var_D[p][tc][l];
+    const float mw = bil(Mv, w, h, X, Y), mx = bil(MD, w, h, X, Y), my = bil(MD + n, w, h, X, Y);
+    float* __restrict__ co = P->var_co[p][dir][l];
+    co[q] = mw - P->pyr[p][tc][l][q];
+    co[n + q] = mx;
+    co[2 * n + q] = my;
+    co[3 * n + q] = mx - TD[q];
+    co[4 * n + q] = my - TD[n + q];
+    co[5 * n + q] = bil(MD + 2 * n, w, h, X, Y);
+    co[6 * n + q] = bil(MD + 3 * n, w, h, X, Y);
+    co[7 * n + q] = bil(MD + 4 * n, w, h, X, Y);
+    dd[q] = make_float2(0.0f, 0.0f);
+}
+
+// the smoothness Psi' at (x, y): forward differences of U = u + du, V = v + dv
+// (0 beyond the last column / row)
+__device__ __forceinline__ float smooth_w(const float2* __restrict__ U, const float2* __restrict__ d, int w, int h,
+                                          int x, int y)
+{
+    const size_t q = (size_t)y * w + x;
+    const float2 a = U[q], da = d[q];
+    const float u0 = a.x + da.x, v0 = a.y + da.y;
+    float ux = 0.0f, uy = 0.0f, vx = 0.0f, vy = 0.0f;
+    if (x + 1 < w) {
+        const float2 r = U[q + 1], dr = d[q + 1];
+        ux = (r.x + dr.x) - u0;
+        vx = (r.y + dr.y) - v0;
+    }
+    if (y + 1 < h) {
+        const float2 r = U[q + w], dr = d[q + w];
+        uy = (r.x + dr.x) - u0;
+        vy = (r.y + dr.y) - v0;
+    }
+    const float s = __builtin_fmaf(ux, ux, __builtin_fmaf(uy, uy, __builtin_fmaf(vx, vx, __builtin_fmaf(vy, vy, VAR_EPS2))));
+    return 0.5f / sqrtf(s);
+}
+
+// One Jacobi step of the linearised equations, increments src -> dst.
+__global__ __launch_bounds__(256) void k_var_jacobi(const Batch B, int l, int src)
+{
+    int c;
+    const int b = batch_block(B, blockIdx.x, c);
+    const DevPlan* __restrict__ P = B.plan[c];
+    int f, x, y, w, h;
+    if (!var_pixel(P, l, b, f, x, y, w, h)) return;
+    const int p = f >> 1, dir = f & 1;
+    if (kept_by_surrogate(P, p)) return;
+    const size_t n = (size_t)w * h, q = (size_t)y * w + x;
+    const float2* __restrict__ U = P->flow[p][dir][l];
+    const float2* __restrict__ d = P->var_dd[p][dir][l][src];
+    const float* __restrict__ co = P->var_co[p][dir][l];
+    const float alpha = P->var_alpha, gamma = P->var_gamma;
+    const float2 u = U[q], dq = d[q];
+    float A11 = 0.0f, A12 = 0.0f, A22 = 0.0f, b1 = 0.0f, b2 = 0.0f;
+    if (P->need[p][l][q]) {
+        const float c0 = co[q], c1 = co[n + q], c2 = co[2 * n + q], c3 = co[3 * n + q];
+        const float c4 = co[4 * n + q], c5 = co[5 * n + q], c6 = co[6 * n + q], c7 = co[7 * n + q];
+        const float e = __builtin_fmaf(c2, dq.y, __builtin_fmaf(c1, dq.x, c0));
+        const float pd = 0.5f / sqrtf(__builtin_fmaf(e, e, VAR_EPS2));
+        const float gx = __builtin_fmaf(c6, dq.y, __builtin_fmaf(c5, dq.x, c3));
+        const float gy = __builtin_fmaf(c7, dq.y, __builtin_fmaf(c6, dq.x, c4));
+        const float pg = gamma * (0.5f / sqrtf(__builtin_fmaf(gx, gx, __builtin_fmaf(gy, gy, VAR_EPS2))));
+        A11 = __builtin_fmaf(pd, c1 * c1, pg * __builtin_fmaf(c5, c5, c6 * c6));
+        A12 = __builtin_fmaf(pd, c1 * c2, pg * __builtin_fmaf(c5, c6, c6 * c7));
+        A22 = __builtin_fmaf(pd, c2 * c2, pg * __builtin_fmaf(c6, c6, c7 * c7));
+        b1 = -__builtin_fmaf(pd, c1 * c0, pg * __builtin_fmaf(c5, c3, c6 * c4));
+        b2 = -__builtin_fmaf(pd, c2 * c0, pg * __builtin_fmaf(c6, c3, c7 * c4));
+    }
+    const float s0 = smooth_w(U, d, w, h, x, y);
+    float S = 0.0f, Su = 0.0f, Sv = 0.0f;
+    const int nx[4] = {x - 1, x + 1, x, x};
+    const int ny[4] = {y, y, y - 1, y + 1};
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        if (nx[k] < 0 || nx[k] >= w || ny[k] < 0 || ny[k] >= h) continue;
+        const size_t qn = (size_t)ny[k] * w + nx[k];
+        const float wn = 0.5f * (s0 + smooth_w(U, d, w, h, nx[k], ny[k]));
+        const float2 un = U[qn], dn = d[qn];
+        S += wn;
+        Su = __builtin_fmaf(wn, (un.x + dn.x) - u.x, Su);
+        Sv = __builtin_fmaf(wn, (un.y + dn.y) - u.y, Sv);
+    }
+    const float dx = __builtin_fmaf(alpha, Su, __builtin_fmaf(-A12, dq.y, b1)) / __builtin_fmaf(alpha, S, A11);
+    const float dy = __builtin_fmaf(alpha, Sv, __builtin_fmaf(-A12, dq.x, b2)) / __builtin_fmaf(alpha, S, A22);
+    P->var_dd[p][dir][l][src ^ 1][q] = make_float2(dx, dy);
+}
+
+// the last warp's increments added to the flow
+__global__ __launch_bounds__(256) void k_var_fold(const Batch B, int l)
+{
+    int c;
+    const int b = batch_block(B, blockIdx.x, c);
+    const DevPlan* __restrict__ P = B.plan[c];
+    int f, x, y, w, h;
+    if (!var_pixel(P, l, b, f, x, y, w, h)) return;
+    const int p = f >> 1, dir = f & 1;
+    if (kept_by_surrogate(P, p)) return;
+    const size_t q = (size_t)y * w + x;
+    float2* __restrict__ U = P->flow[p][dir][l];
+    const float2 u = U[q], d = P->var_dd[p][dir][l][0][q];
+    U[q] = make_float2(u.x + d.x, u.y + d.y);
+}
+
+}  // namespace
+
+// The variational flow of one level for every context of the group (their
+// flow = 2): derivatives, initialisation, `var_outer` warps of `var_inner`
+// Jacobi steps each (even steps end in increment buffer 0), the last
+// increments folded in.
+hipError_t launch_var(const Group& g, int l, hipStream_t s)
+{
+    Batch B;
+    auto blocks = [&](const DevPlan& h) {
+        return h.use_flow == 2 && h.flow_mode != VS_FLOW_SURROGATE && l < h.levels ? h.var_off[l][2 * h.n_pairs] : 0;
+    };
+    if (!make_batch(g, B, blocks)) return hipSuccess;
+    const dim3 grid(B.off[B.n]), blk(256);
+    int outer = g.hp[0]->var_outer, inner = g.hp[0]->var_inner;
+    for (int c = 1; c < g.n; ++c)
+        if (g.hp[c]->var_outer != outer || g.hp[c]->var_inner != inner) return hipErrorInvalidValue;
+    if (inner % 2) return hipErrorInvalidValue;   // the steps end in buffer 0
+    hipLaunchKernelGGL(k_var_deriv, grid, blk, 0, s, B, l);
+    hipLaunchKernelGGL(k_var_init, grid, blk, 0, s, B, l);
+    for (int o = 0; o < outer; ++o) {
+        hipLaunchKernelGGL(k_var_warp, grid, blk, 0, s, B, l, o > 0 ? 1 : 0);
+        for (int it = 0; it < inner; ++it) hipLaunchKernelGGL(k_var_jacobi, grid, blk, 0, s, B, l, it & 1);
+    }
+    if (outer > 0) hipLaunchKernelGGL(k_var_fold, grid, blk, 0, s, B, l);
+    return hipGetLastError();
+}
+
+}  // namespace vs

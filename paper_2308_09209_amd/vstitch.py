@@ -44,7 +44,8 @@ EXPORTS = ["vs_abi_version", "vs_status_str", "vs_default_params", "vs_compose_h
            "vs_nn_lrelu_bwd", "vs_nn_pack_pair", "vs_nn_epe_loss", "vs_nn_adam", "vs_nn_to_bf16",
            "vs_nn_pool_flow", "vs_nn_create", "vs_nn_destroy", "vs_nn_forward", "vs_nn_loss", "vs_nn_backward",
            "vs_nn_adam_step", "vs_nn_params", "vs_nn_save", "vs_nn_load", "vs_flow_create", "vs_flow_run", "vs_flow_destroy", "vs_flow_level",
-           "vs_flow_run_noalloc"]
+           "vs_flow_run_noalloc", "vs_calib_intrinsics", "vs_calib_plane_homography", "vs_calib_pair",
+           "vs_calib_refine", "vs_calib_estimate"]
 
 
 class Rig(C.Structure):
@@ -60,7 +61,8 @@ class Params(C.Structure):
                 ("flow", C.c_int32), ("lk_levels", C.c_int32), ("lk_iters", C.c_int32),
                 ("lk_radius", C.c_int32), ("lk_lambda", C.c_float), ("balance", C.c_int32),
                 ("lambda_pct", C.c_int32), ("debug_taps", C.c_int32), ("pyr_tile_rows", C.c_int32),
-                ("readings", C.c_int32)]
+                ("readings", C.c_int32), ("var_alpha", C.c_float), ("var_gamma", C.c_float),
+                ("var_outer", C.c_int32), ("var_inner", C.c_int32)]
 
 
 READ_OVERLAP_ONLY, READ_LITERAL_EQ17, READ_NEAREST_CDF = 1, 2, 4
@@ -198,6 +200,13 @@ def lib():
         L.vs_flow_destroy.argtypes = [vp]
         L.vs_flow_level.argtypes = [vp, i32, vp, vp, C.POINTER(C.c_int32), C.POINTER(C.c_int32), vp]
         L.vs_flow_run_noalloc.argtypes = [i32, i32, C.POINTER(Params), vp, vp, vp, vp, vp]
+        dbl = C.c_double
+        L.vs_calib_intrinsics.argtypes = [dbl] * 7 + [vp]
+        L.vs_calib_plane_homography.argtypes = [vp, vp, vp, vp]
+        L.vs_calib_pair.argtypes = [vp, vp, vp]
+        L.vs_calib_refine.argtypes = [vp, vp, vp]
+        L.vs_calib_estimate.argtypes = [vp, i32, i32, i32, vp, i32, i32, i32, vp, i32, i32, vp,
+                                        C.POINTER(C.c_int32), C.POINTER(C.c_int32), vp]
         _lib = L
     return _lib
 
@@ -576,3 +585,58 @@ def flow_run_noalloc(yt, ym, flow_tm=None, flow_mt=None, stream=None, **params):
                                     _p(outs[1]) if outs[1] is not False else None, _stream_handle(stream)),
           "vs_flow_run_noalloc")
     return outs[0], outs[1]
+
+
+# ---- section 3.1 set-up ----------------------------------------------------
+
+def _d(a, n):
+    return np.ascontiguousarray(np.asarray(a, np.float64).reshape(n))
+
+
+def calib_intrinsics(f, dx, dy, cx, cy, u0, v0):
+    K = np.zeros(9)
+    check(lib().vs_calib_intrinsics(f, dx, dy, cx, cy, u0, v0, K.ctypes.data_as(C.c_void_p)), "vs_calib_intrinsics")
+    return K.reshape(3, 3)
+
+
+def calib_plane_homography(K, R, t):
+    H = np.zeros(9)
+    k, r, tt = _d(K, 9), _d(R, 9), _d(t, 3)
+    check(lib().vs_calib_plane_homography(k.ctypes.data_as(C.c_void_p), r.ctypes.data_as(C.c_void_p),
+                                          tt.ctypes.data_as(C.c_void_p), H.ctypes.data_as(C.c_void_p)),
+          "vs_calib_plane_homography")
+    return H.reshape(3, 3)
+
+
+def calib_pair(Ha, Hb):
+    H = np.zeros(9)
+    a, b = _d(Ha, 9), _d(Hb, 9)
+    check(lib().vs_calib_pair(a.ctypes.data_as(C.c_void_p), b.ctypes.data_as(C.c_void_p),
+                              H.ctypes.data_as(C.c_void_p)), "vs_calib_pair")
+    return H.reshape(3, 3)
+
+
+def calib_refine(H, p):
+    out = np.zeros(9)
+    h, pp = _d(H, 9), _d(p, 4)
+    check(lib().vs_calib_refine(h.ctypes.data_as(C.c_void_p), pp.ctypes.data_as(C.c_void_p),
+                                out.ctypes.data_as(C.c_void_p)), "vs_calib_refine")
+    return out.reshape(3, 3)
+
+
+def calib_estimate(frame_a, frame_b, H, margin=16, radius=4, stream=None):
+    """(p = (tx, ty, sx, sy) or None, matches, inliers) for device frames a, b
+    (uint8 HWC) and the pre-warp H (a pixels -> b pixels)"""
+    for f in (frame_a, frame_b):
+        if f.dtype != torch.uint8 or not f.is_cuda or f.dim() != 3 or f.shape[2] != 3 or not f.is_contiguous():
+            raise ValueError("frames: contiguous cuda uint8 (h, w, 3)")
+    h = _d(H, 9)
+    p = np.zeros(4)
+    nm, ni = C.c_int32(), C.c_int32()
+    st = lib().vs_calib_estimate(_p(frame_a), frame_a.shape[1] * 3, frame_a.shape[1], frame_a.shape[0], _p(frame_b),
+                                 frame_b.shape[1] * 3, frame_b.shape[1], frame_b.shape[0],
+                                 h.ctypes.data_as(C.c_void_p), margin, radius, p.ctypes.data_as(C.c_void_p),
+                                 C.byref(nm), C.byref(ni), _stream_handle(stream))
+    if st not in (0, -1):
+        raise VSError(st, "vs_calib_estimate")
+    return (p if st == 0 else None), nm.value, ni.value

@@ -164,3 +164,35 @@ def test_create_rejects_unknown_readings():
     h = C.c_void_p()
     assert V.lib().vs_create(C.byref(rig), C.byref(p), C.byref(h)) == -1
     assert not h.value
+
+
+def test_create_rejects_bad_variational_weights():
+    """flow = 2 with an odd number of Jacobi steps, a non-positive smoothness
+    weight or a negative gradient weight is refused by both contexts before
+    any device work; flow outside 0..2 too."""
+    from paper_2308_09209_amd.scenes import small_scene
+    rig = V.make_rig(small_scene().rig())
+    for kw in (dict(var_inner=5), dict(var_alpha=0.0), dict(var_gamma=-1.0), dict(var_outer=-1), dict(flow=3)):
+        p = V.default_params(flow=kw.pop("flow", 2), **kw)
+        h = C.c_void_p()
+        assert V.lib().vs_create(C.byref(rig), C.byref(p), C.byref(h)) == -1, kw
+        assert V.lib().vs_flow_create(64, 48, C.byref(p), C.byref(h)) == -1, kw
+        assert not h.value
+
+
+def test_calibration_host_helpers_equal_the_oracle():
+    """vs_calib_* (host FP64, eqs. (8), (11), (12), (14)) against the oracle's
+    independent implementation, bit for bit."""
+    from tests.test_oracle_calib import rot
+    args = (0.006, 5e-6, 5.2e-6, 1e-5, -2e-5, 960.0, 540.0)
+    K = V.calib_intrinsics(*args)
+    np.testing.assert_array_equal(K, O.calib_intrinsics(*args))
+    R, t = rot(0.05, -0.3, 0.02), np.array([0.2, -0.1, 5.0])
+    Ha = V.calib_plane_homography(K, R, t)
+    np.testing.assert_array_equal(Ha, O.calib_plane_homography(K, R, t))
+    Hb = V.calib_plane_homography(K, rot(0.0, 0.2, 0.01), np.array([-0.3, 0.0, 5.1]))
+    np.testing.assert_array_equal(V.calib_pair(Ha, Hb), O.calib_pair(Ha, Hb))
+    p = (2.5, -1.0, 1.01, 0.98)
+    np.testing.assert_array_equal(V.calib_refine(Ha, p), O.calib_refine(Ha, p))
+    with pytest.raises(V.VSError):
+        V.calib_pair(Ha, np.zeros((3, 3)))
