@@ -710,11 +710,18 @@ static float img_at(const float* I, int w, int h, int x, int y)
  *   G = sum [Ix^2, Ix Iy; Ix Iy, Iy^2] + lambda |window| I,
  *   b = sum [Ix e, Iy e], e = bilinear(Mv, x' + u) - T(x'),
  *   du = (G01 bv - G11 bu) / det, dv = (G01 bu - G00 bv) / det.
- * The warp position x' + u is split once per step into floor(u) and
- * frac(u) so that every tap is the exact bilinear interpolation at x' + u
- * (indices clamped).  Sums run over the window in row-major order.  The
- * initial flow is 0 at the coarsest level, else twice the bilinear sample
- * of the coarser flow at ((x + 1/2)/2 - 1/2, (y + 1/2)/2 - 1/2). */
+ * The warp position x' + u is split once per step into floor(u) = (ox, oy)
+ * and frac(u) = (fx, fy) so that every tap is the exact bilinear
+ * interpolation at x' + u (indices clamped): with ht, hb the moving image
+ * interpolated along x on rows y' + oy and y' + oy + 1, the sample is
+ * ht + fy (hb - ht).  b is evaluated with the sums regrouped (the same sum,
+ * another FP32 rounding order; vso_lk_level_f64 below keeps the plain form):
+ *   bu = (SA + fy (SB - SA)) - C, SA = sum Ix ht, SB = sum Ix hb,
+ *   C = sum Ix T (once per level), and bv alike with Iy,
+ * so the interpolation along y happens once per window instead of per tap.
+ * Sums run over the window in row-major order.  The initial flow is 0 at
+ * the coarsest level, else twice the bilinear sample of the coarser flow at
+ * ((x + 1/2)/2 - 1/2, (y + 1/2)/2 - 1/2). */
 void vso_lk_level(const float* T, const float* Mv, int w, int h,
                   const float* uc, int wc, int hc,
                   int r, int iters, float lambda, const uint8_t* need, float* u_out)
@@ -751,14 +758,17 @@ void vso_lk_level(const float* T, const float* Mv, int w, int h,
             }
             int wx0 = x - r < 0 ? 0 : x - r, wx1 = x + r > w - 1 ? w - 1 : x + r;
             int wy0 = y - r < 0 ? 0 : y - r, wy1 = y + r > h - 1 ? h - 1 : y + r;
-            float g00 = 0.0f, g01 = 0.0f, g11 = 0.0f;
+            float g00 = 0.0f, g01 = 0.0f, g11 = 0.0f, cu = 0.0f, cv = 0.0f;
             for (int yy = wy0; yy <= wy1; ++yy)
                 for (int xx = wx0; xx <= wx1; ++xx) {
                     float ix = 0.5f * (img_at(T, w, h, xx + 1, yy) - img_at(T, w, h, xx - 1, yy));
                     float iy = 0.5f * (img_at(T, w, h, xx, yy + 1) - img_at(T, w, h, xx, yy - 1));
+                    float t = T[(size_t)yy * w + xx];
                     g00 = fmaf(ix, ix, g00);
                     g01 = fmaf(ix, iy, g01);
                     g11 = fmaf(iy, iy, g11);
+                    cu = fmaf(ix, t, cu);
+                    cv = fmaf(iy, t, cv);
                 }
             float reg = lambda * (float)((wy1 - wy0 + 1) * (wx1 - wx0 + 1));
             g00 = g00 + reg;
@@ -768,22 +778,24 @@ void vso_lk_level(const float* T, const float* Mv, int w, int h,
                 float flx = floorf(ux), fly = floorf(uy);
                 int ox = (int)flx, oy = (int)fly;
                 float fx = ux - flx, fy = uy - fly;
-                float bu = 0.0f, bv = 0.0f;
+                float sau = 0.0f, sav = 0.0f, sbu = 0.0f, sbv = 0.0f;
                 for (int yy = wy0; yy <= wy1; ++yy)
                     for (int xx = wx0; xx <= wx1; ++xx) {
                         float p00 = img_at(Mv, w, h, xx + ox, yy + oy);
                         float p10 = img_at(Mv, w, h, xx + ox + 1, yy + oy);
                         float p01 = img_at(Mv, w, h, xx + ox, yy + oy + 1);
                         float p11 = img_at(Mv, w, h, xx + ox + 1, yy + oy + 1);
-                        float a = fmaf(fx, p10 - p00, p00);
-                        float b = fmaf(fx, p11 - p01, p01);
-                        float m = fmaf(fy, b - a, a);
-                        float e = m - T[(size_t)yy * w + xx];
+                        float ht = fmaf(fx, p10 - p00, p00);
+                        float hb = fmaf(fx, p11 - p01, p01);
                         float ix = 0.5f * (img_at(T, w, h, xx + 1, yy) - img_at(T, w, h, xx - 1, yy));
                         float iy = 0.5f * (img_at(T, w, h, xx, yy + 1) - img_at(T, w, h, xx, yy - 1));
-                        bu = fmaf(ix, e, bu);
-                        bv = fmaf(iy, e, bv);
+                        sau = fmaf(ix, ht, sau);
+                        sav = fmaf(iy, ht, sav);
+                        sbu = fmaf(ix, hb, sbu);
+                        sbv = fmaf(iy, hb, sbv);
                     }
+                float bu = fmaf(fy, sbu - sau, sau) - cu;
+                float bv = fmaf(fy, sbv - sav, sav) - cv;
                 float du = (g01 * bv - g11 * bu) / det;
                 float dv = (g01 * bu - g00 * bv) / det;
                 ux = ux + du;

@@ -104,14 +104,17 @@ __device__ __forceinline__ void lk_body(const DevPlan* __restrict__ P, const int
     const int r = P->lk_radius;
     const int wx0 = x - r < 0 ? 0 : x - r, wx1 = x + r > w - 1 ? w - 1 : x + r;
     const int wy0 = y - r < 0 ? 0 : y - r, wy1 = y + r > h - 1 ? h - 1 : y + r;
-    float g00 = 0.0f, g01 = 0.0f, g11 = 0.0f;
+    float g00 = 0.0f, g01 = 0.0f, g11 = 0.0f, cu = 0.0f, cv = 0.0f;
     for (int yy = wy0; yy <= wy1; ++yy)
         for (int xx = wx0; xx <= wx1; ++xx) {
             float ix = sIx[yy - y0 + LK_R_MAX][xx - x0 + LK_R_MAX];
             float iy = sIy[yy - y0 + LK_R_MAX][xx - x0 + LK_R_MAX];
+            float t = sT[yy - y0 + LK_HT][xx - x0 + LK_HT];
             g00 = __builtin_fmaf(ix, ix, g00);
             g01 = __builtin_fmaf(ix, iy, g01);
             g11 = __builtin_fmaf(iy, iy, g11);
+            cu = __builtin_fmaf(ix, t, cu);
+            cv = __builtin_fmaf(iy, t, cv);
         }
     const float reg = P->lk_lambda * (float)((wy1 - wy0 + 1) * (wx1 - wx0 + 1));
     g00 = g00 + reg;
@@ -122,24 +125,27 @@ __device__ __forceinline__ void lk_body(const DevPlan* __restrict__ P, const int
         const float flx = floorf(ux), fly = floorf(uy);
         const int ox = (int)flx, oy = (int)fly;
         const float fx = ux - flx, fy = uy - fly;
-        float bu = 0.0f, bv = 0.0f;
+        // right-hand side regrouped: b = (SA + fy (SB - SA)) - C, SA / SB the
+        // gradient-weighted sums of the moving image interpolated along x on
+        // the top / bottom row of each tap
+        float sau = 0.0f, sav = 0.0f, sbu = 0.0f, sbv = 0.0f;
         const bool fast = ox >= -(LK_D + 1) && ox <= LK_D && oy >= -(LK_D + 1) && oy <= LK_D;
         if (fast) {
             for (int yy = wy0; yy <= wy1; ++yy) {
                 const float* m0 = sM[yy + oy - y0 + LK_HM];
                 const float* m1 = sM[yy + oy + 1 - y0 + LK_HM];
-                const float* tr = sT[yy - y0 + LK_HT];
                 const float* gxr = sIx[yy - y0 + LK_R_MAX];
                 const float* gyr = sIy[yy - y0 + LK_R_MAX];
                 for (int xx = wx0; xx <= wx1; ++xx) {
                     const int cx = xx + ox - x0 + LK_HM;
                     float p00 = m0[cx], p10 = m0[cx + 1], p01 = m1[cx], p11 = m1[cx + 1];
-                    float a = __builtin_fmaf(fx, p10 - p00, p00);
-                    float b = __builtin_fmaf(fx, p11 - p01, p01);
-                    float m = __builtin_fmaf(fy, b - a, a);
-                    float e = m - tr[xx - x0 + LK_HT];
-                    bu = __builtin_fmaf(gxr[xx - x0 + LK_R_MAX], e, bu);
-                    bv = __builtin_fmaf(gyr[xx - x0 + LK_R_MAX], e, bv);
+                    float ht = __builtin_fmaf(fx, p10 - p00, p00);
+                    float hb = __builtin_fmaf(fx, p11 - p01, p01);
+                    const float ix = gxr[xx - x0 + LK_R_MAX], iy = gyr[xx - x0 + LK_R_MAX];
+                    sau = __builtin_fmaf(ix, ht, sau);
+                    sav = __builtin_fmaf(iy, ht, sav);
+                    sbu = __builtin_fmaf(ix, hb, sbu);
+                    sbv = __builtin_fmaf(iy, hb, sbv);
                 }
             }
         } else {
@@ -149,15 +155,19 @@ __device__ __forceinline__ void lk_body(const DevPlan* __restrict__ P, const int
                 for (int xx = wx0; xx <= wx1; ++xx) {
                     const int xa = clampi(xx + ox, 0, w - 1), xb = clampi(xx + ox + 1, 0, w - 1);
                     float p00 = m0[xa], p10 = m0[xb], p01 = m1[xa], p11 = m1[xb];
-                    float a = __builtin_fmaf(fx, p10 - p00, p00);
-                    float b = __builtin_fmaf(fx, p11 - p01, p01);
-                    float m = __builtin_fmaf(fy, b - a, a);
-                    float e = m - sT[yy - y0 + LK_HT][xx - x0 + LK_HT];
-                    bu = __builtin_fmaf(sIx[yy - y0 + LK_R_MAX][xx - x0 + LK_R_MAX], e, bu);
-                    bv = __builtin_fmaf(sIy[yy - y0 + LK_R_MAX][xx - x0 + LK_R_MAX], e, bv);
+                    float ht = __builtin_fmaf(fx, p10 - p00, p00);
+                    float hb = __builtin_fmaf(fx, p11 - p01, p01);
+                    const float ix = sIx[yy - y0 + LK_R_MAX][xx - x0 + LK_R_MAX];
+                    const float iy = sIy[yy - y0 + LK_R_MAX][xx - x0 + LK_R_MAX];
+                    sau = __builtin_fmaf(ix, ht, sau);
+                    sav = __builtin_fmaf(iy, ht, sav);
+                    sbu = __builtin_fmaf(ix, hb, sbu);
+                    sbv = __builtin_fmaf(iy, hb, sbv);
                 }
             }
         }
+        const float bu = __builtin_fmaf(fy, sbu - sau, sau) - cu;
+        const float bv = __builtin_fmaf(fy, sbv - sav, sav) - cv;
         const float du = (g01 * bv - g11 * bu) / det;
         const float dv = (g01 * bu - g00 * bv) / det;
         ux = ux + du;
@@ -176,13 +186,16 @@ __global__ __launch_bounds__(256) void k_lk(const Batch B, int l)
 // 9x9-window form of the same estimator (radius 4), P vertically adjacent
 // pixels per thread, a 64 x 4P block tile.  Identical arithmetic in identical
 // order; what changes is data movement:
-//  - (T, Ix, Iy) of every window position sit in one float4 in LDS, with
-//    Ix = Iy = 0 outside the level, so a clipped window needs no predicate:
-//    such a tap adds fma(0, e, acc) = acc exactly (acc is never -0);
-//  - the P pixels of a thread share each (T, Ix, Iy) row they have in common;
-//  - per pixel the horizontally interpolated moving-image rows slide down the
-//    window in registers: the bottom row of window row r is the top row of
-//    window row r + 1, so each tap costs ~1.1 moving-image LDS reads.
+//  - the template gradients (Ix, Iy) of every window position sit in one
+//    float2 in LDS, zero outside the level, so a clipped window needs no
+//    predicate: such a tap adds fma(0, h, acc) = acc exactly (acc is never -0);
+//  - the P pixels of a thread share each gradient row they have in common;
+//  - per pixel each row of the moving image is interpolated along x once per
+//    step and used at once by the two window rows it serves: as the top row
+//    of window row k (sums SA) and the bottom row of window row k - 1 (SB).
+// ALT keeps the previous gradient row in a second register set (the row
+// loop unrolled by two, no copies); without it that row is read again from
+// LDS (fewer registers).
 // INBLOCK: the block finishes its own deferred pixels at its end (the tail
 // kernel's per-pixel routine, same arithmetic) instead of queueing them: the
 // launches of contexts whose pairs may keep the surrogate's flows, where the
@@ -190,48 +203,52 @@ __global__ __launch_bounds__(256) void k_lk(const Batch B, int l)
 __device__ __forceinline__ void lk_tail_pixel(const DevPlan* __restrict__ Pl, int l, int f, int x, int y, int it0,
                                               float ux, float uy);
 
-// One row j of the P pixels' windows in a Gauss-Newton step: pixel q takes
-// window row jr = j - q.  prev[q] holds the moving image's horizontally
-// interpolated window row jr of pixel q (computed here for jr = 0), next[q]
-// receives row jr + 1; then for each column the vertical interpolation, the
-// residual against the template and the two sums b, in row-major order.
-// prev and next may be the same array.
-template <int P, int TIW, int MWP>
-__device__ __forceinline__ void lk_window_row(int j, const float4* __restrict__ ti_base, const float* __restrict__ sM,
-                                              const int (&mb)[P], const float (&fx)[P], const float (&fy)[P],
-                                              float (&prev)[P][2 * LK_R_MAX + 1], float (&next)[P][2 * LK_R_MAX + 1],
-                                              float (&bu)[P], float (&bv)[P])
+// Tile row t of a Gauss-Newton step: pixel q interpolates its moving-image row
+// k = t - q along x (g_base: this thread's gradient column 0 on the wavefront's
+// first tile row); cur receives gradient row t (window row k of pixel q, sums
+// SA), prev holds row t - 1 (window row k - 1, sums SB), read again from LDS
+// when LOAD_PREV.
+template <int P, int TIW, int MWP, bool LOAD_PREV>
+__device__ __forceinline__ void lk_rhs_row(int t, const float2* __restrict__ g_base, const float* __restrict__ sM,
+                                           const int (&mb)[P], const float (&fx)[P],
+                                           float2 (&cur)[2 * LK_R_MAX + 1], float2 (&prev)[2 * LK_R_MAX + 1],
+                                           float (&sau)[P], float (&sav)[P], float (&sbu)[P], float (&sbv)[P])
 {
-    constexpr int R = LK_R_MAX, NW = 2 * R + 1;
-    float4 ti[NW];
+    constexpr int R = LK_R_MAX, NW = 2 * R + 1, NJ = P + 2 * R;
+    if (t < NJ) {
 #pragma unroll
-    for (int c = 0; c < NW; ++c) ti[c] = ti_base[j * TIW + c];
+        for (int c = 0; c < NW; ++c) cur[c] = g_base[t * TIW + c];
+    }
+    if (LOAD_PREV && t >= 1) {
+#pragma unroll
+        for (int c = 0; c < NW; ++c) prev[c] = g_base[(t - 1) * TIW + c];
+    }
 #pragma unroll
     for (int q = 0; q < P; ++q) {
-        const int jr = j - q;
-        if (jr < 0 || jr > 2 * R) continue;
-        if (jr == 0) {
-            const float* m0 = sM + mb[q];
-            float v0 = m0[0];
-#pragma unroll
-            for (int c = 0; c < NW; ++c) {
-                const float v1 = m0[c + 1];
-                prev[q][c] = __builtin_fmaf(fx[q], v1 - v0, v0);
-                v0 = v1;
-            }
-        }
-        const float* m1 = sM + mb[q] + (jr + 1) * MWP;
-        float v0 = m1[0];
+        const int k = t - q;
+        if (k < 0 || k > 2 * R + 1) continue;
+        const float* m = sM + mb[q] + k * MWP;
+        float hr[NW];
+        float v0 = m[0];
 #pragma unroll
         for (int c = 0; c < NW; ++c) {
-            const float v1 = m1[c + 1];
-            const float hb = __builtin_fmaf(fx[q], v1 - v0, v0);
+            const float v1 = m[c + 1];
+            hr[c] = __builtin_fmaf(fx[q], v1 - v0, v0);
             v0 = v1;
-            const float m = __builtin_fmaf(fy[q], hb - prev[q][c], prev[q][c]);
-            const float e = m - ti[c].x;
-            bu[q] = __builtin_fmaf(ti[c].y, e, bu[q]);
-            bv[q] = __builtin_fmaf(ti[c].z, e, bv[q]);
-            next[q][c] = hb;
+        }
+        if (k <= 2 * R) {
+#pragma unroll
+            for (int c = 0; c < NW; ++c) {
+                sau[q] = __builtin_fmaf(cur[c].x, hr[c], sau[q]);
+                sav[q] = __builtin_fmaf(cur[c].y, hr[c], sav[q]);
+            }
+        }
+        if (k >= 1) {
+#pragma unroll
+            for (int c = 0; c < NW; ++c) {
+                sbu[q] = __builtin_fmaf(prev[c].x, hr[c], sbu[q]);
+                sbv[q] = __builtin_fmaf(prev[c].y, hr[c], sbv[q]);
+            }
         }
     }
 }
@@ -241,14 +258,14 @@ __device__ __forceinline__ void lk_w9_body(const DevPlan* __restrict__ Pl, const
 {
     constexpr int R = LK_R_MAX, NW = 2 * R + 1;
     constexpr int TX = LKW_TX, TY = 4 * P;
-    constexpr int TIW = TX + 2 * R, TIH = TY + 2 * R;       // (T, Ix, Iy) window positions
+    constexpr int TIW = TX + 2 * R, TIH = TY + 2 * R;       // gradient window positions
     constexpr int TSW = TIW + 2, TSH = TIH + 2;             // template + gradient halo
     constexpr int HM = R + LK_D + 1;                        // moving-image halo
     constexpr int MW = TX + 2 * HM, MH = TY + 2 * HM;
     // moving-tile row pitch: a multiple of the 32 LDS banks, so lanes whose
     // displacements put them one row apart read distinct banks
     constexpr int MWP = (MW + 31) / 32 * 32;
-    __shared__ float4 sTI[TIH * TIW];
+    __shared__ float2 sG[TIH * TIW];
     __shared__ float sT[TSH * TSW];
     __shared__ float sM[MH * MWP];
 
@@ -278,7 +295,7 @@ __device__ __forceinline__ void lk_w9_body(const DevPlan* __restrict__ Pl, const
         const bool in = X >= 0 && X < w && Y >= 0 && Y < h;
         const float ix = in ? 0.5f * (sT[c + 1] - sT[c - 1]) : 0.0f;
         const float iy = in ? 0.5f * (sT[c + TSW] - sT[c - TSW]) : 0.0f;
-        sTI[i] = make_float4(sT[c], ix, iy, 0.0f);
+        sG[i] = make_float2(ix, iy);
     }
     __syncthreads();
 
@@ -288,7 +305,7 @@ __device__ __forceinline__ void lk_w9_body(const DevPlan* __restrict__ Pl, const
     const bool has_coarse = l + 1 < Pl->levels;
     const int ncx = min(x + R, w - 1) - max(x - R, 0) + 1;
     const uint8_t* __restrict__ need = Pl->need[p][l];
-    float ux[P], uy[P], g00[P], g01[P], g11[P], det[P];
+    float ux[P], uy[P], g00[P], g01[P], g11[P], cu[P], cv[P], det[P];
     bool act[P];
     int dit[P];   // step at which the pixel was deferred (-1: not deferred)
 #pragma unroll
@@ -320,26 +337,36 @@ __device__ __forceinline__ void lk_w9_body(const DevPlan* __restrict__ Pl, const
         g00[q] = 0.0f;
         g01[q] = 0.0f;
         g11[q] = 0.0f;
+        cu[q] = 0.0f;
+        cv[q] = 0.0f;
     }
     // a wavefront without a flow-domain pixel has nothing to do (no barrier follows)
     bool any_act = false;
 #pragma unroll
     for (int q = 0; q < P; ++q) any_act = any_act || act[q];
     if (!__any(any_act)) return;
-    // normal matrix: rows shared by the P pixels, row-major within each window
+    // normal matrix and template term: rows shared by the P pixels, row-major
+    // within each window
+    const float2* g_base = sG + wv * P * TIW + lane;
 #pragma unroll 1
     for (int j = 0; j < P + 2 * R; ++j) {
-        float4 ti[NW];
+        float2 g[NW];
+        float tv[NW];
 #pragma unroll
-        for (int c = 0; c < NW; ++c) ti[c] = sTI[(wv * P + j) * TIW + lane + c];
+        for (int c = 0; c < NW; ++c) {
+            g[c] = g_base[j * TIW + c];
+            tv[c] = sT[(wv * P + j + 1) * TSW + lane + c + 1];
+        }
 #pragma unroll
         for (int q = 0; q < P; ++q) {
             if (j - q < 0 || j - q > 2 * R) continue;
 #pragma unroll
             for (int c = 0; c < NW; ++c) {
-                g00[q] = __builtin_fmaf(ti[c].y, ti[c].y, g00[q]);
-                g01[q] = __builtin_fmaf(ti[c].y, ti[c].z, g01[q]);
-                g11[q] = __builtin_fmaf(ti[c].z, ti[c].z, g11[q]);
+                g00[q] = __builtin_fmaf(g[c].x, g[c].x, g00[q]);
+                g01[q] = __builtin_fmaf(g[c].x, g[c].y, g01[q]);
+                g11[q] = __builtin_fmaf(g[c].y, g[c].y, g11[q]);
+                cu[q] = __builtin_fmaf(g[c].x, tv[c], cu[q]);
+                cv[q] = __builtin_fmaf(g[c].y, tv[c], cv[q]);
             }
         }
     }
@@ -354,7 +381,7 @@ __device__ __forceinline__ void lk_w9_body(const DevPlan* __restrict__ Pl, const
     }
     const int iters = Pl->lk_iters;
     for (int it = 0; it < iters; ++it) {
-        float fx[P], fy[P], bu[P], bv[P];
+        float fx[P], fy[P], sau[P], sav[P], sbu[P], sbv[P];
         int mb[P];
 #pragma unroll
         for (int q = 0; q < P; ++q) {
@@ -362,8 +389,10 @@ __device__ __forceinline__ void lk_w9_body(const DevPlan* __restrict__ Pl, const
             int ox = (int)flx, oy = (int)fly;
             fx[q] = ux[q] - flx;
             fy[q] = uy[q] - fly;
-            bu[q] = 0.0f;
-            bv[q] = 0.0f;
+            sau[q] = 0.0f;
+            sav[q] = 0.0f;
+            sbu[q] = 0.0f;
+            sbv[q] = 0.0f;
             if (act[q] && !(ox >= -(LK_D + 1) && ox <= LK_D && oy >= -(LK_D + 1) && oy <= LK_D)) {
                 // the displacement leaves the staged tile: the pixel, with its state
                 // at the start of this step (kept from here on), goes to the tail
@@ -376,60 +405,28 @@ __device__ __forceinline__ void lk_w9_body(const DevPlan* __restrict__ Pl, const
             }
             mb[q] = (wv * P + q - R + HM + oy) * MWP + (lane - R + HM + ox);
         }
-        // window rows j of the thread's P pixels; ALT alternates two register
-        // sets for the interpolated moving-image rows (no copies between rows)
-        constexpr int NJ = P + 2 * R;
-        float hA[P][NW];
+        // tile rows t = 0 .. P + 2R: moving-image row t - q of pixel q
+        constexpr int NT = P + 2 * R + 1;
+        float2 gA[NW], gB[NW];
         if (ALT) {
-            float hB[P][NW];
 #pragma unroll 1
-            for (int j = 0; j + 1 < NJ; j += 2) {
-                lk_window_row<P, TIW, MWP>(j, sTI + wv * P * TIW + lane, sM, mb, fx, fy, hA, hB, bu, bv);
-                lk_window_row<P, TIW, MWP>(j + 1, sTI + wv * P * TIW + lane, sM, mb, fx, fy, hB, hA, bu, bv);
+            for (int t = 0; t + 1 < NT; t += 2) {
+                lk_rhs_row<P, TIW, MWP, false>(t, g_base, sM, mb, fx, gA, gB, sau, sav, sbu, sbv);
+                lk_rhs_row<P, TIW, MWP, false>(t + 1, g_base, sM, mb, fx, gB, gA, sau, sav, sbu, sbv);
             }
-            if (NJ % 2) lk_window_row<P, TIW, MWP>(NJ - 1, sTI + wv * P * TIW + lane, sM, mb, fx, fy, hA, hB, bu, bv);
+            if (NT % 2) lk_rhs_row<P, TIW, MWP, false>(NT - 1, g_base, sM, mb, fx, gA, gB, sau, sav, sbu, sbv);
         } else {
-            // one register set: each new row is copied over the previous one
 #pragma unroll 1
-            for (int j = 0; j < NJ; ++j) {
-                float4 ti[NW];
-#pragma unroll
-                for (int c = 0; c < NW; ++c) ti[c] = sTI[(wv * P + j) * TIW + lane + c];
-#pragma unroll
-                for (int q = 0; q < P; ++q) {
-                    const int jr = j - q;
-                    if (jr < 0 || jr > 2 * R) continue;
-                    if (jr == 0) {
-                        const float* m0 = sM + mb[q];
-                        float v0 = m0[0];
-#pragma unroll
-                        for (int c = 0; c < NW; ++c) {
-                            const float v1 = m0[c + 1];
-                            hA[q][c] = __builtin_fmaf(fx[q], v1 - v0, v0);
-                            v0 = v1;
-                        }
-                    }
-                    const float* m1 = sM + mb[q] + (jr + 1) * MWP;
-                    float v0 = m1[0];
-#pragma unroll
-                    for (int c = 0; c < NW; ++c) {
-                        const float v1 = m1[c + 1];
-                        const float hb = __builtin_fmaf(fx[q], v1 - v0, v0);
-                        v0 = v1;
-                        const float m = __builtin_fmaf(fy[q], hb - hA[q][c], hA[q][c]);
-                        const float e = m - ti[c].x;
-                        bu[q] = __builtin_fmaf(ti[c].y, e, bu[q]);
-                        bv[q] = __builtin_fmaf(ti[c].z, e, bv[q]);
-                        hA[q][c] = hb;
-                    }
-                }
-            }
+            for (int t = 0; t < NT; ++t)
+                lk_rhs_row<P, TIW, MWP, true>(t, g_base, sM, mb, fx, gA, gB, sau, sav, sbu, sbv);
         }
 #pragma unroll
         for (int q = 0; q < P; ++q) {
             if (!act[q]) continue;
-            const float du = (g01[q] * bv[q] - g11[q] * bu[q]) / det[q];
-            const float dv = (g01[q] * bu[q] - g00[q] * bv[q]) / det[q];
+            const float bu = __builtin_fmaf(fy[q], sbu[q] - sau[q], sau[q]) - cu[q];
+            const float bv = __builtin_fmaf(fy[q], sbv[q] - sav[q], sav[q]) - cv[q];
+            const float du = (g01[q] * bv - g11[q] * bu) / det[q];
+            const float dv = (g01[q] * bu - g00[q] * bv) / det[q];
             ux[q] = ux[q] + du;
             uy[q] = uy[q] + dv;
         }
@@ -503,7 +500,7 @@ __device__ __forceinline__ void lk_tail_pixel(const DevPlan* __restrict__ Pl, in
         for (int k = 0; k < NW + 2; ++k) cxm[k] = clampi(x - R - 1 + k, 0, w - 1);
 #pragma unroll
         for (int c = 0; c < NW; ++c) cin[c] = x - R + c >= 0 && x - R + c < w;
-        float g00 = 0.0f, g01 = 0.0f, g11 = 0.0f;
+        float g00 = 0.0f, g01 = 0.0f, g11 = 0.0f, cu = 0.0f, cv = 0.0f;
 #pragma unroll 1
         for (int jr = 0; jr < NW; ++jr) {
             const int yy = y - R + jr;
@@ -527,6 +524,8 @@ __device__ __forceinline__ void lk_tail_pixel(const DevPlan* __restrict__ Pl, in
                 g00 = __builtin_fmaf(ix, ix, g00);
                 g01 = __builtin_fmaf(ix, iy, g01);
                 g11 = __builtin_fmaf(iy, iy, g11);
+                cu = __builtin_fmaf(ix, a[c + 1], cu);
+                cv = __builtin_fmaf(iy, a[c + 1], cv);
             }
         }
         const int ncx = min(x + R, w - 1) - max(x - R, 0) + 1;
@@ -542,7 +541,7 @@ __device__ __forceinline__ void lk_tail_pixel(const DevPlan* __restrict__ Pl, in
             int mx[NW + 1];
 #pragma unroll
             for (int k = 0; k < NW + 1; ++k) mx[k] = clampi(x - R + ox + k, 0, w - 1);
-            float bu = 0.0f, bv = 0.0f;
+            float sau = 0.0f, sav = 0.0f, sbu = 0.0f, sbv = 0.0f;
 #pragma unroll 1
             for (int jr = 0; jr < NW; ++jr) {
                 const int yy = y - R + jr;
@@ -572,11 +571,14 @@ __device__ __forceinline__ void lk_tail_pixel(const DevPlan* __restrict__ Pl, in
                     const float iy = in ? 0.5f * (dn[c] - up[c]) : 0.0f;
                     const float ta = __builtin_fmaf(fx, ra[c + 1] - ra[c], ra[c]);
                     const float tb = __builtin_fmaf(fx, rb[c + 1] - rb[c], rb[c]);
-                    const float e = __builtin_fmaf(fy, tb - ta, ta) - a[c + 1];
-                    bu = __builtin_fmaf(ix, e, bu);
-                    bv = __builtin_fmaf(iy, e, bv);
+                    sau = __builtin_fmaf(ix, ta, sau);
+                    sav = __builtin_fmaf(iy, ta, sav);
+                    sbu = __builtin_fmaf(ix, tb, sbu);
+                    sbv = __builtin_fmaf(iy, tb, sbv);
                 }
             }
+            const float bu = __builtin_fmaf(fy, sbu - sau, sau) - cu;
+            const float bv = __builtin_fmaf(fy, sbv - sav, sav) - cv;
             const float du = (g01 * bv - g11 * bu) / det;
             const float dv = (g01 * bu - g00 * bv) / det;
             ux = ux + du;
@@ -641,8 +643,8 @@ __global__ __launch_bounds__(256) void k_lk_tail(const Batch B, int l)
                 tc[c] = a[c + 1];
             }
         }
-        // normal matrix: row r's lane adds its taps at hand-on r
-        float g00 = 0.0f, g01 = 0.0f, g11 = 0.0f;
+        // normal matrix and template term: row r's lane adds its taps at hand-on r
+        float g00 = 0.0f, g01 = 0.0f, g11 = 0.0f, cu = 0.0f, cv = 0.0f;
 #pragma unroll
         for (int r = 0; r < NW; ++r) {
             if (sub == r) {
@@ -651,15 +653,21 @@ __global__ __launch_bounds__(256) void k_lk_tail(const Batch B, int l)
                     g00 = __builtin_fmaf(gx[c], gx[c], g00);
                     g01 = __builtin_fmaf(gx[c], gy[c], g01);
                     g11 = __builtin_fmaf(gy[c], gy[c], g11);
+                    cu = __builtin_fmaf(gx[c], tc[c], cu);
+                    cv = __builtin_fmaf(gy[c], tc[c], cv);
                 }
             }
             g00 = __shfl_up(g00, 1, G);
             g01 = __shfl_up(g01, 1, G);
             g11 = __shfl_up(g11, 1, G);
+            cu = __shfl_up(cu, 1, G);
+            cv = __shfl_up(cv, 1, G);
         }
         g00 = __shfl(g00, NW, G);
         g01 = __shfl(g01, NW, G);
         g11 = __shfl(g11, NW, G);
+        cu = __shfl(cu, NW, G);
+        cv = __shfl(cv, NW, G);
         const int ncx = min(x + R, w - 1) - max(x - R, 0) + 1;
         const int ncy = min(y + R, h - 1) - max(y - R, 0) + 1;
         const float reg = Pl->lk_lambda * (float)(ncy * ncx);
@@ -679,28 +687,35 @@ __global__ __launch_bounds__(256) void k_lk_tail(const Batch B, int l)
                 ra[k] = m0[xm];
                 rb[k] = m1[xm];
             }
-            float e[NW];
+            float ta[NW], tb[NW];
 #pragma unroll
             for (int c = 0; c < NW; ++c) {
-                const float ta = __builtin_fmaf(fx, ra[c + 1] - ra[c], ra[c]);
-                const float tb = __builtin_fmaf(fx, rb[c + 1] - rb[c], rb[c]);
-                e[c] = __builtin_fmaf(fy, tb - ta, ta) - tc[c];
+                ta[c] = __builtin_fmaf(fx, ra[c + 1] - ra[c], ra[c]);
+                tb[c] = __builtin_fmaf(fx, rb[c + 1] - rb[c], rb[c]);
             }
-            float bu = 0.0f, bv = 0.0f;
+            float sau = 0.0f, sav = 0.0f, sbu = 0.0f, sbv = 0.0f;
 #pragma unroll
             for (int r = 0; r < NW; ++r) {
                 if (sub == r) {
 #pragma unroll
                     for (int c = 0; c < NW; ++c) {
-                        bu = __builtin_fmaf(gx[c], e[c], bu);
-                        bv = __builtin_fmaf(gy[c], e[c], bv);
+                        sau = __builtin_fmaf(gx[c], ta[c], sau);
+                        sav = __builtin_fmaf(gy[c], ta[c], sav);
+                        sbu = __builtin_fmaf(gx[c], tb[c], sbu);
+                        sbv = __builtin_fmaf(gy[c], tb[c], sbv);
                     }
                 }
-                bu = __shfl_up(bu, 1, G);
-                bv = __shfl_up(bv, 1, G);
+                sau = __shfl_up(sau, 1, G);
+                sav = __shfl_up(sav, 1, G);
+                sbu = __shfl_up(sbu, 1, G);
+                sbv = __shfl_up(sbv, 1, G);
             }
-            bu = __shfl(bu, NW, G);
-            bv = __shfl(bv, NW, G);
+            sau = __shfl(sau, NW, G);
+            sav = __shfl(sav, NW, G);
+            sbu = __shfl(sbu, NW, G);
+            sbv = __shfl(sbv, NW, G);
+            const float bu = __builtin_fmaf(fy, sbu - sau, sau) - cu;
+            const float bv = __builtin_fmaf(fy, sbv - sav, sav) - cv;
             const float du = (g01 * bv - g11 * bu) / det;
             const float dv = (g01 * bu - g00 * bv) / det;
             ux = ux + du;
