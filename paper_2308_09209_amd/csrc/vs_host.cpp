@@ -132,30 +132,19 @@ void free_ctx(vs_ctx* c)
 }
 
 // Default 9x9 flow-kernel variant of a level, from its count of 64 x 16 tiles
-// (n16) and the blocks the device holds at once (`resident`, three staged
-// flow blocks per compute unit): the most pixels per thread P (4, 3, 2, 1;
-// n16 * 4 / P blocks) whose last wave of blocks is at least three quarters
-// full, else the P that fills its waves best (ties: more pixels per thread).
-// One or two pixels per thread take the alternating-register form (+8),
-// which their register budget allows.
+// (n16) and the blocks the device holds at once (`resident`, four staged flow
+// blocks per compute unit): the most pixels per thread P (4, 3, 2, 1; n16 * 4 / P
+// blocks) that still gives at least one full wave of blocks, else P = 1 (the
+// most blocks for a small level).  Every P takes the form that keeps the
+// previous gradient row in registers (+8): with the regrouped right-hand side
+// it costs no occupancy at P = 4 and saves the row's second LDS read.
 int default_lk_P(int n16, int resident)
 {
-    int best = 1;
-    double best_fill = -1.0;
     for (int P = 4; P >= 1; --P) {
         const long blocks = ((long)n16 * 4 + P - 1) / P;
-        const long waves = (blocks + resident - 1) / resident;
-        const double fill = waves > 0 ? (double)blocks / (double)(waves * resident) : 0.0;
-        if (fill >= 0.75) {
-            best = P;
-            break;
-        }
-        if (fill > best_fill + 1e-9) {
-            best_fill = fill;
-            best = P;
-        }
+        if (blocks >= resident) return P + 8;
     }
-    return best <= 2 ? best + 8 : best;
+    return 1 + 8;
 }
 
 // blocks of the staged flow kernel the current device holds at once
@@ -167,7 +156,7 @@ int lk_resident_blocks()
     if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
         ncu <= 0)
         ncu = 256;
-    cached = 3 * ncu;
+    cached = 4 * ncu;
     return cached;
 }
 
@@ -211,9 +200,12 @@ size_t var_layout(DevPlan& h, uint8_t* base)
     };
     for (int l = 0; l < h.levels; ++l) {
         h.var_off[l][0] = 0;
+        h.var_toff[l][0] = 0;
         for (int f = 0; f < 2 * h.n_pairs; ++f) {
             const int p = f >> 1;
             h.var_off[l][f + 1] = h.var_off[l][f] + (int32_t)(((size_t)h.lw[p][l] * h.lh[p][l] + 255) / 256);
+            h.var_toff[l][f + 1] = h.var_toff[l][f] + ((h.lw[p][l] + VAR_TX - 1) / VAR_TX) *
+                                                          ((h.lh[p][l] + VAR_TY - 1) / VAR_TY);
         }
     }
     for (int p = 0; p < h.n_pairs; ++p)
@@ -767,8 +759,7 @@ hipError_t enqueue_frame(const Group& g, hipStream_t s, hipEvent_t* ev, uint8_t*
     for (int c = 0; c < g.n; ++c) levels = std::max(levels, (int)g.hp[c]->levels);
     if (ev) VS_STEP(hipEventRecord(ev[0], s), "hipEventRecord");
     VS_STEP(launch_strips(g, s), "strips");
-    VS_STEP(launch_lut(g, s), "lut");
-    VS_STEP(launch_moments_b(g, s), "moments");
+    VS_STEP(launch_lut(g, s), "lut");   // + eq. (1)'s B from the strips' conditional sums
     VS_STEP(launch_solve(g, s), "solve");
     if (ev) VS_STEP(hipEventRecord(ev[1], s), "hipEventRecord");
     // pyramids of 3+ levels: levels 0-2 in one pass (plain flow: all three

@@ -36,11 +36,16 @@ static_assert(STRIP_TY % SURR_UP_ROWS == 0, "whole upsampling blocks per strip t
 // Sums that many blocks add to are kept in several copies (tile t adds to copy
 // t % SPREAD, the consumer adds the copies): device-scope atomics on one
 // address from every block of a large grid serialise in the memory system.
-constexpr int HIST_SPREAD = 16, MOM_SPREAD = 32, PANO_SPREAD = 32;
+constexpr int VAR_TX = 64, VAR_TY = 8;        // variational Jacobi tile: 256 threads, 2 px each
+constexpr int HIST_SPREAD = 16, MOM_SPREAD = 32, PANO_SPREAD = 32, CSUM_SPREAD = 4;
 constexpr int SOLVE_THREADS = 256;
 enum { MOM_A = 0, MOM_N = 6, MOM_B = 7 };   // mom[][][]: A (6), n, B (9): 16 sums, one 128-byte line
 struct Accum {
     uint32_t hist[MAXP][HIST_SPREAD][2][3][256];   // [pair][copy][0 = camera j, 1 = camera i][channel][level]
+    // camera i's conditional channel sums over the overlap: csum[..][2 c + k][v]
+    // = the sum of channel a over the pixels whose channel c is v, a the k-th
+    // channel other than c (eq. (1)'s B from the LUT without a second pass)
+    unsigned long long csum[MAXP][CSUM_SPREAD][6][256];
     unsigned long long mom[MAXP][MOM_SPREAD][16];
     uint32_t pano_hist[PANO_SPREAD][3][256];
     uint32_t lk_qn[8];                             // flow pixels deferred to the tail kernel, per level
@@ -72,6 +77,7 @@ struct DevPlan {
     float var_alpha, var_gamma;
     int32_t var_outer, var_inner;
     int32_t var_off[MAXL][2 * MAXP + 1];
+    int32_t var_toff[MAXL][2 * MAXP + 1];   // flow = 2: Jacobi tiles (VAR_TX x VAR_TY) per field, prefix sums
     float lk_lambda;
     double ridge;
     int32_t cam_w[MAXC], cam_h[MAXC], cam_pitch[MAXC];
@@ -174,7 +180,6 @@ hipError_t launch_set_io(const FrameIO& io, int n, hipStream_t s);
 hipError_t launch_zero(const Group& g, hipStream_t s);
 hipError_t launch_strips(const Group& g, hipStream_t s);
 hipError_t launch_lut(const Group& g, hipStream_t s);
-hipError_t launch_moments_b(const Group& g, hipStream_t s);
 hipError_t launch_solve(const Group& g, hipStream_t s);
 enum { PYR_ALL = 0, PYR_UNFUSED = 1, PYR_AFTER = 2 };
 hipError_t launch_pyr0(const Group& g, int phase, hipStream_t s);

@@ -169,20 +169,26 @@ __global__ __launch_bounds__(256) void k_set_io(const FrameIO io, int per)
 // ---------------------------------------------------------------------------
 
 
-__device__ __forceinline__ void strips_body(const DevPlan* __restrict__ P, const int bid)
+__device__ __forceinline__ void strips_body(const DevPlan* __restrict__ P, const int p, const int t,
+                                            uint32_t (*s_hj)[3 * 256 + 1], unsigned long long (*s_hi)[3 * 256 + 1])
 {
-    // 4 copies (lane & 3) against same-address serialisation, each one word
-    // longer than the 6 x 256 bins so that a bin's copies sit in different banks
-    __shared__ uint32_t s_hist[4][2 * 3 * 256 + 1];
+    // Copies against same-address serialisation (camera j: 4, lane & 3;
+    // camera i: 2, lane & 1), each one word longer than the 3 x 256 bins so
+    // that a bin's copies sit in different banks.  Camera j: counts.  Camera
+    // i: per channel c and level v one 64-bit word, the count in bits 0-11 and
+    // the sums of the two other channels in bits 12-31 and 32-63 (a block
+    // holds at most 2048 pixels: counts < 2^12, sums < 2048 * 255 < 2^20, so
+    // no field carries into the next).
+    static_assert(STRIP_TX * STRIP_TY <= 4095, "strip block counts fit 12 bits");
     __shared__ uint32_t s_red[4][7];
     const int tid = threadIdx.x;
-    const int p = find_field(P->strip_off, P->n_pairs, bid);
-    const int t = bid - P->strip_off[p];
     const int sw = P->sw[p], sh = P->sh[p];
     const int tx0 = (t % P->strip_tx[p]) * STRIP_TX, ty0 = (t / P->strip_tx[p]) * STRIP_TY;
-    for (int i = tid; i < 4 * (2 * 3 * 256 + 1); i += 256) (&s_hist[0][0])[i] = 0;
+    for (int i = tid; i < 4 * (3 * 256 + 1); i += 256) (&s_hj[0][0])[i] = 0;
+    for (int i = tid; i < 2 * (3 * 256 + 1); i += 256) (&s_hi[0][0])[i] = 0;
     __syncthreads();
-    uint32_t* const my_hist = s_hist[tid & 3];
+    uint32_t* const my_hj = s_hj[tid & 3];
+    unsigned long long* const my_hi = s_hi[tid & 1];
 
     const int kj = P->pj[p], ki = P->pi[p];
     const int shift_i = P->psi[p] * P->Wp;
@@ -207,12 +213,13 @@ __device__ __forceinline__ void strips_body(const DevPlan* __restrict__ P, const
         const bool ok = okj && oki;
         mask[q] = ok ? 1 : 0;
         if (ok) {
-            atomicAdd(&my_hist[0 * 256 + cj0], 1u);
-            atomicAdd(&my_hist[1 * 256 + cj1], 1u);
-            atomicAdd(&my_hist[2 * 256 + cj2], 1u);
-            atomicAdd(&my_hist[3 * 256 + ci0], 1u);
-            atomicAdd(&my_hist[4 * 256 + ci1], 1u);
-            atomicAdd(&my_hist[5 * 256 + ci2], 1u);
+            atomicAdd(&my_hj[0 * 256 + cj0], 1u);
+            atomicAdd(&my_hj[1 * 256 + cj1], 1u);
+            atomicAdd(&my_hj[2 * 256 + cj2], 1u);
+            typedef unsigned long long u64;
+            atomicAdd(&my_hi[0 * 256 + ci0], 1ull | ((u64)ci1 << 12) | ((u64)ci2 << 32));
+            atomicAdd(&my_hi[1 * 256 + ci1], 1ull | ((u64)ci0 << 12) | ((u64)ci2 << 32));
+            atomicAdd(&my_hi[2 * 256 + ci2], 1ull | ((u64)ci0 << 12) | ((u64)ci1 << 32));
             a00 += ci0 * ci0;
             a01 += ci0 * ci1;
             a02 += ci0 * ci2;
@@ -236,29 +243,35 @@ __device__ __forceinline__ void strips_body(const DevPlan* __restrict__ P, const
         if (s) atomicAdd(&acc->mom[p][t % MOM_SPREAD][MOM_A + tid], s);
     }
     uint32_t* gh = &acc->hist[p][t % HIST_SPREAD][0][0][0];
-    for (int i = tid; i < 2 * 3 * 256; i += 256) {
-        const uint32_t h = s_hist[0][i] + s_hist[1][i] + s_hist[2][i] + s_hist[3][i];
-        if (h) atomicAdd(&gh[i], h);
+    unsigned long long* gs = &acc->csum[p][t % CSUM_SPREAD][0][0];
+    for (int i = tid; i < 3 * 256; i += 256) {
+        const uint32_t hj = s_hj[0][i] + s_hj[1][i] + s_hj[2][i] + s_hj[3][i];
+        if (hj) atomicAdd(&gh[i], hj);
+        const unsigned long long hi = s_hi[0][i] + s_hi[1][i];
+        if (hi) {
+            const int c = i >> 8, v = i & 255;
+            atomicAdd(&gh[3 * 256 + i], (uint32_t)(hi & 0xfffu));
+            const unsigned long long s0 = (hi >> 12) & 0xfffffu, s1 = hi >> 32;
+            if (s0) atomicAdd(&gs[(2 * c) * 256 + v], s0);
+            if (s1) atomicAdd(&gs[(2 * c + 1) * 256 + v], s1);
+        }
     }
 }
 
-__global__ __launch_bounds__(256) void k_strips(const Batch B)
-{
-    int c;
-    const int b = batch_block(B, blockIdx.x, c);
-    strips_body(B.plan[c], b);
-}
-
-
 // ---------------------------------------------------------------------------
-// Section 2.1 step 3: histogram specification LUT(v) = min{w : C_j(w) >= C_i(v)}
+// Section 2.1 step 3: histogram specification LUT(v) = min{w : C_j(w) >= C_i(v)},
+// and eq. (1)'s B = I_i^T I_j with I_j = LUT(I_i) (the histogram-specified
+// image i) from the histograms and conditional sums: B[a][c] = sum_v LUT_c(v)
+// S_a|c(v), S_c|c(v) = v n_c(v).  256 threads, thread v every channel; Cj,
+// Ci: 2 x 768 words of LDS.
 // ---------------------------------------------------------------------------
 
-// one thread per (channel, level): tid = 256 c + v
-__device__ __forceinline__ void lut_body(const DevPlan* __restrict__ P, const int bid)
+__device__ __forceinline__ void lut_body(const DevPlan* __restrict__ P, const int p)
 {
+    // one thread per (channel, level): tid = 256 c + v
     __shared__ uint32_t Ci[3][256], Cj[3][256];
-    const int p = bid, c = threadIdx.x >> 8, v = threadIdx.x & 255;
+    __shared__ unsigned long long s_red[12][3];
+    const int tid = threadIdx.x, c = tid >> 8, v = tid & 255;
     const Accum* acc = P->acc;
     uint32_t sj = 0, si = 0;
 #pragma unroll 8
@@ -266,6 +279,7 @@ __device__ __forceinline__ void lut_body(const DevPlan* __restrict__ P, const in
         sj += acc->hist[p][k][0][c][v];
         si += acc->hist[p][k][1][c][v];
     }
+    const uint32_t ni = si;
     Cj[c][v] = sj;
     Ci[c][v] = si;
     __syncthreads();
@@ -302,77 +316,31 @@ __device__ __forceinline__ void lut_body(const DevPlan* __restrict__ P, const in
         }
         lo = w;
     }
-    P->res->lut[p][c][v] = (uint8_t)(lo > 255 ? 255 : lo);
-}
-
-__global__ __launch_bounds__(768) void k_lut(const Batch B)
-{
-    int c;
-    const int b = batch_block(B, blockIdx.x, c);
-    lut_body(B.plan[c], b);
-}
-
-
-// ---------------------------------------------------------------------------
-// Eq. (1) B = I_i^T I_j with I_j = LUT(I_i) (the histogram-specified image i)
-// ---------------------------------------------------------------------------
-
-__device__ __forceinline__ void moments_b_body(const DevPlan* __restrict__ P, const int bid)
-{
-    __shared__ uint8_t s_lut[3][256];
-    __shared__ uint32_t s_red[4][9];
-    const int tid = threadIdx.x;
-    const int p = find_field(P->strip_off, P->n_pairs, bid);
-    const int t = bid - P->strip_off[p];
-    const int sw = P->sw[p], sh = P->sh[p];
-    const int tx0 = (t % P->strip_tx[p]) * STRIP_TX, ty0 = (t / P->strip_tx[p]) * STRIP_TY;
-    for (int i = tid; i < 3 * 256; i += 256) (&s_lut[0][0])[i] = (&P->res->lut[p][0][0])[i];
-    __syncthreads();
-    const uint32_t* __restrict__ strip_i = P->strip[p] + (size_t)sh * sw;
-    const uint8_t* __restrict__ mask = P->mask[p];
-    const int lx = tx0 + (tid & 63);
-    uint32_t b[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
-    // every row's mask and pixel loads issued before any is used
-    constexpr int NR = STRIP_TY / 4;
-    uint32_t px[NR];
-    uint8_t mk[NR];
+    const uint32_t L = (uint32_t)(lo > 255 ? 255 : lo);
+    P->res->lut[p][c][v] = (uint8_t)L;
+    // column c of B (row a: channel of I_i, column c: channel of LUT(I_i)),
+    // exact: B[c][c] = sum_v v LUT_c(v) n_c(v), B[a][c] = sum_v LUT_c(v) S_a|c(v)
+    unsigned long long s0 = 0, s1 = 0;
 #pragma unroll
-    for (int k = 0; k < NR; ++k) {
-        const int ly = ty0 + (tid >> 6) + 4 * k;
-        const bool in = lx < sw && ly < sh;
-        const size_t q = (size_t)ly * sw + lx;
-        px[k] = in ? strip_i[q] : 0u;
-        mk[k] = in ? mask[q] : (uint8_t)0;
+    for (int k = 0; k < CSUM_SPREAD; ++k) {
+        s0 += acc->csum[p][k][2 * c][v];
+        s1 += acc->csum[p][k][2 * c + 1][v];
     }
-#pragma unroll
-    for (int k = 0; k < NR; ++k) {
-        if (!mk[k]) continue;
-        const uint32_t pix = px[k];
-        uint32_t pv[3] = {pix & 255u, (pix >> 8) & 255u, (pix >> 16) & 255u};
-        uint32_t qv[3] = {s_lut[0][pv[0]], s_lut[1][pv[1]], s_lut[2][pv[2]]};
-#pragma unroll
-        for (int a = 0; a < 3; ++a)
-#pragma unroll
-            for (int c = 0; c < 3; ++c) b[a * 3 + c] += pv[a] * qv[c];
-    }
-#pragma unroll
-    for (int i = 0; i < 9; ++i) b[i] = wave_sum(b[i]);
+    const unsigned long long bd = wave_sum64((unsigned long long)v * L * ni);
+    const unsigned long long b0 = wave_sum64(s0 * L), b1 = wave_sum64(s1 * L);
     if ((tid & 63) == 0) {
-#pragma unroll
-        for (int i = 0; i < 9; ++i) s_red[tid >> 6][i] = b[i];
+        s_red[tid >> 6][0] = bd;
+        s_red[tid >> 6][1] = b0;
+        s_red[tid >> 6][2] = b1;
     }
     __syncthreads();
-    if (tid < 9) {
-        unsigned long long s = (unsigned long long)s_red[0][tid] + s_red[1][tid] + s_red[2][tid] + s_red[3][tid];
-        if (s) atomicAdd(&P->acc->mom[p][t % MOM_SPREAD][MOM_B + tid], s);
+    if (v < 3) {   // thread (c, k): entry k of column c, its channel's 4 wavefronts in order
+        const int w0 = 4 * c;
+        const unsigned long long sum = ((s_red[w0][v] + s_red[w0 + 1][v]) + s_red[w0 + 2][v]) + s_red[w0 + 3][v];
+        const int a0 = c == 0 ? 1 : 0, a1 = c == 2 ? 1 : 2;   // the two other channels, in order
+        const int a = v == 0 ? c : (v == 1 ? a0 : a1);
+        P->acc->mom[p][0][MOM_B + a * 3 + c] = sum;
     }
-}
-
-__global__ __launch_bounds__(256) void k_moments_b(const Batch B)
-{
-    int c;
-    const int b = batch_block(B, blockIdx.x, c);
-    moments_b_body(B.plan[c], b);
 }
 
 
@@ -380,60 +348,60 @@ __global__ __launch_bounds__(256) void k_moments_b(const Batch B)
 // Eqs. (2)-(4): 3D-M solve (FP64) per pair, chain composition, state shift
 // ---------------------------------------------------------------------------
 
-// (A + eps I) M = B + eps I, eps = ridge * trace(A); Gaussian elimination with
-// partial pivoting (first largest on ties) and back substitution.  Returns 1
-// (M = I) when a pivot falls below 1e-12 of the largest |entry|.
-__device__ int solve3(const double* A, const double* B, double ridge, double* M)
+// Column k of M in (A + eps I) M = B + eps I, eps = ridge * trace(A):
+// Gaussian elimination with partial pivoting (first largest on ties) and back
+// substitution, the column's right-hand side carried through the same row
+// operations as the whole matrix would be.  Returns 1 (M = I) when a pivot
+// falls below 1e-12 of the largest |entry|.
+__device__ int solve3_col(const double* A, const double* Bk, int k, double ridge, double* Mk)
 {
-    double a[3][3], b[3][3];
+    double a[3][3], b[3];
     const double eps = ridge * ((A[0] + A[4]) + A[8]);
     double maxabs = 0.0;
-    for (int r = 0; r < 3; ++r)
-        for (int k = 0; k < 3; ++k) {
-            a[r][k] = A[r * 3 + k] + (r == k ? eps : 0.0);
-            b[r][k] = B[r * 3 + k] + (r == k ? eps : 0.0);
-            if (fabs(a[r][k]) > maxabs) maxabs = fabs(a[r][k]);
+    for (int r = 0; r < 3; ++r) {
+        for (int q = 0; q < 3; ++q) {
+            a[r][q] = A[r * 3 + q] + (r == q ? eps : 0.0);
+            if (fabs(a[r][q]) > maxabs) maxabs = fabs(a[r][q]);
         }
+        b[r] = Bk[r] + (r == k ? eps : 0.0);
+    }
     for (int col = 0; col < 3; ++col) {
         int piv = col;
         for (int r = col + 1; r < 3; ++r)
             if (fabs(a[r][col]) > fabs(a[piv][col])) piv = r;
         if (piv != col) {
-            for (int k = 0; k < 3; ++k) {
-                double t = a[col][k];
-                a[col][k] = a[piv][k];
-                a[piv][k] = t;
-                t = b[col][k];
-                b[col][k] = b[piv][k];
-                b[piv][k] = t;
+            for (int q = 0; q < 3; ++q) {
+                const double t = a[col][q];
+                a[col][q] = a[piv][q];
+                a[piv][q] = t;
             }
+            const double t = b[col];
+            b[col] = b[piv];
+            b[piv] = t;
         }
         if (!(fabs(a[col][col]) >= 1e-12 * maxabs) || a[col][col] == 0.0) {
-            for (int i = 0; i < 9; ++i) M[i] = (i % 4 == 0) ? 1.0 : 0.0;
+            for (int r = 0; r < 3; ++r) Mk[r] = r == k ? 1.0 : 0.0;
             return 1;
         }
         for (int r = col + 1; r < 3; ++r) {
-            double f = a[r][col] / a[col][col];
-            for (int k = col; k < 3; ++k) a[r][k] = a[r][k] - f * a[col][k];
-            for (int k = 0; k < 3; ++k) b[r][k] = b[r][k] - f * b[col][k];
+            const double f = a[r][col] / a[col][col];
+            for (int q = col; q < 3; ++q) a[r][q] = a[r][q] - f * a[col][q];
+            b[r] = b[r] - f * b[col];
         }
     }
-    double x[3][3];
-    for (int r = 2; r >= 0; --r)
-        for (int k = 0; k < 3; ++k) {
-            double s = b[r][k];
-            for (int q = r + 1; q < 3; ++q) s = s - a[r][q] * x[q][k];
-            x[r][k] = s / a[r][r];
-        }
-    for (int r = 0; r < 3; ++r)
-        for (int k = 0; k < 3; ++k) M[r * 3 + k] = x[r][k];
+    for (int r = 2; r >= 0; --r) {
+        double s = b[r];
+        for (int q = r + 1; q < 3; ++q) s = s - a[r][q] * Mk[q];
+        Mk[r] = s / a[r][r];
+    }
     return 0;
 }
 
-__device__ __forceinline__ void solve_body(const DevPlan* __restrict__ P, const int bid)
+// s_M, s_mom: LDS of the calling block (MAXP x 9 doubles, MAXP x 16 sums).
+// Three threads per pair, one column of M each; three threads for the chain.
+__device__ __forceinline__ void solve_body(const DevPlan* __restrict__ P, double (*s_M)[9],
+                                           unsigned long long (*s_mom)[16])
 {
-    __shared__ double s_M[MAXP][9];
-    __shared__ unsigned long long s_mom[MAXP][16];
     const int tid = threadIdx.x;
     Accum* acc = P->acc;
     Results* res = P->res;
@@ -448,79 +416,99 @@ __device__ __forceinline__ void solve_body(const DevPlan* __restrict__ P, const 
         s_mom[p][j] = s;
     }
     __syncthreads();
-    if (tid < P->n_pairs) {
-        const int p = tid;
-        unsigned long long A[6], B[9], n;
-        for (int i = 0; i < 6; ++i) A[i] = s_mom[p][MOM_A + i];
-        for (int i = 0; i < 9; ++i) B[i] = s_mom[p][MOM_B + i];
-        n = s_mom[p][MOM_N];
-        for (int i = 0; i < 6; ++i) res->mom[p][i] = A[i];
-        for (int i = 0; i < 9; ++i) res->mom[p][6 + i] = B[i];
-        res->mom[p][15] = n;
-        unsigned long long A3[6], B3[9], n3 = n;
-        for (int i = 0; i < 6; ++i) A3[i] = A[i];
-        for (int i = 0; i < 9; ++i) B3[i] = B[i];
-        const int W = P->color_window;
-        const int T = (int)st->frames_seen;
+    const int W = P->color_window;
+    const int T = (int)st->frames_seen;
+    if (tid < 3 * P->n_pairs) {
+        const int p = tid / 3, k = tid % 3;
+        unsigned long long A3[6], B3[3], n3 = s_mom[p][MOM_N];
+        for (int i = 0; i < 6; ++i) A3[i] = s_mom[p][MOM_A + i];
+        for (int r = 0; r < 3; ++r) B3[r] = s_mom[p][MOM_B + r * 3 + k];
         for (int d = 1; d < W && d <= T; ++d) {
             const vs_moments* o = &st->mom[p][d - 1];
             for (int i = 0; i < 6; ++i) A3[i] += o->A[i];
-            for (int i = 0; i < 9; ++i) B3[i] += o->B[i];
+            for (int r = 0; r < 3; ++r) B3[r] += o->B[r * 3 + k];
             n3 += o->n;
         }
-        double M[9] = {1, 0, 0, 0, 1, 0, 0, 0, 1};
+        double Mk[3] = {k == 0 ? 1.0 : 0.0, k == 1 ? 1.0 : 0.0, k == 2 ? 1.0 : 0.0};
         int flag = 0;
         if (W > 0) {
             if (n3 < (unsigned long long)P->min_pixels) {
                 flag = 1;
             } else {
-                double Ad[9] = {(double)A3[0], (double)A3[1], (double)A3[2], (double)A3[1], (double)A3[3],
-                                (double)A3[4], (double)A3[2], (double)A3[4], (double)A3[5]};
-                double Bd[9];
-                for (int i = 0; i < 9; ++i) Bd[i] = (double)B3[i];
-                if (solve3(Ad, Bd, P->ridge, M)) flag = 2;
+                const double Ad[9] = {(double)A3[0], (double)A3[1], (double)A3[2], (double)A3[1], (double)A3[3],
+                                      (double)A3[4], (double)A3[2], (double)A3[4], (double)A3[5]};
+                const double Bd[3] = {(double)B3[0], (double)B3[1], (double)B3[2]};
+                if (solve3_col(Ad, Bd, k, P->ridge, Mk)) flag = 2;
             }
         }
-        for (int i = 0; i < 9; ++i) {
-            s_M[p][i] = M[i];
-            res->Mpair[p][i] = M[i];
+        for (int r = 0; r < 3; ++r) {
+            s_M[p][r * 3 + k] = Mk[r];
+            res->Mpair[p][r * 3 + k] = Mk[r];
         }
-        res->flags[p] = flag;
-        st->mom[p][1] = st->mom[p][0];
-        for (int i = 0; i < 6; ++i) st->mom[p][0].A[i] = A[i];
-        for (int i = 0; i < 9; ++i) st->mom[p][0].B[i] = B[i];
-        st->mom[p][0].n = n;
+        if (k == 0) res->flags[p] = flag;
     }
-    __syncthreads();
-    if (tid == 0) {
-        double Mk[9] = {1, 0, 0, 0, 1, 0, 0, 0, 1};
-        for (int i = 0; i < 9; ++i) res->Mk[0][i] = (float)Mk[i];
+    __syncthreads();   // the window's moments are read: shift the state
+    if (tid < P->n_pairs) {
+        const int p = tid;
+        for (int i = 0; i < 16; ++i) res->mom[p][i < 6 ? i : (i == MOM_N ? 15 : i - 1)] = s_mom[p][i];
+        st->mom[p][1] = st->mom[p][0];
+        for (int i = 0; i < 6; ++i) st->mom[p][0].A[i] = s_mom[p][MOM_A + i];
+        for (int i = 0; i < 9; ++i) st->mom[p][0].B[i] = s_mom[p][MOM_B + i];
+        st->mom[p][0].n = s_mom[p][MOM_N];
+    } else if (tid >= 64 && tid < 67) {
+        // the chain to camera 0 (row vectors, M_k = M_(k-1,k) M_(k-1)), one
+        // column c of every M_k per thread
+        const int c = tid - 64;
+        double m[3] = {c == 0 ? 1.0 : 0.0, c == 1 ? 1.0 : 0.0, c == 2 ? 1.0 : 0.0};
+        for (int r = 0; r < 3; ++r) res->Mk[0][r * 3 + c] = (float)m[r];
         for (int k = 1; k < P->n_cams; ++k) {
             const double* a = s_M[k - 1];
-            double t[9];
-            for (int r = 0; r < 3; ++r)
-                for (int c = 0; c < 3; ++c)
-                    t[r * 3 + c] = (a[r * 3 + 0] * Mk[0 * 3 + c] + a[r * 3 + 1] * Mk[1 * 3 + c]) + a[r * 3 + 2] * Mk[2 * 3 + c];
-            for (int i = 0; i < 9; ++i) {
-                Mk[i] = t[i];
-                res->Mk[k][i] = (float)t[i];
+            double t[3];
+            for (int r = 0; r < 3; ++r) t[r] = (a[r * 3 + 0] * m[0] + a[r * 3 + 1] * m[1]) + a[r * 3 + 2] * m[2];
+            for (int r = 0; r < 3; ++r) {
+                m[r] = t[r];
+                res->Mk[k][r * 3 + c] = (float)t[r];
             }
         }
         // eq. (4)'s text read literally: no whole-frame (composed) correction;
         // each pair's own matrix corrects camera i inside that overlap
         for (int p = 0; p < P->n_pairs; ++p)
-            for (int i = 0; i < 9; ++i) res->Mpf[p][i] = (float)s_M[p][i];
+            for (int r = 0; r < 3; ++r) res->Mpf[p][r * 3 + c] = (float)s_M[p][r * 3 + c];
         if (P->readings & VS_READ_OVERLAP_ONLY)
             for (int k = 0; k < P->n_cams; ++k)
-                for (int i = 0; i < 9; ++i) res->Mk[k][i] = (i % 4 == 0) ? 1.0f : 0.0f;
+                for (int r = 0; r < 3; ++r) res->Mk[k][r * 3 + c] = r == c ? 1.0f : 0.0f;
     }
 }
 
-__global__ __launch_bounds__(SOLVE_THREADS) void k_solve(const Batch B)
+// Section 2.1 steps 1-2 and eq. (1)'s A and B sums over every strip pixel of
+// every pair.
+__global__ __launch_bounds__(256) void k_strips(const Batch B)
+{
+    __shared__ uint32_t s_hj[4][3 * 256 + 1];
+    __shared__ unsigned long long s_hi[2][3 * 256 + 1];
+    int c;
+    const int b = batch_block(B, blockIdx.x, c);
+    const DevPlan* __restrict__ P = B.plan[c];
+    const int p = find_field(P->strip_off, P->n_pairs, b);
+    strips_body(P, p, b - P->strip_off[p], s_hj, s_hi);
+}
+
+// Section 2.1 step 3 and eq. (1)'s B: one block per pair.
+__global__ __launch_bounds__(768) void k_lut(const Batch B)
 {
     int c;
     const int b = batch_block(B, blockIdx.x, c);
-    solve_body(B.plan[c], b);
+    lut_body(B.plan[c], b);
+}
+
+// Eqs. (2)-(4): one block per context.
+__global__ __launch_bounds__(SOLVE_THREADS) void k_solve(const Batch B)
+{
+    __shared__ double s_M[MAXP][9];
+    __shared__ unsigned long long s_mom[MAXP][16];
+    int c;
+    batch_block(B, blockIdx.x, c);
+    solve_body(B.plan[c], s_M, s_mom);
 }
 
 
@@ -762,11 +750,12 @@ __global__ __launch_bounds__(256) void k_pyr_fused(const Batch B, int after)
 // plus the histogram of the covered output (input of section 2.2)
 // ---------------------------------------------------------------------------
 
-__device__ __forceinline__ void blend_body(const DevPlan* __restrict__ P, const int bid)
+// s_hist: 8 copies of the histogram (lane & 7), LDS of the calling block:
+// neighbouring pixels often share a value, and same-address LDS atomics from
+// one instruction serialise (+ 1: a bin's copies in different banks)
+__device__ __forceinline__ void blend_body(const DevPlan* __restrict__ P, const int bid,
+                                           uint32_t (*s_hist)[3 * 256 + 1])
 {
-    // 8 copies of the histogram (lane & 7): neighbouring pixels often share a
-    // value, and same-address LDS atomics from one instruction serialise
-    __shared__ uint32_t s_hist[8][3 * 256 + 1];   // + 1: a bin's copies in different banks
     // per-camera constants of the frame, indexed by each lane's own camera
     __shared__ float s_hinv[MAXC][9], s_M[MAXC][9];
     __shared__ int s_cw[MAXC], s_ch[MAXC], s_cp[MAXC];
@@ -905,17 +894,20 @@ __device__ __forceinline__ void blend_body(const DevPlan* __restrict__ P, const 
     }
 }
 
-__global__ __launch_bounds__(BL_THREADS) void k_blend(const Batch B)
-{
-    int c;
-    const int b = batch_block(B, blockIdx.x, c);
-    blend_body(B.plan[c], b);
-}
 
 
 // ---------------------------------------------------------------------------
 // Section 2.2, eqs. (5)-(7): thresholds, 3-frame mean, piecewise LUT
 // ---------------------------------------------------------------------------
+
+// Eqs. (15)-(18) over every canvas tile.
+__global__ __launch_bounds__(BL_THREADS) void k_blend(const Batch B)
+{
+    __shared__ uint32_t s_hist[8][3 * 256 + 1];
+    int c;
+    const int b = batch_block(B, blockIdx.x, c);
+    blend_body(B.plan[c], b, s_hist);
+}
 
 __device__ __forceinline__ void balance_lut_body(const DevPlan* __restrict__ P, const int bid)
 {
@@ -1087,14 +1079,6 @@ hipError_t launch_lut(const Group& g, hipStream_t s)
     Batch B;
     if (make_batch(g, B, [](const DevPlan& h) { return h.n_pairs; }))
         hipLaunchKernelGGL(k_lut, dim3(B.off[B.n]), dim3(768), 0, s, B);
-    return hipGetLastError();
-}
-
-hipError_t launch_moments_b(const Group& g, hipStream_t s)
-{
-    Batch B;
-    if (make_batch(g, B, [](const DevPlan& h) { return h.strip_off[h.n_pairs]; }))
-        hipLaunchKernelGGL(k_moments_b, dim3(B.off[B.n]), dim3(256), 0, s, B);
     return hipGetLastError();
 }
 

@@ -155,77 +155,109 @@ __global__ __launch_bounds__(256) void k_var_warp(const Batch B, int l, int fold
     dd[q] = make_float2(0.0f, 0.0f);
 }
 
-// the smoothness Psi' at (x, y): forward differences of U = u + du, V = v + dv
-// (0 beyond the last column / row)
-__device__ __forceinline__ float smooth_w(const float2* __restrict__ U, const float2* __restrict__ d, int w, int h,
-                                          int x, int y)
-{
-    const size_t q = (size_t)y * w + x;
-    const float2 a = U[q], da = d[q];
-    const float u0 = a.x + da.x, v0 = a.y + da.y;
-    float ux = 0.0f, uy = 0.0f, vx = 0.0f, vy = 0.0f;
-    if (x + 1 < w) {
-        const float2 r = U[q + 1], dr = d[q + 1];
-        ux = (r.x + dr.x) - u0;
-        vx = (r.y + dr.y) - v0;
-    }
-    if (y + 1 < h) {
-        const float2 r = U[q + w], dr = d[q + w];
-        uy = (r.x + dr.x) - u0;
-        vy = (r.y + dr.y) - v0;
-    }
-    const float s = __builtin_fmaf(ux, ux, __builtin_fmaf(uy, uy, __builtin_fmaf(vx, vx, __builtin_fmaf(vy, vy, VAR_EPS2))));
-    return 0.5f / sqrtf(s);
-}
-
-// One Jacobi step of the linearised equations, increments src -> dst.
+// One Jacobi step of the linearised equations, increments src -> dst, on a
+// VAR_TX x VAR_TY tile of one field.  The sums V = U + dU of the tile and a
+// ring (one pixel left and up, two right and down) go to LDS once; from them
+// the smoothness Psi' of the tile and a one-pixel ring (forward differences of
+// V, 0 beyond the last column / row of the level), then each pixel's update
+// from its 4 neighbours in the level.  Same operations as the per-pixel form:
+// every V is the same sum, every Psi' the same expression.
 __global__ __launch_bounds__(256) void k_var_jacobi(const Batch B, int l, int src)
 {
+    constexpr int RW = VAR_TX + 3, RH = VAR_TY + 3;   // V region: x0-1 .. x0+TX+1
+    constexpr int SW = VAR_TX + 2, SH = VAR_TY + 2;   // Psi' region: x0-1 .. x0+TX
+    __shared__ float2 sV[RH * RW];
+    __shared__ float sS[SH * SW];
     int c;
     const int b = batch_block(B, blockIdx.x, c);
     const DevPlan* __restrict__ P = B.plan[c];
-    int f, x, y, w, h;
-    if (!var_pixel(P, l, b, f, x, y, w, h)) return;
+    const int f = find_field(P->var_toff[l], 2 * P->n_pairs, b);
     const int p = f >> 1, dir = f & 1;
     if (kept_by_surrogate(P, p)) return;
-    const size_t n = (size_t)w * h, q = (size_t)y * w + x;
+    const int w = P->lw[p][l], h = P->lh[p][l];
+    const int t = b - P->var_toff[l][f], ntx = (w + VAR_TX - 1) / VAR_TX;
+    const int x0 = (t % ntx) * VAR_TX, y0 = (t / ntx) * VAR_TY;
     const float2* __restrict__ U = P->flow[p][dir][l];
     const float2* __restrict__ d = P->var_dd[p][dir][l][src];
+    const int tid = threadIdx.x;
+    for (int i = tid; i < RH * RW; i += 256) {
+        const int xx = x0 - 1 + i % RW, yy = y0 - 1 + i / RW;
+        float2 v = make_float2(0.0f, 0.0f);
+        if (xx >= 0 && xx < w && yy >= 0 && yy < h) {
+            const size_t q = (size_t)yy * w + xx;
+            const float2 a = U[q], da = d[q];
+            v = make_float2(a.x + da.x, a.y + da.y);
+        }
+        sV[i] = v;
+    }
+    __syncthreads();
+    for (int i = tid; i < SH * SW; i += 256) {
+        const int sx = i % SW, sy = i / SW;                 // region position (x0 - 1 + sx, y0 - 1 + sy)
+        const int xx = x0 - 1 + sx, yy = y0 - 1 + sy;
+        float s = 0.0f;
+        if (xx >= 0 && xx < w && yy >= 0 && yy < h) {
+            const float2 v0 = sV[sy * RW + sx];
+            float ux = 0.0f, uy = 0.0f, vx = 0.0f, vy = 0.0f;
+            if (xx + 1 < w) {
+                const float2 r = sV[sy * RW + sx + 1];
+                ux = r.x - v0.x;
+                vx = r.y - v0.y;
+            }
+            if (yy + 1 < h) {
+                const float2 r = sV[(sy + 1) * RW + sx];
+                uy = r.x - v0.x;
+                vy = r.y - v0.y;
+            }
+            s = 0.5f / sqrtf(__builtin_fmaf(ux, ux, __builtin_fmaf(uy, uy, __builtin_fmaf(vx, vx,
+                                                    __builtin_fmaf(vy, vy, VAR_EPS2)))));
+        }
+        sS[i] = s;
+    }
+    __syncthreads();
+    const size_t n = (size_t)w * h;
     const float* __restrict__ co = P->var_co[p][dir][l];
     const float alpha = P->var_alpha, gamma = P->var_gamma;
-    const float2 u = U[q], dq = d[q];
-    float A11 = 0.0f, A12 = 0.0f, A22 = 0.0f, b1 = 0.0f, b2 = 0.0f;
-    if (P->need[p][l][q]) {
-        const float c0 = co[q], c1 = co[n + q], c2 = co[2 * n + q], c3 = co[3 * n + q];
-        const float c4 = co[4 * n + q], c5 = co[5 * n + q], c6 = co[6 * n + q], c7 = co[7 * n + q];
-        const float e = __builtin_fmaf(c2, dq.y, __builtin_fmaf(c1, dq.x, c0));
-        const float pd = 0.5f / sqrtf(__builtin_fmaf(e, e, VAR_EPS2));
-        const float gx = __builtin_fmaf(c6, dq.y, __builtin_fmaf(c5, dq.x, c3));
-        const float gy = __builtin_fmaf(c7, dq.y, __builtin_fmaf(c6, dq.x, c4));
-        const float pg = gamma * (0.5f / sqrtf(__builtin_fmaf(gx, gx, __builtin_fmaf(gy, gy, VAR_EPS2))));
-        A11 = __builtin_fmaf(pd, c1 * c1, pg * __builtin_fmaf(c5, c5, c6 * c6));
-        A12 = __builtin_fmaf(pd, c1 * c2, pg * __builtin_fmaf(c5, c6, c6 * c7));
-        A22 = __builtin_fmaf(pd, c2 * c2, pg * __builtin_fmaf(c6, c6, c7 * c7));
-        b1 = -__builtin_fmaf(pd, c1 * c0, pg * __builtin_fmaf(c5, c3, c6 * c4));
-        b2 = -__builtin_fmaf(pd, c2 * c0, pg * __builtin_fmaf(c6, c3, c7 * c4));
-    }
-    const float s0 = smooth_w(U, d, w, h, x, y);
-    float S = 0.0f, Su = 0.0f, Sv = 0.0f;
-    const int nx[4] = {x - 1, x + 1, x, x};
-    const int ny[4] = {y, y, y - 1, y + 1};
+    const int x = x0 + (tid & 63);
 #pragma unroll
-    for (int k = 0; k < 4; ++k) {
-        if (nx[k] < 0 || nx[k] >= w || ny[k] < 0 || ny[k] >= h) continue;
-        const size_t qn = (size_t)ny[k] * w + nx[k];
-        const float wn = 0.5f * (s0 + smooth_w(U, d, w, h, nx[k], ny[k]));
-        const float2 un = U[qn], dn = d[qn];
-        S += wn;
-        Su = __builtin_fmaf(wn, (un.x + dn.x) - u.x, Su);
-        Sv = __builtin_fmaf(wn, (un.y + dn.y) - u.y, Sv);
+    for (int k = 0; k < VAR_TY / 4; ++k) {
+        const int ty = (tid >> 6) + 4 * k, y = y0 + ty;
+        if (x >= w || y >= h) continue;
+        const size_t q = (size_t)y * w + x;
+        const float2 u = U[q], dq = d[q];
+        float A11 = 0.0f, A12 = 0.0f, A22 = 0.0f, b1 = 0.0f, b2 = 0.0f;
+        if (P->need[p][l][q]) {
+            const float c0 = co[q], c1 = co[n + q], c2 = co[2 * n + q], c3 = co[3 * n + q];
+            const float c4 = co[4 * n + q], c5 = co[5 * n + q], c6 = co[6 * n + q], c7 = co[7 * n + q];
+            const float e = __builtin_fmaf(c2, dq.y, __builtin_fmaf(c1, dq.x, c0));
+            const float pd = 0.5f / sqrtf(__builtin_fmaf(e, e, VAR_EPS2));
+            const float gx = __builtin_fmaf(c6, dq.y, __builtin_fmaf(c5, dq.x, c3));
+            const float gy = __builtin_fmaf(c7, dq.y, __builtin_fmaf(c6, dq.x, c4));
+            const float pg = gamma * (0.5f / sqrtf(__builtin_fmaf(gx, gx, __builtin_fmaf(gy, gy, VAR_EPS2))));
+            A11 = __builtin_fmaf(pd, c1 * c1, pg * __builtin_fmaf(c5, c5, c6 * c6));
+            A12 = __builtin_fmaf(pd, c1 * c2, pg * __builtin_fmaf(c5, c6, c6 * c7));
+            A22 = __builtin_fmaf(pd, c2 * c2, pg * __builtin_fmaf(c6, c6, c7 * c7));
+            b1 = -__builtin_fmaf(pd, c1 * c0, pg * __builtin_fmaf(c5, c3, c6 * c4));
+            b2 = -__builtin_fmaf(pd, c2 * c0, pg * __builtin_fmaf(c6, c3, c7 * c4));
+        }
+        const int sx = (tid & 63) + 1, sy = ty + 1;          // (x, y) in the Psi' region
+        const float s0 = sS[sy * SW + sx];
+        float S = 0.0f, Su = 0.0f, Sv = 0.0f;
+        const int nx[4] = {x - 1, x + 1, x, x};
+        const int ny[4] = {y, y, y - 1, y + 1};
+        const int ox[4] = {-1, 1, 0, 0}, oy[4] = {0, 0, -1, 1};
+#pragma unroll
+        for (int k2 = 0; k2 < 4; ++k2) {
+            if (nx[k2] < 0 || nx[k2] >= w || ny[k2] < 0 || ny[k2] >= h) continue;
+            const float wn = 0.5f * (s0 + sS[(sy + oy[k2]) * SW + sx + ox[k2]]);
+            const float2 vn = sV[(sy + oy[k2]) * RW + sx + ox[k2]];
+            S += wn;
+            Su = __builtin_fmaf(wn, vn.x - u.x, Su);
+            Sv = __builtin_fmaf(wn, vn.y - u.y, Sv);
+        }
+        const float dx = __builtin_fmaf(alpha, Su, __builtin_fmaf(-A12, dq.y, b1)) / __builtin_fmaf(alpha, S, A11);
+        const float dy = __builtin_fmaf(alpha, Sv, __builtin_fmaf(-A12, dq.x, b2)) / __builtin_fmaf(alpha, S, A22);
+        P->var_dd[p][dir][l][src ^ 1][q] = make_float2(dx, dy);
     }
-    const float dx = __builtin_fmaf(alpha, Su, __builtin_fmaf(-A12, dq.y, b1)) / __builtin_fmaf(alpha, S, A11);
-    const float dy = __builtin_fmaf(alpha, Sv, __builtin_fmaf(-A12, dq.x, b2)) / __builtin_fmaf(alpha, S, A22);
-    P->var_dd[p][dir][l][src ^ 1][q] = make_float2(dx, dy);
 }
 
 // the last warp's increments added to the flow
@@ -264,9 +296,14 @@ hipError_t launch_var(const Group& g, int l, hipStream_t s)
     if (inner % 2) return hipErrorInvalidValue;   // the steps end in buffer 0
     hipLaunchKernelGGL(k_var_deriv, grid, blk, 0, s, B, l);
     hipLaunchKernelGGL(k_var_init, grid, blk, 0, s, B, l);
+    Batch BT;
+    make_batch(g, BT, [&](const DevPlan& h) {
+        return h.use_flow == 2 && h.flow_mode != VS_FLOW_SURROGATE && l < h.levels ? h.var_toff[l][2 * h.n_pairs] : 0;
+    });
+    const dim3 tgrid(BT.off[BT.n]);
     for (int o = 0; o < outer; ++o) {
         hipLaunchKernelGGL(k_var_warp, grid, blk, 0, s, B, l, o > 0 ? 1 : 0);
-        for (int it = 0; it < inner; ++it) hipLaunchKernelGGL(k_var_jacobi, grid, blk, 0, s, B, l, it & 1);
+        for (int it = 0; it < inner; ++it) hipLaunchKernelGGL(k_var_jacobi, tgrid, blk, 0, s, BT, l, it & 1);
     }
     if (outer > 0) hipLaunchKernelGGL(k_var_fold, grid, blk, 0, s, B, l);
     return hipGetLastError();
