@@ -233,6 +233,11 @@ def main():
     ap.add_argument("--copy-calibration-mb", type=int, default=0,
                     help="also run one plain device-to-device copy of this many MiB (a "
                          "counter reference for rocprofv3 byte counters)")
+    ap.add_argument("--no-variational", action="store_true", help="skip the variational-flow leg")
+    ap.add_argument("--var-steps", type=int, default=100, help="frames timed in the variational-flow leg")
+    ap.add_argument("--conv-rate", action="store_true",
+                    help="only time the matrix-core 3x3 convolution on level-0 strip sizes "
+                         "(8 images of 1080 x 256) for the layer shapes the library builds")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py: the stitching path runs on one GPU (how it would shard across GPUs is a "
@@ -244,6 +249,8 @@ def main():
     from paper_2308_09209_amd import vstitch as V
     from paper_2308_09209_amd.scenes import WORKLOADS, scene_for
 
+    if args.conv_rate:
+        return conv_rate(V)
     big = args.workload == "8x3840x2160_ring"
     if args.seq is None:
         args.seq = 4 if big else 60
@@ -297,7 +304,10 @@ def main():
     levels = info.lk_levels
     p = st.params
     flops = lk_flops_per_frame(info, p.lk_iters)
-    flops_impl = lk_flops_per_frame(info, p.lk_iters, per_tap_step=14, per_tap=6)
+    # as the kernel issues them: 5 FMA per tap once per level (normal matrix and
+    # template term); per tap and step 4 FMA plus the interpolation along x
+    # (1 sub + 1 FMA) of 10 moving-image rows per 9 window rows
+    flops_impl = lk_flops_per_frame(info, p.lk_iters, per_tap_step=8 + 3 * 10 / 9, per_tap=10)
     taps = sum(int(info.flow_taps[q][l]) for q in range(info.n_pairs) for l in range(levels))
     lk_launch_ms = step_ms[2] / nfr / levels
     achieved = flops / levels / (lk_launch_ms * 1e-3) / 1e12
@@ -312,7 +322,8 @@ def main():
                                f"flow domain ({taps} taps per direction per frame, {p.lk_iters} steps, "
                                "2 directions)",
                     achieved_impl_count=round(flops_impl / levels / (lk_launch_ms * 1e-3) / 1e12, 3),
-                    impl_count="6 flop per tap (normal matrix) + 14 per tap and step, as the kernel "
+                    impl_count="10 flop per tap (normal matrix, template term) + 11.33 per tap and step "
+                               "(4 FMA, interpolation along x shared by two window rows), as the kernel "
                                "issues them")
     names = V.Stitcher.TIMING_STEPS
     metric = ("panorama Mpix/s + p99 frame ms, 4x1080p; surrogate vs plain flow @EPE<=0.5px"
@@ -333,6 +344,8 @@ def main():
                frame_roofline=frame_roofline(wl, H, W, flops, FP32_VECTOR_PEAK_TFLOPS, wall / K * 1e3))
     if args.flow != "plain" and os.path.exists(args.weights):
         out["surrogate"] = surrogate_leg(args, V, rig, frames, st, K, H, W, mpix, float(np.percentile(lat, 99)))
+    if not args.no_variational:
+        out["variational"] = variational_leg(args, V, rig, frames, st, H, W, mpix)
     if not args.no_cpu_baseline:
         print(f"# timing the CPU oracle on {args.cpu_frames} frames", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(scene, host_frames, min(args.cpu_frames, seq))
@@ -389,6 +402,107 @@ def surrogate_leg(args, V, rig, frames, st_plain, K, H, W, mpix_plain, p99_plain
                           unit="TFLOP/s", note="network flops (first layer on its 2 non-zero input "
                           "channels) over the whole flow step (5 convolutions, upsampling, "
                           "forward-backward check, fallback)"))
+
+
+def conv_rate(V, H=1080, W=256, N=8, K=20):
+    """Matrix-core 3x3 convolution rate (BF16 in and out, FP32 accumulation,
+    leaky ReLU) on N images of H x W -- the level-0 strips of a 4 x 1080p ring,
+    both directions of its 4 pairs -- for each layer shape the library builds."""
+    import ctypes as C
+
+    import torch
+    imgs = V.nn_images([(H, W)] * N)
+    P = H * W * N
+    out = {}
+    for cin, cout in ((16, 32), (32, 32), (32, 16)):
+        x = torch.randint(-16000, 16000, (P * cin,), dtype=torch.int16, device="cuda")
+        w = torch.randint(-2000, 2000, (cout * 9 * cin,), dtype=torch.int16, device="cuda")
+        b = torch.zeros(cout, dtype=torch.float32, device="cuda")
+        y = torch.empty(P * cout, dtype=torch.int16, device="cuda")
+
+        def run():
+            V.check(V.lib().vs_nn_conv3x3(C.c_void_p(x.data_ptr()), cin, C.c_void_p(w.data_ptr()),
+                                          C.c_void_p(b.data_ptr()), C.c_void_p(y.data_ptr()), cout,
+                                          C.byref(imgs), V.CONV_LRELU, 0.1, None), "vs_nn_conv3x3")
+        for _ in range(3):
+            run()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(K):
+            run()
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / K
+        fl = 2.0 * 9 * cin * cout * P
+        out[f"{cin}->{cout}"] = dict(ms=round(ms, 4), gflop=round(fl / 1e9, 3),
+                                     tflops=round(fl / ms / 1e9, 2),
+                                     frac=round(fl / ms / 1e9 / BF16_MFMA_PEAK_TFLOPS, 4))
+    print(json.dumps(dict(what="3x3 convolution rate", images=f"{N} x {H}x{W}", peak=BF16_MFMA_PEAK_TFLOPS,
+                          unit="TFLOP/s", layers=out)), flush=True)
+
+
+def var_bytes_per_frame(info, outer, inner):
+    """Algorithmic HBM bytes of the variational flow step per frame: per level
+    and pair, with n the field's pixels: derivatives 2 cameras x (4 read + 20
+    written), initialisation 2 directions x (8 written + 2 read), each warp 2 x
+    (U 8, the moving image and its 5 derivative planes 24, T 4 and its 2
+    gradient planes 8, coefficients 32 and increments 8 written; + 16 to fold
+    the previous increments after the first), each Jacobi step 2 x (coefficients
+    32, U 8, increments 8 and the domain mask 1 read, increments 8 written),
+    the last fold 2 x 24."""
+    total = 0
+    for p in range(info.n_pairs):
+        w, h = int(info.strip_w[p]), int(info.strip_h[p])
+        for l in range(info.lk_levels):
+            n = w * h
+            w, h = (w + 1) // 2, (h + 1) // 2
+            warps = sum(84 + (16 if o > 0 else 0) for o in range(outer))
+            total += n * (2 * 24 + 2 * 10 + 2 * warps + 2 * outer * inner * 57 + 2 * 24)
+    return total
+
+
+def variational_leg(args, V, rig, frames, st_plain, H, W, mpix_plain):
+    """The same frames with the variational flow alternative (flow = 2):
+    throughput, latency, its flows' end-point error against the plain
+    path's, and the flow step's rate against HBM on its algorithmic bytes."""
+    sv = V.Stitcher(rig, flow=2)
+    pano = sv.new_pano()
+    ref = V.Stitcher(rig)
+    epes, p99s = [], []
+    for t in range(args.epe_frames):
+        ref.stitch(frames[t], pano=pano)
+        sv.stitch(frames[t], pano=pano)
+        e, e99 = flow_epe(sv, ref)
+        epes.append(e)
+        p99s.append(e99)
+    ref.close()
+    for i in range(min(args.warmup, 5)):
+        sv.stitch(frames[i % len(frames)], pano=pano)
+    K = args.var_steps
+    wall, lat, step_ms, nfr = time_frames(sv, frames, pano, args.warmup, K)
+    print(f"# variational: timed {K} frames in {wall:.3f} s", file=sys.stderr, flush=True)
+    p = sv.params
+    flow_ms = step_ms[2] / nfr
+    vb = var_bytes_per_frame(sv.info, p.var_outer, p.var_inner)
+    names = V.Stitcher.TIMING_STEPS
+    out = dict(flow=f"variational (L={sv.info.lk_levels}, {p.var_outer} warps x {p.var_inner} Jacobi steps, "
+                    f"alpha={p.var_alpha:g}, gamma={p.var_gamma:g})",
+               value=round(K * H * W / wall / 1e6, 2), unit="Mpix/s", ms_per_step=round(wall / K * 1e3, 4),
+               p50_ms=round(float(np.percentile(lat, 50)), 4), p99_ms=round(float(np.percentile(lat, 99)), 4),
+               vs_plain=round(K * H * W / wall / 1e6 / mpix_plain, 3),
+               epe_vs_plain_px=round(float(np.mean(epes)), 4), epe_p99_px=round(float(np.mean(p99s)), 4),
+               epe_frames=args.epe_frames,
+               step_ms={n: round(v / nfr, 5) for n, v in zip(names, step_ms)},
+               roofline=dict(bound="hbm", kernel="vs::k_var_* (the whole variational flow step)",
+                             achieved=round(vb / (flow_ms * 1e-3) / 1e9, 1), peak=HBM_PEAK_GBS, unit="GB/s",
+                             frac=round(vb / (flow_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4), traffic=None,
+                             bytes_per_frame=vb,
+                             unit_bytes="per level and field pixel: derivatives, initialisation, warps and "
+                                        "Jacobi steps (57 B each: coefficients, flow, increments, mask read; "
+                                        "increments written), fold"))
+    sv.close()
+    return out
 
 
 IN_FLIGHT = 3
