@@ -257,12 +257,15 @@ vs_status vs_get_timing(vs_ctx* c, double ms[6], uint32_t* frames);
 
 /* Flow-kernel variant of one pyramid level: 0 = generic kernel (16 x 16
  * pixel tiles, any radius), 1, 2, 3 or 4 = the 9x9-window kernel (radius 4)
- * with that many vertically adjacent pixels per thread, 9, 10, 11 or 12 = the
- * same with two alternating register sets for the interpolated moving-image
- * rows (more registers, fewer instructions).  Results are identical for every
- * variant; only speed differs.  vs_create picks one per level; the
- * autotuner below measures them. */
-#define VS_FLOW_VARIANTS 8   /* 9x9-window variants the autotuner measures: 1, 2, 3, 4, 9, 10, 11, 12 */
+ * with that many vertically adjacent pixels per thread; + 8 (VS_FLOW_ALT):
+ * the previous gradient row kept in a second register set instead of read
+ * again from LDS; + 16 (VS_FLOW_INBLOCK): pixels whose displacement leaves
+ * the staged tile are finished by their own block at its end instead of by a
+ * tail launch.  Results are identical for every variant; only speed differs.
+ * vs_create picks one per level; the autotuner below measures them. */
+#define VS_FLOW_ALT 8
+#define VS_FLOW_INBLOCK 16
+#define VS_FLOW_VARIANTS 12  /* variants the autotuner measures: 1, 2, 3, 4, 9, 10, 11, 12, 25, 26, 27, 28 */
 vs_status vs_set_flow_variant(vs_ctx* c, int level, int variant);
 vs_status vs_get_flow_variant(const vs_ctx* c, int32_t variant[VS_MAX_LEVELS]);
 
@@ -283,10 +286,10 @@ vs_status vs_batch_destroy(vs_batch* b);
 const char* vs_batch_last_error(const vs_batch* b);
 
 /* Autotuner: for every pyramid level, run the batch on the given frames with
- * each 9x9 flow-kernel variant (1, 2, 3, 4, 9, 10, 11, 12), `reps` timed runs
- * each, and keep the fastest.  ms[l][i] receives the mean frame time of
- * variant {1, 2, 3, 4, 9, 10, 11, 12}[i] at level l (may be NULL); choice[l]
- * the variant kept.
+ * each 9x9 flow-kernel variant (1, 2, 3, 4, 9, 10, 11, 12, 25, 26, 27, 28),
+ * `reps` timed runs each, and keep the fastest.  ms[l][i] receives the mean
+ * frame time of the i-th of those variants at level l (may be NULL);
+ * choice[l] the variant kept.
  * The colour states are restored afterwards.  Synchronous. */
 vs_status vs_batch_autotune(vs_batch* b, const uint8_t* const* const frames[], uint8_t* const panos[], int reps,
                             float ms[VS_MAX_LEVELS][VS_FLOW_VARIANTS], int32_t choice[VS_MAX_LEVELS]);

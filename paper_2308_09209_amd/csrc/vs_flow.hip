@@ -784,14 +784,16 @@ hipError_t launch_lk(const Group& g, int l, hipStream_t s)
 {
     // every context of a group runs the same flow-kernel variant at a level:
     // 0 generic, else pixels per thread (1, 2, 4) plus 8 for alternating row registers
-    const int P = g.hp[0]->lk_P[l];
+    const int code = g.hp[0]->lk_P[l];
     for (int c = 1; c < g.n; ++c)
-        if (g.hp[c]->lk_P[l] != P) return hipErrorInvalidValue;
+        if (g.hp[c]->lk_P[l] != code) return hipErrorInvalidValue;
+    const int P = code & 15;
     Batch B;
     // a context whose flows all come from the surrogate launches no flow blocks
     auto plain = [](const DevPlan& h) { return h.use_flow == 1 && h.flow_mode != VS_FLOW_SURROGATE; };
     // fallback contexts: deferred pixels finished in-block, no tail launch
-    bool inblock = false;
+    // (and variants that ask for it: no tail launch)
+    bool inblock = (code & VS_FLOW_INBLOCK) != 0;
     for (int c = 0; c < g.n; ++c) inblock = inblock || g.hp[c]->flow_mode == VS_FLOW_SURROGATE_FALLBACK;
     if (make_batch(g, B, [&](const DevPlan& h) { return plain(h) && l < h.levels ? h.lk_off[l][2 * h.n_pairs] : 0; })) {
         const dim3 grid(B.off[B.n]);

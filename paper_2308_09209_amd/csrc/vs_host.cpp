@@ -135,16 +135,18 @@ void free_ctx(vs_ctx* c)
 // (n16) and the blocks the device holds at once (`resident`, four staged flow
 // blocks per compute unit): the most pixels per thread P (4, 3, 2, 1; n16 * 4 / P
 // blocks) that still gives at least one full wave of blocks, else P = 1 (the
-// most blocks for a small level).  Every P takes the form that keeps the
-// previous gradient row in registers (+8): with the regrouped right-hand side
-// it costs no occupancy at P = 4 and saves the row's second LDS read.
+// most blocks for a small level), whose few deferred pixels are then finished
+// in-block (a tail launch costs more than they do).  Every P takes the form
+// that keeps the previous gradient row in registers: with the regrouped
+// right-hand side it costs no occupancy at P = 4 and saves the row's second
+// LDS read.
 int default_lk_P(int n16, int resident)
 {
     for (int P = 4; P >= 1; --P) {
         const long blocks = ((long)n16 * 4 + P - 1) / P;
-        if (blocks >= resident) return P + 8;
+        if (blocks >= resident) return P + VS_FLOW_ALT;
     }
-    return 1 + 8;
+    return 1 + VS_FLOW_ALT + VS_FLOW_INBLOCK;
 }
 
 // blocks of the staged flow kernel the current device holds at once
@@ -884,7 +886,7 @@ vs_status vs_set_flow_variant(vs_ctx* c, int level, int variant)
 {
     if (!c || level < 0 || level >= c->hp.levels) return VS_E_INVAL;
     if (c->sticky) return VS_E_DEVICE;
-    if (!(variant == 0 || ((variant & 7) >= 1 && (variant & 7) <= 4 && (variant & ~15) == 0))) return VS_E_INVAL;
+    if (!(variant == 0 || ((variant & 7) >= 1 && (variant & 7) <= 4 && (variant & ~31) == 0))) return VS_E_INVAL;
     if (variant > 0 && c->hp.lk_radius != LK_R_MAX) return fail(c, VS_E_UNSUPPORTED, "9x9 kernel needs lk_radius 4");
     if (variant == 0 && c->hp.lk_qcap[level] > 0) {
         // the generic kernel finishes every pixel itself; nothing else changes
@@ -1237,7 +1239,7 @@ vs_status vs_batch_autotune(vs_batch* b, const uint8_t* const* const frames[], u
     }
     hipEvent_t e0, e1;
     if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) return VS_E_DEVICE;
-    const int variants[VS_FLOW_VARIANTS] = {1, 2, 3, 4, 9, 10, 11, 12};
+    const int variants[VS_FLOW_VARIANTS] = {1, 2, 3, 4, 9, 10, 11, 12, 25, 26, 27, 28};
     vs_status st = VS_OK;
     for (int l = 0; l < levels && st == VS_OK; ++l) {
         float best = 1e30f;

@@ -42,19 +42,28 @@ __device__ __forceinline__ float cdy(const float* __restrict__ a, int w, int h, 
     return 0.5f * (at_clamped(a, w, h, x, y + 1) - at_clamped(a, w, h, x, y - 1));
 }
 
-// bilinear sample of a level plane at (X, Y), the position clamped into it
-__device__ __forceinline__ float bil(const float* __restrict__ a, int w, int h, float X, float Y)
+// Bilinear samples of level planes at (X, Y), the position clamped into the
+// level: the clamped corners and weights computed once for several planes.
+struct BilAt {
+    int i00, i10, i01, i11;
+    float fx, fy;
+};
+
+__device__ __forceinline__ BilAt bil_at(int w, int h, float X, float Y)
 {
     const float cx = clampf(X, 0.0f, (float)(w - 1)), cy = clampf(Y, 0.0f, (float)(h - 1));
     const float flx = floorf(cx), fly = floorf(cy);
     const int x0 = (int)flx, y0 = (int)fly;
-    const float fx = cx - flx, fy = cy - fly;
     const int x1 = x0 + 1 < w ? x0 + 1 : w - 1, y1 = y0 + 1 < h ? y0 + 1 : h - 1;
-    const float p00 = a[(size_t)y0 * w + x0], p10 = a[(size_t)y0 * w + x1];
-    const float p01 = a[(size_t)y1 * w + x0], p11 = a[(size_t)y1 * w + x1];
-    const float t = __builtin_fmaf(fx, p10 - p00, p00);
-    const float b = __builtin_fmaf(fx, p11 - p01, p01);
-    return __builtin_fmaf(fy, b - t, t);
+    return BilAt{y0 * w + x0, y0 * w + x1, y1 * w + x0, y1 * w + x1, cx - flx, cy - fly};
+}
+
+__device__ __forceinline__ float bil_of(const float* __restrict__ a, const BilAt& B)
+{
+    const float p00 = a[B.i00], p10 = a[B.i10], p01 = a[B.i01], p11 = a[B.i11];
+    const float t = __builtin_fmaf(B.fx, p10 - p00, p00);
+    const float b = __builtin_fmaf(B.fx, p11 - p01, p01);
+    return __builtin_fmaf(B.fy, b - t, t);
 }
 
 // Derivative planes of each camera's level image (field f = 2 p + camera):
@@ -142,16 +151,18 @@ __global__ __launch_bounds__(256) void k_var_warp(const Batch B, int l, int fold
     const float* __restrict__ Mv = P->pyr[p][mc][l];
     const float* __restrict__ MD = P->var_D[p][mc][l];
     const float* __restrict__ TD = P->var_D[p][tc][l];
-    const float mw = bil(Mv, w, h, X, Y), mx = bil(MD, w, h, X, Y), my = bil(MD + n, w, h, X, Y);
+    const BilAt at = bil_at(w, h, X, Y);
+    const float mw = bil_of(Mv, at), mx = bil_of(MD, at), my = bil_of(MD + n, at);
+    const float mxx = bil_of(MD + 2 * n, at), mxy = bil_of(MD + 3 * n, at), myy = bil_of(MD + 4 * n, at);
     float* __restrict__ co = P->var_co[p][dir][l];
     co[q] = mw - P->pyr[p][tc][l][q];
     co[n + q] = mx;
     co[2 * n + q] = my;
     co[3 * n + q] = mx - TD[q];
     co[4 * n + q] = my - TD[n + q];
-    co[5 * n + q] = bil(MD + 2 * n, w, h, X, Y);
-    co[6 * n + q] = bil(MD + 3 * n, w, h, X, Y);
-    co[7 * n + q] = bil(MD + 4 * n, w, h, X, Y);
+    co[5 * n + q] = mxx;
+    co[6 * n + q] = mxy;
+    co[7 * n + q] = myy;
     dd[q] = make_float2(0.0f, 0.0f);
 }
 
@@ -180,6 +191,26 @@ __global__ __launch_bounds__(256) void k_var_jacobi(const Batch B, int l, int sr
     const float2* __restrict__ U = P->flow[p][dir][l];
     const float2* __restrict__ d = P->var_dd[p][dir][l][src];
     const int tid = threadIdx.x;
+    const size_t n = (size_t)w * h;
+    const float* __restrict__ co = P->var_co[p][dir][l];
+    const int x = x0 + (tid & 63);
+    // this thread's pixels' own values, loaded before the staging so that
+    // their latency overlaps it
+    constexpr int NP = VAR_TY / 4;
+    float cf[NP][8];
+    float2 uo[NP], dqo[NP];
+    bool in[NP], nd[NP];
+#pragma unroll
+    for (int k = 0; k < NP; ++k) {
+        const int y = y0 + (tid >> 6) + 4 * k;
+        in[k] = x < w && y < h;
+        const size_t q = in[k] ? (size_t)y * w + x : 0;
+        uo[k] = U[q];
+        dqo[k] = d[q];
+        nd[k] = in[k] && P->need[p][l][q] != 0;
+#pragma unroll
+        for (int j = 0; j < 8; ++j) cf[k][j] = co[j * n + q];
+    }
     for (int i = tid; i < RH * RW; i += 256) {
         const int xx = x0 - 1 + i % RW, yy = y0 - 1 + i / RW;
         float2 v = make_float2(0.0f, 0.0f);
@@ -214,20 +245,17 @@ __global__ __launch_bounds__(256) void k_var_jacobi(const Batch B, int l, int sr
         sS[i] = s;
     }
     __syncthreads();
-    const size_t n = (size_t)w * h;
-    const float* __restrict__ co = P->var_co[p][dir][l];
     const float alpha = P->var_alpha, gamma = P->var_gamma;
-    const int x = x0 + (tid & 63);
 #pragma unroll
-    for (int k = 0; k < VAR_TY / 4; ++k) {
+    for (int k = 0; k < NP; ++k) {
         const int ty = (tid >> 6) + 4 * k, y = y0 + ty;
-        if (x >= w || y >= h) continue;
+        if (!in[k]) continue;
         const size_t q = (size_t)y * w + x;
-        const float2 u = U[q], dq = d[q];
+        const float2 u = uo[k], dq = dqo[k];
         float A11 = 0.0f, A12 = 0.0f, A22 = 0.0f, b1 = 0.0f, b2 = 0.0f;
-        if (P->need[p][l][q]) {
-            const float c0 = co[q], c1 = co[n + q], c2 = co[2 * n + q], c3 = co[3 * n + q];
-            const float c4 = co[4 * n + q], c5 = co[5 * n + q], c6 = co[6 * n + q], c7 = co[7 * n + q];
+        if (nd[k]) {
+            const float c0 = cf[k][0], c1 = cf[k][1], c2 = cf[k][2], c3 = cf[k][3];
+            const float c4 = cf[k][4], c5 = cf[k][5], c6 = cf[k][6], c7 = cf[k][7];
             const float e = __builtin_fmaf(c2, dq.y, __builtin_fmaf(c1, dq.x, c0));
             const float pd = 0.5f / sqrtf(__builtin_fmaf(e, e, VAR_EPS2));
             const float gx = __builtin_fmaf(c6, dq.y, __builtin_fmaf(c5, dq.x, c3));

@@ -30,8 +30,9 @@ TAP = dict(strip=1, mask=2, hist=3, lut=4, mom=5, mpair=6, mk=7, flags=8, pyr=9,
            pano_pre=11, pano_hist=12, bal_lut=13, quant=14, mbar=15, cover=16, need=17,
            deferred=18, surr_pred=19, fb=20, surr_ok=21)
 FLOW_PLAIN, FLOW_SURROGATE, FLOW_SURROGATE_FALLBACK = 0, 1, 2
-FLOW_VARIANTS = 8   # 9x9 flow-kernel variants the autotuner measures: 1, 2, 3, 4, 9, 10, 11, 12
-FLOW_VARIANT_CODES = (1, 2, 3, 4, 9, 10, 11, 12)
+FLOW_VARIANTS = 12  # 9x9 flow-kernel variants the autotuner measures
+FLOW_VARIANT_CODES = (1, 2, 3, 4, 9, 10, 11, 12, 25, 26, 27, 28)
+FLOW_ALT, FLOW_INBLOCK = 8, 16
 
 # every symbol include/vstitch.h declares
 EXPORTS = ["vs_abi_version", "vs_status_str", "vs_default_params", "vs_compose_homographies",

@@ -63,7 +63,7 @@ def test_flow_variants_are_bitwise_equal():
     base = V.Stitcher(sc.rig(), debug_taps=1)
     want = [base.stitch(dev(sc.frames(t))).cpu().numpy() for t in range(2)]
     wflow = base.tap("flow", 0, 0)
-    for variant in (0, 1, 2, 3, 4, 9, 10, 11, 12):
+    for variant in (0, 1, 2, 3, 4, 9, 10, 11, 12, 25, 26, 27, 28):
         st = V.Stitcher(sc.rig(), debug_taps=1)
         for l in range(st.info.lk_levels):
             st.set_flow_variant(l, variant)

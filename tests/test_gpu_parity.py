@@ -237,14 +237,15 @@ def test_parity_4x1920x1080_ring_full_size():
 def test_deferred_flow_pixels_match_oracle():
     """Residual displacements of up to 12 px per camera: flow pixels leave the
     staged tile and finish in the tail kernel (16 lanes per pixel, the sums
-    handed down the row lanes); the flows of every pair and direction bit for
-    bit against the oracle, for the staged kernel + tail and for the generic
-    kernel, which finishes every pixel itself."""
+    handed down the row lanes, or, with VS_FLOW_INBLOCK, in their own block);
+    the flows of every pair and direction bit for bit against the oracle, for
+    the staged kernel + tail, the staged kernel finishing its own deferred
+    pixels, and the generic kernel, which finishes every pixel itself."""
     sc = small_scene(n_cams=3, W=320, H=160, overlap=0.3, ring=True, seed_config=95, resid=12.0)
     orc = O.Oracle(sc.rig())
     frames = sc.frames(0)
     want = orc.stitch(frames)
-    for variant in (4, 11, 0):
+    for variant in (4, 11, 28, 25, 0):
         st = V.Stitcher(sc.rig(), debug_taps=1)
         for lvl in range(st.info.lk_levels):
             st.set_flow_variant(lvl, variant)
@@ -254,7 +255,7 @@ def test_deferred_flow_pixels_match_oracle():
             f"panorama max diff {lsb(pano, want)} LSB")
         if variant in (4, 11):
             assert deferred[0] > 0
-        else:
+        else:   # finished in-block or by the generic kernel: no queue
             assert sum(deferred) == 0
         for p in range(orc.n_pairs):
             for d in (0, 1):
