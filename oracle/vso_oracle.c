@@ -998,9 +998,10 @@ static void step_flow(vso_ctx* c)
 /* A chain of 3x3 convolutions maps the level-2 luma pair of a field          */
 /* (template, moving) to the field's flow in level-2 pixels.  Network input:  */
 /* channel 0 = bf16((Y_t - 128) / 64), channel 1 = bf16((Y_m - 128) / 64),     */
-/* other channels 0.  Each layer: the exact sum of its BF16 products and the  */
-/* bias (FP64, rounded once to FP32); hidden layers apply a leaky ReLU in     */
-/* FP32 and store BF16 (round to nearest even); the last layer stays FP32 and */
+/* other channels 0.  Each layer: its BF16 products (each exact in FP64)     */
+/* accumulated with the bias in FP64, rounded once to FP32; hidden layers     */
+/* apply a leaky ReLU in FP32 and store BF16 (round to nearest even); the     */
+/* last layer stays FP32 and                                                  */
 /* its channels 0-1 are the flow.  The level-0 flow is the bilinear          */
 /* upsampling x4 (level-0 x maps to level-2 x / 4 - 3 / 8).  A pair keeps     */
 /* the surrogate's flows when its forward-backward error                      */
