@@ -222,7 +222,11 @@ def main():
                     help="the 6-stream batched workload (2x1280x720, 2x1920x1080, 2x2560x1440, "
                          "3-4 cameras each) through one captured graph, instead of the ring; with an "
                          "explicit --workload, that one workload through the captured graph")
-    ap.add_argument("--autotune", action="store_true", help="autotune the flow kernel first (batch)")
+    ap.add_argument("--autotune", action="store_true",
+                    help="autotune the flow kernel and the fused pyramid's tile height first (batch)")
+    ap.add_argument("--tune-records", default=None,
+                    help="tuning-record file: loaded before the contexts are created (when it exists) "
+                         "and, after --autotune, written back")
     ap.add_argument("--flow", choices=sorted(FLOW_MODES), default=None,
                     help="flow mode of the surrogate leg (default fallback; plain: no surrogate leg); "
                          "with --batch the flow mode of every stream (default plain)")
@@ -276,15 +280,7 @@ def main():
     frames = [[torch.from_numpy(f).to(dev) for f in fr] for fr in host_frames]
 
     if args.copy_calibration_mb > 0:
-        n = args.copy_calibration_mb << 20
-        src = torch.empty(n, dtype=torch.uint8, device=dev).fill_(1)
-        dst = torch.empty_like(src)
-        torch.cuda.synchronize()
-        dst.copy_(src)
-        torch.cuda.synchronize()
-        del src, dst
-        print(f"# copied {args.copy_calibration_mb} MiB device to device (counter reference)",
-              file=sys.stderr, flush=True)
+        copy_calibration(args.copy_calibration_mb, dev)
 
     st = V.Stitcher(rig)
     info = st.info
@@ -369,7 +365,7 @@ def surrogate_leg(args, V, rig, frames, st_plain, K, H, W, mpix_plain, p99_plain
     # EPE against the plain path: both contexts fed the same frames from T = 0
     ref = V.Stitcher(rig)
     epes, p99s, kept, pairs = [], [], 0, 0
-    for t in range(args.epe_frames):
+    for t in range(min(args.epe_frames, len(frames))):
         ref.stitch(frames[t], pano=pano)
         _, _, info = ss.stitch(frames[t], pano=pano, want_info=True)
         e, e99 = flow_epe(ss, ref)
@@ -393,7 +389,7 @@ def surrogate_leg(args, V, rig, frames, st_plain, K, H, W, mpix_plain, p99_plain
                 speedup_vs_plain=round(mpix / mpix_plain, 3),
                 p99_vs_plain=round(float(np.percentile(lat, 99)) / p99_plain, 3),
                 epe_vs_plain_px=round(float(np.mean(epes)), 4), epe_p99_px=round(float(np.mean(p99s)), 4),
-                epe_frames=args.epe_frames, pairs_kept=f"{kept}/{pairs}",
+                epe_frames=min(args.epe_frames, len(frames)), pairs_kept=f"{kept}/{pairs}",
                 step_ms={n: round(v / nfr, 5) for n, v in zip(names, step_ms)},
                 frame_roofline=frame_roofline(WORKLOADS[args.workload], H, W, fl, BF16_MFMA_PEAK_TFLOPS,
                                               wall / K * 1e3),
@@ -402,6 +398,20 @@ def surrogate_leg(args, V, rig, frames, st_plain, K, H, W, mpix_plain, p99_plain
                           unit="TFLOP/s", note="network flops (first layer on its 2 non-zero input "
                           "channels) over the whole flow step (5 convolutions, upsampling, "
                           "forward-backward check, fallback)"))
+
+
+def copy_calibration(mib, dev):
+    """one plain device-to-device copy of `mib` MiB: the reference the
+    rocprofv3 byte counters are scaled by"""
+    import torch
+    n = mib << 20
+    src = torch.empty(n, dtype=torch.uint8, device=dev).fill_(1)
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    del src, dst
+    print(f"# copied {mib} MiB device to device (counter reference)", file=sys.stderr, flush=True)
 
 
 def conv_rate(V, H=1080, W=256, N=8, K=20):
@@ -470,7 +480,7 @@ def variational_leg(args, V, rig, frames, st_plain, H, W, mpix_plain):
     pano = sv.new_pano()
     ref = V.Stitcher(rig)
     epes, p99s = [], []
-    for t in range(args.epe_frames):
+    for t in range(min(args.epe_frames, len(frames))):
         ref.stitch(frames[t], pano=pano)
         sv.stitch(frames[t], pano=pano)
         e, e99 = flow_epe(sv, ref)
@@ -492,7 +502,7 @@ def variational_leg(args, V, rig, frames, st_plain, H, W, mpix_plain):
                p50_ms=round(float(np.percentile(lat, 50)), 4), p99_ms=round(float(np.percentile(lat, 99)), 4),
                vs_plain=round(K * H * W / wall / 1e6 / mpix_plain, 3),
                epe_vs_plain_px=round(float(np.mean(epes)), 4), epe_p99_px=round(float(np.mean(p99s)), 4),
-               epe_frames=args.epe_frames,
+               epe_frames=min(args.epe_frames, len(frames)),
                step_ms={n: round(v / nfr, 5) for n, v in zip(names, step_ms)},
                roofline=dict(bound="hbm", kernel="vs::k_var_* (the whole variational flow step)",
                              achieved=round(vb / (flow_ms * 1e-3) / 1e9, 1), peak=HBM_PEAK_GBS, unit="GB/s",
@@ -524,6 +534,10 @@ def bench_batch(args):
         print(f"# frame {t} generated ({time.perf_counter() - t_gen:.1f} s)", file=sys.stderr, flush=True)
     print(f"# generated {seq} frames of {len(scenes)} streams in {time.perf_counter() - t_gen:.1f} s",
           file=sys.stderr, flush=True)
+    if args.copy_calibration_mb > 0:
+        copy_calibration(args.copy_calibration_mb, dev)
+    if args.tune_records and os.path.exists(args.tune_records):
+        V.tune_load(args.tune_records)
     sts = [V.Stitcher(sc.rig()) for sc in scenes]
     use_surr = args.flow != "plain" and os.path.exists(args.weights)
     if use_surr:
@@ -537,6 +551,8 @@ def bench_batch(args):
     choice = [int(v) for v in sts[0].flow_variants()]
     if args.autotune:
         choice, _ = batch.autotune(frames[0], panos, reps=3)
+        if args.tune_records:
+            V.tune_save(args.tune_records)
     for i in range(args.warmup):
         batch.run(frames[i % seq], panos)
     torch.cuda.synchronize()
@@ -569,6 +585,7 @@ def bench_batch(args):
                config=dict(workload=args.workload or "6stream_batch", streams=streams,
                            panorama_mpix_per_step=round(px / 1e6, 3), seq_frames=seq,
                            flow_variant_per_level=choice, autotuned=bool(args.autotune),
+                           pyr_tile_rows=[int(st.tuning().pyr_tile_rows) for st in sts],
                            flow=args.flow if use_surr else "plain",
                            fb_tau_px=args.fb_tau if use_surr and args.flow == "fallback" else None,
                            steps_in_flight=IN_FLIGHT, parallelism="single GPU"),

@@ -289,10 +289,41 @@ const char* vs_batch_last_error(const vs_batch* b);
  * each 9x9 flow-kernel variant (1, 2, 3, 4, 9, 10, 11, 12, 25, 26, 27, 28),
  * `reps` timed runs each, and keep the fastest.  ms[l][i] receives the mean
  * frame time of the i-th of those variants at level l (may be NULL);
- * choice[l] the variant kept.
+ * choice[l] the variant kept.  Then, with 3 or more levels, the fused
+ * pyramid's tile height (8 or 16 level-2 rows) the same way.  Every context's
+ * choice is recorded in the tuning records (vs_tune_put).
  * The colour states are restored afterwards.  Synchronous. */
 vs_status vs_batch_autotune(vs_batch* b, const uint8_t* const* const frames[], uint8_t* const panos[], int reps,
                             float ms[VS_MAX_LEVELS][VS_FLOW_VARIANTS], int32_t choice[VS_MAX_LEVELS]);
+
+/* Tuning records: what the autotuner chose for one device architecture and
+ * one plan shape, kept process-wide by the library (thread-safe), written to
+ * and read from a text file (one record per line: "vstune1 arch n_cams
+ * canvas_w canvas_h lk_levels lk_radius v0 .. v5 pyr_tile_rows"), and applied
+ * by vs_create to a context whose key matches (its flow variants per level
+ * and its fused-pyramid tile height).  vs_batch_autotune records every
+ * context it tunes.  The records only pick among variants whose results are
+ * identical, so applying one never changes an output.
+ * vs_tune_get: VS_E_UNSUPPORTED when no record matches.
+ * vs_tune_load: VS_E_INVAL (nothing loaded) on a malformed file, an unknown
+ *   variant code or tile height; records replace those of equal keys.
+ * vs_tune_key_of / vs_get_tuning: the key and the current choice of a
+ *   context (host only). */
+typedef struct {
+    char arch[32];                      /* device architecture, e.g. "gfx950" (NUL-terminated) */
+    int32_t n_cams, canvas_w, canvas_h, lk_levels, lk_radius;
+} vs_tune_key;
+typedef struct {
+    int32_t flow_variant[VS_MAX_LEVELS];   /* vs_set_flow_variant codes; 0 past lk_levels */
+    int32_t pyr_tile_rows;                 /* 8 or 16 (levels 0-2 in one pass), 0 = keep the default */
+} vs_tune_entry;
+vs_status vs_tune_put(const vs_tune_key* k, const vs_tune_entry* e);
+vs_status vs_tune_get(const vs_tune_key* k, vs_tune_entry* e);
+vs_status vs_tune_clear(void);
+vs_status vs_tune_save(const char* path);
+vs_status vs_tune_load(const char* path);
+vs_status vs_tune_key_of(const vs_ctx* c, vs_tune_key* k);
+vs_status vs_get_tuning(const vs_ctx* c, vs_tune_entry* e);
 
 /* ------------------------------------------------------------------------
  * Learned flow surrogate (an addition to the paper's method): a small 3x3

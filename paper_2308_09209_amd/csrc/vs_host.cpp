@@ -5,6 +5,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -45,12 +46,80 @@ struct vs_ctx {
     // bumped whenever the launch sequence changes (flow variant, surrogate):
     // a batch holding this context recaptures its graph
     uint32_t gen = 0;
+    char arch[32] = {};                  // device architecture at create (tuning-record key)
 };
 
 namespace {
 
 const char* kStatus[] = {"ok", "invalid argument", "geometry", "out of memory", "device error",
                          "state mismatch", "unsupported"};
+
+// ---- tuning records (process-wide) ----
+struct TuneRec {
+    vs_tune_key k;
+    vs_tune_entry e;
+};
+std::mutex g_tune_mu;
+std::vector<TuneRec> g_tune;
+
+bool tune_key_eq(const vs_tune_key& a, const vs_tune_key& b)
+{
+    return std::strncmp(a.arch, b.arch, sizeof a.arch) == 0 && a.n_cams == b.n_cams && a.canvas_w == b.canvas_w &&
+           a.canvas_h == b.canvas_h && a.lk_levels == b.lk_levels && a.lk_radius == b.lk_radius;
+}
+
+bool variant_code_ok(int v) { return v == 0 || ((v & 7) >= 1 && (v & 7) <= 4 && (v & ~31) == 0); }
+
+// a record usable for its own key: known codes on the key's levels (9x9
+// codes only with radius 4), 0 past them, tile height 0, 8 or 16
+bool tune_rec_ok(const vs_tune_key& k, const vs_tune_entry& e)
+{
+    if (k.arch[0] == 0 || std::memchr(k.arch, 0, sizeof k.arch) == nullptr) return false;
+    if (k.lk_levels < 1 || k.lk_levels > VS_MAX_LEVELS || k.n_cams < 2 || k.n_cams > VS_MAX_CAMS) return false;
+    for (int l = 0; l < VS_MAX_LEVELS; ++l) {
+        const int v = e.flow_variant[l];
+        if (!variant_code_ok(v) || (l >= k.lk_levels && v != 0) || (v > 0 && k.lk_radius != LK_R_MAX)) return false;
+    }
+    return e.pyr_tile_rows == 0 || e.pyr_tile_rows == 8 || e.pyr_tile_rows == 16;
+}
+
+void tune_put_locked(const vs_tune_key& k, const vs_tune_entry& e)
+{
+    for (TuneRec& r : g_tune)
+        if (tune_key_eq(r.k, k)) {
+            r.e = e;
+            return;
+        }
+    g_tune.push_back(TuneRec{k, e});
+}
+
+// the current device's architecture name without its feature suffixes
+void device_arch(char out[32])
+{
+    std::memset(out, 0, 32);
+    int dev = 0;
+    hipDeviceProp_t prop;
+    if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&prop, dev) != hipSuccess) {
+        std::strncpy(out, "unknown", 31);
+        return;
+    }
+    size_t n = 0;
+    while (n < 31 && prop.gcnArchName[n] && prop.gcnArchName[n] != ':') ++n;
+    std::memcpy(out, prop.gcnArchName, n);
+}
+
+// fused-pyramid tile height (level-2 rows) and its tile table
+void set_pyr_rows(DevPlan& h, int rows)
+{
+    h.pyrf_ty = rows;
+    h.pyrf_off[0] = 0;
+    for (int f = 0; f < 2 * h.n_pairs; ++f) {
+        const int p = f >> 1;
+        const int w2 = h.levels >= 3 ? h.lw[p][2] : 0, h2 = h.levels >= 3 ? h.lh[p][2] : 0;
+        h.pyrf_tx[f] = (w2 + PF_TX - 1) / PF_TX;
+        h.pyrf_off[f + 1] = h.pyrf_off[f] + h.pyrf_tx[f] * ((h2 + h.pyrf_ty - 1) / h.pyrf_ty);
+    }
+}
 
 // 3x3 product c = a b, entries ((a_r0 b_0c + a_r1 b_1c) + a_r2 b_2c)
 void mat3_mul(const double* a, const double* b, double* c)
@@ -481,14 +550,7 @@ vs_status vs_create(const vs_rig* rig, const vs_params* prm, vs_ctx** out)
         const int p = f >> 1;
         n16 += ((h.lw[p][2] + PF_TX - 1) / PF_TX) * ((h.lh[p][2] + 15) / 16);
     }
-    h.pyrf_ty = P.pyr_tile_rows ? P.pyr_tile_rows : (n16 >= 1536 ? 16 : 8);
-    h.pyrf_off[0] = 0;
-    for (int f = 0; f < 2 * h.n_pairs; ++f) {
-        const int p = f >> 1;
-        const int w2 = h.levels >= 3 ? h.lw[p][2] : 0, h2 = h.levels >= 3 ? h.lh[p][2] : 0;
-        h.pyrf_tx[f] = (w2 + PF_TX - 1) / PF_TX;
-        h.pyrf_off[f + 1] = h.pyrf_off[f] + h.pyrf_tx[f] * ((h2 + h.pyrf_ty - 1) / h.pyrf_ty);
-    }
+    set_pyr_rows(h, P.pyr_tile_rows ? P.pyr_tile_rows : (n16 >= 1536 ? 16 : 8));
     for (int l = 0; l < h.levels; ++l) {
         h.pyr_off[l][0] = 0;
         for (int f = 0; f < 2 * h.n_pairs; ++f) {
@@ -630,6 +692,18 @@ vs_status vs_create(const vs_rig* rig, const vs_params* prm, vs_ctx** out)
                 I.flow_px[p][l] = px;
                 I.flow_taps[p][l] = taps;
             }
+    }
+    // a tuning record for this device and plan shape: its flow variants and
+    // pyramid tile height (identical results, other speeds)
+    device_arch(c->arch);
+    {
+        vs_tune_key k;
+        vs_tune_entry te;
+        if (vs_tune_key_of(c, &k) == VS_OK && vs_tune_get(&k, &te) == VS_OK) {
+            for (int l = 0; l < h.levels; ++l)
+                if (h.lk_P[l] > 0 && te.flow_variant[l] > 0) set_lk_tiles(h, l, te.flow_variant[l]);
+            if (te.pyr_tile_rows && P.pyr_tile_rows == 0) set_pyr_rows(h, te.pyr_tile_rows);
+        }
     }
     // flow tiles that follow the domain, every level
     size_t tiles_n = 0;
@@ -1034,6 +1108,108 @@ vs_status vs_get_flow_variant(const vs_ctx* c, int32_t variant[VS_MAX_LEVELS])
     return VS_OK;
 }
 
+// ---------------------------------------------------------------------------
+// Tuning records
+// ---------------------------------------------------------------------------
+
+vs_status vs_tune_key_of(const vs_ctx* c, vs_tune_key* k)
+{
+    if (!c || !k) return VS_E_INVAL;
+    std::memset(k, 0, sizeof *k);
+    std::memcpy(k->arch, c->arch, sizeof k->arch);
+    k->n_cams = c->hp.n_cams;
+    k->canvas_w = c->hp.canvas_w;
+    k->canvas_h = c->hp.canvas_h;
+    k->lk_levels = c->hp.levels;
+    k->lk_radius = c->hp.lk_radius;
+    return VS_OK;
+}
+
+vs_status vs_get_tuning(const vs_ctx* c, vs_tune_entry* e)
+{
+    if (!c || !e) return VS_E_INVAL;
+    std::memset(e, 0, sizeof *e);
+    for (int l = 0; l < c->hp.levels; ++l) e->flow_variant[l] = c->hp.lk_P[l];
+    e->pyr_tile_rows = c->hp.levels >= 3 ? c->hp.pyrf_ty : 0;
+    return VS_OK;
+}
+
+vs_status vs_tune_put(const vs_tune_key* k, const vs_tune_entry* e)
+{
+    if (!k || !e || !tune_rec_ok(*k, *e)) return VS_E_INVAL;
+    std::lock_guard<std::mutex> lock(g_tune_mu);
+    tune_put_locked(*k, *e);
+    return VS_OK;
+}
+
+vs_status vs_tune_get(const vs_tune_key* k, vs_tune_entry* e)
+{
+    if (!k || !e) return VS_E_INVAL;
+    std::lock_guard<std::mutex> lock(g_tune_mu);
+    for (const TuneRec& r : g_tune)
+        if (tune_key_eq(r.k, *k)) {
+            *e = r.e;
+            return VS_OK;
+        }
+    return VS_E_UNSUPPORTED;
+}
+
+vs_status vs_tune_clear(void)
+{
+    std::lock_guard<std::mutex> lock(g_tune_mu);
+    g_tune.clear();
+    return VS_OK;
+}
+
+vs_status vs_tune_save(const char* path)
+{
+    if (!path) return VS_E_INVAL;
+    std::lock_guard<std::mutex> lock(g_tune_mu);
+    FILE* f = std::fopen(path, "w");
+    if (!f) return VS_E_INVAL;
+    bool ok = true;
+    for (const TuneRec& r : g_tune) {
+        ok = ok && std::fprintf(f, "vstune1 %s %d %d %d %d %d", r.k.arch, r.k.n_cams, r.k.canvas_w, r.k.canvas_h,
+                                r.k.lk_levels, r.k.lk_radius) > 0;
+        for (int l = 0; l < VS_MAX_LEVELS; ++l) ok = ok && std::fprintf(f, " %d", r.e.flow_variant[l]) > 0;
+        ok = ok && std::fprintf(f, " %d\n", r.e.pyr_tile_rows) > 0;
+    }
+    ok = (std::fclose(f) == 0) && ok;
+    return ok ? VS_OK : VS_E_INVAL;
+}
+
+vs_status vs_tune_load(const char* path)
+{
+    if (!path) return VS_E_INVAL;
+    FILE* f = std::fopen(path, "r");
+    if (!f) return VS_E_INVAL;
+    std::vector<TuneRec> recs;
+    char line[512];
+    bool ok = true;
+    while (ok && std::fgets(line, sizeof line, f)) {
+        if (line[0] == '\n' || line[0] == '#') continue;
+        TuneRec r;
+        std::memset(&r, 0, sizeof r);
+        char tag[16] = {}, arch[32] = {};
+        int v[VS_MAX_LEVELS] = {}, rows = 0, used = 0;
+        static_assert(VS_MAX_LEVELS == 6, "record format");
+        const int got = std::sscanf(line, "%15s %31s %d %d %d %d %d %d %d %d %d %d %d %d %n", tag, arch, &r.k.n_cams,
+                                    &r.k.canvas_w, &r.k.canvas_h, &r.k.lk_levels, &r.k.lk_radius, &v[0], &v[1], &v[2],
+                                    &v[3], &v[4], &v[5], &rows, &used);
+        ok = got == 14 && std::strcmp(tag, "vstune1") == 0 && line[used] == 0;
+        std::memcpy(r.k.arch, arch, sizeof arch);
+        for (int l = 0; l < VS_MAX_LEVELS; ++l) r.e.flow_variant[l] = v[l];
+        r.e.pyr_tile_rows = rows;
+        ok = ok && tune_rec_ok(r.k, r.e);
+        if (ok) recs.push_back(r);
+    }
+    std::fclose(f);
+    if (!ok) return VS_E_INVAL;
+    std::lock_guard<std::mutex> lock(g_tune_mu);
+    for (const TuneRec& r : recs) tune_put_locked(r.k, r.e);
+    return VS_OK;
+}
+
 
 // ---------------------------------------------------------------------------
 // Batches: several contexts (uneven rigs / resolutions) stitched by one graph
@@ -1267,10 +1443,50 @@ vs_status vs_batch_autotune(vs_batch* b, const uint8_t* const* const frames[], u
         choice[l] = best_v;
     }
     for (int l = levels; l < VS_MAX_LEVELS; ++l) choice[l] = 0;
+    // the fused pyramid's tile height, every context alike
+    bool pyr = levels >= 3;
+    for (int c = 0; c < b->n; ++c) pyr = pyr && b->ctx[c]->hp.use_flow && b->ctx[c]->prm.pyr_tile_rows == 0;
+    if (pyr && st == VS_OK) {
+        float best = 1e30f;
+        int best_rows = b->ctx[0]->hp.pyrf_ty;
+        for (const int rows : {8, 16}) {
+            for (int c = 0; c < b->n && st == VS_OK; ++c) {
+                vs_ctx* x = b->ctx[c];
+                set_pyr_rows(x->hp, rows);
+                if (hipMemcpy(x->dp, &x->hp, sizeof(DevPlan), hipMemcpyHostToDevice) != hipSuccess) st = VS_E_DEVICE;
+                x->gen += 1;
+            }
+            if (st == VS_OK) st = capture(b);
+            if (st == VS_OK) st = vs_batch_run(b, frames, panos, nullptr);   // warm
+            if (st != VS_OK) break;
+            (void)hipEventRecord(e0, nullptr);
+            for (int r = 0; r < reps && st == VS_OK; ++r) st = vs_batch_run(b, frames, panos, nullptr);
+            (void)hipEventRecord(e1, nullptr);
+            if (hipEventSynchronize(e1) != hipSuccess) st = VS_E_DEVICE;
+            float ms = 0.0f;
+            (void)hipEventElapsedTime(&ms, e0, e1);
+            if (ms / (float)reps < best) {
+                best = ms / (float)reps;
+                best_rows = rows;
+            }
+        }
+        for (int c = 0; c < b->n && st == VS_OK; ++c) {
+            vs_ctx* x = b->ctx[c];
+            set_pyr_rows(x->hp, best_rows);
+            if (hipMemcpy(x->dp, &x->hp, sizeof(DevPlan), hipMemcpyHostToDevice) != hipSuccess) st = VS_E_DEVICE;
+            x->gen += 1;
+        }
+    }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     if (st == VS_OK) st = capture(b);
     for (int c = 0; c < b->n && st == VS_OK; ++c) st = vs_state_set(b->ctx[c], &saved[c]);
+    // record every context's choice for contexts created later on this device
+    for (int c = 0; c < b->n && st == VS_OK; ++c) {
+        vs_tune_key k;
+        vs_tune_entry te;
+        if (vs_tune_key_of(b->ctx[c], &k) == VS_OK && vs_get_tuning(b->ctx[c], &te) == VS_OK) (void)vs_tune_put(&k, &te);
+    }
     return st;
 }
 

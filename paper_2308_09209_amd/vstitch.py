@@ -41,6 +41,8 @@ EXPORTS = ["vs_abi_version", "vs_status_str", "vs_default_params", "vs_compose_h
            "vs_set_flow_variant", "vs_get_flow_variant", "vs_load_weights", "vs_set_flow_mode",
            "vs_batch_create", "vs_batch_run",
            "vs_batch_destroy", "vs_batch_last_error", "vs_batch_autotune",
+           "vs_tune_put", "vs_tune_get", "vs_tune_clear", "vs_tune_save", "vs_tune_load", "vs_tune_key_of",
+           "vs_get_tuning",
            "vs_nn_conv3x3", "vs_nn_wgrad_scratch_bytes", "vs_nn_conv3x3_wgrad", "vs_nn_flip_weights",
            "vs_nn_lrelu_bwd", "vs_nn_pack_pair", "vs_nn_epe_loss", "vs_nn_adam", "vs_nn_to_bf16",
            "vs_nn_pool_flow", "vs_nn_create", "vs_nn_destroy", "vs_nn_forward", "vs_nn_loss", "vs_nn_backward",
@@ -114,6 +116,49 @@ def nn_images(sizes):
 NN_MAX_LAYERS = 8
 
 
+class TuneKey(C.Structure):
+    _fields_ = [("arch", C.c_char * 32), ("n_cams", C.c_int32), ("canvas_w", C.c_int32), ("canvas_h", C.c_int32),
+                ("lk_levels", C.c_int32), ("lk_radius", C.c_int32)]
+
+
+class TuneEntry(C.Structure):
+    _fields_ = [("flow_variant", C.c_int32 * MAX_LEVELS), ("pyr_tile_rows", C.c_int32)]
+
+
+def tune_entry(variants, pyr_tile_rows=0) -> TuneEntry:
+    e = TuneEntry()
+    for i, v in enumerate(variants):
+        e.flow_variant[i] = v
+    e.pyr_tile_rows = pyr_tile_rows
+    return e
+
+
+def tune_put(key: TuneKey, entry: TuneEntry):
+    check(lib().vs_tune_put(C.byref(key), C.byref(entry)), "vs_tune_put")
+
+
+def tune_get(key: TuneKey):
+    """the record for key, or None"""
+    e = TuneEntry()
+    st = lib().vs_tune_get(C.byref(key), C.byref(e))
+    if st == -6:
+        return None
+    check(st, "vs_tune_get")
+    return e
+
+
+def tune_clear():
+    check(lib().vs_tune_clear(), "vs_tune_clear")
+
+
+def tune_save(path):
+    check(lib().vs_tune_save(os.fsencode(path)), "vs_tune_save")
+
+
+def tune_load(path):
+    check(lib().vs_tune_load(os.fsencode(path)), "vs_tune_load")
+
+
 class NNSpec(C.Structure):
     _fields_ = [("n_layers", C.c_int32), ("cin", C.c_int32 * NN_MAX_LAYERS), ("cout", C.c_int32 * NN_MAX_LAYERS),
                 ("in_live", C.c_int32), ("alpha", C.c_float), ("max_pixels", C.c_int64)]
@@ -174,6 +219,13 @@ def lib():
         L.vs_batch_last_error.argtypes = [C.c_void_p]
         L.vs_batch_autotune.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int, C.c_void_p,
                                         C.c_void_p]
+        L.vs_tune_put.argtypes = [C.POINTER(TuneKey), C.POINTER(TuneEntry)]
+        L.vs_tune_get.argtypes = [C.POINTER(TuneKey), C.POINTER(TuneEntry)]
+        L.vs_tune_clear.argtypes = []
+        L.vs_tune_save.argtypes = [C.c_char_p]
+        L.vs_tune_load.argtypes = [C.c_char_p]
+        L.vs_tune_key_of.argtypes = [C.c_void_p, C.POINTER(TuneKey)]
+        L.vs_get_tuning.argtypes = [C.c_void_p, C.POINTER(TuneEntry)]
         vp, i32, i64, f32 = C.c_void_p, C.c_int, C.c_int64, C.c_float
         imgs = C.POINTER(NNImages)
         L.vs_nn_conv3x3.argtypes = [vp, i32, vp, vp, vp, i32, imgs, i32, f32, vp]
@@ -372,6 +424,17 @@ class Stitcher:
         if st != 0:
             self._err(st, "vs_get_timing")
         return ms, n.value
+
+    def tune_key(self) -> TuneKey:
+        k = TuneKey()
+        check(lib().vs_tune_key_of(self.h, C.byref(k)), "vs_tune_key_of")
+        return k
+
+    def tuning(self) -> TuneEntry:
+        """the context's current flow variants and fused-pyramid tile height"""
+        e = TuneEntry()
+        check(lib().vs_get_tuning(self.h, C.byref(e)), "vs_get_tuning")
+        return e
 
     def flow_variants(self):
         v = np.zeros(MAX_LEVELS, np.int32)

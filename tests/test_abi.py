@@ -196,3 +196,50 @@ def test_calibration_host_helpers_equal_the_oracle():
     np.testing.assert_array_equal(V.calib_refine(Ha, p), O.calib_refine(Ha, p))
     with pytest.raises(V.VSError):
         V.calib_pair(Ha, np.zeros((3, 3)))
+
+
+def test_tuning_records_round_trip_through_a_file(tmp_path):
+    """vs_tune_put / get / save / load / clear (host only): a record file
+    written and read back gives the same records; a later record of an equal
+    key replaces the earlier; malformed lines, unknown variant codes, 9x9
+    codes with another radius and bad tile heights are refused, loading
+    nothing."""
+    def key(arch=b"gfx950", cams=4, w=6144, h=1080, levels=4, radius=4):
+        k = V.TuneKey()
+        k.arch, k.n_cams, k.canvas_w, k.canvas_h, k.lk_levels, k.lk_radius = arch, cams, w, h, levels, radius
+        return k
+    V.tune_clear()
+    assert V.tune_get(key()) is None
+    V.tune_put(key(), V.tune_entry([12, 12, 25, 25], 16))
+    V.tune_put(key(cams=8, w=24576, h=2160), V.tune_entry([12, 12, 11, 27], 8))
+    V.tune_put(key(), V.tune_entry([12, 11, 25, 25], 8))          # replaces the first
+    path = tmp_path / "tune.txt"
+    V.tune_save(path)
+    lines = path.read_text().splitlines()
+    assert len(lines) == 2 and all(ln.startswith("vstune1 gfx950 ") for ln in lines)
+    V.tune_clear()
+    assert V.tune_get(key()) is None
+    V.tune_load(path)
+    e = V.tune_get(key())
+    assert list(e.flow_variant) == [12, 11, 25, 25, 0, 0] and e.pyr_tile_rows == 8
+    e = V.tune_get(key(cams=8, w=24576, h=2160))
+    assert list(e.flow_variant)[:4] == [12, 12, 11, 27] and e.pyr_tile_rows == 8
+    assert V.tune_get(key(arch=b"gfx942")) is None
+    for bad in (V.tune_entry([12, 12, 13, 25]), V.tune_entry([12, 12, 25, 25], 12),
+                V.tune_entry([12, 12, 25, 25, 9])):
+        with pytest.raises(V.VSError):
+            V.tune_put(key(), bad)
+    with pytest.raises(V.VSError):
+        V.tune_put(key(radius=3), V.tune_entry([12, 0, 0, 0]))
+    V.tune_put(key(radius=3), V.tune_entry([0, 0, 0, 0]))
+    for text in ("vstune1 gfx950 4 6144 1080 4 4 12 12 25 25 0 0 16 extra\n",
+                 "vstune2 gfx950 4 6144 1080 4 4 12 12 25 25 0 0 16\n",
+                 "vstune1 gfx950 4 6144 1080 4 4 12 12 25 64 0 0 16\n",
+                 "vstune1 gfx950 4 6144 1080 4\n"):
+        bad_path = tmp_path / "bad.txt"
+        bad_path.write_text("vstune1 gfx950 2 640 360 4 4 9 9 25 25 0 0 8\n" + text)
+        with pytest.raises(V.VSError):
+            V.tune_load(bad_path)
+        k2 = key(cams=2, w=640, h=360)
+        assert V.tune_get(k2) is None        # nothing of a refused file is loaded
+    V.tune_clear()

@@ -95,6 +95,46 @@ def test_batch_autotune_keeps_results():
         for c in range(len(sts)):
             np.testing.assert_array_equal(panos[c].cpu().numpy(), ref[c][t])
     b.close()
+    V.tune_clear()   # the records of this test's rigs do not reach later tests
+
+
+def test_autotune_records_apply_to_new_contexts(tmp_path):
+    """vs_batch_autotune records each context's choice (flow variants and the
+    fused pyramid's tile height); a context created later for the same device
+    and plan shape starts from it, also after the records go through a file;
+    without records it starts from the defaults.  Panoramas stay those of the
+    untuned contexts."""
+    scs = scenes()[:1]
+    ref = reference(scs, 2)
+    V.tune_clear()
+    st0 = V.Stitcher(scs[0].rig())
+    default = (st0.flow_variants(), st0.tuning().pyr_tile_rows)
+    b = V.Batch([st0])
+    panos = [st0.new_pano()]
+    choice, _ = b.autotune([dev(scs[0].frames(0))], panos, reps=2)
+    key = st0.tune_key()
+    rec = V.tune_get(key)
+    tuned = (list(rec.flow_variant)[:len(choice)], rec.pyr_tile_rows)
+    say(f"[tuning records] key {key.arch.decode()} {key.canvas_w}x{key.canvas_h}: default {default}, tuned {tuned}")
+    assert tuned[0] == choice and tuned[1] in (8, 16)
+    assert (st0.flow_variants(), st0.tuning().pyr_tile_rows) == tuned
+    b.close()
+    st0.close()
+    path = tmp_path / "tune.txt"
+    V.tune_save(path)
+    V.tune_clear()
+    st1 = V.Stitcher(scs[0].rig())
+    assert (st1.flow_variants(), st1.tuning().pyr_tile_rows) == default
+    st1.close()
+    V.tune_load(path)
+    st2 = V.Stitcher(scs[0].rig())
+    assert (st2.flow_variants(), st2.tuning().pyr_tile_rows) == tuned
+    pano = st2.new_pano()
+    for t in range(2):
+        st2.stitch(dev(scs[0].frames(t)), pano=pano)
+        np.testing.assert_array_equal(pano.cpu().numpy(), ref[0][t])
+    st2.close()
+    V.tune_clear()
 
 
 def test_batch_with_mixed_pyramid_tile_heights():

@@ -93,6 +93,7 @@ def test_six_stream_batch_full_size():
     b.close()
     for st in sts:
         st.close()
+    V.tune_clear()   # the autotuner's records of these rigs do not reach later tests
 
 
 def test_parity_8x3840x2160_surrogate_fallback_full_size():
