@@ -239,6 +239,9 @@ def main():
                          "counter reference for rocprofv3 byte counters)")
     ap.add_argument("--no-variational", action="store_true", help="skip the variational-flow leg")
     ap.add_argument("--var-steps", type=int, default=100, help="frames timed in the variational-flow leg")
+    ap.add_argument("--streaming-bytes", action="store_true",
+                    help="only print the algorithmic bytes per dispatch of the strip, blend and balance kernels "
+                         "for the 4x1080p ring, the 8x4K ring and the 6-stream batch, from their plans")
     ap.add_argument("--conv-rate", action="store_true",
                     help="only time the matrix-core 3x3 convolution on level-0 strip sizes "
                          "(8 images of 1080 x 256) for the layer shapes the library builds")
@@ -255,6 +258,8 @@ def main():
 
     if args.conv_rate:
         return conv_rate(V)
+    if args.streaming_bytes:
+        return streaming_bytes(V)
     big = args.workload == "8x3840x2160_ring"
     if args.seq is None:
         args.seq = 4 if big else 60
@@ -398,6 +403,31 @@ def surrogate_leg(args, V, rig, frames, st_plain, K, H, W, mpix_plain, p99_plain
                           unit="TFLOP/s", note="network flops (first layer on its 2 non-zero input "
                           "channels) over the whole flow step (5 convolutions, upsampling, "
                           "forward-backward check, fallback)"))
+
+
+def streaming_bytes(V):
+    """Algorithmic HBM bytes per dispatch of the streaming kernels, from the
+    plans: k_strips 15 B per strip pixel (both cameras' source pixel read once,
+    both strips and the overlap mask written), k_blend the camera frames read
+    once, both flows of each overlap pixel (2 x 8 B) and the panorama written
+    once, k_balance_apply the panorama read and written once."""
+    from paper_2308_09209_amd.scenes import batch_scenes, scene_for
+    out = {}
+    for name, scs in (("4x1920x1080_ring", [scene_for("4x1920x1080_ring")]),
+                      ("8x3840x2160_ring", [scene_for("8x3840x2160_ring")]), ("6stream_batch", batch_scenes())):
+        tot = dict(canvas=0, strip=0, overlap=0, frames=0)
+        for sc in scs:
+            st = V.Stitcher(sc.rig())
+            I = st.info
+            tot["canvas"] += I.canvas_w * I.canvas_h
+            tot["strip"] += sum(I.strip_w[p] * I.strip_h[p] for p in range(I.n_pairs))
+            tot["overlap"] += sum(int(I.flow_px[p][0]) for p in range(I.n_pairs))
+            tot["frames"] += sc.n_cams * sc.W * sc.H * 3
+            st.close()
+        out[name] = dict(pixels=tot, k_strips=15 * tot["strip"],
+                         k_blend=tot["frames"] + 16 * tot["overlap"] + 3 * tot["canvas"],
+                         k_balance_apply=6 * tot["canvas"])
+    print(json.dumps(out), flush=True)
 
 
 def copy_calibration(mib, dev):
