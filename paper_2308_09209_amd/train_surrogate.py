@@ -76,10 +76,12 @@ def pool_label(flow, w, h, f):
     return out
 
 
-def build_dataset(n_pairs, H=1080, W=256, max_disp=8.0, seed=0, chunk=64, log=print):
-    """(level-2 template, level-2 moving, level-2 label, level-0 label) tensors"""
+def build_dataset(n_pairs, H=1080, W=256, max_disp=8.0, seed=0, chunk=64, log=print, label_flow=1):
+    """(level-2 template, level-2 moving, level-2 label, level-0 label) tensors;
+    label_flow 1: labels from the pyramidal Lucas-Kanade estimator, 2: from
+    the variational estimator (the library's vs_flow_* context either way)"""
     gen = torch.Generator().manual_seed(seed)
-    pf = V.PlainFlow(W, H)
+    pf = V.PlainFlow(W, H, flow=label_flow)
     t2l, m2l, lab2, lab0 = [], [], [], []
     t0 = time.time()
     for start in range(0, n_pairs, chunk):
@@ -162,10 +164,12 @@ def main():
     ap.add_argument("--batch", type=int, default=16)
     ap.add_argument("--lr", type=float, default=2e-3)
     ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--labels", choices=("lk", "variational"), default="lk",
+                    help="label source: the pyramidal Lucas-Kanade or the variational estimator")
     ap.add_argument("--out", required=True)
     a = ap.parse_args()
     log = lambda s: print(s, file=sys.stderr, flush=True)
-    data = build_dataset(a.pairs, seed=a.seed, log=log)
+    data = build_dataset(a.pairs, seed=a.seed, log=log, label_flow=1 if a.labels == "lk" else 2)
     net = S.Net(seed=a.seed)
     n_tr, n = split(data)
     log(f"# held-out EPE(level 2) before training {evaluate(net, data, n_tr, n):.4f} px")

@@ -247,6 +247,24 @@ def test_training_reduces_the_loss():
     assert net2.blob() == blob
 
 
+def test_training_on_variational_labels_reduces_the_loss():
+    """The variational estimator as the label source (flow = 2 in the
+    library's plain-flow context): its labels differ from the Lucas-Kanade
+    ones, and a network trained on them learns them."""
+    from paper_2308_09209_amd import train_surrogate as TS
+    lk = TS.build_dataset(16, H=256, W=128, max_disp=6.0, seed=5, chunk=16, log=say)
+    data = TS.build_dataset(96, H=256, W=128, max_disp=6.0, seed=5, chunk=16, log=say, label_flow=2)
+    d = (data[2][:16] - lk[2]).norm(dim=-1).mean().item()
+    say(f"[variational labels] mean difference to the Lucas-Kanade labels {d:.4f} level-2 px")
+    assert 0.0 < d < 1.0
+    net = S.Net(seed=0)
+    n_tr, n = TS.split(data, 16)
+    before = TS.evaluate(net, data, n_tr, n)
+    _, after = TS.train(net, data, steps=200, batch=8, lr=2e-3, log=say, val=16)
+    say(f"[variational labels] held-out EPE {before:.4f} -> {after:.4f} level-2 px")
+    assert after < 0.8 * before
+
+
 NET_LAYERS = ((16, 32), (32, 32), (32, 16))
 NET_SIZES = [(23, 41), (16, 16), (5, 70)]
 
