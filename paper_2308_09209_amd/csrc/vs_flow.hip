@@ -271,21 +271,77 @@ __device__ __forceinline__ void lk_w9_body(const DevPlan* __restrict__ Pl, const
 
     const int f = find_field(Pl->lk_off[l], 2 * Pl->n_pairs, bid);
     const int p = f >> 1, dir = f & 1;
-    if (kept_by_surrogate(Pl, p)) return;   // the pair keeps the surrogate's flows
-    const int w = Pl->lw[p][l], h = Pl->lh[p][l];
     int x0, y0;
-    tile_origin(Pl, l, f, bid, TX, TY, x0, y0);
+    tile_origin(Pl, l, f, bid, TX, TY, x0, y0);   // read before the check below waits
+    if (kept_by_surrogate(Pl, p)) return;         // the pair keeps the surrogate's flows
+    const int w = Pl->lw[p][l], h = Pl->lh[p][l];
     const float* __restrict__ Tm = Pl->pyr[p][dir == 0 ? 0 : 1][l];
     const float* __restrict__ Mv = Pl->pyr[p][dir == 0 ? 1 : 0][l];
     const int tid = threadIdx.x;
+    const int lane = tid & 63, wv = tid >> 6;
+    const int x = x0 + lane;
+    const int yb = y0 + wv * P;
+    const bool has_coarse = l + 1 < Pl->levels;
 
-    for (int i = tid; i < TSH * TSW; i += 256) {
-        const int yy = clampi(y0 - R - 1 + i / TSW, 0, h - 1), xx = clampi(x0 - R - 1 + i % TSW, 0, w - 1);
-        sT[i] = Tm[(size_t)yy * w + xx];
+    // the pixels' flow-domain flags and the four coarse-level flows each one
+    // interpolates, loaded before the staging so that their latency overlaps it
+    // (the coarse positions are clamped into the coarse level, so they are read
+    // for every pixel and used for the pixels in the domain)
+    const uint8_t* __restrict__ need = Pl->need[p][l];
+    uint32_t nd[P];
+    float2 c00[P], c10[P], c01[P], c11[P];
+    float cfx[P], cfy[P];
+#pragma unroll
+    for (int q = 0; q < P; ++q) {
+        const int y = yb + q;
+        nd[q] = need[(size_t)min(y, h - 1) * w + min(x, w - 1)];   // used for x < w, y < h
+        if (has_coarse) {
+            const int wc = Pl->lw[p][l + 1], hc = Pl->lh[p][l + 1];
+            const float2* __restrict__ uc = Pl->flow[p][dir][l + 1];
+            const float cx = clampf(__builtin_fmaf((float)x, 0.5f, -0.25f), 0.0f, (float)(wc - 1));
+            const float cy = clampf(__builtin_fmaf((float)y, 0.5f, -0.25f), 0.0f, (float)(hc - 1));
+            const float flx = floorf(cx), fly = floorf(cy);
+            const int xa = (int)flx, ya = (int)fly;
+            cfx[q] = cx - flx;
+            cfy[q] = cy - fly;
+            const int xb = xa + 1 < wc ? xa + 1 : wc - 1;
+            const int ybb = ya + 1 < hc ? ya + 1 : hc - 1;
+            c00[q] = uc[(size_t)ya * wc + xa];
+            c10[q] = uc[(size_t)ya * wc + xb];
+            c01[q] = uc[(size_t)ybb * wc + xa];
+            c11[q] = uc[(size_t)ybb * wc + xb];
+        }
     }
-    for (int i = tid; i < MH * MW; i += 256) {
-        const int yy = clampi(y0 - HM + i / MW, 0, h - 1), xx = clampi(x0 - HM + i % MW, 0, w - 1);
-        sM[(i / MW) * MWP + i % MW] = Mv[(size_t)yy * w + xx];
+
+    // staging: every load of both tiles issued before the first LDS store (one
+    // memory round trip, not one per element a thread stages)
+    constexpr int NST = (TSH * TSW + 255) / 256, NSM = (MH * MW + 255) / 256;
+    float vt[NST], vm[NSM];
+#pragma unroll
+    for (int k = 0; k < NST; ++k) {
+        const int i = tid + 256 * k;
+        if (i < TSH * TSW) {
+            const int yy = clampi(y0 - R - 1 + i / TSW, 0, h - 1), xx = clampi(x0 - R - 1 + i % TSW, 0, w - 1);
+            vt[k] = Tm[(size_t)yy * w + xx];
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < NSM; ++k) {
+        const int i = tid + 256 * k;
+        if (i < MH * MW) {
+            const int yy = clampi(y0 - HM + i / MW, 0, h - 1), xx = clampi(x0 - HM + i % MW, 0, w - 1);
+            vm[k] = Mv[(size_t)yy * w + xx];
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < NST; ++k) {
+        const int i = tid + 256 * k;
+        if (i < TSH * TSW) sT[i] = vt[k];
+    }
+#pragma unroll
+    for (int k = 0; k < NSM; ++k) {
+        const int i = tid + 256 * k;
+        if (i < MH * MW) sM[(i / MW) * MWP + i % MW] = vm[k];
     }
     __syncthreads();
     for (int i = tid; i < TIH * TIW; i += 256) {
@@ -299,34 +355,19 @@ __device__ __forceinline__ void lk_w9_body(const DevPlan* __restrict__ Pl, const
     }
     __syncthreads();
 
-    const int lane = tid & 63, wv = tid >> 6;
-    const int x = x0 + lane;
-    const int yb = y0 + wv * P;
-    const bool has_coarse = l + 1 < Pl->levels;
     const int ncx = min(x + R, w - 1) - max(x - R, 0) + 1;
-    const uint8_t* __restrict__ need = Pl->need[p][l];
     float ux[P], uy[P], g00[P], g01[P], g11[P], cu[P], cv[P], det[P];
     bool act[P];
     int dit[P];   // step at which the pixel was deferred (-1: not deferred)
 #pragma unroll
     for (int q = 0; q < P; ++q) {
-        const int y = yb + q;
-        act[q] = x < w && y < h && need[(size_t)y * w + x] != 0;
+        act[q] = x < w && yb + q < h && nd[q] != 0u;
         dit[q] = -1;
         ux[q] = 0.0f;
         uy[q] = 0.0f;
         if (has_coarse && act[q]) {
-            const int wc = Pl->lw[p][l + 1], hc = Pl->lh[p][l + 1];
-            const float2* __restrict__ uc = Pl->flow[p][dir][l + 1];
-            const float cx = clampf(__builtin_fmaf((float)x, 0.5f, -0.25f), 0.0f, (float)(wc - 1));
-            const float cy = clampf(__builtin_fmaf((float)y, 0.5f, -0.25f), 0.0f, (float)(hc - 1));
-            const float flx = floorf(cx), fly = floorf(cy);
-            const int xa = (int)flx, ya = (int)fly;
-            const float fx = cx - flx, fy = cy - fly;
-            const int xb = xa + 1 < wc ? xa + 1 : wc - 1;
-            const int ybb = ya + 1 < hc ? ya + 1 : hc - 1;
-            const float2 p00 = uc[(size_t)ya * wc + xa], p10 = uc[(size_t)ya * wc + xb];
-            const float2 p01 = uc[(size_t)ybb * wc + xa], p11 = uc[(size_t)ybb * wc + xb];
+            const float fx = cfx[q], fy = cfy[q];
+            const float2 p00 = c00[q], p10 = c10[q], p01 = c01[q], p11 = c11[q];
             float a = __builtin_fmaf(fx, p10.x - p00.x, p00.x);
             float b = __builtin_fmaf(fx, p11.x - p01.x, p01.x);
             ux[q] = 2.0f * __builtin_fmaf(fy, b - a, a);
