@@ -52,50 +52,72 @@ __device__ __forceinline__ __attribute__((address_space(1))) T* gmem(T* p)
     return (__attribute__((address_space(1))) T*)p;
 }
 
-// the 6 bytes at A (a pixel pair of an RGB row) as two words: bytes 0-3 and
-// 4-5; three aligned 32-bit loads, each holding at least one of the 6 bytes
-// (the third is the second again unless the pair starts at byte 3 of a word)
-__device__ __forceinline__ void load_pair6(const uint8_t* A, uint32_t& lo, uint32_t& hi)
-{
-    const uintptr_t a = (uintptr_t)A;
-    const auto* w = gmem((const uint32_t*)(a & ~(uintptr_t)3));
-    const uint32_t w0 = w[0], w1 = w[1], w2 = *gmem((const uint32_t*)((a + 5) & ~(uintptr_t)3));
-    const uint32_t sh = (uint32_t)(a & 3);
-    lo = __builtin_amdgcn_alignbyte(w1, w0, sh);
-    hi = __builtin_amdgcn_alignbyte(w2, w1, sh);
-}
-
 // bilinear resample of an HWC RGB byte image (W >= 2), position clamped into
 // the image; a = p00 + fx (p10 - p00), b likewise on the next row, out =
 // a + fy (b - a), each an FMA.  At the right border (x0 = W - 1, fx = 0) the
 // pair (W - 2, W - 1) with fx = 1 gives the same values exactly (byte-valued
-// samples), so every row pair is two in-row pixels.
-__device__ __forceinline__ void bilin3(const uint8_t* __restrict__ F, int pitch, int W, int H,
-                                       float u, float v, float out[3])
+// samples), so every row pair is two in-row pixels.  bil_load issues the
+// loads of the two rows' pixel pairs, bil_rgb combines them: callers with
+// several samples issue all their loads before combining any.
+struct BilTaps {
+    // rows y0 and y1: the three aligned words holding the 6 bytes of the pixel
+    // pair (x0, x0 + 1), the third being the second again unless the pair
+    // starts at byte 3 of a word; combined they give bytes 0-3 and 4-5
+    uint32_t a0, a1, a2, b0, b1, b2;
+    uint32_t sa, sb;   // byte offsets of the pairs in their first words
+    float fx, fy;
+};
+
+__device__ __forceinline__ void bil_load(const uint8_t* __restrict__ F, int pitch, int W, int H, float u, float v,
+                                         BilTaps& t)
 {
     float uc = clampf(u, 0.0f, (float)(W - 1));
     float vc = clampf(v, 0.0f, (float)(H - 1));
     float flx = floorf(uc), fly = floorf(vc);
     int x0 = (int)flx, y0 = (int)fly;
-    float fx = uc - flx, fy = vc - fly;
+    t.fx = uc - flx;
+    t.fy = vc - fly;
     if (x0 == W - 1) {
         x0 = W - 2;
-        fx = 1.0f;
+        t.fx = 1.0f;
     }
     int y1 = y0 + 1 < H ? y0 + 1 : H - 1;
-    uint32_t l0, h0, l1, h1;
-    load_pair6(F + (size_t)y0 * pitch + x0 * 3, l0, h0);
-    load_pair6(F + (size_t)y1 * pitch + x0 * 3, l1, h1);
+    const uintptr_t A = (uintptr_t)(F + (size_t)y0 * pitch + x0 * 3);
+    const uintptr_t Bq = (uintptr_t)(F + (size_t)y1 * pitch + x0 * 3);
+    const auto* wa = gmem((const uint32_t*)(A & ~(uintptr_t)3));
+    const auto* wb = gmem((const uint32_t*)(Bq & ~(uintptr_t)3));
+    t.a0 = wa[0];
+    t.a1 = wa[1];
+    t.a2 = *gmem((const uint32_t*)((A + 5) & ~(uintptr_t)3));
+    t.b0 = wb[0];
+    t.b1 = wb[1];
+    t.b2 = *gmem((const uint32_t*)((Bq + 5) & ~(uintptr_t)3));
+    t.sa = (uint32_t)(A & 3);
+    t.sb = (uint32_t)(Bq & 3);
+}
+
+__device__ __forceinline__ void bil_rgb(const BilTaps& t, float out[3])
+{
+    const uint32_t l0 = __builtin_amdgcn_alignbyte(t.a1, t.a0, t.sa), h0 = __builtin_amdgcn_alignbyte(t.a2, t.a1, t.sa);
+    const uint32_t l1 = __builtin_amdgcn_alignbyte(t.b1, t.b0, t.sb), h1 = __builtin_amdgcn_alignbyte(t.b2, t.b1, t.sb);
     const float p00[3] = {(float)(l0 & 255u), (float)((l0 >> 8) & 255u), (float)((l0 >> 16) & 255u)};
     const float p10[3] = {(float)(l0 >> 24), (float)(h0 & 255u), (float)((h0 >> 8) & 255u)};
     const float p01[3] = {(float)(l1 & 255u), (float)((l1 >> 8) & 255u), (float)((l1 >> 16) & 255u)};
     const float p11[3] = {(float)(l1 >> 24), (float)(h1 & 255u), (float)((h1 >> 8) & 255u)};
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
-        float a = __builtin_fmaf(fx, p10[c] - p00[c], p00[c]);
-        float b = __builtin_fmaf(fx, p11[c] - p01[c], p01[c]);
-        out[c] = __builtin_fmaf(fy, b - a, a);
+        float a = __builtin_fmaf(t.fx, p10[c] - p00[c], p00[c]);
+        float b = __builtin_fmaf(t.fx, p11[c] - p01[c], p01[c]);
+        out[c] = __builtin_fmaf(t.fy, b - a, a);
     }
+}
+
+__device__ __forceinline__ void bilin3(const uint8_t* __restrict__ F, int pitch, int W, int H,
+                                       float u, float v, float out[3])
+{
+    BilTaps t;
+    bil_load(F, pitch, W, H, u, v, t);
+    bil_rgb(t, out);
 }
 
 // t_c = s . M[:, c] (row-vector convention), clamped to [0, 255]

@@ -630,22 +630,38 @@ __device__ __forceinline__ void lk_tail_pixel(const DevPlan* __restrict__ Pl, in
 }
 
 // The tail kernel proper: 16 lanes per queued pixel, lane r of a group taking
-// window row r.  Every row's taps of a step are loaded at once (one memory
-// round trip per step instead of one per row); the sums then run through the
-// rows in order, the lane of each row adding its taps to the partial sums it
+// window row r.  The moving image around the pixel's displacement is staged
+// in LDS (16 x 16 values, clamped indices: the window and a margin of
+// LK_TAIL_M px), so a step reads memory only when the displacement has moved
+// more than the margin since the staging; the sums then run through the rows
+// in order, the lane of each row adding its taps to the partial sums it
 // received from the lane of the row above and handing them on, so each sum is
 // the same row-major sequence of fused multiply-adds as in lk_tail_pixel.
 constexpr int LK_TAIL_G = 16;
+constexpr int LK_TAIL_M = 3;
+constexpr int LK_TAIL_SW = 2 * LK_R_MAX + 2 + 2 * LK_TAIL_M;   // staged window side (16)
+
+// the value of the lane one below in its row of 16 lanes (0 for a row's first
+// lane), a DPP row shift: no LDS round trip
+__device__ __forceinline__ float row_shr1(float v)
+{
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x111, 0xf, 0xf, true));
+}
 
 __global__ __launch_bounds__(256) void k_lk_tail(const Batch B, int l)
 {
     constexpr int R = LK_R_MAX, NW = 2 * R + 1, G = LK_TAIL_G;
-    static_assert(NW + 1 <= G && 256 % G == 0, "one window row per lane, plus the lane that receives the sums");
+    static_assert(NW + 1 <= G && G == 16, "one window row per lane, plus the lane that receives the sums, in one "
+                                          "DPP row of 16 lanes");
     int cx;
     const int b = batch_block(B, blockIdx.x, cx);
     const int nb = B.off[cx + 1] - B.off[cx];        // this context's blocks
     const DevPlan* __restrict__ Pl = B.plan[cx];
     const uint32_t n = min(Pl->acc->lk_qn[l], (uint32_t)Pl->lk_qcap[l]);
+    constexpr int MG = LK_TAIL_M, SW = LK_TAIL_SW;
+    static_assert(SW == G, "lane r stages row r of the moving window");
+    __shared__ float s_mv[256 / G][SW * SW];
+    float* const mv = s_mv[threadIdx.x / G];          // this group's staged window (its lanes share a wavefront)
     const int sub = (int)(threadIdx.x % G);
     const int jr = sub < NW ? sub : NW - 1;           // lanes past the window repeat its last row, unused
     const int iters = Pl->lk_iters;
@@ -659,6 +675,15 @@ __global__ __launch_bounds__(256) void k_lk_tail(const Batch B, int l)
         const int w = Pl->lw[p][l], h = Pl->lh[p][l];
         const float* __restrict__ Tm = Pl->pyr[p][dir == 0 ? 0 : 1][l];
         const float* __restrict__ Mv = Pl->pyr[p][dir == 0 ? 1 : 0][l];
+        // the moving window, anchored at the displacement's integer part: lane
+        // sub loads row sub (loads issued with the template rows' below)
+        int oxs = (int)floorf(ux), oys = (int)floorf(uy);
+        float stg[SW];
+        {
+            const float* mrow = Mv + (size_t)clampi(y - R + oys - MG + sub, 0, h - 1) * w;
+#pragma unroll
+            for (int k = 0; k < SW; ++k) stg[k] = mrow[clampi(x - R + oxs - MG + k, 0, w - 1)];
+        }
         // this lane's window row: template values and gradients (0 outside the level)
         const int yy = y - R + jr;
         const bool rin = yy >= 0 && yy < h;
@@ -684,6 +709,10 @@ __global__ __launch_bounds__(256) void k_lk_tail(const Batch B, int l)
                 tc[c] = a[c + 1];
             }
         }
+        __builtin_amdgcn_wave_barrier();   // the previous entry's reads of the window come first
+#pragma unroll
+        for (int k = 0; k < SW; ++k) mv[sub * SW + k] = stg[k];
+        __builtin_amdgcn_wave_barrier();
         // normal matrix and template term: row r's lane adds its taps at hand-on r
         float g00 = 0.0f, g01 = 0.0f, g11 = 0.0f, cu = 0.0f, cv = 0.0f;
 #pragma unroll
@@ -698,17 +727,13 @@ __global__ __launch_bounds__(256) void k_lk_tail(const Batch B, int l)
                     cv = __builtin_fmaf(gy[c], tc[c], cv);
                 }
             }
-            g00 = __shfl_up(g00, 1, G);
-            g01 = __shfl_up(g01, 1, G);
-            g11 = __shfl_up(g11, 1, G);
-            cu = __shfl_up(cu, 1, G);
-            cv = __shfl_up(cv, 1, G);
+            g00 = row_shr1(g00);
+            g01 = row_shr1(g01);
+            g11 = row_shr1(g11);
+            cu = row_shr1(cu);
+            cv = row_shr1(cv);
         }
-        g00 = __shfl(g00, NW, G);
-        g01 = __shfl(g01, NW, G);
-        g11 = __shfl(g11, NW, G);
-        cu = __shfl(cu, NW, G);
-        cv = __shfl(cv, NW, G);
+        // lane NW now holds the sums; it solves each step and hands the flow on
         const int ncx = min(x + R, w - 1) - max(x - R, 0) + 1;
         const int ncy = min(y + R, h - 1) - max(y - R, 0) + 1;
         const float reg = Pl->lk_lambda * (float)(ncy * ncx);
@@ -719,14 +744,31 @@ __global__ __launch_bounds__(256) void k_lk_tail(const Batch B, int l)
             const float flx = floorf(ux), fly = floorf(uy);
             const int ox = (int)flx, oy = (int)fly;
             const float fx = ux - flx, fy = uy - fly;
-            const float* m0 = Mv + (size_t)clampi(yy + oy, 0, h - 1) * w;
-            const float* m1 = Mv + (size_t)clampi(yy + oy + 1, 0, h - 1) * w;
+            // the displacement's offset in the staged window (unsigned: any ox, oy)
+            uint32_t ddx = (uint32_t)ox - (uint32_t)oxs + (uint32_t)MG;
+            uint32_t ddy = (uint32_t)oy - (uint32_t)oys + (uint32_t)MG;
+            if (ddx > 2u * MG || ddy > 2u * MG) {
+                // the displacement left the staged window (the whole group: its
+                // lanes hold the same flow): stage it again around the new one
+                oxs = ox;
+                oys = oy;
+                ddx = MG;
+                ddy = MG;
+                const float* mrow = Mv + (size_t)clampi(y - R + oys - MG + sub, 0, h - 1) * w;
+#pragma unroll
+                for (int k = 0; k < SW; ++k) stg[k] = mrow[clampi(x - R + oxs - MG + k, 0, w - 1)];
+                __builtin_amdgcn_wave_barrier();
+#pragma unroll
+                for (int k = 0; k < SW; ++k) mv[sub * SW + k] = stg[k];
+                __builtin_amdgcn_wave_barrier();
+            }
+            // rows yy + oy and yy + oy + 1, columns x - R + ox + k, clamped as staged
+            const float* m0 = mv + (jr + (int)ddy) * SW + (int)ddx;
             float ra[NW + 1], rb[NW + 1];
 #pragma unroll
             for (int k = 0; k < NW + 1; ++k) {
-                const int xm = clampi(x - R + ox + k, 0, w - 1);
-                ra[k] = m0[xm];
-                rb[k] = m1[xm];
+                ra[k] = m0[k];
+                rb[k] = m0[SW + k];
             }
             float ta[NW], tb[NW];
 #pragma unroll
@@ -746,23 +788,19 @@ __global__ __launch_bounds__(256) void k_lk_tail(const Batch B, int l)
                         sbv = __builtin_fmaf(gy[c], tb[c], sbv);
                     }
                 }
-                sau = __shfl_up(sau, 1, G);
-                sav = __shfl_up(sav, 1, G);
-                sbu = __shfl_up(sbu, 1, G);
-                sbv = __shfl_up(sbv, 1, G);
+                sau = row_shr1(sau);
+                sav = row_shr1(sav);
+                sbu = row_shr1(sbu);
+                sbv = row_shr1(sbv);
             }
-            sau = __shfl(sau, NW, G);
-            sav = __shfl(sav, NW, G);
-            sbu = __shfl(sbu, NW, G);
-            sbv = __shfl(sbv, NW, G);
             const float bu = __builtin_fmaf(fy, sbu - sau, sau) - cu;
             const float bv = __builtin_fmaf(fy, sbv - sav, sav) - cv;
             const float du = (g01 * bv - g11 * bu) / det;
             const float dv = (g01 * bu - g00 * bv) / det;
-            ux = ux + du;
-            uy = uy + dv;
+            ux = __shfl(ux + du, NW, G);
+            uy = __shfl(uy + dv, NW, G);
         }
-        if (sub == 0) Pl->flow[p][dir][l][(size_t)y * w + x] = make_float2(ux, uy);
+        if (sub == NW) Pl->flow[p][dir][l][(size_t)y * w + x] = make_float2(ux, uy);
     }
 }
 

@@ -753,6 +753,13 @@ __global__ __launch_bounds__(256) void k_pyr_fused(const Batch B, int after)
 // s_hist: 8 copies of the histogram (lane & 7), LDS of the calling block:
 // neighbouring pixels often share a value, and same-address LDS atomics from
 // one instruction serialise (+ 1: a bin's copies in different banks)
+//
+// A thread's 4 pixels of a row: their 4 codes read at once, then per group of
+// BG pixels three phases, so that the memory reads of a group are in flight
+// together: (1) the covering candidates and their positions; the flows of the
+// two-camera pixels; (2) the bilinear taps of every sample (one camera: at its
+// position; two cameras: at the positions their flows move them to); (3)
+// colour correction, fusion, histogram.
 __device__ __forceinline__ void blend_body(const DevPlan* __restrict__ P, const int bid,
                                            uint32_t (*s_hist)[3 * 256 + 1])
 {
@@ -760,6 +767,11 @@ __device__ __forceinline__ void blend_body(const DevPlan* __restrict__ P, const 
     __shared__ float s_hinv[MAXC][9], s_M[MAXC][9];
     __shared__ int s_cw[MAXC], s_ch[MAXC], s_cp[MAXC];
     __shared__ const uint8_t* s_fr[MAXC];
+    // per-pair constants: pair of two cameras, camera j, flow-domain origin and
+    // width, the two level-0 flows
+    __shared__ int8_t s_pair[MAXC][MAXC];
+    __shared__ int s_pj[MAXP], s_fx0[MAXP], s_fy0[MAXP], s_fw[MAXP];
+    __shared__ const float2* s_fl[MAXP][2];
     const int tid = threadIdx.x;
     for (int i = tid; i < 8 * (3 * 256 + 1); i += BL_THREADS) (&s_hist[0][0])[i] = 0;
     for (int i = tid; i < P->n_cams * 9; i += BL_THREADS) {
@@ -772,10 +784,21 @@ __device__ __forceinline__ void blend_body(const DevPlan* __restrict__ P, const 
         s_cp[tid] = P->cam_pitch[tid];
         s_fr[tid] = P->frame[tid];
     }
+    if (tid < MAXC * MAXC) (&s_pair[0][0])[tid] = (int8_t)(&P->pair_of[0][0])[tid];
+    if (tid < P->n_pairs) {
+        s_pj[tid] = P->pj[tid];
+        s_fx0[tid] = P->sx0[tid];
+        s_fy0[tid] = P->sy0[tid];
+        s_fw[tid] = P->sw[tid];
+        s_fl[tid][0] = P->flow[tid][0][0];
+        s_fl[tid][1] = P->flow[tid][1][0];
+    }
     __syncthreads();
     uint32_t* const my_hist = s_hist[tid & 7];
     const int bx = bid % P->blend_tx, by = bid / P->blend_tx;
     const int W = P->canvas_w, H = P->canvas_h, Wp = P->Wp;
+    const bool lit = (P->readings & VS_READ_LITERAL_EQ17) != 0;
+    const bool ovl_only = (P->readings & VS_READ_OVERLAP_ONLY) != 0;
     // wavefront w takes the 64 columns [64 w, 64 w + 64) of the tile, 16 lanes
     // of 4 pixels per row, 4 rows at a time: a wavefront's pixels lie in one
     // narrow band, so few of them straddle the edge of an overlap (where both
@@ -783,71 +806,127 @@ __device__ __forceinline__ void blend_body(const DevPlan* __restrict__ P, const 
     static_assert(BL_TX == 64 * (BL_THREADS / 64) && BL_TY % 4 == 0, "blend tile = 4 x 64-column bands");
     const int xq = bx * BL_TX + (tid >> 6) * 64 + (tid & 15) * 4;
     const bool vec = (W & 3) == 0;
+    // pixels whose phases run together: 1 (with the 4 codes read at once and
+    // the pair constants in LDS); 2 and 4 need 127 and 162 VGPRs and were
+    // slower (4 x 1080p blend 71 -> 78 / 92 us)
+    constexpr int BG = 1;
     for (int r = (tid & 63) >> 4; r < BL_TY; r += 4) {
         const int y = by * BL_TY + r;
         if (y >= H || xq >= W) continue;
-        uint32_t ob[12];
+        // (1) candidates: bits 0-5 and 6-11 (3 camera + shift + 1), bits 12+ their count
+        uint32_t code[4];
+        if (vec && xq + 3 < W) {
+            typedef uint32_t u2v __attribute__((ext_vector_type(2)));
+            const u2v c4 = *gmem((const u2v*)(P->pix_code + (size_t)y * W + xq));
+            code[0] = c4.x & 0xffffu;
+            code[1] = c4.x >> 16;
+            code[2] = c4.y & 0xffffu;
+            code[3] = c4.y >> 16;
+        } else {
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            const int x = xq + q;
-            uint32_t o0 = 0, o1 = 0, o2 = 0;
-            const uint32_t code = x < W ? gmem(P->pix_code)[(size_t)y * W + x] : 0u;
-            const int nh = (int)(code >> 12);
-            if (nh > 0) {
-                // the covering (camera, shift) candidates found at plan time, in
-                // the coverage scan's order; their positions are evaluated again
+            for (int q = 0; q < 4; ++q) code[q] = xq + q < W ? gmem(P->pix_code)[(size_t)y * W + xq + q] : 0u;
+        }
+        uint32_t ob[3] = {0u, 0u, 0u};
+#pragma unroll
+        for (int g = 0; g < 4; g += BG) {
+            int nh[BG], ka[BG], kb[BG], pq[BG];
+            float th[BG], ua[BG], va[BG];
+            typedef float f2v __attribute__((ext_vector_type(2)));
+            f2v fij[BG], fji[BG];
+#pragma unroll
+            for (int q = 0; q < BG; ++q) {
+                const int x = xq + g + q;
+                nh[q] = (int)(code[g + q] >> 12);
+                ka[q] = 0;
+                kb[q] = 0;
+                pq[q] = 0;
+                th[q] = 0.0f;
+                ua[q] = 0.0f;
+                va[q] = 0.0f;
+                if (nh[q] <= 0) continue;
+                // the covering (camera, shift) candidates found at plan time, in the
+                // coverage scan's order; their positions are evaluated again
                 int hc[2] = {0, 0}, hm[2] = {0, 0};
                 float hu[2] = {0, 0}, hv[2] = {0, 0};
 #pragma unroll
                 for (int e = 0; e < 2; ++e) {
-                    if (e >= nh) break;
-                    const int bit = (int)((code >> (6 * e)) & 63u);   // 3 camera + shift + 1
+                    if (e >= nh[q]) break;
+                    const int bit = (int)((code[g + q] >> (6 * e)) & 63u);
                     const int k = bit / 3, sh = bit % 3 - 1;
                     hc[e] = k;
                     hm[e] = sh;
                     hom(s_hinv[k], (float)(x + sh * Wp), (float)y, s_cw[k], s_ch[k], hu[e], hv[e]);
                 }
-                if (nh == 1) {
-                    const int k = hc[0];
+                if (nh[q] == 1) {
+                    ka[q] = hc[0];
+                    ua[q] = hu[0];
+                    va[q] = hv[0];
+                    continue;
+                }
+                const int p = s_pair[hc[0]][hc[1]];
+                const int ji = hc[0] == s_pj[p] ? 0 : 1;
+                const int kj = hc[ji], ki = hc[1 - ji];
+                const int mj = hm[ji], mi = hm[1 - ji];
+                float dj = fminf(hu[ji], (float)(s_cw[kj] - 1) - hu[ji]);
+                float di = fminf(hu[1 - ji], (float)(s_cw[ki] - 1) - hu[1 - ji]);
+                if (dj < 0.0f) dj = 0.0f;
+                if (di < 0.0f) di = 0.0f;
+                const float sum = di + dj;
+                th[q] = sum > 0.0f ? di / sum : 0.5f;
+                const int lx = x + mj * Wp - s_fx0[p], ly = y - s_fy0[p];
+                const size_t qf = (size_t)ly * s_fw[p] + lx;
+                fij[q] = gmem((const f2v*)s_fl[p][0])[qf];
+                fji[q] = gmem((const f2v*)s_fl[p][1])[qf];
+                ka[q] = ki;
+                kb[q] = kj;
+                pq[q] = p;
+                // the canvas columns of the two samples, shifts included
+                ua[q] = (float)(x + mi * Wp);
+                va[q] = (float)(x + mj * Wp);
+            }
+            // (2) bilinear taps: sample a (one camera, or camera i), sample b (camera j)
+            BilTaps ta[BG], tb[BG];
+#pragma unroll
+            for (int q = 0; q < BG; ++q) {
+                if (nh[q] == 1) {
+                    const int k = ka[q];
+                    bil_load(s_fr[k], s_cp[k], s_cw[k], s_ch[k], ua[q], va[q], ta[q]);
+                } else if (nh[q] >= 2) {
+                    // eq. (17): camera i moves by theta_j flow_ij, camera j by theta_i
+                    // flow_ji (as printed: theta_i and theta_j, VS_READ_LITERAL_EQ17)
+                    const float thi = th[q], thj = 1.0f - thi;
+                    const float wi = lit ? thi : thj, wj = lit ? thj : thi;
+                    const float Xi = __builtin_fmaf(wi, fij[q].x, ua[q]);
+                    const float Yi = __builtin_fmaf(wi, fij[q].y, (float)y);
+                    const float Xj = __builtin_fmaf(wj, fji[q].x, va[q]);
+                    const float Yj = __builtin_fmaf(wj, fji[q].y, (float)y);
+                    const int ki = ka[q], kj = kb[q];
+                    float u, v;
+                    hom(s_hinv[ki], Xi, Yi, s_cw[ki], s_ch[ki], u, v);
+                    bil_load(s_fr[ki], s_cp[ki], s_cw[ki], s_ch[ki], u, v, ta[q]);
+                    hom(s_hinv[kj], Xj, Yj, s_cw[kj], s_ch[kj], u, v);
+                    bil_load(s_fr[kj], s_cp[kj], s_cw[kj], s_ch[kj], u, v, tb[q]);
+                }
+            }
+            // (3) colour correction and fusion, eq. (18)
+#pragma unroll
+            for (int q = 0; q < BG; ++q) {
+                uint32_t o0 = 0, o1 = 0, o2 = 0;
+                if (nh[q] == 1) {
                     float s[3];
-                    bilin3(s_fr[k], s_cp[k], s_cw[k], s_ch[k], hu[0], hv[0], s);
-                    const float* M = s_M[k];
+                    bil_rgb(ta[q], s);
+                    const float* M = s_M[ka[q]];
                     o0 = round8(capply(s, M, 0));
                     o1 = round8(capply(s, M, 1));
                     o2 = round8(capply(s, M, 2));
-                } else if (nh >= 2) {
-                    const int p = P->pair_of[hc[0]][hc[1]];
-                    const int ji = hc[0] == P->pj[p] ? 0 : 1;
-                    const int kj = hc[ji], ki = hc[1 - ji];
-                    const int mj = hm[ji], mi = hm[1 - ji];
-                    float dj = fminf(hu[ji], (float)(s_cw[kj] - 1) - hu[ji]);
-                    float di = fminf(hu[1 - ji], (float)(s_cw[ki] - 1) - hu[1 - ji]);
-                    if (dj < 0.0f) dj = 0.0f;
-                    if (di < 0.0f) di = 0.0f;
-                    const float sum = di + dj;
-                    const float thi = sum > 0.0f ? di / sum : 0.5f;
-                    const float thj = 1.0f - thi;
-                    const int lx = x + mj * Wp - P->sx0[p], ly = y - P->sy0[p];
-                    const size_t qf = (size_t)ly * P->sw[p] + lx;
-                    typedef float f2v __attribute__((ext_vector_type(2)));
-                    const f2v fij = gmem((const f2v*)P->flow[p][0][0])[qf];
-                    const f2v fji = gmem((const f2v*)P->flow[p][1][0])[qf];
-                    // eq. (17): camera i moves by theta_j flow_ij, camera j by theta_i
-                    // flow_ji (as printed: theta_i and theta_j, VS_READ_LITERAL_EQ17)
-                    const bool lit = (P->readings & VS_READ_LITERAL_EQ17) != 0;
-                    const float wi = lit ? thi : thj, wj = lit ? thj : thi;
-                    const float Xi = __builtin_fmaf(wi, fij.x, (float)(x + mi * Wp));
-                    const float Yi = __builtin_fmaf(wi, fij.y, (float)y);
-                    const float Xj = __builtin_fmaf(wj, fji.x, (float)(x + mj * Wp));
-                    const float Yj = __builtin_fmaf(wj, fji.y, (float)y);
-                    float u, v, si[3], sj[3];
-                    hom(s_hinv[ki], Xi, Yi, s_cw[ki], s_ch[ki], u, v);
-                    bilin3(s_fr[ki], s_cp[ki], s_cw[ki], s_ch[ki], u, v, si);
-                    hom(s_hinv[kj], Xj, Yj, s_cw[kj], s_ch[kj], u, v);
-                    bilin3(s_fr[kj], s_cp[kj], s_cw[kj], s_ch[kj], u, v, sj);
+                } else if (nh[q] >= 2) {
+                    float si[3], sj[3];
+                    bil_rgb(ta[q], si);
+                    bil_rgb(tb[q], sj);
                     // overlap-only reading: camera i's own pair matrix (camera j's is I)
-                    const float* Mi = (P->readings & VS_READ_OVERLAP_ONLY) ? P->res->Mpf[p] : s_M[ki];
-                    const float* Mj = s_M[kj];
+                    const float* Mi = ovl_only ? P->res->Mpf[pq[q]] : s_M[ka[q]];
+                    const float* Mj = s_M[kb[q]];
+                    const float thi = th[q];
                     float ti, tj;
                     ti = capply(si, Mi, 0);
                     tj = capply(sj, Mj, 0);
@@ -859,29 +938,27 @@ __device__ __forceinline__ void blend_body(const DevPlan* __restrict__ P, const 
                     tj = capply(sj, Mj, 2);
                     o2 = round8(__builtin_fmaf(thi, ti - tj, tj));
                 }
-                if (nh > 0) {
+                if (nh[q] > 0) {
                     atomicAdd(&my_hist[o0], 1u);
                     atomicAdd(&my_hist[256 + o1], 1u);
                     atomicAdd(&my_hist[512 + o2], 1u);
                 }
+                // byte 3 n + c of the thread's 12 output bytes (pixel n, channel c)
+                const int n3 = (g + q) * 3;
+                ob[n3 >> 2] |= o0 << (8 * (n3 & 3));
+                ob[(n3 + 1) >> 2] |= o1 << (8 * ((n3 + 1) & 3));
+                ob[(n3 + 2) >> 2] |= o2 << (8 * ((n3 + 2) & 3));
             }
-            ob[q * 3 + 0] = o0;
-            ob[q * 3 + 1] = o1;
-            ob[q * 3 + 2] = o2;
         }
         uint8_t* const prow = P->pano + (size_t)y * P->pano_pitch + (size_t)xq * 3;
         auto* row = gmem(prow);
         if (vec && xq + 3 < W) {
             auto* r32 = gmem((uint32_t*)prow);
-            r32[0] = ob[0] | (ob[1] << 8) | (ob[2] << 16) | (ob[3] << 24);
-            r32[1] = ob[4] | (ob[5] << 8) | (ob[6] << 16) | (ob[7] << 24);
-            r32[2] = ob[8] | (ob[9] << 8) | (ob[10] << 16) | (ob[11] << 24);
+            r32[0] = ob[0];
+            r32[1] = ob[1];
+            r32[2] = ob[2];
         } else {
-            for (int q = 0; q < 4 && xq + q < W; ++q) {
-                row[q * 3 + 0] = (uint8_t)ob[q * 3 + 0];
-                row[q * 3 + 1] = (uint8_t)ob[q * 3 + 1];
-                row[q * 3 + 2] = (uint8_t)ob[q * 3 + 2];
-            }
+            for (int b = 0; b < 12 && xq + b / 3 < W; ++b) row[b] = (uint8_t)(ob[b >> 2] >> (8 * (b & 3)));
         }
     }
     __syncthreads();
