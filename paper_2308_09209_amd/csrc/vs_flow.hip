@@ -313,35 +313,48 @@ __device__ __forceinline__ void lk_w9_body(const DevPlan* __restrict__ Pl, const
         }
     }
 
-    // staging: every load of both tiles issued before the first LDS store (one
-    // memory round trip, not one per element a thread stages)
-    constexpr int NST = (TSH * TSW + 255) / 256, NSM = (MH * MW + 255) / 256;
-    float vt[NST], vm[NSM];
+    // staging by rows: wavefront wv takes tile rows wv, wv + 4, ...; lane c
+    // columns c and c + 64 (clamped once), so a row's base address and clamp
+    // are the same for the whole wavefront; every load of both tiles is issued
+    // before the first LDS store (one memory round trip)
+    static_assert(TSW <= 128 && MW <= 128, "two columns per lane");
+    constexpr int RT = (TSH + 3) / 4, RM = (MH + 3) / 4;
+    const int tc0 = clampi(x0 - R - 1 + lane, 0, w - 1), tc1 = clampi(x0 - R - 1 + 64 + lane, 0, w - 1);
+    const int mc0 = clampi(x0 - HM + lane, 0, w - 1), mc1 = clampi(x0 - HM + 64 + lane, 0, w - 1);
+    float vt[RT][2], vm[RM][2];
 #pragma unroll
-    for (int k = 0; k < NST; ++k) {
-        const int i = tid + 256 * k;
-        if (i < TSH * TSW) {
-            const int yy = clampi(y0 - R - 1 + i / TSW, 0, h - 1), xx = clampi(x0 - R - 1 + i % TSW, 0, w - 1);
-            vt[k] = Tm[(size_t)yy * w + xx];
+    for (int j = 0; j < RT; ++j) {
+        const int r = wv + 4 * j;
+        if (r < TSH) {
+            const float* row = Tm + (size_t)clampi(y0 - R - 1 + r, 0, h - 1) * w;
+            vt[j][0] = row[tc0];
+            if (64 + lane < TSW) vt[j][1] = row[tc1];
         }
     }
 #pragma unroll
-    for (int k = 0; k < NSM; ++k) {
-        const int i = tid + 256 * k;
-        if (i < MH * MW) {
-            const int yy = clampi(y0 - HM + i / MW, 0, h - 1), xx = clampi(x0 - HM + i % MW, 0, w - 1);
-            vm[k] = Mv[(size_t)yy * w + xx];
+    for (int j = 0; j < RM; ++j) {
+        const int r = wv + 4 * j;
+        if (r < MH) {
+            const float* row = Mv + (size_t)clampi(y0 - HM + r, 0, h - 1) * w;
+            vm[j][0] = row[mc0];
+            if (64 + lane < MW) vm[j][1] = row[mc1];
         }
     }
 #pragma unroll
-    for (int k = 0; k < NST; ++k) {
-        const int i = tid + 256 * k;
-        if (i < TSH * TSW) sT[i] = vt[k];
+    for (int j = 0; j < RT; ++j) {
+        const int r = wv + 4 * j;
+        if (r < TSH) {
+            sT[r * TSW + lane] = vt[j][0];
+            if (64 + lane < TSW) sT[r * TSW + 64 + lane] = vt[j][1];
+        }
     }
 #pragma unroll
-    for (int k = 0; k < NSM; ++k) {
-        const int i = tid + 256 * k;
-        if (i < MH * MW) sM[(i / MW) * MWP + i % MW] = vm[k];
+    for (int j = 0; j < RM; ++j) {
+        const int r = wv + 4 * j;
+        if (r < MH) {
+            sM[r * MWP + lane] = vm[j][0];
+            if (64 + lane < MW) sM[r * MWP + 64 + lane] = vm[j][1];
+        }
     }
     __syncthreads();
     for (int i = tid; i < TIH * TIW; i += 256) {

@@ -925,7 +925,7 @@ vs_status vs_stitch(vs_ctx* c, const uint8_t* const frames[], const vs_color_sta
         ev = c->ev[i];
         c->slot_used[i] = 1;
     }
-    VS_CHECK(launch_set_io(io, 1, s), "set io");
+    VS_CHECK(launch_set_io(io, 1, h.n_pairs, s), "set io");
     const char* where = "";
     hipError_t e = enqueue_frame(single(c), s, ev, c->pano_pre, pano, (size_t)h.canvas_h * h.pano_pitch, &where);
     if (e != hipSuccess) return dev_fail(c, e, where);
@@ -1384,7 +1384,9 @@ vs_status vs_batch_run(vs_batch* b, const uint8_t* const* const frames[], uint8_
             break;
         }
     hipStream_t s = (hipStream_t)stream;
-    hipError_t e = launch_set_io(io, b->n, s);
+    int max_pairs = 0;
+    for (int c = 0; c < b->n; ++c) max_pairs = std::max(max_pairs, (int)b->ctx[c]->hp.n_pairs);
+    hipError_t e = launch_set_io(io, b->n, max_pairs, s);
     if (e == hipSuccess) e = hipGraphLaunch(b->exec, s);
     if (e != hipSuccess) {
         b->err = std::string("batch run: ") + hipGetErrorString(e);

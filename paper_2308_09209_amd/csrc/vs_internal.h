@@ -2,6 +2,7 @@
 // by the host runtime (vs_host.cpp) and the kernels (vs_kernels.hip).
 #pragma once
 #include <hip/hip_runtime.h>
+#include <stddef.h>
 #include <stdint.h>
 
 #include "../../include/vstitch.h"
@@ -52,6 +53,9 @@ struct Accum {
 };
 static_assert(MAXL <= 8, "one deferral counter per level");
 static_assert(sizeof(Accum) % 16 == 0, "the fill kernels clear whole 16-byte words");
+static_assert(offsetof(Accum, hist) % 16 == 0 && offsetof(Accum, csum) % 16 == 0 && offsetof(Accum, mom) % 16 == 0 &&
+                  offsetof(Accum, pano_hist) % 16 == 0 && offsetof(Accum, lk_qn) > offsetof(Accum, pano_hist),
+              "k_set_io clears per-pair prefixes in 16-byte words, then the histogram and counters at the end");
 
 // Per-frame results (also the taps).
 struct Results {
@@ -176,7 +180,7 @@ struct PlanScan {
 // launchers (vs_kernels.hip); all return hipGetLastError() of the launch
 hipError_t launch_plan_scan(const DevPlan* dp, const DevPlan& hp, PlanScan* scan, hipStream_t s);
 hipError_t launch_need(const DevPlan* dp, const DevPlan& hp, hipStream_t s);
-hipError_t launch_set_io(const FrameIO& io, int n, hipStream_t s);
+hipError_t launch_set_io(const FrameIO& io, int n, int max_pairs, hipStream_t s);
 hipError_t launch_zero(const Group& g, hipStream_t s);
 hipError_t launch_strips(const Group& g, hipStream_t s);
 hipError_t launch_lut(const Group& g, hipStream_t s);

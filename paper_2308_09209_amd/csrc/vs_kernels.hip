@@ -148,7 +148,9 @@ hipError_t launch_fill_u8(uint8_t* p, size_t n, uint8_t v, hipStream_t s)
 // Frame and panorama pointers of every context of the group, written into its
 // device plan before the frame's kernels run (they read them from there, so a
 // captured frame graph replays for any input buffers), and the frame's
-// accumulators cleared (`per` blocks per context; a fill kernel, no memset).
+// accumulators cleared (`per` blocks per context; a fill kernel, no memset):
+// the per-pair arrays up to the context's pair count (the entries of the
+// other pairs are never written), then the panorama histogram and counters.
 __global__ __launch_bounds__(256) void k_set_io(const FrameIO io, int per)
 {
     const int c = blockIdx.x / per, b = blockIdx.x % per;
@@ -158,9 +160,23 @@ __global__ __launch_bounds__(256) void k_set_io(const FrameIO io, int per)
         if (k < MAXC) P->frame[k] = io.frame[c][k];
         if (k == 0) P->pano = io.pano[c];
     }
-    uint4* a = reinterpret_cast<uint4*>(P->acc);
-    const int i = b * 256 + k;
-    if (i < (int)(sizeof(Accum) / 16)) a[i] = make_uint4(0, 0, 0, 0);
+    constexpr uint32_t HW = sizeof(Accum::hist[0]) / 16, CW = sizeof(Accum::csum[0]) / 16;
+    constexpr uint32_t MW = sizeof(Accum::mom[0]) / 16;
+    constexpr uint32_t TW = (sizeof(Accum) - offsetof(Accum, pano_hist)) / 16;
+    const uint32_t np = (uint32_t)P->n_pairs;
+    uint4* const a = reinterpret_cast<uint4*>(P->acc);
+    uint32_t i = (uint32_t)(b * 256 + k);
+    uint4* dst = nullptr;
+    if (i < np * HW) {
+        dst = a + offsetof(Accum, hist) / 16 + i;
+    } else if ((i -= np * HW) < np * CW) {
+        dst = a + offsetof(Accum, csum) / 16 + i;
+    } else if ((i -= np * CW) < np * MW) {
+        dst = a + offsetof(Accum, mom) / 16 + i;
+    } else if ((i -= np * MW) < TW) {
+        dst = a + offsetof(Accum, pano_hist) / 16 + i;
+    }
+    if (dst) *dst = make_uint4(0, 0, 0, 0);
 }
 
 // ---------------------------------------------------------------------------
@@ -1127,9 +1143,11 @@ __global__ __launch_bounds__(BL_THREADS) void k_balance_apply(const Batch B)
 // ---------------------------------------------------------------------------
 
 
-hipError_t launch_set_io(const FrameIO& io, int n, hipStream_t s)
+hipError_t launch_set_io(const FrameIO& io, int n, int max_pairs, hipStream_t s)
 {
-    const int per = (int)((sizeof(Accum) / 16 + 255) / 256);
+    const size_t words = (size_t)max_pairs * ((sizeof(Accum::hist[0]) + sizeof(Accum::csum[0]) + sizeof(Accum::mom[0])) / 16) +
+                         (sizeof(Accum) - offsetof(Accum, pano_hist)) / 16;
+    const int per = (int)((words + 255) / 256);
     hipLaunchKernelGGL(k_set_io, dim3(n * per), dim3(256), 0, s, io, per);
     return hipGetLastError();
 }
