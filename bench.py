@@ -598,12 +598,26 @@ def bench_batch(args):
         batch.run(frames[i % seq], panos)
     torch.cuda.synchronize()
     K = args.steps
+    # a serving loop bounds its queue: at most about 2 IN_FLIGHT steps enqueued
+    # ahead of the GPU (a host far ahead meets the runtime's queue backpressure
+    # inside graph launches, which stalls the GPU in the middle of a step).
+    # Throughput: one marker event per IN_FLIGHT steps (an event recorded on the
+    # stream delays the next kernel by about 5 us); latency: a second pass with
+    # an event pair around every step.
+    marks = []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(K):
+        if i % IN_FLIGHT == 0:
+            if len(marks) >= 2:
+                marks[-2].synchronize()
+            marks.append(torch.cuda.Event())
+            marks[-1].record()
+        batch.run(frames[(args.warmup + i) % seq], panos)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
     starts = [torch.cuda.Event(enable_timing=True) for _ in range(K)]
     ends = [torch.cuda.Event(enable_timing=True) for _ in range(K)]
-    # a serving loop bounds its queue: at most IN_FLIGHT steps enqueued ahead of
-    # the GPU (a host far ahead meets the runtime's queue backpressure inside
-    # graph launches, which stalls the GPU in the middle of a step)
-    t0 = time.perf_counter()
     for i in range(K):
         if i >= IN_FLIGHT:
             ends[i - IN_FLIGHT].synchronize()
@@ -611,7 +625,6 @@ def bench_batch(args):
         batch.run(frames[(args.warmup + i) % seq], panos)
         ends[i].record()
     torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
     lat = np.array([starts[i].elapsed_time(ends[i]) for i in range(K)])
     if args.workload:
         wl = WORKLOADS[args.workload]
@@ -629,7 +642,7 @@ def bench_batch(args):
                            pyr_tile_rows=[int(st.tuning().pyr_tile_rows) for st in sts],
                            flow=args.flow if use_surr else "plain",
                            fb_tau_px=args.fb_tau if use_surr and args.flow == "fallback" else None,
-                           steps_in_flight=IN_FLIGHT, parallelism="single GPU"),
+                           steps_in_flight=2 * IN_FLIGHT, parallelism="single GPU"),
                p50_ms=round(float(np.percentile(lat, 50)), 4),
                p99_ms=round(float(np.percentile(lat, 99)), 4))
     print(json.dumps(out), flush=True)
