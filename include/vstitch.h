@@ -506,6 +506,20 @@ vs_status vs_flow_destroy(vs_flow* f);
  * device; either may be NULL) and its size. */
 vs_status vs_flow_level(vs_flow* f, int level, float* yt, float* ym, int32_t* w, int32_t* h, void* stream);
 
+/* Steps a5-a6 of a stitch context on a caller strip pair (section 3.2):
+ * strip_i (camera i, moving) and strip_j (camera j, template) are w x h RGB
+ * HWC byte images (pitch 3 w, device pointers) whose colours are used as
+ * given (a5 with the identity colour matrix: Y = (77 R + 150 G + 29 B + 128)
+ * >> 8), and flow_ij / flow_ji (FP32 [h][w][2], device, either may be NULL)
+ * receive the pyramidal flow of the context's parameters on the whole strip,
+ * as vs_flow_run gives it (flow_ij: P_i(x + f) ~ P_j(x)).  The context keeps
+ * a plain-flow workspace for the last strip size (allocated, after a device
+ * synchronisation, when the size changes; freed by vs_destroy).
+ * VS_E_INVAL: null context or strip, w or h < 1, or a size the estimator
+ * cannot plan.  Asynchronous on stream. */
+vs_status vs_flow_only(vs_ctx* c, const uint8_t* strip_i, const uint8_t* strip_j, int w, int h, float* flow_ij,
+                       float* flow_ji, void* stream);
+
 /* For callers that cannot allocate device memory (code under HIP graph
  * capture, tight serving loops, harnesses that forbid hipMalloc): the
  * estimator of vs_flow_run on one w x h luma pair without a context.  Same

@@ -47,6 +47,10 @@ struct vs_ctx {
     // a batch holding this context recaptures its graph
     uint32_t gen = 0;
     char arch[32] = {};                  // device architecture at create (tuning-record key)
+    // vs_flow_only: a plain-flow context for the last strip size and its two luma images
+    vs_flow* fo = nullptr;
+    float* fo_luma = nullptr;
+    int fo_w = 0, fo_h = 0;
 };
 
 namespace {
@@ -197,6 +201,8 @@ void free_ctx(vs_ctx* c)
     if (c->surr_mem) (void)hipFree(c->surr_mem);
     if (c->tiles) (void)hipFree(c->tiles);
     if (c->var_mem) (void)hipFree(c->var_mem);
+    if (c->fo) (void)vs_flow_destroy(c->fo);
+    if (c->fo_luma) (void)hipFree(c->fo_luma);
     delete c;
 }
 
@@ -1678,6 +1684,39 @@ vs_status vs_flow_run(vs_flow* f, const float* yt, const float* ym, float* flow_
     if (!f || !yt || !ym) return VS_E_INVAL;
     return flow_run(f->hp, f->dp, yt, ym, flow_tm, flow_mt, (hipStream_t)stream) == hipSuccess ? VS_OK
                                                                                               : VS_E_DEVICE;
+}
+
+vs_status vs_flow_only(vs_ctx* c, const uint8_t* strip_i, const uint8_t* strip_j, int w, int h, float* flow_ij,
+                       float* flow_ji, void* stream)
+{
+    if (!c || !strip_i || !strip_j || w < 1 || h < 1) return VS_E_INVAL;
+    if (c->sticky) return VS_E_DEVICE;
+    if (!c->fo || c->fo_w != w || c->fo_h != h) {
+        // a plain-flow context of this size with the stitch context's parameters
+        VS_CHECK(hipDeviceSynchronize(), "hipDeviceSynchronize");
+        if (c->fo) (void)vs_flow_destroy(c->fo);
+        if (c->fo_luma) (void)hipFree(c->fo_luma);
+        c->fo = nullptr;
+        c->fo_luma = nullptr;
+        c->fo_w = c->fo_h = 0;
+        const vs_status st = vs_flow_create(w, h, &c->prm, &c->fo);
+        if (st != VS_OK) return fail(c, st, "vs_flow_only: strip size");
+        if (hipMalloc((void**)&c->fo_luma, 2 * (size_t)w * h * sizeof(float)) != hipSuccess) {
+            (void)vs_flow_destroy(c->fo);
+            c->fo = nullptr;
+            return fail(c, VS_E_NOMEM, "vs_flow_only: luma buffers");
+        }
+        c->fo_w = w;
+        c->fo_h = h;
+    }
+    hipStream_t s = (hipStream_t)stream;
+    const size_t n = (size_t)w * h;
+    float* yj = c->fo_luma;
+    float* yi = c->fo_luma + n;
+    VS_CHECK(launch_luma_rgb(strip_j, n, yj, s), "luma launch");
+    VS_CHECK(launch_luma_rgb(strip_i, n, yi, s), "luma launch");
+    // flow_ij: template camera j, moving camera i (and the reverse)
+    return vs_flow_run(c->fo, yj, yi, flow_ij, flow_ji, stream);
 }
 
 vs_status vs_flow_level(vs_flow* f, int level, float* yt, float* ym, int32_t* w_out, int32_t* h_out, void* stream)

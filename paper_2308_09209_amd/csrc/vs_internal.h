@@ -205,6 +205,7 @@ struct Fork {
 };
 hipError_t launch_blend(const Group& g, hipStream_t s);
 hipError_t launch_fill_u8(uint8_t* p, size_t n, uint8_t v, hipStream_t s);
+hipError_t launch_luma_rgb(const uint8_t* rgb, size_t n, float* y, hipStream_t s);
 
 // workspace of a plain-flow context (vs_flow_create, vs_flow_run_noalloc)
 struct FlowLayout {

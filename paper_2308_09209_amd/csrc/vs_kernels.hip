@@ -137,6 +137,26 @@ __global__ __launch_bounds__(256) void k_fill_u8(uint8_t* p, size_t n, uint8_t v
     for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < n; i += stride) p[i] = v;
 }
 
+// Section 3.2 flow input of a caller strip (step a5 with the identity colour
+// matrix): Y = (77 R + 150 G + 29 B + 128) >> 8 per pixel of an RGB HWC byte
+// image, as FP32 (grid-stride)
+__global__ __launch_bounds__(256) void k_luma_rgb(const uint8_t* __restrict__ rgb, size_t n, float* __restrict__ y)
+{
+    const size_t stride = (size_t)gridDim.x * 256;
+    for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < n; i += stride) {
+        const uint32_t r = rgb[3 * i], g = rgb[3 * i + 1], b = rgb[3 * i + 2];
+        y[i] = (float)((77u * r + 150u * g + 29u * b + 128u) >> 8);
+    }
+}
+
+hipError_t launch_luma_rgb(const uint8_t* rgb, size_t n, float* y, hipStream_t s)
+{
+    if (n == 0) return hipSuccess;
+    const size_t blocks = std::min<size_t>((n + 255) / 256, 4096);
+    hipLaunchKernelGGL(k_luma_rgb, dim3((unsigned)blocks), dim3(256), 0, s, rgb, n, y);
+    return hipGetLastError();
+}
+
 hipError_t launch_fill_u8(uint8_t* p, size_t n, uint8_t v, hipStream_t s)
 {
     if (n == 0) return hipSuccess;

@@ -46,7 +46,7 @@ EXPORTS = ["vs_abi_version", "vs_status_str", "vs_default_params", "vs_compose_h
            "vs_nn_conv3x3", "vs_nn_wgrad_scratch_bytes", "vs_nn_conv3x3_wgrad", "vs_nn_flip_weights",
            "vs_nn_lrelu_bwd", "vs_nn_pack_pair", "vs_nn_epe_loss", "vs_nn_adam", "vs_nn_to_bf16",
            "vs_nn_pool_flow", "vs_nn_create", "vs_nn_destroy", "vs_nn_forward", "vs_nn_loss", "vs_nn_backward",
-           "vs_nn_adam_step", "vs_nn_params", "vs_nn_save", "vs_nn_load", "vs_flow_create", "vs_flow_run", "vs_flow_destroy", "vs_flow_level",
+           "vs_nn_adam_step", "vs_nn_params", "vs_nn_save", "vs_nn_load", "vs_flow_create", "vs_flow_run", "vs_flow_destroy", "vs_flow_level", "vs_flow_only",
            "vs_flow_run_noalloc", "vs_calib_intrinsics", "vs_calib_plane_homography", "vs_calib_pair",
            "vs_calib_refine", "vs_calib_estimate"]
 
@@ -252,6 +252,7 @@ def lib():
         L.vs_flow_run.argtypes = [vp, vp, vp, vp, vp, vp]
         L.vs_flow_destroy.argtypes = [vp]
         L.vs_flow_level.argtypes = [vp, i32, vp, vp, C.POINTER(C.c_int32), C.POINTER(C.c_int32), vp]
+        L.vs_flow_only.argtypes = [vp, vp, vp, i32, i32, vp, vp, vp]
         L.vs_flow_run_noalloc.argtypes = [i32, i32, C.POINTER(Params), vp, vp, vp, vp, vp]
         dbl = C.c_double
         L.vs_calib_intrinsics.argtypes = [dbl] * 7 + [vp]
@@ -458,6 +459,22 @@ class Stitcher:
         st = lib().vs_set_flow_mode(self.h, mode, fb_tau_px)
         if st != 0:
             self._err(st, "vs_set_flow_mode")
+
+    def flow_only(self, strip_i, strip_j, stream=None):
+        """The context's plain flow on a caller strip pair: RGB uint8 device
+        tensors (h, w, 3), camera i (moving) and camera j (template); returns
+        (flow_ij, flow_ji), float32 (h, w, 2)."""
+        for t in (strip_i, strip_j):
+            if (t.dtype != torch.uint8 or not t.is_cuda or t.dim() != 3 or t.shape[2] != 3
+                    or not t.is_contiguous() or t.shape != strip_i.shape):
+                raise ValueError("strips: contiguous cuda uint8 (h, w, 3), both the same shape")
+        h, w = int(strip_i.shape[0]), int(strip_i.shape[1])
+        fij = torch.empty((h, w, 2), dtype=torch.float32, device=strip_i.device)
+        fji = torch.empty_like(fij)
+        st = lib().vs_flow_only(self.h, _p(strip_i), _p(strip_j), w, h, _p(fij), _p(fji), _stream_handle(stream))
+        if st != 0:
+            self._err(st, "vs_flow_only")
+        return fij, fji
 
     def tap(self, name: str, pair: int = 0, sub: int = 0) -> np.ndarray:
         I = self.info

@@ -155,6 +155,18 @@ def test_noalloc_flow_rejects_oversized_pairs_on_the_host():
     assert L.vs_flow_run_noalloc(1, 64, None, fake, fake, fake, fake, None) == -1
 
 
+def test_flow_only_rejects_bad_arguments_on_the_host():
+    """vs_flow_only refuses a null context or strip and empty sizes before any
+    device call (the pointers are never dereferenced); no GPU needed."""
+    L = V.lib()
+    fake = C.c_void_p(16)
+    assert L.vs_flow_only(None, fake, fake, 64, 32, fake, fake, None) == -1
+    assert L.vs_flow_only(fake, None, fake, 64, 32, fake, fake, None) == -1
+    assert L.vs_flow_only(fake, fake, None, 64, 32, fake, fake, None) == -1
+    assert L.vs_flow_only(fake, fake, fake, 0, 32, fake, fake, None) == -1
+    assert L.vs_flow_only(fake, fake, fake, 64, 0, fake, fake, None) == -1
+
+
 def test_create_rejects_unknown_readings():
     """vs_params.readings outside the VS_READ_* mask is refused before any
     device work."""

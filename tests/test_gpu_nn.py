@@ -399,3 +399,29 @@ def test_pool_flow_block_means():
             for X in range(wo):
                 want[Y, X] = flow[Y * f:(Y + 1) * f, X * f:(X + 1) * f].reshape(-1, 2).astype(np.float64).mean(0) / f
         np.testing.assert_allclose(out.cpu().numpy(), want, rtol=1e-5, atol=1e-6)
+
+
+def test_flow_only_on_caller_strips_matches_oracle():
+    """vs_flow_only (steps a5-a6 on a caller RGB strip pair, identity colour
+    matrix) against the oracle: per-pixel luma, then its pyramidal flow in both
+    directions, bit for bit; a second size re-plans the context's workspace."""
+    from tests.test_oracle_flow import _pyr, texture
+    from paper_2308_09209_amd.scenes import small_scene
+    sc = small_scene(n_cams=2, W=200, H=110, overlap=0.35, ring=False, seed_config=5)
+    st = V.Stitcher(sc.rig())
+    lam = V.default_params().lk_lambda
+    rng = np.random.default_rng(11)
+    for h, w in ((96, 200), (64, 130)):
+        chans = [texture(h, w, 20 + c, sigma=2.0) for c in range(3)]
+        sj = np.stack(chans, -1)
+        si = np.roll(sj, (1, 2), axis=(0, 1)) + rng.normal(scale=2.0, size=sj.shape)
+        sj = np.clip(np.round(sj), 0, 255).astype(np.uint8)
+        si = np.clip(np.round(si), 0, 255).astype(np.uint8)
+        fij, fji = st.flow_only(torch.from_numpy(si).cuda(), torch.from_numpy(sj).cuda())
+        yl = [np.array([[O.luma(*s[y, x]) for x in range(w)] for y in range(h)], np.float32) for s in (sj, si)]
+        want_ij = O.pyramid_flow(_pyr(yl[0]), _pyr(yl[1]), lam=lam)
+        want_ji = O.pyramid_flow(_pyr(yl[1]), _pyr(yl[0]), lam=lam)
+        np.testing.assert_array_equal(fij.cpu().numpy(), want_ij)
+        np.testing.assert_array_equal(fji.cpu().numpy(), want_ji)
+        say(f"[flow_only {w}x{h}] median flow_ij {np.median(want_ij[8:-8, 8:-8], axis=(0, 1))}")
+    st.close()
