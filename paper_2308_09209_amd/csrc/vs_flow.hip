@@ -462,7 +462,17 @@ __device__ __forceinline__ void lk_w9_body(const DevPlan* __restrict__ Pl, const
         // tile rows t = 0 .. P + 2R: moving-image row t - q of pixel q
         constexpr int NT = P + 2 * R + 1;
         float2 gA[NW], gB[NW];
-        if (ALT) {
+        if (ALT && P == 1 && INBLOCK) {
+            // the levels this form is for hold about one wavefront per SIMD: the
+            // rows unrolled, so the next rows' LDS reads are in flight while a
+            // row computes (216 VGPRs, occupancy they do not need)
+#pragma unroll
+            for (int t = 0; t + 1 < NT; t += 2) {
+                lk_rhs_row<P, TIW, MWP, false>(t, g_base, sM, mb, fx, gA, gB, sau, sav, sbu, sbv);
+                lk_rhs_row<P, TIW, MWP, false>(t + 1, g_base, sM, mb, fx, gB, gA, sau, sav, sbu, sbv);
+            }
+            if (NT % 2) lk_rhs_row<P, TIW, MWP, false>(NT - 1, g_base, sM, mb, fx, gA, gB, sau, sav, sbu, sbv);
+        } else if (ALT) {
 #pragma unroll 1
             for (int t = 0; t + 1 < NT; t += 2) {
                 lk_rhs_row<P, TIW, MWP, false>(t, g_base, sM, mb, fx, gA, gB, sau, sav, sbu, sbv);
