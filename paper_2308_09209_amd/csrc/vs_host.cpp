@@ -208,15 +208,17 @@ void free_ctx(vs_ctx* c)
 
 // Default 9x9 flow-kernel variant of a level, from its count of 64 x 16 tiles
 // (n16) and the blocks the device holds at once (`resident`, four staged flow
-// blocks per compute unit): the most pixels per thread P (4, 3, 2, 1; n16 * 4 / P
-// blocks) that still gives at least one full wave of blocks, else P = 1 (the
-// most blocks for a small level), whose few deferred pixels are then finished
-// in-block (a tail launch costs more than they do).  Every P takes the form
-// that keeps the previous gradient row in registers: with the regrouped
-// right-hand side it costs no occupancy at P = 4 and saves the row's second
-// LDS read.
+// blocks per compute unit).  A level with under two waves of resident blocks
+// at 1 pixel per thread takes P = 1 in the unrolled form that finishes its
+// (few) deferred pixels in-block: at about one wavefront per SIMD its rows'
+// LDS reads overlap, and no tail launch follows.  Otherwise the most pixels
+// per thread P (4, 3, 2, 1; n16 * 4 / P blocks) that still gives at least
+// one full wave of blocks.  Every P takes the form that keeps the previous
+// gradient row in registers: with the regrouped right-hand side it costs no
+// occupancy at P = 4 and saves the row's second LDS read.
 int default_lk_P(int n16, int resident)
 {
+    if ((long)n16 * 4 < 2L * resident) return 1 + VS_FLOW_ALT + VS_FLOW_INBLOCK;
     for (int P = 4; P >= 1; --P) {
         const long blocks = ((long)n16 * 4 + P - 1) / P;
         if (blocks >= resident) return P + VS_FLOW_ALT;
