@@ -196,12 +196,32 @@ __global__ __launch_bounds__(256) void k_lk(const Batch B, int l)
 // ALT keeps the previous gradient row in a second register set (the row
 // loop unrolled by two, no copies); without it that row is read again from
 // LDS (fewer registers).
-// INBLOCK: the block finishes its own deferred pixels at its end (the tail
-// kernel's per-pixel routine, same arithmetic) instead of queueing them: the
-// launches of contexts whose pairs may keep the surrogate's flows, where the
-// deferred pixels are few and a tail launch per level would cost more.
-__device__ __forceinline__ void lk_tail_pixel(const DevPlan* __restrict__ Pl, int l, int f, int x, int y, int it0,
-                                              float ux, float uy);
+// INBLOCK: the block finishes its own deferred pixels at its end instead of
+// queueing them for the tail kernel: after a barrier each wavefront takes its
+// deferred pixels four at a time, one per 16-lane group (lk_tail_group, the
+// tail kernel's routine), the staged tiles' LDS then holding the groups'
+// moving windows.
+// Deferred pixels (lk_tail_group): 16 lanes per pixel, lane r of a group
+// taking window row r.  The moving image around the pixel's displacement is
+// staged in LDS (16 x 16 values, clamped indices: the window and a margin of
+// LK_TAIL_M px), so a step reads memory only when the displacement has moved
+// more than the margin since the staging; the sums then run through the rows
+// in order, the lane of each row adding its taps to the partial sums it
+// received from the lane of the row above and handing them on, so each sum is
+// the same row-major sequence of fused multiply-adds as in the staged kernel.
+constexpr int LK_TAIL_G = 16;
+constexpr int LK_TAIL_M = 3;
+constexpr int LK_TAIL_SW = 2 * LK_R_MAX + 2 + 2 * LK_TAIL_M;   // staged window side (16)
+
+// the value of the lane one below in its row of 16 lanes (0 for a row's first
+// lane), a DPP row shift: no LDS round trip
+__device__ __forceinline__ float row_shr1(float v)
+{
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x111, 0xf, 0xf, true));
+}
+
+__device__ __forceinline__ void lk_tail_group(const DevPlan* __restrict__ Pl, int l, int f, int x, int y, int it0,
+                                           float ux, float uy, int sub, float* mv);
 
 // Tile row t of a Gauss-Newton step: pixel q interpolates its moving-image row
 // k = t - q along x (g_base: this thread's gradient column 0 on the wavefront's
@@ -265,9 +285,15 @@ __device__ __forceinline__ void lk_w9_body(const DevPlan* __restrict__ Pl, const
     // moving-tile row pitch: a multiple of the 32 LDS banks, so lanes whose
     // displacements put them one row apart read distinct banks
     constexpr int MWP = (MW + 31) / 32 * 32;
-    __shared__ float2 sG[TIH * TIW];
-    __shared__ float sT[TSH * TSW];
-    __shared__ float sM[MH * MWP];
+    // the staged tiles in one buffer: with INBLOCK its first 16 KB hold the
+    // deferred pixels' moving windows after the steps (4 per wavefront)
+    constexpr int NGF = TIH * TIW * 2, NTF = TSH * TSW, NMF = MH * MWP;   // floats
+    constexpr int NWF = 16 * LK_TAIL_SW * LK_TAIL_SW;
+    constexpr int NBUF = NGF + NTF + NMF > NWF ? NGF + NTF + NMF : NWF;
+    __shared__ __align__(16) float s_lds[NBUF];
+    float2* const sG = reinterpret_cast<float2*>(s_lds);
+    float* const sT = s_lds + NGF;
+    float* const sM = s_lds + NGF + NTF;
 
     const int f = find_field(Pl->lk_off[l], 2 * Pl->n_pairs, bid);
     const int p = f >> 1, dir = f & 1;
@@ -394,113 +420,135 @@ __device__ __forceinline__ void lk_w9_body(const DevPlan* __restrict__ Pl, const
         cu[q] = 0.0f;
         cv[q] = 0.0f;
     }
-    // a wavefront without a flow-domain pixel has nothing to do (no barrier follows)
+    // a wavefront without a flow-domain pixel has nothing to do (it returns at
+    // once unless INBLOCK, whose barrier below every wavefront reaches)
     bool any_act = false;
 #pragma unroll
     for (int q = 0; q < P; ++q) any_act = any_act || act[q];
-    if (!__any(any_act)) return;
-    // normal matrix and template term: rows shared by the P pixels, row-major
-    // within each window
-    const float2* g_base = sG + wv * P * TIW + lane;
+    const bool wave_live = __any(any_act);
+    if (!INBLOCK && !wave_live) return;
+    if (wave_live) {
+        // normal matrix and template term: rows shared by the P pixels, row-major
+        // within each window
+        const float2* g_base = sG + wv * P * TIW + lane;
 #pragma unroll 1
-    for (int j = 0; j < P + 2 * R; ++j) {
-        float2 g[NW];
-        float tv[NW];
-#pragma unroll
-        for (int c = 0; c < NW; ++c) {
-            g[c] = g_base[j * TIW + c];
-            tv[c] = sT[(wv * P + j + 1) * TSW + lane + c + 1];
-        }
-#pragma unroll
-        for (int q = 0; q < P; ++q) {
-            if (j - q < 0 || j - q > 2 * R) continue;
+        for (int j = 0; j < P + 2 * R; ++j) {
+            float2 g[NW];
+            float tv[NW];
 #pragma unroll
             for (int c = 0; c < NW; ++c) {
-                g00[q] = __builtin_fmaf(g[c].x, g[c].x, g00[q]);
-                g01[q] = __builtin_fmaf(g[c].x, g[c].y, g01[q]);
-                g11[q] = __builtin_fmaf(g[c].y, g[c].y, g11[q]);
-                cu[q] = __builtin_fmaf(g[c].x, tv[c], cu[q]);
-                cv[q] = __builtin_fmaf(g[c].y, tv[c], cv[q]);
+                g[c] = g_base[j * TIW + c];
+                tv[c] = sT[(wv * P + j + 1) * TSW + lane + c + 1];
             }
-        }
-    }
 #pragma unroll
-    for (int q = 0; q < P; ++q) {
-        const int y = yb + q;
-        const int ncy = min(y + R, h - 1) - max(y - R, 0) + 1;
-        const float reg = act[q] ? Pl->lk_lambda * (float)(ncy * ncx) : 1.0f;
-        g00[q] = g00[q] + reg;
-        g11[q] = g11[q] + reg;
-        det[q] = g00[q] * g11[q] - g01[q] * g01[q];
-    }
-    const int iters = Pl->lk_iters;
-    for (int it = 0; it < iters; ++it) {
-        float fx[P], fy[P], sau[P], sav[P], sbu[P], sbv[P];
-        int mb[P];
+            for (int q = 0; q < P; ++q) {
+                if (j - q < 0 || j - q > 2 * R) continue;
 #pragma unroll
-        for (int q = 0; q < P; ++q) {
-            const float flx = floorf(ux[q]), fly = floorf(uy[q]);
-            int ox = (int)flx, oy = (int)fly;
-            fx[q] = ux[q] - flx;
-            fy[q] = uy[q] - fly;
-            sau[q] = 0.0f;
-            sav[q] = 0.0f;
-            sbu[q] = 0.0f;
-            sbv[q] = 0.0f;
-            if (act[q] && !(ox >= -(LK_D + 1) && ox <= LK_D && oy >= -(LK_D + 1) && oy <= LK_D)) {
-                // the displacement leaves the staged tile: the pixel, with its state
-                // at the start of this step (kept from here on), goes to the tail
-                dit[q] = it;
-                act[q] = false;
+                for (int c = 0; c < NW; ++c) {
+                    g00[q] = __builtin_fmaf(g[c].x, g[c].x, g00[q]);
+                    g01[q] = __builtin_fmaf(g[c].x, g[c].y, g01[q]);
+                    g11[q] = __builtin_fmaf(g[c].y, g[c].y, g11[q]);
+                    cu[q] = __builtin_fmaf(g[c].x, tv[c], cu[q]);
+                    cv[q] = __builtin_fmaf(g[c].y, tv[c], cv[q]);
+                }
             }
-            if (!act[q]) {
-                ox = 0;
-                oy = 0;
-            }
-            mb[q] = (wv * P + q - R + HM + oy) * MWP + (lane - R + HM + ox);
-        }
-        // tile rows t = 0 .. P + 2R: moving-image row t - q of pixel q
-        constexpr int NT = P + 2 * R + 1;
-        float2 gA[NW], gB[NW];
-        if (ALT && P == 1 && INBLOCK) {
-            // the levels this form is for hold about one wavefront per SIMD: the
-            // rows unrolled, so the next rows' LDS reads are in flight while a
-            // row computes (216 VGPRs, occupancy they do not need)
-#pragma unroll
-            for (int t = 0; t + 1 < NT; t += 2) {
-                lk_rhs_row<P, TIW, MWP, false>(t, g_base, sM, mb, fx, gA, gB, sau, sav, sbu, sbv);
-                lk_rhs_row<P, TIW, MWP, false>(t + 1, g_base, sM, mb, fx, gB, gA, sau, sav, sbu, sbv);
-            }
-            if (NT % 2) lk_rhs_row<P, TIW, MWP, false>(NT - 1, g_base, sM, mb, fx, gA, gB, sau, sav, sbu, sbv);
-        } else if (ALT) {
-#pragma unroll 1
-            for (int t = 0; t + 1 < NT; t += 2) {
-                lk_rhs_row<P, TIW, MWP, false>(t, g_base, sM, mb, fx, gA, gB, sau, sav, sbu, sbv);
-                lk_rhs_row<P, TIW, MWP, false>(t + 1, g_base, sM, mb, fx, gB, gA, sau, sav, sbu, sbv);
-            }
-            if (NT % 2) lk_rhs_row<P, TIW, MWP, false>(NT - 1, g_base, sM, mb, fx, gA, gB, sau, sav, sbu, sbv);
-        } else {
-#pragma unroll 1
-            for (int t = 0; t < NT; ++t)
-                lk_rhs_row<P, TIW, MWP, true>(t, g_base, sM, mb, fx, gA, gB, sau, sav, sbu, sbv);
         }
 #pragma unroll
         for (int q = 0; q < P; ++q) {
-            if (!act[q]) continue;
-            const float bu = __builtin_fmaf(fy[q], sbu[q] - sau[q], sau[q]) - cu[q];
-            const float bv = __builtin_fmaf(fy[q], sbv[q] - sav[q], sav[q]) - cv[q];
-            const float du = (g01[q] * bv - g11[q] * bu) / det[q];
-            const float dv = (g01[q] * bu - g00[q] * bv) / det[q];
-            ux[q] = ux[q] + du;
-            uy[q] = uy[q] + dv;
+            const int y = yb + q;
+            const int ncy = min(y + R, h - 1) - max(y - R, 0) + 1;
+            const float reg = act[q] ? Pl->lk_lambda * (float)(ncy * ncx) : 1.0f;
+            g00[q] = g00[q] + reg;
+            g11[q] = g11[q] + reg;
+            det[q] = g00[q] * g11[q] - g01[q] * g01[q];
         }
-    }
+        const int iters = Pl->lk_iters;
+        for (int it = 0; it < iters; ++it) {
+            float fx[P], fy[P], sau[P], sav[P], sbu[P], sbv[P];
+            int mb[P];
 #pragma unroll
-    for (int q = 0; q < P; ++q)
-        if (act[q]) Pl->flow[p][dir][l][(size_t)(yb + q) * w + x] = make_float2(ux[q], uy[q]);
-    if (INBLOCK) {
+            for (int q = 0; q < P; ++q) {
+                const float flx = floorf(ux[q]), fly = floorf(uy[q]);
+                int ox = (int)flx, oy = (int)fly;
+                fx[q] = ux[q] - flx;
+                fy[q] = uy[q] - fly;
+                sau[q] = 0.0f;
+                sav[q] = 0.0f;
+                sbu[q] = 0.0f;
+                sbv[q] = 0.0f;
+                if (act[q] && !(ox >= -(LK_D + 1) && ox <= LK_D && oy >= -(LK_D + 1) && oy <= LK_D)) {
+                    // the displacement leaves the staged tile: the pixel, with its state
+                    // at the start of this step (kept from here on), goes to the tail
+                    dit[q] = it;
+                    act[q] = false;
+                }
+                if (!act[q]) {
+                    ox = 0;
+                    oy = 0;
+                }
+                mb[q] = (wv * P + q - R + HM + oy) * MWP + (lane - R + HM + ox);
+            }
+            // tile rows t = 0 .. P + 2R: moving-image row t - q of pixel q
+            constexpr int NT = P + 2 * R + 1;
+            float2 gA[NW], gB[NW];
+            if (ALT && P == 1 && INBLOCK) {
+                // the levels this form is for hold about one wavefront per SIMD: the
+                // rows unrolled, so the next rows' LDS reads are in flight while a
+                // row computes (216 VGPRs, occupancy they do not need)
+#pragma unroll
+                for (int t = 0; t + 1 < NT; t += 2) {
+                    lk_rhs_row<P, TIW, MWP, false>(t, g_base, sM, mb, fx, gA, gB, sau, sav, sbu, sbv);
+                    lk_rhs_row<P, TIW, MWP, false>(t + 1, g_base, sM, mb, fx, gB, gA, sau, sav, sbu, sbv);
+                }
+                if (NT % 2) lk_rhs_row<P, TIW, MWP, false>(NT - 1, g_base, sM, mb, fx, gA, gB, sau, sav, sbu, sbv);
+            } else if (ALT) {
+#pragma unroll 1
+                for (int t = 0; t + 1 < NT; t += 2) {
+                    lk_rhs_row<P, TIW, MWP, false>(t, g_base, sM, mb, fx, gA, gB, sau, sav, sbu, sbv);
+                    lk_rhs_row<P, TIW, MWP, false>(t + 1, g_base, sM, mb, fx, gB, gA, sau, sav, sbu, sbv);
+                }
+                if (NT % 2) lk_rhs_row<P, TIW, MWP, false>(NT - 1, g_base, sM, mb, fx, gA, gB, sau, sav, sbu, sbv);
+            } else {
+#pragma unroll 1
+                for (int t = 0; t < NT; ++t)
+                    lk_rhs_row<P, TIW, MWP, true>(t, g_base, sM, mb, fx, gA, gB, sau, sav, sbu, sbv);
+            }
+#pragma unroll
+            for (int q = 0; q < P; ++q) {
+                if (!act[q]) continue;
+                const float bu = __builtin_fmaf(fy[q], sbu[q] - sau[q], sau[q]) - cu[q];
+                const float bv = __builtin_fmaf(fy[q], sbv[q] - sav[q], sav[q]) - cv[q];
+                const float du = (g01[q] * bv - g11[q] * bu) / det[q];
+                const float dv = (g01[q] * bu - g00[q] * bv) / det[q];
+                ux[q] = ux[q] + du;
+                uy[q] = uy[q] + dv;
+            }
+        }
+#pragma unroll
         for (int q = 0; q < P; ++q)
-            if (dit[q] >= 0) lk_tail_pixel(Pl, l, f, x, yb + q, dit[q], ux[q], uy[q]);
+            if (act[q]) Pl->flow[p][dir][l][(size_t)(yb + q) * w + x] = make_float2(ux[q], uy[q]);
+    }   // wave_live
+    if (INBLOCK) {
+        __syncthreads();   // every wavefront is done with the staged tiles
+        float* const win = s_lds + (wv * 4 + (lane >> 4)) * (LK_TAIL_SW * LK_TAIL_SW);
+        const int sub = lane & 15;
+#pragma unroll
+        for (int q = 0; q < P; ++q) {
+            unsigned long long m = __ballot(dit[q] >= 0);
+            while (m != 0ull) {   // the same for the whole wavefront
+                // the next (up to) 4 deferred lanes, one per 16-lane group
+                int src = -1;
+                for (int g = 0; g < 4 && m != 0ull; ++g) {
+                    const int s = __builtin_ctzll(m);
+                    m &= m - 1ull;
+                    if ((lane >> 4) == g) src = s;
+                }
+                const int s0 = src < 0 ? 0 : src;
+                const float pux = __shfl(ux[q], s0, 64), puy = __shfl(uy[q], s0, 64);
+                const int pit = __shfl(dit[q], s0, 64);
+                if (src >= 0) lk_tail_group(Pl, l, f, x0 + src, yb + q, pit, pux, puy, sub, win);
+            }
+        }
     } else {
         // queue the deferred pixels for the tail kernel: one reservation per
         // wavefront, after the steps (a reservation returns only after a round
@@ -533,297 +581,175 @@ __device__ __forceinline__ void lk_w9_body(const DevPlan* __restrict__ Pl, const
     }
 }
 
+// the 4-pixel forms held to 128 VGPRs (4 blocks per compute unit) also when
+// they finish their deferred pixels in-block
 template <int P, bool INBLOCK, bool ALT = false>
-__global__ __launch_bounds__(256) void k_lk_w9(const Batch B, int l)
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(P == 4 && INBLOCK ? 4 : 1)))
+void k_lk_w9(const Batch B, int l)
 {
     int c;
     const int b = batch_block(B, blockIdx.x, c);
     lk_w9_body<P, INBLOCK, ALT>(B.plan[c], b, l);
 }
 
-// Pixels whose displacement left the staged tile finish here (inside the
-// staged kernel, at its end), one pixel per lane, every tap read from global
-// memory with clamped indices (gradients 0 outside the level, as in the staged
-// kernel, so the row-major sums are the same).  Each window row issues all of
-// its loads before using them: about one memory round trip per window row.
-// The window rows are not unrolled: the staged kernel's registers are
-// scarce.
-__device__ __forceinline__ void lk_tail_pixel(const DevPlan* __restrict__ Pl, int l, int f, int x, int y, int it0,
-                                              float ux, float uy)
-{
-    constexpr int R = LK_R_MAX, NW = 2 * R + 1;
-    const int iters = Pl->lk_iters;
-    {
-        const int p = f >> 1, dir = f & 1;
-        const int w = Pl->lw[p][l], h = Pl->lh[p][l];
-        const float* __restrict__ Tm = Pl->pyr[p][dir == 0 ? 0 : 1][l];
-        const float* __restrict__ Mv = Pl->pyr[p][dir == 0 ? 1 : 0][l];
-        int cxm[NW + 2];   // clamped columns x - R - 1 .. x + R + 1
-        bool cin[NW];
-#pragma unroll
-        for (int k = 0; k < NW + 2; ++k) cxm[k] = clampi(x - R - 1 + k, 0, w - 1);
-#pragma unroll
-        for (int c = 0; c < NW; ++c) cin[c] = x - R + c >= 0 && x - R + c < w;
-        float g00 = 0.0f, g01 = 0.0f, g11 = 0.0f, cu = 0.0f, cv = 0.0f;
-#pragma unroll 1
-        for (int jr = 0; jr < NW; ++jr) {
-            const int yy = y - R + jr;
-            const bool rin = yy >= 0 && yy < h;
-            const float* t0 = Tm + (size_t)clampi(yy - 1, 0, h - 1) * w;
-            const float* t1 = Tm + (size_t)clampi(yy, 0, h - 1) * w;
-            const float* t2 = Tm + (size_t)clampi(yy + 1, 0, h - 1) * w;
-            float a[NW + 2], up[NW], dn[NW];
-#pragma unroll
-            for (int k = 0; k < NW + 2; ++k) a[k] = t1[cxm[k]];
-#pragma unroll
-            for (int c = 0; c < NW; ++c) {
-                up[c] = t0[cxm[c + 1]];
-                dn[c] = t2[cxm[c + 1]];
-            }
-#pragma unroll
-            for (int c = 0; c < NW; ++c) {
-                const bool in = rin && cin[c];
-                const float ix = in ? 0.5f * (a[c + 2] - a[c]) : 0.0f;
-                const float iy = in ? 0.5f * (dn[c] - up[c]) : 0.0f;
-                g00 = __builtin_fmaf(ix, ix, g00);
-                g01 = __builtin_fmaf(ix, iy, g01);
-                g11 = __builtin_fmaf(iy, iy, g11);
-                cu = __builtin_fmaf(ix, a[c + 1], cu);
-                cv = __builtin_fmaf(iy, a[c + 1], cv);
-            }
-        }
-        const int ncx = min(x + R, w - 1) - max(x - R, 0) + 1;
-        const int ncy = min(y + R, h - 1) - max(y - R, 0) + 1;
-        const float reg = Pl->lk_lambda * (float)(ncy * ncx);
-        g00 = g00 + reg;
-        g11 = g11 + reg;
-        const float det = g00 * g11 - g01 * g01;
-        for (int it = it0; it < iters; ++it) {
-            const float flx = floorf(ux), fly = floorf(uy);
-            const int ox = (int)flx, oy = (int)fly;
-            const float fx = ux - flx, fy = uy - fly;
-            int mx[NW + 1];
-#pragma unroll
-            for (int k = 0; k < NW + 1; ++k) mx[k] = clampi(x - R + ox + k, 0, w - 1);
-            float sau = 0.0f, sav = 0.0f, sbu = 0.0f, sbv = 0.0f;
-#pragma unroll 1
-            for (int jr = 0; jr < NW; ++jr) {
-                const int yy = y - R + jr;
-                const bool rin = yy >= 0 && yy < h;
-                const float* t0 = Tm + (size_t)clampi(yy - 1, 0, h - 1) * w;
-                const float* t1 = Tm + (size_t)clampi(yy, 0, h - 1) * w;
-                const float* t2 = Tm + (size_t)clampi(yy + 1, 0, h - 1) * w;
-                const float* m0 = Mv + (size_t)clampi(yy + oy, 0, h - 1) * w;
-                const float* m1 = Mv + (size_t)clampi(yy + oy + 1, 0, h - 1) * w;
-                float a[NW + 2], up[NW], dn[NW], ra[NW + 1], rb[NW + 1];
-#pragma unroll
-                for (int k = 0; k < NW + 2; ++k) a[k] = t1[cxm[k]];
-#pragma unroll
-                for (int c = 0; c < NW; ++c) {
-                    up[c] = t0[cxm[c + 1]];
-                    dn[c] = t2[cxm[c + 1]];
-                }
-#pragma unroll
-                for (int k = 0; k < NW + 1; ++k) {
-                    ra[k] = m0[mx[k]];
-                    rb[k] = m1[mx[k]];
-                }
-#pragma unroll
-                for (int c = 0; c < NW; ++c) {
-                    const bool in = rin && cin[c];
-                    const float ix = in ? 0.5f * (a[c + 2] - a[c]) : 0.0f;
-                    const float iy = in ? 0.5f * (dn[c] - up[c]) : 0.0f;
-                    const float ta = __builtin_fmaf(fx, ra[c + 1] - ra[c], ra[c]);
-                    const float tb = __builtin_fmaf(fx, rb[c + 1] - rb[c], rb[c]);
-                    sau = __builtin_fmaf(ix, ta, sau);
-                    sav = __builtin_fmaf(iy, ta, sav);
-                    sbu = __builtin_fmaf(ix, tb, sbu);
-                    sbv = __builtin_fmaf(iy, tb, sbv);
-                }
-            }
-            const float bu = __builtin_fmaf(fy, sbu - sau, sau) - cu;
-            const float bv = __builtin_fmaf(fy, sbv - sav, sav) - cv;
-            const float du = (g01 * bv - g11 * bu) / det;
-            const float dv = (g01 * bu - g00 * bv) / det;
-            ux = ux + du;
-            uy = uy + dv;
-        }
-        Pl->flow[p][dir][l][(size_t)y * w + x] = make_float2(ux, uy);
-    }
-}
 
-// The tail kernel proper: 16 lanes per queued pixel, lane r of a group taking
-// window row r.  The moving image around the pixel's displacement is staged
-// in LDS (16 x 16 values, clamped indices: the window and a margin of
-// LK_TAIL_M px), so a step reads memory only when the displacement has moved
-// more than the margin since the staging; the sums then run through the rows
-// in order, the lane of each row adding its taps to the partial sums it
-// received from the lane of the row above and handing them on, so each sum is
-// the same row-major sequence of fused multiply-adds as in lk_tail_pixel.
-constexpr int LK_TAIL_G = 16;
-constexpr int LK_TAIL_M = 3;
-constexpr int LK_TAIL_SW = 2 * LK_R_MAX + 2 + 2 * LK_TAIL_M;   // staged window side (16)
-
-// the value of the lane one below in its row of 16 lanes (0 for a row's first
-// lane), a DPP row shift: no LDS round trip
-__device__ __forceinline__ float row_shr1(float v)
+// One deferred pixel finished by the 16 lanes of a group (lane sub holding
+// window row sub; mv: the group's 16 x 16 LDS window), from step it0 with the
+// flow (ux, uy) it had then; lane NW writes the flow.
+__device__ __forceinline__ void lk_tail_group(const DevPlan* __restrict__ Pl, int l, int f, int x, int y, int it0,
+                                           float ux, float uy, int sub, float* mv)
 {
-    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x111, 0xf, 0xf, true));
-}
-
-__global__ __launch_bounds__(256) void k_lk_tail(const Batch B, int l)
-{
-    constexpr int R = LK_R_MAX, NW = 2 * R + 1, G = LK_TAIL_G;
-    static_assert(NW + 1 <= G && G == 16, "one window row per lane, plus the lane that receives the sums, in one "
-                                          "DPP row of 16 lanes");
-    int cx;
-    const int b = batch_block(B, blockIdx.x, cx);
-    const int nb = B.off[cx + 1] - B.off[cx];        // this context's blocks
-    const DevPlan* __restrict__ Pl = B.plan[cx];
-    const uint32_t n = min(Pl->acc->lk_qn[l], (uint32_t)Pl->lk_qcap[l]);
-    constexpr int MG = LK_TAIL_M, SW = LK_TAIL_SW;
-    static_assert(SW == G, "lane r stages row r of the moving window");
-    __shared__ float s_mv[256 / G][SW * SW];
-    float* const mv = s_mv[threadIdx.x / G];          // this group's staged window (its lanes share a wavefront)
-    const int sub = (int)(threadIdx.x % G);
+    constexpr int R = LK_R_MAX, NW = 2 * R + 1, G = LK_TAIL_G, MG = LK_TAIL_M, SW = LK_TAIL_SW;
     const int jr = sub < NW ? sub : NW - 1;           // lanes past the window repeat its last row, unused
     const int iters = Pl->lk_iters;
-    // a whole group takes the same entry, so the group's lanes stay together
-    for (uint32_t i = (b * 256 + threadIdx.x) / G; i < n; i += (uint32_t)nb * (256 / G)) {
-        const uint4 ent = Pl->lk_queue[l][i];
-        const int f = (int)(ent.x & 255u), it0 = (int)(ent.x >> 8);
-        const int x = (int)(ent.y & 0xffffu), y = (int)(ent.y >> 16);
-        float ux = __uint_as_float(ent.z), uy = __uint_as_float(ent.w);
-        const int p = f >> 1, dir = f & 1;
-        const int w = Pl->lw[p][l], h = Pl->lh[p][l];
-        const float* __restrict__ Tm = Pl->pyr[p][dir == 0 ? 0 : 1][l];
-        const float* __restrict__ Mv = Pl->pyr[p][dir == 0 ? 1 : 0][l];
-        // the moving window, anchored at the displacement's integer part: lane
-        // sub loads row sub (loads issued with the template rows' below)
-        int oxs = (int)floorf(ux), oys = (int)floorf(uy);
-        float stg[SW];
-        {
+    const int p = f >> 1, dir = f & 1;
+    const int w = Pl->lw[p][l], h = Pl->lh[p][l];
+    const float* __restrict__ Tm = Pl->pyr[p][dir == 0 ? 0 : 1][l];
+    const float* __restrict__ Mv = Pl->pyr[p][dir == 0 ? 1 : 0][l];
+    // the moving window, anchored at the displacement's integer part: lane
+    // sub loads row sub (loads issued with the template rows' below)
+    int oxs = (int)floorf(ux), oys = (int)floorf(uy);
+    float stg[SW];
+    {
+        const float* mrow = Mv + (size_t)clampi(y - R + oys - MG + sub, 0, h - 1) * w;
+#pragma unroll
+        for (int k = 0; k < SW; ++k) stg[k] = mrow[clampi(x - R + oxs - MG + k, 0, w - 1)];
+    }
+    // this lane's window row: template values and gradients (0 outside the level)
+    const int yy = y - R + jr;
+    const bool rin = yy >= 0 && yy < h;
+    float tc[NW], gx[NW], gy[NW];
+    {
+        const float* t0 = Tm + (size_t)clampi(yy - 1, 0, h - 1) * w;
+        const float* t1 = Tm + (size_t)clampi(yy, 0, h - 1) * w;
+        const float* t2 = Tm + (size_t)clampi(yy + 1, 0, h - 1) * w;
+        float a[NW + 2], up[NW], dn[NW];
+#pragma unroll
+        for (int k = 0; k < NW + 2; ++k) a[k] = t1[clampi(x - R - 1 + k, 0, w - 1)];
+#pragma unroll
+        for (int c = 0; c < NW; ++c) {
+            const int xc = clampi(x - R + c, 0, w - 1);
+            up[c] = t0[xc];
+            dn[c] = t2[xc];
+        }
+#pragma unroll
+        for (int c = 0; c < NW; ++c) {
+            const bool in = rin && x - R + c >= 0 && x - R + c < w;
+            gx[c] = in ? 0.5f * (a[c + 2] - a[c]) : 0.0f;
+            gy[c] = in ? 0.5f * (dn[c] - up[c]) : 0.0f;
+            tc[c] = a[c + 1];
+        }
+    }
+    __builtin_amdgcn_wave_barrier();   // the previous entry's reads of the window come first
+#pragma unroll
+    for (int k = 0; k < SW; ++k) mv[sub * SW + k] = stg[k];
+    __builtin_amdgcn_wave_barrier();
+    // normal matrix and template term: row r's lane adds its taps at hand-on r
+    float g00 = 0.0f, g01 = 0.0f, g11 = 0.0f, cu = 0.0f, cv = 0.0f;
+#pragma unroll
+    for (int r = 0; r < NW; ++r) {
+        if (sub == r) {
+#pragma unroll
+            for (int c = 0; c < NW; ++c) {
+                g00 = __builtin_fmaf(gx[c], gx[c], g00);
+                g01 = __builtin_fmaf(gx[c], gy[c], g01);
+                g11 = __builtin_fmaf(gy[c], gy[c], g11);
+                cu = __builtin_fmaf(gx[c], tc[c], cu);
+                cv = __builtin_fmaf(gy[c], tc[c], cv);
+            }
+        }
+        g00 = row_shr1(g00);
+        g01 = row_shr1(g01);
+        g11 = row_shr1(g11);
+        cu = row_shr1(cu);
+        cv = row_shr1(cv);
+    }
+    // lane NW now holds the sums; it solves each step and hands the flow on
+    const int ncx = min(x + R, w - 1) - max(x - R, 0) + 1;
+    const int ncy = min(y + R, h - 1) - max(y - R, 0) + 1;
+    const float reg = Pl->lk_lambda * (float)(ncy * ncx);
+    g00 = g00 + reg;
+    g11 = g11 + reg;
+    const float det = g00 * g11 - g01 * g01;
+    for (int it = it0; it < iters; ++it) {
+        const float flx = floorf(ux), fly = floorf(uy);
+        const int ox = (int)flx, oy = (int)fly;
+        const float fx = ux - flx, fy = uy - fly;
+        // the displacement's offset in the staged window (unsigned: any ox, oy)
+        uint32_t ddx = (uint32_t)ox - (uint32_t)oxs + (uint32_t)MG;
+        uint32_t ddy = (uint32_t)oy - (uint32_t)oys + (uint32_t)MG;
+        if (ddx > 2u * MG || ddy > 2u * MG) {
+            // the displacement left the staged window (the whole group: its
+            // lanes hold the same flow): stage it again around the new one
+            oxs = ox;
+            oys = oy;
+            ddx = MG;
+            ddy = MG;
             const float* mrow = Mv + (size_t)clampi(y - R + oys - MG + sub, 0, h - 1) * w;
 #pragma unroll
             for (int k = 0; k < SW; ++k) stg[k] = mrow[clampi(x - R + oxs - MG + k, 0, w - 1)];
+            __builtin_amdgcn_wave_barrier();
+#pragma unroll
+            for (int k = 0; k < SW; ++k) mv[sub * SW + k] = stg[k];
+            __builtin_amdgcn_wave_barrier();
         }
-        // this lane's window row: template values and gradients (0 outside the level)
-        const int yy = y - R + jr;
-        const bool rin = yy >= 0 && yy < h;
-        float tc[NW], gx[NW], gy[NW];
-        {
-            const float* t0 = Tm + (size_t)clampi(yy - 1, 0, h - 1) * w;
-            const float* t1 = Tm + (size_t)clampi(yy, 0, h - 1) * w;
-            const float* t2 = Tm + (size_t)clampi(yy + 1, 0, h - 1) * w;
-            float a[NW + 2], up[NW], dn[NW];
+        // rows yy + oy and yy + oy + 1, columns x - R + ox + k, clamped as staged
+        const float* m0 = mv + (jr + (int)ddy) * SW + (int)ddx;
+        float ra[NW + 1], rb[NW + 1];
 #pragma unroll
-            for (int k = 0; k < NW + 2; ++k) a[k] = t1[clampi(x - R - 1 + k, 0, w - 1)];
-#pragma unroll
-            for (int c = 0; c < NW; ++c) {
-                const int xc = clampi(x - R + c, 0, w - 1);
-                up[c] = t0[xc];
-                dn[c] = t2[xc];
-            }
-#pragma unroll
-            for (int c = 0; c < NW; ++c) {
-                const bool in = rin && x - R + c >= 0 && x - R + c < w;
-                gx[c] = in ? 0.5f * (a[c + 2] - a[c]) : 0.0f;
-                gy[c] = in ? 0.5f * (dn[c] - up[c]) : 0.0f;
-                tc[c] = a[c + 1];
-            }
+        for (int k = 0; k < NW + 1; ++k) {
+            ra[k] = m0[k];
+            rb[k] = m0[SW + k];
         }
-        __builtin_amdgcn_wave_barrier();   // the previous entry's reads of the window come first
+        float ta[NW], tb[NW];
 #pragma unroll
-        for (int k = 0; k < SW; ++k) mv[sub * SW + k] = stg[k];
-        __builtin_amdgcn_wave_barrier();
-        // normal matrix and template term: row r's lane adds its taps at hand-on r
-        float g00 = 0.0f, g01 = 0.0f, g11 = 0.0f, cu = 0.0f, cv = 0.0f;
+        for (int c = 0; c < NW; ++c) {
+            ta[c] = __builtin_fmaf(fx, ra[c + 1] - ra[c], ra[c]);
+            tb[c] = __builtin_fmaf(fx, rb[c + 1] - rb[c], rb[c]);
+        }
+        float sau = 0.0f, sav = 0.0f, sbu = 0.0f, sbv = 0.0f;
 #pragma unroll
         for (int r = 0; r < NW; ++r) {
             if (sub == r) {
 #pragma unroll
                 for (int c = 0; c < NW; ++c) {
-                    g00 = __builtin_fmaf(gx[c], gx[c], g00);
-                    g01 = __builtin_fmaf(gx[c], gy[c], g01);
-                    g11 = __builtin_fmaf(gy[c], gy[c], g11);
-                    cu = __builtin_fmaf(gx[c], tc[c], cu);
-                    cv = __builtin_fmaf(gy[c], tc[c], cv);
+                    sau = __builtin_fmaf(gx[c], ta[c], sau);
+                    sav = __builtin_fmaf(gy[c], ta[c], sav);
+                    sbu = __builtin_fmaf(gx[c], tb[c], sbu);
+                    sbv = __builtin_fmaf(gy[c], tb[c], sbv);
                 }
             }
-            g00 = row_shr1(g00);
-            g01 = row_shr1(g01);
-            g11 = row_shr1(g11);
-            cu = row_shr1(cu);
-            cv = row_shr1(cv);
+            sau = row_shr1(sau);
+            sav = row_shr1(sav);
+            sbu = row_shr1(sbu);
+            sbv = row_shr1(sbv);
         }
-        // lane NW now holds the sums; it solves each step and hands the flow on
-        const int ncx = min(x + R, w - 1) - max(x - R, 0) + 1;
-        const int ncy = min(y + R, h - 1) - max(y - R, 0) + 1;
-        const float reg = Pl->lk_lambda * (float)(ncy * ncx);
-        g00 = g00 + reg;
-        g11 = g11 + reg;
-        const float det = g00 * g11 - g01 * g01;
-        for (int it = it0; it < iters; ++it) {
-            const float flx = floorf(ux), fly = floorf(uy);
-            const int ox = (int)flx, oy = (int)fly;
-            const float fx = ux - flx, fy = uy - fly;
-            // the displacement's offset in the staged window (unsigned: any ox, oy)
-            uint32_t ddx = (uint32_t)ox - (uint32_t)oxs + (uint32_t)MG;
-            uint32_t ddy = (uint32_t)oy - (uint32_t)oys + (uint32_t)MG;
-            if (ddx > 2u * MG || ddy > 2u * MG) {
-                // the displacement left the staged window (the whole group: its
-                // lanes hold the same flow): stage it again around the new one
-                oxs = ox;
-                oys = oy;
-                ddx = MG;
-                ddy = MG;
-                const float* mrow = Mv + (size_t)clampi(y - R + oys - MG + sub, 0, h - 1) * w;
-#pragma unroll
-                for (int k = 0; k < SW; ++k) stg[k] = mrow[clampi(x - R + oxs - MG + k, 0, w - 1)];
-                __builtin_amdgcn_wave_barrier();
-#pragma unroll
-                for (int k = 0; k < SW; ++k) mv[sub * SW + k] = stg[k];
-                __builtin_amdgcn_wave_barrier();
-            }
-            // rows yy + oy and yy + oy + 1, columns x - R + ox + k, clamped as staged
-            const float* m0 = mv + (jr + (int)ddy) * SW + (int)ddx;
-            float ra[NW + 1], rb[NW + 1];
-#pragma unroll
-            for (int k = 0; k < NW + 1; ++k) {
-                ra[k] = m0[k];
-                rb[k] = m0[SW + k];
-            }
-            float ta[NW], tb[NW];
-#pragma unroll
-            for (int c = 0; c < NW; ++c) {
-                ta[c] = __builtin_fmaf(fx, ra[c + 1] - ra[c], ra[c]);
-                tb[c] = __builtin_fmaf(fx, rb[c + 1] - rb[c], rb[c]);
-            }
-            float sau = 0.0f, sav = 0.0f, sbu = 0.0f, sbv = 0.0f;
-#pragma unroll
-            for (int r = 0; r < NW; ++r) {
-                if (sub == r) {
-#pragma unroll
-                    for (int c = 0; c < NW; ++c) {
-                        sau = __builtin_fmaf(gx[c], ta[c], sau);
-                        sav = __builtin_fmaf(gy[c], ta[c], sav);
-                        sbu = __builtin_fmaf(gx[c], tb[c], sbu);
-                        sbv = __builtin_fmaf(gy[c], tb[c], sbv);
-                    }
-                }
-                sau = row_shr1(sau);
-                sav = row_shr1(sav);
-                sbu = row_shr1(sbu);
-                sbv = row_shr1(sbv);
-            }
-            const float bu = __builtin_fmaf(fy, sbu - sau, sau) - cu;
-            const float bv = __builtin_fmaf(fy, sbv - sav, sav) - cv;
-            const float du = (g01 * bv - g11 * bu) / det;
-            const float dv = (g01 * bu - g00 * bv) / det;
-            ux = __shfl(ux + du, NW, G);
-            uy = __shfl(uy + dv, NW, G);
-        }
-        if (sub == NW) Pl->flow[p][dir][l][(size_t)y * w + x] = make_float2(ux, uy);
+        const float bu = __builtin_fmaf(fy, sbu - sau, sau) - cu;
+        const float bv = __builtin_fmaf(fy, sbv - sav, sav) - cv;
+        const float du = (g01 * bv - g11 * bu) / det;
+        const float dv = (g01 * bu - g00 * bv) / det;
+        ux = __shfl(ux + du, NW, G);
+        uy = __shfl(uy + dv, NW, G);
+    }
+    if (sub == NW) Pl->flow[p][dir][l][(size_t)y * w + x] = make_float2(ux, uy);
+}
+
+__global__ __launch_bounds__(256) void k_lk_tail(const Batch B, int l)
+{
+    constexpr int G = LK_TAIL_G, SW = LK_TAIL_SW;
+    int cx;
+    const int b = batch_block(B, blockIdx.x, cx);
+    const int nb = B.off[cx + 1] - B.off[cx];        // this context's blocks
+    const DevPlan* __restrict__ Pl = B.plan[cx];
+    const uint32_t n = min(Pl->acc->lk_qn[l], (uint32_t)Pl->lk_qcap[l]);
+    __shared__ float s_mv[256 / G][SW * SW];
+    float* const mv = s_mv[threadIdx.x / G];          // this group's staged window (its lanes share a wavefront)
+    const int sub = (int)(threadIdx.x % G);
+    // a whole group takes the same entry, so the group's lanes stay together
+    for (uint32_t i = (b * 256 + threadIdx.x) / G; i < n; i += (uint32_t)nb * (256 / G)) {
+        const uint4 ent = Pl->lk_queue[l][i];
+        lk_tail_group(Pl, l, (int)(ent.x & 255u), (int)(ent.y & 0xffffu), (int)(ent.y >> 16), (int)(ent.x >> 8),
+                      __uint_as_float(ent.z), __uint_as_float(ent.w), sub, mv);
     }
 }
 
