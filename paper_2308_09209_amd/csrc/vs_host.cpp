@@ -213,20 +213,19 @@ void free_ctx(vs_ctx* c)
 // (few) deferred pixels in-block: at about one wavefront per SIMD its rows'
 // LDS reads overlap, and no tail launch follows.  Otherwise the most pixels
 // per thread P (4, 3, 2, 1; n16 * 4 / P blocks) that still gives at least
-// one full wave of blocks, finishing the deferred pixels in-block at every
-// level but the finest: the finest level's displacements are twice the next
-// one's, so nearly all deferred pixels are there, and blocks holding many
-// of them would end long after the others (a tail launch spreads them).
-// Every P takes the form that keeps the previous gradient row in registers:
-// with the regrouped right-hand side it costs no occupancy at P = 4 and
-// saves the row's second LDS read.
-int default_lk_P(int n16, int resident, bool finest)
+// one full wave of blocks, with a tail launch for the deferred pixels: over
+// a sequence, frames whose deferred pixels cluster in a few blocks make
+// in-block finishing end late (4x1080p p99 0.614 -> 0.638 ms, 8x4K mean
+// 3.556 -> 3.584 ms with it at the coarser levels).  Every P takes the form
+// that keeps the previous gradient row in registers: with the regrouped
+// right-hand side it costs no occupancy at P = 4 and saves the row's second
+// LDS read.
+int default_lk_P(int n16, int resident)
 {
     if ((long)n16 * 4 < 2L * resident) return 1 + VS_FLOW_ALT + VS_FLOW_INBLOCK;
-    const int inblock = finest ? 0 : VS_FLOW_INBLOCK;
     for (int P = 4; P >= 1; --P) {
         const long blocks = ((long)n16 * 4 + P - 1) / P;
-        if (blocks >= resident) return P + VS_FLOW_ALT + inblock;
+        if (blocks >= resident) return P + VS_FLOW_ALT;
     }
     return 1 + VS_FLOW_ALT + VS_FLOW_INBLOCK;
 }
@@ -578,7 +577,7 @@ vs_status vs_create(const vs_rig* rig, const vs_params* prm, vs_ctx** out)
             const int p = f >> 1;
             n16 += ((h.lw[p][l] + LKW_TX - 1) / LKW_TX) * ((h.lh[p][l] + 15) / 16);
         }
-        set_lk_tiles(h, l, P.lk_radius == LK_R_MAX ? default_lk_P(n16, lk_resident_blocks(), l == 0) : 0);
+        set_lk_tiles(h, l, P.lk_radius == LK_R_MAX ? default_lk_P(n16, lk_resident_blocks()) : 0);
     }
     // ---- workspace arena ----
     size_t off = 0;
@@ -1333,7 +1332,7 @@ vs_status vs_batch_create(vs_ctx* const ctxs[], int n, vs_batch** out)
                     n16 += ((h.lw[p][l] + LKW_TX - 1) / LKW_TX) * ((h.lh[p][l] + 15) / 16);
                 }
             }
-            variant = default_lk_P(n16, lk_resident_blocks(), l == 0);
+            variant = default_lk_P(n16, lk_resident_blocks());
         }
         vs_status st = set_variant_all(b, l, variant);
         if (st != VS_OK) {
@@ -1555,7 +1554,7 @@ bool flow_plan(int w, int h, const vs_params& P, DevPlan& d, FlowLayout& L)
             d.pyr_off[l][fl + 1] = d.pyr_off[l][fl] + d.pyr_tx[l][fl] * ((d.lh[0][l] + PYR_TY - 1) / PYR_TY);
         }
         const int n16 = 2 * ((d.lw[0][l] + LKW_TX - 1) / LKW_TX) * ((d.lh[0][l] + 15) / 16);
-        set_lk_tiles(d, l, P.lk_radius == LK_R_MAX ? default_lk_P(n16, lk_resident_blocks(), l == 0) : 0);
+        set_lk_tiles(d, l, P.lk_radius == LK_R_MAX ? default_lk_P(n16, lk_resident_blocks()) : 0);
     }
     size_t off = 0;
     for (int l = 0; l < d.levels; ++l) {
